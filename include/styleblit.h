@@ -1,0 +1,138 @@
+/*
+ * styleblit.h -- C ABI of the MI355X (gfx950) StyleBlit library.
+ *
+ * StyleBlit (Sykora et al., EGSR 2018) stylises a target image by copying
+ * coherent chunks of a source exemplar C_S.  Every target pixel p walks a
+ * hierarchy of jittered seed grids from coarse to fine (Sec. 3.2,
+ * Algorithm 2); at each level the nearest seed q's guide value is mapped to
+ * a source pixel u* through a lookup table (Sec. 3.1), and p takes the source
+ * coordinate u* + (p - q) as soon as the guide error there is below a
+ * threshold.  A voting pass then averages, for every target pixel, the
+ * co-located colours of the source patches around its neighbours' source
+ * coordinates (end of Sec. 3.2).
+ *
+ * Conventions (all functions):
+ *   - pointers marked [device] are HIP device pointers, [host] host pointers;
+ *     the caller owns every buffer (the library allocates no device memory);
+ *   - images are row-major; pixel p = (x, y), x the column; raster index
+ *     y*W + x;
+ *   - a guide has two interleaved channels, uint8 (SB_GUIDE_U8X2, 2 B/px) or
+ *     uint16 (SB_GUIDE_U16X2, 4 B/px, native little-endian);
+ *   - source coordinates are packed x | (y << 16);
+ *   - work is enqueued asynchronously on `stream` (0 = the null stream); the
+ *     caller synchronises.  Arguments are validated before anything is
+ *     enqueued: on an error code nothing has been written;
+ *   - functions return sb_status codes and never throw; after SB_EHIP,
+ *     sb_last_hip_error() names the HIP error (per calling thread).
+ */
+#ifndef STYLEBLIT_H
+#define STYLEBLIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SB_OK = 0,
+    SB_EINVAL = -1,  /* bad argument; nothing enqueued */
+    SB_ENOMEM = -2,  /* workspace too small, or a host allocation failed */
+    SB_EHIP = -3,    /* a HIP call or launch failed; see sb_last_hip_error() */
+    SB_EBUDGET = -4  /* serving: request larger than the memory budget */
+} sb_status;
+
+typedef enum { SB_GUIDE_U8X2 = 0, SB_GUIDE_U16X2 = 1 } sb_guide_fmt;
+
+/* Largest target and source side, and limits of the parameters. */
+#define SB_MAX_SIDE 8192
+#define SB_MAX_LEVELS 12
+#define SB_MAX_RADIUS 8
+#define SB_MAX_LUT_BITS 12
+
+/* A style: the exemplar C_S, its guide G_S and the lookup table built from
+ * G_S (Sec. 3.1).  A plain struct of caller-owned device pointers; it must
+ * stay alive while work that reads it is in flight. */
+typedef struct {
+    const uint32_t *rgba;   /* [device] Sw*Sh texels R | G<<8 | B<<16 (byte 3 = 0),
+                               written by sb_pack_exemplar */
+    const void *guide;      /* [device] Sw*Sh*2 guide channels */
+    const uint32_t *lut;    /* [device] (1<<lut_bits)^2 source coordinates, bin index
+                               c = c0 + (c1 << lut_bits), written by sb_lut_build */
+    int32_t sw, sh;         /* source size, 1..SB_MAX_SIDE */
+    int32_t fmt;            /* sb_guide_fmt */
+    int32_t lut_bits;       /* bits per channel of the lookup table: U8X2 1..8,
+                               U16X2 1..SB_MAX_LUT_BITS */
+} sb_style;
+
+/* Per-frame parameters of Algorithm 2 and of the voting blend. */
+typedef struct {
+    int32_t levels;         /* L, 0..SB_MAX_LEVELS; 0 = plain lookup (texture mapping) */
+    int32_t finest;         /* spacing of the finest level, a power of two >= 1; level i
+                               (0 = coarsest) has spacing finest << (L-1-i), at most
+                               SB_MAX_SIDE.  The paper's hierarchy is finest = 2. */
+    uint32_t threshold;     /* t: a level is accepted iff the exact squared L2 guide
+                               error is < t (so t = 0 accepts nothing) */
+    int32_t radius;         /* r, 0..SB_MAX_RADIUS: voting window (2r+1)^2; 0 = copy */
+} sb_params;
+
+/* --------------------------------------------------------------- general */
+
+const char *sb_version(void);
+const char *sb_status_string(int status);
+const char *sb_last_hip_error(void);
+
+/* Entries of the jitter table of a W x H target: level i (coarsest first) has
+ * ceil(W/h_i) x ceil(H/h_i) cells, row-major; each entry is jx | (jy << 16)
+ * with 0 <= jx, jy < h_i, and the cell's seed is (h_i*cx + jx, h_i*cy + jy)
+ * (SeedPoint in Algorithm 2, whose RandomJitterTable this is; the caller draws
+ * it).  Returns -1 on invalid arguments. */
+int64_t sb_jitter_len(int32_t w, int32_t h, int32_t levels, int32_t finest);
+
+/* ------------------------------------------------- style registration */
+
+/* Repack an exemplar from 3 B/px RGB to 4 B/px texels (one aligned load per
+ * texel in the gathers).  rgb [device] Sw*Sh*3; rgba [device] Sw*Sh. */
+int sb_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t *rgba,
+                     hipStream_t stream);
+
+/* Device workspace needed by sb_lut_build. */
+size_t sb_lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits);
+
+/* Build the guide-to-source lookup table of Sec. 3.1 on the device:
+ *   LUT[c] = argmin_u |centre(c) - G_S[u]|^2, ties to the smallest raster
+ *   index of u, where bin c = (c0, c1) holds the guide values whose top
+ *   lut_bits bits per channel are c0, c1 and centre(c) = (c << s) + 2^(s-1)
+ *   per channel for s = depth - lut_bits > 0, centre(c) = c for s = 0.
+ * guide [device] Sw*Sh*2; lut [device] (1<<lut_bits)^2 entries;
+ * workspace [device] of at least sb_lut_workspace_bytes() bytes. */
+int sb_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
+                 uint32_t *lut, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------- one frame */
+
+/* Device workspace needed by sb_stylize for a W x H frame. */
+size_t sb_workspace_bytes(int32_t w, int32_t h, const sb_params *params);
+
+/* Stylise one frame (Algorithm 2 for every pixel, then the voting blend).
+ *   style      [host] struct of device pointers, see sb_style
+ *   tgt_guide  [device] W*H*2 channels, same format as the style's guide
+ *   jitter     [device] sb_jitter_len(W, H, L, finest) entries
+ *   out_rgb    [device] W*H*3 bytes: the stylised image C_T
+ *   out_chunk  [device] W*H: chunk code (level << 26) | (qy << 13) | qx of the
+ *              seed q whose chunk covers the pixel; level = L and q = p when
+ *              no level accepted and the pixel took its own lookup
+ *   out_nnf    [device, may be NULL] W*H source coordinates (x | y << 16)
+ *   workspace  [device] at least sb_workspace_bytes() bytes
+ * The output buffers must not overlap the inputs. */
+int sb_stylize(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+               const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+               uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
+               hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STYLEBLIT_H */

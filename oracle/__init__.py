@@ -1,0 +1,192 @@
+"""CPU oracle for StyleBlit's guided chunk transfer -- TEST INFRASTRUCTURE ONLY.
+
+Python access (ctypes + numpy) to ``styleblit_oracle.c``, the plain C
+implementation of the lookup table (Sec. 3.1), the seed hierarchy and
+per-pixel level loop (Sec. 3.2, Algorithm 2) and the voting blend (end of
+Sec. 3.2).  Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s
+CPU-baseline leg may import this package; the HIP library never does, and
+nothing here imports the HIP library.
+
+Parity pins (all in ``tests/test_oracle_*.py``, CPU only): brute-force
+argmin for the lookup table, the closed form of identity UV guides, seed
+positions against the jitter table read directly, hand-worked 8x8 cases
+(``tests/golden/``), texture mapping as the threshold-0 special case and
+the paper's invariants (identity guide reproduces the source, larger
+threshold never picks a finer level, chunks are pure translations, every
+accepted pixel has error below the threshold).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "styleblit_oracle.c")
+_LIB = os.path.join(_HERE, "libstyleblit_oracle.so")
+_lib = None
+
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def build() -> str:
+    """Compile the oracle with gcc (-O2, OpenMP over rows)."""
+    tmp = _LIB + ".tmp"
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall", "-o", tmp, _SRC],
+                   check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    vp = ctypes.c_void_p
+    i32 = ctypes.c_int
+    lib.ora_lut_build.argtypes = [vp, i32, i32, i32, i32, _u32p]
+    lib.ora_jitter_len.argtypes = [i32, i32, i32, i32]
+    lib.ora_jitter_len.restype = ctypes.c_int64
+    lib.ora_seed_point.argtypes = [i32, i32, i32, i32, _u32p, i32, ctypes.c_int64, ctypes.c_int64,
+                                   _i64p, _i64p]
+    lib.ora_nearest_seed.argtypes = [i32, i32, i32, i32, _u32p, i32, ctypes.c_int64,
+                                     ctypes.c_int64, _i64p, _i64p]
+    lib.ora_assign.argtypes = [vp, i32, i32, _u32p, i32, i32, vp, i32, i32, _u32p, i32, i32,
+                               ctypes.c_uint32, _u32p, _u32p, ctypes.c_int64, ctypes.c_int64]
+    lib.ora_blend.argtypes = [_u8p, i32, i32, _u32p, i32, i32, i32, _u8p, ctypes.c_int64,
+                              ctypes.c_int64]
+    lib.ora_stylize.argtypes = [_u8p, vp, i32, i32, _u32p, i32, i32, vp, i32, i32, _u32p, i32,
+                                i32, ctypes.c_uint32, i32, _u8p, _u32p, _u32p]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+def _guide(g: np.ndarray) -> Tuple[np.ndarray, int]:
+    g = np.ascontiguousarray(g)
+    if g.ndim != 3 or g.shape[2] != 2:
+        raise ValueError("guide must be (rows, cols, 2)")
+    if g.dtype == np.uint8:
+        return g, 0
+    if g.dtype == np.uint16:
+        return g, 1
+    raise ValueError("guide must be uint8 or uint16")
+
+
+def _jit(jitter: Optional[np.ndarray], w: int, h: int, levels: int, finest: int) -> np.ndarray:
+    n = jitter_len(w, h, levels, finest)
+    if jitter is None:
+        return np.zeros(max(n, 1), np.uint32)
+    j = np.ascontiguousarray(jitter, dtype=np.uint32)
+    if j.size != n:
+        raise ValueError(f"jitter table has {j.size} entries, expected {n}")
+    return j if n else np.zeros(1, np.uint32)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def jitter_len(w: int, h: int, levels: int, finest: int) -> int:
+    return int(_load().ora_jitter_len(w, h, levels, finest))
+
+
+def lut_build(src_guide: np.ndarray, lut_bits: int) -> np.ndarray:
+    """Exact lookup table, shape (2**lut_bits)**2, entries x | y << 16."""
+    g, fmt = _guide(src_guide)
+    n = 1 << lut_bits
+    lut = np.zeros(n * n, np.uint32)
+    _check(_load().ora_lut_build(g.ctypes.data, fmt, g.shape[1], g.shape[0], lut_bits,
+                                 _ptr(lut, _u32p)), "lut_build")
+    return lut
+
+
+def seed_point(w, h, levels, finest, jitter, level, bx, by):
+    """(valid, sx, sy) of cell (bx, by) at level `level`."""
+    j = _jit(jitter, w, h, levels, finest)
+    sx, sy = ctypes.c_int64(), ctypes.c_int64()
+    ok = _load().ora_seed_point(w, h, levels, finest, _ptr(j, _u32p), level, bx, by,
+                                ctypes.byref(sx), ctypes.byref(sy))
+    return bool(ok), sx.value, sy.value
+
+
+def nearest_seed(w, h, levels, finest, jitter, level, px, py):
+    """(found, qx, qy) for pixel (px, py) at level `level`."""
+    j = _jit(jitter, w, h, levels, finest)
+    qx, qy = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    ok = _load().ora_nearest_seed(w, h, levels, finest, _ptr(j, _u32p), level, px, py,
+                                  ctypes.byref(qx), ctypes.byref(qy))
+    return bool(ok), qx.value, qy.value
+
+
+def assign(src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest, threshold,
+           rows: Optional[Tuple[int, int]] = None):
+    """Per-pixel level loop only: returns (nnf, chunk), both uint32 (H, W).
+    With ``rows=(row0, n)`` only those rows are computed (others stay 0)."""
+    gs, fmt = _guide(src_guide)
+    gt, fmt_t = _guide(tgt_guide)
+    if fmt != fmt_t:
+        raise ValueError("source and target guide formats differ")
+    h, w = gt.shape[:2]
+    j = _jit(jitter, w, h, levels, finest)
+    lut = np.ascontiguousarray(lut, dtype=np.uint32)
+    nnf = np.zeros((h, w), np.uint32)
+    chunk = np.zeros((h, w), np.uint32)
+    r0, nr = rows if rows is not None else (0, -1)
+    _check(_load().ora_assign(gs.ctypes.data, gs.shape[1], gs.shape[0], _ptr(lut, _u32p), fmt,
+                              lut_bits, gt.ctypes.data, w, h, _ptr(j, _u32p), levels, finest,
+                              threshold, _ptr(nnf, _u32p), _ptr(chunk, _u32p), r0, nr), "assign")
+    return nnf, chunk
+
+
+def blend(src_rgb: np.ndarray, nnf: np.ndarray, radius: int,
+          rows: Optional[Tuple[int, int]] = None) -> np.ndarray:
+    """Voting blend of an NNF (uint32 (H, W), x | y << 16) -> uint8 (H, W, 3)."""
+    rgb = np.ascontiguousarray(src_rgb, dtype=np.uint8)
+    nnf = np.ascontiguousarray(nnf, dtype=np.uint32)
+    h, w = nnf.shape
+    out = np.zeros((h, w, 3), np.uint8)
+    r0, nr = rows if rows is not None else (0, -1)
+    _check(_load().ora_blend(_ptr(rgb, _u8p), rgb.shape[1], rgb.shape[0], _ptr(nnf, _u32p), w, h,
+                             radius, _ptr(out, _u8p), r0, nr), "blend")
+    return out
+
+
+def stylize(src_rgb, src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest, threshold,
+            radius):
+    """The whole per-frame path: returns (rgb (H,W,3) uint8, chunk (H,W) uint32,
+    nnf (H,W) uint32)."""
+    gs, fmt = _guide(src_guide)
+    gt, fmt_t = _guide(tgt_guide)
+    if fmt != fmt_t:
+        raise ValueError("source and target guide formats differ")
+    rgb = np.ascontiguousarray(src_rgb, dtype=np.uint8)
+    h, w = gt.shape[:2]
+    j = _jit(jitter, w, h, levels, finest)
+    lut = np.ascontiguousarray(lut, dtype=np.uint32)
+    out = np.zeros((h, w, 3), np.uint8)
+    chunk = np.zeros((h, w), np.uint32)
+    nnf = np.zeros((h, w), np.uint32)
+    _check(_load().ora_stylize(_ptr(rgb, _u8p), gs.ctypes.data, gs.shape[1], gs.shape[0],
+                               _ptr(lut, _u32p), fmt, lut_bits, gt.ctypes.data, w, h,
+                               _ptr(j, _u32p), levels, finest, threshold, radius,
+                               _ptr(out, _u8p), _ptr(chunk, _u32p), _ptr(nnf, _u32p)), "stylize")
+    return out, chunk, nnf
+
+
+def decode_chunk(chunk: np.ndarray):
+    """(level, qx, qy) arrays from chunk codes (level << 26 | qy << 13 | qx)."""
+    c = np.asarray(chunk, dtype=np.uint32)
+    return (c >> 26).astype(np.int64), (c & 0x1FFF).astype(np.int64), ((c >> 13) & 0x1FFF).astype(np.int64)

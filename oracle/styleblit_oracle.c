@@ -1,0 +1,369 @@
+/*
+ * styleblit_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct CPU oracle for StyleBlit's per-pixel guided
+ * chunk transfer (Sykora et al., "StyleBlit: Fast Example-Based Stylization
+ * with Local Guidance", EGSR 2018): the guide-to-source lookup table of
+ * Sec. 3.1, the seed hierarchy and per-pixel level loop of Sec. 3.2
+ * (Algorithm 2, ParallelStyleBlit, with its SeedPoint and NearestSeed
+ * functions), and the coordinate-transfer-plus-voting blend at the end of
+ * Sec. 3.2.  It exists only to check the HIP library.  Only tests, the smoke
+ * check and the benchmark's CPU-baseline leg may load it; the product path
+ * never does.  It shares no code with the HIP library.
+ *
+ * Readings of points the paper leaves open (all integer, so the result is
+ * unique):
+ *   - guide error and threshold: exact squared L2 over the two guide
+ *     channels, accepted iff error < t (strict, as in both algorithms);
+ *   - level spacings h_i = finest << (L-1-i), level 0 coarsest (the paper's
+ *     2^l, l = L..1, is finest = 2);
+ *   - RandomJitterTable: one integer jitter (jx, jy) in [0,h)^2 per cell and
+ *     level, passed in; SeedPoint(b) = h*b + j, the integer form of
+ *     floor(h*(b + j/h));
+ *   - seeds outside the target are not candidates; a level whose 3x3
+ *     neighbourhood holds no in-image seed is skipped;
+ *   - NearestSeed scans x outer, y inner over {-1,0,1} and keeps the first
+ *     strict minimum of the squared distance;
+ *   - the lookup table maps a (quantised) guide value to the source pixel
+ *     whose guide is nearest to the bin centre, ties to the smallest raster
+ *     index;
+ *   - a transferred coordinate that falls outside the source rejects the
+ *     level;
+ *   - no level accepted: fall back to the pixel's own lookup (the spacing-1
+ *     level, where SeedPoint(p) = p), accepted unconditionally;
+ *   - voting: square (2r+1)^2 window of uniform weight over target pixels n;
+ *     n votes with the source pixel NNF[n] + (p - n) when that lies in the
+ *     source; per channel (sum + floor(k/2)) / k in integers.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORA_OK 0
+#define ORA_EINVAL (-1)
+#define ORA_ENOMEM (-2)
+
+/* ------------------------------------------------------------------ guides */
+
+/* Read the two guide channels of pixel `idx` (raster index). fmt 0: uint8,
+ * fmt 1: uint16. */
+static void guide_read(const void *g, int fmt, int64_t idx, int64_t *c0, int64_t *c1)
+{
+    if (fmt == 0) {
+        const uint8_t *p = (const uint8_t *)g;
+        *c0 = p[2 * idx];
+        *c1 = p[2 * idx + 1];
+    } else {
+        const uint16_t *p = (const uint16_t *)g;
+        *c0 = p[2 * idx];
+        *c1 = p[2 * idx + 1];
+    }
+}
+
+static int guide_depth(int fmt) { return fmt == 0 ? 8 : 16; }
+
+/* Lookup-table bin of one guide channel value: drop the low bits. */
+static int64_t lut_quantise(int64_t v, int fmt, int lut_bits)
+{
+    return v >> (guide_depth(fmt) - lut_bits);
+}
+
+/* Guide value at the centre of bin c of one channel. */
+static int64_t lut_bin_centre(int64_t c, int fmt, int lut_bits)
+{
+    int s = guide_depth(fmt) - lut_bits;
+    return s == 0 ? c : (c << s) + ((int64_t)1 << (s - 1));
+}
+
+/* ---------------------------------------------------- lookup table (Sec. 3.1)
+ *
+ * LUT[c] = argmin_u |centre(c) - G_S[u]|^2, ties to the smallest raster index
+ * of u.  Computed by a ring search over a bucket grid equal to the LUT grid:
+ * after the buckets at Chebyshev distance <= k around c have been visited,
+ * every unvisited source pixel lies at squared distance >= LB(k+1) from the
+ * centre, so the search may stop as soon as best < LB(k+1).  (Equality must
+ * continue: a later ring may hold an equally near pixel with a smaller raster
+ * index.)
+ */
+int ora_lut_build(const void *src_guide, int fmt, int sw, int sh, int lut_bits, uint32_t *lut)
+{
+    if (!src_guide || !lut || sw < 1 || sh < 1 || (fmt != 0 && fmt != 1)) return ORA_EINVAL;
+    if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
+    const int64_t n = (int64_t)1 << lut_bits;          /* bins per channel */
+    const int64_t w = (int64_t)1 << (guide_depth(fmt) - lut_bits); /* bin width */
+    const int64_t npix = (int64_t)sw * sh;
+
+    /* counting sort of the source pixels into buckets, raster order kept */
+    int64_t *start = (int64_t *)calloc((size_t)(n * n + 1), sizeof(int64_t));
+    int64_t *list = (int64_t *)malloc((size_t)npix * sizeof(int64_t));
+    int64_t *fill = (int64_t *)malloc((size_t)(n * n) * sizeof(int64_t));
+    if (!start || !list || !fill) { free(start); free(list); free(fill); return ORA_ENOMEM; }
+    for (int64_t i = 0; i < npix; ++i) {
+        int64_t g0, g1;
+        guide_read(src_guide, fmt, i, &g0, &g1);
+        int64_t b = lut_quantise(g1, fmt, lut_bits) * n + lut_quantise(g0, fmt, lut_bits);
+        start[b + 1]++;
+    }
+    for (int64_t b = 0; b < n * n; ++b) start[b + 1] += start[b];
+    memcpy(fill, start, (size_t)(n * n) * sizeof(int64_t));
+    for (int64_t i = 0; i < npix; ++i) {
+        int64_t g0, g1;
+        guide_read(src_guide, fmt, i, &g0, &g1);
+        int64_t b = lut_quantise(g1, fmt, lut_bits) * n + lut_quantise(g0, fmt, lut_bits);
+        list[fill[b]++] = i;
+    }
+
+    for (int64_t cy = 0; cy < n; ++cy) {
+        for (int64_t cx = 0; cx < n; ++cx) {
+            const int64_t qx = lut_bin_centre(cx, fmt, lut_bits);
+            const int64_t qy = lut_bin_centre(cy, fmt, lut_bits);
+            uint64_t best_d = UINT64_MAX;
+            int64_t best_i = -1;
+            for (int64_t k = 0;; ++k) {
+                int any = 0;
+                for (int64_t by = cy - k; by <= cy + k; ++by) {
+                    if (by < 0 || by >= n) continue;
+                    /* on the ring: full rows at the top and bottom, two
+                     * columns in between */
+                    int64_t step = (by == cy - k || by == cy + k) ? 1 : 2 * k;
+                    if (step == 0) step = 1;
+                    for (int64_t bx = cx - k; bx <= cx + k; bx += step) {
+                        if (bx < 0 || bx >= n) continue;
+                        any = 1;
+                        int64_t b = by * n + bx;
+                        for (int64_t e = start[b]; e < start[b + 1]; ++e) {
+                            int64_t i = list[e], g0, g1;
+                            guide_read(src_guide, fmt, i, &g0, &g1);
+                            uint64_t d = (uint64_t)((qx - g0) * (qx - g0)) +
+                                         (uint64_t)((qy - g1) * (qy - g1));
+                            if (d < best_d || (d == best_d && i < best_i)) {
+                                best_d = d;
+                                best_i = i;
+                            }
+                        }
+                    }
+                }
+                if (!any) break; /* the ring left the grid on every side */
+                int64_t lb = (k + 1) * w - w / 2;
+                if (best_i >= 0 && best_d < (uint64_t)(lb * lb)) break;
+            }
+            lut[cy * n + cx] = (uint32_t)(best_i % sw) | ((uint32_t)(best_i / sw) << 16);
+        }
+    }
+    free(start);
+    free(list);
+    free(fill);
+    return ORA_OK;
+}
+
+/* ------------------------------------------------ seed hierarchy (Sec. 3.2) */
+
+typedef struct {
+    int w, h;               /* target size */
+    int levels, finest;
+    const uint32_t *jitter; /* concatenated per-level tables */
+} seeds_t;
+
+static int64_t level_spacing(const seeds_t *S, int i) { return (int64_t)S->finest << (S->levels - 1 - i); }
+static int64_t cells_x(const seeds_t *S, int i) { int64_t h = level_spacing(S, i); return (S->w + h - 1) / h; }
+static int64_t cells_y(const seeds_t *S, int i) { int64_t h = level_spacing(S, i); return (S->h + h - 1) / h; }
+
+static int64_t level_offset(const seeds_t *S, int i)
+{
+    int64_t off = 0;
+    for (int k = 0; k < i; ++k) off += cells_x(S, k) * cells_y(S, k);
+    return off;
+}
+
+/* Number of jitter entries for the whole hierarchy. */
+int64_t ora_jitter_len(int w, int h, int levels, int finest)
+{
+    seeds_t S = {w, h, levels, finest, NULL};
+    return level_offset(&S, levels);
+}
+
+static int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+/* SeedPoint: the jittered seed of cell (bx, by) at level i.  Returns 0 when
+ * the seed is not a candidate (cell outside the table, or seed outside the
+ * target image). */
+static int seed_point(const seeds_t *S, int i, int64_t bx, int64_t by, int64_t *sx, int64_t *sy)
+{
+    int64_t h = level_spacing(S, i), ncx = cells_x(S, i), ncy = cells_y(S, i);
+    if (bx < 0 || by < 0 || bx >= ncx || by >= ncy) return 0;
+    uint32_t j = S->jitter[level_offset(S, i) + by * ncx + bx];
+    *sx = h * bx + (int64_t)(j & 0xFFFFu);
+    *sy = h * by + (int64_t)(j >> 16);
+    return *sx < S->w && *sy < S->h;
+}
+
+/* NearestSeed: among the seeds of the 3x3 cells around p's cell, the first
+ * (x outer, y inner) with the strictly smallest distance to p. */
+static int nearest_seed(const seeds_t *S, int i, int64_t px, int64_t py, int64_t *qx, int64_t *qy)
+{
+    int64_t h = level_spacing(S, i);
+    int64_t bx = floor_div(px, h), by = floor_div(py, h);
+    uint64_t best = UINT64_MAX;
+    for (int dx = -1; dx <= 1; ++dx) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            int64_t sx, sy;
+            if (!seed_point(S, i, bx + dx, by + dy, &sx, &sy)) continue;
+            uint64_t d = (uint64_t)((sx - px) * (sx - px) + (sy - py) * (sy - py));
+            if (d < best) {
+                best = d;
+                *qx = sx;
+                *qy = sy;
+            }
+        }
+    }
+    return best != UINT64_MAX;
+}
+
+int ora_seed_point(int w, int h, int levels, int finest, const uint32_t *jitter, int level,
+                   int64_t bx, int64_t by, int64_t *sx, int64_t *sy)
+{
+    seeds_t S = {w, h, levels, finest, jitter};
+    return seed_point(&S, level, bx, by, sx, sy);
+}
+
+int ora_nearest_seed(int w, int h, int levels, int finest, const uint32_t *jitter, int level,
+                     int64_t px, int64_t py, int64_t *qx, int64_t *qy)
+{
+    seeds_t S = {w, h, levels, finest, jitter};
+    return nearest_seed(&S, level, px, py, qx, qy);
+}
+
+/* ------------------------------------------ per-pixel level loop (Alg. 2) */
+
+typedef struct {
+    const void *src_guide;
+    int sw, sh;
+    const uint32_t *lut;
+    int fmt, lut_bits;
+    const void *tgt_guide;
+    seeds_t seeds;
+    uint32_t threshold;
+} assign_t;
+
+static uint32_t lut_lookup(const assign_t *A, int64_t g0, int64_t g1)
+{
+    int64_t n = (int64_t)1 << A->lut_bits;
+    return A->lut[lut_quantise(g1, A->fmt, A->lut_bits) * n + lut_quantise(g0, A->fmt, A->lut_bits)];
+}
+
+/* ParallelStyleBlit for one pixel, with colours replaced by coordinates:
+ * returns the source coordinate (x | y << 16) and the chunk code
+ * (level << 26) | (qy << 13) | qx. */
+static void assign_pixel(const assign_t *A, int64_t px, int64_t py, uint32_t *nnf, uint32_t *chunk)
+{
+    const int W = A->seeds.w;
+    int64_t t0, t1;
+    guide_read(A->tgt_guide, A->fmt, py * W + px, &t0, &t1);
+    for (int i = 0; i < A->seeds.levels; ++i) {
+        int64_t qx, qy;
+        if (!nearest_seed(&A->seeds, i, px, py, &qx, &qy)) continue;
+        int64_t q0, q1;
+        guide_read(A->tgt_guide, A->fmt, qy * W + qx, &q0, &q1);
+        uint32_t u = lut_lookup(A, q0, q1);
+        int64_t vx = (int64_t)(u & 0xFFFFu) + (px - qx);
+        int64_t vy = (int64_t)(u >> 16) + (py - qy);
+        if (vx < 0 || vy < 0 || vx >= A->sw || vy >= A->sh) continue;
+        int64_t s0, s1;
+        guide_read(A->src_guide, A->fmt, vy * A->sw + vx, &s0, &s1);
+        uint64_t e = (uint64_t)((t0 - s0) * (t0 - s0)) + (uint64_t)((t1 - s1) * (t1 - s1));
+        if (e < (uint64_t)A->threshold) {
+            *nnf = (uint32_t)vx | ((uint32_t)vy << 16);
+            *chunk = ((uint32_t)i << 26) | ((uint32_t)qy << 13) | (uint32_t)qx;
+            return;
+        }
+    }
+    *nnf = lut_lookup(A, t0, t1);
+    *chunk = ((uint32_t)A->seeds.levels << 26) | ((uint32_t)py << 13) | (uint32_t)px;
+}
+
+static int check_common(int sw, int sh, int fmt, int lut_bits, int w, int h, int levels, int finest)
+{
+    if (sw < 1 || sh < 1 || sw > 8192 || sh > 8192) return ORA_EINVAL;
+    if (w < 1 || h < 1 || w > 8192 || h > 8192) return ORA_EINVAL;
+    if (fmt != 0 && fmt != 1) return ORA_EINVAL;
+    if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
+    if (levels < 0 || levels > 12) return ORA_EINVAL;
+    if (finest < 1 || (finest & (finest - 1)) != 0) return ORA_EINVAL;
+    if (levels > 0 && ((int64_t)finest << (levels - 1)) > 8192) return ORA_EINVAL;
+    return ORA_OK;
+}
+
+int ora_assign(const void *src_guide, int sw, int sh, const uint32_t *lut, int fmt, int lut_bits,
+               const void *tgt_guide, int w, int h, const uint32_t *jitter, int levels, int finest,
+               uint32_t threshold, uint32_t *out_nnf, uint32_t *out_chunk, int64_t row0, int64_t rows)
+{
+    int rc = check_common(sw, sh, fmt, lut_bits, w, h, levels, finest);
+    if (rc) return rc;
+    if (!src_guide || !lut || !tgt_guide || !out_nnf || !out_chunk) return ORA_EINVAL;
+    if (levels > 0 && !jitter) return ORA_EINVAL;
+    if (rows < 0) rows = h;
+    if (row0 < 0 || row0 + rows > h) return ORA_EINVAL;
+    assign_t A = {src_guide, sw, sh, lut, fmt, lut_bits, tgt_guide, {w, h, levels, finest, jitter},
+                  threshold};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t y = row0; y < row0 + rows; ++y)
+        for (int64_t x = 0; x < w; ++x)
+            assign_pixel(&A, x, y, &out_nnf[y * w + x], &out_chunk[y * w + x]);
+    return ORA_OK;
+}
+
+/* ------------------------------------------------ voting blend (Sec. 3.2) */
+
+/* C_T[p] = average over target pixels n in the (2r+1)^2 window around p of
+ * C_S[NNF[n] + (p - n)], counting only co-located pixels inside the source. */
+int ora_blend(const uint8_t *src_rgb, int sw, int sh, const uint32_t *nnf, int w, int h, int radius,
+              uint8_t *out_rgb, int64_t row0, int64_t rows)
+{
+    if (!src_rgb || !nnf || !out_rgb || radius < 0 || radius > 16) return ORA_EINVAL;
+    if (sw < 1 || sh < 1 || w < 1 || h < 1) return ORA_EINVAL;
+    if (rows < 0) rows = h;
+    if (row0 < 0 || row0 + rows > h) return ORA_EINVAL;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t py = row0; py < row0 + rows; ++py) {
+        for (int64_t px = 0; px < w; ++px) {
+            uint64_t sum[3] = {0, 0, 0};
+            uint64_t k = 0;
+            for (int64_t ny = py - radius; ny <= py + radius; ++ny) {
+                for (int64_t nx = px - radius; nx <= px + radius; ++nx) {
+                    if (nx < 0 || ny < 0 || nx >= w || ny >= h) continue;
+                    uint32_t v = nnf[ny * w + nx];
+                    int64_t sx = (int64_t)(v & 0xFFFFu) + (px - nx);
+                    int64_t sy = (int64_t)(v >> 16) + (py - ny);
+                    if (sx < 0 || sy < 0 || sx >= sw || sy >= sh) continue;
+                    const uint8_t *c = &src_rgb[3 * (sy * sw + sx)];
+                    sum[0] += c[0];
+                    sum[1] += c[1];
+                    sum[2] += c[2];
+                    k++;
+                }
+            }
+            uint8_t *o = &out_rgb[3 * (py * w + px)];
+            /* k >= 1 whenever NNF[p] itself lies in the source, which the
+             * level loop guarantees; a foreign NNF without it yields 0. */
+            for (int c = 0; c < 3; ++c) o[c] = k ? (uint8_t)((sum[c] + k / 2) / k) : 0;
+        }
+    }
+    return ORA_OK;
+}
+
+/* ------------------------------------------------------------ whole path */
+
+int ora_stylize(const uint8_t *src_rgb, const void *src_guide, int sw, int sh, const uint32_t *lut,
+                int fmt, int lut_bits, const void *tgt_guide, int w, int h, const uint32_t *jitter,
+                int levels, int finest, uint32_t threshold, int radius, uint8_t *out_rgb,
+                uint32_t *out_chunk, uint32_t *out_nnf)
+{
+    if (!out_rgb || !out_chunk) return ORA_EINVAL;
+    uint32_t *nnf = out_nnf ? out_nnf : (uint32_t *)malloc((size_t)w * h * sizeof(uint32_t));
+    if (!nnf) return ORA_ENOMEM;
+    int rc = ora_assign(src_guide, sw, sh, lut, fmt, lut_bits, tgt_guide, w, h, jitter, levels,
+                        finest, threshold, nnf, out_chunk, 0, -1);
+    if (rc == ORA_OK) rc = ora_blend(src_rgb, sw, sh, nnf, w, h, radius, out_rgb, 0, -1);
+    if (!out_nnf) free(nnf);
+    return rc;
+}
