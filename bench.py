@@ -1,0 +1,169 @@
+"""Benchmark of the StyleBlit hot path on one MI355X.
+
+A step is one frame through the whole per-frame path (seed staging, the
+per-pixel level loop of Algorithm 2 and the voting blend), with the style
+(exemplar, guide and lookup table) already resident, as it is across frames
+in use.  The style's lookup-table build runs once before timing and is
+reported separately.
+
+Default workload: the 1920x1080 normal-guided frame (512x512 sphere
+exemplar, 4 levels of spacing 64..8, threshold 32, radius 3).  Inputs and
+outputs rotate over enough buffer sets (> 512 MB) that each step reads its
+guide from HBM rather than from the 256 MB Infinity Cache.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(w, h, fmt, sw, sh, nseeds):
+    """Bytes the method must move per frame: target guide read, RGB and chunk
+    map written, the exemplar (RGB + guide) read once, and one lookup-table
+    entry per seed."""
+    gb = 2 if fmt == 0 else 4
+    return w * h * (gb + 3 + 4) + sw * sh * (3 + gb) + 4 * nseeds
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rotate-mb", type=float, default=600.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(frames are independent: see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1807_03249_amd as sb
+    import workloads
+
+    torch.cuda.set_device(0)
+    styles, frames = workloads.config(args.workload)
+    st_np, fr = styles[0], frames[0]
+    p = fr.params
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
+    w, h = fr.w, fr.h
+
+    # style registration (lookup table on the device), timed once
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    style = sb.Style(st_np.rgb, st_np.guide, st_np.lut_bits)
+    torch.cuda.synchronize()
+    lut_ms = (time.perf_counter() - t0) * 1e3
+
+    # rotating buffer sets
+    g_np = fr.guide.view(np.int16) if fr.guide.dtype == np.uint16 else fr.guide
+    guide0 = torch.from_numpy(g_np).cuda()
+    jit = torch.from_numpy(fr.jitter.view(np.int32)).cuda()
+    wsb = sb.workspace_bytes(w, h, prm)
+    per_set = guide0.numel() * guide0.element_size() + w * h * 3 + w * h * 4 + wsb
+    nsets = max(2, int(args.rotate_mb * 1e6 // per_set) + 1)
+    sets = []
+    for _ in range(nsets):
+        sets.append((guide0.clone(), torch.empty((h, w, 3), dtype=torch.uint8, device="cuda"),
+                     torch.empty((h, w), dtype=torch.int32, device="cuda"),
+                     torch.empty(wsb, dtype=torch.uint8, device="cuda")))
+    torch.cuda.synchronize()
+
+    def step(k):
+        g, o_rgb, o_chunk, ws = sets[k % nsets]
+        sb.stylize(style, g, jit, prm, out_rgb=o_rgb, out_chunk=o_chunk, workspace=ws)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    mpx_s = w * h * args.steps / elapsed / 1e6
+
+    # per-launch duration with HIP events on the launch stream
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        step(k)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    durs = sorted(a.elapsed_time(b) for a, b in evs)
+    kern_ms = sum(durs) / len(durs)
+    nseeds = sb.jitter_len(w, h, p.levels, p.finest)
+    abytes = algorithmic_bytes(w, h, st_np.fmt, st_np.sw, st_np.sh, nseeds)
+    achieved = abytes / (kern_ms * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        lut = oracle.lut_build(st_np.guide, st_np.lut_bits)
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        n = 0
+        c0 = time.perf_counter()
+        while True:
+            oracle.stylize(st_np.rgb, st_np.guide, lut, st_np.lut_bits, fr.guide, fr.jitter,
+                           p.levels, p.finest, p.threshold, p.radius)
+            n += 1
+            if time.perf_counter() - c0 >= args.cpu_seconds or n >= 200:
+                break
+        csec = time.perf_counter() - c0
+        cpu = {"value": round(w * h * n / csec / 1e6, 3), "unit": "Mpixel/s", "cores": nthreads,
+               "kind": "oracle",
+               "sample": f"{n} full {w}x{h} frames (lookup table built once, not timed)"}
+
+    line = {
+        "metric": "stylized Mpixel/s at 1080p (HBM GB/s and frame latency alongside)",
+        "value": round(mpx_s, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8" if st_np.fmt == 0 else "u16",
+        "data": "synthetic",
+        "config": {"workload": workloads.CONFIG_NAMES[args.workload], "width": w, "height": h,
+                   "source": f"{st_np.sw}x{st_np.sh}", "levels": p.levels, "finest": p.finest,
+                   "threshold": p.threshold, "radius": p.radius, "buffer_sets": nsets},
+        "frame_latency_ms": {"p50": round(durs[len(durs) // 2], 6),
+                             "p99": round(durs[min(len(durs) - 1, int(0.99 * len(durs)))], 6)},
+        "hbm_gbs_algorithmic": round(achieved, 2),
+        "lut_build_ms": round(lut_ms, 3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel_ms": round(kern_ms, 6), "algorithmic_bytes": abytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -49,7 +49,7 @@ typedef enum { SB_GUIDE_U8X2 = 0, SB_GUIDE_U16X2 = 1 } sb_guide_fmt;
 /* Largest target and source side, and limits of the parameters. */
 #define SB_MAX_SIDE 8192
 #define SB_MAX_LEVELS 12
-#define SB_MAX_RADIUS 8
+#define SB_MAX_RADIUS 7
 #define SB_MAX_LUT_BITS 12
 
 /* A style: the exemplar C_S, its guide G_S and the lookup table built from

@@ -1,0 +1,218 @@
+"""MI355X (gfx950) StyleBlit: Python binding of ``libstyleblit.so``.
+
+Argument marshalling only: every step of the path runs in the HIP kernels
+behind the C ABI declared in ``include/styleblit.h``.  PyTorch supplies device
+memory (tensors) and the current HIP stream.  There is no CPU fallback: if
+the library is not built or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstyleblit.so")
+
+GUIDE_U8X2 = 0
+GUIDE_U16X2 = 1
+MAX_SIDE = 8192
+MAX_LEVELS = 12
+MAX_RADIUS = 7
+MAX_LUT_BITS = 12
+
+SB_OK, SB_EINVAL, SB_ENOMEM, SB_EHIP, SB_EBUDGET = 0, -1, -2, -3, -4
+
+
+class StyleBlitError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})" + (f": {detail}" if detail else ""))
+
+
+class SbStyle(ctypes.Structure):
+    _fields_ = [("rgba", ctypes.c_void_p), ("guide", ctypes.c_void_p), ("lut", ctypes.c_void_p),
+                ("sw", ctypes.c_int32), ("sh", ctypes.c_int32), ("fmt", ctypes.c_int32),
+                ("lut_bits", ctypes.c_int32)]
+
+
+class SbParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("finest", ctypes.c_int32),
+                ("threshold", ctypes.c_uint32), ("radius", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C-ABI library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1807_03249_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+    L.sb_version.restype = ctypes.c_char_p
+    L.sb_status_string.restype = ctypes.c_char_p
+    L.sb_status_string.argtypes = [ctypes.c_int]
+    L.sb_last_hip_error.restype = ctypes.c_char_p
+    L.sb_jitter_len.restype = ctypes.c_int64
+    L.sb_jitter_len.argtypes = [i32, i32, i32, i32]
+    L.sb_pack_exemplar.argtypes = [vp, i32, i32, vp, vp]
+    L.sb_lut_workspace_bytes.restype = sz
+    L.sb_lut_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.sb_lut_build.argtypes = [vp, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.sb_workspace_bytes.restype = sz
+    L.sb_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(SbParams)]
+    L.sb_stylize.argtypes = [ctypes.POINTER(SbStyle), vp, i32, i32, vp, ctypes.POINTER(SbParams),
+                             vp, vp, vp, vp, sz, vp]
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    return lib().sb_status_string(status).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != SB_OK:
+        detail = lib().sb_last_hip_error().decode() if rc == SB_EHIP else ""
+        raise StyleBlitError(rc, where, detail)
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("StyleBlit needs a HIP device; none is visible")
+    return torch
+
+
+def _stream(torch) -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(torch, a, dtype=None):
+    """Device tensor (contiguous) from a numpy array or tensor."""
+    if isinstance(a, torch.Tensor):
+        t = a
+    else:
+        t = torch.from_numpy(a)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return t.to("cuda", non_blocking=False).contiguous()
+
+
+def jitter_len(w: int, h: int, levels: int, finest: int) -> int:
+    n = lib().sb_jitter_len(w, h, levels, finest)
+    if n < 0:
+        raise StyleBlitError(SB_EINVAL, "jitter_len")
+    return int(n)
+
+
+def params(levels: int, finest: int, threshold: int, radius: int) -> SbParams:
+    return SbParams(int(levels), int(finest), int(threshold), int(radius))
+
+
+def _guide_fmt(torch, g) -> int:
+    if g.dtype == torch.uint8:
+        return GUIDE_U8X2
+    if g.dtype in (torch.uint16, torch.int16):
+        return GUIDE_U16X2
+    raise TypeError("guides are uint8 or uint16 with two channels")
+
+
+class Style:
+    """A device-resident style: RGBA-packed exemplar, its guide and the lookup
+    table built from it on the GPU (Sec. 3.1)."""
+
+    def __init__(self, rgb, guide, lut_bits: int, stream=None):
+        torch = _torch()
+        self.rgb = _dev(torch, rgb)
+        if self.rgb.dtype != torch.uint8 or self.rgb.dim() != 3 or self.rgb.shape[2] != 3:
+            raise TypeError("exemplar must be uint8 (rows, cols, 3)")
+        g = guide
+        if not isinstance(g, torch.Tensor) and getattr(g, "dtype", None) is not None and str(g.dtype) == "uint16":
+            g = g.view("int16")  # torch.from_numpy has no uint16 on every build; same bits
+        self.guide = _dev(torch, g)
+        if self.guide.dim() != 3 or self.guide.shape[2] != 2:
+            raise TypeError("guide must be (rows, cols, 2)")
+        self.fmt = _guide_fmt(torch, self.guide)
+        self.sh, self.sw = int(self.rgb.shape[0]), int(self.rgb.shape[1])
+        if tuple(self.guide.shape[:2]) != (self.sh, self.sw):
+            raise ValueError("exemplar and guide sizes differ")
+        self.lut_bits = int(lut_bits)
+        L = lib()
+        s = _stream(torch) if stream is None else stream
+        self.rgba = torch.empty((self.sh, self.sw), dtype=torch.int32, device="cuda")
+        _check(L.sb_pack_exemplar(self.rgb.data_ptr(), self.sw, self.sh, self.rgba.data_ptr(), s),
+               "sb_pack_exemplar")
+        wsb = L.sb_lut_workspace_bytes(self.fmt, self.sw, self.sh, self.lut_bits)
+        if wsb == 0:
+            raise StyleBlitError(SB_EINVAL, "sb_lut_workspace_bytes")
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        self.lut = torch.empty(1 << (2 * self.lut_bits), dtype=torch.int32, device="cuda")
+        _check(L.sb_lut_build(self.guide.data_ptr(), self.fmt, self.sw, self.sh, self.lut_bits,
+                              self.lut.data_ptr(), ws.data_ptr(), wsb, s), "sb_lut_build")
+        self._ws = ws  # keep alive until the enqueued build has run
+        self.c = SbStyle(self.rgba.data_ptr(), self.guide.data_ptr(), self.lut.data_ptr(),
+                         self.sw, self.sh, self.fmt, self.lut_bits)
+
+    def resident_bytes(self) -> int:
+        return (self.rgba.numel() * 4 + self.guide.numel() * self.guide.element_size()
+                + self.lut.numel() * 4)
+
+
+def workspace_bytes(w: int, h: int, p: SbParams) -> int:
+    n = lib().sb_workspace_bytes(w, h, ctypes.byref(p))
+    if n == 0:
+        raise StyleBlitError(SB_EINVAL, "sb_workspace_bytes")
+    return int(n)
+
+
+def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chunk=None,
+            want_nnf: bool = False, workspace=None, stream=None):
+    """Stylise one frame.  ``tgt_guide`` (H, W, 2) and ``jitter`` (uint32 as
+    int32 bits) may be numpy arrays or device tensors.  Returns
+    ``(rgb (H,W,3) uint8, chunk (H,W) int32-bits[, nnf])`` as device tensors;
+    the work is enqueued on the current stream."""
+    torch = _torch()
+    g = tgt_guide
+    if not isinstance(g, torch.Tensor) and str(getattr(g, "dtype", "")) == "uint16":
+        g = g.view("int16")
+    g = _dev(torch, g)
+    if g.dim() != 3 or g.shape[2] != 2:
+        raise TypeError("target guide must be (rows, cols, 2)")
+    if _guide_fmt(torch, g) != style.fmt:
+        raise TypeError("target guide format differs from the style's guide format")
+    h, w = int(g.shape[0]), int(g.shape[1])
+    nj = jitter_len(w, h, p.levels, p.finest)
+    if jitter is None:  # seeds on the cell corners
+        j = torch.zeros(max(nj, 1), dtype=torch.int32, device="cuda")
+    else:
+        j = jitter
+        if not isinstance(j, torch.Tensor):
+            j = j.view("int32") if str(j.dtype) == "uint32" else j
+        j = _dev(torch, j)
+        if j.numel() < nj or j.element_size() != 4:
+            raise ValueError(f"jitter table needs {nj} 32-bit entries, got {j.numel()}")
+        if j.numel() == 0:
+            j = torch.zeros(1, dtype=torch.int32, device="cuda")
+    if out_rgb is None:
+        out_rgb = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
+    if out_chunk is None:
+        out_chunk = torch.empty((h, w), dtype=torch.int32, device="cuda")
+    if out_rgb.numel() != h * w * 3 or out_rgb.dtype != torch.uint8 or out_chunk.numel() != h * w:
+        raise ValueError("output tensors do not match the frame size")
+    nnf = torch.empty((h, w), dtype=torch.int32, device="cuda") if want_nnf else None
+    wsb = workspace_bytes(w, h, p)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    s = _stream(torch) if stream is None else stream
+    _check(lib().sb_stylize(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(), ctypes.byref(p),
+                            out_rgb.data_ptr(), out_chunk.data_ptr(),
+                            nnf.data_ptr() if nnf is not None else None, workspace.data_ptr(), wsb, s),
+           "sb_stylize")
+    if want_nnf:
+        return out_rgb, out_chunk, nnf
+    return out_rgb, out_chunk

@@ -1,0 +1,172 @@
+// capi.hip -- the C ABI (include/styleblit.h): argument validation, workspace
+// carving and kernel dispatch.  No device memory is allocated here; every
+// buffer comes from the caller.
+#include <stdio.h>
+#include <string.h>
+
+#include "sb_internal.h"
+
+namespace sb {
+
+namespace {
+thread_local char g_err[256] = "";
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int32_t ilog2(int32_t v) {
+  int32_t l = 0;
+  while ((int32_t(1) << (l + 1)) <= v) ++l;
+  return l;
+}
+
+bool side_ok(int32_t v) { return v >= 1 && v <= SB_MAX_SIDE; }
+
+bool style_ok(const sb_style *s) {
+  if (!s || !s->rgba || !s->guide || !s->lut) return false;
+  if (!side_ok(s->sw) || !side_ok(s->sh)) return false;
+  if (s->fmt != SB_GUIDE_U8X2 && s->fmt != SB_GUIDE_U16X2) return false;
+  const int32_t depth = s->fmt == SB_GUIDE_U8X2 ? 8 : 16;
+  return s->lut_bits >= 1 && s->lut_bits <= depth && s->lut_bits <= SB_MAX_LUT_BITS;
+}
+
+bool params_ok(const sb_params *p) {
+  if (!p) return false;
+  if (p->radius < 0 || p->radius > SB_MAX_RADIUS) return false;
+  Levels lv;
+  return make_levels(1, 1, p->levels, p->finest, &lv);
+}
+}  // namespace
+
+void set_error_text(const char *msg) { snprintf(g_err, sizeof g_err, "%s", msg); }
+
+void set_hip_error(hipError_t e, const char *where) {
+  snprintf(g_err, sizeof g_err, "%s: %s (%d)", where, hipGetErrorString(e), int(e));
+}
+
+bool make_levels(int32_t w, int32_t h, int32_t levels, int32_t finest, Levels *out) {
+  if (levels < 0 || levels > SB_MAX_LEVELS) return false;
+  if (finest < 1 || (finest & (finest - 1)) != 0) return false;
+  const int32_t lf = ilog2(finest);
+  if (levels > 0 && lf + levels - 1 > ilog2(SB_MAX_SIDE)) return false;
+  memset(out, 0, sizeof *out);
+  out->count = levels;
+  int32_t off = 0;
+  for (int32_t i = 0; i < levels; ++i) {
+    const int32_t ls = lf + (levels - 1 - i);
+    const int32_t sp = int32_t(1) << ls;
+    out->log2_spacing[i] = ls;
+    out->cells_x[i] = (w + sp - 1) / sp;
+    out->cells_y[i] = (h + sp - 1) / sp;
+    out->offset[i] = off;
+    off += out->cells_x[i] * out->cells_y[i];
+  }
+  out->offset[levels] = off;
+  return true;
+}
+
+}  // namespace sb
+
+using namespace sb;
+
+extern "C" {
+
+const char *sb_version(void) { return "styleblit-gfx950 0.1"; }
+
+const char *sb_status_string(int status) {
+  switch (status) {
+    case SB_OK: return "ok";
+    case SB_EINVAL: return "invalid argument";
+    case SB_ENOMEM: return "workspace too small or host allocation failed";
+    case SB_EHIP: return "HIP error";
+    case SB_EBUDGET: return "request exceeds the memory budget";
+    default: return "unknown status";
+  }
+}
+
+const char *sb_last_hip_error(void) { return g_err; }
+
+int64_t sb_jitter_len(int32_t w, int32_t h, int32_t levels, int32_t finest) {
+  Levels lv;
+  if (!side_ok(w) || !side_ok(h) || !make_levels(w, h, levels, finest, &lv)) return -1;
+  return lv.offset[levels];
+}
+
+int sb_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t *rgba,
+                     hipStream_t stream) {
+  if (!rgb || !rgba || !side_ok(sw) || !side_ok(sh)) return SB_EINVAL;
+  hipError_t e = launch_pack_exemplar(rgb, sw, sh, rgba, stream);
+  if (e != hipSuccess) {
+    set_hip_error(e, "sb_pack_exemplar");
+    return SB_EHIP;
+  }
+  return SB_OK;
+}
+
+size_t sb_lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits) {
+  if ((fmt != SB_GUIDE_U8X2 && fmt != SB_GUIDE_U16X2) || !side_ok(sw) || !side_ok(sh)) return 0;
+  const int32_t depth = fmt == SB_GUIDE_U8X2 ? 8 : 16;
+  if (lut_bits < 1 || lut_bits > depth || lut_bits > SB_MAX_LUT_BITS) return 0;
+  return lut_workspace_bytes(fmt, sw, sh, lut_bits);
+}
+
+int sb_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
+                 uint32_t *lut, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!guide || !lut || !workspace) return SB_EINVAL;
+  const size_t need = sb_lut_workspace_bytes(fmt, sw, sh, lut_bits);
+  if (need == 0) return SB_EINVAL;
+  if (workspace_bytes < need) return SB_ENOMEM;
+  hipError_t e = launch_lut_build(guide, fmt, sw, sh, lut_bits, lut, workspace, stream);
+  if (e != hipSuccess) {
+    set_hip_error(e, "sb_lut_build");
+    return SB_EHIP;
+  }
+  return SB_OK;
+}
+
+size_t sb_workspace_bytes(int32_t w, int32_t h, const sb_params *params) {
+  if (!side_ok(w) || !side_ok(h) || !params_ok(params)) return 0;
+  Levels lv;
+  make_levels(w, h, params->levels, params->finest, &lv);
+  return align256(size_t(lv.offset[lv.count]) * 8 + 8) + align256(size_t(w) * size_t(h) * 4);
+}
+
+int sb_stylize(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+               const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+               uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
+               hipStream_t stream) {
+  if (!style_ok(style) || !tgt_guide || !out_rgb || !out_chunk || !workspace) return SB_EINVAL;
+  if (!side_ok(w) || !side_ok(h) || !params_ok(params)) return SB_EINVAL;
+  if (params->levels > 0 && !jitter) return SB_EINVAL;
+  const size_t need = sb_workspace_bytes(w, h, params);
+  if (workspace_bytes < need) return SB_ENOMEM;
+  FrameArgs a;
+  memset(&a, 0, sizeof a);
+  make_levels(w, h, params->levels, params->finest, &a.lv);
+  a.src_rgba = style->rgba;
+  a.src_guide = style->guide;
+  a.lut = style->lut;
+  a.tgt_guide = tgt_guide;
+  a.jitter = jitter;
+  a.out_rgb = out_rgb;
+  a.out_chunk = out_chunk;
+  a.out_nnf = out_nnf;
+  char *ws = static_cast<char *>(workspace);
+  a.seeds = reinterpret_cast<uint2 *>(ws);
+  a.offsets = reinterpret_cast<uint32_t *>(ws + align256(size_t(a.lv.offset[a.lv.count]) * 8 + 8));
+  a.sw = style->sw;
+  a.sh = style->sh;
+  a.w = w;
+  a.h = h;
+  a.lut_bits = style->lut_bits;
+  a.lut_shift = (style->fmt == SB_GUIDE_U8X2 ? 8 : 16) - style->lut_bits;
+  a.threshold = params->threshold;
+  a.radius = params->radius;
+  hipError_t e = launch_stylize(a, style->fmt, stream);
+  if (e != hipSuccess) {
+    set_hip_error(e, "sb_stylize");
+    return SB_EHIP;
+  }
+  return SB_OK;
+}
+
+}  // extern "C"

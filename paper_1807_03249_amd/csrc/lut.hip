@@ -1,0 +1,215 @@
+// lut.hip -- device-side build of the guide-to-source lookup table (Sec. 3.1).
+//
+// LUT[c] = argmin_u |centre(c) - G_S[u]|^2 over all source pixels u, ties to
+// the smallest raster index.  The source pixels are bucketed on a grid whose
+// cells are at least twice as wide as a lookup bin (counting sort: count,
+// scan, scatter), and each bin then searches square rings of buckets around
+// the bucket holding its centre.  After ring k the searched box is known, so
+// every unsearched pixel is at least `gap` away along one axis, where gap is
+// the distance from the centre to the nearest open side of the box; the
+// search ends once the best squared distance is strictly below gap^2 (an
+// equal distance further out could still win the raster-index tie).
+#include "sb_internal.h"
+
+namespace sb {
+namespace {
+
+struct LutGeom {
+  int32_t depth;       // guide bits per channel: 8 or 16
+  int32_t lut_bits;    // bins per channel = 1 << lut_bits
+  int32_t bucket_bits; // buckets per channel = 1 << bucket_bits
+  int32_t npix;
+};
+
+LutGeom lut_geom(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits) {
+  LutGeom g;
+  g.depth = fmt == SB_GUIDE_U8X2 ? 8 : 16;
+  g.lut_bits = lut_bits;
+  g.npix = sw * sh;
+  // about one bucket per few source pixels, never finer than half a bin
+  int32_t side_bits = 0;
+  while ((int64_t(1) << (2 * (side_bits + 1))) <= int64_t(g.npix)) ++side_bits;
+  int32_t bb = side_bits - 1;
+  if (bb > lut_bits - 1) bb = lut_bits - 1;
+  if (bb < 1) bb = 1;
+  if (bb > g.depth) bb = g.depth;
+  g.bucket_bits = bb;
+  return g;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct LutWs {
+  uint32_t *count;  // nb  (counts, then scatter cursors)
+  uint32_t *start;  // nb + 1
+  uint2 *pts;       // npix: {g0 | g1 << 16, raster index}
+};
+
+LutWs lut_ws(void *base, const LutGeom &g) {
+  size_t nb = size_t(1) << (2 * g.bucket_bits);
+  char *p = static_cast<char *>(base);
+  LutWs w;
+  w.count = reinterpret_cast<uint32_t *>(p);
+  p += align256(nb * 4);
+  w.start = reinterpret_cast<uint32_t *>(p);
+  p += align256((nb + 1) * 4);
+  w.pts = reinterpret_cast<uint2 *>(p);
+  return w;
+}
+
+template <int FMT>
+__device__ inline void read_guide(const void *g, uint32_t i, uint32_t &c0, uint32_t &c1) {
+  if (FMT == SB_GUIDE_U8X2) {
+    uint32_t v = static_cast<const uint16_t *>(g)[i];
+    c0 = v & 0xFFu;
+    c1 = v >> 8;
+  } else {
+    uint32_t v = static_cast<const uint32_t *>(g)[i];
+    c0 = v & 0xFFFFu;
+    c1 = v >> 16;
+  }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+template <int FMT>
+__global__ void k_lut_count(const void *guide, int32_t npix, int32_t shift, int32_t bb,
+                            uint32_t *count) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= uint32_t(npix)) return;
+  uint32_t c0, c1;
+  read_guide<FMT>(guide, i, c0, c1);
+  atomicAdd(&count[((c1 >> shift) << bb) | (c0 >> shift)], 1u);
+}
+
+// Exclusive scan of n counts into start[0..n], one workgroup of 1024 threads;
+// each thread owns a contiguous run.  Also turns count[] into the scatter
+// cursors (= start).
+__global__ void __launch_bounds__(1024) k_lut_scan(uint32_t *count, uint32_t *start, uint32_t n) {
+  __shared__ uint32_t part[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (n + 1023) / 1024;
+  const uint32_t b0 = t * per < n ? t * per : n;
+  const uint32_t b1 = b0 + per < n ? b0 + per : n;
+  uint32_t s = 0;
+  for (uint32_t i = b0; i < b1; ++i) s += count[i];
+  part[t] = s;
+  __syncthreads();
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    uint32_t v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;  // exclusive prefix of this thread's run
+  for (uint32_t i = b0; i < b1; ++i) {
+    uint32_t c = count[i];
+    start[i] = run;
+    count[i] = run;
+    run += c;
+  }
+  if (t == 1023) start[n] = part[1023];
+}
+
+template <int FMT>
+__global__ void k_lut_scatter(const void *guide, int32_t npix, int32_t shift, int32_t bb,
+                              uint32_t *cursor, uint2 *pts) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= uint32_t(npix)) return;
+  uint32_t c0, c1;
+  read_guide<FMT>(guide, i, c0, c1);
+  uint32_t pos = atomicAdd(&cursor[((c1 >> shift) << bb) | (c0 >> shift)], 1u);
+  pts[pos] = make_uint2(c0 | (c1 << 16), i);
+}
+
+__global__ void k_lut_query(const uint32_t *start, const uint2 *pts, int32_t lut_bits,
+                            int32_t bin_shift, int32_t bucket_bits, int32_t bucket_shift,
+                            int32_t sw, uint32_t *lut) {
+  const uint32_t nbins = 1u << (2 * lut_bits);
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nbins) return;
+  const uint32_t half = bin_shift ? (1u << (bin_shift - 1)) : 0u;
+  const uint32_t qx = ((c & ((1u << lut_bits) - 1)) << bin_shift) + half;
+  const uint32_t qy = ((c >> lut_bits) << bin_shift) + half;
+  const int32_t nb = 1 << bucket_bits;
+  const int32_t bw = 1 << bucket_shift;  // bucket width in guide units
+  const int32_t bx0 = int32_t(qx >> bucket_shift), by0 = int32_t(qy >> bucket_shift);
+  uint64_t best_d = ~0ull;
+  uint32_t best_i = ~0u;
+  for (int32_t k = 0;; ++k) {
+    const int32_t x0 = bx0 - k, x1 = bx0 + k, y0 = by0 - k, y1 = by0 + k;
+    const int32_t ya = y0 > 0 ? y0 : 0, yb = y1 < nb - 1 ? y1 : nb - 1;
+    for (int32_t by = ya; by <= yb; ++by) {
+      const bool full = (by == y0) || (by == y1);
+      const int32_t step = full ? 1 : (x1 - x0);
+      for (int32_t bx = x0; bx <= x1; bx += (step > 0 ? step : 1)) {
+        if (bx < 0 || bx >= nb) continue;
+        const uint32_t b = (uint32_t(by) << bucket_bits) | uint32_t(bx);
+        const uint32_t e1 = start[b + 1];
+        for (uint32_t e = start[b]; e < e1; ++e) {
+          const uint2 p = pts[e];
+          const int64_t dx = int64_t(qx) - int64_t(p.x & 0xFFFFu);
+          const int64_t dy = int64_t(qy) - int64_t(p.x >> 16);
+          const uint64_t d = uint64_t(dx * dx) + uint64_t(dy * dy);
+          if (d < best_d || (d == best_d && p.y < best_i)) {
+            best_d = d;
+            best_i = p.y;
+          }
+        }
+      }
+    }
+    // distance from the centre to the nearest side of the searched box that
+    // still has buckets beyond it
+    uint32_t gap = ~0u;
+    if (x0 > 0) gap = min(gap, qx - uint32_t(x0 * bw) + 1u);
+    if (x1 < nb - 1) gap = min(gap, uint32_t((x1 + 1) * bw) - qx);
+    if (y0 > 0) gap = min(gap, qy - uint32_t(y0 * bw) + 1u);
+    if (y1 < nb - 1) gap = min(gap, uint32_t((y1 + 1) * bw) - qy);
+    if (gap == ~0u) break;  // every bucket searched
+    if (best_i != ~0u && best_d < uint64_t(gap) * gap) break;
+  }
+  lut[c] = pack_xy(best_i % uint32_t(sw), best_i / uint32_t(sw));
+}
+
+unsigned blocks_for(uint64_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
+
+}  // namespace
+
+size_t lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits) {
+  LutGeom g = lut_geom(fmt, sw, sh, lut_bits);
+  size_t nb = size_t(1) << (2 * g.bucket_bits);
+  return align256(nb * 4) + align256((nb + 1) * 4) + align256(size_t(g.npix) * 8);
+}
+
+hipError_t launch_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh,
+                            int32_t lut_bits, uint32_t *lut, void *workspace, hipStream_t stream) {
+  const LutGeom g = lut_geom(fmt, sw, sh, lut_bits);
+  const LutWs w = lut_ws(workspace, g);
+  const uint32_t nb = 1u << (2 * g.bucket_bits);
+  const int32_t shift = g.depth - g.bucket_bits;
+  k_fill_u32<<<blocks_for(nb, 256) < 4096 ? blocks_for(nb, 256) : 4096, 256, 0, stream>>>(
+      w.count, nb, 0u);
+  if (fmt == SB_GUIDE_U8X2) {
+    k_lut_count<SB_GUIDE_U8X2><<<blocks_for(g.npix, 256), 256, 0, stream>>>(
+        guide, g.npix, shift, g.bucket_bits, w.count);
+  } else {
+    k_lut_count<SB_GUIDE_U16X2><<<blocks_for(g.npix, 256), 256, 0, stream>>>(
+        guide, g.npix, shift, g.bucket_bits, w.count);
+  }
+  k_lut_scan<<<1, 1024, 0, stream>>>(w.count, w.start, nb);
+  if (fmt == SB_GUIDE_U8X2) {
+    k_lut_scatter<SB_GUIDE_U8X2><<<blocks_for(g.npix, 256), 256, 0, stream>>>(
+        guide, g.npix, shift, g.bucket_bits, w.count, w.pts);
+  } else {
+    k_lut_scatter<SB_GUIDE_U16X2><<<blocks_for(g.npix, 256), 256, 0, stream>>>(
+        guide, g.npix, shift, g.bucket_bits, w.count, w.pts);
+  }
+  const uint64_t nbins = uint64_t(1) << (2 * lut_bits);
+  k_lut_query<<<blocks_for(nbins, 256), 256, 0, stream>>>(
+      w.start, w.pts, lut_bits, g.depth - lut_bits, g.bucket_bits, shift, sw, lut);
+  return hipGetLastError();
+}
+
+}  // namespace sb
