@@ -132,6 +132,78 @@ int sb_stylize(const sb_style *style, const void *tgt_guide, int32_t w, int32_t 
                uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
                hipStream_t stream);
 
+/* Kernel choice for one frame.  Every choice computes the same result bit for
+ * bit; they differ only in speed.
+ *   path: SB_PATH_TWO_PASS runs a seed-record pass, a per-pixel level-loop
+ *         pass writing NNF offsets to the workspace, and a voting pass;
+ *         SB_PATH_FUSED runs the whole frame in one kernel (tiles with their
+ *         seed grids, voting halo and outputs staged in LDS); SB_PATH_AUTO is
+ *         the library's default (currently the two-pass path).
+ *   tile: the fused path's tile in pixels (SB_TILE_AUTO = 32x16). */
+typedef enum { SB_PATH_AUTO = 0, SB_PATH_FUSED = 1, SB_PATH_TWO_PASS = 2 } sb_path;
+typedef enum {
+    SB_TILE_AUTO = 0, SB_TILE_32x16 = 1, SB_TILE_32x32 = 2, SB_TILE_64x16 = 3, SB_TILE_64x32 = 4
+} sb_tile;
+typedef struct {
+    int32_t path;   /* sb_path */
+    int32_t tile;   /* sb_tile */
+} sb_tune;
+
+/* sb_stylize with an explicit kernel choice (tune may be NULL = auto).  With a
+ * fused choice the workspace is not touched and may be NULL with size 0;
+ * SB_EINVAL if the requested tile does not fit in 64 KiB of LDS (radius and
+ * finest spacing decide its size). */
+int sb_stylize_ex(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+                  const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+                  uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
+                  size_t workspace_bytes, const sb_tune *tune, hipStream_t stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/* One frame of a batch: the arguments of sb_stylize for that frame. */
+typedef struct {
+    const sb_style *style;      /* [host] */
+    const void *tgt_guide;      /* [device] W*H*2 channels in the style's format */
+    const uint32_t *jitter;     /* [device] sb_jitter_len() entries */
+    int32_t w, h;
+    sb_params params;
+    uint8_t *out_rgb;           /* [device] W*H*3 */
+    uint32_t *out_chunk;        /* [device] W*H */
+    uint32_t *out_nnf;          /* [device, may be NULL] W*H */
+} sb_frame;
+
+typedef struct sb_batch sb_batch;  /* opaque: descriptor buffers and captured graphs */
+
+/* Most frames per batch run. */
+int32_t sb_batch_max_frames(void);
+/* Bytes of the descriptor buffers a plan needs, both on the device and in
+ * pinned host memory (two halves, used alternately by successive runs). */
+size_t sb_batch_desc_bytes(void);
+/* Device workspace for running these frames as one batch (0 if invalid). */
+size_t sb_batch_workspace_bytes(const sb_frame *frames, int32_t n);
+
+/* A batch plan.  desc_dev [device] and desc_host [host, pinned, e.g. from
+ * hipHostMalloc] of sb_batch_desc_bytes() each stay owned by the caller and
+ * must outlive the plan.  With use_graph != 0 the plan captures, once, two
+ * hipGraphs on `stream` (which must not be the null stream): the upload of
+ * one descriptor half followed by three persistent kernels (seed records,
+ * per-pixel level loop, voting) that stride over the concatenated tiles of
+ * all frames of the batch.  The graphs hold no shapes, so they serve every
+ * later batch.  With use_graph == 0 the same upload and kernels are
+ * enqueued directly on each run. */
+int sb_batch_create(void *desc_dev, void *desc_host, int32_t use_graph, hipStream_t stream,
+                    sb_batch **out);
+/* Stylise n frames (1..sb_batch_max_frames()) with one graph launch on
+ * `stream`; the results equal n separate sb_stylize calls bit for bit.
+ * Validates every frame first (SB_EINVAL / SB_ENOMEM and nothing enqueued
+ * on a bad argument).  Blocks only while the run two calls back still reads
+ * the descriptor half this run reuses.  workspace [device] of at least
+ * sb_batch_workspace_bytes() bytes, not shared with a run still in flight. */
+int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace,
+                 size_t workspace_bytes, hipStream_t stream);
+/* Wait for the plan's runs, then release its graphs and events. */
+int sb_batch_destroy(sb_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

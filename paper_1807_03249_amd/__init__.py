@@ -35,9 +35,27 @@ class SbStyle(ctypes.Structure):
                 ("lut_bits", ctypes.c_int32)]
 
 
+class SbTune(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("tile", ctypes.c_int32)]
+
+
+PATH_AUTO, PATH_FUSED, PATH_TWO_PASS = 0, 1, 2
+TILE_AUTO, TILE_32x16, TILE_32x32, TILE_64x16, TILE_64x32 = 0, 1, 2, 3, 4
+# every kernel choice; all compute the same bits
+TUNES = [(PATH_TWO_PASS, TILE_AUTO)] + [(PATH_FUSED, t) for t in
+                                        (TILE_32x16, TILE_32x32, TILE_64x16, TILE_64x32)]
+
+
 class SbParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("finest", ctypes.c_int32),
                 ("threshold", ctypes.c_uint32), ("radius", ctypes.c_int32)]
+
+
+class SbFrame(ctypes.Structure):
+    _fields_ = [("style", ctypes.POINTER(SbStyle)), ("tgt_guide", ctypes.c_void_p),
+                ("jitter", ctypes.c_void_p), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
+                ("params", SbParams), ("out_rgb", ctypes.c_void_p), ("out_chunk", ctypes.c_void_p),
+                ("out_nnf", ctypes.c_void_p)]
 
 
 _lib = None
@@ -66,6 +84,16 @@ def lib():
     L.sb_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(SbParams)]
     L.sb_stylize.argtypes = [ctypes.POINTER(SbStyle), vp, i32, i32, vp, ctypes.POINTER(SbParams),
                              vp, vp, vp, vp, sz, vp]
+    L.sb_stylize_ex.argtypes = [ctypes.POINTER(SbStyle), vp, i32, i32, vp,
+                                ctypes.POINTER(SbParams), vp, vp, vp, vp, sz,
+                                ctypes.POINTER(SbTune), vp]
+    L.sb_batch_max_frames.restype = ctypes.c_int32
+    L.sb_batch_desc_bytes.restype = sz
+    L.sb_batch_workspace_bytes.restype = sz
+    L.sb_batch_workspace_bytes.argtypes = [ctypes.POINTER(SbFrame), i32]
+    L.sb_batch_create.argtypes = [vp, vp, i32, vp, ctypes.POINTER(ctypes.c_void_p)]
+    L.sb_batch_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(SbFrame), i32, vp, sz, vp]
+    L.sb_batch_destroy.argtypes = [ctypes.c_void_p]
     _lib = L
     return L
 
@@ -171,7 +199,7 @@ def workspace_bytes(w: int, h: int, p: SbParams) -> int:
 
 
 def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chunk=None,
-            want_nnf: bool = False, workspace=None, stream=None):
+            want_nnf: bool = False, workspace=None, stream=None, tune=None):
     """Stylise one frame.  ``tgt_guide`` (H, W, 2) and ``jitter`` (uint32 as
     int32 bits) may be numpy arrays or device tensors.  Returns
     ``(rgb (H,W,3) uint8, chunk (H,W) int32-bits[, nnf])`` as device tensors;
@@ -209,10 +237,117 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     s = _stream(torch) if stream is None else stream
-    _check(lib().sb_stylize(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(), ctypes.byref(p),
-                            out_rgb.data_ptr(), out_chunk.data_ptr(),
-                            nnf.data_ptr() if nnf is not None else None, workspace.data_ptr(), wsb, s),
-           "sb_stylize")
+    if tune is None:
+        _check(lib().sb_stylize(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
+                                ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
+                                nnf.data_ptr() if nnf is not None else None,
+                                workspace.data_ptr(), wsb, s), "sb_stylize")
+    else:
+        tn = SbTune(int(tune[0]), int(tune[1]))
+        _check(lib().sb_stylize_ex(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
+                                   ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
+                                   nnf.data_ptr() if nnf is not None else None,
+                                   workspace.data_ptr(), wsb, ctypes.byref(tn), s),
+               "sb_stylize_ex")
     if want_nnf:
         return out_rgb, out_chunk, nnf
     return out_rgb, out_chunk
+
+
+class FrameJob:
+    """One frame of a batch: device tensors for the target guide, jitter and
+    outputs (allocated here when not given)."""
+
+    def __init__(self, style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chunk=None,
+                 out_nnf=None):
+        torch = _torch()
+        g = tgt_guide
+        if not isinstance(g, torch.Tensor) and str(getattr(g, "dtype", "")) == "uint16":
+            g = g.view("int16")
+        self.style = style
+        self.guide = _dev(torch, g)
+        if _guide_fmt(torch, self.guide) != style.fmt:
+            raise TypeError("target guide format differs from the style's guide format")
+        self.h, self.w = int(self.guide.shape[0]), int(self.guide.shape[1])
+        nj = jitter_len(self.w, self.h, p.levels, p.finest)
+        if jitter is None:
+            self.jitter = torch.zeros(max(nj, 1), dtype=torch.int32, device="cuda")
+        else:
+            j = jitter
+            if not isinstance(j, torch.Tensor):
+                j = j.view("int32") if str(j.dtype) == "uint32" else j
+            self.jitter = _dev(torch, j)
+            if self.jitter.numel() < nj:
+                raise ValueError(f"jitter table needs {nj} entries")
+            if self.jitter.numel() == 0:
+                self.jitter = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.params = p
+        self.out_rgb = out_rgb if out_rgb is not None else torch.empty(
+            (self.h, self.w, 3), dtype=torch.uint8, device="cuda")
+        self.out_chunk = out_chunk if out_chunk is not None else torch.empty(
+            (self.h, self.w), dtype=torch.int32, device="cuda")
+        self.out_nnf = out_nnf
+
+    def c(self) -> SbFrame:
+        return SbFrame(ctypes.pointer(self.style.c), self.guide.data_ptr(), self.jitter.data_ptr(),
+                       self.w, self.h, self.params, self.out_rgb.data_ptr(),
+                       self.out_chunk.data_ptr(),
+                       self.out_nnf.data_ptr() if self.out_nnf is not None else None)
+
+
+class Batch:
+    """A batch plan: many frames per launch.  With ``use_graph`` the launch
+    is one replay of a hipGraph captured once (descriptor upload + three
+    persistent kernels) on the plan's own stream."""
+
+    def __init__(self, use_graph: bool = True):
+        torch = _torch()
+        L = lib()
+        nb = L.sb_batch_desc_bytes()
+        self.desc_dev = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        self.desc_host = torch.empty(nb, dtype=torch.uint8).pin_memory()
+        self.capture_stream = torch.cuda.Stream()
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(L.sb_batch_create(self.desc_dev.data_ptr(), self.desc_host.data_ptr(),
+                                 1 if use_graph else 0, self.capture_stream.cuda_stream,
+                                 ctypes.byref(h)), "sb_batch_create")
+        self.handle = h
+        self.max_frames = L.sb_batch_max_frames()
+        self._ws = None
+        self._keep = [None, None]
+        self._k = 0
+
+    def workspace_bytes(self, jobs) -> int:
+        arr = (SbFrame * len(jobs))(*[j.c() for j in jobs])
+        n = lib().sb_batch_workspace_bytes(arr, len(jobs))
+        if n == 0:
+            raise StyleBlitError(SB_EINVAL, "sb_batch_workspace_bytes")
+        return int(n)
+
+    def run(self, jobs, workspace=None, stream=None):
+        torch = _torch()
+        arr = (SbFrame * len(jobs))(*[j.c() for j in jobs])
+        wsb = lib().sb_batch_workspace_bytes(arr, len(jobs))
+        if wsb == 0:
+            raise StyleBlitError(SB_EINVAL, "sb_batch_workspace_bytes")
+        if workspace is None:
+            workspace = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        s = _stream(torch) if stream is None else stream
+        _check(lib().sb_batch_run(self.handle, arr, len(jobs), workspace.data_ptr(), wsb, s),
+               "sb_batch_run")
+        # keep this run's tensors alive until its descriptor half is reused
+        self._keep[self._k] = (jobs, workspace)
+        self._k ^= 1
+        return jobs
+
+    def close(self):
+        if self.handle:
+            _check(lib().sb_batch_destroy(self.handle), "sb_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

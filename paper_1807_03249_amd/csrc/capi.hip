@@ -64,6 +64,41 @@ bool make_levels(int32_t w, int32_t h, int32_t levels, int32_t finest, Levels *o
   return true;
 }
 
+bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+                const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+                uint32_t *out_chunk, uint32_t *out_nnf, FrameArgs *a) {
+  if (!style_ok(style) || !tgt_guide || !out_rgb || !out_chunk) return false;
+  if (!side_ok(w) || !side_ok(h) || !params_ok(params)) return false;
+  if (params->levels > 0 && !jitter) return false;
+  memset(a, 0, sizeof *a);
+  make_levels(w, h, params->levels, params->finest, &a->lv);
+  a->src_rgba = style->rgba;
+  a->src_guide = style->guide;
+  a->lut = style->lut;
+  a->tgt_guide = tgt_guide;
+  a->jitter = jitter;
+  a->out_rgb = out_rgb;
+  a->out_chunk = out_chunk;
+  a->out_nnf = out_nnf;
+  a->sw = style->sw;
+  a->sh = style->sh;
+  a->w = w;
+  a->h = h;
+  a->lut_bits = style->lut_bits;
+  a->lut_shift = (style->fmt == SB_GUIDE_U8X2 ? 8 : 16) - style->lut_bits;
+  a->threshold = params->threshold;
+  a->radius = params->radius;
+  a->fmt = style->fmt;
+  return true;
+}
+
+void carve_workspace(FrameArgs *a, void *workspace) {
+  char *ws = static_cast<char *>(workspace);
+  a->seeds = reinterpret_cast<uint2 *>(ws);
+  a->offsets =
+      reinterpret_cast<uint32_t *>(ws + align256(size_t(a->lv.offset[a->lv.count]) * 8 + 8));
+}
+
 }  // namespace sb
 
 using namespace sb;
@@ -130,43 +165,50 @@ size_t sb_workspace_bytes(int32_t w, int32_t h, const sb_params *params) {
   return align256(size_t(lv.offset[lv.count]) * 8 + 8) + align256(size_t(w) * size_t(h) * 4);
 }
 
-int sb_stylize(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
-               const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
-               uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
-               hipStream_t stream) {
-  if (!style_ok(style) || !tgt_guide || !out_rgb || !out_chunk || !workspace) return SB_EINVAL;
-  if (!side_ok(w) || !side_ok(h) || !params_ok(params)) return SB_EINVAL;
-  if (params->levels > 0 && !jitter) return SB_EINVAL;
-  const size_t need = sb_workspace_bytes(w, h, params);
-  if (workspace_bytes < need) return SB_ENOMEM;
+int sb_stylize_ex(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+                  const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+                  uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
+                  size_t workspace_bytes, const sb_tune *tune, hipStream_t stream) {
   FrameArgs a;
-  memset(&a, 0, sizeof a);
-  make_levels(w, h, params->levels, params->finest, &a.lv);
-  a.src_rgba = style->rgba;
-  a.src_guide = style->guide;
-  a.lut = style->lut;
-  a.tgt_guide = tgt_guide;
-  a.jitter = jitter;
-  a.out_rgb = out_rgb;
-  a.out_chunk = out_chunk;
-  a.out_nnf = out_nnf;
-  char *ws = static_cast<char *>(workspace);
-  a.seeds = reinterpret_cast<uint2 *>(ws);
-  a.offsets = reinterpret_cast<uint32_t *>(ws + align256(size_t(a.lv.offset[a.lv.count]) * 8 + 8));
-  a.sw = style->sw;
-  a.sh = style->sh;
-  a.w = w;
-  a.h = h;
-  a.lut_bits = style->lut_bits;
-  a.lut_shift = (style->fmt == SB_GUIDE_U8X2 ? 8 : 16) - style->lut_bits;
-  a.threshold = params->threshold;
-  a.radius = params->radius;
-  hipError_t e = launch_stylize(a, style->fmt, stream);
+  if (!fill_frame(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf, &a))
+    return SB_EINVAL;
+  const int32_t path = tune ? tune->path : SB_PATH_AUTO;
+  const int32_t tile_req = tune ? tune->tile : SB_TILE_AUTO;
+  if (path < SB_PATH_AUTO || path > SB_PATH_TWO_PASS) return SB_EINVAL;
+  if (tile_req < SB_TILE_AUTO || tile_req > SB_TILE_64x32) return SB_EINVAL;
+  int32_t tile = 0;
+  if (path == SB_PATH_FUSED) {
+    tile = tile_req != SB_TILE_AUTO ? tile_req : int32_t(kTile32x16);
+    if (!frame_tile_fits(a, tile)) return SB_EINVAL;
+  }
+  hipError_t e;
+  if (tile) {
+    e = launch_frame(a, style->fmt, tile, stream);
+  } else {
+    if (!workspace) return SB_EINVAL;
+    if (workspace_bytes < sb_workspace_bytes(w, h, params)) return SB_ENOMEM;
+    carve_workspace(&a, workspace);
+    e = launch_stylize(a, style->fmt, stream);
+  }
   if (e != hipSuccess) {
     set_hip_error(e, "sb_stylize");
     return SB_EHIP;
   }
   return SB_OK;
+}
+
+int sb_stylize(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+               const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+               uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
+               hipStream_t stream) {
+  // the plain entry point keeps one contract whichever path runs: the
+  // workspace must be there and large enough
+  if (!workspace) return SB_EINVAL;
+  const size_t need = sb_workspace_bytes(w, h, params);
+  if (need == 0) return SB_EINVAL;
+  if (workspace_bytes < need) return SB_ENOMEM;
+  return sb_stylize_ex(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf,
+                       workspace, workspace_bytes, nullptr, stream);
 }
 
 }  // extern "C"

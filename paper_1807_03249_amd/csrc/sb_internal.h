@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "styleblit.h"
 
@@ -40,12 +41,51 @@ struct FrameArgs {
   int32_t lut_bits, lut_shift; // lut_shift = guide depth - lut_bits
   uint32_t threshold;
   int32_t radius;
+  int32_t fmt;                 // sb_guide_fmt (read by the batch kernels)
   Levels lv;
+};
+
+// Batch descriptor block in device memory: header, per-pass tile prefix sums
+// (kMaxBatchFrames + 1 entries each: seeds, assign, blend) and the frames.
+constexpr uint32_t kMaxBatchFrames = 128;
+struct BatchHeader {
+  uint32_t nframes, pad[3];
+};
+__host__ __device__ constexpr size_t batch_prefix_offset(int kind) {
+  return 16 + size_t(kind) * (kMaxBatchFrames + 1) * 4;
+}
+__host__ __device__ constexpr size_t batch_frames_offset() {
+  return (batch_prefix_offset(3) + 255) & ~size_t(255);
+}
+__host__ __device__ constexpr size_t batch_desc_bytes() {
+  return batch_frames_offset() + kMaxBatchFrames * sizeof(FrameArgs);
+}
+
+// Fused-path tile shapes (width x height in pixels; 8x8 blocks per wave).
+enum { kTile32x16 = 1, kTile32x32 = 2, kTile64x16 = 3, kTile64x32 = 4 };
+constexpr size_t kMaxLds = 64 * 1024;
+
+// Per-launch geometry of the fused path: the staged seed grid of each level
+// (cells around the tile plus halo plus one ring) and the LDS carve-up.
+struct TileGeom {
+  int32_t grid_w[SB_MAX_LEVELS], grid_h[SB_MAX_LEVELS];
+  int32_t seed_off[SB_MAX_LEVELS + 1];  // in records; seed_off[L] = total
+  int32_t lds_seeds, lds_masks, lds_region, lds_chunk, lds_rgb, lds_vote, lds_bytes;
+  int32_t tiles_x, tiles_y, tile_w, tile_h;
 };
 
 // Fill the level geometry for a W x H frame; false if the parameters are out
 // of range.
 bool make_levels(int32_t w, int32_t h, int32_t levels, int32_t finest, Levels *out);
+
+// Validate one frame's arguments and fill its kernel arguments (workspace
+// pointers are left null).  False on any invalid argument.
+bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+                const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+                uint32_t *out_chunk, uint32_t *out_nnf, FrameArgs *a);
+// Point a frame's seed table and offset map into a workspace of at least
+// sb_workspace_bytes() bytes.
+void carve_workspace(FrameArgs *a, void *workspace);
 
 // Thread-local error text of the last failed HIP call.
 void set_hip_error(hipError_t e, const char *where);
@@ -56,6 +96,12 @@ void set_error_text(const char *msg);
 hipError_t launch_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t *rgba,
                                 hipStream_t stream);
 hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, hipStream_t stream);
+// Tiles of the three two-pass kernels for one frame (seeds, assign, blend).
+void tile_counts(const FrameArgs &a, uint32_t counts[3]);
+// The three passes over a batch described at desc_dev, persistent grids.
+hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, hipStream_t stream);
+bool frame_tile_fits(const FrameArgs &a, int32_t tile);
+hipError_t launch_frame(const FrameArgs &a, int32_t fmt, int32_t tile, hipStream_t stream);
 size_t lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits);
 hipError_t launch_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh,
                             int32_t lut_bits, uint32_t *lut, void *workspace, hipStream_t stream);

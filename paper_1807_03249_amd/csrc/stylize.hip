@@ -53,80 +53,135 @@ __global__ void k_pack_exemplar(const uint8_t *rgb, uint32_t n, uint32_t *rgba) 
   rgba[i] = uint32_t(rgb[3 * i]) | (uint32_t(rgb[3 * i + 1]) << 8) | (uint32_t(rgb[3 * i + 2]) << 16);
 }
 
+// Seed record of table entry idx (idx == total writes the sentinel record
+// that out-of-table cells read).
 template <int FMT>
-__global__ void k_seeds(FrameArgs a) {
-  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
   const Levels &lv = a.lv;
-  if (idx >= uint32_t(lv.offset[lv.count])) return;
-  int32_t i = 0;
-  while (idx >= uint32_t(lv.offset[i + 1])) ++i;
-  const uint32_t local = idx - uint32_t(lv.offset[i]);
-  const uint32_t cx = local % uint32_t(lv.cells_x[i]);
-  const uint32_t cy = local / uint32_t(lv.cells_x[i]);
-  const uint32_t j = a.jitter[idx];
-  const uint32_t sx = (cx << lv.log2_spacing[i]) + (j & 0xFFFFu);
-  const uint32_t sy = (cy << lv.log2_spacing[i]) + (j >> 16);
+  const uint32_t total = uint32_t(lv.offset[lv.count]);
+  if (idx > total) return;
   uint2 rec = make_uint2(kNoSeed, 0u);
-  if (sx < uint32_t(a.w) && sy < uint32_t(a.h)) {
-    const uint32_t g = guide_word<FMT>(a.tgt_guide, sy * uint32_t(a.w) + sx);
-    const uint32_t u = a.lut[lut_bin(g, a.lut_shift, a.lut_bits)];
-    rec.x = pack_xy(sx, sy);
-    rec.y = pack_off(int32_t(u & 0xFFFFu) - int32_t(sx), int32_t(u >> 16) - int32_t(sy));
+  if (idx < total) {
+    int32_t i = 0;
+    while (idx >= uint32_t(lv.offset[i + 1])) ++i;
+    const uint32_t local = idx - uint32_t(lv.offset[i]);
+    const uint32_t cx = local % uint32_t(lv.cells_x[i]);
+    const uint32_t cy = local / uint32_t(lv.cells_x[i]);
+    const uint32_t j = a.jitter[idx];
+    const uint32_t sx = (cx << lv.log2_spacing[i]) + (j & 0xFFFFu);
+    const uint32_t sy = (cy << lv.log2_spacing[i]) + (j >> 16);
+    if (sx < uint32_t(a.w) && sy < uint32_t(a.h)) {
+      const uint32_t g = guide_word<FMT>(a.tgt_guide, sy * uint32_t(a.w) + sx);
+      const uint32_t u = a.lut[lut_bin(g, a.lut_shift, a.lut_bits)];
+      rec.x = pack_xy(sx, sy);
+      rec.y = pack_off(int32_t(u & 0xFFFFu) - int32_t(sx), int32_t(u >> 16) - int32_t(sy));
+    }
   }
   a.seeds[idx] = rec;
 }
 
 template <int FMT>
-__global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
-  const int32_t x = int32_t(blockIdx.x * 16 + (threadIdx.x & 15));
-  const int32_t y = int32_t(blockIdx.y * 16 + (threadIdx.x >> 4));
+__global__ void __launch_bounds__(256) k_seeds(FrameArgs a) {
+  seeds_body<FMT>(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Candidate of one level for pixel (x, y) from the nine seed records around
+// its cell (loaded by the caller, out-of-table cells read the sentinel):
+// NearestSeed's first strict minimum, then the source index to test (0 when
+// the translated coordinate leaves the source, so the gather is issued
+// unconditionally).
+struct LevelCand {
+  bool ok;
+  uint32_t q, off, idx;
+};
+
+__device__ inline LevelCand pick(const uint2 rec[9], int32_t x, int32_t y, int32_t sw, int32_t sh) {
+  uint32_t best = ~0u, bq = 0, bo = 0;
+#pragma unroll
+  for (int32_t k = 0; k < 9; ++k) {  // k = (dx+1)*3 + (dy+1): x outer, y inner
+    const uint32_t ex = (rec[k].x & 0xFFFFu) - uint32_t(x), ey = (rec[k].x >> 16) - uint32_t(y);
+    const uint32_t d = rec[k].x == kNoSeed ? ~0u : ex * ex + ey * ey;
+    if (d < best) {
+      best = d;
+      bq = rec[k].x;
+      bo = rec[k].y;
+    }
+  }
+  LevelCand c;
+  const int32_t vx = x + off_x(bo), vy = y + off_y(bo);
+  c.ok = best != ~0u && uint32_t(vx) < uint32_t(sw) && uint32_t(vy) < uint32_t(sh);
+  c.q = bq;
+  c.off = bo;
+  c.idx = c.ok ? uint32_t(vy) * uint32_t(sw) + uint32_t(vx) : 0u;
+  return c;
+}
+
+__device__ inline void load_level(const FrameArgs &a, int32_t i, int32_t x, int32_t y,
+                                  uint2 rec[9]) {
+  const Levels &lv = a.lv;
+  const int32_t ls = lv.log2_spacing[i];
+  const int32_t bx = x >> ls, by = y >> ls;
+  const int32_t ncx = lv.cells_x[i], ncy = lv.cells_y[i];
+  const uint32_t none = uint32_t(lv.offset[lv.count]);  // the sentinel record
+#pragma unroll
+  for (int32_t k = 0; k < 9; ++k) {
+    const int32_t cx = bx + k / 3 - 1, cy = by + k % 3 - 1;
+    const bool in = cx >= 0 && cy >= 0 && cx < ncx && cy < ncy;
+    rec[k] = a.seeds[in ? uint32_t(lv.offset[i] + cy * ncx + cx) : none];
+  }
+}
+
+// One 16 x 16 pixel tile (tile index row-major over the frame's tiles).
+template <int FMT>
+__device__ inline void assign_body(const FrameArgs &a, uint32_t tile, uint32_t tid) {
+  const uint32_t tiles_x = (uint32_t(a.w) + 15) / 16;
+  const int32_t x = int32_t((tile % tiles_x) * 16 + (tid & 15));
+  const int32_t y = int32_t((tile / tiles_x) * 16 + (tid >> 4));
   if (x >= a.w || y >= a.h) return;
   const uint32_t pidx = uint32_t(y) * uint32_t(a.w) + uint32_t(x);
   const uint32_t gt = guide_word<FMT>(a.tgt_guide, pidx);
-  const Levels &lv = a.lv;
+  const int32_t L = a.lv.count;
   uint32_t chunk = 0, off = 0;
   bool done = false;
-  for (int32_t i = 0; i < lv.count && !done; ++i) {
-    const int32_t ls = lv.log2_spacing[i];
-    const int32_t bx = x >> ls, by = y >> ls;
-    const int32_t ncx = lv.cells_x[i], ncy = lv.cells_y[i];
-    const uint2 *tab = a.seeds + lv.offset[i];
-    uint32_t best = ~0u, bq = 0, bo = 0;
-    for (int32_t dx = -1; dx <= 1; ++dx) {      // NearestSeed: x outer,
-      const int32_t cx = bx + dx;
-      if (cx < 0 || cx >= ncx) continue;
-      for (int32_t dy = -1; dy <= 1; ++dy) {    // y inner, first strict minimum
-        const int32_t cy = by + dy;
-        if (cy < 0 || cy >= ncy) continue;
-        const uint2 rec = tab[cy * ncx + cx];
-        if (rec.x == kNoSeed) continue;
-        const int32_t ex = int32_t(rec.x & 0xFFFFu) - x, ey = int32_t(rec.x >> 16) - y;
-        const uint32_t d = uint32_t(ex * ex + ey * ey);
-        if (d < best) {
-          best = d;
-          bq = rec.x;
-          bo = rec.y;
-        }
-      }
-    }
-    if (best == ~0u) continue;  // no in-image seed around p at this level
-    const int32_t vx = x + off_x(bo), vy = y + off_y(bo);
-    if (uint32_t(vx) >= uint32_t(a.sw) || uint32_t(vy) >= uint32_t(a.sh)) continue;
-    const uint32_t gs = guide_word<FMT>(a.src_guide, uint32_t(vy) * uint32_t(a.sw) + uint32_t(vx));
-    if (error_below(gt, gs, a.threshold)) {
-      chunk = (uint32_t(i) << 26) | ((bq >> 16) << 13) | (bq & 0xFFFFu);
-      off = bo;
+  // two levels per step: their 18 seed records, then both source-guide
+  // gathers, are in flight together
+  for (int32_t i = 0; i < L && !done; i += 2) {
+    uint2 r0[9], r1[9];
+    load_level(a, i, x, y, r0);
+    const bool two = i + 1 < L;
+    if (two) load_level(a, i + 1, x, y, r1);
+    const LevelCand c0 = pick(r0, x, y, a.sw, a.sh);
+    LevelCand c1;
+    c1.ok = false;
+    c1.idx = 0;
+    c1.q = 0;
+    c1.off = 0;
+    if (two) c1 = pick(r1, x, y, a.sw, a.sh);
+    const uint32_t g0 = guide_word<FMT>(a.src_guide, c0.idx);
+    const uint32_t g1 = guide_word<FMT>(a.src_guide, c1.idx);
+    if (c0.ok && error_below(gt, g0, a.threshold)) {
+      chunk = (uint32_t(i) << 26) | ((c0.q >> 16) << 13) | (c0.q & 0xFFFFu);
+      off = c0.off;
+      done = true;
+    } else if (c1.ok && error_below(gt, g1, a.threshold)) {
+      chunk = (uint32_t(i + 1) << 26) | ((c1.q >> 16) << 13) | (c1.q & 0xFFFFu);
+      off = c1.off;
       done = true;
     }
   }
   if (!done) {  // no level accepted: the pixel's own lookup
     const uint32_t u = a.lut[lut_bin(gt, a.lut_shift, a.lut_bits)];
-    chunk = (uint32_t(lv.count) << 26) | (uint32_t(y) << 13) | uint32_t(x);
+    chunk = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
     off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
   }
   a.out_chunk[pidx] = chunk;
   a.offsets[pidx] = off;
   if (a.out_nnf) a.out_nnf[pidx] = pack_xy(uint32_t(x + off_x(off)), uint32_t(y + off_y(off)));
+}
+
+template <int FMT>
+__global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
+  assign_body<FMT>(a, blockIdx.x, threadIdx.x);
 }
 
 // Exact n / k for n < 2^20 and 1 <= k <= 225 via a float reciprocal and one
@@ -141,40 +196,134 @@ __device__ inline uint32_t div_small(uint32_t n, uint32_t k) {
 
 constexpr int kBlendTW = 32, kBlendTH = 8;
 
-__global__ void __launch_bounds__(256) k_blend(FrameArgs a) {
-  extern __shared__ uint32_t tile[];  // (TW + 2r) x (TH + 2r) offsets
+// The votes of one pixel: (2r+1)^2 gathers issued in batches of up to ~25
+// with out-of-source votes reading texel 0 and masked out of the sums.
+template <int R>
+__device__ inline uint32_t vote(const uint32_t *tile, int32_t lw, int32_t lx, int32_t ly,
+                                int32_t x, int32_t y, const uint32_t *rgba, uint32_t sw,
+                                uint32_t sh) {
+  constexpr int W = 2 * R + 1;
+  constexpr int ROWS = W * W <= 25 ? W : (25 / W > 0 ? 25 / W : 1);
+  uint32_t rb = 0, g = 0, k = 0;
+#pragma unroll 1
+  for (int32_t r0 = 0; r0 < W; r0 += ROWS) {
+    uint32_t idx[ROWS * W];
+    bool ok[ROWS * W];
+#pragma unroll
+    for (int32_t q = 0; q < ROWS * W; ++q) {
+      ok[q] = false;
+      idx[q] = 0;
+      if (r0 + q / W < W) {
+        const uint32_t o = tile[(ly + r0 + q / W) * lw + lx + q % W];
+        const int32_t sx = x + off_x(o), sy = y + off_y(o);
+        ok[q] = uint32_t(sx) < sw && uint32_t(sy) < sh;
+        idx[q] = ok[q] ? uint32_t(sy) * sw + uint32_t(sx) : 0u;
+      }
+    }
+    uint32_t t[ROWS * W];
+#pragma unroll
+    for (int32_t q = 0; q < ROWS * W; ++q) t[q] = rgba[idx[q]];
+#pragma unroll
+    for (int32_t q = 0; q < ROWS * W; ++q) {
+      const uint32_t c = ok[q] ? t[q] : 0u;
+      rb += c & 0x00FF00FFu;
+      g += c & 0x0000FF00u;
+      k += ok[q] ? 1u : 0u;
+    }
+  }
+  const uint32_t h = k >> 1;
+  return div_small((rb & 0xFFFFu) + h, k) | (div_small((g >> 8) + h, k) << 8) |
+         (div_small((rb >> 16) + h, k) << 16);
+}
+
+// One 32 x 8 pixel tile; `tile` holds (32 + 2r) x (8 + 2r) offsets in LDS.
+// Ends with all threads past their last LDS read (callers that reuse the
+// tile synchronise before refilling it).
+__device__ inline void blend_body(const FrameArgs &a, uint32_t t_index, uint32_t tid,
+                                  uint32_t *tile) {
   const int32_t r = a.radius;
   const int32_t lw = kBlendTW + 2 * r, lh = kBlendTH + 2 * r;
-  const int32_t x0 = int32_t(blockIdx.x) * kBlendTW - r, y0 = int32_t(blockIdx.y) * kBlendTH - r;
-  for (int32_t t = threadIdx.x; t < lw * lh; t += 256) {
+  const uint32_t tiles_x = (uint32_t(a.w) + kBlendTW - 1) / kBlendTW;
+  const int32_t x0 = int32_t(t_index % tiles_x) * kBlendTW - r;
+  const int32_t y0 = int32_t(t_index / tiles_x) * kBlendTH - r;
+  for (int32_t t = int32_t(tid); t < lw * lh; t += 256) {
     const int32_t tx = x0 + t % lw, ty = y0 + t / lw;
     uint32_t o = kNoVote;
     if (tx >= 0 && ty >= 0 && tx < a.w && ty < a.h) o = a.offsets[uint32_t(ty) * a.w + uint32_t(tx)];
     tile[t] = o;
   }
   __syncthreads();
-  const int32_t lx = threadIdx.x & (kBlendTW - 1), ly = threadIdx.x / kBlendTW;
+  const int32_t lx = int32_t(tid) & (kBlendTW - 1), ly = int32_t(tid) / kBlendTW;
   const int32_t x = x0 + r + lx, y = y0 + r + ly;
   if (x >= a.w || y >= a.h) return;
-  uint32_t rb = 0, g = 0, k = 0;
-  for (int32_t dy = 0; dy <= 2 * r; ++dy) {
-    for (int32_t dx = 0; dx <= 2 * r; ++dx) {
-      const uint32_t o = tile[(ly + dy) * lw + lx + dx];
-      // the neighbour's source patch, co-located with p: p + (NNF[n] - n)
-      const int32_t sx = x + off_x(o), sy = y + off_y(o);
-      if (uint32_t(sx) < uint32_t(a.sw) && uint32_t(sy) < uint32_t(a.sh) && o != kNoVote) {
-        const uint32_t c = a.src_rgba[uint32_t(sy) * uint32_t(a.sw) + uint32_t(sx)];
-        rb += c & 0x00FF00FFu;
-        g += c & 0x0000FF00u;
-        ++k;
-      }
+  const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
+  uint32_t c;
+  switch (r) {
+    case 0: c = vote<0>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+    case 1: c = vote<1>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+    case 2: c = vote<2>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+    case 3: c = vote<3>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+    case 4: c = vote<4>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+    case 5: c = vote<5>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+    case 6: c = vote<6>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+    default: c = vote<7>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+  }
+  uint8_t *o = a.out_rgb + 3 * (uint32_t(y) * uint32_t(a.w) + uint32_t(x));
+  o[0] = uint8_t(c);
+  o[1] = uint8_t(c >> 8);
+  o[2] = uint8_t(c >> 16);
+}
+
+__global__ void __launch_bounds__(256) k_blend(FrameArgs a) {
+  extern __shared__ uint32_t tile[];
+  blend_body(a, blockIdx.x, threadIdx.x, tile);
+}
+
+// ------------------------------------------------------------------ batches
+//
+// A batch runs the same three passes over many frames: each kernel is
+// persistent (a fixed grid striding over the concatenated tiles of all
+// frames) and reads the frames' arguments from a descriptor block in device
+// memory, so one captured graph serves any mix of sizes and formats.
+
+// Frame owning global tile t: the last f with pre[f] <= t (pre in LDS).
+__device__ inline uint32_t frame_of(const uint32_t *pre, uint32_t n, uint32_t t) {
+  uint32_t lo = 0, hi = n;  // pre[lo] <= t < pre[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (pre[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_batch(const unsigned char *desc) {
+  extern __shared__ uint32_t dyn[];  // blend tile
+  __shared__ uint32_t pre[kMaxBatchFrames + 1];
+  const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(desc);
+  const uint32_t n = hd->nframes;
+  const uint32_t *gpre = reinterpret_cast<const uint32_t *>(desc + batch_prefix_offset(KIND));
+  for (uint32_t i = threadIdx.x; i <= n; i += 256) pre[i] = gpre[i];
+  __syncthreads();
+  const FrameArgs *frames = reinterpret_cast<const FrameArgs *>(desc + batch_frames_offset());
+  const uint32_t total = pre[n];
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const uint32_t f = frame_of(pre, n, t);
+    const FrameArgs &a = frames[f];
+    const uint32_t local = t - pre[f];
+    if (KIND == 0) {
+      const uint32_t idx = local * 256 + threadIdx.x;
+      if (a.fmt == SB_GUIDE_U8X2) seeds_body<SB_GUIDE_U8X2>(a, idx);
+      else seeds_body<SB_GUIDE_U16X2>(a, idx);
+    } else if (KIND == 1) {
+      if (a.fmt == SB_GUIDE_U8X2) assign_body<SB_GUIDE_U8X2>(a, local, threadIdx.x);
+      else assign_body<SB_GUIDE_U16X2>(a, local, threadIdx.x);
+    } else {
+      blend_body(a, local, threadIdx.x, dyn);
+      __syncthreads();  // the next tile refills the LDS tile
     }
   }
-  const uint32_t h = k >> 1;
-  uint8_t *o = a.out_rgb + 3 * (uint32_t(y) * uint32_t(a.w) + uint32_t(x));
-  o[0] = uint8_t(div_small((rb & 0xFFFFu) + h, k));
-  o[1] = uint8_t(div_small((g >> 8) + h, k));
-  o[2] = uint8_t(div_small((rb >> 16) + h, k));
 }
 
 unsigned blocks_for(uint64_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
@@ -188,22 +337,33 @@ hipError_t launch_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint
   return hipGetLastError();
 }
 
+void tile_counts(const FrameArgs &a, uint32_t counts[3]) {
+  counts[0] = (uint32_t(a.lv.offset[a.lv.count]) + 1 + 255) / 256;  // + sentinel
+  counts[1] = ((uint32_t(a.w) + 15) / 16) * ((uint32_t(a.h) + 15) / 16);
+  counts[2] = ((uint32_t(a.w) + kBlendTW - 1) / kBlendTW) * ((uint32_t(a.h) + kBlendTH - 1) / kBlendTH);
+}
+
 hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, hipStream_t stream) {
-  const uint32_t ncells = uint32_t(a.lv.offset[a.lv.count]);
-  if (ncells) {
-    if (fmt == SB_GUIDE_U8X2)
-      k_seeds<SB_GUIDE_U8X2><<<blocks_for(ncells, 256), 256, 0, stream>>>(a);
-    else
-      k_seeds<SB_GUIDE_U16X2><<<blocks_for(ncells, 256), 256, 0, stream>>>(a);
-  }
-  dim3 ga(blocks_for(a.w, 16), blocks_for(a.h, 16));
+  uint32_t c[3];
+  tile_counts(a, c);
   if (fmt == SB_GUIDE_U8X2)
-    k_assign<SB_GUIDE_U8X2><<<ga, 256, 0, stream>>>(a);
+    k_seeds<SB_GUIDE_U8X2><<<c[0], 256, 0, stream>>>(a);
   else
-    k_assign<SB_GUIDE_U16X2><<<ga, 256, 0, stream>>>(a);
-  dim3 gb(blocks_for(a.w, kBlendTW), blocks_for(a.h, kBlendTH));
+    k_seeds<SB_GUIDE_U16X2><<<c[0], 256, 0, stream>>>(a);
+  if (fmt == SB_GUIDE_U8X2)
+    k_assign<SB_GUIDE_U8X2><<<c[1], 256, 0, stream>>>(a);
+  else
+    k_assign<SB_GUIDE_U16X2><<<c[1], 256, 0, stream>>>(a);
   const size_t lds = size_t(kBlendTW + 2 * a.radius) * (kBlendTH + 2 * a.radius) * 4;
-  k_blend<<<gb, 256, lds, stream>>>(a);
+  k_blend<<<c[2], 256, lds, stream>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, hipStream_t stream) {
+  const size_t lds = size_t(kBlendTW + 2 * SB_MAX_RADIUS) * (kBlendTH + 2 * SB_MAX_RADIUS) * 4;
+  k_batch<0><<<grid, 256, 0, stream>>>(desc_dev);
+  k_batch<1><<<grid, 256, 0, stream>>>(desc_dev);
+  k_batch<2><<<grid, 256, lds, stream>>>(desc_dev);
   return hipGetLastError();
 }
 

@@ -1,0 +1,154 @@
+"""Batched form on the GPU: many frames of uneven size and mixed guidance in
+one graph launch must equal per-frame launches bit for bit (and the oracle),
+across repeated replays of the same captured graphs."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def sb():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1807_03249_amd as m
+
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def mix(sb):
+    """12 uneven frames, half normal-guided and half UV-guided, 4 styles."""
+    styles_np, frames_np = workloads.config(4, frames=12)
+    styles = [sb.Style(s.rgb, s.guide, s.lut_bits) for s in styles_np]
+    return styles_np, frames_np, styles
+
+
+def jobs_for(sb, styles, frames_np, idx):
+    out = []
+    for i in idx:
+        f = frames_np[i]
+        p = f.params
+        out.append(sb.FrameJob(styles[f.style], f.guide, f.jitter,
+                               sb.params(p.levels, p.finest, p.threshold, p.radius)))
+    return out
+
+
+def single(sb, styles, f):
+    import torch
+
+    p = f.params
+    rgb, chunk = sb.stylize(styles[f.style], f.guide, f.jitter,
+                            sb.params(p.levels, p.finest, p.threshold, p.radius),
+                            tune=(sb.PATH_TWO_PASS, sb.TILE_AUTO))
+    torch.cuda.synchronize()
+    return rgb.cpu().numpy(), chunk.cpu().numpy()
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_equals_single(sb, mix, use_graph):
+    import torch
+
+    styles_np, frames_np, styles = mix
+    b = sb.Batch(use_graph=use_graph)
+    idx = list(range(len(frames_np)))
+    say(f"batch of {len(idx)} graph={use_graph}")
+    jobs = jobs_for(sb, styles, frames_np, idx)
+    b.run(jobs)
+    torch.cuda.synchronize()
+    for i, j in zip(idx, jobs):
+        rgb, chunk = single(sb, styles, frames_np[i])
+        np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), rgb, err_msg=f"frame {i} rgb")
+        np.testing.assert_array_equal(j.out_chunk.cpu().numpy(), chunk, err_msg=f"frame {i} chunk")
+    b.close()
+
+
+def test_batch_matches_oracle(sb, mix):
+    import torch
+
+    styles_np, frames_np, styles = mix
+    b = sb.Batch(use_graph=True)
+    idx = [0, 7]  # one normal-guided, one UV-guided frame
+    jobs = jobs_for(sb, styles, frames_np, idx)
+    b.run(jobs)
+    torch.cuda.synchronize()
+    for i, j in zip(idx, jobs):
+        f = frames_np[i]
+        st = styles_np[f.style]
+        p = f.params
+        say(f"oracle frame {i} {f.w}x{f.h}")
+        lut = oracle.lut_build(st.guide, st.lut_bits)
+        e_rgb, e_chunk, _ = oracle.stylize(st.rgb, st.guide, lut, st.lut_bits, f.guide, f.jitter,
+                                           p.levels, p.finest, p.threshold, p.radius)
+        np.testing.assert_array_equal(j.out_chunk.cpu().numpy().view(np.uint32), e_chunk)
+        np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), e_rgb)
+    b.close()
+
+
+def test_graph_replays_any_shapes(sb, mix):
+    """One plan, many replays with different frame sets and eager work and
+    synchronisation in between; every replay matches the eager results."""
+    import torch
+
+    styles_np, frames_np, styles = mix
+    b = sb.Batch(use_graph=True)
+    expect = {i: single(sb, styles, frames_np[i]) for i in range(len(frames_np))}
+    rng = np.random.default_rng(5)
+    for rep in range(6):
+        idx = sorted(rng.choice(len(frames_np), size=int(rng.integers(1, len(frames_np) + 1)),
+                                replace=False).tolist())
+        say(f"replay {rep}: frames {idx}")
+        jobs = jobs_for(sb, styles, frames_np, idx)
+        b.run(jobs)
+        # eager work on the same device between replays
+        _ = single(sb, styles, frames_np[idx[0]])
+        torch.cuda.synchronize()
+        for i, j in zip(idx, jobs):
+            np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), expect[i][0])
+            np.testing.assert_array_equal(j.out_chunk.cpu().numpy(), expect[i][1])
+    b.close()
+
+
+def test_back_to_back_runs(sb, mix):
+    """Runs enqueued without waiting: the two descriptor halves alternate."""
+    import torch
+
+    styles_np, frames_np, styles = mix
+    b = sb.Batch(use_graph=True)
+    sets = [[0, 1, 2], [3, 4, 5, 6], [7, 8], [9, 10, 11], [0, 6, 11]]
+    runs = []
+    for idx in sets:
+        jobs = jobs_for(sb, styles, frames_np, idx)
+        b.run(jobs)
+        runs.append((idx, jobs))
+    torch.cuda.synchronize()
+    for idx, jobs in runs:
+        for i, j in zip(idx, jobs):
+            rgb, chunk = single(sb, styles, frames_np[i])
+            np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), rgb)
+            np.testing.assert_array_equal(j.out_chunk.cpu().numpy(), chunk)
+    b.close()
+
+
+def test_batch_rejects_bad_frames(sb, mix):
+    import torch
+
+    styles_np, frames_np, styles = mix
+    b = sb.Batch(use_graph=True)
+    jobs = jobs_for(sb, styles, frames_np, [0])
+    bad = sb.FrameJob(styles[0], frames_np[0].guide, frames_np[0].jitter, sb.params(4, 8, 10, 9))
+    with pytest.raises(sb.StyleBlitError):
+        b.run(jobs + [bad])
+    with pytest.raises(sb.StyleBlitError):
+        b.run(jobs * (b.max_frames + 1))
+    torch.cuda.synchronize()
+    b.close()

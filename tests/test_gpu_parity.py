@@ -36,29 +36,44 @@ def u32(t):
     return to_np(t).view(np.uint32)
 
 
-def run_gpu(sb, style_np, lut_bits, frame_guide, jit, levels, finest, t, r, style_obj=None):
+def run_gpu(sb, style_np, lut_bits, frame_guide, jit, levels, finest, t, r, style_obj=None,
+            tune=None):
     import torch
 
     st = style_obj or sb.Style(style_np.rgb, style_np.guide, lut_bits)
     p = sb.params(levels, finest, t, r)
-    rgb, chunk, nnf = sb.stylize(st, frame_guide, jit, p, want_nnf=True)
+    rgb, chunk, nnf = sb.stylize(st, frame_guide, jit, p, want_nnf=True, tune=tune)
     torch.cuda.synchronize()
     return to_np(rgb), u32(chunk), u32(nnf), st
 
 
 def check_frame(sb, st_np, fr_guide, jit, levels, finest, t, r, lut=None, style_obj=None,
-                name=""):
-    say(f"{name} {fr_guide.shape[1]}x{fr_guide.shape[0]} L={levels} f={finest} t={t} r={r}")
+                name="", tunes=(None,)):
     if lut is None:
         lut = oracle.lut_build(st_np.guide, st_np.lut_bits)
     e_rgb, e_chunk, e_nnf = oracle.stylize(st_np.rgb, st_np.guide, lut, st_np.lut_bits, fr_guide,
                                            jit, levels, finest, t, r)
-    g_rgb, g_chunk, g_nnf, st = run_gpu(sb, st_np, st_np.lut_bits, fr_guide, jit, levels, finest,
-                                        t, r, style_obj)
-    np.testing.assert_array_equal(g_chunk, e_chunk, err_msg=f"{name}: chunk map")
-    np.testing.assert_array_equal(g_nnf, e_nnf, err_msg=f"{name}: nnf")
-    np.testing.assert_array_equal(g_rgb, e_rgb, err_msg=f"{name}: rgb")
+    st = style_obj
+    for tune in tunes:
+        say(f"{name} {fr_guide.shape[1]}x{fr_guide.shape[0]} L={levels} f={finest} t={t} r={r} "
+            f"tune={tune}")
+        try:
+            g_rgb, g_chunk, g_nnf, st = run_gpu(sb, st_np, st_np.lut_bits, fr_guide, jit, levels,
+                                                finest, t, r, st, tune)
+        except sb.StyleBlitError as e:
+            # a forced fused tile that does not fit in LDS is refused up front
+            assert tune is not None and tune[0] == sb.PATH_FUSED and e.status == sb.SB_EINVAL
+            say(f"  tile refused: {tune}")
+            continue
+        msg = f"{name} tune={tune}"
+        np.testing.assert_array_equal(g_chunk, e_chunk, err_msg=f"{msg}: chunk map")
+        np.testing.assert_array_equal(g_nnf, e_nnf, err_msg=f"{msg}: nnf")
+        np.testing.assert_array_equal(g_rgb, e_rgb, err_msg=f"{msg}: rgb")
     return st
+
+
+def all_tunes(sb):
+    return [None] + list(sb.TUNES)
 
 
 # ----------------------------------------------------------------- LUT
@@ -119,7 +134,7 @@ def test_workload_frames(sb, n):
     st, fr = styles[0], frames[0]
     p = fr.params
     check_frame(sb, st, fr.guide, fr.jitter, p.levels, p.finest, p.threshold, p.radius,
-                name=f"workload {n}")
+                name=f"workload {n}", tunes=all_tunes(sb))
 
 
 def test_workload2_param_sweep(sb):
@@ -130,7 +145,8 @@ def test_workload2_param_sweep(sb):
     style_obj = None
     for t, r in [(0, 0), (1, 1), (200, 2), (5000, 7), (1 << 31, 3)]:
         style_obj = check_frame(sb, st, fr.guide, fr.jitter, 4, 8, t, r, lut=lut,
-                                style_obj=style_obj, name="workload 2 sweep")
+                                style_obj=style_obj, name="workload 2 sweep",
+                                tunes=[None, sb.TUNES[0]])
 
 
 @pytest.mark.parametrize("seed", range(24))
@@ -157,7 +173,8 @@ def test_random_small(sb, seed):
     jit = workloads.jitter_table(w, h, levels, finest, seed)
     t = int(rng.integers(0, 8 * scale))
     r = int(rng.integers(0, 8))
-    check_frame(sb, st, gt, jit, levels, finest, t, r, name=f"random {seed} u16={u16}")
+    check_frame(sb, st, gt, jit, levels, finest, t, r, name=f"random {seed} u16={u16}",
+                tunes=all_tunes(sb))
 
 
 def test_degenerate_shapes(sb):
@@ -170,16 +187,17 @@ def test_degenerate_shapes(sb):
         gt = rng.integers(0, 256, size=(h, w, 2), dtype=np.uint8)
         jit = workloads.jitter_table(w, h, levels, finest, w * 31 + h)
         style_obj = check_frame(sb, st, gt, jit, levels, finest, 64, 3, lut=lut,
-                                style_obj=style_obj, name="degenerate")
+                                style_obj=style_obj, name="degenerate", tunes=all_tunes(sb))
 
 
 def test_no_jitter_and_zero_levels(sb):
     styles, frames = workloads.config(1)
     st, fr = styles[0], frames[0]
     lut = oracle.lut_build(st.guide, 8)
-    o = check_frame(sb, st, fr.guide, None, 3, 8, 48, 2, lut=lut, name="no jitter")
+    o = check_frame(sb, st, fr.guide, None, 3, 8, 48, 2, lut=lut, name="no jitter",
+                    tunes=all_tunes(sb))
     check_frame(sb, st, fr.guide, np.zeros(0, np.uint32), 0, 8, 48, 2, lut=lut, style_obj=o,
-                name="zero levels")
+                name="zero levels", tunes=all_tunes(sb))
 
 
 def test_identity_reproduces_source(sb):
@@ -205,4 +223,26 @@ def test_rejects_format_mismatch(sb):
     with pytest.raises(Exception):
         sb.stylize(st, g16.view(np.int16), np.zeros(sb.jitter_len(8, 8, 1, 8), np.uint32),
                    sb.params(1, 8, 10, 1))
+    torch.cuda.synchronize()
+
+
+def test_unaligned_output_rows(sb):
+    """Odd widths take the byte-store path of the fused kernel."""
+    styles, frames = workloads.config(1)
+    st, fr = styles[0], frames[0]
+    lut = oracle.lut_build(st.guide, 8)
+    g = np.ascontiguousarray(fr.guide[:, :253])
+    jit = workloads.jitter_table(253, 256, 3, 8, 5)
+    check_frame(sb, st, g, jit, 3, 8, 48, 2, lut=lut, name="width 253", tunes=all_tunes(sb))
+
+
+def test_fused_rejects_oversized_tile(sb):
+    """A fused tile whose LDS would exceed the limit is refused, not launched."""
+    import torch
+
+    st = sb.Style(workloads.value_noise_rgb(32, 32, 1), workloads.sphere_guide_u8(32), 8)
+    g = np.zeros((64, 64, 2), np.uint8)
+    jit = np.zeros(sb.jitter_len(64, 64, 12, 1), np.uint32)
+    with pytest.raises(sb.StyleBlitError):
+        sb.stylize(st, g, jit, sb.params(12, 1, 10, 7), tune=(sb.PATH_FUSED, sb.TILE_64x32))
     torch.cuda.synchronize()
