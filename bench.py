@@ -45,6 +45,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rotate-mb", type=float, default=600.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame batch leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-qps", type=float, default=2000.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -137,6 +141,10 @@ def main():
                "kind": "oracle",
                "sample": f"{n} full {w}x{h} frames (lookup table built once, not timed)"}
 
+    batch = None if args.no_batch else batch_leg(sb, torch, workloads)
+    serve = None if args.no_serve else serve_leg(sb, torch, np, workloads, args.serve_requests,
+                                                 args.serve_qps)
+
     line = {
         "metric": "stylized Mpixel/s at 1080p (HBM GB/s and frame latency alongside)",
         "value": round(mpx_s, 3),
@@ -161,8 +169,91 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel_ms": round(kern_ms, 6), "algorithmic_bytes": abytes},
         "cpu_baseline": cpu,
+        "batch": batch,
+        "serve": serve,
     }
     print(json.dumps(line), flush=True)
+
+
+def batch_leg(sb, torch, workloads, reps=5):
+    """64 frames of uneven size, half normal- and half UV-guided, 4 resident
+    styles: one graph launch per batch vs one plain launch per frame."""
+    styles_np, frames_np = workloads.config(4)
+    styles = [sb.Style(s.rgb, s.guide, s.lut_bits) for s in styles_np]
+    jobs = []
+    for f in frames_np:
+        p = f.params
+        jobs.append(sb.FrameJob(styles[f.style], f.guide, f.jitter,
+                                sb.params(p.levels, p.finest, p.threshold, p.radius)))
+    px = sum(j.w * j.h for j in jobs)
+    b = sb.Batch(use_graph=True)
+    ws = torch.empty(b.workspace_bytes(jobs), dtype=torch.uint8, device="cuda")
+    plain_ws = torch.empty(max(sb.workspace_bytes(j.w, j.h, j.params) for j in jobs),
+                           dtype=torch.uint8, device="cuda")
+
+    def run_batch():
+        b.run(jobs, workspace=ws)
+
+    def run_plain():
+        for j in jobs:
+            sb.stylize(j.style, j.guide, j.jitter, j.params, out_rgb=j.out_rgb,
+                       out_chunk=j.out_chunk, workspace=plain_ws)
+
+    out = {}
+    for name, fn in (("graph", run_batch), ("plain", run_plain)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        out[name] = {"ms_per_batch": round(ms, 4), "mpixel_per_s": round(px / (ms * 1e-3) / 1e6, 2)}
+    b.close()
+    out["frames"] = len(jobs)
+    out["mpixel"] = round(px / 1e6, 3)
+    out["speedup"] = round(out["plain"]["ms_per_batch"] / out["graph"]["ms_per_batch"], 3)
+    return out
+
+
+def serve_leg(sb, torch, np, workloads, nreq, qps):
+    """Poisson trace at a fixed QPS over 8 resident styles and three frame
+    sizes: continuous batching (4 streams) vs the plain per-request path."""
+    import paper_1807_03249_amd.serve as sv
+
+    trace = workloads.config(5, requests=nreq, qps=qps, pool=2)
+    styles = [sb.Style(s.rgb, s.guide, s.lut_bits) for s in trace["styles"]]
+    guides, jits = {}, {}
+    reqs, px = [], []
+    for i in range(nreq):
+        si, st = int(trace["size_idx"][i]), int(trace["style_idx"][i])
+        fmt = trace["styles"][st].fmt
+        key = (si, fmt, int(trace["pool_idx"][i]))
+        if key not in guides:
+            g = trace["guides"][key]
+            guides[key] = torch.from_numpy(g.view(np.int16) if g.dtype == np.uint16 else g).cuda()
+        g = guides[key]
+        h, w = int(g.shape[0]), int(g.shape[1])
+        p = trace["params"][fmt]
+        jk = (w, h, fmt, i % 4)  # a few jitter tables per shape (per-frame seeds)
+        if jk not in jits:
+            jt = workloads.jitter_table(w, h, p.levels, p.finest, 7000 + len(jits))
+            jits[jk] = torch.from_numpy(jt.view(np.int32)).cuda()
+        reqs.append(sv.Request(float(trace["arrivals"][i]), styles[st], g, jits[jk],
+                               sb.params(p.levels, p.finest, p.threshold, p.radius)))
+        px.append(w * h)
+    px = np.array(px, dtype=np.float64)
+    res = {"qps": qps, "requests": nreq, "budget_mib": 1024}
+    for name, kw in (("batched", dict(slots=4, max_batch=16, plain=False)),
+                     ("plain", dict(plain=True))):
+        out = sv.run(reqs, budget_bytes=1 << 30, **kw)
+        summ = sv.summarize(out, pixels=px)
+        is1080 = np.array([r.w == 1920 for r in reqs])
+        k = int(nreq * 0.05)
+        lat = out["latency"][k:][is1080[k:]] * 1e3
+        summ["p99_ms_1080p"] = float(np.percentile(lat, 99)) if lat.size else None
+        res[name] = {k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in summ.items()}
+    return res
 
 
 if __name__ == "__main__":

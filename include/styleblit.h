@@ -204,6 +204,55 @@ int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace
 /* Wait for the plan's runs, then release its graphs and events. */
 int sb_batch_destroy(sb_batch *b);
 
+/* ---------------------------------------------------------------- serving */
+
+/* Device bytes a request's outputs take from the serving arena. */
+size_t sb_frame_bytes(int32_t w, int32_t h);
+
+typedef struct {
+    int32_t slots;      /* batches in flight, each on its own stream, 1..8 */
+    int32_t max_batch;  /* frames per batch, 1..sb_batch_max_frames() */
+    int32_t use_graph;  /* batches as graph replays (1) or direct launches (0) */
+    int32_t plain;      /* 1: no batching; every request is its own sb_stylize on one
+                           stream, in arrival order (the per-request baseline) */
+    void *arena;        /* [device] outputs of requests in flight are carved from here:
+                           its size is the memory budget for admission */
+    size_t arena_bytes;
+    void *desc_dev;     /* [device] slots * sb_batch_desc_bytes() (unused when plain) */
+    void *desc_host;    /* [host, pinned] slots * sb_batch_desc_bytes() (unused when plain) */
+    void *workspace;    /* [device] slots * workspace_bytes_per_slot */
+    size_t workspace_bytes_per_slot;  /* >= max_batch * (sb_workspace_bytes + 256) of the
+                                         largest request */
+} sb_serve_config;
+
+typedef struct {
+    double arrival_s;           /* arrival time, seconds after the run starts; sorted */
+    const sb_style *style;      /* [host] resident style */
+    const void *tgt_guide;      /* [device] */
+    const uint32_t *jitter;     /* [device] */
+    int32_t w, h;
+    sb_params params;
+    uint8_t *out_rgb;           /* [device] or NULL: taken from the arena on admission and
+                                   released at completion */
+    uint32_t *out_chunk;        /* [device] or NULL (with out_rgb) */
+} sb_request;
+
+typedef struct {
+    double admitted_s, launched_s, completed_s;  /* seconds after the run starts, host
+                                                    clock; completion as seen by polling */
+    int32_t batch, slot, batch_size;
+    int32_t status;             /* SB_OK, or SB_EBUDGET if it can never fit the arena */
+} sb_request_result;
+
+/* Run a request trace in real time on the calling thread: arrivals at their
+ * times, admission in arrival order while the outputs fit in the arena,
+ * continuous batching over `slots` streams (a free slot takes every admitted
+ * request up to max_batch), completion by event polling.  Every result is
+ * the one sb_stylize gives for that request alone.  Returns after the last
+ * request finished and the slots' streams drained. */
+int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
+                 sb_request_result *res);
+
 #ifdef __cplusplus
 }
 #endif

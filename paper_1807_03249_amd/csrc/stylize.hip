@@ -179,9 +179,118 @@ __device__ inline void assign_body(const FrameArgs &a, uint32_t tile, uint32_t t
   if (a.out_nnf) a.out_nnf[pidx] = pack_xy(uint32_t(x + off_x(off)), uint32_t(y + off_y(off)));
 }
 
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+// The level loop for one 8 x 8 block whose pixels share one cell at every
+// level (every spacing >= 8 and <= 4096): the nine seed records of a level
+// are wave-uniform scalar loads, and each lane scans them with a packed
+// difference and a dot product, keeping min((d << 4) | k) -- the smallest
+// squared distance d, ties to the first candidate k in scan order (x outer,
+// y inner), exactly NearestSeed's first strict minimum.
+// NearestSeed for a block's pixel at level i from the level's nine records
+// (scalar loads at wave-uniform addresses): min over (d << 4) | k, i.e. the
+// smallest squared distance d, ties to the first k in scan order.  Returns the
+// record index of the winner, or `none` when the block has no in-image seed.
+__device__ inline uint32_t scan_level(const FrameArgs &a, const uint2 *__restrict__ seeds,
+                                      int32_t i, int32_t bx0, int32_t by0, short2_t pv,
+                                      uint32_t none) {
+  const Levels &lv = a.lv;
+  const int32_t ls = lv.log2_spacing[i];
+  const int32_t cx = bx0 >> ls, cy = by0 >> ls;
+  const int32_t ncx = lv.cells_x[i], ncy = lv.cells_y[i], base = lv.offset[i];
+  uint32_t key = ~0u;
+#pragma unroll
+  for (int32_t k = 0; k < 9; ++k) {
+    const int32_t ccx = cx + k / 3 - 1, ccy = cy + k % 3 - 1;
+    const bool tab = ccx >= 0 && ccy >= 0 && ccx < ncx && ccy < ncy;
+    const uint32_t ridx = tab ? uint32_t(base + ccy * ncx + ccx) : none;
+    const uint32_t pos = seeds[ridx].x;  // uniform address: scalar load
+    if (pos != kNoSeed) {
+      const short2_t dv = __builtin_bit_cast(short2_t, pos) - pv;
+      const uint32_t d = uint32_t(__builtin_amdgcn_sdot2(dv, dv, 0, false));
+      key = min(key, (d << 4) | uint32_t(k));
+    }
+  }
+  if (key == ~0u) return none;
+  const int32_t kk = int32_t(key & 15u);
+  const int32_t kdx = (kk * 11) >> 5;  // kk / 3 for kk < 9
+  return uint32_t(base + (cy + kk - 3 * kdx - 1) * ncx + (cx + kdx - 1));
+}
+
+// The level loop for one 8 x 8 block whose pixels share one cell at every
+// level (every spacing >= 8 and <= 4096, so d << 4 stays below 2^31).  Two
+// levels per step: both scans, both winning records, both source-guide
+// gathers in flight together, then the tests in level order.
+template <int FMT>
+__device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0,
+                                    int32_t lane) {
+  const int32_t x = bx0 + (lane & 7), y = by0 + (lane >> 3);
+  const bool in = x < a.w && y < a.h;
+  const uint32_t pidx = in ? uint32_t(y) * uint32_t(a.w) + uint32_t(x) : 0u;
+  const uint32_t gt = guide_word<FMT>(a.tgt_guide, pidx);
+  const short2_t pv = __builtin_bit_cast(short2_t, pack_xy(uint32_t(x), uint32_t(y)));
+  const uint2 *__restrict__ seeds = a.seeds;
+  const int32_t L = a.lv.count;
+  const uint32_t none = uint32_t(a.lv.offset[L]);  // the sentinel record
+  uint32_t chunk = 0, off = 0;
+  bool done = !in;
+  for (int32_t i = 0; i < L; i += 2) {
+    if (__all(done)) break;
+    const uint32_t r0 = scan_level(a, seeds, i, bx0, by0, pv, none);
+    const uint32_t r1 = i + 1 < L ? scan_level(a, seeds, i + 1, bx0, by0, pv, none) : none;
+    const uint2 c0 = seeds[r0], c1 = seeds[r1];  // the sentinel when none
+    const int32_t vx0 = x + off_x(c0.y), vy0 = y + off_y(c0.y);
+    const int32_t vx1 = x + off_x(c1.y), vy1 = y + off_y(c1.y);
+    const bool ok0 = c0.x != kNoSeed && uint32_t(vx0) < uint32_t(a.sw) && uint32_t(vy0) < uint32_t(a.sh);
+    const bool ok1 = c1.x != kNoSeed && uint32_t(vx1) < uint32_t(a.sw) && uint32_t(vy1) < uint32_t(a.sh);
+    const uint32_t g0 = guide_word<FMT>(a.src_guide, ok0 ? uint32_t(vy0) * uint32_t(a.sw) + uint32_t(vx0) : 0u);
+    const uint32_t g1 = guide_word<FMT>(a.src_guide, ok1 ? uint32_t(vy1) * uint32_t(a.sw) + uint32_t(vx1) : 0u);
+    if (!done && ok0 && error_below(gt, g0, a.threshold)) {
+      chunk = (uint32_t(i) << 26) | ((c0.x >> 16) << 13) | (c0.x & 0xFFFFu);
+      off = c0.y;
+      done = true;
+    }
+    if (!done && ok1 && error_below(gt, g1, a.threshold)) {
+      chunk = (uint32_t(i + 1) << 26) | ((c1.x >> 16) << 13) | (c1.x & 0xFFFFu);
+      off = c1.y;
+      done = true;
+    }
+  }
+  if (!in) return;
+  if (!done) {  // no level accepted: the pixel's own lookup
+    const uint32_t u = a.lut[lut_bin(gt, a.lut_shift, a.lut_bits)];
+    chunk = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
+    off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
+  }
+  a.out_chunk[pidx] = chunk;
+  a.offsets[pidx] = off;
+  if (a.out_nnf) a.out_nnf[pidx] = pack_xy(uint32_t(x + off_x(off)), uint32_t(y + off_y(off)));
+}
+
+// Whether every level's cells hold whole 8 x 8 blocks and distances stay
+// below 2^27 (spacings 8 ... 4096).
+__device__ inline bool uniform_cells(const Levels &lv) {
+  return lv.count == 0 || (lv.log2_spacing[lv.count - 1] >= 3 && lv.log2_spacing[0] <= 12);
+}
+
+// One 16 x 16 tile: four 8 x 8 blocks, one per wave, on the uniform-cell
+// path; otherwise one pixel per thread on the general path.
+template <int FMT>
+__device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t tid) {
+  if (uniform_cells(a.lv)) {
+    const uint32_t tiles_x = (uint32_t(a.w) + 15) / 16;
+    const int32_t wave = __builtin_amdgcn_readfirstlane(int32_t(tid >> 6));
+    const int32_t bx0 = int32_t((tile % tiles_x) * 16) + (wave & 1) * 8;
+    const int32_t by0 = int32_t((tile / tiles_x) * 16) + (wave >> 1) * 8;
+    assign_block<FMT>(a, bx0, by0, int32_t(tid & 63));
+  } else {
+    assign_body<FMT>(a, tile, tid);
+  }
+}
+
 template <int FMT>
 __global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
-  assign_body<FMT>(a, blockIdx.x, threadIdx.x);
+  assign_tile<FMT>(a, blockIdx.x, threadIdx.x);
 }
 
 // Exact n / k for n < 2^20 and 1 <= k <= 225 via a float reciprocal and one
@@ -203,7 +312,7 @@ __device__ inline uint32_t vote(const uint32_t *tile, int32_t lw, int32_t lx, in
                                 int32_t x, int32_t y, const uint32_t *rgba, uint32_t sw,
                                 uint32_t sh) {
   constexpr int W = 2 * R + 1;
-  constexpr int ROWS = W * W <= 25 ? W : (25 / W > 0 ? 25 / W : 1);
+  constexpr int ROWS = W * W <= 9 ? W : 1;  // gathers of one row in flight together
   uint32_t rb = 0, g = 0, k = 0;
 #pragma unroll 1
   for (int32_t r0 = 0; r0 < W; r0 += ROWS) {
@@ -236,37 +345,137 @@ __device__ inline uint32_t vote(const uint32_t *tile, int32_t lw, int32_t lx, in
          (div_small((rb >> 16) + h, k) << 16);
 }
 
-// One 32 x 8 pixel tile; `tile` holds (32 + 2r) x (8 + 2r) offsets in LDS.
-// Ends with all threads past their last LDS read (callers that reuse the
-// tile synchronise before refilling it).
+// The votes of one pixel when every neighbour's source patch lies inside the
+// source.  `lin` holds, per tile cell n, 4 * (raster index of NNF[n]) with two
+// flags in the low bits: bit 0 when n has the same offset NNF[n] - n as its
+// left neighbour, bit 1 when it has the same offset as the neighbour above.
+// A vote's texel address is a per-row scalar base plus that byte offset (flags
+// cleared) plus a per-column immediate.  Moving one column right within a run
+// of equal offsets reads the same texel (and likewise one row down), so a lane
+// loads only where its window's run starts and reuses the texel otherwise.
+// The vote count is the constant (2r+1)^2.
+template <int R>
+__device__ inline uint32_t vote_inside(const uint32_t *lin, int32_t lw, int32_t lx, int32_t ly,
+                                       const unsigned char *texels, uint32_t sw) {
+  constexpr int W = 2 * R + 1;
+  uint32_t rb = 0, g = 0;
+  uint32_t up[W];
+#pragma unroll
+  for (int32_t dx = 0; dx < W; ++dx) up[dx] = 0;
+#pragma unroll 1
+  for (int32_t dy = 0; dy < W; ++dy) {
+    // neighbour n = p + (dx - R, dy - R) votes with NNF[n] - (dx - R, dy - R)
+    const unsigned char *row = texels - int64_t(dy - R) * int64_t(sw) * 4;
+    const uint32_t *lrow = lin + (ly + dy) * lw + lx;
+    uint32_t left = 0;
+#pragma unroll
+    for (int32_t dx = 0; dx < W; ++dx) {
+      const uint32_t v = lrow[dx];
+      uint32_t t;
+      if (dx > 0 && (v & 1u)) t = left;
+      else if (dy > 0 && (v & 2u)) t = up[dx];
+      else t = *reinterpret_cast<const uint32_t *>(row + uint64_t(v & ~3u) - 4 * (dx - R));
+      rb += t & 0x00FF00FFu;
+      g += t & 0x0000FF00u;
+      left = t;
+      up[dx] = t;
+    }
+  }
+  constexpr uint32_t k = W * W, hk = k / 2;
+  return (((rb & 0xFFFFu) + hk) / k) | ((((g >> 8) + hk) / k) << 8) |
+         ((((rb >> 16) + hk) / k) << 16);
+}
+
+__device__ inline uint32_t vote_inside_any(int32_t r, const uint32_t *lin, int32_t lw, int32_t lx,
+                                           int32_t ly, const unsigned char *texels, uint32_t sw) {
+  switch (r) {
+    case 0: return vote_inside<0>(lin, lw, lx, ly, texels, sw);
+    case 1: return vote_inside<1>(lin, lw, lx, ly, texels, sw);
+    case 2: return vote_inside<2>(lin, lw, lx, ly, texels, sw);
+    case 3: return vote_inside<3>(lin, lw, lx, ly, texels, sw);
+    case 4: return vote_inside<4>(lin, lw, lx, ly, texels, sw);
+    case 5: return vote_inside<5>(lin, lw, lx, ly, texels, sw);
+    case 6: return vote_inside<6>(lin, lw, lx, ly, texels, sw);
+    default: return vote_inside<7>(lin, lw, lx, ly, texels, sw);
+  }
+}
+
+// One 32 x 8 pixel tile.  `tile` is LDS for two (32 + 2r) x (8 + 2r) arrays:
+// the offsets NNF[n] - n and, when the whole tile votes inside the source,
+// the texel byte offsets of NNF[n].  Each wave covers two rows; a wave whose
+// voting footprint holds one offset copies C_S[NNF[p]] (every vote is that
+// texel).  Ends with all threads past their last LDS read (callers that reuse
+// the tile synchronise before refilling it).
 __device__ inline void blend_body(const FrameArgs &a, uint32_t t_index, uint32_t tid,
                                   uint32_t *tile) {
   const int32_t r = a.radius;
   const int32_t lw = kBlendTW + 2 * r, lh = kBlendTH + 2 * r;
+  const int32_t nel = lw * lh;  // <= 46 * 22, at most 4 per thread
+  uint32_t *toff = tile, *tlin = tile + nel;
   const uint32_t tiles_x = (uint32_t(a.w) + kBlendTW - 1) / kBlendTW;
   const int32_t x0 = int32_t(t_index % tiles_x) * kBlendTW - r;
   const int32_t y0 = int32_t(t_index / tiles_x) * kBlendTH - r;
-  for (int32_t t = int32_t(tid); t < lw * lh; t += 256) {
-    const int32_t tx = x0 + t % lw, ty = y0 + t / lw;
-    uint32_t o = kNoVote;
-    if (tx >= 0 && ty >= 0 && tx < a.w && ty < a.h) o = a.offsets[uint32_t(ty) * a.w + uint32_t(tx)];
-    tile[t] = o;
+  const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
+  uint32_t ov[4];
+  bool inside = true;
+#pragma unroll
+  for (int32_t e = 0; e < 4; ++e) {
+    const int32_t t = int32_t(tid) + 256 * e;
+    ov[e] = kNoVote;
+    if (t < nel) {
+      const int32_t tx = x0 + t % lw, ty = y0 + t / lw;
+      if (tx >= 0 && ty >= 0 && tx < a.w && ty < a.h) ov[e] = a.offsets[uint32_t(ty) * a.w + uint32_t(tx)];
+      const int32_t nx = tx + off_x(ov[e]), ny = ty + off_y(ov[e]);
+      inside &= ov[e] != kNoVote && nx >= r && ny >= r && nx < int32_t(sw) - r &&
+                ny < int32_t(sh) - r;
+    }
+  }
+#pragma unroll
+  for (int32_t e = 0; e < 4; ++e) {
+    const int32_t t = int32_t(tid) + 256 * e;
+    if (t < nel) toff[t] = ov[e];
+  }
+  const bool all_inside = __syncthreads_and(inside);  // also orders the toff writes
+  if (all_inside) {
+#pragma unroll
+    for (int32_t e = 0; e < 4; ++e) {
+      const int32_t t = int32_t(tid) + 256 * e;
+      if (t < nel) {
+        const int32_t cx = t % lw, cy = t / lw;
+        const int32_t tx = x0 + cx, ty = y0 + cy;
+        uint32_t v = (uint32_t(ty + off_y(ov[e])) * sw + uint32_t(tx + off_x(ov[e]))) * 4u;
+        if (cx > 0 && toff[t - 1] == ov[e]) v |= 1u;
+        if (cy > 0 && toff[t - lw] == ov[e]) v |= 2u;
+        tlin[t] = v;
+      }
+    }
   }
   __syncthreads();
   const int32_t lx = int32_t(tid) & (kBlendTW - 1), ly = int32_t(tid) / kBlendTW;
   const int32_t x = x0 + r + lx, y = y0 + r + ly;
+  // a wave's footprint: rows [2w, 2w + 2 + 2r) of the tile, all columns
+  const int32_t lane = int32_t(tid) & 63, wrow = (int32_t(tid) >> 6) * 2;
+  const uint32_t ref = toff[(wrow + r) * lw + r];
+  bool same = ref != kNoVote;
+  for (int32_t q = lane; q < lw * (2 + 2 * r); q += 64) same &= toff[wrow * lw + q] == ref;
+  const bool copy = __all(same);
   if (x >= a.w || y >= a.h) return;
-  const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
   uint32_t c;
-  switch (r) {
-    case 0: c = vote<0>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-    case 1: c = vote<1>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-    case 2: c = vote<2>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-    case 3: c = vote<3>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-    case 4: c = vote<4>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-    case 5: c = vote<5>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-    case 6: c = vote<6>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-    default: c = vote<7>(tile, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+  if (copy) {
+    c = a.src_rgba[uint32_t(y + off_y(ref)) * sw + uint32_t(x + off_x(ref))];
+  } else if (all_inside) {
+    c = vote_inside_any(r, tlin, lw, lx, ly, reinterpret_cast<const unsigned char *>(a.src_rgba), sw);
+  } else {
+    switch (r) {
+      case 0: c = vote<0>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+      case 1: c = vote<1>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+      case 2: c = vote<2>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+      case 3: c = vote<3>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+      case 4: c = vote<4>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+      case 5: c = vote<5>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+      case 6: c = vote<6>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+      default: c = vote<7>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+    }
   }
   uint8_t *o = a.out_rgb + 3 * (uint32_t(y) * uint32_t(a.w) + uint32_t(x));
   o[0] = uint8_t(c);
@@ -317,8 +526,8 @@ __global__ void __launch_bounds__(256) k_batch(const unsigned char *desc) {
       if (a.fmt == SB_GUIDE_U8X2) seeds_body<SB_GUIDE_U8X2>(a, idx);
       else seeds_body<SB_GUIDE_U16X2>(a, idx);
     } else if (KIND == 1) {
-      if (a.fmt == SB_GUIDE_U8X2) assign_body<SB_GUIDE_U8X2>(a, local, threadIdx.x);
-      else assign_body<SB_GUIDE_U16X2>(a, local, threadIdx.x);
+      if (a.fmt == SB_GUIDE_U8X2) assign_tile<SB_GUIDE_U8X2>(a, local, threadIdx.x);
+      else assign_tile<SB_GUIDE_U16X2>(a, local, threadIdx.x);
     } else {
       blend_body(a, local, threadIdx.x, dyn);
       __syncthreads();  // the next tile refills the LDS tile
@@ -354,13 +563,13 @@ hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, hipStream_t stream) {
     k_assign<SB_GUIDE_U8X2><<<c[1], 256, 0, stream>>>(a);
   else
     k_assign<SB_GUIDE_U16X2><<<c[1], 256, 0, stream>>>(a);
-  const size_t lds = size_t(kBlendTW + 2 * a.radius) * (kBlendTH + 2 * a.radius) * 4;
+  const size_t lds = size_t(kBlendTW + 2 * a.radius) * (kBlendTH + 2 * a.radius) * 8;
   k_blend<<<c[2], 256, lds, stream>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, hipStream_t stream) {
-  const size_t lds = size_t(kBlendTW + 2 * SB_MAX_RADIUS) * (kBlendTH + 2 * SB_MAX_RADIUS) * 4;
+  const size_t lds = size_t(kBlendTW + 2 * SB_MAX_RADIUS) * (kBlendTH + 2 * SB_MAX_RADIUS) * 8;
   k_batch<0><<<grid, 256, 0, stream>>>(desc_dev);
   k_batch<1><<<grid, 256, 0, stream>>>(desc_dev);
   k_batch<2><<<grid, 256, lds, stream>>>(desc_dev);

@@ -1,0 +1,105 @@
+"""Serving on the GPU: a Poisson request trace through the native request
+loop (memory-budget admission, continuous batching over several streams).
+Each request's result in the mix must equal the same request stylised alone
+(tolerance 0: the outputs are integers)."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1807_03249_amd as sb
+    import paper_1807_03249_amd.serve as sv
+
+    trace = workloads.config(5, requests=48, qps=3000.0, pool=1)
+    styles = [sb.Style(s.rgb, s.guide, s.lut_bits) for s in trace["styles"]]
+    return sb, sv, trace, styles
+
+
+def make_requests(env, explicit_outputs, n=None):
+    import torch
+
+    sb, sv, trace, styles = env
+    reqs = []
+    guides = {}
+    n = n or len(trace["arrivals"])
+    for i in range(n):
+        si, st = int(trace["size_idx"][i]), int(trace["style_idx"][i])
+        fmt = trace["styles"][st].fmt
+        key = (si, fmt, int(trace["pool_idx"][i]))
+        if key not in guides:
+            g = trace["guides"][key]
+            g = g.view(np.int16) if g.dtype == np.uint16 else g
+            guides[key] = torch.from_numpy(g).cuda()
+        g = guides[key]
+        h, w = int(g.shape[0]), int(g.shape[1])
+        p = trace["params"][fmt]
+        jit = workloads.jitter_table(w, h, p.levels, p.finest, 9000 + i)
+        jt = torch.from_numpy(jit.view(np.int32)).cuda()
+        prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
+        out_rgb = out_chunk = None
+        if explicit_outputs:
+            out_rgb = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
+            out_chunk = torch.empty((h, w), dtype=torch.int32, device="cuda")
+        reqs.append(sv.Request(float(trace["arrivals"][i]), styles[st], g, jt, prm, out_rgb,
+                               out_chunk))
+    return reqs
+
+
+def alone(sb, r):
+    import torch
+
+    rgb, chunk = sb.stylize(r.style, r.guide, r.jitter, r.params)
+    torch.cuda.synchronize()
+    return rgb.cpu().numpy(), chunk.cpu().numpy()
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_each_result_same_alone_and_in_mix(env, plain):
+    sb, sv, trace, styles = env
+    reqs = make_requests(env, explicit_outputs=True)
+    say(f"serve {len(reqs)} requests plain={plain}")
+    out = sv.run(reqs, slots=3, max_batch=8, budget_bytes=1 << 30, plain=plain)
+    assert np.all(out["status"] == sb.SB_OK)
+    assert np.all(out["completed"] >= out["arrival"])
+    if not plain:
+        assert out["batch_size"].max() >= 1
+    for i, r in enumerate(reqs):
+        rgb, chunk = alone(sb, r)
+        np.testing.assert_array_equal(r.out_rgb.cpu().numpy(), rgb, err_msg=f"request {i}")
+        np.testing.assert_array_equal(r.out_chunk.cpu().numpy(), chunk, err_msg=f"request {i}")
+
+
+def test_budget_bounds_bytes_in_flight(env):
+    sb, sv, trace, styles = env
+    reqs = make_requests(env, explicit_outputs=False)
+    budget = 24 << 20  # room for about one 1080p request plus a small one
+    say(f"serve with a {budget >> 20} MiB budget")
+    out = sv.run(reqs, slots=4, max_batch=8, budget_bytes=budget)
+    assert np.all(out["status"] == sb.SB_OK)
+    sizes = np.array([sv._bind().sb_frame_bytes(r.w, r.h) for r in reqs], dtype=np.int64)
+    # at every admission instant, bytes admitted and not yet completed fit the budget
+    for t in out["admitted"]:
+        live = (out["admitted"] <= t) & (out["completed"] > t)
+        assert sizes[live].sum() <= budget
+
+
+def test_request_larger_than_budget_is_refused(env):
+    sb, sv, trace, styles = env
+    reqs = make_requests(env, explicit_outputs=False, n=16)
+    budget = 4 << 20  # smaller than a 1280x720 request
+    out = sv.run(reqs, slots=2, max_batch=4, budget_bytes=budget)
+    sizes = np.array([sv._bind().sb_frame_bytes(r.w, r.h) for r in reqs])
+    assert np.all(out["status"][sizes > budget] == sb.SB_EBUDGET)
+    assert np.all(out["status"][sizes <= budget] == sb.SB_OK)
