@@ -56,8 +56,8 @@ typedef enum { SB_GUIDE_U8X2 = 0, SB_GUIDE_U16X2 = 1 } sb_guide_fmt;
  * G_S (Sec. 3.1).  A plain struct of caller-owned device pointers; it must
  * stay alive while work that reads it is in flight. */
 typedef struct {
-    const uint32_t *rgba;   /* [device] Sw*Sh texels R | G<<8 | B<<16 (byte 3 = 0),
-                               written by sb_pack_exemplar */
+    const uint32_t *rgba;   /* [device] padded exemplar of sb_exemplar_texels(sw, sh)
+                               texels, written by sb_pack_exemplar */
     const void *guide;      /* [device] Sw*Sh*2 guide channels */
     const uint32_t *lut;    /* [device] (1<<lut_bits)^2 source coordinates, bin index
                                c = c0 + (c1 << lut_bits), written by sb_lut_build */
@@ -93,8 +93,16 @@ int64_t sb_jitter_len(int32_t w, int32_t h, int32_t levels, int32_t finest);
 
 /* ------------------------------------------------- style registration */
 
-/* Repack an exemplar from 3 B/px RGB to 4 B/px texels (one aligned load per
- * texel in the gathers).  rgb [device] Sw*Sh*3; rgba [device] Sw*Sh. */
+/* Texels of the padded exemplar of an Sw x Sh source (0 on invalid sizes).
+ * Layout: rows of Sw + 16 texels; source texel (x, y) at (y + 8) * (Sw + 16)
+ * + (x + 8); an 8-texel zero margin on every side, then zero rows.  A texel
+ * is R | G<<8 | B<<16 | A<<24 with A = 1 inside the source and 0 elsewhere,
+ * so the blend's (2r+1)^2 gathers need no bounds checks and count their
+ * in-source votes in A (the vote rule at the end of Sec. 3.2). */
+size_t sb_exemplar_texels(int32_t sw, int32_t sh);
+
+/* Write the padded exemplar (every texel, margins included) from 3 B/px RGB.
+ * rgb [device] Sw*Sh*3; rgba [device] sb_exemplar_texels(sw, sh) texels. */
 int sb_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t *rgba,
                      hipStream_t stream);
 

@@ -76,6 +76,8 @@ def lib():
     L.sb_last_hip_error.restype = ctypes.c_char_p
     L.sb_jitter_len.restype = ctypes.c_int64
     L.sb_jitter_len.argtypes = [i32, i32, i32, i32]
+    L.sb_exemplar_texels.restype = sz
+    L.sb_exemplar_texels.argtypes = [i32, i32]
     L.sb_pack_exemplar.argtypes = [vp, i32, i32, vp, vp]
     L.sb_lut_workspace_bytes.restype = sz
     L.sb_lut_workspace_bytes.argtypes = [i32, i32, i32, i32]
@@ -172,7 +174,9 @@ class Style:
         self.lut_bits = int(lut_bits)
         L = lib()
         s = _stream(torch) if stream is None else stream
-        self.rgba = torch.empty((self.sh, self.sw), dtype=torch.int32, device="cuda")
+        # padded RGBA exemplar (zero margins, alpha 1 inside), see sb_exemplar_texels
+        self.rgba = torch.empty(int(L.sb_exemplar_texels(self.sw, self.sh)), dtype=torch.int32,
+                                device="cuda")
         _check(L.sb_pack_exemplar(self.rgb.data_ptr(), self.sw, self.sh, self.rgba.data_ptr(), s),
                "sb_pack_exemplar")
         wsb = L.sb_lut_workspace_bytes(self.fmt, self.sw, self.sh, self.lut_bits)

@@ -50,7 +50,7 @@ bool make_levels(int32_t w, int32_t h, int32_t levels, int32_t finest, Levels *o
   if (levels > 0 && lf + levels - 1 > ilog2(SB_MAX_SIDE)) return false;
   memset(out, 0, sizeof *out);
   out->count = levels;
-  int32_t off = 0;
+  int32_t off = 0, poff = 0;
   for (int32_t i = 0; i < levels; ++i) {
     const int32_t ls = lf + (levels - 1 - i);
     const int32_t sp = int32_t(1) << ls;
@@ -58,9 +58,12 @@ bool make_levels(int32_t w, int32_t h, int32_t levels, int32_t finest, Levels *o
     out->cells_x[i] = (w + sp - 1) / sp;
     out->cells_y[i] = (h + sp - 1) / sp;
     out->offset[i] = off;
+    out->poffset[i] = poff;
     off += out->cells_x[i] * out->cells_y[i];
+    poff += (out->cells_x[i] + 2) * (out->cells_y[i] + 2);
   }
   out->offset[levels] = off;
+  out->poffset[levels] = poff;
   return true;
 }
 
@@ -89,14 +92,15 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
   a->threshold = params->threshold;
   a->radius = params->radius;
   a->fmt = style->fmt;
+  a->ex_stride = ex_stride(style->sw);
+  a->ex_zero = uint32_t(ex_stride(style->sw)) * uint32_t(style->sh + 2 * kExMargin);
   return true;
 }
 
 void carve_workspace(FrameArgs *a, void *workspace) {
   char *ws = static_cast<char *>(workspace);
   a->seeds = reinterpret_cast<uint2 *>(ws);
-  a->offsets =
-      reinterpret_cast<uint32_t *>(ws + align256(size_t(a->lv.offset[a->lv.count]) * 8 + 8));
+  a->offsets = reinterpret_cast<uint32_t *>(ws + align256(size_t(a->lv.poffset[a->lv.count]) * 8));
 }
 
 }  // namespace sb
@@ -105,7 +109,7 @@ using namespace sb;
 
 extern "C" {
 
-const char *sb_version(void) { return "styleblit-gfx950 0.1"; }
+const char *sb_version(void) { return "styleblit-gfx950 0.2"; }
 
 const char *sb_status_string(int status) {
   switch (status) {
@@ -124,6 +128,11 @@ int64_t sb_jitter_len(int32_t w, int32_t h, int32_t levels, int32_t finest) {
   Levels lv;
   if (!side_ok(w) || !side_ok(h) || !make_levels(w, h, levels, finest, &lv)) return -1;
   return lv.offset[levels];
+}
+
+size_t sb_exemplar_texels(int32_t sw, int32_t sh) {
+  if (!side_ok(sw) || !side_ok(sh)) return 0;
+  return ex_texels(sw, sh);
 }
 
 int sb_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t *rgba,
@@ -162,7 +171,7 @@ size_t sb_workspace_bytes(int32_t w, int32_t h, const sb_params *params) {
   if (!side_ok(w) || !side_ok(h) || !params_ok(params)) return 0;
   Levels lv;
   make_levels(w, h, params->levels, params->finest, &lv);
-  return align256(size_t(lv.offset[lv.count]) * 8 + 8) + align256(size_t(w) * size_t(h) * 4);
+  return align256(size_t(lv.poffset[lv.count]) * 8) + align256(size_t(w) * size_t(h) * 4);
 }
 
 int sb_stylize_ex(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,

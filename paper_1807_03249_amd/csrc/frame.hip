@@ -193,7 +193,7 @@ template <int R>
 __device__ __forceinline__ uint32_t vote_block(const uint32_t *reg, int32_t RW, int32_t bxl,
                                                int32_t byl, int32_t lane, int32_t x, int32_t y,
                                                bool inimg, const uint32_t *rgba, uint32_t sw,
-                                               uint32_t sh, const VoteLds &v) {
+                                               uint32_t sh, uint32_t P, const VoteLds &v) {
   constexpr int FW = 8 + 2 * R, NC = FW * FW, NS = (NC + 63) / 64;
   constexpr int W = 2 * R + 1;
   uint32_t o[NS], lab[NS];
@@ -248,7 +248,7 @@ __device__ __forceinline__ uint32_t vote_block(const uint32_t *reg, int32_t RW, 
         const uint32_t os = j < nj ? v.offs[j] : kNoVote;
         const int32_t sx = x + sx16(os), sy = y + sy16(os);
         tok[j] = inimg && uint32_t(sx) < sw && uint32_t(sy) < sh;
-        tv[j] = rgba[tok[j] ? uint32_t(sy) * sw + uint32_t(sx) : 0u];
+        tv[j] = rgba[tok[j] ? uint32_t(sy + kExMargin) * P + uint32_t(sx + kExMargin) : 0u];
       }
 #pragma unroll
       for (uint32_t j = 0; j < kDMax; ++j)
@@ -294,16 +294,16 @@ __device__ __forceinline__ uint32_t vote_block(const uint32_t *reg, int32_t RW, 
 __device__ __forceinline__ uint32_t vote_any(int32_t r, const uint32_t *reg, int32_t RW,
                                              int32_t bxl, int32_t byl, int32_t lane, int32_t x,
                                              int32_t y, bool inimg, const uint32_t *rgba,
-                                             uint32_t sw, uint32_t sh, const VoteLds &v) {
+                                             uint32_t sw, uint32_t sh, uint32_t P, const VoteLds &v) {
   switch (r) {
-    case 0: return vote_block<0>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, v);
-    case 1: return vote_block<1>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, v);
-    case 2: return vote_block<2>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, v);
-    case 3: return vote_block<3>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, v);
-    case 4: return vote_block<4>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, v);
-    case 5: return vote_block<5>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, v);
-    case 6: return vote_block<6>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, v);
-    default: return vote_block<7>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, v);
+    case 0: return vote_block<0>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, P, v);
+    case 1: return vote_block<1>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, P, v);
+    case 2: return vote_block<2>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, P, v);
+    case 3: return vote_block<3>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, P, v);
+    case 4: return vote_block<4>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, P, v);
+    case 5: return vote_block<5>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, P, v);
+    case 6: return vote_block<6>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, P, v);
+    default: return vote_block<7>(reg, RW, bxl, byl, lane, x, y, inimg, rgba, sw, sh, P, v);
   }
 }
 
@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(kThreads) k_frame(FrameArgs a, TileGeom tg) {
     const int32_t x = x0 + lx, y = y0 + ly;
     const bool inimg = x < a.w && y < a.h;
     o_rgb[ly * TW + lx] = vote_any(r, reg, RW, bxl, byl, lane, x, y, inimg, a.src_rgba,
-                                   uint32_t(a.sw), uint32_t(a.sh), vl);
+                                   uint32_t(a.sw), uint32_t(a.sh), uint32_t(a.ex_stride), vl);
     wave_lds_sync();
   }
   __syncthreads();

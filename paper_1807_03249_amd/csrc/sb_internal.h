@@ -10,8 +10,9 @@
 
 namespace sb {
 
-// An invalid seed record: no in-image seed for that cell.
-constexpr uint32_t kNoSeed = 0xFFFFFFFFu;
+// Position word of an invalid seed record (no in-image seed for that cell):
+// the int16 pair (-32768, -32768), farther from every pixel than any seed.
+constexpr uint32_t kNoSeed = 0x80008000u;
 // Offset of an out-of-target neighbour in the voting tile: adding it to any
 // in-range pixel coordinate lands at x or y >= 32768, outside every source.
 constexpr uint32_t kNoVote = 0x80008000u;
@@ -22,12 +23,32 @@ struct Levels {
   int32_t log2_spacing[SB_MAX_LEVELS]; // level i (0 = coarsest)
   int32_t cells_x[SB_MAX_LEVELS];
   int32_t cells_y[SB_MAX_LEVELS];
-  int32_t offset[SB_MAX_LEVELS + 1];   // first table entry of level i; offset[L] = total
+  int32_t offset[SB_MAX_LEVELS + 1];   // first jitter entry of level i; offset[L] = total
+  // seed records: per level a (cells_x + 2) x (cells_y + 2) grid, the cells
+  // plus a ring of empty records, so every 3x3 neighbourhood is in the table
+  int32_t poffset[SB_MAX_LEVELS + 1];  // first record of level i; poffset[L] = total
 };
+
+// Voting tile of the blend (pixels): 256 threads, 4 horizontal pixels each.
+constexpr int32_t kBlendTW = 64, kBlendTH = 16;
+
+// Padded exemplar: texels of Sw x Sh sit in rows of sw + 2 * kExMargin
+// texels with kExMargin empty (zero) texels on every side, followed by zero
+// rows that hold one voting tile.  Inside texels carry alpha 1, so a sum of
+// votes counts its in-source votes in byte 3.  Every vote lands within
+// SB_MAX_RADIUS of the source, so no vote needs a bounds check.
+constexpr int32_t kExMargin = 8;
+__host__ __device__ constexpr int32_t ex_stride(int32_t sw) { return sw + 2 * kExMargin; }
+__host__ __device__ constexpr int32_t ex_zero_rows(int32_t sw) {
+  return kBlendTH - 1 + (kBlendTW + ex_stride(sw) - 1) / ex_stride(sw);
+}
+__host__ __device__ constexpr size_t ex_texels(int32_t sw, int32_t sh) {
+  return size_t(ex_stride(sw)) * size_t(sh + 2 * kExMargin + ex_zero_rows(sw));
+}
 
 // Everything one frame's kernels read: device pointers plus sizes.
 struct FrameArgs {
-  const uint32_t *src_rgba;   // Sw*Sh texels
+  const uint32_t *src_rgba;   // padded exemplar, ex_texels(sw, sh)
   const void *src_guide;      // Sw*Sh*2 channels
   const uint32_t *lut;        // (1 << lut_bits)^2
   const void *tgt_guide;      // W*H*2 channels
@@ -35,13 +56,15 @@ struct FrameArgs {
   uint8_t *out_rgb;           // W*H*3
   uint32_t *out_chunk;        // W*H
   uint32_t *out_nnf;          // W*H or null
-  uint2 *seeds;               // workspace: per cell {position x|y<<16, offset dx|dy<<16}
+  uint2 *seeds;               // workspace: per padded cell {4x | 4y << 16, dx | dy << 16}
   uint32_t *offsets;          // workspace: per pixel NNF[p] - p as two int16
   int32_t sw, sh, w, h;
   int32_t lut_bits, lut_shift; // lut_shift = guide depth - lut_bits
   uint32_t threshold;
   int32_t radius;
   int32_t fmt;                 // sb_guide_fmt (read by the batch kernels)
+  int32_t ex_stride;           // texels per padded exemplar row
+  uint32_t ex_zero;            // first texel of the padded exemplar's zero rows
   Levels lv;
 };
 
@@ -107,5 +130,14 @@ hipError_t launch_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t 
                             int32_t lut_bits, uint32_t *lut, void *workspace, hipStream_t stream);
 
 __host__ __device__ inline uint32_t pack_xy(uint32_t x, uint32_t y) { return x | (y << 16); }
+
+// A frame pointer as a global-memory pointer.  Kernels that read their
+// FrameArgs from memory (the batch kernels) would otherwise address through
+// flat instructions.
+#define SB_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ SB_GLOBAL T *glb(T *p) {
+  return (SB_GLOBAL T *)p;
+}
 
 }  // namespace sb

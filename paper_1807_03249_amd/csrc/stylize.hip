@@ -1,29 +1,43 @@
 // stylize.hip -- per-frame StyleBlit kernels for gfx950.
 //
-//   k_seeds   one thread per cell of every level: the jittered seed
-//             (SeedPoint, Algorithm 2), whether it is inside the target, and
-//             the translation u* - q its lookup (Sec. 3.1) gives the chunk it
-//             starts.  Tiny: one record per seed.
-//   k_assign  one thread per target pixel: the level loop of Algorithm 2,
-//             NearestSeed over the 3x3 cells from the seed records, the exact
-//             integer guide error at u* + (p - q) against the threshold, and
-//             the own-lookup fallback.  Writes the chunk code and the offset
-//             NNF[p] - p.
-//   k_blend   the voting step (end of Sec. 3.2): a tile of offsets plus an
-//             r-pixel halo in LDS, (2r+1)^2 votes per pixel gathered from the
-//             RGBA exemplar, integer average rounded half up.
+//   k_seeds   one thread per record of the padded seed table: the jittered
+//             seed of a cell (SeedPoint, Algorithm 2) if it lies in the
+//             target, and the translation u* - q its lookup (Sec. 3.1) gives
+//             the chunk it starts; the ring around each level's grid and
+//             out-of-image seeds hold the empty record.
+//   k_assign  the level loop of Algorithm 2 per pixel: NearestSeed over the
+//             3x3 cells, the exact integer guide error at u* + (p - q)
+//             against the threshold, and the own-lookup fallback.  Writes the
+//             chunk code and the offset NNF[p] - p.
+//   k_blend   the voting step (end of Sec. 3.2): a tile of offsets with an
+//             r-pixel halo in LDS; each lane averages the (2r+1)^2 votes of
+//             four adjacent pixels, one vector gather per (cell, pixel run).
 #include "sb_internal.h"
 
 namespace sb {
 namespace {
 
+typedef short short2_t __attribute__((ext_vector_type(2)));
+// Dword-aligned vectors of 2..4 texels (global loads need dword alignment
+// only).
+typedef uint32_t u32x2a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t u32x3a4 __attribute__((ext_vector_type(3), aligned(4)));
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Seed records as plain vectors in global memory.
+__device__ __forceinline__ SB_GLOBAL u32x2 *seed_table(const FrameArgs &a) {
+  return reinterpret_cast<SB_GLOBAL u32x2 *>(glb(a.seeds));
+}
+
 template <int FMT>
 __device__ inline uint32_t guide_word(const void *g, uint32_t i) {
   if (FMT == SB_GUIDE_U8X2) {
-    uint32_t v = static_cast<const uint16_t *>(g)[i];
+    uint32_t v = glb(static_cast<const uint16_t *>(g))[i];
     return (v & 0xFFu) | ((v >> 8) << 16);  // unpack to the u16 pair layout
   } else {
-    return static_cast<const uint32_t *>(g)[i];
+    return glb(static_cast<const uint32_t *>(g))[i];
   }
 }
 
@@ -33,11 +47,21 @@ __device__ inline uint32_t lut_bin(uint32_t g, int32_t shift, int32_t bits) {
 }
 
 // Exact squared L2 error of two guide words compared with t: true iff e < t.
+// 8-bit channels: the differences fit int16, one packed subtract and one
+// dot product.  16-bit channels: 24-bit multiplies (|d| < 2^16, d^2 < 2^32)
+// and a saturating add (a sum that saturates is >= 2^32 - 1 >= t anyway).
+template <int FMT>
 __device__ inline bool error_below(uint32_t a, uint32_t b, uint32_t t) {
-  const int32_t d0 = int32_t(a & 0xFFFFu) - int32_t(b & 0xFFFFu);
-  const int32_t d1 = int32_t(a >> 16) - int32_t(b >> 16);
-  const uint64_t e = uint64_t(uint32_t(d0 * d0)) + uint64_t(uint32_t(d1 * d1));
-  return e < uint64_t(t);
+  if (FMT == SB_GUIDE_U8X2) {
+    const short2_t d = __builtin_bit_cast(short2_t, a) - __builtin_bit_cast(short2_t, b);
+    return uint32_t(__builtin_amdgcn_sdot2(d, d, 0, false)) < t;
+  } else {
+    const int32_t d0 = int32_t(a & 0xFFFFu) - int32_t(b & 0xFFFFu);
+    const int32_t d1 = int32_t(a >> 16) - int32_t(b >> 16);
+    const uint32_t e0 = uint32_t(__mul24(d0, d0));
+    const uint32_t e1 = uint32_t(__mul24(d1, d1));
+    return __builtin_elementwise_add_sat(e0, e1) < t;
+  }
 }
 
 // Offsets are two int16 in one word; x in the low half.
@@ -47,37 +71,50 @@ __device__ inline uint32_t pack_off(int32_t dx, int32_t dy) {
 __device__ inline int32_t off_x(uint32_t o) { return int32_t(int16_t(o & 0xFFFFu)); }
 __device__ inline int32_t off_y(uint32_t o) { return int32_t(int16_t(o >> 16)); }
 
-__global__ void k_pack_exemplar(const uint8_t *rgb, uint32_t n, uint32_t *rgba) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  rgba[i] = uint32_t(rgb[3 * i]) | (uint32_t(rgb[3 * i + 1]) << 8) | (uint32_t(rgb[3 * i + 2]) << 16);
+// Chunk code of the seed whose position word (4x | 4y << 16) is q4.
+__device__ inline uint32_t chunk_code(int32_t level, uint32_t q4) {
+  return (uint32_t(level) << 26) | ((q4 >> 18) << 13) | ((q4 & 0xFFFFu) >> 2);
 }
 
-// Seed record of table entry idx (idx == total writes the sentinel record
-// that out-of-table cells read).
+// Every texel of the padded exemplar: source texels with alpha 1, margins and
+// zero rows 0.
+__global__ void k_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t n,
+                                uint32_t *rgba) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t P = ex_stride(sw);
+  const int32_t x = int32_t(i % uint32_t(P)) - kExMargin, y = int32_t(i / uint32_t(P)) - kExMargin;
+  uint32_t t = 0;
+  if (x >= 0 && y >= 0 && x < sw && y < sh) {
+    const uint8_t *c = rgb + 3 * (size_t(y) * size_t(sw) + size_t(x));
+    t = uint32_t(c[0]) | (uint32_t(c[1]) << 8) | (uint32_t(c[2]) << 16) | (1u << 24);
+  }
+  rgba[i] = t;
+}
+
+// Record idx of the padded seed table.
 template <int FMT>
 __device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
   const Levels &lv = a.lv;
-  const uint32_t total = uint32_t(lv.offset[lv.count]);
-  if (idx > total) return;
-  uint2 rec = make_uint2(kNoSeed, 0u);
-  if (idx < total) {
-    int32_t i = 0;
-    while (idx >= uint32_t(lv.offset[i + 1])) ++i;
-    const uint32_t local = idx - uint32_t(lv.offset[i]);
-    const uint32_t cx = local % uint32_t(lv.cells_x[i]);
-    const uint32_t cy = local / uint32_t(lv.cells_x[i]);
-    const uint32_t j = a.jitter[idx];
-    const uint32_t sx = (cx << lv.log2_spacing[i]) + (j & 0xFFFFu);
-    const uint32_t sy = (cy << lv.log2_spacing[i]) + (j >> 16);
+  if (idx >= uint32_t(lv.poffset[lv.count])) return;
+  int32_t i = 0;
+  while (idx >= uint32_t(lv.poffset[i + 1])) ++i;
+  const int32_t ncx = lv.cells_x[i], ncy = lv.cells_y[i];
+  const uint32_t local = idx - uint32_t(lv.poffset[i]), pc = uint32_t(ncx + 2);
+  const int32_t cx = int32_t(local % pc) - 1, cy = int32_t(local / pc) - 1;
+  u32x2 rec = {kNoSeed, 0u};
+  if (cx >= 0 && cy >= 0 && cx < ncx && cy < ncy) {
+    const uint32_t j = glb(a.jitter)[lv.offset[i] + cy * ncx + cx];
+    const uint32_t sx = (uint32_t(cx) << lv.log2_spacing[i]) + (j & 0xFFFFu);
+    const uint32_t sy = (uint32_t(cy) << lv.log2_spacing[i]) + (j >> 16);
     if (sx < uint32_t(a.w) && sy < uint32_t(a.h)) {
       const uint32_t g = guide_word<FMT>(a.tgt_guide, sy * uint32_t(a.w) + sx);
-      const uint32_t u = a.lut[lut_bin(g, a.lut_shift, a.lut_bits)];
-      rec.x = pack_xy(sx, sy);
+      const uint32_t u = glb(a.lut)[lut_bin(g, a.lut_shift, a.lut_bits)];
+      rec.x = pack_xy(4 * sx, 4 * sy);
       rec.y = pack_off(int32_t(u & 0xFFFFu) - int32_t(sx), int32_t(u >> 16) - int32_t(sy));
     }
   }
-  a.seeds[idx] = rec;
+  seed_table(a)[idx] = rec;
 }
 
 template <int FMT>
@@ -85,212 +122,185 @@ __global__ void __launch_bounds__(256) k_seeds(FrameArgs a) {
   seeds_body<FMT>(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Candidate of one level for pixel (x, y) from the nine seed records around
-// its cell (loaded by the caller, out-of-table cells read the sentinel):
-// NearestSeed's first strict minimum, then the source index to test (0 when
-// the translated coordinate leaves the source, so the gather is issued
-// unconditionally).
-struct LevelCand {
-  bool ok;
-  uint32_t q, off, idx;
-};
-
-__device__ inline LevelCand pick(const uint2 rec[9], int32_t x, int32_t y, int32_t sw, int32_t sh) {
-  uint32_t best = ~0u, bq = 0, bo = 0;
-#pragma unroll
-  for (int32_t k = 0; k < 9; ++k) {  // k = (dx+1)*3 + (dy+1): x outer, y inner
-    const uint32_t ex = (rec[k].x & 0xFFFFu) - uint32_t(x), ey = (rec[k].x >> 16) - uint32_t(y);
-    const uint32_t d = rec[k].x == kNoSeed ? ~0u : ex * ex + ey * ey;
-    if (d < best) {
-      best = d;
-      bq = rec[k].x;
-      bo = rec[k].y;
-    }
-  }
-  LevelCand c;
-  const int32_t vx = x + off_x(bo), vy = y + off_y(bo);
-  c.ok = best != ~0u && uint32_t(vx) < uint32_t(sw) && uint32_t(vy) < uint32_t(sh);
-  c.q = bq;
-  c.off = bo;
-  c.idx = c.ok ? uint32_t(vy) * uint32_t(sw) + uint32_t(vx) : 0u;
-  return c;
+// NearestSeed key of candidate k (k = (dx+1)*3 + (dy+1): x outer, y inner):
+// 16 d + k for the squared distance d, from the packed int16 pair 4q - 4p
+// (|4 dx| <= 4 * 8191 fits int16, so 16 d + k <= 2146959400 < 2^31 - 1).
+// The empty record (-32768, -32768) saturates the subtraction and then the
+// dot product, giving INT32_MAX, above every real key.  The minimum key over
+// k = 0..8 is NearestSeed's first strict minimum; INT32_MAX means no seed.
+__device__ inline int32_t seed_key(uint32_t q4, short2_t p4, int32_t k) {
+  const short2_t dv = __builtin_elementwise_sub_sat(__builtin_bit_cast(short2_t, q4), p4);
+  return __builtin_amdgcn_sdot2(dv, dv, k, true);
 }
 
-__device__ inline void load_level(const FrameArgs &a, int32_t i, int32_t x, int32_t y,
-                                  uint2 rec[9]) {
-  const Levels &lv = a.lv;
-  const int32_t ls = lv.log2_spacing[i];
-  const int32_t bx = x >> ls, by = y >> ls;
-  const int32_t ncx = lv.cells_x[i], ncy = lv.cells_y[i];
-  const uint32_t none = uint32_t(lv.offset[lv.count]);  // the sentinel record
-#pragma unroll
-  for (int32_t k = 0; k < 9; ++k) {
-    const int32_t cx = bx + k / 3 - 1, cy = by + k % 3 - 1;
-    const bool in = cx >= 0 && cy >= 0 && cx < ncx && cy < ncy;
-    rec[k] = a.seeds[in ? uint32_t(lv.offset[i] + cy * ncx + cx) : none];
-  }
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
 }
 
-// One 16 x 16 pixel tile (tile index row-major over the frame's tiles).
-template <int FMT>
-__device__ inline void assign_body(const FrameArgs &a, uint32_t tile, uint32_t tid) {
-  const uint32_t tiles_x = (uint32_t(a.w) + 15) / 16;
-  const int32_t x = int32_t((tile % tiles_x) * 16 + (tid & 15));
-  const int32_t y = int32_t((tile / tiles_x) * 16 + (tid >> 4));
-  if (x >= a.w || y >= a.h) return;
-  const uint32_t pidx = uint32_t(y) * uint32_t(a.w) + uint32_t(x);
-  const uint32_t gt = guide_word<FMT>(a.tgt_guide, pidx);
-  const int32_t L = a.lv.count;
-  uint32_t chunk = 0, off = 0;
-  bool done = false;
-  // two levels per step: their 18 seed records, then both source-guide
-  // gathers, are in flight together
-  for (int32_t i = 0; i < L && !done; i += 2) {
-    uint2 r0[9], r1[9];
-    load_level(a, i, x, y, r0);
-    const bool two = i + 1 < L;
-    if (two) load_level(a, i + 1, x, y, r1);
-    const LevelCand c0 = pick(r0, x, y, a.sw, a.sh);
-    LevelCand c1;
-    c1.ok = false;
-    c1.idx = 0;
-    c1.q = 0;
-    c1.off = 0;
-    if (two) c1 = pick(r1, x, y, a.sw, a.sh);
-    const uint32_t g0 = guide_word<FMT>(a.src_guide, c0.idx);
-    const uint32_t g1 = guide_word<FMT>(a.src_guide, c1.idx);
-    if (c0.ok && error_below(gt, g0, a.threshold)) {
-      chunk = (uint32_t(i) << 26) | ((c0.q >> 16) << 13) | (c0.q & 0xFFFFu);
-      off = c0.off;
-      done = true;
-    } else if (c1.ok && error_below(gt, g1, a.threshold)) {
-      chunk = (uint32_t(i + 1) << 26) | ((c1.q >> 16) << 13) | (c1.q & 0xFFFFu);
-      off = c1.off;
-      done = true;
-    }
-  }
-  if (!done) {  // no level accepted: the pixel's own lookup
-    const uint32_t u = a.lut[lut_bin(gt, a.lut_shift, a.lut_bits)];
-    chunk = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
-    off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
-  }
-  a.out_chunk[pidx] = chunk;
-  a.offsets[pidx] = off;
-  if (a.out_nnf) a.out_nnf[pidx] = pack_xy(uint32_t(x + off_x(off)), uint32_t(y + off_y(off)));
-}
-
-typedef short short2_t __attribute__((ext_vector_type(2)));
+// Records staged per wave: level i's nine at [kRecStride * i, + 9).
+constexpr int32_t kRecStride = 12;
+constexpr int32_t kWaveRecs = SB_MAX_LEVELS * kRecStride;
 
 // The level loop for one 8 x 8 block whose pixels share one cell at every
-// level (every spacing >= 8 and <= 4096): the nine seed records of a level
-// are wave-uniform scalar loads, and each lane scans them with a packed
-// difference and a dot product, keeping min((d << 4) | k) -- the smallest
-// squared distance d, ties to the first candidate k in scan order (x outer,
-// y inner), exactly NearestSeed's first strict minimum.
-// NearestSeed for a block's pixel at level i from the level's nine records
-// (scalar loads at wave-uniform addresses): min over (d << 4) | k, i.e. the
-// smallest squared distance d, ties to the first k in scan order.  Returns the
-// record index of the winner, or `none` when the block has no in-image seed.
-__device__ inline uint32_t scan_level(const FrameArgs &a, const uint2 *__restrict__ seeds,
-                                      int32_t i, int32_t bx0, int32_t by0, short2_t pv,
-                                      uint32_t none) {
+// level (every spacing >= 8).  The wave stages its 9 L seed records in LDS
+// (one gather), scans each level's nine with packed arithmetic, and keeps up
+// to four levels' source-guide gathers in flight before testing them in
+// level order.
+template <int FMT>
+__device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0, int32_t lane,
+                                    uint32_t *lpos, uint32_t *loff) {
   const Levels &lv = a.lv;
-  const int32_t ls = lv.log2_spacing[i];
-  const int32_t cx = bx0 >> ls, cy = by0 >> ls;
-  const int32_t ncx = lv.cells_x[i], ncy = lv.cells_y[i], base = lv.offset[i];
-  uint32_t key = ~0u;
-#pragma unroll
-  for (int32_t k = 0; k < 9; ++k) {
-    const int32_t ccx = cx + k / 3 - 1, ccy = cy + k % 3 - 1;
-    const bool tab = ccx >= 0 && ccy >= 0 && ccx < ncx && ccy < ncy;
-    const uint32_t ridx = tab ? uint32_t(base + ccy * ncx + ccx) : none;
-    const uint32_t pos = seeds[ridx].x;  // uniform address: scalar load
-    if (pos != kNoSeed) {
-      const short2_t dv = __builtin_bit_cast(short2_t, pos) - pv;
-      const uint32_t d = uint32_t(__builtin_amdgcn_sdot2(dv, dv, 0, false));
-      key = min(key, (d << 4) | uint32_t(k));
+  const int32_t L = lv.count;
+  for (int32_t j0 = 0; j0 < 9 * L; j0 += 64) {
+    const int32_t j = j0 + lane;
+    uint32_t ridx = 0;
+    int32_t slot = -1;
+    const int32_t i_end = min(L, (j0 + 72) / 9);
+    for (int32_t i = j0 / 9; i < i_end; ++i) {
+      const int32_t ls = lv.log2_spacing[i], pc = lv.cells_x[i] + 2;
+      // padded coordinates of the 3x3 neighbourhood's top-left cell
+      const int32_t top = lv.poffset[i] + (by0 >> ls) * pc + (bx0 >> ls);
+      const int32_t k = j - 9 * i;
+      if (k >= 0 && k < 9) {
+        const int32_t kx = (k * 11) >> 5;  // k / 3 for k < 9
+        ridx = uint32_t(top + (k - 3 * kx) * pc + kx);
+        slot = kRecStride * i + k;
+      }
+    }
+    if (slot >= 0) {
+      const u32x2 r = seed_table(a)[ridx];
+      lpos[slot] = r.x;
+      loff[slot] = r.y;
     }
   }
-  if (key == ~0u) return none;
-  const int32_t kk = int32_t(key & 15u);
-  const int32_t kdx = (kk * 11) >> 5;  // kk / 3 for kk < 9
-  return uint32_t(base + (cy + kk - 3 * kdx - 1) * ncx + (cx + kdx - 1));
-}
-
-// The level loop for one 8 x 8 block whose pixels share one cell at every
-// level (every spacing >= 8 and <= 4096, so d << 4 stays below 2^31).  Two
-// levels per step: both scans, both winning records, both source-guide
-// gathers in flight together, then the tests in level order.
-template <int FMT>
-__device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0,
-                                    int32_t lane) {
+  wave_lds_sync();
   const int32_t x = bx0 + (lane & 7), y = by0 + (lane >> 3);
   const bool in = x < a.w && y < a.h;
   const uint32_t pidx = in ? uint32_t(y) * uint32_t(a.w) + uint32_t(x) : 0u;
   const uint32_t gt = guide_word<FMT>(a.tgt_guide, pidx);
-  const short2_t pv = __builtin_bit_cast(short2_t, pack_xy(uint32_t(x), uint32_t(y)));
-  const uint2 *__restrict__ seeds = a.seeds;
-  const int32_t L = a.lv.count;
-  const uint32_t none = uint32_t(a.lv.offset[L]);  // the sentinel record
+  const short2_t p4 = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x), uint32_t(4 * y)));
+  const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
   uint32_t chunk = 0, off = 0;
   bool done = !in;
-  for (int32_t i = 0; i < L; i += 2) {
+  for (int32_t i0 = 0; i0 < L; i0 += 4) {
     if (__all(done)) break;
-    const uint32_t r0 = scan_level(a, seeds, i, bx0, by0, pv, none);
-    const uint32_t r1 = i + 1 < L ? scan_level(a, seeds, i + 1, bx0, by0, pv, none) : none;
-    const uint2 c0 = seeds[r0], c1 = seeds[r1];  // the sentinel when none
-    const int32_t vx0 = x + off_x(c0.y), vy0 = y + off_y(c0.y);
-    const int32_t vx1 = x + off_x(c1.y), vy1 = y + off_y(c1.y);
-    const bool ok0 = c0.x != kNoSeed && uint32_t(vx0) < uint32_t(a.sw) && uint32_t(vy0) < uint32_t(a.sh);
-    const bool ok1 = c1.x != kNoSeed && uint32_t(vx1) < uint32_t(a.sw) && uint32_t(vy1) < uint32_t(a.sh);
-    const uint32_t g0 = guide_word<FMT>(a.src_guide, ok0 ? uint32_t(vy0) * uint32_t(a.sw) + uint32_t(vx0) : 0u);
-    const uint32_t g1 = guide_word<FMT>(a.src_guide, ok1 ? uint32_t(vy1) * uint32_t(a.sw) + uint32_t(vx1) : 0u);
-    if (!done && ok0 && error_below(gt, g0, a.threshold)) {
-      chunk = (uint32_t(i) << 26) | ((c0.x >> 16) << 13) | (c0.x & 0xFFFFu);
-      off = c0.y;
-      done = true;
+    uint32_t g[4], wq[4], wo[4];
+    bool ok[4];
+#pragma unroll
+    for (int32_t u = 0; u < 4; ++u) {
+      ok[u] = false;
+      g[u] = wq[u] = wo[u] = 0;
+      if (i0 + u < L) {
+        const uint32_t *P = lpos + kRecStride * (i0 + u);
+        const i32x4 q03 = *reinterpret_cast<const i32x4 *>(P);
+        const i32x4 q47 = *reinterpret_cast<const i32x4 *>(P + 4);
+        int32_t key = seed_key(uint32_t(q03.x), p4, 0);
+        key = min(key, seed_key(uint32_t(q03.y), p4, 1));
+        key = min(key, seed_key(uint32_t(q03.z), p4, 2));
+        key = min(key, seed_key(uint32_t(q03.w), p4, 3));
+        key = min(key, seed_key(uint32_t(q47.x), p4, 4));
+        key = min(key, seed_key(uint32_t(q47.y), p4, 5));
+        key = min(key, seed_key(uint32_t(q47.z), p4, 6));
+        key = min(key, seed_key(uint32_t(q47.w), p4, 7));
+        key = min(key, seed_key(P[8], p4, 8));
+        const int32_t w = kRecStride * (i0 + u) + (key & 15);
+        wq[u] = lpos[w];
+        wo[u] = loff[w];
+        const int32_t vx = x + off_x(wo[u]), vy = y + off_y(wo[u]);
+        ok[u] = key != INT32_MAX && uint32_t(vx) < sw && uint32_t(vy) < sh;
+        g[u] = guide_word<FMT>(a.src_guide, ok[u] ? uint32_t(vy) * sw + uint32_t(vx) : 0u);
+      }
     }
-    if (!done && ok1 && error_below(gt, g1, a.threshold)) {
-      chunk = (uint32_t(i + 1) << 26) | ((c1.x >> 16) << 13) | (c1.x & 0xFFFFu);
-      off = c1.y;
-      done = true;
+#pragma unroll
+    for (int32_t u = 0; u < 4; ++u) {
+      if (!done && ok[u] && error_below<FMT>(gt, g[u], a.threshold)) {
+        chunk = chunk_code(i0 + u, wq[u]);
+        off = wo[u];
+        done = true;
+      }
     }
   }
   if (!in) return;
   if (!done) {  // no level accepted: the pixel's own lookup
-    const uint32_t u = a.lut[lut_bin(gt, a.lut_shift, a.lut_bits)];
+    const uint32_t u = glb(a.lut)[lut_bin(gt, a.lut_shift, a.lut_bits)];
     chunk = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
     off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
   }
-  a.out_chunk[pidx] = chunk;
-  a.offsets[pidx] = off;
-  if (a.out_nnf) a.out_nnf[pidx] = pack_xy(uint32_t(x + off_x(off)), uint32_t(y + off_y(off)));
+  glb(a.out_chunk)[pidx] = chunk;
+  glb(a.offsets)[pidx] = off;
+  if (a.out_nnf) glb(a.out_nnf)[pidx] = pack_xy(uint32_t(x + off_x(off)), uint32_t(y + off_y(off)));
 }
 
-// Whether every level's cells hold whole 8 x 8 blocks and distances stay
-// below 2^27 (spacings 8 ... 4096).
+// The level loop for one pixel when cells are smaller than 8 x 8 blocks:
+// each lane reads its own nine records per level.
+template <int FMT>
+__device__ inline void assign_pixel(const FrameArgs &a, int32_t x, int32_t y) {
+  if (x >= a.w || y >= a.h) return;
+  const Levels &lv = a.lv;
+  const int32_t L = lv.count;
+  const uint32_t pidx = uint32_t(y) * uint32_t(a.w) + uint32_t(x);
+  const uint32_t gt = guide_word<FMT>(a.tgt_guide, pidx);
+  const short2_t p4 = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x), uint32_t(4 * y)));
+  const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
+  uint32_t chunk = 0, off = 0;
+  bool done = false;
+  for (int32_t i = 0; i < L && !done; ++i) {
+    const int32_t ls = lv.log2_spacing[i], pc = lv.cells_x[i] + 2;
+    const SB_GLOBAL u32x2 *top = seed_table(a) + lv.poffset[i] + (y >> ls) * pc + (x >> ls);
+    int32_t key = INT32_MAX;
+#pragma unroll
+    for (int32_t k = 0; k < 9; ++k) key = min(key, seed_key(top[(k % 3) * pc + k / 3].x, p4, k));
+    if (key == INT32_MAX) continue;
+    const int32_t k = key & 15, kx = (k * 11) >> 5;
+    const u32x2 w = top[(k - 3 * kx) * pc + kx];
+    const int32_t vx = x + off_x(w.y), vy = y + off_y(w.y);
+    if (uint32_t(vx) >= sw || uint32_t(vy) >= sh) continue;
+    const uint32_t g = guide_word<FMT>(a.src_guide, uint32_t(vy) * sw + uint32_t(vx));
+    if (error_below<FMT>(gt, g, a.threshold)) {
+      chunk = chunk_code(i, w.x);
+      off = w.y;
+      done = true;
+    }
+  }
+  if (!done) {
+    const uint32_t u = glb(a.lut)[lut_bin(gt, a.lut_shift, a.lut_bits)];
+    chunk = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
+    off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
+  }
+  glb(a.out_chunk)[pidx] = chunk;
+  glb(a.offsets)[pidx] = off;
+  if (a.out_nnf) glb(a.out_nnf)[pidx] = pack_xy(uint32_t(x + off_x(off)), uint32_t(y + off_y(off)));
+}
+
+// Whether every level's cells hold whole 8 x 8 blocks.
 __device__ inline bool uniform_cells(const Levels &lv) {
-  return lv.count == 0 || (lv.log2_spacing[lv.count - 1] >= 3 && lv.log2_spacing[0] <= 12);
+  return lv.count == 0 || lv.log2_spacing[lv.count - 1] >= 3;
 }
 
 // One 16 x 16 tile: four 8 x 8 blocks, one per wave, on the uniform-cell
-// path; otherwise one pixel per thread on the general path.
+// path; otherwise one pixel per thread.  `recs` is LDS for 4 waves' records.
 template <int FMT>
-__device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t tid) {
+__device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t tid,
+                                   uint32_t *recs) {
+  const uint32_t tiles_x = (uint32_t(a.w) + 15) / 16;
+  const int32_t tx0 = int32_t((tile % tiles_x) * 16), ty0 = int32_t((tile / tiles_x) * 16);
   if (uniform_cells(a.lv)) {
-    const uint32_t tiles_x = (uint32_t(a.w) + 15) / 16;
     const int32_t wave = __builtin_amdgcn_readfirstlane(int32_t(tid >> 6));
-    const int32_t bx0 = int32_t((tile % tiles_x) * 16) + (wave & 1) * 8;
-    const int32_t by0 = int32_t((tile / tiles_x) * 16) + (wave >> 1) * 8;
-    assign_block<FMT>(a, bx0, by0, int32_t(tid & 63));
+    const int32_t bx0 = tx0 + (wave & 1) * 8, by0 = ty0 + (wave >> 1) * 8;
+    // a block wholly outside the frame has no cells in the table
+    if (bx0 >= a.w || by0 >= a.h) return;
+    uint32_t *lpos = recs + wave * 2 * kWaveRecs;
+    assign_block<FMT>(a, bx0, by0, int32_t(tid & 63), lpos, lpos + kWaveRecs);
   } else {
-    assign_body<FMT>(a, tile, tid);
+    assign_pixel<FMT>(a, tx0 + int32_t(tid & 15), ty0 + int32_t(tid >> 4));
   }
 }
 
 template <int FMT>
 __global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
-  assign_tile<FMT>(a, blockIdx.x, threadIdx.x);
+  __shared__ __attribute__((aligned(16))) uint32_t recs[4 * 2 * kWaveRecs];
+  assign_tile<FMT>(a, blockIdx.x, threadIdx.x, recs);
 }
 
 // Exact n / k for n < 2^20 and 1 <= k <= 225 via a float reciprocal and one
@@ -303,189 +313,152 @@ __device__ inline uint32_t div_small(uint32_t n, uint32_t k) {
   return q;
 }
 
-constexpr int kBlendTW = 32, kBlendTH = 8;
+// LDS row length and rows of a voting tile of radius R (rows padded to a
+// multiple of 4 cells so each lane's cells start 16-byte aligned).
+__host__ __device__ constexpr int32_t blend_lw(int32_t r) { return (kBlendTW + 2 * r + 3) & ~3; }
+__host__ __device__ constexpr int32_t blend_lh(int32_t r) { return kBlendTH + 2 * r; }
 
-// The votes of one pixel: (2r+1)^2 gathers issued in batches of up to ~25
-// with out-of-source votes reading texel 0 and masked out of the sums.
+// Load n = 1..4 consecutive texels at byte offset `at` of the exemplar.
+template <int N>
+__device__ __forceinline__ void load_texels(const SB_GLOBAL unsigned char *ex, uint32_t at,
+                                            uint32_t t[4]) {
+  const SB_GLOBAL unsigned char *p = ex + uint64_t(at);
+  if (N == 4) {
+    const u32x4a4 v = *reinterpret_cast<const SB_GLOBAL u32x4a4 *>(p);
+    t[0] = v.x, t[1] = v.y, t[2] = v.z, t[3] = v.w;
+  } else if (N == 3) {
+    const u32x3a4 v = *reinterpret_cast<const SB_GLOBAL u32x3a4 *>(p);
+    t[0] = v.x, t[1] = v.y, t[2] = v.z;
+  } else if (N == 2) {
+    const u32x2a4 v = *reinterpret_cast<const SB_GLOBAL u32x2a4 *>(p);
+    t[0] = v.x, t[1] = v.y;
+  } else {
+    t[0] = *reinterpret_cast<const SB_GLOBAL uint32_t *>(p);
+  }
+}
+
+// The votes of cell column c (0 .. W+2) of one window row for the lane's
+// pixels j = c - 2R .. c (clipped to 0..3): one gather of their texels, which
+// are adjacent in the exemplar because the cell's offset is shared.
+template <int R, int C>
+__device__ __forceinline__ void vote_cell(const SB_GLOBAL unsigned char *ex, uint32_t pbase, int32_t lin,
+                                          uint32_t S[4], uint32_t RB[4]) {
+  constexpr int J0 = C - 2 * R > 0 ? C - 2 * R : 0;
+  constexpr int J1 = C < 3 ? C : 3;
+  constexpr int N = J1 - J0 + 1;
+  uint32_t t[4];
+  load_texels<N>(ex, pbase + 4u * J0 + uint32_t(lin), t);
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    S[J0 + m] += t[m];
+    RB[J0 + m] += t[m] & 0x00FF00FFu;
+  }
+}
+
+template <int R, int C>
+__device__ __forceinline__ void vote_row(const SB_GLOBAL unsigned char *ex, uint32_t pbase,
+                                         const int32_t *cells, uint32_t S[4], uint32_t RB[4]) {
+  if constexpr (C < 2 * R + 4) {
+    vote_cell<R, C>(ex, pbase, cells[C], S, RB);
+    vote_row<R, C + 1>(ex, pbase, cells, S, RB);
+  }
+}
+
+// One 64 x 16 pixel tile; `lin` is LDS for blend_lw(R) x blend_lh(R) cells.
+// Cell n of the tile holds 4 * (oy * P + ox) for its offset o = NNF[n] - n
+// and the padded exemplar's row length P: a vote of n for pixel p is the
+// texel at p's own padded position plus that many bytes.  Cells outside the
+// target hold the distance to the exemplar's zero rows instead, so their
+// votes read zeros, which count for nothing (alpha 0).  Pixel p's average is
+// (sum + floor(k/2)) / k per channel over its k in-source votes, the vote
+// rule at the end of Sec. 3.2.  Ends with all threads past their last LDS
+// read (callers that reuse `lin` synchronise before refilling it).
 template <int R>
-__device__ inline uint32_t vote(const uint32_t *tile, int32_t lw, int32_t lx, int32_t ly,
-                                int32_t x, int32_t y, const uint32_t *rgba, uint32_t sw,
-                                uint32_t sh) {
-  constexpr int W = 2 * R + 1;
-  constexpr int ROWS = W * W <= 9 ? W : 1;  // gathers of one row in flight together
-  uint32_t rb = 0, g = 0, k = 0;
-#pragma unroll 1
-  for (int32_t r0 = 0; r0 < W; r0 += ROWS) {
-    uint32_t idx[ROWS * W];
-    bool ok[ROWS * W];
-#pragma unroll
-    for (int32_t q = 0; q < ROWS * W; ++q) {
-      ok[q] = false;
-      idx[q] = 0;
-      if (r0 + q / W < W) {
-        const uint32_t o = tile[(ly + r0 + q / W) * lw + lx + q % W];
-        const int32_t sx = x + off_x(o), sy = y + off_y(o);
-        ok[q] = uint32_t(sx) < sw && uint32_t(sy) < sh;
-        idx[q] = ok[q] ? uint32_t(sy) * sw + uint32_t(sx) : 0u;
-      }
-    }
-    uint32_t t[ROWS * W];
-#pragma unroll
-    for (int32_t q = 0; q < ROWS * W; ++q) t[q] = rgba[idx[q]];
-#pragma unroll
-    for (int32_t q = 0; q < ROWS * W; ++q) {
-      const uint32_t c = ok[q] ? t[q] : 0u;
-      rb += c & 0x00FF00FFu;
-      g += c & 0x0000FF00u;
-      k += ok[q] ? 1u : 0u;
-    }
-  }
-  const uint32_t h = k >> 1;
-  return div_small((rb & 0xFFFFu) + h, k) | (div_small((g >> 8) + h, k) << 8) |
-         (div_small((rb >> 16) + h, k) << 16);
-}
-
-// The votes of one pixel when every neighbour's source patch lies inside the
-// source.  `lin` holds, per tile cell n, 4 * (raster index of NNF[n]) with two
-// flags in the low bits: bit 0 when n has the same offset NNF[n] - n as its
-// left neighbour, bit 1 when it has the same offset as the neighbour above.
-// A vote's texel address is a per-row scalar base plus that byte offset (flags
-// cleared) plus a per-column immediate.  Moving one column right within a run
-// of equal offsets reads the same texel (and likewise one row down), so a lane
-// loads only where its window's run starts and reuses the texel otherwise.
-// The vote count is the constant (2r+1)^2.
-template <int R>
-__device__ inline uint32_t vote_inside(const uint32_t *lin, int32_t lw, int32_t lx, int32_t ly,
-                                       const unsigned char *texels, uint32_t sw) {
-  constexpr int W = 2 * R + 1;
-  uint32_t rb = 0, g = 0;
-  uint32_t up[W];
-#pragma unroll
-  for (int32_t dx = 0; dx < W; ++dx) up[dx] = 0;
-#pragma unroll 1
-  for (int32_t dy = 0; dy < W; ++dy) {
-    // neighbour n = p + (dx - R, dy - R) votes with NNF[n] - (dx - R, dy - R)
-    const unsigned char *row = texels - int64_t(dy - R) * int64_t(sw) * 4;
-    const uint32_t *lrow = lin + (ly + dy) * lw + lx;
-    uint32_t left = 0;
-#pragma unroll
-    for (int32_t dx = 0; dx < W; ++dx) {
-      const uint32_t v = lrow[dx];
-      uint32_t t;
-      if (dx > 0 && (v & 1u)) t = left;
-      else if (dy > 0 && (v & 2u)) t = up[dx];
-      else t = *reinterpret_cast<const uint32_t *>(row + uint64_t(v & ~3u) - 4 * (dx - R));
-      rb += t & 0x00FF00FFu;
-      g += t & 0x0000FF00u;
-      left = t;
-      up[dx] = t;
-    }
-  }
-  constexpr uint32_t k = W * W, hk = k / 2;
-  return (((rb & 0xFFFFu) + hk) / k) | ((((g >> 8) + hk) / k) << 8) |
-         ((((rb >> 16) + hk) / k) << 16);
-}
-
-__device__ inline uint32_t vote_inside_any(int32_t r, const uint32_t *lin, int32_t lw, int32_t lx,
-                                           int32_t ly, const unsigned char *texels, uint32_t sw) {
-  switch (r) {
-    case 0: return vote_inside<0>(lin, lw, lx, ly, texels, sw);
-    case 1: return vote_inside<1>(lin, lw, lx, ly, texels, sw);
-    case 2: return vote_inside<2>(lin, lw, lx, ly, texels, sw);
-    case 3: return vote_inside<3>(lin, lw, lx, ly, texels, sw);
-    case 4: return vote_inside<4>(lin, lw, lx, ly, texels, sw);
-    case 5: return vote_inside<5>(lin, lw, lx, ly, texels, sw);
-    case 6: return vote_inside<6>(lin, lw, lx, ly, texels, sw);
-    default: return vote_inside<7>(lin, lw, lx, ly, texels, sw);
-  }
-}
-
-// One 32 x 8 pixel tile.  `tile` is LDS for two (32 + 2r) x (8 + 2r) arrays:
-// the offsets NNF[n] - n and, when the whole tile votes inside the source,
-// the texel byte offsets of NNF[n].  Each wave covers two rows; a wave whose
-// voting footprint holds one offset copies C_S[NNF[p]] (every vote is that
-// texel).  Ends with all threads past their last LDS read (callers that reuse
-// the tile synchronise before refilling it).
-__device__ inline void blend_body(const FrameArgs &a, uint32_t t_index, uint32_t tid,
-                                  uint32_t *tile) {
-  const int32_t r = a.radius;
-  const int32_t lw = kBlendTW + 2 * r, lh = kBlendTH + 2 * r;
-  const int32_t nel = lw * lh;  // <= 46 * 22, at most 4 per thread
-  uint32_t *toff = tile, *tlin = tile + nel;
+__device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t tid,
+                                  int32_t *lin) {
+  constexpr int32_t LW = blend_lw(R), LH = blend_lh(R), NC = LW * LH;
   const uint32_t tiles_x = (uint32_t(a.w) + kBlendTW - 1) / kBlendTW;
-  const int32_t x0 = int32_t(t_index % tiles_x) * kBlendTW - r;
-  const int32_t y0 = int32_t(t_index / tiles_x) * kBlendTH - r;
-  const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
-  uint32_t ov[4];
-  bool inside = true;
-#pragma unroll
-  for (int32_t e = 0; e < 4; ++e) {
-    const int32_t t = int32_t(tid) + 256 * e;
-    ov[e] = kNoVote;
-    if (t < nel) {
-      const int32_t tx = x0 + t % lw, ty = y0 + t / lw;
-      if (tx >= 0 && ty >= 0 && tx < a.w && ty < a.h) ov[e] = a.offsets[uint32_t(ty) * a.w + uint32_t(tx)];
-      const int32_t nx = tx + off_x(ov[e]), ny = ty + off_y(ov[e]);
-      inside &= ov[e] != kNoVote && nx >= r && ny >= r && nx < int32_t(sw) - r &&
-                ny < int32_t(sh) - r;
+  const int32_t X0 = int32_t(t_index % tiles_x) * kBlendTW;
+  const int32_t Y0 = int32_t(t_index / tiles_x) * kBlendTH;
+  const int32_t P = a.ex_stride;
+  const int32_t zero_rel =
+      int32_t(a.ex_zero) - ((Y0 + kExMargin) * P + (X0 + kExMargin));
+  for (int32_t e = int32_t(tid); e < NC; e += 256) {
+    const int32_t cx = e % LW, cy = e / LW;
+    const int32_t tx = X0 - R + cx, ty = Y0 - R + cy;
+    int32_t v = zero_rel;
+    if (tx >= 0 && ty >= 0 && tx < a.w && ty < a.h) {
+      const uint32_t o = glb(a.offsets)[uint32_t(ty) * uint32_t(a.w) + uint32_t(tx)];
+      v = off_y(o) * P + off_x(o);
     }
-  }
-#pragma unroll
-  for (int32_t e = 0; e < 4; ++e) {
-    const int32_t t = int32_t(tid) + 256 * e;
-    if (t < nel) toff[t] = ov[e];
-  }
-  const bool all_inside = __syncthreads_and(inside);  // also orders the toff writes
-  if (all_inside) {
-#pragma unroll
-    for (int32_t e = 0; e < 4; ++e) {
-      const int32_t t = int32_t(tid) + 256 * e;
-      if (t < nel) {
-        const int32_t cx = t % lw, cy = t / lw;
-        const int32_t tx = x0 + cx, ty = y0 + cy;
-        uint32_t v = (uint32_t(ty + off_y(ov[e])) * sw + uint32_t(tx + off_x(ov[e]))) * 4u;
-        if (cx > 0 && toff[t - 1] == ov[e]) v |= 1u;
-        if (cy > 0 && toff[t - lw] == ov[e]) v |= 2u;
-        tlin[t] = v;
-      }
-    }
+    lin[e] = 4 * v;
   }
   __syncthreads();
-  const int32_t lx = int32_t(tid) & (kBlendTW - 1), ly = int32_t(tid) / kBlendTW;
-  const int32_t x = x0 + r + lx, y = y0 + r + ly;
-  // a wave's footprint: rows [2w, 2w + 2 + 2r) of the tile, all columns
-  const int32_t lane = int32_t(tid) & 63, wrow = (int32_t(tid) >> 6) * 2;
-  const uint32_t ref = toff[(wrow + r) * lw + r];
-  bool same = ref != kNoVote;
-  for (int32_t q = lane; q < lw * (2 + 2 * r); q += 64) same &= toff[wrow * lw + q] == ref;
-  const bool copy = __all(same);
-  if (x >= a.w || y >= a.h) return;
-  uint32_t c;
-  if (copy) {
-    c = a.src_rgba[uint32_t(y + off_y(ref)) * sw + uint32_t(x + off_x(ref))];
-  } else if (all_inside) {
-    c = vote_inside_any(r, tlin, lw, lx, ly, reinterpret_cast<const unsigned char *>(a.src_rgba), sw);
+  const int32_t gx = int32_t(tid & 15), ly = int32_t(tid >> 4);
+  const int32_t x = X0 + 4 * gx, y = Y0 + ly;
+  const uint32_t pbase = 4u * uint32_t((y + kExMargin) * P + (x + kExMargin));
+  const SB_GLOBAL unsigned char *ex = glb(reinterpret_cast<const unsigned char *>(a.src_rgba));
+  uint32_t S[4] = {0, 0, 0, 0}, RB[4] = {0, 0, 0, 0};
+  constexpr int32_t NQ = (2 * R + 4 + 3) / 4;  // 16-byte LDS reads per window row
+#pragma unroll 1
+  for (int32_t dy = 0; dy < 2 * R + 1; ++dy) {
+    const i32x4 *row = reinterpret_cast<const i32x4 *>(lin + (ly + dy) * LW + 4 * gx);
+    int32_t cells[4 * NQ];
+#pragma unroll
+    for (int32_t q = 0; q < NQ; ++q) {
+      const i32x4 v = row[q];
+      cells[4 * q] = v.x, cells[4 * q + 1] = v.y, cells[4 * q + 2] = v.z, cells[4 * q + 3] = v.w;
+    }
+    vote_row<R, 0>(ex, pbase, cells, S, RB);
+  }
+  if (y >= a.h || x >= a.w) return;
+  uint32_t c[4];
+#pragma unroll
+  for (int32_t j = 0; j < 4; ++j) {
+    // S = sum R + 2^8 sum G + 2^16 sum B + 2^24 k and RB = sum R + 2^16 sum B
+    // (mod 2^32); every channel sum is < 2^16 and k <= 225
+    const uint32_t gk = S[j] - RB[j];
+    const uint32_t k = gk >> 24, hk = k >> 1;
+    c[j] = div_small((RB[j] & 0xFFFFu) + hk, k) | (div_small(((gk >> 8) & 0xFFFFu) + hk, k) << 8) |
+           (div_small((RB[j] >> 16) + hk, k) << 16);
+  }
+  SB_GLOBAL uint8_t *o = glb(a.out_rgb) + 3 * (size_t(y) * size_t(a.w) + size_t(x));
+  if (x + 4 <= a.w && (reinterpret_cast<uintptr_t>(a.out_rgb + 3 * (size_t(y) * size_t(a.w) + size_t(x))) & 3) == 0) {
+    u32x3a4 v;
+    v.x = c[0] | (c[1] << 24);
+    v.y = (c[1] >> 8) | (c[2] << 16);
+    v.z = (c[2] >> 16) | (c[3] << 8);
+    *reinterpret_cast<SB_GLOBAL u32x3a4 *>(o) = v;
   } else {
-    switch (r) {
-      case 0: c = vote<0>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-      case 1: c = vote<1>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-      case 2: c = vote<2>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-      case 3: c = vote<3>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-      case 4: c = vote<4>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-      case 5: c = vote<5>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-      case 6: c = vote<6>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
-      default: c = vote<7>(toff, lw, lx, ly, x, y, a.src_rgba, sw, sh); break;
+#pragma unroll
+    for (int32_t j = 0; j < 4; ++j) {
+      if (x + j < a.w) {
+        o[3 * j] = uint8_t(c[j]);
+        o[3 * j + 1] = uint8_t(c[j] >> 8);
+        o[3 * j + 2] = uint8_t(c[j] >> 16);
+      }
     }
   }
-  uint8_t *o = a.out_rgb + 3 * (uint32_t(y) * uint32_t(a.w) + uint32_t(x));
-  o[0] = uint8_t(c);
-  o[1] = uint8_t(c >> 8);
-  o[2] = uint8_t(c >> 16);
 }
 
+__device__ inline void blend_tile_any(const FrameArgs &a, uint32_t t_index, uint32_t tid,
+                                      int32_t *lin) {
+  switch (a.radius) {
+    case 0: blend_tile<0>(a, t_index, tid, lin); break;
+    case 1: blend_tile<1>(a, t_index, tid, lin); break;
+    case 2: blend_tile<2>(a, t_index, tid, lin); break;
+    case 3: blend_tile<3>(a, t_index, tid, lin); break;
+    case 4: blend_tile<4>(a, t_index, tid, lin); break;
+    case 5: blend_tile<5>(a, t_index, tid, lin); break;
+    case 6: blend_tile<6>(a, t_index, tid, lin); break;
+    default: blend_tile<7>(a, t_index, tid, lin); break;
+  }
+}
+
+template <int R>
 __global__ void __launch_bounds__(256) k_blend(FrameArgs a) {
-  extern __shared__ uint32_t tile[];
-  blend_body(a, blockIdx.x, threadIdx.x, tile);
+  __shared__ __attribute__((aligned(16))) int32_t lin[blend_lw(R) * blend_lh(R)];
+  blend_tile<R>(a, blockIdx.x, threadIdx.x, lin);
 }
 
 // ------------------------------------------------------------------ batches
@@ -493,7 +466,8 @@ __global__ void __launch_bounds__(256) k_blend(FrameArgs a) {
 // A batch runs the same three passes over many frames: each kernel is
 // persistent (a fixed grid striding over the concatenated tiles of all
 // frames) and reads the frames' arguments from a descriptor block in device
-// memory, so one captured graph serves any mix of sizes and formats.
+// memory, so one captured graph serves any mix of sizes and formats.  A
+// block copies the arguments of the frame it is working on into LDS.
 
 // Frame owning global tile t: the last f with pre[f] <= t (pre in LDS).
 __device__ inline uint32_t frame_of(const uint32_t *pre, uint32_t n, uint32_t t) {
@@ -506,30 +480,45 @@ __device__ inline uint32_t frame_of(const uint32_t *pre, uint32_t n, uint32_t t)
   return lo;
 }
 
+constexpr int32_t kBatchLds = blend_lw(SB_MAX_RADIUS) * blend_lh(SB_MAX_RADIUS) * 4 >
+                                      4 * 2 * kWaveRecs * 4
+                                  ? blend_lw(SB_MAX_RADIUS) * blend_lh(SB_MAX_RADIUS) * 4
+                                  : 4 * 2 * kWaveRecs * 4;
+
 template <int KIND>
 __global__ void __launch_bounds__(256) k_batch(const unsigned char *desc) {
-  extern __shared__ uint32_t dyn[];  // blend tile
+  __shared__ __attribute__((aligned(16))) uint32_t work[kBatchLds / 4];
   __shared__ uint32_t pre[kMaxBatchFrames + 1];
+  __shared__ FrameArgs fa;
   const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(desc);
   const uint32_t n = hd->nframes;
   const uint32_t *gpre = reinterpret_cast<const uint32_t *>(desc + batch_prefix_offset(KIND));
   for (uint32_t i = threadIdx.x; i <= n; i += 256) pre[i] = gpre[i];
   __syncthreads();
-  const FrameArgs *frames = reinterpret_cast<const FrameArgs *>(desc + batch_frames_offset());
   const uint32_t total = pre[n];
+  uint32_t cur = ~0u;
   for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
     const uint32_t f = frame_of(pre, n, t);
-    const FrameArgs &a = frames[f];
+    if (f != cur) {  // block-uniform
+      const uint32_t *src = reinterpret_cast<const uint32_t *>(desc + batch_frames_offset() +
+                                                               size_t(f) * sizeof(FrameArgs));
+      uint32_t *dst = reinterpret_cast<uint32_t *>(&fa);
+      __syncthreads();  // every thread is done with the previous frame's arguments
+      for (uint32_t i = threadIdx.x; i < sizeof(FrameArgs) / 4; i += 256) dst[i] = src[i];
+      __syncthreads();
+      cur = f;
+    }
     const uint32_t local = t - pre[f];
     if (KIND == 0) {
       const uint32_t idx = local * 256 + threadIdx.x;
-      if (a.fmt == SB_GUIDE_U8X2) seeds_body<SB_GUIDE_U8X2>(a, idx);
-      else seeds_body<SB_GUIDE_U16X2>(a, idx);
+      if (fa.fmt == SB_GUIDE_U8X2) seeds_body<SB_GUIDE_U8X2>(fa, idx);
+      else seeds_body<SB_GUIDE_U16X2>(fa, idx);
     } else if (KIND == 1) {
-      if (a.fmt == SB_GUIDE_U8X2) assign_tile<SB_GUIDE_U8X2>(a, local, threadIdx.x);
-      else assign_tile<SB_GUIDE_U16X2>(a, local, threadIdx.x);
+      if (fa.fmt == SB_GUIDE_U8X2) assign_tile<SB_GUIDE_U8X2>(fa, local, threadIdx.x, work);
+      else assign_tile<SB_GUIDE_U16X2>(fa, local, threadIdx.x, work);
+      __syncthreads();  // the next tile restages its records
     } else {
-      blend_body(a, local, threadIdx.x, dyn);
+      blend_tile_any(fa, local, threadIdx.x, reinterpret_cast<int32_t *>(work));
       __syncthreads();  // the next tile refills the LDS tile
     }
   }
@@ -541,13 +530,13 @@ unsigned blocks_for(uint64_t n, unsigned bs) { return unsigned((n + bs - 1) / bs
 
 hipError_t launch_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t *rgba,
                                 hipStream_t stream) {
-  const uint32_t n = uint32_t(sw) * uint32_t(sh);
-  k_pack_exemplar<<<blocks_for(n, 256), 256, 0, stream>>>(rgb, n, rgba);
+  const uint32_t n = uint32_t(ex_texels(sw, sh));
+  k_pack_exemplar<<<blocks_for(n, 256), 256, 0, stream>>>(rgb, sw, sh, n, rgba);
   return hipGetLastError();
 }
 
 void tile_counts(const FrameArgs &a, uint32_t counts[3]) {
-  counts[0] = (uint32_t(a.lv.offset[a.lv.count]) + 1 + 255) / 256;  // + sentinel
+  counts[0] = (uint32_t(a.lv.poffset[a.lv.count]) + 255) / 256;
   counts[1] = ((uint32_t(a.w) + 15) / 16) * ((uint32_t(a.h) + 15) / 16);
   counts[2] = ((uint32_t(a.w) + kBlendTW - 1) / kBlendTW) * ((uint32_t(a.h) + kBlendTH - 1) / kBlendTH);
 }
@@ -555,24 +544,33 @@ void tile_counts(const FrameArgs &a, uint32_t counts[3]) {
 hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, hipStream_t stream) {
   uint32_t c[3];
   tile_counts(a, c);
-  if (fmt == SB_GUIDE_U8X2)
-    k_seeds<SB_GUIDE_U8X2><<<c[0], 256, 0, stream>>>(a);
-  else
-    k_seeds<SB_GUIDE_U16X2><<<c[0], 256, 0, stream>>>(a);
+  if (c[0] > 0) {
+    if (fmt == SB_GUIDE_U8X2)
+      k_seeds<SB_GUIDE_U8X2><<<c[0], 256, 0, stream>>>(a);
+    else
+      k_seeds<SB_GUIDE_U16X2><<<c[0], 256, 0, stream>>>(a);
+  }
   if (fmt == SB_GUIDE_U8X2)
     k_assign<SB_GUIDE_U8X2><<<c[1], 256, 0, stream>>>(a);
   else
     k_assign<SB_GUIDE_U16X2><<<c[1], 256, 0, stream>>>(a);
-  const size_t lds = size_t(kBlendTW + 2 * a.radius) * (kBlendTH + 2 * a.radius) * 8;
-  k_blend<<<c[2], 256, lds, stream>>>(a);
+  switch (a.radius) {
+    case 0: k_blend<0><<<c[2], 256, 0, stream>>>(a); break;
+    case 1: k_blend<1><<<c[2], 256, 0, stream>>>(a); break;
+    case 2: k_blend<2><<<c[2], 256, 0, stream>>>(a); break;
+    case 3: k_blend<3><<<c[2], 256, 0, stream>>>(a); break;
+    case 4: k_blend<4><<<c[2], 256, 0, stream>>>(a); break;
+    case 5: k_blend<5><<<c[2], 256, 0, stream>>>(a); break;
+    case 6: k_blend<6><<<c[2], 256, 0, stream>>>(a); break;
+    default: k_blend<7><<<c[2], 256, 0, stream>>>(a); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, hipStream_t stream) {
-  const size_t lds = size_t(kBlendTW + 2 * SB_MAX_RADIUS) * (kBlendTH + 2 * SB_MAX_RADIUS) * 8;
   k_batch<0><<<grid, 256, 0, stream>>>(desc_dev);
   k_batch<1><<<grid, 256, 0, stream>>>(desc_dev);
-  k_batch<2><<<grid, 256, lds, stream>>>(desc_dev);
+  k_batch<2><<<grid, 256, 0, stream>>>(desc_dev);
   return hipGetLastError();
 }
 
