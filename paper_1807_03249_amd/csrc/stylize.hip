@@ -337,30 +337,51 @@ __device__ __forceinline__ void load_texels(const SB_GLOBAL unsigned char *ex, u
   }
 }
 
-// The votes of cell column c (0 .. W+2) of one window row for the lane's
-// pixels j = c - 2R .. c (clipped to 0..3): one gather of their texels, which
-// are adjacent in the exemplar because the cell's offset is shared.
+// Texels of the lane's four pixels for one window cell, indexed by pixel
+// J = 0..3 (only J0(c)..J1(c) are meaningful).
+struct Texels4 {
+  uint32_t t[4];
+};
+
+// The votes of cell column C (0 .. W+2) of one window row for the lane's
+// pixels J = C - 2R .. C (clipped to 0..3).  Every vote of a cell with offset
+// o for pixel p is the texel at p + o, so a cell with the same offset as the
+// cell above it (same column, previous row) or, from column 4 on, as its
+// left neighbour needs texels the lane already holds; only lanes whose cell
+// starts a new offset issue the gather, which is one vector load of the
+// pixels' adjacent texels.
 template <int R, int C>
-__device__ __forceinline__ void vote_cell(const SB_GLOBAL unsigned char *ex, uint32_t pbase, int32_t lin,
-                                          uint32_t S[4], uint32_t RB[4]) {
+__device__ __forceinline__ void vote_cell(const SB_GLOBAL unsigned char *ex, uint32_t pbase,
+                                          const int32_t *cells, const int32_t *up_cells,
+                                          Texels4 *row, const Texels4 *up_row, uint32_t S[4],
+                                          uint32_t RB[4]) {
   constexpr int J0 = C - 2 * R > 0 ? C - 2 * R : 0;
   constexpr int J1 = C < 3 ? C : 3;
   constexpr int N = J1 - J0 + 1;
-  uint32_t t[4];
-  load_texels<N>(ex, pbase + 4u * J0 + uint32_t(lin), t);
+  const int32_t lin = cells[C];
+  const bool up = lin == up_cells[C];
+  const bool left = C >= 4 && lin == cells[C > 0 ? C - 1 : 0];
+  uint32_t t[4] = {0, 0, 0, 0};
+  if (!up && !left) load_texels<N>(ex, pbase + 4u * J0 + uint32_t(lin), t);
 #pragma unroll
   for (int m = 0; m < N; ++m) {
-    S[J0 + m] += t[m];
-    RB[J0 + m] += t[m] & 0x00FF00FFu;
+    uint32_t v = t[m];
+    if (left) v = row[C > 0 ? C - 1 : 0].t[J0 + m];
+    if (up) v = up_row[C].t[J0 + m];
+    row[C].t[J0 + m] = v;
+    S[J0 + m] += v;
+    RB[J0 + m] += v & 0x00FF00FFu;
   }
 }
 
 template <int R, int C>
 __device__ __forceinline__ void vote_row(const SB_GLOBAL unsigned char *ex, uint32_t pbase,
-                                         const int32_t *cells, uint32_t S[4], uint32_t RB[4]) {
+                                         const int32_t *cells, const int32_t *up_cells,
+                                         Texels4 *row, const Texels4 *up_row, uint32_t S[4],
+                                         uint32_t RB[4]) {
   if constexpr (C < 2 * R + 4) {
-    vote_cell<R, C>(ex, pbase, cells[C], S, RB);
-    vote_row<R, C + 1>(ex, pbase, cells, S, RB);
+    vote_cell<R, C>(ex, pbase, cells, up_cells, row, up_row, S, RB);
+    vote_row<R, C + 1>(ex, pbase, cells, up_cells, row, up_row, S, RB);
   }
 }
 
@@ -399,17 +420,29 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
   const uint32_t pbase = 4u * uint32_t((y + kExMargin) * P + (x + kExMargin));
   const SB_GLOBAL unsigned char *ex = glb(reinterpret_cast<const unsigned char *>(a.src_rgba));
   uint32_t S[4] = {0, 0, 0, 0}, RB[4] = {0, 0, 0, 0};
-  constexpr int32_t NQ = (2 * R + 4 + 3) / 4;  // 16-byte LDS reads per window row
+  constexpr int32_t NC4 = 2 * R + 4, NQ = (NC4 + 3) / 4;  // cells, 16-byte LDS reads per row
+  // the previous row's cells and texels; INT32_MIN is no cell value (|lin| < 2^30)
+  int32_t up_cells[4 * NQ];
+  Texels4 up_row[NC4];
+#pragma unroll
+  for (int32_t c = 0; c < 4 * NQ; ++c) up_cells[c] = INT32_MIN;
+#pragma unroll
+  for (int32_t c = 0; c < NC4; ++c) up_row[c] = Texels4{{0, 0, 0, 0}};
 #pragma unroll 1
   for (int32_t dy = 0; dy < 2 * R + 1; ++dy) {
-    const i32x4 *row = reinterpret_cast<const i32x4 *>(lin + (ly + dy) * LW + 4 * gx);
+    const i32x4 *q4 = reinterpret_cast<const i32x4 *>(lin + (ly + dy) * LW + 4 * gx);
     int32_t cells[4 * NQ];
 #pragma unroll
     for (int32_t q = 0; q < NQ; ++q) {
-      const i32x4 v = row[q];
+      const i32x4 v = q4[q];
       cells[4 * q] = v.x, cells[4 * q + 1] = v.y, cells[4 * q + 2] = v.z, cells[4 * q + 3] = v.w;
     }
-    vote_row<R, 0>(ex, pbase, cells, S, RB);
+    Texels4 row[NC4];
+    vote_row<R, 0>(ex, pbase, cells, up_cells, row, up_row, S, RB);
+#pragma unroll
+    for (int32_t c = 0; c < 4 * NQ; ++c) up_cells[c] = cells[c];
+#pragma unroll
+    for (int32_t c = 0; c < NC4; ++c) up_row[c] = row[c];
   }
   if (y >= a.h || x >= a.w) return;
   uint32_t c[4];
