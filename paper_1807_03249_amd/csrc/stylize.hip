@@ -31,14 +31,21 @@ __device__ __forceinline__ SB_GLOBAL u32x2 *seed_table(const FrameArgs &a) {
   return reinterpret_cast<SB_GLOBAL u32x2 *>(glb(a.seeds));
 }
 
+// A guide texel as stored (2 x u8 or 2 x u16) and unpacked to the u16 pair
+// layout (channel 1 in the high half).
+template <int FMT>
+__device__ inline uint32_t guide_raw(const void *g, uint32_t i) {
+  if (FMT == SB_GUIDE_U8X2) return glb(static_cast<const uint16_t *>(g))[i];
+  return glb(static_cast<const uint32_t *>(g))[i];
+}
+template <int FMT>
+__device__ inline uint32_t guide_unpack(uint32_t v) {
+  if (FMT == SB_GUIDE_U8X2) return (v & 0xFFu) | ((v >> 8) << 16);
+  return v;
+}
 template <int FMT>
 __device__ inline uint32_t guide_word(const void *g, uint32_t i) {
-  if (FMT == SB_GUIDE_U8X2) {
-    uint32_t v = glb(static_cast<const uint16_t *>(g))[i];
-    return (v & 0xFFu) | ((v >> 8) << 16);  // unpack to the u16 pair layout
-  } else {
-    return glb(static_cast<const uint32_t *>(g))[i];
-  }
+  return guide_unpack<FMT>(guide_raw<FMT>(g, i));
 }
 
 // Lookup-table bin of a guide word (two channels, 16 bits apart).
@@ -142,90 +149,117 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int32_t kRecStride = 12;
 constexpr int32_t kWaveRecs = SB_MAX_LEVELS * kRecStride;
 
+// Levels per group of the block level loop (two: one round trip of gathers
+// per two levels, and an early exit once every pixel of the block is done).
+constexpr int32_t kLevelGroup = 2;
+
+// N levels i0 .. i0+N-1 of the block level loop for one pixel: NearestSeed
+// over each level's nine staged records, then all N source-guide gathers in
+// flight together, then the tests in level order.  Straight-line code
+// (levels past L rescan level L-1 and are never taken), so the gathers issue
+// back to back.
+template <int FMT, int N>
+__device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *lpos,
+                                            const uint32_t *loff, int32_t i0, int32_t x, int32_t y,
+                                            short2_t p4, uint32_t gt, uint32_t &chunk,
+                                            uint32_t &off, bool &done) {
+  const int32_t L = a.lv.count;
+  const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
+  uint32_t g[N], wq[N], wo[N];
+  bool ok[N];
+#pragma unroll
+  for (int32_t u = 0; u < N; ++u) {
+    const int32_t li = min(i0 + u, L - 1);
+    const uint32_t *P = lpos + kRecStride * li;
+    const i32x4 q03 = *reinterpret_cast<const i32x4 *>(P);
+    const i32x4 q47 = *reinterpret_cast<const i32x4 *>(P + 4);
+    int32_t key = seed_key(uint32_t(q03.x), p4, 0);
+    key = min(key, seed_key(uint32_t(q03.y), p4, 1));
+    key = min(key, seed_key(uint32_t(q03.z), p4, 2));
+    key = min(key, seed_key(uint32_t(q03.w), p4, 3));
+    key = min(key, seed_key(uint32_t(q47.x), p4, 4));
+    key = min(key, seed_key(uint32_t(q47.y), p4, 5));
+    key = min(key, seed_key(uint32_t(q47.z), p4, 6));
+    key = min(key, seed_key(uint32_t(q47.w), p4, 7));
+    key = min(key, seed_key(P[8], p4, 8));
+    const int32_t w = kRecStride * li + (key & 15);
+    wq[u] = lpos[w];
+    wo[u] = loff[w];
+    const int32_t vx = x + off_x(wo[u]), vy = y + off_y(wo[u]);
+    // non-short-circuit: keeps the group one straight-line block
+    ok[u] = (i0 + u < L) & (key != INT32_MAX) & (uint32_t(vx) < sw) & (uint32_t(vy) < sh);
+    g[u] = ok[u] ? uint32_t(vy) * sw + uint32_t(vx) : 0u;
+  }
+#pragma unroll
+  for (int32_t u = 0; u < N; ++u) g[u] = guide_raw<FMT>(a.src_guide, g[u]);
+#pragma unroll
+  for (int32_t u = 0; u < N; ++u) {
+    const bool below = error_below<FMT>(gt, guide_unpack<FMT>(g[u]), a.threshold);
+    const bool take = (!done) & ok[u] & below;
+    chunk = take ? chunk_code(i0 + u, wq[u]) : chunk;
+    off = take ? wo[u] : off;
+    done = done || take;
+  }
+}
+
 // The level loop for one 8 x 8 block whose pixels share one cell at every
 // level (every spacing >= 8).  The wave stages its 9 L seed records in LDS
-// (one gather), scans each level's nine with packed arithmetic, and keeps up
-// to four levels' source-guide gathers in flight before testing them in
-// level order.
+// (one gather per 64 records) and runs the levels in groups (level_group).  The target guide, the records and the
+// pixel's own lookup (its fallback) are all requested up front, so the chain
+// of dependent memory round trips is guide -> lookup and records -> source
+// guide, side by side.
 template <int FMT>
 __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0, int32_t lane,
                                     uint32_t *lpos, uint32_t *loff) {
   const Levels &lv = a.lv;
   const int32_t L = lv.count;
-  for (int32_t j0 = 0; j0 < 9 * L; j0 += 64) {
-    const int32_t j = j0 + lane;
-    uint32_t ridx = 0;
-    int32_t slot = -1;
-    const int32_t i_end = min(L, (j0 + 72) / 9);
-    for (int32_t i = j0 / 9; i < i_end; ++i) {
-      const int32_t ls = lv.log2_spacing[i], pc = lv.cells_x[i] + 2;
-      // padded coordinates of the 3x3 neighbourhood's top-left cell
-      const int32_t top = lv.poffset[i] + (by0 >> ls) * pc + (bx0 >> ls);
-      const int32_t k = j - 9 * i;
-      if (k >= 0 && k < 9) {
-        const int32_t kx = (k * 11) >> 5;  // k / 3 for k < 9
-        ridx = uint32_t(top + (k - 3 * kx) * pc + kx);
-        slot = kRecStride * i + k;
-      }
-    }
-    if (slot >= 0) {
-      const u32x2 r = seed_table(a)[ridx];
-      lpos[slot] = r.x;
-      loff[slot] = r.y;
-    }
-  }
-  wave_lds_sync();
   const int32_t x = bx0 + (lane & 7), y = by0 + (lane >> 3);
   const bool in = x < a.w && y < a.h;
   const uint32_t pidx = in ? uint32_t(y) * uint32_t(a.w) + uint32_t(x) : 0u;
   const uint32_t gt = guide_word<FMT>(a.tgt_guide, pidx);
-  const short2_t p4 = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x), uint32_t(4 * y)));
-  const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
-  uint32_t chunk = 0, off = 0;
-  bool done = !in;
-  for (int32_t i0 = 0; i0 < L; i0 += 4) {
-    if (__all(done)) break;
-    uint32_t g[4], wq[4], wo[4];
-    bool ok[4];
+  // record j of the block (level j / 9, neighbour j % 9) for lanes j and j + 64
+  uint32_t ridx[2] = {0, 0};
+  int32_t slot[2] = {-1, -1};
+  for (int32_t i = 0; i < L; ++i) {
+    const int32_t ls = lv.log2_spacing[i], pc = lv.cells_x[i] + 2;
+    // padded coordinates of the 3x3 neighbourhood's top-left cell
+    const int32_t top = lv.poffset[i] + (by0 >> ls) * pc + (bx0 >> ls);
 #pragma unroll
-    for (int32_t u = 0; u < 4; ++u) {
-      ok[u] = false;
-      g[u] = wq[u] = wo[u] = 0;
-      if (i0 + u < L) {
-        const uint32_t *P = lpos + kRecStride * (i0 + u);
-        const i32x4 q03 = *reinterpret_cast<const i32x4 *>(P);
-        const i32x4 q47 = *reinterpret_cast<const i32x4 *>(P + 4);
-        int32_t key = seed_key(uint32_t(q03.x), p4, 0);
-        key = min(key, seed_key(uint32_t(q03.y), p4, 1));
-        key = min(key, seed_key(uint32_t(q03.z), p4, 2));
-        key = min(key, seed_key(uint32_t(q03.w), p4, 3));
-        key = min(key, seed_key(uint32_t(q47.x), p4, 4));
-        key = min(key, seed_key(uint32_t(q47.y), p4, 5));
-        key = min(key, seed_key(uint32_t(q47.z), p4, 6));
-        key = min(key, seed_key(uint32_t(q47.w), p4, 7));
-        key = min(key, seed_key(P[8], p4, 8));
-        const int32_t w = kRecStride * (i0 + u) + (key & 15);
-        wq[u] = lpos[w];
-        wo[u] = loff[w];
-        const int32_t vx = x + off_x(wo[u]), vy = y + off_y(wo[u]);
-        ok[u] = key != INT32_MAX && uint32_t(vx) < sw && uint32_t(vy) < sh;
-        g[u] = guide_word<FMT>(a.src_guide, ok[u] ? uint32_t(vy) * sw + uint32_t(vx) : 0u);
-      }
-    }
-#pragma unroll
-    for (int32_t u = 0; u < 4; ++u) {
-      if (!done && ok[u] && error_below<FMT>(gt, g[u], a.threshold)) {
-        chunk = chunk_code(i0 + u, wq[u]);
-        off = wo[u];
-        done = true;
+    for (int32_t h = 0; h < 2; ++h) {
+      const int32_t k = lane + 64 * h - 9 * i;
+      if (k >= 0 && k < 9) {
+        const int32_t kx = (k * 11) >> 5;  // k / 3 for k < 9
+        ridx[h] = uint32_t(top + (k - 3 * kx) * pc + kx);
+        slot[h] = kRecStride * i + k;
       }
     }
   }
+  u32x2 rec[2] = {{0, 0}, {0, 0}};
+#pragma unroll
+  for (int32_t h = 0; h < 2; ++h)
+    if (slot[h] >= 0) rec[h] = seed_table(a)[ridx[h]];
+#pragma unroll
+  for (int32_t h = 0; h < 2; ++h) {
+    if (slot[h] >= 0) {
+      lpos[slot[h]] = rec[h].x;
+      loff[slot[h]] = rec[h].y;
+    }
+  }
+  wave_lds_sync();
+  // the pixel's own lookup, used when no level accepts
+  const uint32_t own = glb(a.lut)[lut_bin(gt, a.lut_shift, a.lut_bits)];
+  const short2_t p4 = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x), uint32_t(4 * y)));
+  uint32_t chunk = 0, off = 0;
+  bool done = !in;
+  // groups of levels until every pixel of the block has one or they run out
+  for (int32_t i0 = 0; i0 < L; i0 += kLevelGroup) {
+    if (__all(done)) break;
+    level_group<FMT, kLevelGroup>(a, lpos, loff, i0, x, y, p4, gt, chunk, off, done);
+  }
   if (!in) return;
   if (!done) {  // no level accepted: the pixel's own lookup
-    const uint32_t u = glb(a.lut)[lut_bin(gt, a.lut_shift, a.lut_bits)];
     chunk = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
-    off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
+    off = pack_off(int32_t(own & 0xFFFFu) - x, int32_t(own >> 16) - y);
   }
   glb(a.out_chunk)[pidx] = chunk;
   glb(a.offsets)[pidx] = off;
