@@ -140,31 +140,37 @@ int sb_stylize(const sb_style *style, const void *tgt_guide, int32_t w, int32_t 
                uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
                hipStream_t stream);
 
-/* Kernel choice for one frame.  Every choice computes the same result bit for
- * bit; they differ only in speed.
- *   path: SB_PATH_TWO_PASS runs a seed-record pass, a per-pixel level-loop
- *         pass writing NNF offsets to the workspace, and a voting pass;
- *         SB_PATH_FUSED runs the whole frame in one kernel (tiles with their
- *         seed grids, voting halo and outputs staged in LDS); SB_PATH_AUTO is
- *         the library's default (currently the two-pass path).
- *   tile: the fused path's tile in pixels (SB_TILE_AUTO = 32x16). */
-typedef enum { SB_PATH_AUTO = 0, SB_PATH_FUSED = 1, SB_PATH_TWO_PASS = 2 } sb_path;
-typedef enum {
-    SB_TILE_AUTO = 0, SB_TILE_32x16 = 1, SB_TILE_32x32 = 2, SB_TILE_64x16 = 3, SB_TILE_64x32 = 4
-} sb_tile;
+/* Kernel choice.  Every choice computes the same result bit for bit; they
+ * differ only in speed, so an autotuner may pick any.  0 in a field takes the
+ * library's default.
+ *   blend_ppt    pixels per thread of the voting pass, adjacent in a row: 2 or
+ *                4 (default 4); each vote gather loads that many texels
+ *   blend_rows   rows of the voting tile: 8 or 16 (default 16); the tile is
+ *                (16 * blend_ppt) x blend_rows pixels, one thread per
+ *                blend_ppt pixels
+ *   level_group  levels of Algorithm 2 whose source-guide gathers are in
+ *                flight together before their tests: 2 or 4 (default 2) */
 typedef struct {
-    int32_t path;   /* sb_path */
-    int32_t tile;   /* sb_tile */
+    int32_t blend_ppt;
+    int32_t blend_rows;
+    int32_t level_group;
 } sb_tune;
 
-/* sb_stylize with an explicit kernel choice (tune may be NULL = auto).  With a
- * fused choice the workspace is not touched and may be NULL with size 0;
- * SB_EINVAL if the requested tile does not fit in 64 KiB of LDS (radius and
- * finest spacing decide its size). */
+/* sb_stylize with an explicit kernel choice (tune may be NULL = defaults);
+ * SB_EINVAL for an unsupported field value. */
 int sb_stylize_ex(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
                   const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
                   uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
                   size_t workspace_bytes, const sb_tune *tune, hipStream_t stream);
+
+/* sb_stylize_ex that also records events[0..3] (created by the caller, with
+ * timing) on `stream` before the seed-record pass, before the level-loop
+ * pass, before the voting pass and after it, for per-pass timing. */
+int sb_stylize_timed(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+                     const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+                     uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
+                     size_t workspace_bytes, const sb_tune *tune, hipEvent_t events[4],
+                     hipStream_t stream);
 
 /* ---------------------------------------------------------------- batches */
 
@@ -194,13 +200,15 @@ size_t sb_batch_workspace_bytes(const sb_frame *frames, int32_t n);
  * hipHostMalloc] of sb_batch_desc_bytes() each stay owned by the caller and
  * must outlive the plan.  With use_graph != 0 the plan captures, once, two
  * hipGraphs on `stream` (which must not be the null stream): the upload of
- * one descriptor half followed by three persistent kernels (seed records,
- * per-pixel level loop, voting) that stride over the concatenated tiles of
- * all frames of the batch.  The graphs hold no shapes, so they serve every
- * later batch.  With use_graph == 0 the same upload and kernels are
- * enqueued directly on each run. */
-int sb_batch_create(void *desc_dev, void *desc_host, int32_t use_graph, hipStream_t stream,
-                    sb_batch **out);
+ * one descriptor half followed by persistent kernels (seed records,
+ * per-pixel level loop, voting for radius 0..3 and for 4..7) that stride
+ * over the concatenated tiles of all frames of the batch.  The graphs hold
+ * no shapes, so they serve every later batch.  With use_graph == 0 the same
+ * upload and kernels are enqueued directly on each run.  tune (may be NULL)
+ * fixes the kernel choice of every run; blocks_per_cu (0 = 8, else 1..16)
+ * sets the persistent grid to that many blocks per compute unit. */
+int sb_batch_create(void *desc_dev, void *desc_host, int32_t use_graph, const sb_tune *tune,
+                    int32_t blocks_per_cu, hipStream_t stream, sb_batch **out);
 /* Stylise n frames (1..sb_batch_max_frames()) with one graph launch on
  * `stream`; the results equal n separate sb_stylize calls bit for bit.
  * Validates every frame first (SB_EINVAL / SB_ENOMEM and nothing enqueued
@@ -231,6 +239,8 @@ typedef struct {
     void *workspace;    /* [device] slots * workspace_bytes_per_slot */
     size_t workspace_bytes_per_slot;  /* >= max_batch * (sb_workspace_bytes + 256) of the
                                          largest request */
+    sb_tune tune;       /* kernel choice of every launch (zeros = defaults) */
+    int32_t blocks_per_cu;  /* batch plans' persistent grid, as in sb_batch_create */
 } sb_serve_config;
 
 typedef struct {

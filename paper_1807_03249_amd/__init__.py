@@ -36,14 +36,22 @@ class SbStyle(ctypes.Structure):
 
 
 class SbTune(ctypes.Structure):
-    _fields_ = [("path", ctypes.c_int32), ("tile", ctypes.c_int32)]
+    _fields_ = [("blend_ppt", ctypes.c_int32), ("blend_rows", ctypes.c_int32),
+                ("level_group", ctypes.c_int32)]
 
 
-PATH_AUTO, PATH_FUSED, PATH_TWO_PASS = 0, 1, 2
-TILE_AUTO, TILE_32x16, TILE_32x32, TILE_64x16, TILE_64x32 = 0, 1, 2, 3, 4
-# every kernel choice; all compute the same bits
-TUNES = [(PATH_TWO_PASS, TILE_AUTO)] + [(PATH_FUSED, t) for t in
-                                        (TILE_32x16, TILE_32x32, TILE_64x16, TILE_64x32)]
+# every kernel choice (blend_ppt, blend_rows, level_group); all compute the
+# same bits, (0, 0, 0) is the library default
+TUNES = [(ppt, rows, grp) for ppt in (4, 2) for rows in (16, 8) for grp in (2, 4)]
+
+
+def tune_struct(tune) -> Optional[SbTune]:
+    """SbTune from a (blend_ppt, blend_rows, level_group) tuple (None stays None)."""
+    if tune is None:
+        return None
+    if isinstance(tune, SbTune):
+        return tune
+    return SbTune(*(int(v) for v in tune))
 
 
 class SbParams(ctypes.Structure):
@@ -89,11 +97,15 @@ def lib():
     L.sb_stylize_ex.argtypes = [ctypes.POINTER(SbStyle), vp, i32, i32, vp,
                                 ctypes.POINTER(SbParams), vp, vp, vp, vp, sz,
                                 ctypes.POINTER(SbTune), vp]
+    L.sb_stylize_timed.argtypes = [ctypes.POINTER(SbStyle), vp, i32, i32, vp,
+                                   ctypes.POINTER(SbParams), vp, vp, vp, vp, sz,
+                                   ctypes.POINTER(SbTune), ctypes.POINTER(vp), vp]
     L.sb_batch_max_frames.restype = ctypes.c_int32
     L.sb_batch_desc_bytes.restype = sz
     L.sb_batch_workspace_bytes.restype = sz
     L.sb_batch_workspace_bytes.argtypes = [ctypes.POINTER(SbFrame), i32]
-    L.sb_batch_create.argtypes = [vp, vp, i32, vp, ctypes.POINTER(ctypes.c_void_p)]
+    L.sb_batch_create.argtypes = [vp, vp, i32, ctypes.POINTER(SbTune), i32, vp,
+                                  ctypes.POINTER(ctypes.c_void_p)]
     L.sb_batch_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(SbFrame), i32, vp, sz, vp]
     L.sb_batch_destroy.argtypes = [ctypes.c_void_p]
     _lib = L
@@ -203,11 +215,14 @@ def workspace_bytes(w: int, h: int, p: SbParams) -> int:
 
 
 def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chunk=None,
-            want_nnf: bool = False, workspace=None, stream=None, tune=None):
+            want_nnf: bool = False, workspace=None, stream=None, tune=None, events=None):
     """Stylise one frame.  ``tgt_guide`` (H, W, 2) and ``jitter`` (uint32 as
     int32 bits) may be numpy arrays or device tensors.  Returns
     ``(rgb (H,W,3) uint8, chunk (H,W) int32-bits[, nnf])`` as device tensors;
-    the work is enqueued on the current stream."""
+    the work is enqueued on the current stream.  ``tune`` is a
+    (blend_ppt, blend_rows, level_group) choice (None = defaults); with
+    ``events`` (four timing ``torch.cuda.Event``) the passes are bracketed by
+    them (sb_stylize_timed)."""
     torch = _torch()
     g = tgt_guide
     if not isinstance(g, torch.Tensor) and str(getattr(g, "dtype", "")) == "uint16":
@@ -241,21 +256,38 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     s = _stream(torch) if stream is None else stream
-    if tune is None:
+    tn = tune_struct(tune)
+    tp = ctypes.byref(tn) if tn is not None else None
+    nnf_p = nnf.data_ptr() if nnf is not None else None
+    if events is not None:
+        evs = (ctypes.c_void_p * 4)(*[e.cuda_event for e in _recorded(torch, events, s)])
+        _check(lib().sb_stylize_timed(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
+                                      ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
+                                      nnf_p, workspace.data_ptr(), wsb, tp, evs, s),
+               "sb_stylize_timed")
+    elif tn is None:
         _check(lib().sb_stylize(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
                                 ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
-                                nnf.data_ptr() if nnf is not None else None,
-                                workspace.data_ptr(), wsb, s), "sb_stylize")
+                                nnf_p, workspace.data_ptr(), wsb, s), "sb_stylize")
     else:
-        tn = SbTune(int(tune[0]), int(tune[1]))
         _check(lib().sb_stylize_ex(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
                                    ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
-                                   nnf.data_ptr() if nnf is not None else None,
-                                   workspace.data_ptr(), wsb, ctypes.byref(tn), s),
-               "sb_stylize_ex")
+                                   nnf_p, workspace.data_ptr(), wsb, tp, s), "sb_stylize_ex")
     if want_nnf:
         return out_rgb, out_chunk, nnf
     return out_rgb, out_chunk
+
+
+def _recorded(torch, events, stream):
+    """torch.cuda.Events whose HIP events exist (torch creates them lazily at
+    the first record): record each once on the stream, then hand them over."""
+    if len(events) != 4:
+        raise ValueError("sb_stylize_timed takes four events")
+    st = torch.cuda.ExternalStream(stream) if isinstance(stream, int) else torch.cuda.current_stream()
+    for e in events:
+        if e.cuda_event == 0:
+            e.record(st)
+    return events
 
 
 class FrameJob:
@@ -301,20 +333,24 @@ class FrameJob:
 
 class Batch:
     """A batch plan: many frames per launch.  With ``use_graph`` the launch
-    is one replay of a hipGraph captured once (descriptor upload + three
-    persistent kernels) on the plan's own stream."""
+    is one replay of a hipGraph captured once (descriptor upload + the
+    persistent kernels) on the plan's own stream.  ``tune`` and
+    ``blocks_per_cu`` fix the kernel choice and persistent grid."""
 
-    def __init__(self, use_graph: bool = True):
+    def __init__(self, use_graph: bool = True, tune=None, blocks_per_cu: int = 0):
         torch = _torch()
         L = lib()
         nb = L.sb_batch_desc_bytes()
         self.desc_dev = torch.empty(nb, dtype=torch.uint8, device="cuda")
         self.desc_host = torch.empty(nb, dtype=torch.uint8).pin_memory()
         self.capture_stream = torch.cuda.Stream()
+        self.tune = tune_struct(tune)
         h = ctypes.c_void_p()
         torch.cuda.synchronize()
         _check(L.sb_batch_create(self.desc_dev.data_ptr(), self.desc_host.data_ptr(),
-                                 1 if use_graph else 0, self.capture_stream.cuda_stream,
+                                 1 if use_graph else 0,
+                                 ctypes.byref(self.tune) if self.tune is not None else None,
+                                 int(blocks_per_cu), self.capture_stream.cuda_stream,
                                  ctypes.byref(h)), "sb_batch_create")
         self.handle = h
         self.max_frames = L.sb_batch_max_frames()

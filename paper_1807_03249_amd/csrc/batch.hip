@@ -23,6 +23,7 @@ struct sb_batch {
   bool used[2];
   bool use_graph;
   uint32_t grid;
+  sb::Tune tune;
   int next;
 };
 
@@ -65,14 +66,18 @@ size_t sb_batch_workspace_bytes(const sb_frame *frames, int32_t n) {
   return total;
 }
 
-int sb_batch_create(void *desc_dev, void *desc_host, int32_t use_graph, hipStream_t stream,
-                    sb_batch **out) {
+int sb_batch_create(void *desc_dev, void *desc_host, int32_t use_graph, const sb_tune *tune,
+                    int32_t blocks_per_cu, hipStream_t stream, sb_batch **out) {
   if (!desc_dev || !desc_host || !out) return SB_EINVAL;
   if (use_graph && stream == nullptr) return SB_EINVAL;  // capture needs a created stream
+  if (blocks_per_cu < 0 || blocks_per_cu > 16) return SB_EINVAL;
+  Tune t;
+  if (!resolve_tune(tune, &t)) return SB_EINVAL;
   sb_batch *b = new (std::nothrow) sb_batch;
   if (!b) return SB_ENOMEM;
   memset(b, 0, sizeof *b);
   b->use_graph = use_graph != 0;
+  b->tune = t;
   for (int k = 0; k < 2; ++k) {
     b->desc_dev[k] = static_cast<unsigned char *>(desc_dev) + k * batch_desc_bytes();
     b->desc_host[k] = static_cast<unsigned char *>(desc_host) + k * batch_desc_bytes();
@@ -80,7 +85,7 @@ int sb_batch_create(void *desc_dev, void *desc_host, int32_t use_graph, hipStrea
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  b->grid = uint32_t(cus > 0 ? cus : 256) * 8;
+  b->grid = uint32_t(cus > 0 ? cus : 256) * uint32_t(blocks_per_cu > 0 ? blocks_per_cu : 8);
   for (int k = 0; k < 2 && e == hipSuccess; ++k)
     e = hipEventCreateWithFlags(&b->done[k], hipEventDisableTiming);
   for (int k = 0; k < 2 && e == hipSuccess && b->use_graph; ++k) {
@@ -88,7 +93,7 @@ int sb_batch_create(void *desc_dev, void *desc_host, int32_t use_graph, hipStrea
     if (e != hipSuccess) break;
     hipError_t ec = hipMemcpyAsync(b->desc_dev[k], b->desc_host[k], batch_desc_bytes(),
                                    hipMemcpyHostToDevice, stream);
-    if (ec == hipSuccess) ec = launch_batch(b->desc_dev[k], b->grid, stream);
+    if (ec == hipSuccess) ec = launch_batch(b->desc_dev[k], b->grid, b->tune, stream);
     e = hipStreamEndCapture(stream, &b->graph[k]);
     if (ec != hipSuccess) e = ec;
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[k], b->graph[k], nullptr, nullptr, 0);
@@ -133,15 +138,15 @@ int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace
   memset(&hdr, 0, sizeof hdr);
   hdr.nframes = uint32_t(n);
   memcpy(hd, &hdr, sizeof hdr);
-  uint32_t *pre[3];
-  for (int kind = 0; kind < 3; ++kind) {
+  uint32_t *pre[kBatchKinds];
+  for (int kind = 0; kind < kBatchKinds; ++kind) {
     pre[kind] = reinterpret_cast<uint32_t *>(hd + batch_prefix_offset(kind));
     pre[kind][0] = 0;
   }
   for (int32_t f = 0; f < n; ++f) {
-    uint32_t c[3];
-    tile_counts(args[f], c);
-    for (int kind = 0; kind < 3; ++kind) pre[kind][f + 1] = pre[kind][f] + c[kind];
+    uint32_t c[kBatchKinds];
+    tile_counts(args[f], b->tune, c);
+    for (int kind = 0; kind < kBatchKinds; ++kind) pre[kind][f + 1] = pre[kind][f] + c[kind];
   }
   memcpy(hd + batch_frames_offset(), args, size_t(n) * sizeof(FrameArgs));
   hipError_t e;
@@ -149,7 +154,7 @@ int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace
     e = hipGraphLaunch(b->exec[k], stream);
   } else {
     e = hipMemcpyAsync(b->desc_dev[k], hd, batch_desc_bytes(), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = launch_batch(b->desc_dev[k], b->grid, stream);
+    if (e == hipSuccess) e = launch_batch(b->desc_dev[k], b->grid, b->tune, stream);
   }
   if (e == hipSuccess) e = hipEventRecord(b->done[k], stream);
   if (e != hipSuccess) {

@@ -97,6 +97,26 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
   return true;
 }
 
+bool resolve_tune(const sb_tune *in, Tune *out) {
+  out->ppt = 4;
+  out->rows = 16;
+  out->group = 2;
+  if (!in) return true;
+  if (in->blend_ppt != 0) {
+    if (in->blend_ppt != 2 && in->blend_ppt != 4) return false;
+    out->ppt = in->blend_ppt;
+  }
+  if (in->blend_rows != 0) {
+    if (in->blend_rows != 8 && in->blend_rows != 16) return false;
+    out->rows = in->blend_rows;
+  }
+  if (in->level_group != 0) {
+    if (in->level_group != 2 && in->level_group != 4) return false;
+    out->group = in->level_group;
+  }
+  return true;
+}
+
 void carve_workspace(FrameArgs *a, void *workspace) {
   char *ws = static_cast<char *>(workspace);
   a->seeds = reinterpret_cast<uint2 *>(ws);
@@ -109,7 +129,7 @@ using namespace sb;
 
 extern "C" {
 
-const char *sb_version(void) { return "styleblit-gfx950 0.2"; }
+const char *sb_version(void) { return "styleblit-gfx950 0.3"; }
 
 const char *sb_status_string(int status) {
   switch (status) {
@@ -174,36 +194,44 @@ size_t sb_workspace_bytes(int32_t w, int32_t h, const sb_params *params) {
   return align256(size_t(lv.poffset[lv.count]) * 8) + align256(size_t(w) * size_t(h) * 4);
 }
 
-int sb_stylize_ex(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
-                  const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
-                  uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
-                  size_t workspace_bytes, const sb_tune *tune, hipStream_t stream) {
+namespace {
+int stylize_impl(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+                 const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+                 uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
+                 const sb_tune *tune, hipEvent_t *events, hipStream_t stream) {
   FrameArgs a;
   if (!fill_frame(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf, &a))
     return SB_EINVAL;
-  const int32_t path = tune ? tune->path : SB_PATH_AUTO;
-  const int32_t tile_req = tune ? tune->tile : SB_TILE_AUTO;
-  if (path < SB_PATH_AUTO || path > SB_PATH_TWO_PASS) return SB_EINVAL;
-  if (tile_req < SB_TILE_AUTO || tile_req > SB_TILE_64x32) return SB_EINVAL;
-  int32_t tile = 0;
-  if (path == SB_PATH_FUSED) {
-    tile = tile_req != SB_TILE_AUTO ? tile_req : int32_t(kTile32x16);
-    if (!frame_tile_fits(a, tile)) return SB_EINVAL;
-  }
-  hipError_t e;
-  if (tile) {
-    e = launch_frame(a, style->fmt, tile, stream);
-  } else {
-    if (!workspace) return SB_EINVAL;
-    if (workspace_bytes < sb_workspace_bytes(w, h, params)) return SB_ENOMEM;
-    carve_workspace(&a, workspace);
-    e = launch_stylize(a, style->fmt, stream);
-  }
+  Tune t;
+  if (!resolve_tune(tune, &t)) return SB_EINVAL;
+  if (!workspace) return SB_EINVAL;
+  if (workspace_bytes < sb_workspace_bytes(w, h, params)) return SB_ENOMEM;
+  carve_workspace(&a, workspace);
+  const hipError_t e = launch_stylize(a, style->fmt, t, events, stream);
   if (e != hipSuccess) {
     set_hip_error(e, "sb_stylize");
     return SB_EHIP;
   }
   return SB_OK;
+}
+}  // namespace
+
+int sb_stylize_ex(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+                  const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+                  uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
+                  size_t workspace_bytes, const sb_tune *tune, hipStream_t stream) {
+  return stylize_impl(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf,
+                      workspace, workspace_bytes, tune, nullptr, stream);
+}
+
+int sb_stylize_timed(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+                     const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+                     uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
+                     size_t workspace_bytes, const sb_tune *tune, hipEvent_t events[4],
+                     hipStream_t stream) {
+  if (!events || !events[0] || !events[1] || !events[2] || !events[3]) return SB_EINVAL;
+  return stylize_impl(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf,
+                      workspace, workspace_bytes, tune, events, stream);
 }
 
 int sb_stylize(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,

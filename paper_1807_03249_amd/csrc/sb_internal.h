@@ -29,8 +29,18 @@ struct Levels {
   int32_t poffset[SB_MAX_LEVELS + 1];  // first record of level i; poffset[L] = total
 };
 
-// Voting tile of the blend (pixels): 256 threads, 4 horizontal pixels each.
-constexpr int32_t kBlendTW = 64, kBlendTH = 16;
+// Largest voting tile of the blend (pixels): 256 threads, 4 horizontal
+// pixels each.
+constexpr int32_t kBlendMaxTW = 64, kBlendMaxTH = 16;
+
+// A resolved kernel choice (see sb_tune): pixels per thread and tile rows of
+// the vote pass, levels per gather round of the level loop.
+struct Tune {
+  int32_t ppt, rows, group;
+};
+// Fill a Tune from the caller's sb_tune (NULL or 0 fields = defaults); false
+// if a field holds an unsupported value.
+bool resolve_tune(const sb_tune *in, Tune *out);
 
 // Padded exemplar: texels of Sw x Sh sit in rows of sw + 2 * kExMargin
 // texels with kExMargin empty (zero) texels on every side, followed by zero
@@ -40,7 +50,7 @@ constexpr int32_t kBlendTW = 64, kBlendTH = 16;
 constexpr int32_t kExMargin = 8;
 __host__ __device__ constexpr int32_t ex_stride(int32_t sw) { return sw + 2 * kExMargin; }
 __host__ __device__ constexpr int32_t ex_zero_rows(int32_t sw) {
-  return kBlendTH - 1 + (kBlendTW + ex_stride(sw) - 1) / ex_stride(sw);
+  return kBlendMaxTH - 1 + (kBlendMaxTW + ex_stride(sw) - 1) / ex_stride(sw);
 }
 __host__ __device__ constexpr size_t ex_texels(int32_t sw, int32_t sh) {
   return size_t(ex_stride(sw)) * size_t(sh + 2 * kExMargin + ex_zero_rows(sw));
@@ -69,8 +79,10 @@ struct FrameArgs {
 };
 
 // Batch descriptor block in device memory: header, per-pass tile prefix sums
-// (kMaxBatchFrames + 1 entries each: seeds, assign, blend) and the frames.
+// (kMaxBatchFrames + 1 entries each: seeds, assign, blend of radius 0..3,
+// blend of radius 4..7) and the frames.
 constexpr uint32_t kMaxBatchFrames = 128;
+constexpr int kBatchKinds = 4;
 struct BatchHeader {
   uint32_t nframes, pad[3];
 };
@@ -78,24 +90,11 @@ __host__ __device__ constexpr size_t batch_prefix_offset(int kind) {
   return 16 + size_t(kind) * (kMaxBatchFrames + 1) * 4;
 }
 __host__ __device__ constexpr size_t batch_frames_offset() {
-  return (batch_prefix_offset(3) + 255) & ~size_t(255);
+  return (batch_prefix_offset(kBatchKinds) + 255) & ~size_t(255);
 }
 __host__ __device__ constexpr size_t batch_desc_bytes() {
   return batch_frames_offset() + kMaxBatchFrames * sizeof(FrameArgs);
 }
-
-// Fused-path tile shapes (width x height in pixels; 8x8 blocks per wave).
-enum { kTile32x16 = 1, kTile32x32 = 2, kTile64x16 = 3, kTile64x32 = 4 };
-constexpr size_t kMaxLds = 64 * 1024;
-
-// Per-launch geometry of the fused path: the staged seed grid of each level
-// (cells around the tile plus halo plus one ring) and the LDS carve-up.
-struct TileGeom {
-  int32_t grid_w[SB_MAX_LEVELS], grid_h[SB_MAX_LEVELS];
-  int32_t seed_off[SB_MAX_LEVELS + 1];  // in records; seed_off[L] = total
-  int32_t lds_seeds, lds_masks, lds_region, lds_chunk, lds_rgb, lds_vote, lds_bytes;
-  int32_t tiles_x, tiles_y, tile_w, tile_h;
-};
 
 // Fill the level geometry for a W x H frame; false if the parameters are out
 // of range.
@@ -118,13 +117,15 @@ void set_error_text(const char *msg);
 // error.
 hipError_t launch_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t *rgba,
                                 hipStream_t stream);
-hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, hipStream_t stream);
-// Tiles of the three two-pass kernels for one frame (seeds, assign, blend).
-void tile_counts(const FrameArgs &a, uint32_t counts[3]);
-// The three passes over a batch described at desc_dev, persistent grids.
-hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, hipStream_t stream);
-bool frame_tile_fits(const FrameArgs &a, int32_t tile);
-hipError_t launch_frame(const FrameArgs &a, int32_t fmt, int32_t tile, hipStream_t stream);
+// One frame's three passes; with ev (4 events) records ev[0..3] before the
+// seed, assignment and vote passes and after the vote pass.
+hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, const Tune &t, hipEvent_t *ev,
+                          hipStream_t stream);
+// Tiles of one frame per batch pass kind (seeds, assign, vote r <= 3, vote r >= 4).
+void tile_counts(const FrameArgs &a, const Tune &t, uint32_t counts[kBatchKinds]);
+// The passes over a batch described at desc_dev, persistent grids.
+hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, const Tune &t,
+                        hipStream_t stream);
 size_t lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits);
 hipError_t launch_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh,
                             int32_t lut_bits, uint32_t *lut, void *workspace, hipStream_t stream);

@@ -105,6 +105,9 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
   if (slots < 1 || slots > 8 || maxb < 1 || maxb > sb_batch_max_frames()) return SB_EINVAL;
   if (!plain && (!cfg->desc_dev || !cfg->desc_host || !cfg->workspace)) return SB_EINVAL;
   if (!cfg->workspace) return SB_EINVAL;
+  Tune tune;
+  if (!resolve_tune(&cfg->tune, &tune)) return SB_EINVAL;
+  if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 16) return SB_EINVAL;
   for (int32_t i = 0; i < n; ++i) {
     const sb_request &r = reqs[i];
     FrameArgs a;
@@ -132,7 +135,8 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
     if (e == hipSuccess && !plain) {
       const int rc = sb_batch_create(static_cast<char *>(cfg->desc_dev) + s * sb_batch_desc_bytes(),
                                      static_cast<char *>(cfg->desc_host) + s * sb_batch_desc_bytes(),
-                                     cfg->use_graph, sl[s].stream, &sl[s].plan);
+                                     cfg->use_graph, &cfg->tune, cfg->blocks_per_cu, sl[s].stream,
+                                     &sl[s].plan);
       if (rc != SB_OK) e = hipErrorUnknown;
     }
   }
@@ -225,9 +229,9 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
       while (!admitted.empty() && plain_inflight.size() < pev.size()) {
         const int32_t i = admitted.front();
         const sb_frame &f = fr[i];
-        const int r = sb_stylize(f.style, f.tgt_guide, f.w, f.h, f.jitter, &f.params, f.out_rgb,
-                                 f.out_chunk, nullptr, sl[0].workspace,
-                                 cfg->workspace_bytes_per_slot, sl[0].stream);
+        const int r = sb_stylize_ex(f.style, f.tgt_guide, f.w, f.h, f.jitter, &f.params,
+                                    f.out_rgb, f.out_chunk, nullptr, sl[0].workspace,
+                                    cfg->workspace_bytes_per_slot, &cfg->tune, sl[0].stream);
         if (r != SB_OK) {
           rc = r;
           break;

@@ -149,10 +149,6 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int32_t kRecStride = 12;
 constexpr int32_t kWaveRecs = SB_MAX_LEVELS * kRecStride;
 
-// Levels per group of the block level loop (two: one round trip of gathers
-// per two levels, and an early exit once every pixel of the block is done).
-constexpr int32_t kLevelGroup = 2;
-
 // N levels i0 .. i0+N-1 of the block level loop for one pixel: NearestSeed
 // over each level's nine staged records, then all N source-guide gathers in
 // flight together, then the tests in level order.  Straight-line code
@@ -204,11 +200,12 @@ __device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *
 
 // The level loop for one 8 x 8 block whose pixels share one cell at every
 // level (every spacing >= 8).  The wave stages its 9 L seed records in LDS
-// (one gather per 64 records) and runs the levels in groups (level_group).  The target guide, the records and the
+// (one gather per 64 records) and runs the levels in groups of G
+// (level_group).  The target guide, the records and the
 // pixel's own lookup (its fallback) are all requested up front, so the chain
 // of dependent memory round trips is guide -> lookup and records -> source
 // guide, side by side.
-template <int FMT>
+template <int FMT, int G>
 __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0, int32_t lane,
                                     uint32_t *lpos, uint32_t *loff) {
   const Levels &lv = a.lv;
@@ -251,10 +248,11 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
   const short2_t p4 = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x), uint32_t(4 * y)));
   uint32_t chunk = 0, off = 0;
   bool done = !in;
-  // groups of levels until every pixel of the block has one or they run out
-  for (int32_t i0 = 0; i0 < L; i0 += kLevelGroup) {
+  // groups of G levels (one round trip of gathers each) until every pixel of
+  // the block has a level or the levels run out
+  for (int32_t i0 = 0; i0 < L; i0 += G) {
     if (__all(done)) break;
-    level_group<FMT, kLevelGroup>(a, lpos, loff, i0, x, y, p4, gt, chunk, off, done);
+    level_group<FMT, G>(a, lpos, loff, i0, x, y, p4, gt, chunk, off, done);
   }
   if (!in) return;
   if (!done) {  // no level accepted: the pixel's own lookup
@@ -314,7 +312,7 @@ __device__ inline bool uniform_cells(const Levels &lv) {
 
 // One 16 x 16 tile: four 8 x 8 blocks, one per wave, on the uniform-cell
 // path; otherwise one pixel per thread.  `recs` is LDS for 4 waves' records.
-template <int FMT>
+template <int FMT, int G>
 __device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t tid,
                                    uint32_t *recs) {
   const uint32_t tiles_x = (uint32_t(a.w) + 15) / 16;
@@ -325,16 +323,16 @@ __device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t t
     // a block wholly outside the frame has no cells in the table
     if (bx0 >= a.w || by0 >= a.h) return;
     uint32_t *lpos = recs + wave * 2 * kWaveRecs;
-    assign_block<FMT>(a, bx0, by0, int32_t(tid & 63), lpos, lpos + kWaveRecs);
+    assign_block<FMT, G>(a, bx0, by0, int32_t(tid & 63), lpos, lpos + kWaveRecs);
   } else {
     assign_pixel<FMT>(a, tx0 + int32_t(tid & 15), ty0 + int32_t(tid >> 4));
   }
 }
 
-template <int FMT>
+template <int FMT, int G>
 __global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
   __shared__ __attribute__((aligned(16))) uint32_t recs[4 * 2 * kWaveRecs];
-  assign_tile<FMT>(a, blockIdx.x, threadIdx.x, recs);
+  assign_tile<FMT, G>(a, blockIdx.x, threadIdx.x, recs);
 }
 
 // Exact n / k for n < 2^20 and 1 <= k <= 225 via a float reciprocal and one
@@ -347,15 +345,15 @@ __device__ inline uint32_t div_small(uint32_t n, uint32_t k) {
   return q;
 }
 
-// LDS row length and rows of a voting tile of radius R (rows padded to a
-// multiple of 4 cells so each lane's cells start 16-byte aligned).
-__host__ __device__ constexpr int32_t blend_lw(int32_t r) { return (kBlendTW + 2 * r + 3) & ~3; }
-__host__ __device__ constexpr int32_t blend_lh(int32_t r) { return kBlendTH + 2 * r; }
+// LDS row length and rows of a voting tile of TW x TH pixels and radius R
+// (rows padded to a multiple of 4 cells so each lane's cells start aligned).
+__host__ __device__ constexpr int32_t blend_lw(int32_t tw, int32_t r) { return (tw + 2 * r + 3) & ~3; }
+__host__ __device__ constexpr int32_t blend_lh(int32_t th, int32_t r) { return th + 2 * r; }
 
 // Load n = 1..4 consecutive texels at byte offset `at` of the exemplar.
 template <int N>
 __device__ __forceinline__ void load_texels(const SB_GLOBAL unsigned char *ex, uint32_t at,
-                                            uint32_t t[4]) {
+                                            uint32_t *t) {
   const SB_GLOBAL unsigned char *p = ex + uint64_t(at);
   if (N == 4) {
     const u32x4a4 v = *reinterpret_cast<const SB_GLOBAL u32x4a4 *>(p);
@@ -371,31 +369,32 @@ __device__ __forceinline__ void load_texels(const SB_GLOBAL unsigned char *ex, u
   }
 }
 
-// Texels of the lane's four pixels for one window cell, indexed by pixel
-// J = 0..3 (only J0(c)..J1(c) are meaningful).
-struct Texels4 {
-  uint32_t t[4];
+// Texels of the lane's PPT pixels for one window cell, indexed by pixel J
+// (only J0(c)..J1(c) are meaningful).
+template <int PPT>
+struct TexelsN {
+  uint32_t t[PPT];
 };
 
-// The votes of cell column C (0 .. W+2) of one window row for the lane's
-// pixels J = C - 2R .. C (clipped to 0..3).  Every vote of a cell with offset
-// o for pixel p is the texel at p + o, so a cell with the same offset as the
-// cell above it (same column, previous row) or, from column 4 on, as its
-// left neighbour needs texels the lane already holds; only lanes whose cell
-// starts a new offset issue the gather, which is one vector load of the
+// The votes of cell column C (0 .. 2R+PPT-1) of one window row for the
+// lane's pixels J = C - 2R .. C (clipped to 0..PPT-1).  Every vote of a cell
+// with offset o for pixel p is the texel at p + o, so a cell with the same
+// offset as the cell above it (same column, previous row) or, from column PPT
+// on, as its left neighbour needs texels the lane already holds; only lanes
+// whose cell starts a new offset issue the gather, one vector load of the
 // pixels' adjacent texels.
-template <int R, int C>
+template <int R, int PPT, int C>
 __device__ __forceinline__ void vote_cell(const SB_GLOBAL unsigned char *ex, uint32_t pbase,
                                           const int32_t *cells, const int32_t *up_cells,
-                                          Texels4 *row, const Texels4 *up_row, uint32_t S[4],
-                                          uint32_t RB[4]) {
+                                          TexelsN<PPT> *row, const TexelsN<PPT> *up_row,
+                                          uint32_t *S, uint32_t *RB) {
   constexpr int J0 = C - 2 * R > 0 ? C - 2 * R : 0;
-  constexpr int J1 = C < 3 ? C : 3;
+  constexpr int J1 = C < PPT - 1 ? C : PPT - 1;
   constexpr int N = J1 - J0 + 1;
   const int32_t lin = cells[C];
   const bool up = lin == up_cells[C];
-  const bool left = C >= 4 && lin == cells[C > 0 ? C - 1 : 0];
-  uint32_t t[4] = {0, 0, 0, 0};
+  const bool left = C >= PPT && lin == cells[C > 0 ? C - 1 : 0];
+  uint32_t t[PPT] = {};
   if (!up && !left) load_texels<N>(ex, pbase + 4u * J0 + uint32_t(lin), t);
 #pragma unroll
   for (int m = 0; m < N; ++m) {
@@ -408,37 +407,39 @@ __device__ __forceinline__ void vote_cell(const SB_GLOBAL unsigned char *ex, uin
   }
 }
 
-template <int R, int C>
+template <int R, int PPT, int C>
 __device__ __forceinline__ void vote_row(const SB_GLOBAL unsigned char *ex, uint32_t pbase,
                                          const int32_t *cells, const int32_t *up_cells,
-                                         Texels4 *row, const Texels4 *up_row, uint32_t S[4],
-                                         uint32_t RB[4]) {
-  if constexpr (C < 2 * R + 4) {
-    vote_cell<R, C>(ex, pbase, cells, up_cells, row, up_row, S, RB);
-    vote_row<R, C + 1>(ex, pbase, cells, up_cells, row, up_row, S, RB);
+                                         TexelsN<PPT> *row, const TexelsN<PPT> *up_row,
+                                         uint32_t *S, uint32_t *RB) {
+  if constexpr (C < 2 * R + PPT) {
+    vote_cell<R, PPT, C>(ex, pbase, cells, up_cells, row, up_row, S, RB);
+    vote_row<R, PPT, C + 1>(ex, pbase, cells, up_cells, row, up_row, S, RB);
   }
 }
 
-// One 64 x 16 pixel tile; `lin` is LDS for blend_lw(R) x blend_lh(R) cells.
-// Cell n of the tile holds 4 * (oy * P + ox) for its offset o = NNF[n] - n
-// and the padded exemplar's row length P: a vote of n for pixel p is the
-// texel at p's own padded position plus that many bytes.  Cells outside the
-// target hold the distance to the exemplar's zero rows instead, so their
-// votes read zeros, which count for nothing (alpha 0).  Pixel p's average is
+// One (16 PPT) x TH pixel voting tile with 16 TH threads: thread t votes for
+// PPT horizontally adjacent pixels.  `lin` is LDS for blend_lw x blend_lh
+// cells; cell n holds 4 * (oy * P + ox) for its offset o = NNF[n] - n and the
+// padded exemplar's row length P: a vote of n for pixel p is the texel at
+// p's own padded position plus that many bytes.  Cells outside the target
+// hold the distance to the exemplar's zero rows instead, so their votes read
+// zeros, which count for nothing (alpha 0).  Pixel p's average is
 // (sum + floor(k/2)) / k per channel over its k in-source votes, the vote
 // rule at the end of Sec. 3.2.  Ends with all threads past their last LDS
 // read (callers that reuse `lin` synchronise before refilling it).
-template <int R>
+template <int R, int PPT, int TH>
 __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t tid,
                                   int32_t *lin) {
-  constexpr int32_t LW = blend_lw(R), LH = blend_lh(R), NC = LW * LH;
-  const uint32_t tiles_x = (uint32_t(a.w) + kBlendTW - 1) / kBlendTW;
-  const int32_t X0 = int32_t(t_index % tiles_x) * kBlendTW;
-  const int32_t Y0 = int32_t(t_index / tiles_x) * kBlendTH;
+  constexpr int32_t TW = 16 * PPT, NT = 16 * TH;
+  constexpr int32_t LW = blend_lw(TW, R), LH = blend_lh(TH, R), NC = LW * LH;
+  static_assert(TW <= kBlendMaxTW && TH <= kBlendMaxTH, "tile exceeds the exemplar zero rows");
+  const uint32_t tiles_x = (uint32_t(a.w) + TW - 1) / TW;
+  const int32_t X0 = int32_t(t_index % tiles_x) * TW;
+  const int32_t Y0 = int32_t(t_index / tiles_x) * TH;
   const int32_t P = a.ex_stride;
-  const int32_t zero_rel =
-      int32_t(a.ex_zero) - ((Y0 + kExMargin) * P + (X0 + kExMargin));
-  for (int32_t e = int32_t(tid); e < NC; e += 256) {
+  const int32_t zero_rel = int32_t(a.ex_zero) - ((Y0 + kExMargin) * P + (X0 + kExMargin));
+  for (int32_t e = int32_t(tid); e < NC; e += NT) {
     const int32_t cx = e % LW, cy = e / LW;
     const int32_t tx = X0 - R + cx, ty = Y0 - R + cy;
     int32_t v = zero_rel;
@@ -450,38 +451,41 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
   }
   __syncthreads();
   const int32_t gx = int32_t(tid & 15), ly = int32_t(tid >> 4);
-  const int32_t x = X0 + 4 * gx, y = Y0 + ly;
+  const int32_t x = X0 + PPT * gx, y = Y0 + ly;
   const uint32_t pbase = 4u * uint32_t((y + kExMargin) * P + (x + kExMargin));
   const SB_GLOBAL unsigned char *ex = glb(reinterpret_cast<const unsigned char *>(a.src_rgba));
-  uint32_t S[4] = {0, 0, 0, 0}, RB[4] = {0, 0, 0, 0};
-  constexpr int32_t NC4 = 2 * R + 4, NQ = (NC4 + 3) / 4;  // cells, 16-byte LDS reads per row
+  uint32_t S[PPT] = {}, RB[PPT] = {};
+  // the lane's cells of a window row: 2R + PPT, read as aligned PPT-vectors
+  constexpr int32_t NCL = 2 * R + PPT, NQ = (NCL + PPT - 1) / PPT;
+  typedef int32_t lvec __attribute__((ext_vector_type(PPT)));
   // the previous row's cells and texels; INT32_MIN is no cell value (|lin| < 2^30)
-  int32_t up_cells[4 * NQ];
-  Texels4 up_row[NC4];
+  int32_t up_cells[PPT * NQ];
+  TexelsN<PPT> up_row[NCL];
 #pragma unroll
-  for (int32_t c = 0; c < 4 * NQ; ++c) up_cells[c] = INT32_MIN;
+  for (int32_t c = 0; c < PPT * NQ; ++c) up_cells[c] = INT32_MIN;
 #pragma unroll
-  for (int32_t c = 0; c < NC4; ++c) up_row[c] = Texels4{{0, 0, 0, 0}};
+  for (int32_t c = 0; c < NCL; ++c) up_row[c] = TexelsN<PPT>{};
 #pragma unroll 1
   for (int32_t dy = 0; dy < 2 * R + 1; ++dy) {
-    const i32x4 *q4 = reinterpret_cast<const i32x4 *>(lin + (ly + dy) * LW + 4 * gx);
-    int32_t cells[4 * NQ];
+    const lvec *q = reinterpret_cast<const lvec *>(lin + (ly + dy) * LW + PPT * gx);
+    int32_t cells[PPT * NQ];
 #pragma unroll
-    for (int32_t q = 0; q < NQ; ++q) {
-      const i32x4 v = q4[q];
-      cells[4 * q] = v.x, cells[4 * q + 1] = v.y, cells[4 * q + 2] = v.z, cells[4 * q + 3] = v.w;
+    for (int32_t i = 0; i < NQ; ++i) {
+      const lvec v = q[i];
+#pragma unroll
+      for (int32_t j = 0; j < PPT; ++j) cells[PPT * i + j] = v[j];
     }
-    Texels4 row[NC4];
-    vote_row<R, 0>(ex, pbase, cells, up_cells, row, up_row, S, RB);
+    TexelsN<PPT> row[NCL];
+    vote_row<R, PPT, 0>(ex, pbase, cells, up_cells, row, up_row, S, RB);
 #pragma unroll
-    for (int32_t c = 0; c < 4 * NQ; ++c) up_cells[c] = cells[c];
+    for (int32_t c = 0; c < PPT * NQ; ++c) up_cells[c] = cells[c];
 #pragma unroll
-    for (int32_t c = 0; c < NC4; ++c) up_row[c] = row[c];
+    for (int32_t c = 0; c < NCL; ++c) up_row[c] = row[c];
   }
   if (y >= a.h || x >= a.w) return;
-  uint32_t c[4];
+  uint32_t c[PPT];
 #pragma unroll
-  for (int32_t j = 0; j < 4; ++j) {
+  for (int32_t j = 0; j < PPT; ++j) {
     // S = sum R + 2^8 sum G + 2^16 sum B + 2^24 k and RB = sum R + 2^16 sum B
     // (mod 2^32); every channel sum is < 2^16 and k <= 225
     const uint32_t gk = S[j] - RB[j];
@@ -489,16 +493,23 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
     c[j] = div_small((RB[j] & 0xFFFFu) + hk, k) | (div_small(((gk >> 8) & 0xFFFFu) + hk, k) << 8) |
            (div_small((RB[j] >> 16) + hk, k) << 16);
   }
-  SB_GLOBAL uint8_t *o = glb(a.out_rgb) + 3 * (size_t(y) * size_t(a.w) + size_t(x));
-  if (x + 4 <= a.w && (reinterpret_cast<uintptr_t>(a.out_rgb + 3 * (size_t(y) * size_t(a.w) + size_t(x))) & 3) == 0) {
+  const size_t at = 3 * (size_t(y) * size_t(a.w) + size_t(x));
+  SB_GLOBAL uint8_t *o = glb(a.out_rgb) + at;
+  const uintptr_t oa = reinterpret_cast<uintptr_t>(a.out_rgb) + at;
+  if (PPT == 4 && x + 4 <= a.w && (oa & 3) == 0) {
     u32x3a4 v;
-    v.x = c[0] | (c[1] << 24);
-    v.y = (c[1] >> 8) | (c[2] << 16);
-    v.z = (c[2] >> 16) | (c[3] << 8);
+    v.x = c[0] | (c[1 % PPT] << 24);
+    v.y = (c[1 % PPT] >> 8) | (c[2 % PPT] << 16);
+    v.z = (c[2 % PPT] >> 16) | (c[3 % PPT] << 8);
     *reinterpret_cast<SB_GLOBAL u32x3a4 *>(o) = v;
+  } else if (PPT == 2 && x + 2 <= a.w && (oa & 1) == 0) {
+    SB_GLOBAL uint16_t *o16 = reinterpret_cast<SB_GLOBAL uint16_t *>(o);
+    o16[0] = uint16_t(c[0]);
+    o16[1] = uint16_t((c[0] >> 16) | (c[1 % PPT] << 8));
+    o16[2] = uint16_t(c[1 % PPT] >> 8);
   } else {
 #pragma unroll
-    for (int32_t j = 0; j < 4; ++j) {
+    for (int32_t j = 0; j < PPT; ++j) {
       if (x + j < a.w) {
         o[3 * j] = uint8_t(c[j]);
         o[3 * j + 1] = uint8_t(c[j] >> 8);
@@ -508,33 +519,31 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
   }
 }
 
-__device__ inline void blend_tile_any(const FrameArgs &a, uint32_t t_index, uint32_t tid,
-                                      int32_t *lin) {
-  switch (a.radius) {
-    case 0: blend_tile<0>(a, t_index, tid, lin); break;
-    case 1: blend_tile<1>(a, t_index, tid, lin); break;
-    case 2: blend_tile<2>(a, t_index, tid, lin); break;
-    case 3: blend_tile<3>(a, t_index, tid, lin); break;
-    case 4: blend_tile<4>(a, t_index, tid, lin); break;
-    case 5: blend_tile<5>(a, t_index, tid, lin); break;
-    case 6: blend_tile<6>(a, t_index, tid, lin); break;
-    default: blend_tile<7>(a, t_index, tid, lin); break;
+// Radius dispatch over [RLO, RHI] for the batch kernels.
+template <int PPT, int TH, int RLO, int RHI>
+__device__ inline void blend_tile_r(const FrameArgs &a, uint32_t t_index, uint32_t tid,
+                                    int32_t *lin) {
+  if constexpr (RLO <= RHI) {
+    if (a.radius == RLO) blend_tile<RLO, PPT, TH>(a, t_index, tid, lin);
+    else blend_tile_r<PPT, TH, RLO + 1, RHI>(a, t_index, tid, lin);
   }
 }
 
-template <int R>
-__global__ void __launch_bounds__(256) k_blend(FrameArgs a) {
-  __shared__ __attribute__((aligned(16))) int32_t lin[blend_lw(R) * blend_lh(R)];
-  blend_tile<R>(a, blockIdx.x, threadIdx.x, lin);
+template <int R, int PPT, int TH>
+__global__ void __launch_bounds__(16 * TH) k_blend(FrameArgs a) {
+  __shared__ __attribute__((aligned(16))) int32_t lin[blend_lw(16 * PPT, R) * blend_lh(TH, R)];
+  blend_tile<R, PPT, TH>(a, blockIdx.x, threadIdx.x, lin);
 }
 
 // ------------------------------------------------------------------ batches
 //
-// A batch runs the same three passes over many frames: each kernel is
-// persistent (a fixed grid striding over the concatenated tiles of all
-// frames) and reads the frames' arguments from a descriptor block in device
-// memory, so one captured graph serves any mix of sizes and formats.  A
-// block copies the arguments of the frame it is working on into LDS.
+// A batch runs the same passes over many frames: each kernel is persistent
+// (a fixed grid striding over the concatenated tiles of all frames) and reads
+// the frames' arguments from a descriptor block in device memory, so one
+// captured graph serves any mix of sizes and formats.  A block copies the
+// arguments of the frame it is working on into LDS.  The vote pass runs as
+// two kernels, radius 0..3 and 4..7, each over its own frames' tiles, so the
+// common small radii do not pay the register budget of the large ones.
 
 // Frame owning global tile t: the last f with pre[f] <= t (pre in LDS).
 __device__ inline uint32_t frame_of(const uint32_t *pre, uint32_t n, uint32_t t) {
@@ -547,20 +556,16 @@ __device__ inline uint32_t frame_of(const uint32_t *pre, uint32_t n, uint32_t t)
   return lo;
 }
 
-constexpr int32_t kBatchLds = blend_lw(SB_MAX_RADIUS) * blend_lh(SB_MAX_RADIUS) * 4 >
-                                      4 * 2 * kWaveRecs * 4
-                                  ? blend_lw(SB_MAX_RADIUS) * blend_lh(SB_MAX_RADIUS) * 4
-                                  : 4 * 2 * kWaveRecs * 4;
-
-template <int KIND>
-__global__ void __launch_bounds__(256) k_batch(const unsigned char *desc) {
-  __shared__ __attribute__((aligned(16))) uint32_t work[kBatchLds / 4];
+// Batch pass KIND over the descriptor's frames; BODY(fa, local tile, work).
+template <int KIND, int NT, int WORDS, class Body>
+__device__ __forceinline__ void batch_loop(const unsigned char *desc, Body body) {
+  __shared__ __attribute__((aligned(16))) uint32_t work[WORDS];
   __shared__ uint32_t pre[kMaxBatchFrames + 1];
   __shared__ FrameArgs fa;
   const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(desc);
   const uint32_t n = hd->nframes;
   const uint32_t *gpre = reinterpret_cast<const uint32_t *>(desc + batch_prefix_offset(KIND));
-  for (uint32_t i = threadIdx.x; i <= n; i += 256) pre[i] = gpre[i];
+  for (uint32_t i = threadIdx.x; i <= n; i += NT) pre[i] = gpre[i];
   __syncthreads();
   const uint32_t total = pre[n];
   uint32_t cur = ~0u;
@@ -571,27 +576,66 @@ __global__ void __launch_bounds__(256) k_batch(const unsigned char *desc) {
                                                                size_t(f) * sizeof(FrameArgs));
       uint32_t *dst = reinterpret_cast<uint32_t *>(&fa);
       __syncthreads();  // every thread is done with the previous frame's arguments
-      for (uint32_t i = threadIdx.x; i < sizeof(FrameArgs) / 4; i += 256) dst[i] = src[i];
+      for (uint32_t i = threadIdx.x; i < sizeof(FrameArgs) / 4; i += NT) dst[i] = src[i];
       __syncthreads();
       cur = f;
     }
-    const uint32_t local = t - pre[f];
-    if (KIND == 0) {
-      const uint32_t idx = local * 256 + threadIdx.x;
-      if (fa.fmt == SB_GUIDE_U8X2) seeds_body<SB_GUIDE_U8X2>(fa, idx);
-      else seeds_body<SB_GUIDE_U16X2>(fa, idx);
-    } else if (KIND == 1) {
-      if (fa.fmt == SB_GUIDE_U8X2) assign_tile<SB_GUIDE_U8X2>(fa, local, threadIdx.x, work);
-      else assign_tile<SB_GUIDE_U16X2>(fa, local, threadIdx.x, work);
-      __syncthreads();  // the next tile restages its records
-    } else {
-      blend_tile_any(fa, local, threadIdx.x, reinterpret_cast<int32_t *>(work));
-      __syncthreads();  // the next tile refills the LDS tile
-    }
+    body(fa, t - pre[f], work);
+    __syncthreads();  // the next tile restages its LDS
   }
 }
 
+__global__ void __launch_bounds__(256) k_batch_seeds(const unsigned char *desc) {
+  batch_loop<0, 256, 1>(desc, [](const FrameArgs &fa, uint32_t local, uint32_t *) {
+    const uint32_t idx = local * 256 + threadIdx.x;
+    if (fa.fmt == SB_GUIDE_U8X2) seeds_body<SB_GUIDE_U8X2>(fa, idx);
+    else seeds_body<SB_GUIDE_U16X2>(fa, idx);
+  });
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_batch_assign(const unsigned char *desc) {
+  batch_loop<1, 256, 4 * 2 * kWaveRecs>(desc, [](const FrameArgs &fa, uint32_t local, uint32_t *w) {
+    if (fa.fmt == SB_GUIDE_U8X2) assign_tile<SB_GUIDE_U8X2, G>(fa, local, threadIdx.x, w);
+    else assign_tile<SB_GUIDE_U16X2, G>(fa, local, threadIdx.x, w);
+  });
+}
+
+template <int PPT, int TH, int RLO, int RHI>
+__global__ void __launch_bounds__(16 * TH) k_batch_blend(const unsigned char *desc) {
+  constexpr int WORDS = blend_lw(16 * PPT, RHI) * blend_lh(TH, RHI);
+  batch_loop<RLO == 0 ? 2 : 3, 16 * TH, WORDS>(desc, [](const FrameArgs &fa, uint32_t local,
+                                                        uint32_t *w) {
+    blend_tile_r<PPT, TH, RLO, RHI>(fa, local, threadIdx.x, reinterpret_cast<int32_t *>(w));
+  });
+}
+
 unsigned blocks_for(uint64_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
+
+template <int FMT, int G>
+void launch_assign(const FrameArgs &a, uint32_t blocks, hipStream_t stream) {
+  k_assign<FMT, G><<<blocks, 256, 0, stream>>>(a);
+}
+
+template <int PPT, int TH>
+void launch_blend(const FrameArgs &a, uint32_t blocks, hipStream_t stream) {
+  switch (a.radius) {
+    case 0: k_blend<0, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 1: k_blend<1, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 2: k_blend<2, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 3: k_blend<3, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 4: k_blend<4, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 5: k_blend<5, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 6: k_blend<6, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    default: k_blend<7, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
+  }
+}
+
+template <int PPT, int TH>
+void launch_batch_blend(const unsigned char *desc, uint32_t grid, hipStream_t stream) {
+  k_batch_blend<PPT, TH, 0, 3><<<grid, 16 * TH, 0, stream>>>(desc);
+  k_batch_blend<PPT, TH, 4, SB_MAX_RADIUS><<<grid, 16 * TH, 0, stream>>>(desc);
+}
 
 }  // namespace
 
@@ -602,42 +646,60 @@ hipError_t launch_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint
   return hipGetLastError();
 }
 
-void tile_counts(const FrameArgs &a, uint32_t counts[3]) {
+void tile_counts(const FrameArgs &a, const Tune &t, uint32_t counts[4]) {
+  const uint32_t tw = 16 * uint32_t(t.ppt), th = uint32_t(t.rows);
+  const uint32_t blend = ((uint32_t(a.w) + tw - 1) / tw) * ((uint32_t(a.h) + th - 1) / th);
   counts[0] = (uint32_t(a.lv.poffset[a.lv.count]) + 255) / 256;
   counts[1] = ((uint32_t(a.w) + 15) / 16) * ((uint32_t(a.h) + 15) / 16);
-  counts[2] = ((uint32_t(a.w) + kBlendTW - 1) / kBlendTW) * ((uint32_t(a.h) + kBlendTH - 1) / kBlendTH);
+  counts[2] = a.radius <= 3 ? blend : 0;
+  counts[3] = a.radius <= 3 ? 0 : blend;
 }
 
-hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, hipStream_t stream) {
-  uint32_t c[3];
-  tile_counts(a, c);
-  if (c[0] > 0) {
+hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, const Tune &t, hipEvent_t *ev,
+                          hipStream_t stream) {
+  uint32_t c[4];
+  tile_counts(a, t, c);
+  hipError_t e = hipSuccess;
+  if (ev) e = hipEventRecord(ev[0], stream);
+  if (e == hipSuccess && c[0] > 0) {
     if (fmt == SB_GUIDE_U8X2)
       k_seeds<SB_GUIDE_U8X2><<<c[0], 256, 0, stream>>>(a);
     else
       k_seeds<SB_GUIDE_U16X2><<<c[0], 256, 0, stream>>>(a);
   }
-  if (fmt == SB_GUIDE_U8X2)
-    k_assign<SB_GUIDE_U8X2><<<c[1], 256, 0, stream>>>(a);
-  else
-    k_assign<SB_GUIDE_U16X2><<<c[1], 256, 0, stream>>>(a);
-  switch (a.radius) {
-    case 0: k_blend<0><<<c[2], 256, 0, stream>>>(a); break;
-    case 1: k_blend<1><<<c[2], 256, 0, stream>>>(a); break;
-    case 2: k_blend<2><<<c[2], 256, 0, stream>>>(a); break;
-    case 3: k_blend<3><<<c[2], 256, 0, stream>>>(a); break;
-    case 4: k_blend<4><<<c[2], 256, 0, stream>>>(a); break;
-    case 5: k_blend<5><<<c[2], 256, 0, stream>>>(a); break;
-    case 6: k_blend<6><<<c[2], 256, 0, stream>>>(a); break;
-    default: k_blend<7><<<c[2], 256, 0, stream>>>(a); break;
+  if (ev && e == hipSuccess) e = hipEventRecord(ev[1], stream);
+  if (e == hipSuccess) {
+    const bool u8 = fmt == SB_GUIDE_U8X2;
+    if (t.group == 4) {
+      if (u8) launch_assign<SB_GUIDE_U8X2, 4>(a, c[1], stream);
+      else launch_assign<SB_GUIDE_U16X2, 4>(a, c[1], stream);
+    } else {
+      if (u8) launch_assign<SB_GUIDE_U8X2, 2>(a, c[1], stream);
+      else launch_assign<SB_GUIDE_U16X2, 2>(a, c[1], stream);
+    }
   }
+  if (ev && e == hipSuccess) e = hipEventRecord(ev[2], stream);
+  if (e == hipSuccess) {
+    const uint32_t nb = c[2] + c[3];
+    if (t.ppt == 4 && t.rows == 16) launch_blend<4, 16>(a, nb, stream);
+    else if (t.ppt == 4) launch_blend<4, 8>(a, nb, stream);
+    else if (t.rows == 16) launch_blend<2, 16>(a, nb, stream);
+    else launch_blend<2, 8>(a, nb, stream);
+  }
+  if (ev && e == hipSuccess) e = hipEventRecord(ev[3], stream);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, hipStream_t stream) {
-  k_batch<0><<<grid, 256, 0, stream>>>(desc_dev);
-  k_batch<1><<<grid, 256, 0, stream>>>(desc_dev);
-  k_batch<2><<<grid, 256, 0, stream>>>(desc_dev);
+hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, const Tune &t,
+                        hipStream_t stream) {
+  k_batch_seeds<<<grid, 256, 0, stream>>>(desc_dev);
+  if (t.group == 4) k_batch_assign<4><<<grid, 256, 0, stream>>>(desc_dev);
+  else k_batch_assign<2><<<grid, 256, 0, stream>>>(desc_dev);
+  if (t.ppt == 4 && t.rows == 16) launch_batch_blend<4, 16>(desc_dev, grid, stream);
+  else if (t.ppt == 4) launch_batch_blend<4, 8>(desc_dev, grid, stream);
+  else if (t.rows == 16) launch_batch_blend<2, 16>(desc_dev, grid, stream);
+  else launch_batch_blend<2, 8>(desc_dev, grid, stream);
   return hipGetLastError();
 }
 

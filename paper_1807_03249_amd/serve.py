@@ -11,7 +11,8 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-from . import (SB_OK, SbParams, SbStyle, Style, StyleBlitError, _check, _dev, _torch, lib,
+from . import (SB_OK, SbParams, SbStyle, SbTune, Style, StyleBlitError, _check, _dev, _torch, lib,
+               tune_struct,
                workspace_bytes)
 
 
@@ -20,7 +21,8 @@ class SbServeConfig(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
                 ("desc_dev", ctypes.c_void_p), ("desc_host", ctypes.c_void_p),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes_per_slot", ctypes.c_size_t)]
+                ("workspace", ctypes.c_void_p), ("workspace_bytes_per_slot", ctypes.c_size_t),
+                ("tune", SbTune), ("blocks_per_cu", ctypes.c_int32)]
 
 
 class SbRequest(ctypes.Structure):
@@ -73,10 +75,12 @@ class Request:
 
 
 def run(requests: Sequence[Request], slots: int = 4, max_batch: int = 16,
-        budget_bytes: int = 1 << 30, use_graph: bool = True, plain: bool = False):
+        budget_bytes: int = 1 << 30, use_graph: bool = True, plain: bool = False, tune=None,
+        blocks_per_cu: int = 0):
     """Run the trace in real time.  Returns a dict of numpy arrays (arrival,
     admitted, launched, completed times in seconds, batch ids and sizes,
-    status) plus latency percentiles and throughput."""
+    status) plus latency percentiles and throughput.  ``tune`` and
+    ``blocks_per_cu`` fix the kernel choice (as for a batch plan)."""
     torch = _torch()
     L = _bind()
     n = len(requests)
@@ -98,7 +102,8 @@ def run(requests: Sequence[Request], slots: int = 4, max_batch: int = 16,
     desc_host = torch.empty(db * nslots, dtype=torch.uint8).pin_memory()
     cfg = SbServeConfig(nslots, mb, 1 if use_graph else 0, 1 if plain else 0, arena.data_ptr(),
                         int(budget_bytes), desc_dev.data_ptr(), desc_host.data_ptr(),
-                        ws.data_ptr(), per_slot)
+                        ws.data_ptr(), per_slot, tune_struct(tune) or SbTune(0, 0, 0),
+                        int(blocks_per_cu))
     res = (SbRequestResult * n)()
     torch.cuda.synchronize()
     _check(L.sb_serve_run(ctypes.byref(cfg), reqs, n, res), "sb_serve_run")

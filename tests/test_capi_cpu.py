@@ -107,3 +107,44 @@ def test_validation_rejects_before_launch(L):
     assert L.sb_lut_build(fake, 0, 512, 512, 8, fake, fake, 10, None) == sb.SB_ENOMEM
     assert L.sb_lut_build(None, 0, 512, 512, 8, fake, fake, 1 << 30, None) == sb.SB_EINVAL
     assert L.sb_pack_exemplar(None, 4, 4, fake, None) == sb.SB_EINVAL
+
+
+def test_tune_validation(L):
+    """Unsupported kernel choices are refused on the host (no launch)."""
+    import paper_1807_03249_amd as sb
+
+    fake = 0x1000
+    st = sb.SbStyle(fake, fake, fake, 512, 512, 0, 8)
+    p = sb.params(4, 8, 32, 3)
+    ws = sb.workspace_bytes(64, 64, p)
+
+    def call(tune):
+        return L.sb_stylize_ex(ctypes.byref(st), fake, 64, 64, fake, ctypes.byref(p), fake, fake,
+                               None, fake, ws, ctypes.byref(sb.SbTune(*tune)), None)
+
+    for bad in [(3, 16, 2), (1, 16, 2), (4, 12, 2), (4, 32, 2), (4, 16, 3), (4, 16, 1),
+                (-4, 16, 2)]:
+        assert call(bad) == sb.SB_EINVAL, bad
+    ev = (ctypes.c_void_p * 4)()
+    assert L.sb_stylize_timed(ctypes.byref(st), fake, 64, 64, fake, ctypes.byref(p), fake, fake,
+                              None, fake, ws, None, ev, None) == sb.SB_EINVAL  # null events
+    h = ctypes.c_void_p()
+    assert L.sb_batch_create(fake, fake, 0, ctypes.byref(sb.SbTune(4, 16, 5)), 0, None,
+                             ctypes.byref(h)) == sb.SB_EINVAL
+    assert L.sb_batch_create(fake, fake, 0, None, 17, None, ctypes.byref(h)) == sb.SB_EINVAL
+    assert L.sb_batch_create(fake, fake, 0, None, -1, None, ctypes.byref(h)) == sb.SB_EINVAL
+
+
+def test_exemplar_layout(L):
+    """The padded exemplar holds the source with an 8-texel margin and at
+    least one voting tile of zero rows below it."""
+    for sw, sh in [(512, 512), (1, 1), (17, 3), (8192, 8192)]:
+        n = L.sb_exemplar_texels(sw, sh)
+        P = sw + 16
+        assert n % P == 0
+        rows = n // P
+        assert rows >= sh + 16 + 15
+        # zero rows must cover a 64 x 16 tile laid out with this row length
+        assert (rows - sh - 16) * P >= 15 * P + 64
+    assert L.sb_exemplar_texels(0, 5) == 0
+    assert L.sb_exemplar_texels(5, 8193) == 0

@@ -48,8 +48,7 @@ def single(sb, styles, f):
 
     p = f.params
     rgb, chunk = sb.stylize(styles[f.style], f.guide, f.jitter,
-                            sb.params(p.levels, p.finest, p.threshold, p.radius),
-                            tune=(sb.PATH_TWO_PASS, sb.TILE_AUTO))
+                            sb.params(p.levels, p.finest, p.threshold, p.radius))
     torch.cuda.synchronize()
     return rgb.cpu().numpy(), chunk.cpu().numpy()
 
@@ -62,6 +61,25 @@ def test_batch_equals_single(sb, mix, use_graph):
     b = sb.Batch(use_graph=use_graph)
     idx = list(range(len(frames_np)))
     say(f"batch of {len(idx)} graph={use_graph}")
+    jobs = jobs_for(sb, styles, frames_np, idx)
+    b.run(jobs)
+    torch.cuda.synchronize()
+    for i, j in zip(idx, jobs):
+        rgb, chunk = single(sb, styles, frames_np[i])
+        np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), rgb, err_msg=f"frame {i} rgb")
+        np.testing.assert_array_equal(j.out_chunk.cpu().numpy(), chunk, err_msg=f"frame {i} chunk")
+    b.close()
+
+
+@pytest.mark.parametrize("tune,bpc", [((2, 8, 4), 2), ((4, 8, 2), 1), ((2, 16, 2), 16)])
+def test_batch_tunes_equal_single(sb, mix, tune, bpc):
+    """Every kernel choice and persistent grid size gives the same bits."""
+    import torch
+
+    styles_np, frames_np, styles = mix
+    b = sb.Batch(use_graph=True, tune=tune, blocks_per_cu=bpc)
+    idx = [0, 3, 6, 7, 10]
+    say(f"batch tune={tune} blocks_per_cu={bpc}")
     jobs = jobs_for(sb, styles, frames_np, idx)
     b.run(jobs)
     torch.cuda.synchronize()

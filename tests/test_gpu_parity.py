@@ -57,14 +57,8 @@ def check_frame(sb, st_np, fr_guide, jit, levels, finest, t, r, lut=None, style_
     for tune in tunes:
         say(f"{name} {fr_guide.shape[1]}x{fr_guide.shape[0]} L={levels} f={finest} t={t} r={r} "
             f"tune={tune}")
-        try:
-            g_rgb, g_chunk, g_nnf, st = run_gpu(sb, st_np, st_np.lut_bits, fr_guide, jit, levels,
-                                                finest, t, r, st, tune)
-        except sb.StyleBlitError as e:
-            # a forced fused tile that does not fit in LDS is refused up front
-            assert tune is not None and tune[0] == sb.PATH_FUSED and e.status == sb.SB_EINVAL
-            say(f"  tile refused: {tune}")
-            continue
+        g_rgb, g_chunk, g_nnf, st = run_gpu(sb, st_np, st_np.lut_bits, fr_guide, jit, levels,
+                                            finest, t, r, st, tune)
         msg = f"{name} tune={tune}"
         np.testing.assert_array_equal(g_chunk, e_chunk, err_msg=f"{msg}: chunk map")
         np.testing.assert_array_equal(g_nnf, e_nnf, err_msg=f"{msg}: nnf")
@@ -236,13 +230,3 @@ def test_unaligned_output_rows(sb):
     check_frame(sb, st, g, jit, 3, 8, 48, 2, lut=lut, name="width 253", tunes=all_tunes(sb))
 
 
-def test_fused_rejects_oversized_tile(sb):
-    """A fused tile whose LDS would exceed the limit is refused, not launched."""
-    import torch
-
-    st = sb.Style(workloads.value_noise_rgb(32, 32, 1), workloads.sphere_guide_u8(32), 8)
-    g = np.zeros((64, 64, 2), np.uint8)
-    jit = np.zeros(sb.jitter_len(64, 64, 12, 1), np.uint32)
-    with pytest.raises(sb.StyleBlitError):
-        sb.stylize(st, g, jit, sb.params(12, 1, 10, 7), tune=(sb.PATH_FUSED, sb.TILE_64x32))
-    torch.cuda.synchronize()
