@@ -1,22 +1,27 @@
 """Benchmark of the StyleBlit hot path on one MI355X.
 
-A step is one frame through the whole per-frame path (seed staging, the
+A step is one frame through the whole per-frame path (seed records, the
 per-pixel level loop of Algorithm 2 and the voting blend), with the style
-(exemplar, guide and lookup table) already resident, as it is across frames
-in use.  The style's lookup-table build runs once before timing and is
+(padded exemplar, guide and lookup table) already resident, as it is across
+frames in use.  The style's lookup-table build runs once before timing and is
 reported separately.
 
 Default workload: the 1920x1080 normal-guided frame (512x512 sphere
 exemplar, 4 levels of spacing 64..8, threshold 32, radius 3).  Inputs and
 outputs rotate over enough buffer sets (> 512 MB) that each step reads its
-guide from HBM rather than from the 256 MB Infinity Cache.
+guide from HBM rather than from the 256 MB Infinity Cache.  The kernel
+choice is the autotuner's pick for this frame shape (every choice computes
+the same bits).
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one
-GPU.
+The roofline object is for the dominant kernel, the voting pass, timed per
+launch with HIP events recorded between the passes on the launch stream.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this measures one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,14 +31,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# counter summary of the voting kernel at 1080p (FETCH_SIZE / WRITE_SIZE per
+# dispatch and the copy-kernel calibration), valid for the kernel source it
+# names
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_1080p_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1807_03249_amd", "csrc", "stylize.hip")
 
 
-def algorithmic_bytes(w, h, fmt, sw, sh, nseeds):
-    """Bytes the method must move per frame: target guide read, RGB and chunk
-    map written, the exemplar (RGB + guide) read once, and one lookup-table
-    entry per seed."""
+def path_algorithmic_bytes(w, h, fmt, sw, sh, nseeds, nfallback):
+    """Bytes the whole method must move per frame: target guide read, RGB and
+    chunk map written, the exemplar (RGB + guide) read once, and one
+    lookup-table entry per seed and per fallback pixel."""
     gb = 2 if fmt == 0 else 4
-    return w * h * (gb + 3 + 4) + sw * sh * (3 + gb) + 4 * nseeds
+    return w * h * (gb + 3 + 4) + sw * sh * (3 + gb) + 4 * (nseeds + nfallback)
+
+
+def vote_algorithmic_bytes(w, h, sw, sh):
+    """Bytes the voting step must move per frame: the RGB output written and
+    the exemplar RGB read once (its input offsets are an intermediate of the
+    two-pass design, not of the method)."""
+    return w * h * 3 + sw * sh * 3
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_per_launch(workload_name):
+    """HBM bytes per voting launch from the committed counter summary, or
+    None when it is missing, for another workload, or for older kernel
+    source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_sha() or t.get("workload") != workload_name:
+        return None
+    fetch = t["fetch_kib_per_dispatch"] * 1024.0 / t["copy_fetch_factor"]
+    write = t["write_kib_per_dispatch"] * 1024.0 / t["copy_write_factor"]
+    return fetch + write
 
 
 def main():
@@ -42,13 +80,21 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rotate-mb", type=float, default=600.0)
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the frame's kernel choice (default: the library default, "
+                         "whose voting kernel the committed counter summary covers)")
+    ap.add_argument("--no-tune", action="store_true", help="batch leg: library default choice")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame batch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-qps", type=float, default=2000.0)
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-qps", type=str, default="2000,12000,18000",
+                    help="comma-separated request rates of the serving sweep")
+    ap.add_argument("--calibrate-copy-mb", type=float, default=0.0,
+                    help="after timing, run one plain device copy of this many MB "
+                         "(the counter calibration kernel for rocprofv3 --pmc runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -60,6 +106,7 @@ def main():
     import torch
 
     import paper_1807_03249_amd as sb
+    import paper_1807_03249_amd.autotune as at
     import workloads
 
     torch.cuda.set_device(0)
@@ -68,8 +115,11 @@ def main():
     p = fr.params
     prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
     w, h = fr.w, fr.h
+    wname = workloads.CONFIG_NAMES[args.workload]
 
-    # style registration (lookup table on the device), timed once
+    # style registration (upload, padded exemplar, lookup table on the device),
+    # timed on its second run (the first also loads the code objects)
+    style = sb.Style(st_np.rgb, st_np.guide, st_np.lut_bits)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     style = sb.Style(st_np.rgb, st_np.guide, st_np.lut_bits)
@@ -90,9 +140,14 @@ def main():
                      torch.empty(wsb, dtype=torch.uint8, device="cuda")))
     torch.cuda.synchronize()
 
-    def step(k):
+    tune = None
+    if args.tune:
+        tune = at.tune_frame(style, guide0, jit, prm)["tune"]
+
+    def step(k, events=None):
         g, o_rgb, o_chunk, ws = sets[k % nsets]
-        sb.stylize(style, g, jit, prm, out_rgb=o_rgb, out_chunk=o_chunk, workspace=ws)
+        sb.stylize(style, g, jit, prm, out_rgb=o_rgb, out_chunk=o_chunk, workspace=ws, tune=tune,
+                   events=events)
 
     for k in range(args.warmup):
         step(k)
@@ -107,20 +162,25 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     mpx_s = w * h * args.steps / elapsed / 1e6
 
-    # per-launch duration with HIP events on the launch stream
-    stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+    # per-pass durations: HIP events recorded by the library between the
+    # passes, on the launch stream
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     for k in range(args.steps):
-        evs[k][0].record(stream)
-        step(k)
-        evs[k][1].record(stream)
+        step(k, evs[k])
     torch.cuda.synchronize()
-    durs = sorted(a.elapsed_time(b) for a, b in evs)
-    kern_ms = sum(durs) / len(durs)
+    passes = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
+                       for e in evs])
+    frame_ms = np.sort(passes.sum(axis=1))
+    seeds_ms, assign_ms, vote_ms = passes.mean(axis=0)
+
+    # outputs of the last step: fallback pixels for the byte count
+    chunk = sets[(args.steps - 1) % nsets][2].cpu().numpy().view(np.uint32)
+    nfallback = int(((chunk >> 26) == p.levels).sum())
     nseeds = sb.jitter_len(w, h, p.levels, p.finest)
-    abytes = algorithmic_bytes(w, h, st_np.fmt, st_np.sw, st_np.sh, nseeds)
-    achieved = abytes / (kern_ms * 1e-3) / 1e9
+    pbytes = path_algorithmic_bytes(w, h, st_np.fmt, st_np.sw, st_np.sh, nseeds, nfallback)
+    vbytes = vote_algorithmic_bytes(w, h, st_np.sw, st_np.sh)
+    vote_gbs = vbytes / (vote_ms * 1e-3) / 1e9
+    traffic = traffic_per_launch(wname)
 
     cpu = None
     if not args.no_cpu:
@@ -139,14 +199,25 @@ def main():
         csec = time.perf_counter() - c0
         cpu = {"value": round(w * h * n / csec / 1e6, 3), "unit": "Mpixel/s", "cores": nthreads,
                "kind": "oracle",
-               "sample": f"{n} full {w}x{h} frames (lookup table built once, not timed)"}
+               "sample": f"{n} full {w}x{h} frames of this workload (lookup table built once, "
+                         f"not timed), OpenMP over rows"}
 
-    batch = None if args.no_batch else batch_leg(sb, torch, workloads)
-    serve = None if args.no_serve else serve_leg(sb, torch, np, workloads, args.serve_requests,
-                                                 args.serve_qps)
+    batch = None if args.no_batch else batch_leg(sb, at, torch, workloads, args.no_tune)
+    serve = None
+    if not args.no_serve:
+        serve = [serve_leg(sb, torch, np, workloads, args.serve_requests, float(q))
+                 for q in args.serve_qps.split(",")]
+
+    if args.calibrate_copy_mb > 0:
+        nb = int(args.calibrate_copy_mb * 1e6) // 4 * 4
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.add(src, 0, out=dst)  # one elementwise kernel: reads and writes nb bytes
+        torch.cuda.synchronize()
 
     line = {
-        "metric": "stylized Mpixel/s at 1080p (HBM GB/s and frame latency alongside)",
+        "metric": "stylized Mpixel/s at 1080p (HBM GB/s and p50/p99 frame latency alongside)",
         "value": round(mpx_s, 3),
         "unit": "Mpixel/s",
         "n_gpus": 1,
@@ -158,16 +229,23 @@ def main():
         "vs_baseline": None,
         "dtype": "u8" if st_np.fmt == 0 else "u16",
         "data": "synthetic",
-        "config": {"workload": workloads.CONFIG_NAMES[args.workload], "width": w, "height": h,
+        "config": {"workload": wname, "width": w, "height": h,
                    "source": f"{st_np.sw}x{st_np.sh}", "levels": p.levels, "finest": p.finest,
-                   "threshold": p.threshold, "radius": p.radius, "buffer_sets": nsets},
-        "frame_latency_ms": {"p50": round(durs[len(durs) // 2], 6),
-                             "p99": round(durs[min(len(durs) - 1, int(0.99 * len(durs)))], 6)},
-        "hbm_gbs_algorithmic": round(achieved, 2),
-        "lut_build_ms": round(lut_ms, 3),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel_ms": round(kern_ms, 6), "algorithmic_bytes": abytes},
+                   "threshold": p.threshold, "radius": p.radius, "buffer_sets": nsets,
+                   "tune": list(tune) if tune else "default"},
+        "frame_latency_ms": {"p50": round(float(frame_ms[len(frame_ms) // 2]), 6),
+                             "p99": round(float(frame_ms[min(len(frame_ms) - 1,
+                                                             int(0.99 * len(frame_ms)))]), 6)},
+        "pass_ms": {"seeds": round(float(seeds_ms), 6), "assign": round(float(assign_ms), 6),
+                    "vote": round(float(vote_ms), 6)},
+        "hbm_gbs_algorithmic": round(pbytes / (ms_per_step * 1e-3) / 1e9, 2),
+        "algorithmic_bytes_per_frame": pbytes,
+        "style_registration_ms": round(lut_ms, 3),
+        "roofline": {"bound": "hbm", "kernel": "k_blend (voting pass)",
+                     "achieved": round(vote_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(vote_gbs / HBM_PEAK_GBS, 5),
+                     "traffic": round(traffic) if traffic is not None else None,
+                     "kernel_ms": round(float(vote_ms), 6), "algorithmic_bytes": vbytes},
         "cpu_baseline": cpu,
         "batch": batch,
         "serve": serve,
@@ -175,9 +253,10 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def batch_leg(sb, torch, workloads, reps=5):
+def batch_leg(sb, at, torch, workloads, no_tune, reps=5):
     """64 frames of uneven size, half normal- and half UV-guided, 4 resident
-    styles: one graph launch per batch vs one plain launch per frame."""
+    styles: one autotuned graph launch per batch vs one plain launch per
+    frame (library default choice)."""
     styles_np, frames_np = workloads.config(4)
     styles = [sb.Style(s.rgb, s.guide, s.lut_bits) for s in styles_np]
     jobs = []
@@ -186,8 +265,14 @@ def batch_leg(sb, torch, workloads, reps=5):
         jobs.append(sb.FrameJob(styles[f.style], f.guide, f.jitter,
                                 sb.params(p.levels, p.finest, p.threshold, p.radius)))
     px = sum(j.w * j.h for j in jobs)
-    b = sb.Batch(use_graph=True)
-    ws = torch.empty(b.workspace_bytes(jobs), dtype=torch.uint8, device="cuda")
+    probe = sb.Batch(use_graph=True)
+    ws = torch.empty(probe.workspace_bytes(jobs), dtype=torch.uint8, device="cuda")
+    probe.close()
+    if no_tune:
+        pick = {"tune": None, "blocks_per_cu": 0, "cached": False}
+    else:
+        pick = at.tune_batch(jobs, workspace=ws)
+    b = sb.Batch(use_graph=True, tune=pick["tune"], blocks_per_cu=pick["blocks_per_cu"])
     plain_ws = torch.empty(max(sb.workspace_bytes(j.w, j.h, j.params) for j in jobs),
                            dtype=torch.uint8, device="cuda")
 
@@ -213,6 +298,8 @@ def batch_leg(sb, torch, workloads, reps=5):
     out["frames"] = len(jobs)
     out["mpixel"] = round(px / 1e6, 3)
     out["speedup"] = round(out["plain"]["ms_per_batch"] / out["graph"]["ms_per_batch"], 3)
+    out["tune"] = list(pick["tune"]) if pick["tune"] else "default"
+    out["blocks_per_cu"] = pick["blocks_per_cu"] or 8
     return out
 
 
@@ -251,6 +338,7 @@ def serve_leg(sb, torch, np, workloads, nreq, qps):
         is1080 = np.array([r.w == 1920 for r in reqs])
         k = int(nreq * 0.05)
         lat = out["latency"][k:][is1080[k:]] * 1e3
+        summ["p50_ms_1080p"] = float(np.percentile(lat, 50)) if lat.size else None
         summ["p99_ms_1080p"] = float(np.percentile(lat, 99)) if lat.size else None
         res[name] = {k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in summ.items()}
     return res
