@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame batch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=10000)
-    ap.add_argument("--serve-qps", type=str, default="2000,12000,18000",
+    ap.add_argument("--serve-qps", type=str, default="2000,12000,18000,24000",
                     help="comma-separated request rates of the serving sweep")
     ap.add_argument("--calibrate-copy-mb", type=float, default=0.0,
                     help="after timing, run one plain device copy of this many MB "
@@ -162,14 +162,15 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     mpx_s = w * h * args.steps / elapsed / 1e6
 
-    # per-pass durations: HIP events recorded by the library between the
-    # passes, on the launch stream
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    # per-pass durations: fence-free HIP timing events recorded by the
+    # library between the passes, on the launch stream
+    evs = [sb.TimingEvents() for _ in range(args.steps)]
     for k in range(args.steps):
         step(k, evs[k])
     torch.cuda.synchronize()
-    passes = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
-                       for e in evs])
+    passes = np.array([e.pass_ms() for e in evs])
+    for e in evs:
+        e.close()
     frame_ms = np.sort(passes.sum(axis=1))
     seeds_ms, assign_ms, vote_ms = passes.mean(axis=0)
 

@@ -163,14 +163,24 @@ int sb_stylize_ex(const sb_style *style, const void *tgt_guide, int32_t w, int32
                   uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
                   size_t workspace_bytes, const sb_tune *tune, hipStream_t stream);
 
-/* sb_stylize_ex that also records events[0..3] (created by the caller, with
- * timing) on `stream` before the seed-record pass, before the level-loop
- * pass, before the voting pass and after it, for per-pass timing. */
+/* sb_stylize_ex that also records events[0..3] (timing events, e.g. from
+ * sb_timing_events_create) on `stream` before the seed-record pass, before
+ * the level-loop pass, before the voting pass and after it, for per-pass
+ * timing. */
 int sb_stylize_timed(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
                      const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
                      uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
                      size_t workspace_bytes, const sb_tune *tune, hipEvent_t events[4],
                      hipStream_t stream);
+
+/* Four timing events for sb_stylize_timed, created without the system-scope
+ * fence (hipEventDisableSystemFence), so recording them
+ * between passes adds no cache write-back or invalidation to the timed work.
+ * The caller owns them and frees them with sb_timing_events_destroy. */
+int sb_timing_events_create(hipEvent_t events[4]);
+int sb_timing_events_destroy(hipEvent_t events[4]);
+/* Milliseconds between two completed events (hipEventElapsedTime). */
+int sb_event_elapsed_ms(hipEvent_t start, hipEvent_t stop, float *ms);
 
 /* ---------------------------------------------------------------- batches */
 
@@ -265,7 +275,9 @@ typedef struct {
 /* Run a request trace in real time on the calling thread: arrivals at their
  * times, admission in arrival order while the outputs fit in the arena,
  * continuous batching over `slots` streams (a free slot takes every admitted
- * request up to max_batch), completion by event polling.  Every result is
+ * request up to max_batch and runs them as one batch-plan replay, or, for a
+ * single request, as one sb_stylize_ex on the slot's stream), completion by
+ * event polling.  Every result is
  * the one sb_stylize gives for that request alone.  Returns after the last
  * request finished and the slots' streams drained. */
 int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,

@@ -100,6 +100,9 @@ def lib():
     L.sb_stylize_timed.argtypes = [ctypes.POINTER(SbStyle), vp, i32, i32, vp,
                                    ctypes.POINTER(SbParams), vp, vp, vp, vp, sz,
                                    ctypes.POINTER(SbTune), ctypes.POINTER(vp), vp]
+    L.sb_timing_events_create.argtypes = [ctypes.POINTER(vp)]
+    L.sb_timing_events_destroy.argtypes = [ctypes.POINTER(vp)]
+    L.sb_event_elapsed_ms.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float)]
     L.sb_batch_max_frames.restype = ctypes.c_int32
     L.sb_batch_desc_bytes.restype = sz
     L.sb_batch_workspace_bytes.restype = sz
@@ -221,8 +224,8 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     ``(rgb (H,W,3) uint8, chunk (H,W) int32-bits[, nnf])`` as device tensors;
     the work is enqueued on the current stream.  ``tune`` is a
     (blend_ppt, blend_rows, level_group) choice (None = defaults); with
-    ``events`` (four timing ``torch.cuda.Event``) the passes are bracketed by
-    them (sb_stylize_timed)."""
+    ``events`` (a TimingEvents) the passes are bracketed by its events
+    (sb_stylize_timed)."""
     torch = _torch()
     g = tgt_guide
     if not isinstance(g, torch.Tensor) and str(getattr(g, "dtype", "")) == "uint16":
@@ -260,10 +263,9 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     tp = ctypes.byref(tn) if tn is not None else None
     nnf_p = nnf.data_ptr() if nnf is not None else None
     if events is not None:
-        evs = (ctypes.c_void_p * 4)(*[e.cuda_event for e in _recorded(torch, events, s)])
         _check(lib().sb_stylize_timed(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
                                       ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
-                                      nnf_p, workspace.data_ptr(), wsb, tp, evs, s),
+                                      nnf_p, workspace.data_ptr(), wsb, tp, events.handles, s),
                "sb_stylize_timed")
     elif tn is None:
         _check(lib().sb_stylize(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
@@ -278,16 +280,34 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     return out_rgb, out_chunk
 
 
-def _recorded(torch, events, stream):
-    """torch.cuda.Events whose HIP events exist (torch creates them lazily at
-    the first record): record each once on the stream, then hand them over."""
-    if len(events) != 4:
-        raise ValueError("sb_stylize_timed takes four events")
-    st = torch.cuda.ExternalStream(stream) if isinstance(stream, int) else torch.cuda.current_stream()
-    for e in events:
-        if e.cuda_event == 0:
-            e.record(st)
-    return events
+class TimingEvents:
+    """Four fence-free timing events (sb_timing_events_create) for one
+    stylize(..., events=...) call; ``pass_ms()`` after the work completed
+    gives the seed, level-loop and voting pass durations in milliseconds."""
+
+    def __init__(self):
+        self.handles = (ctypes.c_void_p * 4)()
+        _check(lib().sb_timing_events_create(self.handles), "sb_timing_events_create")
+
+    def elapsed_ms(self, i: int, j: int) -> float:
+        ms = ctypes.c_float()
+        _check(lib().sb_event_elapsed_ms(self.handles[i], self.handles[j], ctypes.byref(ms)),
+               "sb_event_elapsed_ms")
+        return float(ms.value)
+
+    def pass_ms(self):
+        return [self.elapsed_ms(0, 1), self.elapsed_ms(1, 2), self.elapsed_ms(2, 3)]
+
+    def close(self):
+        if self.handles is not None:
+            _check(lib().sb_timing_events_destroy(self.handles), "sb_timing_events_destroy")
+            self.handles = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class FrameJob:

@@ -234,6 +234,48 @@ int sb_stylize_timed(const sb_style *style, const void *tgt_guide, int32_t w, in
                       workspace, workspace_bytes, tune, events, stream);
 }
 
+int sb_timing_events_create(hipEvent_t events[4]) {
+  if (!events) return SB_EINVAL;
+  for (int i = 0; i < 4; ++i) events[i] = nullptr;
+  for (int i = 0; i < 4; ++i) {
+    const hipError_t e =
+        hipEventCreateWithFlags(&events[i], hipEventDisableSystemFence);
+    if (e != hipSuccess) {
+      set_hip_error(e, "sb_timing_events_create");
+      for (int k = 0; k < i; ++k) hipEventDestroy(events[k]);
+      for (int k = 0; k < 4; ++k) events[k] = nullptr;
+      return SB_EHIP;
+    }
+  }
+  return SB_OK;
+}
+
+int sb_timing_events_destroy(hipEvent_t events[4]) {
+  if (!events) return SB_EINVAL;
+  hipError_t first = hipSuccess;
+  for (int i = 0; i < 4; ++i) {
+    if (!events[i]) continue;
+    const hipError_t e = hipEventDestroy(events[i]);
+    if (first == hipSuccess) first = e;
+    events[i] = nullptr;
+  }
+  if (first != hipSuccess) {
+    set_hip_error(first, "sb_timing_events_destroy");
+    return SB_EHIP;
+  }
+  return SB_OK;
+}
+
+int sb_event_elapsed_ms(hipEvent_t start, hipEvent_t stop, float *ms) {
+  if (!start || !stop || !ms) return SB_EINVAL;
+  const hipError_t e = hipEventElapsedTime(ms, start, stop);
+  if (e != hipSuccess) {
+    set_hip_error(e, "sb_event_elapsed_ms");
+    return SB_EHIP;
+  }
+  return SB_OK;
+}
+
 int sb_stylize(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
                const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
                uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,

@@ -9,7 +9,8 @@
 //   3. retires finished batches (event query), freeing their arena bytes and
 //      their slot;
 //   4. gives every free slot (its own stream, batch plan and workspace) all
-//      admitted requests up to max_batch, launched as one graph replay.
+//      admitted requests up to max_batch, launched as one graph replay (a
+//      single request takes the per-frame kernels on the slot's stream).
 // Requests that arrive while batches run are admitted as memory frees up and
 // start on the next free slot, so their work overlaps batches already on the
 // device.  The plain mode launches every request alone on one stream, in
@@ -253,8 +254,16 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
           bf.push_back(fr[size_t(admitted.front())]);
           admitted.pop_front();
         }
-        const int r = sb_batch_run(S.plan, bf.data(), int32_t(bf.size()), S.workspace,
-                                   cfg->workspace_bytes_per_slot, S.stream);
+        // a batch of one goes straight to the per-frame kernels (sized to the
+        // frame, no descriptor upload); larger batches replay the plan
+        const sb_frame &f0 = bf[0];
+        const int r = bf.size() == 1
+                          ? sb_stylize_ex(f0.style, f0.tgt_guide, f0.w, f0.h, f0.jitter,
+                                          &f0.params, f0.out_rgb, f0.out_chunk, nullptr,
+                                          S.workspace, cfg->workspace_bytes_per_slot, &cfg->tune,
+                                          S.stream)
+                          : sb_batch_run(S.plan, bf.data(), int32_t(bf.size()), S.workspace,
+                                         cfg->workspace_bytes_per_slot, S.stream);
         if (r != SB_OK) {
           rc = r;
           break;
