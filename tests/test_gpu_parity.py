@@ -221,7 +221,8 @@ def test_rejects_format_mismatch(sb):
 
 
 def test_unaligned_output_rows(sb):
-    """Odd widths take the byte-store path of the fused kernel."""
+    """Odd widths: rows start unaligned, so the vote takes its byte and
+    16-bit store paths and its partial pixel groups."""
     styles, frames = workloads.config(1)
     st, fr = styles[0], frames[0]
     lut = oracle.lut_build(st.guide, 8)
