@@ -145,15 +145,18 @@ int sb_stylize(const sb_style *style, const void *tgt_guide, int32_t w, int32_t 
  * library's default.
  *   blend_ppt    pixels per thread of the voting pass, adjacent in a row: 2 or
  *                4 (default 4); each vote gather loads that many texels
- *   blend_rows   rows of the voting tile: 8 or 16 (default 16); the tile is
+ *   blend_rows   rows of the voting tile: 8 or 16 (default 8); the tile is
  *                (16 * blend_ppt) x blend_rows pixels, one thread per
  *                blend_ppt pixels
  *   level_group  levels of Algorithm 2 whose source-guide gathers are in
- *                flight together before their tests: 2 or 4 (default 2) */
+ *                flight together before their tests: 2 or 4 (default 2)
+ *   level_ppt    pixels per thread of the level loop (horizontally adjacent
+ *                8x8 blocks per wave): 1 or 2 (default 2) */
 typedef struct {
     int32_t blend_ppt;
     int32_t blend_rows;
     int32_t level_group;
+    int32_t level_ppt;
 } sb_tune;
 
 /* sb_stylize with an explicit kernel choice (tune may be NULL = defaults);

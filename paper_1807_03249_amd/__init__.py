@@ -37,21 +37,24 @@ class SbStyle(ctypes.Structure):
 
 class SbTune(ctypes.Structure):
     _fields_ = [("blend_ppt", ctypes.c_int32), ("blend_rows", ctypes.c_int32),
-                ("level_group", ctypes.c_int32)]
+                ("level_group", ctypes.c_int32), ("level_ppt", ctypes.c_int32)]
 
 
-# every kernel choice (blend_ppt, blend_rows, level_group); all compute the
-# same bits, (0, 0, 0) is the library default
-TUNES = [(ppt, rows, grp) for ppt in (4, 2) for rows in (16, 8) for grp in (2, 4)]
+# every kernel choice (blend_ppt, blend_rows, level_group, level_ppt); all
+# compute the same bits, (0, 0, 0, 0) is the library default
+TUNES = [(ppt, rows, grp, lpx) for ppt in (4, 2) for rows in (16, 8) for grp in (2, 4)
+         for lpx in (1, 2)]
 
 
 def tune_struct(tune) -> Optional[SbTune]:
-    """SbTune from a (blend_ppt, blend_rows, level_group) tuple (None stays None)."""
+    """SbTune from a (blend_ppt, blend_rows, level_group, level_ppt) tuple
+    (None stays None; a shorter tuple leaves the rest at their defaults)."""
     if tune is None:
         return None
     if isinstance(tune, SbTune):
         return tune
-    return SbTune(*(int(v) for v in tune))
+    vals = [int(v) for v in tune] + [0] * (4 - len(tune))
+    return SbTune(*vals)
 
 
 class SbParams(ctypes.Structure):
@@ -223,7 +226,7 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     int32 bits) may be numpy arrays or device tensors.  Returns
     ``(rgb (H,W,3) uint8, chunk (H,W) int32-bits[, nnf])`` as device tensors;
     the work is enqueued on the current stream.  ``tune`` is a
-    (blend_ppt, blend_rows, level_group) choice (None = defaults); with
+    (blend_ppt, blend_rows, level_group, level_ppt) choice (None = defaults); with
     ``events`` (a TimingEvents) the passes are bracketed by its events
     (sb_stylize_timed)."""
     torch = _torch()

@@ -99,8 +99,9 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
 
 bool resolve_tune(const sb_tune *in, Tune *out) {
   out->ppt = 4;
-  out->rows = 16;
+  out->rows = 8;
   out->group = 2;
+  out->apx = 2;
   if (!in) return true;
   if (in->blend_ppt != 0) {
     if (in->blend_ppt != 2 && in->blend_ppt != 4) return false;
@@ -113,6 +114,10 @@ bool resolve_tune(const sb_tune *in, Tune *out) {
   if (in->level_group != 0) {
     if (in->level_group != 2 && in->level_group != 4) return false;
     out->group = in->level_group;
+  }
+  if (in->level_ppt != 0) {
+    if (in->level_ppt != 1 && in->level_ppt != 2) return false;
+    out->apx = in->level_ppt;
   }
   return true;
 }

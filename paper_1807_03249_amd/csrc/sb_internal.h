@@ -34,9 +34,10 @@ struct Levels {
 constexpr int32_t kBlendMaxTW = 64, kBlendMaxTH = 16;
 
 // A resolved kernel choice (see sb_tune): pixels per thread and tile rows of
-// the vote pass, levels per gather round of the level loop.
+// the vote pass, levels per gather round and pixels per thread of the level
+// loop.
 struct Tune {
-  int32_t ppt, rows, group;
+  int32_t ppt, rows, group, apx;
 };
 // Fill a Tune from the caller's sb_tune (NULL or 0 fields = defaults); false
 // if a field holds an unsupported value.

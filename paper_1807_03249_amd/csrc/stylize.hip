@@ -149,119 +149,166 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int32_t kRecStride = 12;
 constexpr int32_t kWaveRecs = SB_MAX_LEVELS * kRecStride;
 
-// N levels i0 .. i0+N-1 of the block level loop for one pixel: NearestSeed
-// over each level's nine staged records, then all N source-guide gathers in
-// flight together, then the tests in level order.  Straight-line code
+// N levels i0 .. i0+N-1 of the block level loop for the lane's B pixels
+// (pixel b in block b, whose records start at lpos + b * kWaveRecs): NearestSeed
+// over each level's nine staged records, then all N * B source-guide gathers
+// in flight together, then the tests in level order.  Straight-line code
 // (levels past L rescan level L-1 and are never taken), so the gathers issue
 // back to back.
-template <int FMT, int N>
+template <int FMT, int N, int B>
 __device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *lpos,
-                                            const uint32_t *loff, int32_t i0, int32_t x, int32_t y,
-                                            short2_t p4, uint32_t gt, uint32_t &chunk,
-                                            uint32_t &off, bool &done) {
+                                            const uint32_t *loff, int32_t i0, const int32_t *x,
+                                            int32_t y, const short2_t *p4, const uint32_t *gt,
+                                            uint32_t *chunk, uint32_t *off, bool *done) {
   const int32_t L = a.lv.count;
   const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
-  uint32_t g[N], wq[N], wo[N];
-  bool ok[N];
+  uint32_t g[B][N], wq[B][N], wo[B][N];
+  bool ok[B][N];
 #pragma unroll
-  for (int32_t u = 0; u < N; ++u) {
-    const int32_t li = min(i0 + u, L - 1);
-    const uint32_t *P = lpos + kRecStride * li;
-    const i32x4 q03 = *reinterpret_cast<const i32x4 *>(P);
-    const i32x4 q47 = *reinterpret_cast<const i32x4 *>(P + 4);
-    int32_t key = seed_key(uint32_t(q03.x), p4, 0);
-    key = min(key, seed_key(uint32_t(q03.y), p4, 1));
-    key = min(key, seed_key(uint32_t(q03.z), p4, 2));
-    key = min(key, seed_key(uint32_t(q03.w), p4, 3));
-    key = min(key, seed_key(uint32_t(q47.x), p4, 4));
-    key = min(key, seed_key(uint32_t(q47.y), p4, 5));
-    key = min(key, seed_key(uint32_t(q47.z), p4, 6));
-    key = min(key, seed_key(uint32_t(q47.w), p4, 7));
-    key = min(key, seed_key(P[8], p4, 8));
-    const int32_t w = kRecStride * li + (key & 15);
-    wq[u] = lpos[w];
-    wo[u] = loff[w];
-    const int32_t vx = x + off_x(wo[u]), vy = y + off_y(wo[u]);
-    // non-short-circuit: keeps the group one straight-line block
-    ok[u] = (i0 + u < L) & (key != INT32_MAX) & (uint32_t(vx) < sw) & (uint32_t(vy) < sh);
-    g[u] = ok[u] ? uint32_t(vy) * sw + uint32_t(vx) : 0u;
+  for (int32_t b = 0; b < B; ++b) {
+#pragma unroll
+    for (int32_t u = 0; u < N; ++u) {
+      const int32_t li = min(i0 + u, L - 1);
+      const uint32_t *P = lpos + b * kWaveRecs + kRecStride * li;
+      const uint32_t *O = loff + b * kWaveRecs + kRecStride * li;
+      const i32x4 q03 = *reinterpret_cast<const i32x4 *>(P);
+      const i32x4 q47 = *reinterpret_cast<const i32x4 *>(P + 4);
+      int32_t key = seed_key(uint32_t(q03.x), p4[b], 0);
+      key = min(key, seed_key(uint32_t(q03.y), p4[b], 1));
+      key = min(key, seed_key(uint32_t(q03.z), p4[b], 2));
+      key = min(key, seed_key(uint32_t(q03.w), p4[b], 3));
+      key = min(key, seed_key(uint32_t(q47.x), p4[b], 4));
+      key = min(key, seed_key(uint32_t(q47.y), p4[b], 5));
+      key = min(key, seed_key(uint32_t(q47.z), p4[b], 6));
+      key = min(key, seed_key(uint32_t(q47.w), p4[b], 7));
+      key = min(key, seed_key(P[8], p4[b], 8));
+      wq[b][u] = P[key & 15];
+      wo[b][u] = O[key & 15];
+      const int32_t vx = x[b] + off_x(wo[b][u]), vy = y + off_y(wo[b][u]);
+      // non-short-circuit: keeps the group one straight-line block
+      ok[b][u] = (i0 + u < L) & (key != INT32_MAX) & (uint32_t(vx) < sw) & (uint32_t(vy) < sh);
+      g[b][u] = ok[b][u] ? uint32_t(vy) * sw + uint32_t(vx) : 0u;
+    }
   }
 #pragma unroll
-  for (int32_t u = 0; u < N; ++u) g[u] = guide_raw<FMT>(a.src_guide, g[u]);
+  for (int32_t b = 0; b < B; ++b) {
 #pragma unroll
-  for (int32_t u = 0; u < N; ++u) {
-    const bool below = error_below<FMT>(gt, guide_unpack<FMT>(g[u]), a.threshold);
-    const bool take = (!done) & ok[u] & below;
-    chunk = take ? chunk_code(i0 + u, wq[u]) : chunk;
-    off = take ? wo[u] : off;
-    done = done || take;
+    for (int32_t u = 0; u < N; ++u) g[b][u] = guide_raw<FMT>(a.src_guide, g[b][u]);
+  }
+#pragma unroll
+  for (int32_t b = 0; b < B; ++b) {
+#pragma unroll
+    for (int32_t u = 0; u < N; ++u) {
+      const bool below = error_below<FMT>(gt[b], guide_unpack<FMT>(g[b][u]), a.threshold);
+      const bool take = (!done[b]) & ok[b][u] & below;
+      chunk[b] = take ? chunk_code(i0 + u, wq[b][u]) : chunk[b];
+      off[b] = take ? wo[b][u] : off[b];
+      done[b] = done[b] || take;
+    }
   }
 }
 
-// The level loop for one 8 x 8 block whose pixels share one cell at every
-// level (every spacing >= 8).  The wave stages its 9 L seed records in LDS
-// (one gather per 64 records) and runs the levels in groups of G
-// (level_group).  The target guide, the records and the
-// pixel's own lookup (its fallback) are all requested up front, so the chain
-// of dependent memory round trips is guide -> lookup and records -> source
-// guide, side by side.
-template <int FMT, int G>
+// The level loop for B horizontally adjacent 8 x 8 blocks whose pixels share
+// one cell at every level (every spacing >= 8); lane l takes pixel l of each
+// block.  The wave stages each block's 9 L seed records in LDS (one gather
+// per 64 records) and runs the levels in groups of G (level_group).  The
+// target guide, the records and the pixels' own lookups (their fallback) are
+// all requested up front, so the chain of dependent memory round trips is
+// guide -> lookup and records -> source guide, side by side.
+template <int FMT, int G, int B>
 __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0, int32_t lane,
                                     uint32_t *lpos, uint32_t *loff) {
   const Levels &lv = a.lv;
   const int32_t L = lv.count;
-  const int32_t x = bx0 + (lane & 7), y = by0 + (lane >> 3);
-  const bool in = x < a.w && y < a.h;
-  const uint32_t pidx = in ? uint32_t(y) * uint32_t(a.w) + uint32_t(x) : 0u;
-  const uint32_t gt = guide_word<FMT>(a.tgt_guide, pidx);
-  // record j of the block (level j / 9, neighbour j % 9) for lanes j and j + 64
-  uint32_t ridx[2] = {0, 0};
-  int32_t slot[2] = {-1, -1};
-  for (int32_t i = 0; i < L; ++i) {
-    const int32_t ls = lv.log2_spacing[i], pc = lv.cells_x[i] + 2;
-    // padded coordinates of the 3x3 neighbourhood's top-left cell
-    const int32_t top = lv.poffset[i] + (by0 >> ls) * pc + (bx0 >> ls);
+  const int32_t y = by0 + (lane >> 3);
+  int32_t x[B];
+  bool in[B];
+  uint32_t pidx[B], gt[B];
 #pragma unroll
-    for (int32_t h = 0; h < 2; ++h) {
-      const int32_t k = lane + 64 * h - 9 * i;
-      if (k >= 0 && k < 9) {
-        const int32_t kx = (k * 11) >> 5;  // k / 3 for k < 9
-        ridx[h] = uint32_t(top + (k - 3 * kx) * pc + kx);
-        slot[h] = kRecStride * i + k;
+  for (int32_t b = 0; b < B; ++b) {
+    x[b] = bx0 + 8 * b + (lane & 7);
+    in[b] = x[b] < a.w && y < a.h;
+    pidx[b] = in[b] ? uint32_t(y) * uint32_t(a.w) + uint32_t(x[b]) : 0u;
+    gt[b] = guide_word<FMT>(a.tgt_guide, pidx[b]);
+  }
+  // record j of block b (level j / 9, neighbour j % 9) for lanes j and j + 64;
+  // a block past the frame's right edge stages the last column's cells (its
+  // pixels are all outside, so they are never used)
+  uint32_t ridx[B][2];
+  int32_t slot[B][2];
+#pragma unroll
+  for (int32_t b = 0; b < B; ++b) {
+    const int32_t cx0 = min(bx0 + 8 * b, a.w - 1);
+    ridx[b][0] = ridx[b][1] = 0;
+    slot[b][0] = slot[b][1] = -1;
+    for (int32_t i = 0; i < L; ++i) {
+      const int32_t ls = lv.log2_spacing[i], pc = lv.cells_x[i] + 2;
+      // padded coordinates of the 3x3 neighbourhood's top-left cell
+      const int32_t top = lv.poffset[i] + (by0 >> ls) * pc + (cx0 >> ls);
+#pragma unroll
+      for (int32_t h = 0; h < 2; ++h) {
+        const int32_t k = lane + 64 * h - 9 * i;
+        if (k >= 0 && k < 9) {
+          const int32_t kx = (k * 11) >> 5;  // k / 3 for k < 9
+          ridx[b][h] = uint32_t(top + (k - 3 * kx) * pc + kx);
+          slot[b][h] = b * kWaveRecs + kRecStride * i + k;
+        }
       }
     }
   }
-  u32x2 rec[2] = {{0, 0}, {0, 0}};
+  u32x2 rec[B][2];
 #pragma unroll
-  for (int32_t h = 0; h < 2; ++h)
-    if (slot[h] >= 0) rec[h] = seed_table(a)[ridx[h]];
+  for (int32_t b = 0; b < B; ++b) {
 #pragma unroll
-  for (int32_t h = 0; h < 2; ++h) {
-    if (slot[h] >= 0) {
-      lpos[slot[h]] = rec[h].x;
-      loff[slot[h]] = rec[h].y;
+    for (int32_t h = 0; h < 2; ++h) {
+      rec[b][h] = u32x2{0, 0};
+      if (slot[b][h] >= 0) rec[b][h] = seed_table(a)[ridx[b][h]];
+    }
+  }
+#pragma unroll
+  for (int32_t b = 0; b < B; ++b) {
+#pragma unroll
+    for (int32_t h = 0; h < 2; ++h) {
+      if (slot[b][h] >= 0) {
+        lpos[slot[b][h]] = rec[b][h].x;
+        loff[slot[b][h]] = rec[b][h].y;
+      }
     }
   }
   wave_lds_sync();
-  // the pixel's own lookup, used when no level accepts
-  const uint32_t own = glb(a.lut)[lut_bin(gt, a.lut_shift, a.lut_bits)];
-  const short2_t p4 = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x), uint32_t(4 * y)));
-  uint32_t chunk = 0, off = 0;
-  bool done = !in;
+  // the pixels' own lookups, used when no level accepts
+  uint32_t own[B], chunk[B], off[B];
+  short2_t p4[B];
+  bool done[B];
+#pragma unroll
+  for (int32_t b = 0; b < B; ++b) {
+    own[b] = glb(a.lut)[lut_bin(gt[b], a.lut_shift, a.lut_bits)];
+    p4[b] = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x[b]), uint32_t(4 * y)));
+    chunk[b] = off[b] = 0;
+    done[b] = !in[b];
+  }
   // groups of G levels (one round trip of gathers each) until every pixel of
-  // the block has a level or the levels run out
+  // the blocks has a level or the levels run out
   for (int32_t i0 = 0; i0 < L; i0 += G) {
-    if (__all(done)) break;
-    level_group<FMT, G>(a, lpos, loff, i0, x, y, p4, gt, chunk, off, done);
+    bool all = true;
+#pragma unroll
+    for (int32_t b = 0; b < B; ++b) all = all && done[b];
+    if (__all(all)) break;
+    level_group<FMT, G, B>(a, lpos, loff, i0, x, y, p4, gt, chunk, off, done);
   }
-  if (!in) return;
-  if (!done) {  // no level accepted: the pixel's own lookup
-    chunk = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
-    off = pack_off(int32_t(own & 0xFFFFu) - x, int32_t(own >> 16) - y);
+#pragma unroll
+  for (int32_t b = 0; b < B; ++b) {
+    if (!in[b]) continue;
+    if (!done[b]) {  // no level accepted: the pixel's own lookup
+      chunk[b] = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x[b]);
+      off[b] = pack_off(int32_t(own[b] & 0xFFFFu) - x[b], int32_t(own[b] >> 16) - y);
+    }
+    glb(a.out_chunk)[pidx[b]] = chunk[b];
+    glb(a.offsets)[pidx[b]] = off[b];
+    if (a.out_nnf)
+      glb(a.out_nnf)[pidx[b]] =
+          pack_xy(uint32_t(x[b] + off_x(off[b])), uint32_t(y + off_y(off[b])));
   }
-  glb(a.out_chunk)[pidx] = chunk;
-  glb(a.offsets)[pidx] = off;
-  if (a.out_nnf) glb(a.out_nnf)[pidx] = pack_xy(uint32_t(x + off_x(off)), uint32_t(y + off_y(off)));
 }
 
 // The level loop for one pixel when cells are smaller than 8 x 8 blocks:
@@ -310,29 +357,33 @@ __device__ inline bool uniform_cells(const Levels &lv) {
   return lv.count == 0 || lv.log2_spacing[lv.count - 1] >= 3;
 }
 
-// One 16 x 16 tile: four 8 x 8 blocks, one per wave, on the uniform-cell
-// path; otherwise one pixel per thread.  `recs` is LDS for 4 waves' records.
-template <int FMT, int G>
+// One (16 B) x 16 tile: four groups of B 8 x 8 blocks, one group per wave, on
+// the uniform-cell path; otherwise B pixels per thread.  `recs` is LDS for 4
+// waves' records (2 B kWaveRecs words each).
+template <int FMT, int G, int B>
 __device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t tid,
                                    uint32_t *recs) {
-  const uint32_t tiles_x = (uint32_t(a.w) + 15) / 16;
-  const int32_t tx0 = int32_t((tile % tiles_x) * 16), ty0 = int32_t((tile / tiles_x) * 16);
+  const uint32_t tw = 16 * B;
+  const uint32_t tiles_x = (uint32_t(a.w) + tw - 1) / tw;
+  const int32_t tx0 = int32_t((tile % tiles_x) * tw), ty0 = int32_t((tile / tiles_x) * 16);
   if (uniform_cells(a.lv)) {
     const int32_t wave = __builtin_amdgcn_readfirstlane(int32_t(tid >> 6));
-    const int32_t bx0 = tx0 + (wave & 1) * 8, by0 = ty0 + (wave >> 1) * 8;
-    // a block wholly outside the frame has no cells in the table
+    const int32_t bx0 = tx0 + (wave & 1) * 8 * B, by0 = ty0 + (wave >> 1) * 8;
+    // a block group wholly outside the frame has no cells in the table
     if (bx0 >= a.w || by0 >= a.h) return;
-    uint32_t *lpos = recs + wave * 2 * kWaveRecs;
-    assign_block<FMT, G>(a, bx0, by0, int32_t(tid & 63), lpos, lpos + kWaveRecs);
+    uint32_t *lpos = recs + wave * 2 * B * kWaveRecs;
+    assign_block<FMT, G, B>(a, bx0, by0, int32_t(tid & 63), lpos, lpos + B * kWaveRecs);
   } else {
-    assign_pixel<FMT>(a, tx0 + int32_t(tid & 15), ty0 + int32_t(tid >> 4));
+#pragma unroll
+    for (int32_t b = 0; b < B; ++b)
+      assign_pixel<FMT>(a, tx0 + 16 * b + int32_t(tid & 15), ty0 + int32_t(tid >> 4));
   }
 }
 
-template <int FMT, int G>
+template <int FMT, int G, int B>
 __global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
-  __shared__ __attribute__((aligned(16))) uint32_t recs[4 * 2 * kWaveRecs];
-  assign_tile<FMT, G>(a, blockIdx.x, threadIdx.x, recs);
+  __shared__ __attribute__((aligned(16))) uint32_t recs[4 * 2 * B * kWaveRecs];
+  assign_tile<FMT, G, B>(a, blockIdx.x, threadIdx.x, recs);
 }
 
 // Exact n / k for n < 2^20 and 1 <= k <= 225 via a float reciprocal and one
@@ -593,11 +644,12 @@ __global__ void __launch_bounds__(256) k_batch_seeds(const unsigned char *desc) 
   });
 }
 
-template <int G>
+template <int G, int B>
 __global__ void __launch_bounds__(256) k_batch_assign(const unsigned char *desc) {
-  batch_loop<1, 256, 4 * 2 * kWaveRecs>(desc, [](const FrameArgs &fa, uint32_t local, uint32_t *w) {
-    if (fa.fmt == SB_GUIDE_U8X2) assign_tile<SB_GUIDE_U8X2, G>(fa, local, threadIdx.x, w);
-    else assign_tile<SB_GUIDE_U16X2, G>(fa, local, threadIdx.x, w);
+  batch_loop<1, 256, 4 * 2 * B * kWaveRecs>(desc, [](const FrameArgs &fa, uint32_t local,
+                                                     uint32_t *w) {
+    if (fa.fmt == SB_GUIDE_U8X2) assign_tile<SB_GUIDE_U8X2, G, B>(fa, local, threadIdx.x, w);
+    else assign_tile<SB_GUIDE_U16X2, G, B>(fa, local, threadIdx.x, w);
   });
 }
 
@@ -612,9 +664,17 @@ __global__ void __launch_bounds__(16 * TH) k_batch_blend(const unsigned char *de
 
 unsigned blocks_for(uint64_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
 
-template <int FMT, int G>
+template <int FMT, int G, int B>
 void launch_assign(const FrameArgs &a, uint32_t blocks, hipStream_t stream) {
-  k_assign<FMT, G><<<blocks, 256, 0, stream>>>(a);
+  k_assign<FMT, G, B><<<blocks, 256, 0, stream>>>(a);
+}
+
+template <int FMT>
+void launch_assign_any(const FrameArgs &a, const Tune &t, uint32_t blocks, hipStream_t stream) {
+  if (t.group == 4 && t.apx == 2) launch_assign<FMT, 4, 2>(a, blocks, stream);
+  else if (t.group == 4) launch_assign<FMT, 4, 1>(a, blocks, stream);
+  else if (t.apx == 2) launch_assign<FMT, 2, 2>(a, blocks, stream);
+  else launch_assign<FMT, 2, 1>(a, blocks, stream);
 }
 
 template <int PPT, int TH>
@@ -650,7 +710,8 @@ void tile_counts(const FrameArgs &a, const Tune &t, uint32_t counts[4]) {
   const uint32_t tw = 16 * uint32_t(t.ppt), th = uint32_t(t.rows);
   const uint32_t blend = ((uint32_t(a.w) + tw - 1) / tw) * ((uint32_t(a.h) + th - 1) / th);
   counts[0] = (uint32_t(a.lv.poffset[a.lv.count]) + 255) / 256;
-  counts[1] = ((uint32_t(a.w) + 15) / 16) * ((uint32_t(a.h) + 15) / 16);
+  const uint32_t aw = 16 * uint32_t(t.apx);
+  counts[1] = ((uint32_t(a.w) + aw - 1) / aw) * ((uint32_t(a.h) + 15) / 16);
   counts[2] = a.radius <= 3 ? blend : 0;
   counts[3] = a.radius <= 3 ? 0 : blend;
 }
@@ -669,14 +730,8 @@ hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, const Tune &t, hipEve
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[1], stream);
   if (e == hipSuccess) {
-    const bool u8 = fmt == SB_GUIDE_U8X2;
-    if (t.group == 4) {
-      if (u8) launch_assign<SB_GUIDE_U8X2, 4>(a, c[1], stream);
-      else launch_assign<SB_GUIDE_U16X2, 4>(a, c[1], stream);
-    } else {
-      if (u8) launch_assign<SB_GUIDE_U8X2, 2>(a, c[1], stream);
-      else launch_assign<SB_GUIDE_U16X2, 2>(a, c[1], stream);
-    }
+    if (fmt == SB_GUIDE_U8X2) launch_assign_any<SB_GUIDE_U8X2>(a, t, c[1], stream);
+    else launch_assign_any<SB_GUIDE_U16X2>(a, t, c[1], stream);
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[2], stream);
   if (e == hipSuccess) {
@@ -694,8 +749,10 @@ hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, const Tune &t, hipEve
 hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, const Tune &t,
                         hipStream_t stream) {
   k_batch_seeds<<<grid, 256, 0, stream>>>(desc_dev);
-  if (t.group == 4) k_batch_assign<4><<<grid, 256, 0, stream>>>(desc_dev);
-  else k_batch_assign<2><<<grid, 256, 0, stream>>>(desc_dev);
+  if (t.group == 4 && t.apx == 2) k_batch_assign<4, 2><<<grid, 256, 0, stream>>>(desc_dev);
+  else if (t.group == 4) k_batch_assign<4, 1><<<grid, 256, 0, stream>>>(desc_dev);
+  else if (t.apx == 2) k_batch_assign<2, 2><<<grid, 256, 0, stream>>>(desc_dev);
+  else k_batch_assign<2, 1><<<grid, 256, 0, stream>>>(desc_dev);
   if (t.ppt == 4 && t.rows == 16) launch_batch_blend<4, 16>(desc_dev, grid, stream);
   else if (t.ppt == 4) launch_batch_blend<4, 8>(desc_dev, grid, stream);
   else if (t.rows == 16) launch_batch_blend<2, 16>(desc_dev, grid, stream);

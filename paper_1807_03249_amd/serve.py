@@ -102,7 +102,7 @@ def run(requests: Sequence[Request], slots: int = 4, max_batch: int = 16,
     desc_host = torch.empty(db * nslots, dtype=torch.uint8).pin_memory()
     cfg = SbServeConfig(nslots, mb, 1 if use_graph else 0, 1 if plain else 0, arena.data_ptr(),
                         int(budget_bytes), desc_dev.data_ptr(), desc_host.data_ptr(),
-                        ws.data_ptr(), per_slot, tune_struct(tune) or SbTune(0, 0, 0),
+                        ws.data_ptr(), per_slot, tune_struct(tune) or SbTune(0, 0, 0, 0),
                         int(blocks_per_cu))
     res = (SbRequestResult * n)()
     torch.cuda.synchronize()

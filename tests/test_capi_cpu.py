@@ -123,7 +123,7 @@ def test_tune_validation(L):
                                None, fake, ws, ctypes.byref(sb.SbTune(*tune)), None)
 
     for bad in [(3, 16, 2), (1, 16, 2), (4, 12, 2), (4, 32, 2), (4, 16, 3), (4, 16, 1),
-                (-4, 16, 2)]:
+                (-4, 16, 2), (4, 16, 2, 3), (4, 16, 2, -1)]:
         assert call(bad) == sb.SB_EINVAL, bad
     ev = (ctypes.c_void_p * 4)()
     assert L.sb_stylize_timed(ctypes.byref(st), fake, 64, 64, fake, ctypes.byref(p), fake, fake,

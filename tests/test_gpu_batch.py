@@ -71,7 +71,8 @@ def test_batch_equals_single(sb, mix, use_graph):
     b.close()
 
 
-@pytest.mark.parametrize("tune,bpc", [((2, 8, 4), 2), ((4, 8, 2), 1), ((2, 16, 2), 16)])
+@pytest.mark.parametrize("tune,bpc", [((2, 8, 4, 2), 2), ((4, 8, 2, 1), 1), ((2, 16, 2, 2), 16),
+                                      ((4, 16, 4, 2), 8)])
 def test_batch_tunes_equal_single(sb, mix, tune, bpc):
     """Every kernel choice and persistent grid size gives the same bits."""
     import torch
@@ -170,3 +171,34 @@ def test_batch_rejects_bad_frames(sb, mix):
         b.run(jobs * (b.max_frames + 1))
     torch.cuda.synchronize()
     b.close()
+
+
+def test_batch_mixed_radii(sb):
+    """Frames of radius 0..7 in one batch: both vote kernels (radius 0-3 and
+    4-7) run in the same replay, each over its own frames' tiles."""
+    import torch
+
+    styles_np, frames_np = workloads.config(1)
+    st = sb.Style(styles_np[0].rgb, styles_np[0].guide, styles_np[0].lut_bits)
+    f = frames_np[0]
+    rng = np.random.default_rng(11)
+    jobs, expect = [], []
+    for i, r in enumerate([7, 0, 4, 3, 6, 1, 5, 2]):
+        w, h = int(rng.integers(40, 257)), int(rng.integers(30, 257))
+        g = np.ascontiguousarray(f.guide[:h, :w])
+        jit = workloads.jitter_table(w, h, 3, 8, 100 + i)
+        p = sb.params(3, 8, 48, r)
+        jobs.append(sb.FrameJob(st, g, jit, p))
+        rgb, chunk = sb.stylize(st, g, jit, p)
+        expect.append((rgb, chunk))
+    torch.cuda.synchronize()
+    for tune in [None, (2, 16, 4, 1)]:
+        say(f"mixed radii batch tune={tune}")
+        b = sb.Batch(use_graph=True, tune=tune)
+        b.run(jobs)
+        torch.cuda.synchronize()
+        for j, (rgb, chunk) in zip(jobs, expect):
+            np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), rgb.cpu().numpy(),
+                                          err_msg=f"r={j.params.radius}")
+            np.testing.assert_array_equal(j.out_chunk.cpu().numpy(), chunk.cpu().numpy())
+        b.close()

@@ -34,7 +34,7 @@ def test_timed_entry_matches_plain_and_orders_events(env):
     say("sb_stylize_timed vs sb_stylize")
     ref_rgb, ref_chunk = sb.stylize(style, fr.guide, fr.jitter, prm)
     ev = sb.TimingEvents()
-    rgb, chunk = sb.stylize(style, fr.guide, fr.jitter, prm, events=ev, tune=(2, 8, 4))
+    rgb, chunk = sb.stylize(style, fr.guide, fr.jitter, prm, events=ev, tune=(2, 8, 4, 2))
     torch.cuda.synchronize()
     assert torch.equal(rgb, ref_rgb) and torch.equal(chunk, ref_chunk)
     d = ev.pass_ms()
@@ -72,7 +72,7 @@ def test_tune_batch_picks_an_exact_choice(env, tmp_path):
         jobs.append(sb.FrameJob(styles[f.style], f.guide, f.jitter,
                                 sb.params(p.levels, p.finest, p.threshold, p.radius)))
     say(f"tune_batch over {len(jobs)} frames")
-    r = at.tune_batch(jobs, candidates=[(4, 16, 2), (2, 8, 4)], blocks_per_cu=(2, 8), reps=2,
+    r = at.tune_batch(jobs, candidates=[(4, 16, 2, 1), (2, 8, 4, 2)], blocks_per_cu=(2, 8), reps=2,
                       cache_path=str(tmp_path / "tune.json"))
     assert all(v["exact"] for v in r["candidates"].values()), r["candidates"]
     b = sb.Batch(use_graph=True, tune=r["tune"], blocks_per_cu=r["blocks_per_cu"])
