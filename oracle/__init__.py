@@ -13,7 +13,11 @@ positions against the jitter table read directly, hand-worked 8x8 cases
 (``tests/golden/``), texture mapping as the threshold-0 special case and
 the paper's invariants (identity guide reproduces the source, larger
 threshold never picks a finer level, chunks are pure translations, every
-accepted pixel has error below the threshold).
+accepted pixel has error below the threshold).  The segmentation-guide
+variant (per-label tables, the label constraint in the level loop) is pinned
+by its reduction to the plain path with one label, brute-force per-label
+tables, a hand-worked case and its label invariants
+(``tests/test_oracle_seg.py``).
 """
 from __future__ import annotations
 
@@ -65,6 +69,10 @@ def _load():
                               ctypes.c_int64]
     lib.ora_stylize.argtypes = [_u8p, vp, i32, i32, _u32p, i32, i32, vp, i32, i32, _u32p, i32,
                                 i32, ctypes.c_uint32, i32, _u8p, _u32p, _u32p]
+    lib.ora_lut_build_labels.argtypes = [vp, _u8p, i32, i32, i32, i32, i32, _u32p]
+    lib.ora_stylize_seg.argtypes = [_u8p, vp, _u8p, i32, i32, _u32p, i32, i32, i32, vp, _u8p,
+                                    i32, i32, _u32p, i32, i32, ctypes.c_uint32, i32, _u8p, _u32p,
+                                    _u32p]
     _lib = lib
     return lib
 
@@ -183,6 +191,55 @@ def stylize(src_rgb, src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest
                                _ptr(lut, _u32p), fmt, lut_bits, gt.ctypes.data, w, h,
                                _ptr(j, _u32p), levels, finest, threshold, radius,
                                _ptr(out, _u8p), _ptr(chunk, _u32p), _ptr(nnf, _u32p)), "stylize")
+    return out, chunk, nnf
+
+
+def _labels(lab: np.ndarray, shape) -> np.ndarray:
+    lab = np.ascontiguousarray(lab, dtype=np.uint8)
+    if lab.shape != tuple(shape):
+        raise ValueError(f"label map has shape {lab.shape}, expected {tuple(shape)}")
+    return lab
+
+
+def lut_build_labels(src_guide: np.ndarray, src_labels: np.ndarray, nlabels: int,
+                     lut_bits: int) -> np.ndarray:
+    """Per-label lookup tables (segmentation guide), shape (nlabels, bins):
+    table l from the source pixels labelled l; a label without source pixels
+    gets the unconstrained table."""
+    g, fmt = _guide(src_guide)
+    lab = _labels(src_labels, g.shape[:2])
+    n = 1 << lut_bits
+    luts = np.zeros((nlabels, n * n), np.uint32)
+    _check(_load().ora_lut_build_labels(g.ctypes.data, _ptr(lab, _u8p), nlabels, fmt, g.shape[1],
+                                        g.shape[0], lut_bits, _ptr(luts, _u32p)),
+           "lut_build_labels")
+    return luts
+
+
+def stylize_seg(src_rgb, src_guide, src_labels, luts, nlabels, lut_bits, tgt_guide, tgt_labels,
+                jitter, levels, finest, threshold, radius):
+    """The per-frame path with the segmentation guide as a hard constraint:
+    returns (rgb, chunk, nnf) as ``stylize``."""
+    gs, fmt = _guide(src_guide)
+    gt, fmt_t = _guide(tgt_guide)
+    if fmt != fmt_t:
+        raise ValueError("source and target guide formats differ")
+    ls = _labels(src_labels, gs.shape[:2])
+    lt = _labels(tgt_labels, gt.shape[:2])
+    rgb = np.ascontiguousarray(src_rgb, dtype=np.uint8)
+    h, w = gt.shape[:2]
+    j = _jit(jitter, w, h, levels, finest)
+    luts = np.ascontiguousarray(luts, dtype=np.uint32)
+    if luts.size != nlabels << (2 * lut_bits):
+        raise ValueError("luts must hold nlabels tables")
+    out = np.zeros((h, w, 3), np.uint8)
+    chunk = np.zeros((h, w), np.uint32)
+    nnf = np.zeros((h, w), np.uint32)
+    _check(_load().ora_stylize_seg(_ptr(rgb, _u8p), gs.ctypes.data, _ptr(ls, _u8p), gs.shape[1],
+                                   gs.shape[0], _ptr(luts, _u32p), nlabels, fmt, lut_bits,
+                                   gt.ctypes.data, _ptr(lt, _u8p), w, h, _ptr(j, _u32p), levels,
+                                   finest, threshold, radius, _ptr(out, _u8p), _ptr(chunk, _u32p),
+                                   _ptr(nnf, _u32p)), "stylize_seg")
     return out, chunk, nnf
 
 

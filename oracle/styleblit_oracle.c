@@ -34,6 +34,19 @@
  *   - voting: square (2r+1)^2 window of uniform weight over target pixels n;
  *     n votes with the source pixel NNF[n] + (p - n) when that lies in the
  *     source; per channel (sum + floor(k/2)) / k in integers.
+ *
+ * Segmentation guide (the extra guide of Sec. 4 that keeps chunks inside
+ * semantic regions), read as a hard constraint:
+ *   - a uint8 label per source pixel and per target pixel, labels
+ *     0..nlabels-1 (a larger value selects table nlabels-1 and is compared
+ *     as is);
+ *   - one lookup table per label over the source pixels of that label
+ *     (ties as above); a label with no source pixel uses the unconstrained
+ *     table;
+ *   - a seed q looks up u* in the table of its own label L_T[q];
+ *   - a level is accepted only if, besides the error test, the transferred
+ *     source pixel carries the pixel's label: L_S[v] == L_T[p];
+ *   - the fallback is the pixel's own lookup in the table of its label.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -85,7 +98,11 @@ static int64_t lut_bin_centre(int64_t c, int fmt, int lut_bits)
  * continue: a later ring may hold an equally near pixel with a smaller raster
  * index.)
  */
-int ora_lut_build(const void *src_guide, int fmt, int sw, int sh, int lut_bits, uint32_t *lut)
+/* The table over the source pixels whose label is `want` (labels NULL: all
+ * pixels).  Returns ORA_OK, or 1 when no source pixel qualifies (lut left
+ * untouched). */
+static int lut_build_filtered(const void *src_guide, const uint8_t *labels, int want, int fmt,
+                              int sw, int sh, int lut_bits, uint32_t *lut)
 {
     if (!src_guide || !lut || sw < 1 || sh < 1 || (fmt != 0 && fmt != 1)) return ORA_EINVAL;
     if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
@@ -99,14 +116,17 @@ int ora_lut_build(const void *src_guide, int fmt, int sw, int sh, int lut_bits, 
     int64_t *fill = (int64_t *)malloc((size_t)(n * n) * sizeof(int64_t));
     if (!start || !list || !fill) { free(start); free(list); free(fill); return ORA_ENOMEM; }
     for (int64_t i = 0; i < npix; ++i) {
+        if (labels && labels[i] != want) continue;
         int64_t g0, g1;
         guide_read(src_guide, fmt, i, &g0, &g1);
         int64_t b = lut_quantise(g1, fmt, lut_bits) * n + lut_quantise(g0, fmt, lut_bits);
         start[b + 1]++;
     }
     for (int64_t b = 0; b < n * n; ++b) start[b + 1] += start[b];
+    if (start[n * n] == 0) { free(start); free(list); free(fill); return 1; }
     memcpy(fill, start, (size_t)(n * n) * sizeof(int64_t));
     for (int64_t i = 0; i < npix; ++i) {
+        if (labels && labels[i] != want) continue;
         int64_t g0, g1;
         guide_read(src_guide, fmt, i, &g0, &g1);
         int64_t b = lut_quantise(g1, fmt, lut_bits) * n + lut_quantise(g0, fmt, lut_bits);
@@ -153,6 +173,28 @@ int ora_lut_build(const void *src_guide, int fmt, int sw, int sh, int lut_bits, 
     free(start);
     free(list);
     free(fill);
+    return ORA_OK;
+}
+
+int ora_lut_build(const void *src_guide, int fmt, int sw, int sh, int lut_bits, uint32_t *lut)
+{
+    return lut_build_filtered(src_guide, NULL, 0, fmt, sw, sh, lut_bits, lut);
+}
+
+/* Per-label tables luts[l * bins + c] for labels l = 0..nlabels-1, from the
+ * source pixels labelled l; a label without source pixels gets the
+ * unconstrained table. */
+int ora_lut_build_labels(const void *src_guide, const uint8_t *labels, int nlabels, int fmt, int sw,
+                         int sh, int lut_bits, uint32_t *luts)
+{
+    if (!labels || !luts || nlabels < 1 || nlabels > 256) return ORA_EINVAL;
+    if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
+    const int64_t bins = (int64_t)1 << (2 * lut_bits);
+    for (int l = 0; l < nlabels; ++l) {
+        int rc = lut_build_filtered(src_guide, labels, l, fmt, sw, sh, lut_bits, luts + l * bins);
+        if (rc == 1) rc = lut_build_filtered(src_guide, NULL, 0, fmt, sw, sh, lut_bits, luts + l * bins);
+        if (rc != ORA_OK) return rc;
+    }
     return ORA_OK;
 }
 
@@ -238,17 +280,23 @@ int ora_nearest_seed(int w, int h, int levels, int finest, const uint32_t *jitte
 typedef struct {
     const void *src_guide;
     int sw, sh;
-    const uint32_t *lut;
+    const uint32_t *lut;    /* one table, or nlabels tables with labels */
     int fmt, lut_bits;
     const void *tgt_guide;
     seeds_t seeds;
     uint32_t threshold;
+    const uint8_t *src_labels, *tgt_labels;  /* both NULL without segmentation */
+    int nlabels;
 } assign_t;
 
-static uint32_t lut_lookup(const assign_t *A, int64_t g0, int64_t g1)
+/* The lookup of a guide value in the table of `label` (ignored without
+ * segmentation; values past the last table use the last one). */
+static uint32_t lut_lookup(const assign_t *A, int64_t g0, int64_t g1, int label)
 {
     int64_t n = (int64_t)1 << A->lut_bits;
-    return A->lut[lut_quantise(g1, A->fmt, A->lut_bits) * n + lut_quantise(g0, A->fmt, A->lut_bits)];
+    const uint32_t *t = A->lut;
+    if (A->tgt_labels) t += (int64_t)(label < A->nlabels ? label : A->nlabels - 1) * n * n;
+    return t[lut_quantise(g1, A->fmt, A->lut_bits) * n + lut_quantise(g0, A->fmt, A->lut_bits)];
 }
 
 /* ParallelStyleBlit for one pixel, with colours replaced by coordinates:
@@ -259,15 +307,19 @@ static void assign_pixel(const assign_t *A, int64_t px, int64_t py, uint32_t *nn
     const int W = A->seeds.w;
     int64_t t0, t1;
     guide_read(A->tgt_guide, A->fmt, py * W + px, &t0, &t1);
+    const int lp = A->tgt_labels ? A->tgt_labels[py * W + px] : 0;
     for (int i = 0; i < A->seeds.levels; ++i) {
         int64_t qx, qy;
         if (!nearest_seed(&A->seeds, i, px, py, &qx, &qy)) continue;
         int64_t q0, q1;
         guide_read(A->tgt_guide, A->fmt, qy * W + qx, &q0, &q1);
-        uint32_t u = lut_lookup(A, q0, q1);
+        const int lq = A->tgt_labels ? A->tgt_labels[qy * W + qx] : 0;
+        uint32_t u = lut_lookup(A, q0, q1, lq);
         int64_t vx = (int64_t)(u & 0xFFFFu) + (px - qx);
         int64_t vy = (int64_t)(u >> 16) + (py - qy);
         if (vx < 0 || vy < 0 || vx >= A->sw || vy >= A->sh) continue;
+        /* segmentation: the source pixel must carry the pixel's label */
+        if (A->tgt_labels && A->src_labels[vy * A->sw + vx] != lp) continue;
         int64_t s0, s1;
         guide_read(A->src_guide, A->fmt, vy * A->sw + vx, &s0, &s1);
         uint64_t e = (uint64_t)((t0 - s0) * (t0 - s0)) + (uint64_t)((t1 - s1) * (t1 - s1));
@@ -277,7 +329,7 @@ static void assign_pixel(const assign_t *A, int64_t px, int64_t py, uint32_t *nn
             return;
         }
     }
-    *nnf = lut_lookup(A, t0, t1);
+    *nnf = lut_lookup(A, t0, t1, lp);
     *chunk = ((uint32_t)A->seeds.levels << 26) | ((uint32_t)py << 13) | (uint32_t)px;
 }
 
@@ -304,7 +356,7 @@ int ora_assign(const void *src_guide, int sw, int sh, const uint32_t *lut, int f
     if (rows < 0) rows = h;
     if (row0 < 0 || row0 + rows > h) return ORA_EINVAL;
     assign_t A = {src_guide, sw, sh, lut, fmt, lut_bits, tgt_guide, {w, h, levels, finest, jitter},
-                  threshold};
+                  threshold, NULL, NULL, 0};
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t y = row0; y < row0 + rows; ++y)
         for (int64_t x = 0; x < w; ++x)
@@ -363,6 +415,46 @@ int ora_stylize(const uint8_t *src_rgb, const void *src_guide, int sw, int sh, c
     if (!nnf) return ORA_ENOMEM;
     int rc = ora_assign(src_guide, sw, sh, lut, fmt, lut_bits, tgt_guide, w, h, jitter, levels,
                         finest, threshold, nnf, out_chunk, 0, -1);
+    if (rc == ORA_OK) rc = ora_blend(src_rgb, sw, sh, nnf, w, h, radius, out_rgb, 0, -1);
+    if (!out_nnf) free(nnf);
+    return rc;
+}
+
+/* ----------------------------------------------------- segmentation guide */
+
+/* ora_assign with label maps: src_labels Sw*Sh, tgt_labels W*H, luts the
+ * nlabels tables of ora_lut_build_labels. */
+int ora_assign_seg(const void *src_guide, const uint8_t *src_labels, int sw, int sh,
+                   const uint32_t *luts, int nlabels, int fmt, int lut_bits, const void *tgt_guide,
+                   const uint8_t *tgt_labels, int w, int h, const uint32_t *jitter, int levels,
+                   int finest, uint32_t threshold, uint32_t *out_nnf, uint32_t *out_chunk)
+{
+    int rc = check_common(sw, sh, fmt, lut_bits, w, h, levels, finest);
+    if (rc) return rc;
+    if (!src_guide || !src_labels || !luts || !tgt_guide || !tgt_labels || !out_nnf || !out_chunk)
+        return ORA_EINVAL;
+    if (nlabels < 1 || nlabels > 256) return ORA_EINVAL;
+    if (levels > 0 && !jitter) return ORA_EINVAL;
+    assign_t A = {src_guide, sw, sh, luts, fmt, lut_bits, tgt_guide, {w, h, levels, finest, jitter},
+                  threshold, src_labels, tgt_labels, nlabels};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t y = 0; y < h; ++y)
+        for (int64_t x = 0; x < w; ++x)
+            assign_pixel(&A, x, y, &out_nnf[y * w + x], &out_chunk[y * w + x]);
+    return ORA_OK;
+}
+
+int ora_stylize_seg(const uint8_t *src_rgb, const void *src_guide, const uint8_t *src_labels, int sw,
+                    int sh, const uint32_t *luts, int nlabels, int fmt, int lut_bits,
+                    const void *tgt_guide, const uint8_t *tgt_labels, int w, int h,
+                    const uint32_t *jitter, int levels, int finest, uint32_t threshold, int radius,
+                    uint8_t *out_rgb, uint32_t *out_chunk, uint32_t *out_nnf)
+{
+    if (!out_rgb || !out_chunk) return ORA_EINVAL;
+    uint32_t *nnf = out_nnf ? out_nnf : (uint32_t *)malloc((size_t)w * h * sizeof(uint32_t));
+    if (!nnf) return ORA_ENOMEM;
+    int rc = ora_assign_seg(src_guide, src_labels, sw, sh, luts, nlabels, fmt, lut_bits, tgt_guide,
+                            tgt_labels, w, h, jitter, levels, finest, threshold, nnf, out_chunk);
     if (rc == ORA_OK) rc = ora_blend(src_rgb, sw, sh, nnf, w, h, radius, out_rgb, 0, -1);
     if (!out_nnf) free(nnf);
     return rc;

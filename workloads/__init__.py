@@ -20,6 +20,7 @@ from .gen import (  # noqa: F401
     bump_guide_u8,
     identity_uv_guide_u16,
     warped_uv_guide_u16,
+    voronoi_labels,
     config,
     CONFIG_NAMES,
 )

@@ -223,6 +223,25 @@ def warped_uv_guide_u16(w: int, h: int, sw: int, sh: int, seed: int,
 # the five workloads
 # ---------------------------------------------------------------------------
 
+def voronoi_labels(w: int, h: int, nlabels: int, nsites: int, seed: int) -> np.ndarray:
+    """A uint8 label map of (h, w): seeded sites at uniform random positions,
+    site k labelled k mod nlabels, every pixel labelled by its nearest site
+    (squared distance, ties to the lower site index).  Stands in for the
+    segmentation maps of semantic regions."""
+    rng = np.random.default_rng(seed)
+    sx = rng.integers(0, w, size=nsites)
+    sy = rng.integers(0, h, size=nsites)
+    yy, xx = np.mgrid[0:h, 0:w]
+    best = np.full((h, w), np.iinfo(np.int64).max, np.int64)
+    lab = np.zeros((h, w), np.uint8)
+    for k in range(nsites):
+        d = (xx - int(sx[k])) ** 2 + (yy - int(sy[k])) ** 2
+        take = d < best
+        best[take] = d[take]
+        lab[take] = k % nlabels
+    return lab
+
+
 CONFIG_NAMES = {
     1: "normal-256x256",
     2: "normal-1920x1080",
