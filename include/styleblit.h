@@ -51,6 +51,7 @@ typedef enum { SB_GUIDE_U8X2 = 0, SB_GUIDE_U16X2 = 1 } sb_guide_fmt;
 #define SB_MAX_LEVELS 12
 #define SB_MAX_RADIUS 7
 #define SB_MAX_LUT_BITS 12
+#define SB_MAX_LABELS 256
 
 /* A style: the exemplar C_S, its guide G_S and the lookup table built from
  * G_S (Sec. 3.1).  A plain struct of caller-owned device pointers; it must
@@ -65,6 +66,15 @@ typedef struct {
     int32_t fmt;            /* sb_guide_fmt */
     int32_t lut_bits;       /* bits per channel of the lookup table: U8X2 1..8,
                                U16X2 1..SB_MAX_LUT_BITS */
+    /* Segmentation guide (optional; nlabels = 0 and NULLs without it): a
+     * label per source pixel and one lookup table per label, so chunks stay
+     * inside regions of equal label (the extra segmentation guide of the
+     * paper's results section, read as a hard constraint: see
+     * sb_stylize_seg). */
+    const uint8_t *labels;      /* [device] Sw*Sh labels 0..nlabels-1 */
+    const uint32_t *label_luts; /* [device] nlabels tables of (1<<lut_bits)^2 entries,
+                                   written by sb_lut_build_labels */
+    int32_t nlabels;            /* 0, or 1..SB_MAX_LABELS */
 } sb_style;
 
 /* Per-frame parameters of Algorithm 2 and of the voting blend. */
@@ -118,6 +128,18 @@ size_t sb_lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_b
  * workspace [device] of at least sb_lut_workspace_bytes() bytes. */
 int sb_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
                  uint32_t *lut, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Per-label lookup tables for the segmentation guide: table l holds, for
+ * every bin, the source pixel labelled l whose guide is nearest to the bin
+ * centre (ties to the smallest raster index, as sb_lut_build); a label with
+ * no source pixel gets the unconstrained table `lut` (from sb_lut_build).
+ * guide [device] Sw*Sh*2; labels [device] Sw*Sh (values >= nlabels belong
+ * to no table); lut [device] the unconstrained table; luts [device] nlabels
+ * tables, label-major; workspace [device] of sb_lut_workspace_bytes(). */
+int sb_lut_build_labels(const void *guide, const uint8_t *labels, int32_t fmt, int32_t sw,
+                        int32_t sh, int32_t lut_bits, int32_t nlabels, const uint32_t *lut,
+                        uint32_t *luts, void *workspace, size_t workspace_bytes,
+                        hipStream_t stream);
 
 /* -------------------------------------------------------- one frame */
 
@@ -176,6 +198,18 @@ int sb_stylize_timed(const sb_style *style, const void *tgt_guide, int32_t w, in
                      size_t workspace_bytes, const sb_tune *tune, hipEvent_t events[4],
                      hipStream_t stream);
 
+/* sb_stylize_ex with the segmentation guide.  tgt_labels [device] W*H: the
+ * target's label map; the style must carry labels (nlabels >= 1).  A seed q
+ * takes its lookup from the table of its label L_T[q]; a level is accepted
+ * only if, besides the error test, the transferred source pixel v carries
+ * the pixel's label (L_S[v] == L_T[p]); a pixel no level accepts takes its
+ * own lookup in the table of its label.  A label value >= nlabels selects
+ * table nlabels-1 and is compared as is.  Voting is unchanged. */
+int sb_stylize_seg(const sb_style *style, const void *tgt_guide, const uint8_t *tgt_labels,
+                   int32_t w, int32_t h, const uint32_t *jitter, const sb_params *params,
+                   uint8_t *out_rgb, uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
+                   size_t workspace_bytes, const sb_tune *tune, hipStream_t stream);
+
 /* Four timing events for sb_stylize_timed, created without the system-scope
  * fence (hipEventDisableSystemFence), so recording them
  * between passes adds no cache write-back or invalidation to the timed work.
@@ -197,6 +231,8 @@ typedef struct {
     uint8_t *out_rgb;           /* [device] W*H*3 */
     uint32_t *out_chunk;        /* [device] W*H */
     uint32_t *out_nnf;          /* [device, may be NULL] W*H */
+    const uint8_t *tgt_labels;  /* [device, may be NULL] W*H target labels: the frame
+                                   runs as sb_stylize_seg (the style must carry labels) */
 } sb_frame;
 
 typedef struct sb_batch sb_batch;  /* opaque: descriptor buffers and captured graphs */

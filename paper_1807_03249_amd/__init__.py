@@ -32,7 +32,8 @@ class StyleBlitError(RuntimeError):
 class SbStyle(ctypes.Structure):
     _fields_ = [("rgba", ctypes.c_void_p), ("guide", ctypes.c_void_p), ("lut", ctypes.c_void_p),
                 ("sw", ctypes.c_int32), ("sh", ctypes.c_int32), ("fmt", ctypes.c_int32),
-                ("lut_bits", ctypes.c_int32)]
+                ("lut_bits", ctypes.c_int32), ("labels", ctypes.c_void_p),
+                ("label_luts", ctypes.c_void_p), ("nlabels", ctypes.c_int32)]
 
 
 class SbTune(ctypes.Structure):
@@ -66,7 +67,7 @@ class SbFrame(ctypes.Structure):
     _fields_ = [("style", ctypes.POINTER(SbStyle)), ("tgt_guide", ctypes.c_void_p),
                 ("jitter", ctypes.c_void_p), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
                 ("params", SbParams), ("out_rgb", ctypes.c_void_p), ("out_chunk", ctypes.c_void_p),
-                ("out_nnf", ctypes.c_void_p)]
+                ("out_nnf", ctypes.c_void_p), ("tgt_labels", ctypes.c_void_p)]
 
 
 _lib = None
@@ -100,6 +101,10 @@ def lib():
     L.sb_stylize_ex.argtypes = [ctypes.POINTER(SbStyle), vp, i32, i32, vp,
                                 ctypes.POINTER(SbParams), vp, vp, vp, vp, sz,
                                 ctypes.POINTER(SbTune), vp]
+    L.sb_lut_build_labels.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp]
+    L.sb_stylize_seg.argtypes = [ctypes.POINTER(SbStyle), vp, vp, i32, i32, vp,
+                                 ctypes.POINTER(SbParams), vp, vp, vp, vp, sz,
+                                 ctypes.POINTER(SbTune), vp]
     L.sb_stylize_timed.argtypes = [ctypes.POINTER(SbStyle), vp, i32, i32, vp,
                                    ctypes.POINTER(SbParams), vp, vp, vp, vp, sz,
                                    ctypes.POINTER(SbTune), ctypes.POINTER(vp), vp]
@@ -172,9 +177,12 @@ def _guide_fmt(torch, g) -> int:
 
 class Style:
     """A device-resident style: RGBA-packed exemplar, its guide and the lookup
-    table built from it on the GPU (Sec. 3.1)."""
+    table built from it on the GPU (Sec. 3.1).  With ``labels`` (uint8
+    (rows, cols), values below ``nlabels``) the style also carries the
+    segmentation guide: its label map and one lookup table per label."""
 
-    def __init__(self, rgb, guide, lut_bits: int, stream=None):
+    def __init__(self, rgb, guide, lut_bits: int, stream=None, labels=None,
+                 nlabels: Optional[int] = None):
         torch = _torch()
         self.rgb = _dev(torch, rgb)
         if self.rgb.dtype != torch.uint8 or self.rgb.dim() != 3 or self.rgb.shape[2] != 3:
@@ -205,12 +213,31 @@ class Style:
         _check(L.sb_lut_build(self.guide.data_ptr(), self.fmt, self.sw, self.sh, self.lut_bits,
                               self.lut.data_ptr(), ws.data_ptr(), wsb, s), "sb_lut_build")
         self._ws = ws  # keep alive until the enqueued build has run
+        self.labels = self.label_luts = None
+        self.nlabels = 0
+        if labels is not None:
+            self.labels = _dev(torch, labels, torch.uint8)
+            if tuple(self.labels.shape) != (self.sh, self.sw):
+                raise ValueError("label map and exemplar sizes differ")
+            self.nlabels = int(nlabels if nlabels is not None else int(self.labels.max()) + 1)
+            self.label_luts = torch.empty((self.nlabels, 1 << (2 * self.lut_bits)),
+                                          dtype=torch.int32, device="cuda")
+            _check(L.sb_lut_build_labels(self.guide.data_ptr(), self.labels.data_ptr(), self.fmt,
+                                         self.sw, self.sh, self.lut_bits, self.nlabels,
+                                         self.lut.data_ptr(), self.label_luts.data_ptr(),
+                                         ws.data_ptr(), wsb, s), "sb_lut_build_labels")
         self.c = SbStyle(self.rgba.data_ptr(), self.guide.data_ptr(), self.lut.data_ptr(),
-                         self.sw, self.sh, self.fmt, self.lut_bits)
+                         self.sw, self.sh, self.fmt, self.lut_bits,
+                         self.labels.data_ptr() if self.labels is not None else None,
+                         self.label_luts.data_ptr() if self.label_luts is not None else None,
+                         self.nlabels)
 
     def resident_bytes(self) -> int:
-        return (self.rgba.numel() * 4 + self.guide.numel() * self.guide.element_size()
-                + self.lut.numel() * 4)
+        n = (self.rgba.numel() * 4 + self.guide.numel() * self.guide.element_size()
+             + self.lut.numel() * 4)
+        if self.labels is not None:
+            n += self.labels.numel() + self.label_luts.numel() * 4
+        return n
 
 
 def workspace_bytes(w: int, h: int, p: SbParams) -> int:
@@ -221,14 +248,16 @@ def workspace_bytes(w: int, h: int, p: SbParams) -> int:
 
 
 def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chunk=None,
-            want_nnf: bool = False, workspace=None, stream=None, tune=None, events=None):
+            want_nnf: bool = False, workspace=None, stream=None, tune=None, events=None,
+            tgt_labels=None):
     """Stylise one frame.  ``tgt_guide`` (H, W, 2) and ``jitter`` (uint32 as
     int32 bits) may be numpy arrays or device tensors.  Returns
     ``(rgb (H,W,3) uint8, chunk (H,W) int32-bits[, nnf])`` as device tensors;
     the work is enqueued on the current stream.  ``tune`` is a
     (blend_ppt, blend_rows, level_group, level_ppt) choice (None = defaults); with
     ``events`` (a TimingEvents) the passes are bracketed by its events
-    (sb_stylize_timed)."""
+    (sb_stylize_timed).  With ``tgt_labels`` (uint8 (H, W)) the frame runs
+    with the segmentation guide (sb_stylize_seg; the style must carry labels)."""
     torch = _torch()
     g = tgt_guide
     if not isinstance(g, torch.Tensor) and str(getattr(g, "dtype", "")) == "uint16":
@@ -265,7 +294,17 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     tn = tune_struct(tune)
     tp = ctypes.byref(tn) if tn is not None else None
     nnf_p = nnf.data_ptr() if nnf is not None else None
-    if events is not None:
+    if tgt_labels is not None:
+        if events is not None:
+            raise ValueError("timed runs take no label maps")
+        lt = _dev(torch, tgt_labels, torch.uint8)
+        if tuple(lt.shape) != (h, w):
+            raise ValueError("target label map and guide sizes differ")
+        _check(lib().sb_stylize_seg(ctypes.byref(style.c), g.data_ptr(), lt.data_ptr(), w, h,
+                                    j.data_ptr(), ctypes.byref(p), out_rgb.data_ptr(),
+                                    out_chunk.data_ptr(), nnf_p, workspace.data_ptr(), wsb, tp, s),
+               "sb_stylize_seg")
+    elif events is not None:
         _check(lib().sb_stylize_timed(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
                                       ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
                                       nnf_p, workspace.data_ptr(), wsb, tp, events.handles, s),
@@ -318,7 +357,7 @@ class FrameJob:
     outputs (allocated here when not given)."""
 
     def __init__(self, style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chunk=None,
-                 out_nnf=None):
+                 out_nnf=None, tgt_labels=None):
         torch = _torch()
         g = tgt_guide
         if not isinstance(g, torch.Tensor) and str(getattr(g, "dtype", "")) == "uint16":
@@ -346,12 +385,14 @@ class FrameJob:
         self.out_chunk = out_chunk if out_chunk is not None else torch.empty(
             (self.h, self.w), dtype=torch.int32, device="cuda")
         self.out_nnf = out_nnf
+        self.tgt_labels = None if tgt_labels is None else _dev(torch, tgt_labels, torch.uint8)
 
     def c(self) -> SbFrame:
         return SbFrame(ctypes.pointer(self.style.c), self.guide.data_ptr(), self.jitter.data_ptr(),
                        self.w, self.h, self.params, self.out_rgb.data_ptr(),
                        self.out_chunk.data_ptr(),
-                       self.out_nnf.data_ptr() if self.out_nnf is not None else None)
+                       self.out_nnf.data_ptr() if self.out_nnf is not None else None,
+                       self.tgt_labels.data_ptr() if self.tgt_labels is not None else None)
 
 
 class Batch:

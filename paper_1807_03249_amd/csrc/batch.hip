@@ -120,7 +120,7 @@ int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace
   for (int32_t f = 0; f < n; ++f) {
     const sb_frame &fr = frames[f];
     if (!fill_frame(fr.style, fr.tgt_guide, fr.w, fr.h, fr.jitter, &fr.params, fr.out_rgb,
-                    fr.out_chunk, fr.out_nnf, &args[f]))
+                    fr.out_chunk, fr.out_nnf, &args[f], fr.tgt_labels))
       return SB_EINVAL;
     carve_workspace(&args[f], ws);
     ws += align256(sb_workspace_bytes(fr.w, fr.h, &fr.params));

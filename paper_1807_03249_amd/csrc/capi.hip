@@ -25,6 +25,8 @@ bool style_ok(const sb_style *s) {
   if (!s || !s->rgba || !s->guide || !s->lut) return false;
   if (!side_ok(s->sw) || !side_ok(s->sh)) return false;
   if (s->fmt != SB_GUIDE_U8X2 && s->fmt != SB_GUIDE_U16X2) return false;
+  if (s->nlabels < 0 || s->nlabels > SB_MAX_LABELS) return false;
+  if (s->nlabels > 0 && (!s->labels || !s->label_luts)) return false;
   const int32_t depth = s->fmt == SB_GUIDE_U8X2 ? 8 : 16;
   return s->lut_bits >= 1 && s->lut_bits <= depth && s->lut_bits <= SB_MAX_LUT_BITS;
 }
@@ -69,8 +71,10 @@ bool make_levels(int32_t w, int32_t h, int32_t levels, int32_t finest, Levels *o
 
 bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
                 const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
-                uint32_t *out_chunk, uint32_t *out_nnf, FrameArgs *a) {
+                uint32_t *out_chunk, uint32_t *out_nnf, FrameArgs *a,
+                const uint8_t *tgt_labels) {
   if (!style_ok(style) || !tgt_guide || !out_rgb || !out_chunk) return false;
+  if (tgt_labels && style->nlabels < 1) return false;  // labels on one side only
   if (!side_ok(w) || !side_ok(h) || !params_ok(params)) return false;
   if (params->levels > 0 && !jitter) return false;
   memset(a, 0, sizeof *a);
@@ -94,6 +98,12 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
   a->fmt = style->fmt;
   a->ex_stride = ex_stride(style->sw);
   a->ex_zero = uint32_t(ex_stride(style->sw)) * uint32_t(style->sh + 2 * kExMargin);
+  if (tgt_labels) {
+    a->src_labels = style->labels;
+    a->tgt_labels = tgt_labels;
+    a->label_luts = style->label_luts;
+    a->nlabels = style->nlabels;
+  }
   return true;
 }
 
@@ -192,6 +202,24 @@ int sb_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t
   return SB_OK;
 }
 
+int sb_lut_build_labels(const void *guide, const uint8_t *labels, int32_t fmt, int32_t sw,
+                        int32_t sh, int32_t lut_bits, int32_t nlabels, const uint32_t *lut,
+                        uint32_t *luts, void *workspace, size_t workspace_bytes,
+                        hipStream_t stream) {
+  if (!guide || !labels || !lut || !luts || !workspace) return SB_EINVAL;
+  if (nlabels < 1 || nlabels > SB_MAX_LABELS) return SB_EINVAL;
+  const size_t need = sb_lut_workspace_bytes(fmt, sw, sh, lut_bits);
+  if (need == 0) return SB_EINVAL;
+  if (workspace_bytes < need) return SB_ENOMEM;
+  const hipError_t e = launch_lut_build_labels(guide, labels, fmt, sw, sh, lut_bits, nlabels, lut,
+                                               luts, workspace, stream);
+  if (e != hipSuccess) {
+    set_hip_error(e, "sb_lut_build_labels");
+    return SB_EHIP;
+  }
+  return SB_OK;
+}
+
 size_t sb_workspace_bytes(int32_t w, int32_t h, const sb_params *params) {
   if (!side_ok(w) || !side_ok(h) || !params_ok(params)) return 0;
   Levels lv;
@@ -203,9 +231,11 @@ namespace {
 int stylize_impl(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
                  const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
                  uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
-                 const sb_tune *tune, hipEvent_t *events, hipStream_t stream) {
+                 const sb_tune *tune, hipEvent_t *events, hipStream_t stream,
+                 const uint8_t *tgt_labels = nullptr) {
   FrameArgs a;
-  if (!fill_frame(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf, &a))
+  if (!fill_frame(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf, &a,
+                  tgt_labels))
     return SB_EINVAL;
   Tune t;
   if (!resolve_tune(tune, &t)) return SB_EINVAL;
@@ -227,6 +257,15 @@ int sb_stylize_ex(const sb_style *style, const void *tgt_guide, int32_t w, int32
                   size_t workspace_bytes, const sb_tune *tune, hipStream_t stream) {
   return stylize_impl(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf,
                       workspace, workspace_bytes, tune, nullptr, stream);
+}
+
+int sb_stylize_seg(const sb_style *style, const void *tgt_guide, const uint8_t *tgt_labels,
+                   int32_t w, int32_t h, const uint32_t *jitter, const sb_params *params,
+                   uint8_t *out_rgb, uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
+                   size_t workspace_bytes, const sb_tune *tune, hipStream_t stream) {
+  if (!tgt_labels) return SB_EINVAL;
+  return stylize_impl(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf,
+                      workspace, workspace_bytes, tune, nullptr, stream, tgt_labels);
 }
 
 int sb_stylize_timed(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,

@@ -74,11 +74,14 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
+// Counting sort over the source pixels; with `labels`, only the pixels
+// labelled `want` (one per-label table of the segmentation guide).
 template <int FMT>
 __global__ void k_lut_count(const void *guide, int32_t npix, int32_t shift, int32_t bb,
-                            uint32_t *count) {
+                            uint32_t *count, const uint8_t *labels, int32_t want) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= uint32_t(npix)) return;
+  if (labels && labels[i] != want) return;
   uint32_t c0, c1;
   read_guide<FMT>(guide, i, c0, c1);
   atomicAdd(&count[((c1 >> shift) << bb) | (c0 >> shift)], 1u);
@@ -115,21 +118,28 @@ __global__ void __launch_bounds__(1024) k_lut_scan(uint32_t *count, uint32_t *st
 
 template <int FMT>
 __global__ void k_lut_scatter(const void *guide, int32_t npix, int32_t shift, int32_t bb,
-                              uint32_t *cursor, uint2 *pts) {
+                              uint32_t *cursor, uint2 *pts, const uint8_t *labels, int32_t want) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= uint32_t(npix)) return;
+  if (labels && labels[i] != want) return;
   uint32_t c0, c1;
   read_guide<FMT>(guide, i, c0, c1);
   uint32_t pos = atomicAdd(&cursor[((c1 >> shift) << bb) | (c0 >> shift)], 1u);
   pts[pos] = make_uint2(c0 | (c1 << 16), i);
 }
 
+// `fallback` (may be null): when no pixel was bucketed (a label absent from
+// the exemplar), copy this table instead.
 __global__ void k_lut_query(const uint32_t *start, const uint2 *pts, int32_t lut_bits,
                             int32_t bin_shift, int32_t bucket_bits, int32_t bucket_shift,
-                            int32_t sw, uint32_t *lut) {
+                            int32_t sw, uint32_t *lut, const uint32_t *fallback) {
   const uint32_t nbins = 1u << (2 * lut_bits);
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nbins) return;
+  if (fallback && start[1u << (2 * bucket_bits)] == 0) {
+    lut[c] = fallback[c];
+    return;
+  }
   const uint32_t half = bin_shift ? (1u << (bin_shift - 1)) : 0u;
   const uint32_t qx = ((c & ((1u << lut_bits) - 1)) << bin_shift) + half;
   const uint32_t qy = ((c >> lut_bits) << bin_shift) + half;
@@ -183,8 +193,11 @@ size_t lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits
   return align256(nb * 4) + align256((nb + 1) * 4) + align256(size_t(g.npix) * 8);
 }
 
-hipError_t launch_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh,
-                            int32_t lut_bits, uint32_t *lut, void *workspace, hipStream_t stream) {
+namespace {
+// One table: over all source pixels (labels null) or those labelled `want`.
+hipError_t build_one(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
+                     uint32_t *lut, void *workspace, const uint8_t *labels, int32_t want,
+                     const uint32_t *fallback, hipStream_t stream) {
   const LutGeom g = lut_geom(fmt, sw, sh, lut_bits);
   const LutWs w = lut_ws(workspace, g);
   const uint32_t nb = 1u << (2 * g.bucket_bits);
@@ -193,23 +206,42 @@ hipError_t launch_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t 
       w.count, nb, 0u);
   if (fmt == SB_GUIDE_U8X2) {
     k_lut_count<SB_GUIDE_U8X2><<<blocks_for(g.npix, 256), 256, 0, stream>>>(
-        guide, g.npix, shift, g.bucket_bits, w.count);
+        guide, g.npix, shift, g.bucket_bits, w.count, labels, want);
   } else {
     k_lut_count<SB_GUIDE_U16X2><<<blocks_for(g.npix, 256), 256, 0, stream>>>(
-        guide, g.npix, shift, g.bucket_bits, w.count);
+        guide, g.npix, shift, g.bucket_bits, w.count, labels, want);
   }
   k_lut_scan<<<1, 1024, 0, stream>>>(w.count, w.start, nb);
   if (fmt == SB_GUIDE_U8X2) {
     k_lut_scatter<SB_GUIDE_U8X2><<<blocks_for(g.npix, 256), 256, 0, stream>>>(
-        guide, g.npix, shift, g.bucket_bits, w.count, w.pts);
+        guide, g.npix, shift, g.bucket_bits, w.count, w.pts, labels, want);
   } else {
     k_lut_scatter<SB_GUIDE_U16X2><<<blocks_for(g.npix, 256), 256, 0, stream>>>(
-        guide, g.npix, shift, g.bucket_bits, w.count, w.pts);
+        guide, g.npix, shift, g.bucket_bits, w.count, w.pts, labels, want);
   }
   const uint64_t nbins = uint64_t(1) << (2 * lut_bits);
   k_lut_query<<<blocks_for(nbins, 256), 256, 0, stream>>>(
-      w.start, w.pts, lut_bits, g.depth - lut_bits, g.bucket_bits, shift, sw, lut);
+      w.start, w.pts, lut_bits, g.depth - lut_bits, g.bucket_bits, shift, sw, lut, fallback);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh,
+                            int32_t lut_bits, uint32_t *lut, void *workspace, hipStream_t stream) {
+  return build_one(guide, fmt, sw, sh, lut_bits, lut, workspace, nullptr, 0, nullptr, stream);
+}
+
+hipError_t launch_lut_build_labels(const void *guide, const uint8_t *labels, int32_t fmt,
+                                   int32_t sw, int32_t sh, int32_t lut_bits, int32_t nlabels,
+                                   const uint32_t *lut, uint32_t *luts, void *workspace,
+                                   hipStream_t stream) {
+  const size_t bins = size_t(1) << (2 * lut_bits);
+  for (int32_t l = 0; l < nlabels; ++l) {
+    const hipError_t e = build_one(guide, fmt, sw, sh, lut_bits, luts + size_t(l) * bins,
+                                   workspace, labels, l, lut, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace sb

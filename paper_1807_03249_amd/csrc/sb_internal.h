@@ -76,6 +76,11 @@ struct FrameArgs {
   int32_t fmt;                 // sb_guide_fmt (read by the batch kernels)
   int32_t ex_stride;           // texels per padded exemplar row
   uint32_t ex_zero;            // first texel of the padded exemplar's zero rows
+  // segmentation guide: all null / 0 without it
+  const uint8_t *src_labels;   // Sw*Sh
+  const uint8_t *tgt_labels;   // W*H
+  const uint32_t *label_luts;  // nlabels tables of (1 << lut_bits)^2 entries
+  int32_t nlabels;
   Levels lv;
 };
 
@@ -105,7 +110,8 @@ bool make_levels(int32_t w, int32_t h, int32_t levels, int32_t finest, Levels *o
 // pointers are left null).  False on any invalid argument.
 bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
                 const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
-                uint32_t *out_chunk, uint32_t *out_nnf, FrameArgs *a);
+                uint32_t *out_chunk, uint32_t *out_nnf, FrameArgs *a,
+                const uint8_t *tgt_labels = nullptr);
 // Point a frame's seed table and offset map into a workspace of at least
 // sb_workspace_bytes() bytes.
 void carve_workspace(FrameArgs *a, void *workspace);
@@ -130,6 +136,10 @@ hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, const Tune
 size_t lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits);
 hipError_t launch_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh,
                             int32_t lut_bits, uint32_t *lut, void *workspace, hipStream_t stream);
+hipError_t launch_lut_build_labels(const void *guide, const uint8_t *labels, int32_t fmt,
+                                   int32_t sw, int32_t sh, int32_t lut_bits, int32_t nlabels,
+                                   const uint32_t *lut, uint32_t *luts, void *workspace,
+                                   hipStream_t stream);
 
 __host__ __device__ inline uint32_t pack_xy(uint32_t x, uint32_t y) { return x | (y << 16); }
 

@@ -193,6 +193,7 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
                                 : reinterpret_cast<uint32_t *>(
                                       base + ((size_t(r.w) * r.h * 3 + 255) & ~size_t(255)));
       f.out_nnf = nullptr;
+      f.tgt_labels = nullptr;
       res[i].admitted_s = now_s(t0);
       admitted.push_back(i);
       pending.pop_front();

@@ -7,8 +7,9 @@
 //             out-of-image seeds hold the empty record.
 //   k_assign  the level loop of Algorithm 2 per pixel: NearestSeed over the
 //             3x3 cells, the exact integer guide error at u* + (p - q)
-//             against the threshold, and the own-lookup fallback.  Writes the
-//             chunk code and the offset NNF[p] - p.
+//             against the threshold (with the segmentation guide, also the
+//             label test), and the own-lookup fallback.  Writes the chunk
+//             code and the offset NNF[p] - p.
 //   k_blend   the voting step (end of Sec. 3.2): a tile of offsets with an
 //             r-pixel halo in LDS; each lane averages the (2r+1)^2 votes of
 //             four adjacent pixels, one vector gather per (cell, pixel run).
@@ -99,6 +100,15 @@ __global__ void k_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint
   rgba[i] = t;
 }
 
+// The lookup table a target pixel uses: the unconstrained one, or with the
+// segmentation guide the table of the pixel's label (past the last label:
+// the last table).
+__device__ inline const uint32_t *lut_of(const FrameArgs &a, uint32_t pidx) {
+  if (!a.tgt_labels) return a.lut;
+  const uint32_t l = min(uint32_t(glb(a.tgt_labels)[pidx]), uint32_t(a.nlabels - 1));
+  return a.label_luts + (size_t(l) << (2 * a.lut_bits));
+}
+
 // Record idx of the padded seed table.
 template <int FMT>
 __device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
@@ -116,7 +126,7 @@ __device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
     const uint32_t sy = (uint32_t(cy) << lv.log2_spacing[i]) + (j >> 16);
     if (sx < uint32_t(a.w) && sy < uint32_t(a.h)) {
       const uint32_t g = guide_word<FMT>(a.tgt_guide, sy * uint32_t(a.w) + sx);
-      const uint32_t u = glb(a.lut)[lut_bin(g, a.lut_shift, a.lut_bits)];
+      const uint32_t u = glb(lut_of(a, sy * uint32_t(a.w) + sx))[lut_bin(g, a.lut_shift, a.lut_bits)];
       rec.x = pack_xy(4 * sx, 4 * sy);
       rec.y = pack_off(int32_t(u & 0xFFFFu) - int32_t(sx), int32_t(u >> 16) - int32_t(sy));
     }
@@ -155,11 +165,12 @@ constexpr int32_t kWaveRecs = SB_MAX_LEVELS * kRecStride;
 // in flight together, then the tests in level order.  Straight-line code
 // (levels past L rescan level L-1 and are never taken), so the gathers issue
 // back to back.
-template <int FMT, int N, int B>
+template <int FMT, int N, int B, bool SEG>
 __device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *lpos,
                                             const uint32_t *loff, int32_t i0, const int32_t *x,
                                             int32_t y, const short2_t *p4, const uint32_t *gt,
-                                            uint32_t *chunk, uint32_t *off, bool *done) {
+                                            const uint32_t *lt, uint32_t *chunk, uint32_t *off,
+                                            bool *done) {
   const int32_t L = a.lv.count;
   const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
   uint32_t g[B][N], wq[B][N], wo[B][N];
@@ -190,17 +201,23 @@ __device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *
       g[b][u] = ok[b][u] ? uint32_t(vy) * sw + uint32_t(vx) : 0u;
     }
   }
+  uint32_t ls[B][N];
 #pragma unroll
   for (int32_t b = 0; b < B; ++b) {
 #pragma unroll
-    for (int32_t u = 0; u < N; ++u) g[b][u] = guide_raw<FMT>(a.src_guide, g[b][u]);
+    for (int32_t u = 0; u < N; ++u) {
+      // with the segmentation guide the source label is gathered beside the guide
+      ls[b][u] = SEG ? uint32_t(glb(a.src_labels)[g[b][u]]) : 0u;
+      g[b][u] = guide_raw<FMT>(a.src_guide, g[b][u]);
+    }
   }
 #pragma unroll
   for (int32_t b = 0; b < B; ++b) {
 #pragma unroll
     for (int32_t u = 0; u < N; ++u) {
       const bool below = error_below<FMT>(gt[b], guide_unpack<FMT>(g[b][u]), a.threshold);
-      const bool take = (!done[b]) & ok[b][u] & below;
+      const bool same = !SEG || ls[b][u] == lt[b];
+      const bool take = (!done[b]) & ok[b][u] & below & same;
       chunk[b] = take ? chunk_code(i0 + u, wq[b][u]) : chunk[b];
       off[b] = take ? wo[b][u] : off[b];
       done[b] = done[b] || take;
@@ -215,7 +232,7 @@ __device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *
 // target guide, the records and the pixels' own lookups (their fallback) are
 // all requested up front, so the chain of dependent memory round trips is
 // guide -> lookup and records -> source guide, side by side.
-template <int FMT, int G, int B>
+template <int FMT, int G, int B, bool SEG>
 __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0, int32_t lane,
                                     uint32_t *lpos, uint32_t *loff) {
   const Levels &lv = a.lv;
@@ -223,13 +240,14 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
   const int32_t y = by0 + (lane >> 3);
   int32_t x[B];
   bool in[B];
-  uint32_t pidx[B], gt[B];
+  uint32_t pidx[B], gt[B], lt[B];
 #pragma unroll
   for (int32_t b = 0; b < B; ++b) {
     x[b] = bx0 + 8 * b + (lane & 7);
     in[b] = x[b] < a.w && y < a.h;
     pidx[b] = in[b] ? uint32_t(y) * uint32_t(a.w) + uint32_t(x[b]) : 0u;
     gt[b] = guide_word<FMT>(a.tgt_guide, pidx[b]);
+    lt[b] = SEG ? uint32_t(glb(a.tgt_labels)[pidx[b]]) : 0u;
   }
   // record j of block b (level j / 9, neighbour j % 9) for lanes j and j + 64;
   // a block past the frame's right edge stages the last column's cells (its
@@ -282,7 +300,10 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
   bool done[B];
 #pragma unroll
   for (int32_t b = 0; b < B; ++b) {
-    own[b] = glb(a.lut)[lut_bin(gt[b], a.lut_shift, a.lut_bits)];
+    const uint32_t *table =
+        SEG ? a.label_luts + (size_t(min(lt[b], uint32_t(a.nlabels - 1))) << (2 * a.lut_bits))
+            : a.lut;
+    own[b] = glb(table)[lut_bin(gt[b], a.lut_shift, a.lut_bits)];
     p4[b] = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x[b]), uint32_t(4 * y)));
     chunk[b] = off[b] = 0;
     done[b] = !in[b];
@@ -294,7 +315,7 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
 #pragma unroll
     for (int32_t b = 0; b < B; ++b) all = all && done[b];
     if (__all(all)) break;
-    level_group<FMT, G, B>(a, lpos, loff, i0, x, y, p4, gt, chunk, off, done);
+    level_group<FMT, G, B, SEG>(a, lpos, loff, i0, x, y, p4, gt, lt, chunk, off, done);
   }
 #pragma unroll
   for (int32_t b = 0; b < B; ++b) {
@@ -313,7 +334,7 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
 
 // The level loop for one pixel when cells are smaller than 8 x 8 blocks:
 // each lane reads its own nine records per level.
-template <int FMT>
+template <int FMT, bool SEG>
 __device__ inline void assign_pixel(const FrameArgs &a, int32_t x, int32_t y) {
   if (x >= a.w || y >= a.h) return;
   const Levels &lv = a.lv;
@@ -335,7 +356,9 @@ __device__ inline void assign_pixel(const FrameArgs &a, int32_t x, int32_t y) {
     const u32x2 w = top[(k - 3 * kx) * pc + kx];
     const int32_t vx = x + off_x(w.y), vy = y + off_y(w.y);
     if (uint32_t(vx) >= sw || uint32_t(vy) >= sh) continue;
-    const uint32_t g = guide_word<FMT>(a.src_guide, uint32_t(vy) * sw + uint32_t(vx));
+    const uint32_t vidx = uint32_t(vy) * sw + uint32_t(vx);
+    if (SEG && glb(a.src_labels)[vidx] != glb(a.tgt_labels)[pidx]) continue;
+    const uint32_t g = guide_word<FMT>(a.src_guide, vidx);
     if (error_below<FMT>(gt, g, a.threshold)) {
       chunk = chunk_code(i, w.x);
       off = w.y;
@@ -343,7 +366,7 @@ __device__ inline void assign_pixel(const FrameArgs &a, int32_t x, int32_t y) {
     }
   }
   if (!done) {
-    const uint32_t u = glb(a.lut)[lut_bin(gt, a.lut_shift, a.lut_bits)];
+    const uint32_t u = glb(lut_of(a, pidx))[lut_bin(gt, a.lut_shift, a.lut_bits)];
     chunk = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
     off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
   }
@@ -360,7 +383,7 @@ __device__ inline bool uniform_cells(const Levels &lv) {
 // One (16 B) x 16 tile: four groups of B 8 x 8 blocks, one group per wave, on
 // the uniform-cell path; otherwise B pixels per thread.  `recs` is LDS for 4
 // waves' records (2 B kWaveRecs words each).
-template <int FMT, int G, int B>
+template <int FMT, int G, int B, bool SEG>
 __device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t tid,
                                    uint32_t *recs) {
   const uint32_t tw = 16 * B;
@@ -372,18 +395,18 @@ __device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t t
     // a block group wholly outside the frame has no cells in the table
     if (bx0 >= a.w || by0 >= a.h) return;
     uint32_t *lpos = recs + wave * 2 * B * kWaveRecs;
-    assign_block<FMT, G, B>(a, bx0, by0, int32_t(tid & 63), lpos, lpos + B * kWaveRecs);
+    assign_block<FMT, G, B, SEG>(a, bx0, by0, int32_t(tid & 63), lpos, lpos + B * kWaveRecs);
   } else {
 #pragma unroll
     for (int32_t b = 0; b < B; ++b)
-      assign_pixel<FMT>(a, tx0 + 16 * b + int32_t(tid & 15), ty0 + int32_t(tid >> 4));
+      assign_pixel<FMT, SEG>(a, tx0 + 16 * b + int32_t(tid & 15), ty0 + int32_t(tid >> 4));
   }
 }
 
-template <int FMT, int G, int B>
+template <int FMT, int G, int B, bool SEG>
 __global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
   __shared__ __attribute__((aligned(16))) uint32_t recs[4 * 2 * B * kWaveRecs];
-  assign_tile<FMT, G, B>(a, blockIdx.x, threadIdx.x, recs);
+  assign_tile<FMT, G, B, SEG>(a, blockIdx.x, threadIdx.x, recs);
 }
 
 // Exact n / k for n < 2^20 and 1 <= k <= 225 via a float reciprocal and one
@@ -648,8 +671,14 @@ template <int G, int B>
 __global__ void __launch_bounds__(256) k_batch_assign(const unsigned char *desc) {
   batch_loop<1, 256, 4 * 2 * B * kWaveRecs>(desc, [](const FrameArgs &fa, uint32_t local,
                                                      uint32_t *w) {
-    if (fa.fmt == SB_GUIDE_U8X2) assign_tile<SB_GUIDE_U8X2, G, B>(fa, local, threadIdx.x, w);
-    else assign_tile<SB_GUIDE_U16X2, G, B>(fa, local, threadIdx.x, w);
+    const bool seg = fa.tgt_labels != nullptr;
+    if (fa.fmt == SB_GUIDE_U8X2) {
+      if (seg) assign_tile<SB_GUIDE_U8X2, G, B, true>(fa, local, threadIdx.x, w);
+      else assign_tile<SB_GUIDE_U8X2, G, B, false>(fa, local, threadIdx.x, w);
+    } else {
+      if (seg) assign_tile<SB_GUIDE_U16X2, G, B, true>(fa, local, threadIdx.x, w);
+      else assign_tile<SB_GUIDE_U16X2, G, B, false>(fa, local, threadIdx.x, w);
+    }
   });
 }
 
@@ -666,7 +695,8 @@ unsigned blocks_for(uint64_t n, unsigned bs) { return unsigned((n + bs - 1) / bs
 
 template <int FMT, int G, int B>
 void launch_assign(const FrameArgs &a, uint32_t blocks, hipStream_t stream) {
-  k_assign<FMT, G, B><<<blocks, 256, 0, stream>>>(a);
+  if (a.tgt_labels) k_assign<FMT, G, B, true><<<blocks, 256, 0, stream>>>(a);
+  else k_assign<FMT, G, B, false><<<blocks, 256, 0, stream>>>(a);
 }
 
 template <int FMT>

@@ -148,3 +148,33 @@ def test_exemplar_layout(L):
         assert (rows - sh - 16) * P >= 15 * P + 64
     assert L.sb_exemplar_texels(0, 5) == 0
     assert L.sb_exemplar_texels(5, 8193) == 0
+
+
+def test_segmentation_validation(L):
+    """Label maps on one side only, bad label counts and missing tables are
+    refused on the host."""
+    import paper_1807_03249_amd as sb
+
+    fake = 0x1000
+    p = sb.params(4, 8, 32, 3)
+    ws = sb.workspace_bytes(64, 64, p)
+
+    def seg(style, labels=fake):
+        return L.sb_stylize_seg(ctypes.byref(style), fake, labels, 64, 64, fake, ctypes.byref(p),
+                                fake, fake, None, fake, ws, None, None)
+
+    plain = sb.SbStyle(fake, fake, fake, 512, 512, 0, 8)
+    labelled = sb.SbStyle(fake, fake, fake, 512, 512, 0, 8, fake, fake, 3)
+    assert seg(plain) == sb.SB_EINVAL                       # style without labels
+    assert seg(labelled, labels=None) == sb.SB_EINVAL       # frame without labels
+    assert seg(sb.SbStyle(fake, fake, fake, 512, 512, 0, 8, None, fake, 3)) == sb.SB_EINVAL
+    assert seg(sb.SbStyle(fake, fake, fake, 512, 512, 0, 8, fake, None, 3)) == sb.SB_EINVAL
+    assert seg(sb.SbStyle(fake, fake, fake, 512, 512, 0, 8, fake, fake, 257)) == sb.SB_EINVAL
+    assert seg(sb.SbStyle(fake, fake, fake, 512, 512, 0, 8, fake, fake, -1)) == sb.SB_EINVAL
+    wsl = L.sb_lut_workspace_bytes(0, 512, 512, 8)
+    assert L.sb_lut_build_labels(fake, fake, 0, 512, 512, 8, 0, fake, fake, fake, wsl,
+                                 None) == sb.SB_EINVAL
+    assert L.sb_lut_build_labels(fake, None, 0, 512, 512, 8, 2, fake, fake, fake, wsl,
+                                 None) == sb.SB_EINVAL
+    assert L.sb_lut_build_labels(fake, fake, 0, 512, 512, 8, 2, fake, fake, fake, wsl - 1,
+                                 None) == sb.SB_ENOMEM
