@@ -17,7 +17,13 @@ accepted pixel has error below the threshold).  The segmentation-guide
 variant (per-label tables, the label constraint in the level loop) is pinned
 by its reduction to the plain path with one label, brute-force per-label
 tables, a hand-worked case and its label invariants
-(``tests/test_oracle_seg.py``).
+(``tests/test_oracle_seg.py``).  The animation extension (Sec. 3.3) adds
+no arithmetic of its own: a sequence is frames of the plain path with a
+per-frame jitter table, and ``frame_change`` counts the pixels that changed
+between two of them; ``tests/test_oracle_animation.py`` pins the paper's
+statements about it (seeds that do not move leave a static target
+unchanged, threshold 0 makes the result independent of the seeds, a larger
+threshold changes more pixels) and checks the counts by brute force.
 """
 from __future__ import annotations
 
@@ -247,3 +253,21 @@ def decode_chunk(chunk: np.ndarray):
     """(level, qx, qy) arrays from chunk codes (level << 26 | qy << 13 | qx)."""
     c = np.asarray(chunk, dtype=np.uint32)
     return (c >> 26).astype(np.int64), (c & 0x1FFF).astype(np.int64), ((c >> 13) & 0x1FFF).astype(np.int64)
+
+
+def frame_change(chunk_a, chunk_b, nnf_a=None, nnf_b=None) -> Tuple[int, int]:
+    """Frame-to-frame change of an animation (Sec. 3.3, extension to
+    animation): (pixels whose chunk code differs, pixels whose source
+    coordinate differs; 0 without NNF maps).  The definition, written out."""
+    a = np.asarray(chunk_a).view(np.uint32).ravel()
+    b = np.asarray(chunk_b).view(np.uint32).ravel()
+    if a.shape != b.shape:
+        raise ValueError("frames differ in size")
+    code = int(np.count_nonzero(a != b))
+    if nnf_a is None:
+        return code, 0
+    na = np.asarray(nnf_a).view(np.uint32).ravel()
+    nb = np.asarray(nnf_b).view(np.uint32).ravel()
+    if na.shape != a.shape or nb.shape != a.shape:
+        raise ValueError("frames differ in size")
+    return code, int(np.count_nonzero(na != nb))

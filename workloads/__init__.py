@@ -21,6 +21,8 @@ from .gen import (  # noqa: F401
     identity_uv_guide_u16,
     warped_uv_guide_u16,
     voronoi_labels,
+    animated_bump_guides,
+    jitter_schedule,
     config,
     CONFIG_NAMES,
 )

@@ -192,6 +192,48 @@ def bump_guide_u8(w: int, h: int, nbumps: int, seed: int) -> np.ndarray:
     return _encode_normal(-gx / norm, -gy / norm)
 
 
+def animated_bump_guides(w: int, h: int, nbumps: int, nframes: int, drift: float,
+                         seed: int) -> List[np.ndarray]:
+    """An animated target: the heightfield of bump_guide_u8 with every bump
+    centre moving by up to ``drift`` pixels per frame in its own seeded
+    direction; one normal guide per frame."""
+    rng = np.random.default_rng(seed)
+    m = float(min(w, h))
+    bumps = []
+    for _ in range(nbumps):
+        cx, cy = rng.uniform(0, w), rng.uniform(0, h)
+        sig = rng.uniform(0.03, 0.12) * m
+        amp = rng.uniform(0.5, 1.5) * sig * (1.0 if rng.random() < 0.5 else -1.0)
+        ang = rng.uniform(0, 2 * np.pi)
+        spd = rng.uniform(0.5, 1.0) * drift
+        bumps.append((cx, cy, sig, amp, spd * np.cos(ang), spd * np.sin(ang)))
+    out = []
+    for f in range(nframes):
+        hf = np.zeros((h, w))
+        for cx0, cy0, sig, amp, vx, vy in bumps:
+            cx, cy = cx0 + vx * f, cy0 + vy * f
+            rad = 5.0 * sig
+            x0, x1 = max(0, int(cx - rad)), min(w, int(cx + rad) + 1)
+            y0, y1 = max(0, int(cy - rad)), min(h, int(cy + rad) + 1)
+            if x0 >= x1 or y0 >= y1:
+                continue
+            xs = np.arange(x0, x1) + 0.5 - cx
+            ys = np.arange(y0, y1) + 0.5 - cy
+            hf[y0:y1, x0:x1] += amp * np.exp(-(ys[:, None] ** 2 + xs[None, :] ** 2) / (2 * sig * sig))
+        gy, gx = np.gradient(hf)
+        norm = np.sqrt(gx * gx + gy * gy + 1.0)
+        out.append(_encode_normal(-gx / norm, -gy / norm))
+    return out
+
+
+def jitter_schedule(w: int, h: int, levels: int, finest: int, nframes: int, hold: int,
+                    seed: int) -> List[np.ndarray]:
+    """Per-frame jitter tables for an animation: a fresh table every ``hold``
+    frames (hold = 1: seeds re-drawn every frame, the flickering
+    hand-coloured look; hold >= nframes: one table for the whole sequence)."""
+    return [jitter_table(w, h, levels, finest, seed + f // max(1, hold)) for f in range(nframes)]
+
+
 def identity_uv_guide_u16(sw: int, sh: int) -> np.ndarray:
     """Texture coordinates of each texel centre, scaled to 16 bits."""
     gx = np.floor((np.arange(sw) + 0.5) * 65536.0 / sw).astype(np.int64)
