@@ -219,6 +219,29 @@ int sb_timing_events_destroy(hipEvent_t events[4]);
 /* Milliseconds between two completed events (hipEventElapsedTime). */
 int sb_event_elapsed_ms(hipEvent_t start, hipEvent_t stop, float *ms);
 
+/* ------------------------------------------------------------- animation */
+
+/* Frame-to-frame change of an animated sequence (Sec. 3.3, extension to
+ * animation: seeds re-drawn per frame perturb the mosaic, and a larger
+ * threshold t gives larger chunks and more change).  Counts, over n pixels
+ * of two frames of the same size:
+ *   counts[0]  pixels whose chunk code differs (chunk_a[i] != chunk_b[i]),
+ *   counts[1]  pixels whose source coordinate differs (nnf_a[i] != nnf_b[i]);
+ *              0 when nnf_a and nnf_b are both NULL.
+ * chunk_a, chunk_b, nnf_a, nnf_b [device] n entries each, as written by
+ *   sb_stylize (out_chunk, out_nnf); any alignment (16-byte aligned maps are
+ *   read as vectors).
+ * counts     [device, 8-byte aligned] 2 entries, written on `stream`.
+ * workspace  [device, 8-byte aligned] at least sb_change_workspace_bytes().
+ * n = 0 writes two zeros (the maps may then be NULL).  Returns SB_EINVAL
+ * (null maps, only one NNF map, n < 0 or n > 2^40, misaligned
+ * counts/workspace) or SB_ENOMEM (workspace too small) before enqueuing
+ * anything. */
+size_t sb_change_workspace_bytes(void);
+int sb_frame_change(const uint32_t *chunk_a, const uint32_t *chunk_b, const uint32_t *nnf_a,
+                    const uint32_t *nnf_b, int64_t n, uint64_t *counts, void *workspace,
+                    size_t workspace_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- batches */
 
 /* One frame of a batch: the arguments of sb_stylize for that frame. */
@@ -302,6 +325,11 @@ typedef struct {
     uint8_t *out_rgb;           /* [device] or NULL: taken from the arena on admission and
                                    released at completion */
     uint32_t *out_chunk;        /* [device] or NULL (with out_rgb) */
+    uint32_t *out_nnf;          /* [device] or NULL: source coordinates, as in sb_stylize */
+    int32_t session;            /* >= 0: a frame of an animated sequence; frames of one
+                                   session complete in arrival order (a later frame's
+                                   kernels wait for the earlier frame's batch when it runs
+                                   on another slot).  < 0: independent request */
 } sb_request;
 
 typedef struct {
@@ -313,6 +341,7 @@ typedef struct {
 
 /* Run a request trace in real time on the calling thread: arrivals at their
  * times, admission in arrival order while the outputs fit in the arena,
+ * frames of one session completing in order,
  * continuous batching over `slots` streams (a free slot takes every admitted
  * request up to max_batch and runs them as one batch-plan replay, or, for a
  * single request, as one sb_stylize_ex on the slot's stream), completion by

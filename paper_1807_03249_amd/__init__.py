@@ -119,6 +119,8 @@ def lib():
                                   ctypes.POINTER(ctypes.c_void_p)]
     L.sb_batch_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(SbFrame), i32, vp, sz, vp]
     L.sb_batch_destroy.argtypes = [ctypes.c_void_p]
+    L.sb_change_workspace_bytes.restype = sz
+    L.sb_frame_change.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp, sz, vp]
     _lib = L
     return L
 
@@ -320,6 +322,33 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     if want_nnf:
         return out_rgb, out_chunk, nnf
     return out_rgb, out_chunk
+
+
+def frame_change(chunk_a, chunk_b, nnf_a=None, nnf_b=None, counts=None, workspace=None):
+    """Pixels that changed between two frames of a sequence (sb_frame_change):
+    a device int64 tensor [chunk codes that differ, source coordinates that
+    differ] (the second 0 without NNF maps), enqueued on the current stream."""
+    torch = _torch()
+    L = lib()
+    maps = [chunk_a, chunk_b] + ([nnf_a, nnf_b] if nnf_a is not None else [])
+    for m in maps:
+        if not isinstance(m, torch.Tensor) or not m.is_cuda or m.element_size() != 4 \
+                or not m.is_contiguous():
+            raise TypeError("change maps must be contiguous 32-bit device tensors")
+        if m.numel() != chunk_a.numel():
+            raise ValueError("change maps must have the same number of pixels")
+    if (nnf_a is None) != (nnf_b is None):
+        raise ValueError("give both NNF maps or neither")
+    if counts is None:
+        counts = torch.empty(2, dtype=torch.int64, device="cuda")
+    if workspace is None:
+        workspace = torch.empty(L.sb_change_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    _check(L.sb_frame_change(chunk_a.data_ptr(), chunk_b.data_ptr(),
+                             nnf_a.data_ptr() if nnf_a is not None else None,
+                             nnf_b.data_ptr() if nnf_b is not None else None, chunk_a.numel(),
+                             counts.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                             _stream(torch)), "sb_frame_change")
+    return counts
 
 
 class TimingEvents:

@@ -11,6 +11,10 @@
 //   4. gives every free slot (its own stream, batch plan and workspace) all
 //      admitted requests up to max_batch, launched as one graph replay (a
 //      single request takes the per-frame kernels on the slot's stream).
+//      When a request belongs to a session (the frames of one animation)
+//      whose previous frame still runs on another slot, the slot's stream
+//      first waits for that slot's batch, so a session's frames complete in
+//      order.
 // Requests that arrive while batches run are admitted as memory frees up and
 // start on the next free slot, so their work overlaps batches already on the
 // device.  The plain mode launches every request alone on one stream, in
@@ -81,7 +85,13 @@ struct Slot {
   sb_batch *plan = nullptr;
   void *workspace = nullptr;
   bool busy = false;
+  int32_t batch = -1;  // id of the batch in flight
   std::vector<int32_t> reqs;
+};
+
+// Where the latest launched frame of a session runs.
+struct SessionTail {
+  int32_t slot, batch;
 };
 
 }  // namespace
@@ -153,6 +163,7 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
   std::vector<size_t> aoff(static_cast<size_t>(n), 0);
   std::vector<sb_frame> fr(static_cast<size_t>(n));
   std::deque<int32_t> pending, admitted, plain_inflight;
+  std::map<int32_t, SessionTail> tails;  // session -> slot and batch of its latest frame
   int32_t next = 0, finished = 0, batch_id = 0, rc = SB_OK;
   const auto t0 = std::chrono::steady_clock::now();
   auto finish = [&](int32_t i, double t) {
@@ -192,7 +203,7 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
       f.out_chunk = r.out_chunk ? r.out_chunk
                                 : reinterpret_cast<uint32_t *>(
                                       base + ((size_t(r.w) * r.h * 3 + 255) & ~size_t(255)));
-      f.out_nnf = nullptr;
+      f.out_nnf = r.out_nnf;
       f.tgt_labels = nullptr;
       res[i].admitted_s = now_s(t0);
       admitted.push_back(i);
@@ -212,6 +223,10 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
         plain_inflight.pop_front();
       }
     } else {
+      // query every slot first, then retire them at one time stamp: a slot
+      // that waited for another completes after it, and the two must not be
+      // stamped in the opposite order
+      std::vector<Slot *> done;
       for (auto &s : sl) {
         if (!s.busy) continue;
         const hipError_t q = hipEventQuery(s.done);
@@ -220,10 +235,14 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
           e = q;
           break;
         }
-        const double tc = now_s(t0);
-        for (int32_t i : s.reqs) finish(i, tc);
-        s.reqs.clear();
-        s.busy = false;
+        done.push_back(&s);
+      }
+      const double tc = now_s(t0);
+      for (Slot *s : done) {
+        for (int32_t i : s->reqs) finish(i, tc);
+        s->reqs.clear();
+        s->busy = false;
+        s->batch = -1;
       }
     }
     // launch: continuous batching over free slots
@@ -232,7 +251,7 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
         const int32_t i = admitted.front();
         const sb_frame &f = fr[i];
         const int r = sb_stylize_ex(f.style, f.tgt_guide, f.w, f.h, f.jitter, &f.params,
-                                    f.out_rgb, f.out_chunk, nullptr, sl[0].workspace,
+                                    f.out_rgb, f.out_chunk, f.out_nnf, sl[0].workspace,
                                     cfg->workspace_bytes_per_slot, &cfg->tune, sl[0].stream);
         if (r != SB_OK) {
           rc = r;
@@ -255,12 +274,28 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
           bf.push_back(fr[size_t(admitted.front())]);
           admitted.pop_front();
         }
+        // sessions whose previous frame still runs on another slot: wait
+        // for that slot's batch (each slot once)
+        uint32_t waited = 0;
+        for (int32_t i : S.reqs) {
+          const int32_t ses = reqs[i].session;
+          if (ses < 0) continue;
+          const auto it = tails.find(ses);
+          if (it == tails.end()) continue;
+          const SessionTail &tl = it->second;
+          if (tl.slot == s || (waited >> tl.slot) & 1u) continue;
+          const Slot &P = sl[size_t(tl.slot)];
+          if (!P.busy || P.batch != tl.batch) continue;  // already retired
+          if (e == hipSuccess) e = hipStreamWaitEvent(S.stream, P.done, 0);
+          waited |= 1u << tl.slot;
+        }
+        if (e != hipSuccess) break;
         // a batch of one goes straight to the per-frame kernels (sized to the
         // frame, no descriptor upload); larger batches replay the plan
         const sb_frame &f0 = bf[0];
         const int r = bf.size() == 1
                           ? sb_stylize_ex(f0.style, f0.tgt_guide, f0.w, f0.h, f0.jitter,
-                                          &f0.params, f0.out_rgb, f0.out_chunk, nullptr,
+                                          &f0.params, f0.out_rgb, f0.out_chunk, f0.out_nnf,
                                           S.workspace, cfg->workspace_bytes_per_slot, &cfg->tune,
                                           S.stream)
                           : sb_batch_run(S.plan, bf.data(), int32_t(bf.size()), S.workspace,
@@ -275,7 +310,9 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
           res[i].slot = s;
           res[i].launched_s = tl;
           res[i].batch_size = int32_t(S.reqs.size());
+          if (reqs[i].session >= 0) tails[reqs[i].session] = SessionTail{s, batch_id};
         }
+        S.batch = batch_id;
         ++batch_id;
         e = hipEventRecord(S.done, S.stream);
         S.busy = true;

@@ -29,7 +29,8 @@ class SbRequest(ctypes.Structure):
     _fields_ = [("arrival_s", ctypes.c_double), ("style", ctypes.POINTER(SbStyle)),
                 ("tgt_guide", ctypes.c_void_p), ("jitter", ctypes.c_void_p),
                 ("w", ctypes.c_int32), ("h", ctypes.c_int32), ("params", SbParams),
-                ("out_rgb", ctypes.c_void_p), ("out_chunk", ctypes.c_void_p)]
+                ("out_rgb", ctypes.c_void_p), ("out_chunk", ctypes.c_void_p),
+                ("out_nnf", ctypes.c_void_p), ("session", ctypes.c_int32)]
 
 
 class SbRequestResult(ctypes.Structure):
@@ -53,10 +54,12 @@ def _bind():
 
 class Request:
     """One request: a resident style, a device-resident target guide and
-    jitter table, the frame parameters and (optionally) output tensors."""
+    jitter table, the frame parameters and (optionally) output tensors.
+    ``session`` >= 0 marks a frame of an animated sequence: frames of one
+    session complete in arrival order."""
 
     def __init__(self, arrival_s: float, style: Style, guide, jitter, p: SbParams,
-                 out_rgb=None, out_chunk=None):
+                 out_rgb=None, out_chunk=None, out_nnf=None, session: int = -1):
         self.arrival_s = float(arrival_s)
         self.style = style
         self.guide = guide
@@ -64,6 +67,8 @@ class Request:
         self.params = p
         self.out_rgb = out_rgb
         self.out_chunk = out_chunk
+        self.out_nnf = out_nnf
+        self.session = int(session)
 
     @property
     def h(self):
@@ -90,7 +95,9 @@ def run(requests: Sequence[Request], slots: int = 4, max_batch: int = 16,
         reqs[i] = SbRequest(r.arrival_s, ctypes.pointer(r.style.c), r.guide.data_ptr(),
                             r.jitter.data_ptr(), r.w, r.h, r.params,
                             r.out_rgb.data_ptr() if r.out_rgb is not None else None,
-                            r.out_chunk.data_ptr() if r.out_chunk is not None else None)
+                            r.out_chunk.data_ptr() if r.out_chunk is not None else None,
+                            r.out_nnf.data_ptr() if r.out_nnf is not None else None,
+                            r.session)
         max_ws = max(max_ws, workspace_bytes(r.w, r.h, r.params))
     nslots = 1 if plain else slots
     mb = 1 if plain else max_batch
@@ -117,6 +124,8 @@ def run(requests: Sequence[Request], slots: int = 4, max_batch: int = 16,
         "batch": np.array([x.batch for x in res]),
         "batch_size": np.array([x.batch_size for x in res]),
         "status": np.array([x.status for x in res]),
+        "slot": np.array([x.slot for x in res]),
+        "session": np.array([r.session for r in requests]),
     }
     out["latency"] = out["completed"] - arrival
     return out
