@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="batch leg: library default choice")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame batch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-seg", action="store_true", help="skip the segmentation-guide leg")
+    ap.add_argument("--no-anim", action="store_true", help="skip the animation leg")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-qps", type=str, default="2000,12000,18000,24000",
                     help="comma-separated request rates of the serving sweep")
@@ -203,6 +205,8 @@ def main():
                "sample": f"{n} full {w}x{h} frames of this workload (lookup table built once, "
                          f"not timed), OpenMP over rows"}
 
+    seg = None if args.no_seg else seg_leg(sb, torch, np, workloads, st_np, fr, prm, ms_per_step)
+    anim = None if args.no_anim else anim_leg(sb, torch, np, workloads, style, w, h, p)
     batch = None if args.no_batch else batch_leg(sb, at, torch, workloads, args.no_tune)
     serve = None
     if not args.no_serve:
@@ -248,10 +252,132 @@ def main():
                      "traffic": round(traffic) if traffic is not None else None,
                      "kernel_ms": round(float(vote_ms), 6), "algorithmic_bytes": vbytes},
         "cpu_baseline": cpu,
+        "segmentation": seg,
+        "animation": anim,
         "batch": batch,
         "serve": serve,
     }
     print(json.dumps(line), flush=True)
+
+
+def seg_leg(sb, torch, np, workloads, st_np, fr, prm, plain_ms, nlabels=6, steps=100):
+    """The same frame with the segmentation guide: seeded Voronoi label maps
+    (nlabels labels over 40 exemplar and 60 target regions), per-label
+    lookup tables resident with the style."""
+    ls = workloads.voronoi_labels(st_np.sw, st_np.sh, nlabels, 40, 11)
+    lt = workloads.voronoi_labels(fr.w, fr.h, nlabels, 60, 12)
+    style = sb.Style(st_np.rgb, st_np.guide, st_np.lut_bits, labels=ls, nlabels=nlabels)
+    g_np = fr.guide.view(np.int16) if fr.guide.dtype == np.uint16 else fr.guide
+    g = torch.from_numpy(g_np).cuda()
+    jit = torch.from_numpy(fr.jitter.view(np.int32)).cuda()
+    ltd = torch.from_numpy(lt).cuda()
+    rgb = torch.empty((fr.h, fr.w, 3), dtype=torch.uint8, device="cuda")
+    chunk = torch.empty((fr.h, fr.w), dtype=torch.int32, device="cuda")
+    ws = torch.empty(sb.workspace_bytes(fr.w, fr.h, prm), dtype=torch.uint8, device="cuda")
+
+    def run():
+        sb.stylize(style, g, jit, prm, out_rgb=rgb, out_chunk=chunk, workspace=ws, tgt_labels=ltd)
+
+    for _ in range(10):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    lv = chunk.cpu().numpy().view(np.uint32) >> 26
+    return {"labels": nlabels, "ms_per_frame": round(ms, 6),
+            "mpixel_per_s": round(fr.w * fr.h / (ms * 1e-3) / 1e6, 2),
+            "vs_plain": round(plain_ms / ms, 3),
+            "fallback_fraction": round(float((lv == prm.levels).mean()), 4),
+            "label_tables_mib": round(style.label_luts.numel() * 4 / 2**20, 2)}
+
+
+def anim_leg(sb, torch, np, workloads, style, w, h, p, nframes=12, reps=5):
+    """The per-frame seed schedule on a static and on an animated target
+    (drifting bumps): the fraction of pixels whose source coordinate / chunk
+    code changes between consecutive frames as a function of the threshold
+    t -- static target with seeds re-drawn every frame (the flicker alone),
+    moving target with seeds held (the motion alone) and moving target with
+    seeds re-drawn; 12-frame sequences as one graph launch; then sessions of
+    60 fps frames served with in-order completion."""
+    import paper_1807_03249_amd.serve as sv
+
+    guides_np = workloads.animated_bump_guides(w, h, 64, nframes, 3.0, 601)
+    guides = [torch.from_numpy(g).cuda() for g in guides_np]
+    pool = [torch.from_numpy(workloads.jitter_table(w, h, p.levels, p.finest, 610 + k)
+                             .view(np.int32)).cuda() for k in range(16)]
+    held = [pool[0]] * nframes
+    redrawn = pool[:nframes]
+    base = int(p.threshold)
+    ts = sorted({0, base // 4, base // 2, base, 2 * base, 4 * base, 16 * base, 64 * base})
+    b = sb.Batch(use_graph=True)
+    outs = [(torch.empty((h, w, 3), dtype=torch.uint8, device="cuda"),
+             torch.empty((h, w), dtype=torch.int32, device="cuda"),
+             torch.empty((h, w), dtype=torch.int32, device="cuda")) for _ in range(nframes)]
+    ws = None
+    cws = torch.empty(sb.lib().sb_change_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    counts = torch.empty((nframes - 1, 2), dtype=torch.int64, device="cuda")
+    sweep = []
+    seq_ms = None
+    for t in ts:
+        prm = sb.params(p.levels, p.finest, t, p.radius)
+        row = {"t": t}
+        cases = (("static_redrawn", [guides[0]] * nframes, redrawn),
+                 ("moving_held", guides, held), ("moving_redrawn", guides, redrawn))
+        for name, gs, jits in cases:
+            jobs = [sb.FrameJob(style, g, j, prm, o[0], o[1], o[2])
+                    for g, j, o in zip(gs, jits, outs)]
+            if ws is None:
+                ws = torch.empty(b.workspace_bytes(jobs), dtype=torch.uint8, device="cuda")
+            b.run(jobs, workspace=ws)
+            for k in range(nframes - 1):
+                sb.frame_change(outs[k][1], outs[k + 1][1], outs[k][2], outs[k + 1][2],
+                                counts=counts[k], workspace=cws)
+            c = counts.cpu().numpy().astype(np.float64) / (w * h)
+            lv = (outs[0][1].cpu().numpy().view(np.uint32) >> 26)
+            row[name] = {"src_changed": round(float(c[:, 1].mean()), 4),
+                         "chunk_changed": round(float(c[:, 0].mean()), 4),
+                         "fallback": round(float((lv == p.levels).mean()), 4)}
+            if t == base and name == "moving_redrawn":
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    b.run(jobs, workspace=ws)
+                torch.cuda.synchronize()
+                seq_ms = (time.perf_counter() - t0) * 1e3 / reps
+        sweep.append(row)
+    b.close()
+    res = {"frames": nframes, "size": f"{w}x{h}", "drift_px_per_frame": 3.0, "sweep": sweep,
+           "sequence_ms": round(seq_ms, 4),
+           "sequence_mpixel_per_s": round(nframes * w * h / (seq_ms * 1e-3) / 1e6, 2)}
+
+    # sessions: S viewers at 60 fps for one second, random phases; frame k of
+    # session s shows guide (k + s) mod nframes with a fresh jitter table
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
+    rng = np.random.default_rng(620)
+    res["sessions"] = []
+    for nses in (32, 128, 256):
+        phase = rng.uniform(0.0, 1.0, nses)
+        reqs = []
+        for k in range(60):
+            for s in range(nses):
+                reqs.append(((k + phase[s]) / 60.0, s, k))
+        reqs.sort()
+        rq = [sv.Request(a, style, guides[(k + s) % nframes], pool[(s * 13 + k) % len(pool)],
+                         prm, session=s) for a, s, k in reqs]
+        ent = {"sessions": nses, "fps": 60, "frames": len(rq)}
+        for name, kw in (("batched", dict(slots=4, max_batch=16)), ("plain", dict(plain=True))):
+            out = sv.run(rq, budget_bytes=1 << 30, **kw)
+            summ = sv.summarize(out, pixels=np.full(len(rq), float(w * h)))
+            order = all(np.all(np.diff(out["completed"][out["session"] == s]) >= 0)
+                        for s in range(nses))
+            ent[name] = {"p50_ms": round(summ["p50_ms"], 4), "p99_ms": round(summ["p99_ms"], 4),
+                         "frames_per_s": round(summ["req_per_s"], 1),
+                         "mean_batch": round(summ["mean_batch"], 2), "in_order": bool(order)}
+        res["sessions"].append(ent)
+    return res
 
 
 def batch_leg(sb, at, torch, workloads, no_tune, reps=5):
