@@ -24,6 +24,12 @@ between two of them; ``tests/test_oracle_animation.py`` pins the paper's
 statements about it (seeds that do not move leave a static target
 unchanged, threshold 0 makes the result independent of the seeds, a larger
 threshold changes more pixels) and checks the counts by brute force.
+Three-channel guides (format 2, the additional guiding channels of
+Sec. 3.1) are pinned in ``tests/test_oracle_channels.py``: the table against
+an independent vectorised argmin and a full-coverage closed form, the
+reduction to the two-channel path when the third channel is constant, an
+adversarial third channel that alone decides acceptance, and the level
+loop's invariants with the three-channel error.
 """
 from __future__ import annotations
 
@@ -76,6 +82,7 @@ def _load():
     lib.ora_stylize.argtypes = [_u8p, vp, i32, i32, _u32p, i32, i32, vp, i32, i32, _u32p, i32,
                                 i32, ctypes.c_uint32, i32, _u8p, _u32p, _u32p]
     lib.ora_lut_build_labels.argtypes = [vp, _u8p, i32, i32, i32, i32, i32, _u32p]
+    lib.ora_lut_query.argtypes = [vp, i32, i32, i32, i32, _i64p, ctypes.c_int64, _u32p]
     lib.ora_stylize_seg.argtypes = [_u8p, vp, _u8p, i32, i32, _u32p, i32, i32, i32, vp, _u8p,
                                     i32, i32, _u32p, i32, i32, ctypes.c_uint32, i32, _u8p, _u32p,
                                     _u32p]
@@ -88,14 +95,23 @@ def _ptr(a: np.ndarray, t):
 
 
 def _guide(g: np.ndarray) -> Tuple[np.ndarray, int]:
+    """Guide bytes and format: (rows, cols, 2) uint8 -> 0, (rows, cols, 2)
+    uint16 -> 1, (rows, cols, 4) uint8 -> 2 (three channels, byte 3
+    ignored)."""
     g = np.ascontiguousarray(g)
+    if g.ndim == 3 and g.shape[2] == 4 and g.dtype == np.uint8:
+        return g, 2
     if g.ndim != 3 or g.shape[2] != 2:
-        raise ValueError("guide must be (rows, cols, 2)")
+        raise ValueError("guide must be (rows, cols, 2), or (rows, cols, 4) uint8")
     if g.dtype == np.uint8:
         return g, 0
     if g.dtype == np.uint16:
         return g, 1
     raise ValueError("guide must be uint8 or uint16")
+
+
+def _bins(fmt: int, lut_bits: int) -> int:
+    return 1 << ((3 if fmt == 2 else 2) * lut_bits)
 
 
 def _jit(jitter: Optional[np.ndarray], w: int, h: int, levels: int, finest: int) -> np.ndarray:
@@ -118,13 +134,24 @@ def jitter_len(w: int, h: int, levels: int, finest: int) -> int:
 
 
 def lut_build(src_guide: np.ndarray, lut_bits: int) -> np.ndarray:
-    """Exact lookup table, shape (2**lut_bits)**2, entries x | y << 16."""
+    """Exact lookup table, (2**lut_bits)**2 entries ((2**lut_bits)**3 for
+    three-channel guides), entries x | y << 16."""
     g, fmt = _guide(src_guide)
-    n = 1 << lut_bits
-    lut = np.zeros(n * n, np.uint32)
+    lut = np.zeros(_bins(fmt, lut_bits), np.uint32)
     _check(_load().ora_lut_build(g.ctypes.data, fmt, g.shape[1], g.shape[0], lut_bits,
                                  _ptr(lut, _u32p)), "lut_build")
     return lut
+
+
+def lut_query(src_guide: np.ndarray, lut_bits: int, bins) -> np.ndarray:
+    """Selected entries of the lookup table, each by brute force over every
+    source pixel (for sampling tables too large to build here)."""
+    g, fmt = _guide(src_guide)
+    b = np.ascontiguousarray(bins, dtype=np.int64)
+    out = np.zeros(b.size, np.uint32)
+    _check(_load().ora_lut_query(g.ctypes.data, fmt, g.shape[1], g.shape[0], lut_bits,
+                                 _ptr(b, _i64p), b.size, _ptr(out, _u32p)), "lut_query")
+    return out
 
 
 def seed_point(w, h, levels, finest, jitter, level, bx, by):
@@ -214,8 +241,7 @@ def lut_build_labels(src_guide: np.ndarray, src_labels: np.ndarray, nlabels: int
     gets the unconstrained table."""
     g, fmt = _guide(src_guide)
     lab = _labels(src_labels, g.shape[:2])
-    n = 1 << lut_bits
-    luts = np.zeros((nlabels, n * n), np.uint32)
+    luts = np.zeros((nlabels, _bins(fmt, lut_bits)), np.uint32)
     _check(_load().ora_lut_build_labels(g.ctypes.data, _ptr(lab, _u8p), nlabels, fmt, g.shape[1],
                                         g.shape[0], lut_bits, _ptr(luts, _u32p)),
            "lut_build_labels")

@@ -47,6 +47,14 @@
  *   - a level is accepted only if, besides the error test, the transferred
  *     source pixel carries the pixel's label: L_S[v] == L_T[p];
  *   - the fallback is the pixel's own lookup in the table of its label.
+ *
+ * More than two guide channels (the additional guiding channels of Sec. 3.1,
+ * for which the paper suggests a search tree; here the same exact argmin,
+ * tabulated): fmt 2 holds three uint8 channels in 4 bytes per pixel (byte 3
+ * ignored).  The error sums the three squared differences; the table has
+ * (1 << lut_bits)^3 bins indexed c0 + (c1 << b) + (c2 << 2b) and is built by
+ * brute force over every source pixel (the definition: nearest to the bin
+ * centre, ties to the smallest raster index).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -59,21 +67,37 @@
 /* ------------------------------------------------------------------ guides */
 
 /* Read the two guide channels of pixel `idx` (raster index). fmt 0: uint8,
- * fmt 1: uint16. */
+ * fmt 1: uint16 (fmt 2 reads its first two channels here). */
 static void guide_read(const void *g, int fmt, int64_t idx, int64_t *c0, int64_t *c1)
 {
     if (fmt == 0) {
         const uint8_t *p = (const uint8_t *)g;
         *c0 = p[2 * idx];
         *c1 = p[2 * idx + 1];
-    } else {
+    } else if (fmt == 1) {
         const uint16_t *p = (const uint16_t *)g;
         *c0 = p[2 * idx];
         *c1 = p[2 * idx + 1];
+    } else {
+        const uint8_t *p = (const uint8_t *)g;
+        *c0 = p[4 * idx];
+        *c1 = p[4 * idx + 1];
     }
 }
 
-static int guide_depth(int fmt) { return fmt == 0 ? 8 : 16; }
+/* Number of guide channels of a format. */
+static int guide_channels(int fmt) { return fmt == 2 ? 3 : 2; }
+
+/* Every channel of pixel `idx`: c[0..guide_channels(fmt)-1]. */
+static void guide_read_all(const void *g, int fmt, int64_t idx, int64_t *c)
+{
+    guide_read(g, fmt, idx, &c[0], &c[1]);
+    if (fmt == 2) c[2] = ((const uint8_t *)g)[4 * idx + 2];
+}
+
+static int guide_depth(int fmt) { return fmt == 1 ? 16 : 8; }
+
+static int fmt_ok(int fmt) { return fmt == 0 || fmt == 1 || fmt == 2; }
 
 /* Lookup-table bin of one guide channel value: drop the low bits. */
 static int64_t lut_quantise(int64_t v, int fmt, int lut_bits)
@@ -101,10 +125,47 @@ static int64_t lut_bin_centre(int64_t c, int fmt, int lut_bits)
 /* The table over the source pixels whose label is `want` (labels NULL: all
  * pixels).  Returns ORA_OK, or 1 when no source pixel qualifies (lut left
  * untouched). */
+/* Three channels: every bin by brute force over every qualifying source
+ * pixel, in raster order with a strict compare (so ties keep the smallest
+ * raster index).  Returns 1 when no source pixel qualifies. */
+static int lut_build3_filtered(const void *src_guide, const uint8_t *labels, int want, int sw,
+                               int sh, int lut_bits, uint32_t *lut)
+{
+    const int64_t n = (int64_t)1 << lut_bits, npix = (int64_t)sw * sh;
+    int64_t any = 0;
+    for (int64_t i = 0; i < npix && !any; ++i) any = !labels || labels[i] == want;
+    if (!any) return 1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t c = 0; c < n * n * n; ++c) {
+        const int64_t q[3] = {lut_bin_centre(c % n, 2, lut_bits),
+                              lut_bin_centre((c / n) % n, 2, lut_bits),
+                              lut_bin_centre(c / (n * n), 2, lut_bits)};
+        uint64_t best_d = UINT64_MAX;
+        int64_t best_i = -1;
+        for (int64_t i = 0; i < npix; ++i) {
+            if (labels && labels[i] != want) continue;
+            int64_t g[3];
+            guide_read_all(src_guide, 2, i, g);
+            uint64_t d = 0;
+            for (int k = 0; k < 3; ++k) d += (uint64_t)((q[k] - g[k]) * (q[k] - g[k]));
+            if (d < best_d) {
+                best_d = d;
+                best_i = i;
+            }
+        }
+        lut[c] = (uint32_t)(best_i % sw) | ((uint32_t)(best_i / sw) << 16);
+    }
+    return ORA_OK;
+}
+
 static int lut_build_filtered(const void *src_guide, const uint8_t *labels, int want, int fmt,
                               int sw, int sh, int lut_bits, uint32_t *lut)
 {
-    if (!src_guide || !lut || sw < 1 || sh < 1 || (fmt != 0 && fmt != 1)) return ORA_EINVAL;
+    if (!src_guide || !lut || sw < 1 || sh < 1 || !fmt_ok(fmt)) return ORA_EINVAL;
+    if (fmt == 2) {
+        if (lut_bits < 1 || lut_bits > 8) return ORA_EINVAL;
+        return lut_build3_filtered(src_guide, labels, want, sw, sh, lut_bits, lut);
+    }
     if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
     const int64_t n = (int64_t)1 << lut_bits;          /* bins per channel */
     const int64_t w = (int64_t)1 << (guide_depth(fmt) - lut_bits); /* bin width */
@@ -181,6 +242,41 @@ int ora_lut_build(const void *src_guide, int fmt, int sw, int sh, int lut_bits, 
     return lut_build_filtered(src_guide, NULL, 0, fmt, sw, sh, lut_bits, lut);
 }
 
+/* Selected bins of the table of any format, each by brute force over every
+ * source pixel (the definition; for checking large tables by sampling):
+ * out[k] = LUT[bins[k]]. */
+int ora_lut_query(const void *src_guide, int fmt, int sw, int sh, int lut_bits,
+                  const int64_t *bins, int64_t nbins, uint32_t *out)
+{
+    if (!src_guide || !bins || !out || sw < 1 || sh < 1 || !fmt_ok(fmt)) return ORA_EINVAL;
+    if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
+    const int nc = guide_channels(fmt);
+    const int64_t n = (int64_t)1 << lut_bits, npix = (int64_t)sw * sh;
+    int64_t nb = 1;
+    for (int k = 0; k < nc; ++k) nb *= n;
+    for (int64_t j = 0; j < nbins; ++j)
+        if (bins[j] < 0 || bins[j] >= nb) return ORA_EINVAL;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t j = 0; j < nbins; ++j) {
+        int64_t q[3], c = bins[j];
+        for (int k = 0; k < nc; ++k, c /= n) q[k] = lut_bin_centre(c % n, fmt, lut_bits);
+        uint64_t best_d = UINT64_MAX;
+        int64_t best_i = -1;
+        for (int64_t i = 0; i < npix; ++i) {
+            int64_t g[3];
+            guide_read_all(src_guide, fmt, i, g);
+            uint64_t d = 0;
+            for (int k = 0; k < nc; ++k) d += (uint64_t)((q[k] - g[k]) * (q[k] - g[k]));
+            if (d < best_d) {
+                best_d = d;
+                best_i = i;
+            }
+        }
+        out[j] = (uint32_t)(best_i % sw) | ((uint32_t)(best_i / sw) << 16);
+    }
+    return ORA_OK;
+}
+
 /* Per-label tables luts[l * bins + c] for labels l = 0..nlabels-1, from the
  * source pixels labelled l; a label without source pixels gets the
  * unconstrained table. */
@@ -188,8 +284,9 @@ int ora_lut_build_labels(const void *src_guide, const uint8_t *labels, int nlabe
                          int sh, int lut_bits, uint32_t *luts)
 {
     if (!labels || !luts || nlabels < 1 || nlabels > 256) return ORA_EINVAL;
-    if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
-    const int64_t bins = (int64_t)1 << (2 * lut_bits);
+    if (!fmt_ok(fmt) || lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12)
+        return ORA_EINVAL;
+    const int64_t bins = (int64_t)1 << (guide_channels(fmt) * lut_bits);
     for (int l = 0; l < nlabels; ++l) {
         int rc = lut_build_filtered(src_guide, labels, l, fmt, sw, sh, lut_bits, luts + l * bins);
         if (rc == 1) rc = lut_build_filtered(src_guide, NULL, 0, fmt, sw, sh, lut_bits, luts + l * bins);
@@ -289,14 +386,21 @@ typedef struct {
     int nlabels;
 } assign_t;
 
-/* The lookup of a guide value in the table of `label` (ignored without
- * segmentation; values past the last table use the last one). */
-static uint32_t lut_lookup(const assign_t *A, int64_t g0, int64_t g1, int label)
+/* The lookup of a guide value g[] in the table of `label` (ignored without
+ * segmentation; values past the last table use the last one).  Bin index
+ * c0 + c1 * n (+ c2 * n^2 with three channels). */
+static uint32_t lut_lookup(const assign_t *A, const int64_t *g, int label)
 {
-    int64_t n = (int64_t)1 << A->lut_bits;
+    const int nc = guide_channels(A->fmt);
+    const int64_t n = (int64_t)1 << A->lut_bits;
+    int64_t bins = 1, c = 0;
+    for (int k = 0; k < nc; ++k) {
+        c += lut_quantise(g[k], A->fmt, A->lut_bits) * bins;
+        bins *= n;
+    }
     const uint32_t *t = A->lut;
-    if (A->tgt_labels) t += (int64_t)(label < A->nlabels ? label : A->nlabels - 1) * n * n;
-    return t[lut_quantise(g1, A->fmt, A->lut_bits) * n + lut_quantise(g0, A->fmt, A->lut_bits)];
+    if (A->tgt_labels) t += (int64_t)(label < A->nlabels ? label : A->nlabels - 1) * bins;
+    return t[c];
 }
 
 /* ParallelStyleBlit for one pixel, with colours replaced by coordinates:
@@ -304,32 +408,33 @@ static uint32_t lut_lookup(const assign_t *A, int64_t g0, int64_t g1, int label)
  * (level << 26) | (qy << 13) | qx. */
 static void assign_pixel(const assign_t *A, int64_t px, int64_t py, uint32_t *nnf, uint32_t *chunk)
 {
-    const int W = A->seeds.w;
-    int64_t t0, t1;
-    guide_read(A->tgt_guide, A->fmt, py * W + px, &t0, &t1);
+    const int W = A->seeds.w, nc = guide_channels(A->fmt);
+    int64_t tg[3];
+    guide_read_all(A->tgt_guide, A->fmt, py * W + px, tg);
     const int lp = A->tgt_labels ? A->tgt_labels[py * W + px] : 0;
     for (int i = 0; i < A->seeds.levels; ++i) {
         int64_t qx, qy;
         if (!nearest_seed(&A->seeds, i, px, py, &qx, &qy)) continue;
-        int64_t q0, q1;
-        guide_read(A->tgt_guide, A->fmt, qy * W + qx, &q0, &q1);
+        int64_t qg[3];
+        guide_read_all(A->tgt_guide, A->fmt, qy * W + qx, qg);
         const int lq = A->tgt_labels ? A->tgt_labels[qy * W + qx] : 0;
-        uint32_t u = lut_lookup(A, q0, q1, lq);
+        uint32_t u = lut_lookup(A, qg, lq);
         int64_t vx = (int64_t)(u & 0xFFFFu) + (px - qx);
         int64_t vy = (int64_t)(u >> 16) + (py - qy);
         if (vx < 0 || vy < 0 || vx >= A->sw || vy >= A->sh) continue;
         /* segmentation: the source pixel must carry the pixel's label */
         if (A->tgt_labels && A->src_labels[vy * A->sw + vx] != lp) continue;
-        int64_t s0, s1;
-        guide_read(A->src_guide, A->fmt, vy * A->sw + vx, &s0, &s1);
-        uint64_t e = (uint64_t)((t0 - s0) * (t0 - s0)) + (uint64_t)((t1 - s1) * (t1 - s1));
+        int64_t sg[3];
+        guide_read_all(A->src_guide, A->fmt, vy * A->sw + vx, sg);
+        uint64_t e = 0;
+        for (int k = 0; k < nc; ++k) e += (uint64_t)((tg[k] - sg[k]) * (tg[k] - sg[k]));
         if (e < (uint64_t)A->threshold) {
             *nnf = (uint32_t)vx | ((uint32_t)vy << 16);
             *chunk = ((uint32_t)i << 26) | ((uint32_t)qy << 13) | (uint32_t)qx;
             return;
         }
     }
-    *nnf = lut_lookup(A, t0, t1, lp);
+    *nnf = lut_lookup(A, tg, lp);
     *chunk = ((uint32_t)A->seeds.levels << 26) | ((uint32_t)py << 13) | (uint32_t)px;
 }
 
@@ -337,7 +442,7 @@ static int check_common(int sw, int sh, int fmt, int lut_bits, int w, int h, int
 {
     if (sw < 1 || sh < 1 || sw > 8192 || sh > 8192) return ORA_EINVAL;
     if (w < 1 || h < 1 || w > 8192 || h > 8192) return ORA_EINVAL;
-    if (fmt != 0 && fmt != 1) return ORA_EINVAL;
+    if (!fmt_ok(fmt)) return ORA_EINVAL;
     if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
     if (levels < 0 || levels > 12) return ORA_EINVAL;
     if (finest < 1 || (finest & (finest - 1)) != 0) return ORA_EINVAL;

@@ -9,6 +9,7 @@ the same inputs without sharing any code with each other.
 from .gen import (  # noqa: F401
     GUIDE_U8X2,
     GUIDE_U16X2,
+    GUIDE_U8X3,
     Frame,
     Style,
     Params,
@@ -23,6 +24,10 @@ from .gen import (  # noqa: F401
     voronoi_labels,
     animated_bump_guides,
     jitter_schedule,
+    appearance_u8,
+    guide_u8x3,
+    appearance_target,
+    APPEARANCE_PARAMS,
     config,
     CONFIG_NAMES,
 )

@@ -11,8 +11,10 @@ Conventions shared by both consumers (oracle and HIP library):
 
 * images are row-major ``(rows, cols, channels)``; pixel p = (x, y) with x the
   column and y the row;
-* a guide has exactly two channels, ``uint8`` (format ``GUIDE_U8X2``) or
-  ``uint16`` (format ``GUIDE_U16X2``);
+* a guide has two channels, ``uint8`` (format ``GUIDE_U8X2``) or ``uint16``
+  (format ``GUIDE_U16X2``), or three ``uint8`` channels stored in four bytes
+  per pixel, the fourth zero (format ``GUIDE_U8X3``: a normal pair plus an
+  appearance channel);
 * the seed hierarchy has ``levels`` levels with spacings
   ``finest << (levels - 1 - i)`` for level i = 0 (coarsest) ... levels-1;
 * level i's jitter table covers ``ceil(W/h) x ceil(H/h)`` cells, row-major,
@@ -28,6 +30,7 @@ import numpy as np
 
 GUIDE_U8X2 = 0
 GUIDE_U16X2 = 1
+GUIDE_U8X3 = 2
 
 
 @dataclasses.dataclass
@@ -234,6 +237,30 @@ def jitter_schedule(w: int, h: int, levels: int, finest: int, nframes: int, hold
     return [jitter_table(w, h, levels, finest, seed + f // max(1, hold)) for f in range(nframes)]
 
 
+def appearance_u8(rgb: np.ndarray, radius: int) -> np.ndarray:
+    """Appearance channel: integer luma (77 R + 150 G + 29 B + 128) >> 8,
+    box-averaged over a (2 radius + 1)^2 window clamped at the borders."""
+    luma = ((77 * rgb[..., 0].astype(np.int64) + 150 * rgb[..., 1].astype(np.int64)
+             + 29 * rgb[..., 2].astype(np.int64) + 128) >> 8)
+    h, w = luma.shape
+    k = 2 * radius + 1
+    pad = np.pad(luma, radius, mode="edge")
+    c = np.zeros((h + 2 * radius + 1, w + 2 * radius + 1), np.int64)
+    c[1:, 1:] = pad.cumsum(0).cumsum(1)
+    box = c[k:, k:] - c[:-k, k:] - c[k:, :-k] + c[:-k, :-k]
+    return ((box + k * k // 2) // (k * k)).astype(np.uint8)
+
+
+def guide_u8x3(two: np.ndarray, third: np.ndarray) -> np.ndarray:
+    """A three-channel guide in its storage layout: (rows, cols, 4) uint8,
+    channels 0-1 from ``two``, channel 2 from ``third``, byte 3 zero."""
+    h, w = third.shape
+    out = np.zeros((h, w, 4), np.uint8)
+    out[..., :2] = two
+    out[..., 2] = third
+    return out
+
+
 def identity_uv_guide_u16(sw: int, sh: int) -> np.ndarray:
     """Texture coordinates of each texel centre, scaled to 16 bits."""
     gx = np.floor((np.arange(sw) + 0.5) * 65536.0 / sw).astype(np.int64)
@@ -290,6 +317,7 @@ CONFIG_NAMES = {
     3: "uv-3840x2160",
     4: "batch-64-uneven",
     5: "serve-poisson",
+    6: "appearance-1920x1080",
 }
 
 NORMAL_PARAMS = Params(levels=4, finest=8, threshold=32, radius=3)
@@ -305,6 +333,22 @@ def _uv_style(size: int, seed: int, lut_bits: int) -> Style:
                  GUIDE_U16X2, lut_bits)
 
 
+APPEARANCE_PARAMS = Params(levels=4, finest=8, threshold=64, radius=3)
+
+
+def _appearance_style(size: int, seed: int, lut_bits: int) -> Style:
+    rgb = value_noise_rgb(size, size, seed)
+    g = guide_u8x3(sphere_guide_u8(size), appearance_u8(rgb, 4))
+    return Style(rgb, g, GUIDE_U8X3, lut_bits)
+
+
+def appearance_target(w: int, h: int, nbumps: int, seed: int) -> np.ndarray:
+    """Target of the appearance workload: bump normals plus the appearance
+    channel of a value-noise image standing in for the subject."""
+    return guide_u8x3(bump_guide_u8(w, h, nbumps, seed),
+                      appearance_u8(value_noise_rgb(w, h, seed + 1), 4))
+
+
 def _frame(guide: np.ndarray, fmt: int, p: Params, jseed: Optional[int], style: int = 0) -> Frame:
     h, w = guide.shape[:2]
     return Frame(np.ascontiguousarray(guide), fmt, jitter_table(w, h, p.levels, p.finest, jseed),
@@ -312,9 +356,9 @@ def _frame(guide: np.ndarray, fmt: int, p: Params, jseed: Optional[int], style: 
 
 
 def config(n: int, **kw):
-    """Return ``(styles, frames)`` for workload n (1..4), or for n == 5 a dict
-    describing the serving trace.  Keyword overrides: ``frames`` (cfg 4),
-    ``requests`` and ``qps`` (cfg 5)."""
+    """Return ``(styles, frames)`` for workload n (1..4, 6), or for n == 5 a
+    dict describing the serving trace.  Keyword overrides: ``frames`` (cfg 4),
+    ``requests`` and ``qps`` (cfg 5), ``lut_bits``, ``w`` and ``h`` (cfg 6)."""
     if n == 1:
         st = _sphere_style(256, 101)
         p = Params(levels=3, finest=8, threshold=48, radius=2)
@@ -373,4 +417,8 @@ def config(n: int, **kw):
             "pool_idx": pool_idx,
             "params": {GUIDE_U8X2: NORMAL_PARAMS, GUIDE_U16X2: UV_PARAMS},
         }
+    if n == 6:
+        st = _appearance_style(512, 601, int(kw.get("lut_bits", 8)))
+        w, h = int(kw.get("w", 1920)), int(kw.get("h", 1080))
+        return [st], [_frame(appearance_target(w, h, 64, 602), GUIDE_U8X3, APPEARANCE_PARAMS, 1)]
     raise ValueError(f"unknown workload {n}")
