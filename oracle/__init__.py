@@ -183,6 +183,8 @@ def assign(src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest, threshol
     h, w = gt.shape[:2]
     j = _jit(jitter, w, h, levels, finest)
     lut = np.ascontiguousarray(lut, dtype=np.uint32)
+    if lut.size != _bins(fmt, lut_bits):
+        raise ValueError("lookup table size does not match the guide format and lut_bits")
     nnf = np.zeros((h, w), np.uint32)
     chunk = np.zeros((h, w), np.uint32)
     r0, nr = rows if rows is not None else (0, -1)
@@ -217,6 +219,8 @@ def stylize(src_rgb, src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest
     h, w = gt.shape[:2]
     j = _jit(jitter, w, h, levels, finest)
     lut = np.ascontiguousarray(lut, dtype=np.uint32)
+    if lut.size != _bins(fmt, lut_bits):
+        raise ValueError("lookup table size does not match the guide format and lut_bits")
     out = np.zeros((h, w, 3), np.uint8)
     chunk = np.zeros((h, w), np.uint32)
     nnf = np.zeros((h, w), np.uint32)
@@ -262,7 +266,7 @@ def stylize_seg(src_rgb, src_guide, src_labels, luts, nlabels, lut_bits, tgt_gui
     h, w = gt.shape[:2]
     j = _jit(jitter, w, h, levels, finest)
     luts = np.ascontiguousarray(luts, dtype=np.uint32)
-    if luts.size != nlabels << (2 * lut_bits):
+    if luts.size != nlabels * _bins(fmt, lut_bits):
         raise ValueError("luts must hold nlabels tables")
     out = np.zeros((h, w, 3), np.uint8)
     chunk = np.zeros((h, w), np.uint32)

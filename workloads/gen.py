@@ -333,7 +333,7 @@ def _uv_style(size: int, seed: int, lut_bits: int) -> Style:
                  GUIDE_U16X2, lut_bits)
 
 
-APPEARANCE_PARAMS = Params(levels=4, finest=8, threshold=64, radius=3)
+APPEARANCE_PARAMS = Params(levels=4, finest=8, threshold=192, radius=3)
 
 
 def _appearance_style(size: int, seed: int, lut_bits: int) -> Style:
