@@ -17,7 +17,10 @@
  *   - images are row-major; pixel p = (x, y), x the column; raster index
  *     y*W + x;
  *   - a guide has two interleaved channels, uint8 (SB_GUIDE_U8X2, 2 B/px) or
- *     uint16 (SB_GUIDE_U16X2, 4 B/px, native little-endian);
+ *     uint16 (SB_GUIDE_U16X2, 4 B/px, native little-endian), or three uint8
+ *     channels in 4 B/px (SB_GUIDE_U8X3: channels in bytes 0..2, byte 3
+ *     ignored) -- the additional guiding channels of Sec. 3.1, e.g. a
+ *     normal pair plus an appearance channel;
  *   - source coordinates are packed x | (y << 16);
  *   - work is enqueued asynchronously on `stream` (0 = the null stream); the
  *     caller synchronises.  Arguments are validated before anything is
@@ -44,7 +47,7 @@ typedef enum {
     SB_EBUDGET = -4  /* serving: request larger than the memory budget */
 } sb_status;
 
-typedef enum { SB_GUIDE_U8X2 = 0, SB_GUIDE_U16X2 = 1 } sb_guide_fmt;
+typedef enum { SB_GUIDE_U8X2 = 0, SB_GUIDE_U16X2 = 1, SB_GUIDE_U8X3 = 2 } sb_guide_fmt;
 
 /* Largest target and source side, and limits of the parameters. */
 #define SB_MAX_SIDE 8192
@@ -59,13 +62,15 @@ typedef enum { SB_GUIDE_U8X2 = 0, SB_GUIDE_U16X2 = 1 } sb_guide_fmt;
 typedef struct {
     const uint32_t *rgba;   /* [device] padded exemplar of sb_exemplar_texels(sw, sh)
                                texels, written by sb_pack_exemplar */
-    const void *guide;      /* [device] Sw*Sh*2 guide channels */
+    const void *guide;      /* [device] Sw*Sh guide texels (2 or 4 B each, by fmt) */
     const uint32_t *lut;    /* [device] (1<<lut_bits)^2 source coordinates, bin index
-                               c = c0 + (c1 << lut_bits), written by sb_lut_build */
+                               c = c0 + (c1 << lut_bits); SB_GUIDE_U8X3: (1<<lut_bits)^3,
+                               c = c0 + (c1 << lut_bits) + (c2 << 2*lut_bits); written
+                               by sb_lut_build */
     int32_t sw, sh;         /* source size, 1..SB_MAX_SIDE */
     int32_t fmt;            /* sb_guide_fmt */
-    int32_t lut_bits;       /* bits per channel of the lookup table: U8X2 1..8,
-                               U16X2 1..SB_MAX_LUT_BITS */
+    int32_t lut_bits;       /* bits per channel of the lookup table: U8X2 and U8X3
+                               1..8, U16X2 1..SB_MAX_LUT_BITS */
     /* Segmentation guide (optional; nlabels = 0 and NULLs without it): a
      * label per source pixel and one lookup table per label, so chunks stay
      * inside regions of equal label (the extra segmentation guide of the
@@ -84,7 +89,8 @@ typedef struct {
                                (0 = coarsest) has spacing finest << (L-1-i), at most
                                SB_MAX_SIDE.  The paper's hierarchy is finest = 2. */
     uint32_t threshold;     /* t: a level is accepted iff the exact squared L2 guide
-                               error is < t (so t = 0 accepts nothing) */
+                               error over all channels is < t (so t = 0 accepts
+                               nothing) */
     int32_t radius;         /* r, 0..SB_MAX_RADIUS: voting window (2r+1)^2; 0 = copy */
 } sb_params;
 
@@ -121,11 +127,17 @@ size_t sb_lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_b
 
 /* Build the guide-to-source lookup table of Sec. 3.1 on the device:
  *   LUT[c] = argmin_u |centre(c) - G_S[u]|^2, ties to the smallest raster
- *   index of u, where bin c = (c0, c1) holds the guide values whose top
- *   lut_bits bits per channel are c0, c1 and centre(c) = (c << s) + 2^(s-1)
- *   per channel for s = depth - lut_bits > 0, centre(c) = c for s = 0.
- * guide [device] Sw*Sh*2; lut [device] (1<<lut_bits)^2 entries;
- * workspace [device] of at least sb_lut_workspace_bytes() bytes. */
+ *   index of u, where bin c = (c0, c1[, c2]) holds the guide values whose top
+ *   lut_bits bits per channel are c0, c1[, c2] and centre(c) = (c << s) +
+ *   2^(s-1) per channel for s = depth - lut_bits > 0, centre(c) = c for s = 0.
+ *   With three channels this exact table stands in for the search tree the
+ *   paper suggests for additional guiding channels (Sec. 3.1): same argmin,
+ *   one load per query.
+ * guide [device] Sw*Sh texels; lut [device] (1<<lut_bits)^2 entries, or
+ * (1<<lut_bits)^3 for SB_GUIDE_U8X3 (64 MiB at 8 bits);
+ * workspace [device] of at least sb_lut_workspace_bytes() bytes (8-bit
+ * guides: about 2^(8*(channels-1)+lut_bits+4) bytes, 256 MiB for three
+ * channels at 8 bits). */
 int sb_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
                  uint32_t *lut, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
@@ -133,9 +145,10 @@ int sb_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t
  * every bin, the source pixel labelled l whose guide is nearest to the bin
  * centre (ties to the smallest raster index, as sb_lut_build); a label with
  * no source pixel gets the unconstrained table `lut` (from sb_lut_build).
- * guide [device] Sw*Sh*2; labels [device] Sw*Sh (values >= nlabels belong
- * to no table); lut [device] the unconstrained table; luts [device] nlabels
- * tables, label-major; workspace [device] of sb_lut_workspace_bytes(). */
+ * guide [device] Sw*Sh texels; labels [device] Sw*Sh (values >= nlabels
+ * belong to no table); lut [device] the unconstrained table; luts [device]
+ * nlabels tables (each the size of `lut`), label-major; workspace [device]
+ * of sb_lut_workspace_bytes(). */
 int sb_lut_build_labels(const void *guide, const uint8_t *labels, int32_t fmt, int32_t sw,
                         int32_t sh, int32_t lut_bits, int32_t nlabels, const uint32_t *lut,
                         uint32_t *luts, void *workspace, size_t workspace_bytes,
@@ -148,7 +161,7 @@ size_t sb_workspace_bytes(int32_t w, int32_t h, const sb_params *params);
 
 /* Stylise one frame (Algorithm 2 for every pixel, then the voting blend).
  *   style      [host] struct of device pointers, see sb_style
- *   tgt_guide  [device] W*H*2 channels, same format as the style's guide
+ *   tgt_guide  [device] W*H texels, same format as the style's guide
  *   jitter     [device] sb_jitter_len(W, H, L, finest) entries
  *   out_rgb    [device] W*H*3 bytes: the stylised image C_T
  *   out_chunk  [device] W*H: chunk code (level << 26) | (qy << 13) | qx of the
@@ -247,7 +260,7 @@ int sb_frame_change(const uint32_t *chunk_a, const uint32_t *chunk_b, const uint
 /* One frame of a batch: the arguments of sb_stylize for that frame. */
 typedef struct {
     const sb_style *style;      /* [host] */
-    const void *tgt_guide;      /* [device] W*H*2 channels in the style's format */
+    const void *tgt_guide;      /* [device] W*H texels in the style's format */
     const uint32_t *jitter;     /* [device] sb_jitter_len() entries */
     int32_t w, h;
     sb_params params;

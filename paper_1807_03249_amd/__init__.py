@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstylebli
 
 GUIDE_U8X2 = 0
 GUIDE_U16X2 = 1
+GUIDE_U8X3 = 2  # three uint8 channels in 4 bytes per pixel (byte 3 ignored)
 MAX_SIDE = 8192
 MAX_LEVELS = 12
 MAX_RADIUS = 7
@@ -170,11 +171,22 @@ def params(levels: int, finest: int, threshold: int, radius: int) -> SbParams:
 
 
 def _guide_fmt(torch, g) -> int:
+    """Format of a (rows, cols, channels) guide tensor: two uint8 channels,
+    two uint16 channels, or (rows, cols, 4) uint8 holding three channels."""
+    if g.dim() == 3 and g.shape[2] == 4 and g.dtype == torch.uint8:
+        return GUIDE_U8X3
+    if g.dim() != 3 or g.shape[2] != 2:
+        raise TypeError("guide must be (rows, cols, 2), or (rows, cols, 4) uint8")
     if g.dtype == torch.uint8:
         return GUIDE_U8X2
     if g.dtype in (torch.uint16, torch.int16):
         return GUIDE_U16X2
     raise TypeError("guides are uint8 or uint16 with two channels")
+
+
+def table_entries(fmt: int, lut_bits: int) -> int:
+    """Entries of one lookup table: (2**lut_bits)**channels."""
+    return 1 << ((3 if fmt == GUIDE_U8X3 else 2) * lut_bits)
 
 
 class Style:
@@ -193,8 +205,6 @@ class Style:
         if not isinstance(g, torch.Tensor) and getattr(g, "dtype", None) is not None and str(g.dtype) == "uint16":
             g = g.view("int16")  # torch.from_numpy has no uint16 on every build; same bits
         self.guide = _dev(torch, g)
-        if self.guide.dim() != 3 or self.guide.shape[2] != 2:
-            raise TypeError("guide must be (rows, cols, 2)")
         self.fmt = _guide_fmt(torch, self.guide)
         self.sh, self.sw = int(self.rgb.shape[0]), int(self.rgb.shape[1])
         if tuple(self.guide.shape[:2]) != (self.sh, self.sw):
@@ -211,7 +221,8 @@ class Style:
         if wsb == 0:
             raise StyleBlitError(SB_EINVAL, "sb_lut_workspace_bytes")
         ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
-        self.lut = torch.empty(1 << (2 * self.lut_bits), dtype=torch.int32, device="cuda")
+        self.lut = torch.empty(table_entries(self.fmt, self.lut_bits), dtype=torch.int32,
+                               device="cuda")
         _check(L.sb_lut_build(self.guide.data_ptr(), self.fmt, self.sw, self.sh, self.lut_bits,
                               self.lut.data_ptr(), ws.data_ptr(), wsb, s), "sb_lut_build")
         self._ws = ws  # keep alive until the enqueued build has run
@@ -222,7 +233,7 @@ class Style:
             if tuple(self.labels.shape) != (self.sh, self.sw):
                 raise ValueError("label map and exemplar sizes differ")
             self.nlabels = int(nlabels if nlabels is not None else int(self.labels.max()) + 1)
-            self.label_luts = torch.empty((self.nlabels, 1 << (2 * self.lut_bits)),
+            self.label_luts = torch.empty((self.nlabels, table_entries(self.fmt, self.lut_bits)),
                                           dtype=torch.int32, device="cuda")
             _check(L.sb_lut_build_labels(self.guide.data_ptr(), self.labels.data_ptr(), self.fmt,
                                          self.sw, self.sh, self.lut_bits, self.nlabels,
@@ -252,7 +263,7 @@ def workspace_bytes(w: int, h: int, p: SbParams) -> int:
 def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chunk=None,
             want_nnf: bool = False, workspace=None, stream=None, tune=None, events=None,
             tgt_labels=None):
-    """Stylise one frame.  ``tgt_guide`` (H, W, 2) and ``jitter`` (uint32 as
+    """Stylise one frame.  ``tgt_guide`` (H, W, 2) or (H, W, 4) and ``jitter`` (uint32 as
     int32 bits) may be numpy arrays or device tensors.  Returns
     ``(rgb (H,W,3) uint8, chunk (H,W) int32-bits[, nnf])`` as device tensors;
     the work is enqueued on the current stream.  ``tune`` is a
@@ -265,8 +276,6 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     if not isinstance(g, torch.Tensor) and str(getattr(g, "dtype", "")) == "uint16":
         g = g.view("int16")
     g = _dev(torch, g)
-    if g.dim() != 3 or g.shape[2] != 2:
-        raise TypeError("target guide must be (rows, cols, 2)")
     if _guide_fmt(torch, g) != style.fmt:
         raise TypeError("target guide format differs from the style's guide format")
     h, w = int(g.shape[0]), int(g.shape[1])

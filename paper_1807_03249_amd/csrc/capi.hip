@@ -24,11 +24,10 @@ bool side_ok(int32_t v) { return v >= 1 && v <= SB_MAX_SIDE; }
 bool style_ok(const sb_style *s) {
   if (!s || !s->rgba || !s->guide || !s->lut) return false;
   if (!side_ok(s->sw) || !side_ok(s->sh)) return false;
-  if (s->fmt != SB_GUIDE_U8X2 && s->fmt != SB_GUIDE_U16X2) return false;
+  if (!fmt_ok(s->fmt)) return false;
   if (s->nlabels < 0 || s->nlabels > SB_MAX_LABELS) return false;
   if (s->nlabels > 0 && (!s->labels || !s->label_luts)) return false;
-  const int32_t depth = s->fmt == SB_GUIDE_U8X2 ? 8 : 16;
-  return s->lut_bits >= 1 && s->lut_bits <= depth && s->lut_bits <= SB_MAX_LUT_BITS;
+  return s->lut_bits >= 1 && s->lut_bits <= fmt_depth(s->fmt) && s->lut_bits <= SB_MAX_LUT_BITS;
 }
 
 bool params_ok(const sb_params *p) {
@@ -92,7 +91,8 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
   a->w = w;
   a->h = h;
   a->lut_bits = style->lut_bits;
-  a->lut_shift = (style->fmt == SB_GUIDE_U8X2 ? 8 : 16) - style->lut_bits;
+  a->lut_shift = fmt_depth(style->fmt) - style->lut_bits;
+  a->lut_log2 = fmt_channels(style->fmt) * style->lut_bits;
   a->threshold = params->threshold;
   a->radius = params->radius;
   a->fmt = style->fmt;
@@ -182,9 +182,8 @@ int sb_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t *rgba,
 }
 
 size_t sb_lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits) {
-  if ((fmt != SB_GUIDE_U8X2 && fmt != SB_GUIDE_U16X2) || !side_ok(sw) || !side_ok(sh)) return 0;
-  const int32_t depth = fmt == SB_GUIDE_U8X2 ? 8 : 16;
-  if (lut_bits < 1 || lut_bits > depth || lut_bits > SB_MAX_LUT_BITS) return 0;
+  if (!fmt_ok(fmt) || !side_ok(sw) || !side_ok(sh)) return 0;
+  if (lut_bits < 1 || lut_bits > fmt_depth(fmt) || lut_bits > SB_MAX_LUT_BITS) return 0;
   return lut_workspace_bytes(fmt, sw, sh, lut_bits);
 }
 

@@ -29,6 +29,17 @@ struct Levels {
   int32_t poffset[SB_MAX_LEVELS + 1];  // first record of level i; poffset[L] = total
 };
 
+// Guide formats: channels and bits per channel.
+__host__ __device__ constexpr bool fmt_ok(int32_t fmt) {
+  return fmt == SB_GUIDE_U8X2 || fmt == SB_GUIDE_U16X2 || fmt == SB_GUIDE_U8X3;
+}
+__host__ __device__ constexpr int32_t fmt_channels(int32_t fmt) {
+  return fmt == SB_GUIDE_U8X3 ? 3 : 2;
+}
+__host__ __device__ constexpr int32_t fmt_depth(int32_t fmt) {
+  return fmt == SB_GUIDE_U16X2 ? 16 : 8;
+}
+
 // Largest voting tile of the blend (pixels): 256 threads, 4 horizontal
 // pixels each.
 constexpr int32_t kBlendMaxTW = 64, kBlendMaxTH = 16;
@@ -71,6 +82,7 @@ struct FrameArgs {
   uint32_t *offsets;          // workspace: per pixel NNF[p] - p as two int16
   int32_t sw, sh, w, h;
   int32_t lut_bits, lut_shift; // lut_shift = guide depth - lut_bits
+  int32_t lut_log2;            // log2 of the table's entries: channels * lut_bits
   uint32_t threshold;
   int32_t radius;
   int32_t fmt;                 // sb_guide_fmt (read by the batch kernels)

@@ -32,8 +32,9 @@ __device__ __forceinline__ SB_GLOBAL u32x2 *seed_table(const FrameArgs &a) {
   return reinterpret_cast<SB_GLOBAL u32x2 *>(glb(a.seeds));
 }
 
-// A guide texel as stored (2 x u8 or 2 x u16) and unpacked to the u16 pair
-// layout (channel 1 in the high half).
+// A guide texel as stored (2 x u8, 2 x u16 or 3 x u8 in a word) and unpacked
+// to its guide word: two channels as a u16 pair (channel 1 in the high
+// half), or three u8 channels in bytes 0..2 (byte 3 cleared).
 template <int FMT>
 __device__ inline uint32_t guide_raw(const void *g, uint32_t i) {
   if (FMT == SB_GUIDE_U8X2) return glb(static_cast<const uint16_t *>(g))[i];
@@ -42,6 +43,7 @@ __device__ inline uint32_t guide_raw(const void *g, uint32_t i) {
 template <int FMT>
 __device__ inline uint32_t guide_unpack(uint32_t v) {
   if (FMT == SB_GUIDE_U8X2) return (v & 0xFFu) | ((v >> 8) << 16);
+  if (FMT == SB_GUIDE_U8X3) return v & 0xFFFFFFu;
   return v;
 }
 template <int FMT>
@@ -49,20 +51,32 @@ __device__ inline uint32_t guide_word(const void *g, uint32_t i) {
   return guide_unpack<FMT>(guide_raw<FMT>(g, i));
 }
 
-// Lookup-table bin of a guide word (two channels, 16 bits apart).
+// Lookup-table bin of a guide word: c0 | c1 << bits (| c2 << 2 bits), each
+// channel's top `bits` bits.
+template <int FMT>
 __device__ inline uint32_t lut_bin(uint32_t g, int32_t shift, int32_t bits) {
+  if (FMT == SB_GUIDE_U8X3)
+    return ((g & 0xFFu) >> shift) | ((((g >> 8) & 0xFFu) >> shift) << bits) |
+           (((g >> 16) >> shift) << (2 * bits));
   return ((g & 0xFFFFu) >> shift) | (((g >> 16) >> shift) << bits);
 }
 
 // Exact squared L2 error of two guide words compared with t: true iff e < t.
 // 8-bit channels: the differences fit int16, one packed subtract and one
-// dot product.  16-bit channels: 24-bit multiplies (|d| < 2^16, d^2 < 2^32)
-// and a saturating add (a sum that saturates is >= 2^32 - 1 >= t anyway).
+// dot product (three channels: channels 0 and 2 as the packed pair, channel
+// 1's square as the accumulator; e <= 3 * 255^2).  16-bit channels: 24-bit
+// multiplies (|d| < 2^16, d^2 < 2^32) and a saturating add (a sum that
+// saturates is >= 2^32 - 1 >= t anyway).
 template <int FMT>
 __device__ inline bool error_below(uint32_t a, uint32_t b, uint32_t t) {
   if (FMT == SB_GUIDE_U8X2) {
     const short2_t d = __builtin_bit_cast(short2_t, a) - __builtin_bit_cast(short2_t, b);
     return uint32_t(__builtin_amdgcn_sdot2(d, d, 0, false)) < t;
+  } else if (FMT == SB_GUIDE_U8X3) {
+    const uint32_t m = 0x00FF00FFu;
+    const short2_t d = __builtin_bit_cast(short2_t, a & m) - __builtin_bit_cast(short2_t, b & m);
+    const int32_t d1 = int32_t((a >> 8) & 0xFFu) - int32_t((b >> 8) & 0xFFu);
+    return uint32_t(__builtin_amdgcn_sdot2(d, d, __mul24(d1, d1), false)) < t;
   } else {
     const int32_t d0 = int32_t(a & 0xFFFFu) - int32_t(b & 0xFFFFu);
     const int32_t d1 = int32_t(a >> 16) - int32_t(b >> 16);
@@ -106,7 +120,7 @@ __global__ void k_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint
 __device__ inline const uint32_t *lut_of(const FrameArgs &a, uint32_t pidx) {
   if (!a.tgt_labels) return a.lut;
   const uint32_t l = min(uint32_t(glb(a.tgt_labels)[pidx]), uint32_t(a.nlabels - 1));
-  return a.label_luts + (size_t(l) << (2 * a.lut_bits));
+  return a.label_luts + (size_t(l) << a.lut_log2);
 }
 
 // Record idx of the padded seed table.
@@ -126,7 +140,8 @@ __device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
     const uint32_t sy = (uint32_t(cy) << lv.log2_spacing[i]) + (j >> 16);
     if (sx < uint32_t(a.w) && sy < uint32_t(a.h)) {
       const uint32_t g = guide_word<FMT>(a.tgt_guide, sy * uint32_t(a.w) + sx);
-      const uint32_t u = glb(lut_of(a, sy * uint32_t(a.w) + sx))[lut_bin(g, a.lut_shift, a.lut_bits)];
+      const uint32_t u =
+          glb(lut_of(a, sy * uint32_t(a.w) + sx))[lut_bin<FMT>(g, a.lut_shift, a.lut_bits)];
       rec.x = pack_xy(4 * sx, 4 * sy);
       rec.y = pack_off(int32_t(u & 0xFFFFu) - int32_t(sx), int32_t(u >> 16) - int32_t(sy));
     }
@@ -301,9 +316,9 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
 #pragma unroll
   for (int32_t b = 0; b < B; ++b) {
     const uint32_t *table =
-        SEG ? a.label_luts + (size_t(min(lt[b], uint32_t(a.nlabels - 1))) << (2 * a.lut_bits))
+        SEG ? a.label_luts + (size_t(min(lt[b], uint32_t(a.nlabels - 1))) << a.lut_log2)
             : a.lut;
-    own[b] = glb(table)[lut_bin(gt[b], a.lut_shift, a.lut_bits)];
+    own[b] = glb(table)[lut_bin<FMT>(gt[b], a.lut_shift, a.lut_bits)];
     p4[b] = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x[b]), uint32_t(4 * y)));
     chunk[b] = off[b] = 0;
     done[b] = !in[b];
@@ -366,7 +381,7 @@ __device__ inline void assign_pixel(const FrameArgs &a, int32_t x, int32_t y) {
     }
   }
   if (!done) {
-    const uint32_t u = glb(lut_of(a, pidx))[lut_bin(gt, a.lut_shift, a.lut_bits)];
+    const uint32_t u = glb(lut_of(a, pidx))[lut_bin<FMT>(gt, a.lut_shift, a.lut_bits)];
     chunk = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
     off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
   }
@@ -663,6 +678,7 @@ __global__ void __launch_bounds__(256) k_batch_seeds(const unsigned char *desc) 
   batch_loop<0, 256, 1>(desc, [](const FrameArgs &fa, uint32_t local, uint32_t *) {
     const uint32_t idx = local * 256 + threadIdx.x;
     if (fa.fmt == SB_GUIDE_U8X2) seeds_body<SB_GUIDE_U8X2>(fa, idx);
+    else if (fa.fmt == SB_GUIDE_U8X3) seeds_body<SB_GUIDE_U8X3>(fa, idx);
     else seeds_body<SB_GUIDE_U16X2>(fa, idx);
   });
 }
@@ -675,6 +691,9 @@ __global__ void __launch_bounds__(256) k_batch_assign(const unsigned char *desc)
     if (fa.fmt == SB_GUIDE_U8X2) {
       if (seg) assign_tile<SB_GUIDE_U8X2, G, B, true>(fa, local, threadIdx.x, w);
       else assign_tile<SB_GUIDE_U8X2, G, B, false>(fa, local, threadIdx.x, w);
+    } else if (fa.fmt == SB_GUIDE_U8X3) {
+      if (seg) assign_tile<SB_GUIDE_U8X3, G, B, true>(fa, local, threadIdx.x, w);
+      else assign_tile<SB_GUIDE_U8X3, G, B, false>(fa, local, threadIdx.x, w);
     } else {
       if (seg) assign_tile<SB_GUIDE_U16X2, G, B, true>(fa, local, threadIdx.x, w);
       else assign_tile<SB_GUIDE_U16X2, G, B, false>(fa, local, threadIdx.x, w);
@@ -755,12 +774,15 @@ hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, const Tune &t, hipEve
   if (e == hipSuccess && c[0] > 0) {
     if (fmt == SB_GUIDE_U8X2)
       k_seeds<SB_GUIDE_U8X2><<<c[0], 256, 0, stream>>>(a);
+    else if (fmt == SB_GUIDE_U8X3)
+      k_seeds<SB_GUIDE_U8X3><<<c[0], 256, 0, stream>>>(a);
     else
       k_seeds<SB_GUIDE_U16X2><<<c[0], 256, 0, stream>>>(a);
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[1], stream);
   if (e == hipSuccess) {
     if (fmt == SB_GUIDE_U8X2) launch_assign_any<SB_GUIDE_U8X2>(a, t, c[1], stream);
+    else if (fmt == SB_GUIDE_U8X3) launch_assign_any<SB_GUIDE_U8X3>(a, t, c[1], stream);
     else launch_assign_any<SB_GUIDE_U16X2>(a, t, c[1], stream);
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[2], stream);

@@ -66,10 +66,16 @@ def test_workspace_sizes(L):
     n = sb.workspace_bytes(1920, 1080, p)
     assert n >= 1920 * 1080 * 4 + sb.jitter_len(1920, 1080, 4, 8) * 8
     assert L.sb_workspace_bytes(1920, 1080, ctypes.byref(sb.params(4, 8, 32, 8))) == 0  # r > 7
-    assert L.sb_lut_workspace_bytes(0, 512, 512, 8) >= 512 * 512 * 8
+    # 8-bit guides: the separable build's key grids, independent of the source size
+    assert L.sb_lut_workspace_bytes(0, 512, 512, 8) == 256 * 256 * 8 + 256 * 256 * 4
+    assert L.sb_lut_workspace_bytes(0, 7, 3, 8) == 256 * 256 * 8 + 256 * 256 * 4
+    assert L.sb_lut_workspace_bytes(2, 512, 512, 8) == 2 * (128 << 20)
+    assert L.sb_lut_workspace_bytes(2, 512, 512, 4) == (256 * 256 * 16 * 8 + (64 << 20))
     assert L.sb_lut_workspace_bytes(0, 512, 512, 9) == 0  # 9 bits from an 8-bit guide
+    assert L.sb_lut_workspace_bytes(2, 512, 512, 9) == 0
     assert L.sb_lut_workspace_bytes(1, 512, 512, 13) == 0
-    assert L.sb_lut_workspace_bytes(2, 512, 512, 8) == 0
+    assert L.sb_lut_workspace_bytes(1, 512, 512, 11) >= 512 * 512 * 8
+    assert L.sb_lut_workspace_bytes(3, 512, 512, 8) == 0  # no such format
 
 
 def test_validation_rejects_before_launch(L):
