@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-seg", action="store_true", help="skip the segmentation-guide leg")
     ap.add_argument("--no-anim", action="store_true", help="skip the animation leg")
+    ap.add_argument("--no-channels", action="store_true",
+                    help="skip the three-channel (appearance) guide leg")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-qps", type=str, default="2000,12000,18000,24000",
                     help="comma-separated request rates of the serving sweep")
@@ -207,6 +209,7 @@ def main():
 
     seg = None if args.no_seg else seg_leg(sb, torch, np, workloads, st_np, fr, prm, ms_per_step)
     anim = None if args.no_anim else anim_leg(sb, torch, np, workloads, style, w, h, p)
+    chan = None if args.no_channels else channels_leg(sb, torch, np, workloads, ms_per_step)
     batch = None if args.no_batch else batch_leg(sb, at, torch, workloads, args.no_tune)
     serve = None
     if not args.no_serve:
@@ -254,6 +257,7 @@ def main():
         "cpu_baseline": cpu,
         "segmentation": seg,
         "animation": anim,
+        "three_channels": chan,
         "batch": batch,
         "serve": serve,
     }
@@ -292,6 +296,47 @@ def seg_leg(sb, torch, np, workloads, st_np, fr, prm, plain_ms, nlabels=6, steps
             "vs_plain": round(plain_ms / ms, 3),
             "fallback_fraction": round(float((lv == prm.levels).mean()), 4),
             "label_tables_mib": round(style.label_luts.numel() * 4 / 2**20, 2)}
+
+
+def channels_leg(sb, torch, np, workloads, plain_ms, steps=100):
+    """The appearance workload: a 1080p target with two normal channels plus
+    an appearance channel, the 512x512 style's exact table over 2^24 bins
+    (three 8-bit channels).  Style registration (table build included) and
+    the frame, against the two-channel frame of the main leg."""
+    styles, frames = workloads.config(6)
+    st_np, fr = styles[0], frames[0]
+    p = fr.params
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
+    style = sb.Style(st_np.rgb, st_np.guide, st_np.lut_bits)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    style = sb.Style(st_np.rgb, st_np.guide, st_np.lut_bits)
+    torch.cuda.synchronize()
+    reg_ms = (time.perf_counter() - t0) * 1e3
+    g = torch.from_numpy(fr.guide).cuda()
+    jit = torch.from_numpy(fr.jitter.view(np.int32)).cuda()
+    rgb = torch.empty((fr.h, fr.w, 3), dtype=torch.uint8, device="cuda")
+    chunk = torch.empty((fr.h, fr.w), dtype=torch.int32, device="cuda")
+    ws = torch.empty(sb.workspace_bytes(fr.w, fr.h, prm), dtype=torch.uint8, device="cuda")
+
+    def run():
+        sb.stylize(style, g, jit, prm, out_rgb=rgb, out_chunk=chunk, workspace=ws)
+
+    for _ in range(10):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    lv = chunk.cpu().numpy().view(np.uint32) >> 26
+    return {"workload": workloads.CONFIG_NAMES[6], "ms_per_frame": round(ms, 6),
+            "mpixel_per_s": round(fr.w * fr.h / (ms * 1e-3) / 1e6, 2),
+            "vs_two_channel": round(plain_ms / ms, 3),
+            "fallback_fraction": round(float((lv == p.levels).mean()), 4),
+            "table_mib": round(style.lut.numel() * 4 / 2**20, 1),
+            "style_registration_ms": round(reg_ms, 3)}
 
 
 def anim_leg(sb, torch, np, workloads, style, w, h, p, nframes=12, reps=5):
