@@ -31,10 +31,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs, each issuing one wave64 instruction
+# every 4 cycles (16 lanes per cycle), at 2.4 GHz = 614.4 G wave instructions/s
+VALU_PEAK_G_WAVE_INSTR = 256 * 2.4
 # counter summary of the voting kernel at 1080p (FETCH_SIZE / WRITE_SIZE per
 # dispatch and the copy-kernel calibration), valid for the kernel source it
 # names
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_1080p_traffic.json")
+# instruction counts of the per-frame kernels at 1080p (SQ_INSTS_VALU etc. per
+# dispatch), valid for the kernel source it names
+INSTR_FILE = os.path.join(ROOT, "profiles", "path_1080p_instructions.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1807_03249_amd", "csrc", "stylize.hip")
 
 
@@ -72,6 +78,28 @@ def traffic_per_launch(workload_name):
     fetch = t["fetch_kib_per_dispatch"] * 1024.0 / t["copy_fetch_factor"]
     write = t["write_kib_per_dispatch"] * 1024.0 / t["copy_write_factor"]
     return fetch + write
+
+
+def valu_issue(workload_name, kernel_prefix, kernel_ms):
+    """Vector-ALU issue rate of one per-frame kernel: its wave instructions
+    per launch from the committed counter summary over the live kernel time,
+    against the issue peak; None when the summary is missing, for another
+    workload, or for older kernel source."""
+    try:
+        with open(INSTR_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_sha() or t.get("workload") != workload_name:
+        return None
+    for name, k in t["kernels"].items():
+        if name.startswith(kernel_prefix):
+            g = k["valu_wave_instructions"] / (kernel_ms * 1e-3) / 1e9
+            return {"kernel": name, "valu_wave_instructions": k["valu_wave_instructions"],
+                    "lane_ops_per_px": round(k["valu_wave_instructions"] * 64 / t["pixels"], 1),
+                    "achieved": round(g, 1), "peak": VALU_PEAK_G_WAVE_INSTR,
+                    "unit": "G wave instructions/s", "frac": round(g / VALU_PEAK_G_WAVE_INSTR, 4)}
+    return None
 
 
 def main():
@@ -187,12 +215,26 @@ def main():
     vote_gbs = vbytes / (vote_ms * 1e-3) / 1e9
     traffic = traffic_per_launch(wname)
 
+    # a streaming device copy of 1 GiB on this GPU: what HBM sustains for
+    # plain reads and writes (reported beside the 8 TB/s peak)
+    csrc = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cdst.copy_(csrc)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = round(2 * 10 * csrc.numel() / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del csrc, cdst
+
     cpu = None
     if not args.no_cpu:
         import oracle
 
         lut = oracle.lut_build(st_np.guide, st_np.lut_bits)
-        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        nthreads = oracle.set_threads(0)
         n = 0
         c0 = time.perf_counter()
         while True:
@@ -206,6 +248,20 @@ def main():
                "kind": "oracle",
                "sample": f"{n} full {w}x{h} frames of this workload (lookup table built once, "
                          f"not timed), OpenMP over rows"}
+        # the same oracle on one thread (the paper-like single-core figure)
+        oracle.set_threads(1)
+        n1 = 0
+        c0 = time.perf_counter()
+        while True:
+            oracle.stylize(st_np.rgb, st_np.guide, lut, st_np.lut_bits, fr.guide, fr.jitter,
+                           p.levels, p.finest, p.threshold, p.radius)
+            n1 += 1
+            if time.perf_counter() - c0 >= args.cpu_seconds / 4 or n1 >= 20:
+                break
+        c1 = time.perf_counter() - c0
+        oracle.set_threads(nthreads)
+        cpu["single_thread"] = {"value": round(w * h * n1 / c1 / 1e6, 3),
+                                "sample": f"{n1} full {w}x{h} frames on one thread"}
 
     seg = None if args.no_seg else seg_leg(sb, torch, np, workloads, st_np, fr, prm, ms_per_step)
     anim = None if args.no_anim else anim_leg(sb, torch, np, workloads, style, w, h, p)
@@ -253,7 +309,12 @@ def main():
                      "achieved": round(vote_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(vote_gbs / HBM_PEAK_GBS, 5),
                      "traffic": round(traffic) if traffic is not None else None,
+                     "traffic_gbs": (round(traffic / (vote_ms * 1e-3) / 1e9, 2)
+                                     if traffic is not None else None),
                      "kernel_ms": round(float(vote_ms), 6), "algorithmic_bytes": vbytes},
+        "hbm_stream_copy_gbs": copy_gbs,
+        "valu_issue": {"vote": valu_issue(wname, "k_blend<", float(vote_ms)),
+                       "level_loop": valu_issue(wname, "k_assign<", float(assign_ms))},
         "cpu_baseline": cpu,
         "segmentation": seg,
         "animation": anim,

@@ -83,6 +83,7 @@ def _load():
                                 i32, ctypes.c_uint32, i32, _u8p, _u32p, _u32p]
     lib.ora_lut_build_labels.argtypes = [vp, _u8p, i32, i32, i32, i32, i32, _u32p]
     lib.ora_lut_query.argtypes = [vp, i32, i32, i32, i32, _i64p, ctypes.c_int64, _u32p]
+    lib.ora_set_threads.argtypes = [i32]
     lib.ora_stylize_seg.argtypes = [_u8p, vp, _u8p, i32, i32, _u32p, i32, i32, i32, vp, _u8p,
                                     i32, i32, _u32p, i32, i32, ctypes.c_uint32, i32, _u8p, _u32p,
                                     _u32p]
@@ -127,6 +128,12 @@ def _jit(jitter: Optional[np.ndarray], w: int, h: int, levels: int, finest: int)
 def _check(rc: int, what: str):
     if rc != 0:
         raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops (n <= 0: unchanged); returns the
+    number in effect.  Timing only: results do not depend on it."""
+    return int(_load().ora_set_threads(int(n)))
 
 
 def jitter_len(w: int, h: int, levels: int, finest: int) -> int:

@@ -59,6 +59,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORA_OK 0
 #define ORA_EINVAL (-1)
@@ -235,6 +238,19 @@ static int lut_build_filtered(const void *src_guide, const uint8_t *labels, int 
     free(list);
     free(fill);
     return ORA_OK;
+}
+
+/* Threads of the OpenMP loops (timing only; results do not depend on it).
+ * n <= 0 leaves the setting.  Returns the number now in effect. */
+int ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 int ora_lut_build(const void *src_guide, int fmt, int sw, int sh, int lut_bits, uint32_t *lut)
