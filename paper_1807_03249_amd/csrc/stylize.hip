@@ -458,6 +458,20 @@ __device__ __forceinline__ void load_texels(const SB_GLOBAL unsigned char *ex, u
   }
 }
 
+// Per-lane select r = (lane's bit of mask) ? a : b as one v_cndmask, and
+// the lane mask of a == b as one v_cmp: written out so the compiler neither
+// branches around copies nor turns a mask into a 0/1 value and back.
+__device__ __forceinline__ uint32_t lane_select(uint64_t mask, uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+  return r;
+}
+__device__ __forceinline__ uint64_t lane_equal(int32_t a, int32_t b) {
+  uint64_t m;
+  asm("v_cmp_eq_u32_e64 %0, %1, %2" : "=s"(m) : "v"(a), "v"(b));
+  return m;
+}
+
 // Texels of the lane's PPT pixels for one window cell, indexed by pixel J
 // (only J0(c)..J1(c) are meaningful).
 template <int PPT>
@@ -465,34 +479,56 @@ struct TexelsN {
   uint32_t t[PPT];
 };
 
-// The votes of cell column C (0 .. 2R+PPT-1) of one window row for the
-// lane's pixels J = C - 2R .. C (clipped to 0..PPT-1).  Every vote of a cell
-// with offset o for pixel p is the texel at p + o, so a cell with the same
-// offset as the cell above it (same column, previous row) or, from column PPT
-// on, as its left neighbour needs texels the lane already holds; only lanes
-// whose cell starts a new offset issue the gather, one vector load of the
-// pixels' adjacent texels.
+// Cell column C (0 .. 2R+PPT-1) of one window row votes for the lane's
+// pixels J = C - 2R .. C (clipped to 0..PPT-1).  Every vote of a cell with
+// offset o for pixel p is the texel at p + o, so a cell with the same offset
+// as the cell above it (same column, previous row) or, from column PPT on, as
+// its left neighbour needs texels the lane already holds; only lanes whose
+// cell starts a new offset issue the gather, one vector load of the pixels'
+// adjacent texels.  Two phases per row: first every cell's gather, landing
+// over the upper cell's texels (so no gather waits for another), then in
+// column order the left-neighbour reuse (one select) and the sums.
 template <int R, int PPT, int C>
-__device__ __forceinline__ void vote_cell(const SB_GLOBAL unsigned char *ex, uint32_t pbase,
-                                          const int32_t *cells, const int32_t *up_cells,
-                                          TexelsN<PPT> *row, const TexelsN<PPT> *up_row,
-                                          uint32_t *S, uint32_t *RB) {
-  constexpr int J0 = C - 2 * R > 0 ? C - 2 * R : 0;
-  constexpr int J1 = C < PPT - 1 ? C : PPT - 1;
-  constexpr int N = J1 - J0 + 1;
-  const int32_t lin = cells[C];
-  const bool up = lin == up_cells[C];
-  const bool left = C >= PPT && lin == cells[C > 0 ? C - 1 : 0];
-  uint32_t t[PPT] = {};
-  if (!up && !left) load_texels<N>(ex, pbase + 4u * J0 + uint32_t(lin), t);
+__device__ __forceinline__ void vote_gather(const SB_GLOBAL unsigned char *ex, uint32_t pbase,
+                                            const int32_t *cells, const int32_t *up_cells,
+                                            TexelsN<PPT> *row, const TexelsN<PPT> *up_row) {
+  if constexpr (C < 2 * R + PPT) {
+    constexpr int J0 = C - 2 * R > 0 ? C - 2 * R : 0;
+    constexpr int J1 = C < PPT - 1 ? C : PPT - 1;
+    constexpr int N = J1 - J0 + 1;
+    const int32_t lin = cells[C];
+    const bool up = lin == up_cells[C];
+    const bool left = C >= PPT && lin == cells[C > 0 ? C - 1 : 0];
+    uint32_t t[PPT];
 #pragma unroll
-  for (int m = 0; m < N; ++m) {
-    uint32_t v = t[m];
-    if (left) v = row[C > 0 ? C - 1 : 0].t[J0 + m];
-    if (up) v = up_row[C].t[J0 + m];
-    row[C].t[J0 + m] = v;
-    S[J0 + m] += v;
-    RB[J0 + m] += v & 0x00FF00FFu;
+    for (int m = 0; m < N; ++m) t[m] = up_row[C].t[J0 + m];
+    if (!up && !left) load_texels<N>(ex, pbase + 4u * J0 + uint32_t(lin), t);
+#pragma unroll
+    for (int m = 0; m < N; ++m) row[C].t[J0 + m] = t[m];
+    vote_gather<R, PPT, C + 1>(ex, pbase, cells, up_cells, row, up_row);
+  }
+}
+
+template <int R, int PPT, int C>
+__device__ __forceinline__ void vote_sum(const int32_t *cells, TexelsN<PPT> *row, uint32_t *S,
+                                         uint32_t *RB) {
+  if constexpr (C < 2 * R + PPT) {
+    constexpr int J0 = C - 2 * R > 0 ? C - 2 * R : 0;
+    constexpr int J1 = C < PPT - 1 ? C : PPT - 1;
+    constexpr int N = J1 - J0 + 1;
+    if constexpr (C >= PPT) {
+      const uint64_t left = lane_equal(cells[C], cells[C - 1]);
+#pragma unroll
+      for (int m = 0; m < N; ++m)
+        row[C].t[J0 + m] = lane_select(left, row[C - 1].t[J0 + m], row[C].t[J0 + m]);
+    }
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      const uint32_t v = row[C].t[J0 + m];
+      S[J0 + m] += v;
+      RB[J0 + m] += v & 0x00FF00FFu;
+    }
+    vote_sum<R, PPT, C + 1>(cells, row, S, RB);
   }
 }
 
@@ -501,10 +537,8 @@ __device__ __forceinline__ void vote_row(const SB_GLOBAL unsigned char *ex, uint
                                          const int32_t *cells, const int32_t *up_cells,
                                          TexelsN<PPT> *row, const TexelsN<PPT> *up_row,
                                          uint32_t *S, uint32_t *RB) {
-  if constexpr (C < 2 * R + PPT) {
-    vote_cell<R, PPT, C>(ex, pbase, cells, up_cells, row, up_row, S, RB);
-    vote_row<R, PPT, C + 1>(ex, pbase, cells, up_cells, row, up_row, S, RB);
-  }
+  vote_gather<R, PPT, C>(ex, pbase, cells, up_cells, row, up_row);
+  vote_sum<R, PPT, C>(cells, row, S, RB);
 }
 
 // One (16 PPT) x TH pixel voting tile with 16 TH threads: thread t votes for
