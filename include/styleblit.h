@@ -343,6 +343,8 @@ typedef struct {
                                    session complete in arrival order (a later frame's
                                    kernels wait for the earlier frame's batch when it runs
                                    on another slot).  < 0: independent request */
+    const uint8_t *tgt_labels;  /* [device] or NULL: W*H target labels, the frame runs with
+                                   the segmentation guide (the style must carry labels) */
 } sb_request;
 
 typedef struct {

@@ -89,6 +89,16 @@ struct Slot {
   std::vector<int32_t> reqs;
 };
 
+// One frame through the per-frame entry points (with the segmentation guide
+// when the frame carries target labels).
+int run_one(const sb_frame &f, void *ws, size_t ws_bytes, const sb_tune *tune, hipStream_t s) {
+  if (f.tgt_labels)
+    return sb_stylize_seg(f.style, f.tgt_guide, f.tgt_labels, f.w, f.h, f.jitter, &f.params,
+                          f.out_rgb, f.out_chunk, f.out_nnf, ws, ws_bytes, tune, s);
+  return sb_stylize_ex(f.style, f.tgt_guide, f.w, f.h, f.jitter, &f.params, f.out_rgb,
+                       f.out_chunk, f.out_nnf, ws, ws_bytes, tune, s);
+}
+
 // Where the latest launched frame of a session runs.
 struct SessionTail {
   int32_t slot, batch;
@@ -125,7 +135,7 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
     uint8_t *probe_rgb = r.out_rgb ? r.out_rgb : reinterpret_cast<uint8_t *>(1);
     uint32_t *probe_chunk = r.out_chunk ? r.out_chunk : reinterpret_cast<uint32_t *>(1);
     if (!fill_frame(r.style, r.tgt_guide, r.w, r.h, r.jitter, &r.params, probe_rgb, probe_chunk,
-                    nullptr, &a))
+                    nullptr, &a, r.tgt_labels))
       return SB_EINVAL;
     if (i > 0 && r.arrival_s < reqs[i - 1].arrival_s) return SB_EINVAL;  // sorted arrivals
     if ((r.out_rgb == nullptr) != (r.out_chunk == nullptr)) return SB_EINVAL;  // both or neither
@@ -204,7 +214,7 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
                                 : reinterpret_cast<uint32_t *>(
                                       base + ((size_t(r.w) * r.h * 3 + 255) & ~size_t(255)));
       f.out_nnf = r.out_nnf;
-      f.tgt_labels = nullptr;
+      f.tgt_labels = r.tgt_labels;
       res[i].admitted_s = now_s(t0);
       admitted.push_back(i);
       pending.pop_front();
@@ -250,9 +260,8 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
       while (!admitted.empty() && plain_inflight.size() < pev.size()) {
         const int32_t i = admitted.front();
         const sb_frame &f = fr[i];
-        const int r = sb_stylize_ex(f.style, f.tgt_guide, f.w, f.h, f.jitter, &f.params,
-                                    f.out_rgb, f.out_chunk, f.out_nnf, sl[0].workspace,
-                                    cfg->workspace_bytes_per_slot, &cfg->tune, sl[0].stream);
+        const int r = run_one(f, sl[0].workspace, cfg->workspace_bytes_per_slot, &cfg->tune,
+                              sl[0].stream);
         if (r != SB_OK) {
           rc = r;
           break;
@@ -294,10 +303,8 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
         // frame, no descriptor upload); larger batches replay the plan
         const sb_frame &f0 = bf[0];
         const int r = bf.size() == 1
-                          ? sb_stylize_ex(f0.style, f0.tgt_guide, f0.w, f0.h, f0.jitter,
-                                          &f0.params, f0.out_rgb, f0.out_chunk, f0.out_nnf,
-                                          S.workspace, cfg->workspace_bytes_per_slot, &cfg->tune,
-                                          S.stream)
+                          ? run_one(f0, S.workspace, cfg->workspace_bytes_per_slot, &cfg->tune,
+                                    S.stream)
                           : sb_batch_run(S.plan, bf.data(), int32_t(bf.size()), S.workspace,
                                          cfg->workspace_bytes_per_slot, S.stream);
         if (r != SB_OK) {

@@ -30,7 +30,8 @@ class SbRequest(ctypes.Structure):
                 ("tgt_guide", ctypes.c_void_p), ("jitter", ctypes.c_void_p),
                 ("w", ctypes.c_int32), ("h", ctypes.c_int32), ("params", SbParams),
                 ("out_rgb", ctypes.c_void_p), ("out_chunk", ctypes.c_void_p),
-                ("out_nnf", ctypes.c_void_p), ("session", ctypes.c_int32)]
+                ("out_nnf", ctypes.c_void_p), ("session", ctypes.c_int32),
+                ("tgt_labels", ctypes.c_void_p)]
 
 
 class SbRequestResult(ctypes.Structure):
@@ -56,10 +57,12 @@ class Request:
     """One request: a resident style, a device-resident target guide and
     jitter table, the frame parameters and (optionally) output tensors.
     ``session`` >= 0 marks a frame of an animated sequence: frames of one
-    session complete in arrival order."""
+    session complete in arrival order.  ``tgt_labels`` (uint8 (H, W) device
+    tensor) runs the frame with the segmentation guide."""
 
     def __init__(self, arrival_s: float, style: Style, guide, jitter, p: SbParams,
-                 out_rgb=None, out_chunk=None, out_nnf=None, session: int = -1):
+                 out_rgb=None, out_chunk=None, out_nnf=None, session: int = -1,
+                 tgt_labels=None):
         self.arrival_s = float(arrival_s)
         self.style = style
         self.guide = guide
@@ -69,6 +72,7 @@ class Request:
         self.out_chunk = out_chunk
         self.out_nnf = out_nnf
         self.session = int(session)
+        self.tgt_labels = tgt_labels
 
     @property
     def h(self):
@@ -97,7 +101,8 @@ def run(requests: Sequence[Request], slots: int = 4, max_batch: int = 16,
                             r.out_rgb.data_ptr() if r.out_rgb is not None else None,
                             r.out_chunk.data_ptr() if r.out_chunk is not None else None,
                             r.out_nnf.data_ptr() if r.out_nnf is not None else None,
-                            r.session)
+                            r.session,
+                            r.tgt_labels.data_ptr() if r.tgt_labels is not None else None)
         max_ws = max(max_ws, workspace_bytes(r.w, r.h, r.params))
     nslots = 1 if plain else slots
     mb = 1 if plain else max_batch

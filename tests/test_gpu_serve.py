@@ -103,3 +103,50 @@ def test_request_larger_than_budget_is_refused(env):
     sizes = np.array([sv._bind().sb_frame_bytes(r.w, r.h) for r in reqs])
     assert np.all(out["status"][sizes > budget] == sb.SB_EBUDGET)
     assert np.all(out["status"][sizes <= budget] == sb.SB_OK)
+
+
+def test_mixed_guides_labels_and_sessions(env):
+    """One trace mixing two-channel, three-channel (appearance) and
+    segmentation-guided requests, some in sessions: every result equals the
+    request run alone, and sessions complete in order."""
+    import torch
+
+    sb, sv, trace, styles = env
+    s2_np = workloads.config(1)[0][0]
+    s2 = sb.Style(s2_np.rgb, s2_np.guide, s2_np.lut_bits)
+    s3_np = workloads.config(6, lut_bits=6, w=64, h=64)[0][0]
+    s3 = sb.Style(s3_np.rgb, s3_np.guide, 6)
+    ls = workloads.voronoi_labels(s2_np.sw, s2_np.sh, 4, 10, 81)
+    sl = sb.Style(s2_np.rgb, s2_np.guide, s2_np.lut_bits, labels=ls, nlabels=4)
+    prm = sb.params(3, 8, 64, 2)
+    rng = np.random.default_rng(82)
+    reqs = []
+    for i in range(36):
+        w, h = int(rng.integers(64, 700)), int(rng.integers(48, 500))
+        kind = i % 3
+        if kind == 0:
+            st, g, lab = s2, workloads.bump_guide_u8(w, h, 4, 900 + i), None
+        elif kind == 1:
+            st, g, lab = s3, workloads.appearance_target(w, h, 4, 900 + i), None
+        else:
+            st, g = sl, workloads.bump_guide_u8(w, h, 4, 900 + i)
+            lab = torch.from_numpy(workloads.voronoi_labels(w, h, 5, 8, 950 + i)).cuda()
+        jit = torch.from_numpy(workloads.jitter_table(w, h, 3, 8, 990 + i).view(np.int32)).cuda()
+        reqs.append(sv.Request(i * 2e-5, st, torch.from_numpy(g).cuda(), jit, prm,
+                               torch.empty((h, w, 3), dtype=torch.uint8, device="cuda"),
+                               torch.empty((h, w), dtype=torch.int32, device="cuda"),
+                               torch.empty((h, w), dtype=torch.int32, device="cuda"),
+                               session=(i % 4) if i < 24 else -1, tgt_labels=lab))
+    say("serve 36 mixed requests (two/three channels, labels, sessions)")
+    out = sv.run(reqs, slots=3, max_batch=4, budget_bytes=1 << 30)
+    assert np.all(out["status"] == sb.SB_OK)
+    for s in range(4):
+        idx = np.nonzero(out["session"] == s)[0]
+        assert np.all(np.diff(out["completed"][idx]) >= 0)
+    for i, r in enumerate(reqs):
+        rgb, chunk, nnf = sb.stylize(r.style, r.guide, r.jitter, r.params, want_nnf=True,
+                                     tgt_labels=r.tgt_labels)
+        torch.cuda.synchronize()
+        assert torch.equal(r.out_rgb, rgb), f"request {i}"
+        assert torch.equal(r.out_chunk, chunk), f"request {i}"
+        assert torch.equal(r.out_nnf, nnf), f"request {i}"
