@@ -29,7 +29,10 @@ Sec. 3.1) are pinned in ``tests/test_oracle_channels.py``: the table against
 an independent vectorised argmin and a full-coverage closed form, the
 reduction to the two-channel path when the third channel is constant, an
 adversarial third channel that alone decides acceptance, and the level
-loop's invariants with the three-channel error.
+loop's invariants with the three-channel error.  Channel weights (the
+strong or weak appearance guide) are pinned by a weighted vectorised argmin,
+a zero weight that reduces the path to the first two channels, and uniform
+weights that only rescale the threshold.
 """
 from __future__ import annotations
 
@@ -84,6 +87,17 @@ def _load():
     lib.ora_lut_build_labels.argtypes = [vp, _u8p, i32, i32, i32, i32, i32, _u32p]
     lib.ora_lut_query.argtypes = [vp, i32, i32, i32, i32, _i64p, ctypes.c_int64, _u32p]
     lib.ora_set_threads.argtypes = [i32]
+    lib.ora_lut_build_w.argtypes = [vp, i32, i32, i32, i32, _u8p, _u32p]
+    lib.ora_lut_query_w.argtypes = [vp, i32, i32, i32, i32, _u8p, _i64p, ctypes.c_int64, _u32p]
+    lib.ora_lut_build_labels_w.argtypes = [vp, _u8p, i32, i32, i32, i32, i32, _u8p, _u32p]
+    lib.ora_assign_w.argtypes = [vp, i32, i32, _u32p, i32, i32, _u8p, vp, i32, i32, _u32p, i32,
+                                 i32, ctypes.c_uint32, _u32p, _u32p, ctypes.c_int64,
+                                 ctypes.c_int64]
+    lib.ora_stylize_w.argtypes = [_u8p, vp, i32, i32, _u32p, i32, i32, _u8p, vp, i32, i32, _u32p,
+                                  i32, i32, ctypes.c_uint32, i32, _u8p, _u32p, _u32p]
+    lib.ora_stylize_seg_w.argtypes = [_u8p, vp, _u8p, i32, i32, _u32p, i32, i32, i32, _u8p, vp,
+                                      _u8p, i32, i32, _u32p, i32, i32, ctypes.c_uint32, i32,
+                                      _u8p, _u32p, _u32p]
     lib.ora_stylize_seg.argtypes = [_u8p, vp, _u8p, i32, i32, _u32p, i32, i32, i32, vp, _u8p,
                                     i32, i32, _u32p, i32, i32, ctypes.c_uint32, i32, _u8p, _u32p,
                                     _u32p]
@@ -115,6 +129,16 @@ def _bins(fmt: int, lut_bits: int) -> int:
     return 1 << ((3 if fmt == 2 else 2) * lut_bits)
 
 
+def _weights(weights):
+    """Channel weights as a ctypes pointer (None: unit weights)."""
+    if weights is None:
+        return None, None
+    w = np.ascontiguousarray(weights, dtype=np.uint8)
+    if w.size != 3:
+        raise ValueError("weights must hold three values")
+    return w, _ptr(w, _u8p)
+
+
 def _jit(jitter: Optional[np.ndarray], w: int, h: int, levels: int, finest: int) -> np.ndarray:
     n = jitter_len(w, h, levels, finest)
     if jitter is None:
@@ -140,24 +164,27 @@ def jitter_len(w: int, h: int, levels: int, finest: int) -> int:
     return int(_load().ora_jitter_len(w, h, levels, finest))
 
 
-def lut_build(src_guide: np.ndarray, lut_bits: int) -> np.ndarray:
+def lut_build(src_guide: np.ndarray, lut_bits: int, weights=None) -> np.ndarray:
     """Exact lookup table, (2**lut_bits)**2 entries ((2**lut_bits)**3 for
-    three-channel guides), entries x | y << 16."""
+    three-channel guides), entries x | y << 16.  ``weights``: three channel
+    weights 0..127 of a three-channel guide (None: unit)."""
     g, fmt = _guide(src_guide)
     lut = np.zeros(_bins(fmt, lut_bits), np.uint32)
-    _check(_load().ora_lut_build(g.ctypes.data, fmt, g.shape[1], g.shape[0], lut_bits,
-                                 _ptr(lut, _u32p)), "lut_build")
+    w, wp = _weights(weights)
+    _check(_load().ora_lut_build_w(g.ctypes.data, fmt, g.shape[1], g.shape[0], lut_bits, wp,
+                                   _ptr(lut, _u32p)), "lut_build")
     return lut
 
 
-def lut_query(src_guide: np.ndarray, lut_bits: int, bins) -> np.ndarray:
+def lut_query(src_guide: np.ndarray, lut_bits: int, bins, weights=None) -> np.ndarray:
     """Selected entries of the lookup table, each by brute force over every
     source pixel (for sampling tables too large to build here)."""
     g, fmt = _guide(src_guide)
     b = np.ascontiguousarray(bins, dtype=np.int64)
     out = np.zeros(b.size, np.uint32)
-    _check(_load().ora_lut_query(g.ctypes.data, fmt, g.shape[1], g.shape[0], lut_bits,
-                                 _ptr(b, _i64p), b.size, _ptr(out, _u32p)), "lut_query")
+    w, wp = _weights(weights)
+    _check(_load().ora_lut_query_w(g.ctypes.data, fmt, g.shape[1], g.shape[0], lut_bits, wp,
+                                   _ptr(b, _i64p), b.size, _ptr(out, _u32p)), "lut_query")
     return out
 
 
@@ -180,7 +207,7 @@ def nearest_seed(w, h, levels, finest, jitter, level, px, py):
 
 
 def assign(src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest, threshold,
-           rows: Optional[Tuple[int, int]] = None):
+           rows: Optional[Tuple[int, int]] = None, weights=None):
     """Per-pixel level loop only: returns (nnf, chunk), both uint32 (H, W).
     With ``rows=(row0, n)`` only those rows are computed (others stay 0)."""
     gs, fmt = _guide(src_guide)
@@ -195,9 +222,11 @@ def assign(src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest, threshol
     nnf = np.zeros((h, w), np.uint32)
     chunk = np.zeros((h, w), np.uint32)
     r0, nr = rows if rows is not None else (0, -1)
-    _check(_load().ora_assign(gs.ctypes.data, gs.shape[1], gs.shape[0], _ptr(lut, _u32p), fmt,
-                              lut_bits, gt.ctypes.data, w, h, _ptr(j, _u32p), levels, finest,
-                              threshold, _ptr(nnf, _u32p), _ptr(chunk, _u32p), r0, nr), "assign")
+    wt, wp = _weights(weights)
+    _check(_load().ora_assign_w(gs.ctypes.data, gs.shape[1], gs.shape[0], _ptr(lut, _u32p), fmt,
+                                lut_bits, wp, gt.ctypes.data, w, h, _ptr(j, _u32p), levels,
+                                finest, threshold, _ptr(nnf, _u32p), _ptr(chunk, _u32p), r0, nr),
+           "assign")
     return nnf, chunk
 
 
@@ -215,9 +244,10 @@ def blend(src_rgb: np.ndarray, nnf: np.ndarray, radius: int,
 
 
 def stylize(src_rgb, src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest, threshold,
-            radius):
+            radius, weights=None):
     """The whole per-frame path: returns (rgb (H,W,3) uint8, chunk (H,W) uint32,
-    nnf (H,W) uint32)."""
+    nnf (H,W) uint32).  ``weights``: channel weights of a three-channel guide
+    (the table must be built with the same weights)."""
     gs, fmt = _guide(src_guide)
     gt, fmt_t = _guide(tgt_guide)
     if fmt != fmt_t:
@@ -231,10 +261,12 @@ def stylize(src_rgb, src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest
     out = np.zeros((h, w, 3), np.uint8)
     chunk = np.zeros((h, w), np.uint32)
     nnf = np.zeros((h, w), np.uint32)
-    _check(_load().ora_stylize(_ptr(rgb, _u8p), gs.ctypes.data, gs.shape[1], gs.shape[0],
-                               _ptr(lut, _u32p), fmt, lut_bits, gt.ctypes.data, w, h,
-                               _ptr(j, _u32p), levels, finest, threshold, radius,
-                               _ptr(out, _u8p), _ptr(chunk, _u32p), _ptr(nnf, _u32p)), "stylize")
+    wt, wp = _weights(weights)
+    _check(_load().ora_stylize_w(_ptr(rgb, _u8p), gs.ctypes.data, gs.shape[1], gs.shape[0],
+                                 _ptr(lut, _u32p), fmt, lut_bits, wp, gt.ctypes.data, w, h,
+                                 _ptr(j, _u32p), levels, finest, threshold, radius,
+                                 _ptr(out, _u8p), _ptr(chunk, _u32p), _ptr(nnf, _u32p)),
+           "stylize")
     return out, chunk, nnf
 
 
@@ -246,21 +278,22 @@ def _labels(lab: np.ndarray, shape) -> np.ndarray:
 
 
 def lut_build_labels(src_guide: np.ndarray, src_labels: np.ndarray, nlabels: int,
-                     lut_bits: int) -> np.ndarray:
+                     lut_bits: int, weights=None) -> np.ndarray:
     """Per-label lookup tables (segmentation guide), shape (nlabels, bins):
     table l from the source pixels labelled l; a label without source pixels
     gets the unconstrained table."""
     g, fmt = _guide(src_guide)
     lab = _labels(src_labels, g.shape[:2])
     luts = np.zeros((nlabels, _bins(fmt, lut_bits)), np.uint32)
-    _check(_load().ora_lut_build_labels(g.ctypes.data, _ptr(lab, _u8p), nlabels, fmt, g.shape[1],
-                                        g.shape[0], lut_bits, _ptr(luts, _u32p)),
-           "lut_build_labels")
+    w, wp = _weights(weights)
+    _check(_load().ora_lut_build_labels_w(g.ctypes.data, _ptr(lab, _u8p), nlabels, fmt,
+                                          g.shape[1], g.shape[0], lut_bits, wp,
+                                          _ptr(luts, _u32p)), "lut_build_labels")
     return luts
 
 
 def stylize_seg(src_rgb, src_guide, src_labels, luts, nlabels, lut_bits, tgt_guide, tgt_labels,
-                jitter, levels, finest, threshold, radius):
+                jitter, levels, finest, threshold, radius, weights=None):
     """The per-frame path with the segmentation guide as a hard constraint:
     returns (rgb, chunk, nnf) as ``stylize``."""
     gs, fmt = _guide(src_guide)
@@ -278,11 +311,13 @@ def stylize_seg(src_rgb, src_guide, src_labels, luts, nlabels, lut_bits, tgt_gui
     out = np.zeros((h, w, 3), np.uint8)
     chunk = np.zeros((h, w), np.uint32)
     nnf = np.zeros((h, w), np.uint32)
-    _check(_load().ora_stylize_seg(_ptr(rgb, _u8p), gs.ctypes.data, _ptr(ls, _u8p), gs.shape[1],
-                                   gs.shape[0], _ptr(luts, _u32p), nlabels, fmt, lut_bits,
-                                   gt.ctypes.data, _ptr(lt, _u8p), w, h, _ptr(j, _u32p), levels,
-                                   finest, threshold, radius, _ptr(out, _u8p), _ptr(chunk, _u32p),
-                                   _ptr(nnf, _u32p)), "stylize_seg")
+    wt, wp = _weights(weights)
+    _check(_load().ora_stylize_seg_w(_ptr(rgb, _u8p), gs.ctypes.data, _ptr(ls, _u8p),
+                                     gs.shape[1], gs.shape[0], _ptr(luts, _u32p), nlabels, fmt,
+                                     lut_bits, wp, gt.ctypes.data, _ptr(lt, _u8p), w, h,
+                                     _ptr(j, _u32p), levels, finest, threshold, radius,
+                                     _ptr(out, _u8p), _ptr(chunk, _u32p), _ptr(nnf, _u32p)),
+           "stylize_seg")
     return out, chunk, nnf
 
 

@@ -54,7 +54,11 @@
  * ignored).  The error sums the three squared differences; the table has
  * (1 << lut_bits)^3 bins indexed c0 + (c1 << b) + (c2 << 2b) and is built by
  * brute force over every source pixel (the definition: nearest to the bin
- * centre, ties to the smallest raster index).
+ * centre, ties to the smallest raster index).  Optional integer channel
+ * weights w0..w2 (0..127; the paper's strong or weak appearance guide) scale
+ * each channel's squared difference, in the table's argmin and in the
+ * error alike: e = sum_k w_k (a_k - b_k)^2.  Unit weights are the plain
+ * case; two-channel formats take unit weights only.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -102,6 +106,20 @@ static int guide_depth(int fmt) { return fmt == 1 ? 16 : 8; }
 
 static int fmt_ok(int fmt) { return fmt == 0 || fmt == 1 || fmt == 2; }
 
+/* Channel weights: NULL = unit; otherwise three values 0..127, and only for
+ * three-channel guides (two-channel guides take unit weights).  Fills w[3]. */
+static int weights_get(int fmt, const uint8_t *weights, int64_t *w)
+{
+    w[0] = w[1] = w[2] = 1;
+    if (!weights) return ORA_OK;
+    for (int k = 0; k < 3; ++k) {
+        if (weights[k] > 127) return ORA_EINVAL;
+        w[k] = weights[k];
+    }
+    if (fmt != 2 && (w[0] != 1 || w[1] != 1 || w[2] != 1)) return ORA_EINVAL;
+    return ORA_OK;
+}
+
 /* Lookup-table bin of one guide channel value: drop the low bits. */
 static int64_t lut_quantise(int64_t v, int fmt, int lut_bits)
 {
@@ -132,7 +150,7 @@ static int64_t lut_bin_centre(int64_t c, int fmt, int lut_bits)
  * pixel, in raster order with a strict compare (so ties keep the smallest
  * raster index).  Returns 1 when no source pixel qualifies. */
 static int lut_build3_filtered(const void *src_guide, const uint8_t *labels, int want, int sw,
-                               int sh, int lut_bits, uint32_t *lut)
+                               int sh, int lut_bits, const int64_t *w, uint32_t *lut)
 {
     const int64_t n = (int64_t)1 << lut_bits, npix = (int64_t)sw * sh;
     int64_t any = 0;
@@ -150,7 +168,7 @@ static int lut_build3_filtered(const void *src_guide, const uint8_t *labels, int
             int64_t g[3];
             guide_read_all(src_guide, 2, i, g);
             uint64_t d = 0;
-            for (int k = 0; k < 3; ++k) d += (uint64_t)((q[k] - g[k]) * (q[k] - g[k]));
+            for (int k = 0; k < 3; ++k) d += (uint64_t)(w[k] * (q[k] - g[k]) * (q[k] - g[k]));
             if (d < best_d) {
                 best_d = d;
                 best_i = i;
@@ -162,12 +180,12 @@ static int lut_build3_filtered(const void *src_guide, const uint8_t *labels, int
 }
 
 static int lut_build_filtered(const void *src_guide, const uint8_t *labels, int want, int fmt,
-                              int sw, int sh, int lut_bits, uint32_t *lut)
+                              int sw, int sh, int lut_bits, const int64_t *wt, uint32_t *lut)
 {
     if (!src_guide || !lut || sw < 1 || sh < 1 || !fmt_ok(fmt)) return ORA_EINVAL;
     if (fmt == 2) {
         if (lut_bits < 1 || lut_bits > 8) return ORA_EINVAL;
-        return lut_build3_filtered(src_guide, labels, want, sw, sh, lut_bits, lut);
+        return lut_build3_filtered(src_guide, labels, want, sw, sh, lut_bits, wt, lut);
     }
     if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
     const int64_t n = (int64_t)1 << lut_bits;          /* bins per channel */
@@ -253,18 +271,29 @@ int ora_set_threads(int n)
 #endif
 }
 
+/* The table with channel weights (NULL: unit). */
+int ora_lut_build_w(const void *src_guide, int fmt, int sw, int sh, int lut_bits,
+                    const uint8_t *weights, uint32_t *lut)
+{
+    int64_t w[3];
+    if (weights_get(fmt, weights, w)) return ORA_EINVAL;
+    return lut_build_filtered(src_guide, NULL, 0, fmt, sw, sh, lut_bits, w, lut);
+}
+
 int ora_lut_build(const void *src_guide, int fmt, int sw, int sh, int lut_bits, uint32_t *lut)
 {
-    return lut_build_filtered(src_guide, NULL, 0, fmt, sw, sh, lut_bits, lut);
+    return ora_lut_build_w(src_guide, fmt, sw, sh, lut_bits, NULL, lut);
 }
 
 /* Selected bins of the table of any format, each by brute force over every
  * source pixel (the definition; for checking large tables by sampling):
  * out[k] = LUT[bins[k]]. */
-int ora_lut_query(const void *src_guide, int fmt, int sw, int sh, int lut_bits,
-                  const int64_t *bins, int64_t nbins, uint32_t *out)
+int ora_lut_query_w(const void *src_guide, int fmt, int sw, int sh, int lut_bits,
+                    const uint8_t *weights, const int64_t *bins, int64_t nbins, uint32_t *out)
 {
     if (!src_guide || !bins || !out || sw < 1 || sh < 1 || !fmt_ok(fmt)) return ORA_EINVAL;
+    int64_t w[3];
+    if (weights_get(fmt, weights, w)) return ORA_EINVAL;
     if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
     const int nc = guide_channels(fmt);
     const int64_t n = (int64_t)1 << lut_bits, npix = (int64_t)sw * sh;
@@ -282,7 +311,7 @@ int ora_lut_query(const void *src_guide, int fmt, int sw, int sh, int lut_bits,
             int64_t g[3];
             guide_read_all(src_guide, fmt, i, g);
             uint64_t d = 0;
-            for (int k = 0; k < nc; ++k) d += (uint64_t)((q[k] - g[k]) * (q[k] - g[k]));
+            for (int k = 0; k < nc; ++k) d += (uint64_t)(w[k] * (q[k] - g[k]) * (q[k] - g[k]));
             if (d < best_d) {
                 best_d = d;
                 best_i = i;
@@ -293,22 +322,37 @@ int ora_lut_query(const void *src_guide, int fmt, int sw, int sh, int lut_bits,
     return ORA_OK;
 }
 
+int ora_lut_query(const void *src_guide, int fmt, int sw, int sh, int lut_bits,
+                  const int64_t *bins, int64_t nbins, uint32_t *out)
+{
+    return ora_lut_query_w(src_guide, fmt, sw, sh, lut_bits, NULL, bins, nbins, out);
+}
+
 /* Per-label tables luts[l * bins + c] for labels l = 0..nlabels-1, from the
  * source pixels labelled l; a label without source pixels gets the
  * unconstrained table. */
-int ora_lut_build_labels(const void *src_guide, const uint8_t *labels, int nlabels, int fmt, int sw,
-                         int sh, int lut_bits, uint32_t *luts)
+int ora_lut_build_labels_w(const void *src_guide, const uint8_t *labels, int nlabels, int fmt,
+                           int sw, int sh, int lut_bits, const uint8_t *weights, uint32_t *luts)
 {
     if (!labels || !luts || nlabels < 1 || nlabels > 256) return ORA_EINVAL;
+    int64_t w[3];
+    if (weights_get(fmt, weights, w)) return ORA_EINVAL;
     if (!fmt_ok(fmt) || lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12)
         return ORA_EINVAL;
     const int64_t bins = (int64_t)1 << (guide_channels(fmt) * lut_bits);
     for (int l = 0; l < nlabels; ++l) {
-        int rc = lut_build_filtered(src_guide, labels, l, fmt, sw, sh, lut_bits, luts + l * bins);
-        if (rc == 1) rc = lut_build_filtered(src_guide, NULL, 0, fmt, sw, sh, lut_bits, luts + l * bins);
+        int rc = lut_build_filtered(src_guide, labels, l, fmt, sw, sh, lut_bits, w, luts + l * bins);
+        if (rc == 1)
+            rc = lut_build_filtered(src_guide, NULL, 0, fmt, sw, sh, lut_bits, w, luts + l * bins);
         if (rc != ORA_OK) return rc;
     }
     return ORA_OK;
+}
+
+int ora_lut_build_labels(const void *src_guide, const uint8_t *labels, int nlabels, int fmt, int sw,
+                         int sh, int lut_bits, uint32_t *luts)
+{
+    return ora_lut_build_labels_w(src_guide, labels, nlabels, fmt, sw, sh, lut_bits, NULL, luts);
 }
 
 /* ------------------------------------------------ seed hierarchy (Sec. 3.2) */
@@ -400,6 +444,7 @@ typedef struct {
     uint32_t threshold;
     const uint8_t *src_labels, *tgt_labels;  /* both NULL without segmentation */
     int nlabels;
+    int64_t wt[3];          /* channel weights of the error (unit without weights) */
 } assign_t;
 
 /* The lookup of a guide value g[] in the table of `label` (ignored without
@@ -443,7 +488,7 @@ static void assign_pixel(const assign_t *A, int64_t px, int64_t py, uint32_t *nn
         int64_t sg[3];
         guide_read_all(A->src_guide, A->fmt, vy * A->sw + vx, sg);
         uint64_t e = 0;
-        for (int k = 0; k < nc; ++k) e += (uint64_t)((tg[k] - sg[k]) * (tg[k] - sg[k]));
+        for (int k = 0; k < nc; ++k) e += (uint64_t)(A->wt[k] * (tg[k] - sg[k]) * (tg[k] - sg[k]));
         if (e < (uint64_t)A->threshold) {
             *nnf = (uint32_t)vx | ((uint32_t)vy << 16);
             *chunk = ((uint32_t)i << 26) | ((uint32_t)qy << 13) | (uint32_t)qx;
@@ -466,9 +511,12 @@ static int check_common(int sw, int sh, int fmt, int lut_bits, int w, int h, int
     return ORA_OK;
 }
 
-int ora_assign(const void *src_guide, int sw, int sh, const uint32_t *lut, int fmt, int lut_bits,
-               const void *tgt_guide, int w, int h, const uint32_t *jitter, int levels, int finest,
-               uint32_t threshold, uint32_t *out_nnf, uint32_t *out_chunk, int64_t row0, int64_t rows)
+/* The level loop with channel weights (NULL: unit); the table must have
+ * been built with the same weights. */
+int ora_assign_w(const void *src_guide, int sw, int sh, const uint32_t *lut, int fmt, int lut_bits,
+                 const uint8_t *weights, const void *tgt_guide, int w, int h,
+                 const uint32_t *jitter, int levels, int finest, uint32_t threshold,
+                 uint32_t *out_nnf, uint32_t *out_chunk, int64_t row0, int64_t rows)
 {
     int rc = check_common(sw, sh, fmt, lut_bits, w, h, levels, finest);
     if (rc) return rc;
@@ -477,12 +525,21 @@ int ora_assign(const void *src_guide, int sw, int sh, const uint32_t *lut, int f
     if (rows < 0) rows = h;
     if (row0 < 0 || row0 + rows > h) return ORA_EINVAL;
     assign_t A = {src_guide, sw, sh, lut, fmt, lut_bits, tgt_guide, {w, h, levels, finest, jitter},
-                  threshold, NULL, NULL, 0};
+                  threshold, NULL, NULL, 0, {1, 1, 1}};
+    if (weights_get(fmt, weights, A.wt)) return ORA_EINVAL;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t y = row0; y < row0 + rows; ++y)
         for (int64_t x = 0; x < w; ++x)
             assign_pixel(&A, x, y, &out_nnf[y * w + x], &out_chunk[y * w + x]);
     return ORA_OK;
+}
+
+int ora_assign(const void *src_guide, int sw, int sh, const uint32_t *lut, int fmt, int lut_bits,
+               const void *tgt_guide, int w, int h, const uint32_t *jitter, int levels, int finest,
+               uint32_t threshold, uint32_t *out_nnf, uint32_t *out_chunk, int64_t row0, int64_t rows)
+{
+    return ora_assign_w(src_guide, sw, sh, lut, fmt, lut_bits, NULL, tgt_guide, w, h, jitter,
+                        levels, finest, threshold, out_nnf, out_chunk, row0, rows);
 }
 
 /* ------------------------------------------------ voting blend (Sec. 3.2) */
@@ -526,29 +583,40 @@ int ora_blend(const uint8_t *src_rgb, int sw, int sh, const uint32_t *nnf, int w
 
 /* ------------------------------------------------------------ whole path */
 
+int ora_stylize_w(const uint8_t *src_rgb, const void *src_guide, int sw, int sh,
+                  const uint32_t *lut, int fmt, int lut_bits, const uint8_t *weights,
+                  const void *tgt_guide, int w, int h, const uint32_t *jitter, int levels,
+                  int finest, uint32_t threshold, int radius, uint8_t *out_rgb,
+                  uint32_t *out_chunk, uint32_t *out_nnf)
+{
+    if (!out_rgb || !out_chunk) return ORA_EINVAL;
+    uint32_t *nnf = out_nnf ? out_nnf : (uint32_t *)malloc((size_t)w * h * sizeof(uint32_t));
+    if (!nnf) return ORA_ENOMEM;
+    int rc = ora_assign_w(src_guide, sw, sh, lut, fmt, lut_bits, weights, tgt_guide, w, h, jitter,
+                          levels, finest, threshold, nnf, out_chunk, 0, -1);
+    if (rc == ORA_OK) rc = ora_blend(src_rgb, sw, sh, nnf, w, h, radius, out_rgb, 0, -1);
+    if (!out_nnf) free(nnf);
+    return rc;
+}
+
 int ora_stylize(const uint8_t *src_rgb, const void *src_guide, int sw, int sh, const uint32_t *lut,
                 int fmt, int lut_bits, const void *tgt_guide, int w, int h, const uint32_t *jitter,
                 int levels, int finest, uint32_t threshold, int radius, uint8_t *out_rgb,
                 uint32_t *out_chunk, uint32_t *out_nnf)
 {
-    if (!out_rgb || !out_chunk) return ORA_EINVAL;
-    uint32_t *nnf = out_nnf ? out_nnf : (uint32_t *)malloc((size_t)w * h * sizeof(uint32_t));
-    if (!nnf) return ORA_ENOMEM;
-    int rc = ora_assign(src_guide, sw, sh, lut, fmt, lut_bits, tgt_guide, w, h, jitter, levels,
-                        finest, threshold, nnf, out_chunk, 0, -1);
-    if (rc == ORA_OK) rc = ora_blend(src_rgb, sw, sh, nnf, w, h, radius, out_rgb, 0, -1);
-    if (!out_nnf) free(nnf);
-    return rc;
+    return ora_stylize_w(src_rgb, src_guide, sw, sh, lut, fmt, lut_bits, NULL, tgt_guide, w, h,
+                         jitter, levels, finest, threshold, radius, out_rgb, out_chunk, out_nnf);
 }
 
 /* ----------------------------------------------------- segmentation guide */
 
 /* ora_assign with label maps: src_labels Sw*Sh, tgt_labels W*H, luts the
  * nlabels tables of ora_lut_build_labels. */
-int ora_assign_seg(const void *src_guide, const uint8_t *src_labels, int sw, int sh,
-                   const uint32_t *luts, int nlabels, int fmt, int lut_bits, const void *tgt_guide,
-                   const uint8_t *tgt_labels, int w, int h, const uint32_t *jitter, int levels,
-                   int finest, uint32_t threshold, uint32_t *out_nnf, uint32_t *out_chunk)
+int ora_assign_seg_w(const void *src_guide, const uint8_t *src_labels, int sw, int sh,
+                     const uint32_t *luts, int nlabels, int fmt, int lut_bits,
+                     const uint8_t *weights, const void *tgt_guide, const uint8_t *tgt_labels,
+                     int w, int h, const uint32_t *jitter, int levels, int finest,
+                     uint32_t threshold, uint32_t *out_nnf, uint32_t *out_chunk)
 {
     int rc = check_common(sw, sh, fmt, lut_bits, w, h, levels, finest);
     if (rc) return rc;
@@ -557,12 +625,41 @@ int ora_assign_seg(const void *src_guide, const uint8_t *src_labels, int sw, int
     if (nlabels < 1 || nlabels > 256) return ORA_EINVAL;
     if (levels > 0 && !jitter) return ORA_EINVAL;
     assign_t A = {src_guide, sw, sh, luts, fmt, lut_bits, tgt_guide, {w, h, levels, finest, jitter},
-                  threshold, src_labels, tgt_labels, nlabels};
+                  threshold, src_labels, tgt_labels, nlabels, {1, 1, 1}};
+    if (weights_get(fmt, weights, A.wt)) return ORA_EINVAL;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t y = 0; y < h; ++y)
         for (int64_t x = 0; x < w; ++x)
             assign_pixel(&A, x, y, &out_nnf[y * w + x], &out_chunk[y * w + x]);
     return ORA_OK;
+}
+
+int ora_assign_seg(const void *src_guide, const uint8_t *src_labels, int sw, int sh,
+                   const uint32_t *luts, int nlabels, int fmt, int lut_bits, const void *tgt_guide,
+                   const uint8_t *tgt_labels, int w, int h, const uint32_t *jitter, int levels,
+                   int finest, uint32_t threshold, uint32_t *out_nnf, uint32_t *out_chunk)
+{
+    return ora_assign_seg_w(src_guide, src_labels, sw, sh, luts, nlabels, fmt, lut_bits, NULL,
+                            tgt_guide, tgt_labels, w, h, jitter, levels, finest, threshold,
+                            out_nnf, out_chunk);
+}
+
+int ora_stylize_seg_w(const uint8_t *src_rgb, const void *src_guide, const uint8_t *src_labels,
+                      int sw, int sh, const uint32_t *luts, int nlabels, int fmt, int lut_bits,
+                      const uint8_t *weights, const void *tgt_guide, const uint8_t *tgt_labels,
+                      int w, int h, const uint32_t *jitter, int levels, int finest,
+                      uint32_t threshold, int radius, uint8_t *out_rgb, uint32_t *out_chunk,
+                      uint32_t *out_nnf)
+{
+    if (!out_rgb || !out_chunk) return ORA_EINVAL;
+    uint32_t *nnf = out_nnf ? out_nnf : (uint32_t *)malloc((size_t)w * h * sizeof(uint32_t));
+    if (!nnf) return ORA_ENOMEM;
+    int rc = ora_assign_seg_w(src_guide, src_labels, sw, sh, luts, nlabels, fmt, lut_bits, weights,
+                              tgt_guide, tgt_labels, w, h, jitter, levels, finest, threshold, nnf,
+                              out_chunk);
+    if (rc == ORA_OK) rc = ora_blend(src_rgb, sw, sh, nnf, w, h, radius, out_rgb, 0, -1);
+    if (!out_nnf) free(nnf);
+    return rc;
 }
 
 int ora_stylize_seg(const uint8_t *src_rgb, const void *src_guide, const uint8_t *src_labels, int sw,

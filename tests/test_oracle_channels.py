@@ -156,3 +156,83 @@ def test_third_channel_decides_acceptance():
     assert np.all((chunk >> 26) == 3)
     _, chunk, _ = oracle.stylize(rgb, src, lut, 4, tgt, jit, 3, 4, 127 * 127 + 400, 1)
     assert np.any((chunk >> 26) < 3)
+
+
+# --------------------------------------------------------- channel weights
+
+def _numpy_lut3_weighted(src, lut_bits, w):
+    n = 1 << lut_bits
+    s = 8 - lut_bits
+    cen = (np.arange(n) << s) + ((1 << (s - 1)) if s else 0)
+    b0, b1, b2 = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    q = np.stack([cen[b0.ravel()], cen[b1.ravel()], cen[b2.ravel()]], axis=1)
+    g = src[..., :3].reshape(-1, 3).astype(np.int64)
+    d = (np.asarray(w, np.int64)[None, None, :] * (q[:, None, :] - g[None, :, :]) ** 2).sum(axis=2)
+    best = np.argmin(d, axis=1)
+    sw = src.shape[1]
+    out = np.zeros(n ** 3, np.uint32)
+    out[(b0 + b1 * n + b2 * n * n).ravel()] = (best % sw) | ((best // sw) << 16)
+    return out
+
+
+@pytest.mark.parametrize("weights", [(1, 1, 1), (3, 1, 7), (0, 2, 5), (127, 0, 1)])
+def test_weighted_lut3_matches_vectorised_argmin(weights):
+    rng = np.random.default_rng(sum(weights))
+    src = np.zeros((10, 13, 4), np.uint8)
+    src[..., :3] = np.linspace(0, 255, 5).astype(np.uint8)[rng.integers(0, 5, (10, 13, 3))]
+    src[..., 3] = rng.integers(0, 256, (10, 13))
+    for bits in (2, 4):
+        np.testing.assert_array_equal(oracle.lut_build(src, bits, weights),
+                                      _numpy_lut3_weighted(src, bits, weights))
+        bins = rng.integers(0, 1 << (3 * bits), 50)
+        np.testing.assert_array_equal(oracle.lut_query(src, bits, bins, weights),
+                                      _numpy_lut3_weighted(src, bits, weights)[bins])
+
+
+def test_zero_weight_drops_the_channel():
+    """Weights (1, 1, 0) make a three-channel guide behave exactly as its
+    first two channels (table and frames), whatever the third channel holds."""
+    rgb = workloads.value_noise_rgb(80, 80, 7)
+    g2s = workloads.sphere_guide_u8(80)
+    g2t = workloads.bump_guide_u8(100, 70, 5, 8)
+    g3s = workloads.guide_u8x3(g2s, workloads.appearance_u8(rgb, 3))
+    g3t = workloads.appearance_target(100, 70, 5, 9)
+    g3t[..., :2] = g2t
+    jit = workloads.jitter_table(100, 70, 3, 4, 10)
+    bits = 4
+    w = (1, 1, 0)
+    l2 = oracle.lut_build(g2s, bits)
+    l3 = oracle.lut_build(g3s, bits, w).reshape(1 << bits, -1)
+    for c2 in range(1 << bits):
+        np.testing.assert_array_equal(l3[c2], l2)
+    for t in (0, 40, 300):
+        a = oracle.stylize(rgb, g2s, l2, bits, g2t, jit, 3, 4, t, 2)
+        b = oracle.stylize(rgb, g3s, l3.ravel(), bits, g3t, jit, 3, 4, t, 2, weights=w)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_uniform_weight_scales_the_threshold():
+    """Weights (k, k, k) with threshold k t equal unit weights with t."""
+    st = workloads.config(6, lut_bits=4, w=64, h=64)[0][0]
+    src, rgb = st.guide[:72, :72], st.rgb[:72, :72]
+    tgt = workloads.appearance_target(90, 60, 4, 15)
+    jit = workloads.jitter_table(90, 60, 3, 8, 16)
+    l1 = oracle.lut_build(src, 4)
+    l3 = oracle.lut_build(src, 4, (3, 3, 3))
+    np.testing.assert_array_equal(l1, l3)
+    for t in (50, 200):
+        a = oracle.stylize(rgb, src, l1, 4, tgt, jit, 3, 8, t, 1)
+        b = oracle.stylize(rgb, src, l3, 4, tgt, jit, 3, 8, 3 * t, 1, weights=(3, 3, 3))
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_weights_are_validated():
+    g3 = workloads.guide_u8x3(workloads.sphere_guide_u8(16), np.zeros((16, 16), np.uint8))
+    with pytest.raises(ValueError):
+        oracle.lut_build(g3, 3, (1, 128, 1))
+    with pytest.raises(ValueError):
+        oracle.lut_build(workloads.sphere_guide_u8(16), 3, (2, 1, 1))  # two channels: unit only
+    np.testing.assert_array_equal(oracle.lut_build(workloads.sphere_guide_u8(16), 3, (1, 1, 1)),
+                                  oracle.lut_build(workloads.sphere_guide_u8(16), 3))
