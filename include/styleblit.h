@@ -80,6 +80,12 @@ typedef struct {
     const uint32_t *label_luts; /* [device] nlabels tables of (1<<lut_bits)^2 entries,
                                    written by sb_lut_build_labels */
     int32_t nlabels;            /* 0, or 1..SB_MAX_LABELS */
+    /* Channel weights of a three-channel guide (the paper's strong or weak
+     * appearance guide): the error and the table's argmin sum w_k * d_k^2.
+     * weights[0..2] in 0..127 (byte 3 unused); all zero means unit weights,
+     * the only choice for two-channel guides.  The tables must have been
+     * built with the same weights (sb_lut_build_w). */
+    uint8_t weights[4];
 } sb_style;
 
 /* Per-frame parameters of Algorithm 2 and of the voting blend. */
@@ -140,6 +146,12 @@ size_t sb_lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_b
  * channels at 8 bits). */
 int sb_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
                  uint32_t *lut, void *workspace, size_t workspace_bytes, hipStream_t stream);
+/* The same with channel weights: LUT[c] = argmin_u sum_k w_k (centre_k(c) -
+ * G_S[u]_k)^2, ties as above.  weights [host] three values 0..127 (NULL or
+ * all zero: unit weights); non-unit weights need SB_GUIDE_U8X3. */
+int sb_lut_build_w(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
+                   const uint8_t *weights, uint32_t *lut, void *workspace,
+                   size_t workspace_bytes, hipStream_t stream);
 
 /* Per-label lookup tables for the segmentation guide: table l holds, for
  * every bin, the source pixel labelled l whose guide is nearest to the bin
@@ -153,6 +165,12 @@ int sb_lut_build_labels(const void *guide, const uint8_t *labels, int32_t fmt, i
                         int32_t sh, int32_t lut_bits, int32_t nlabels, const uint32_t *lut,
                         uint32_t *luts, void *workspace, size_t workspace_bytes,
                         hipStream_t stream);
+/* The same with channel weights, as sb_lut_build_w (the unconstrained
+ * table `lut` must use the same weights). */
+int sb_lut_build_labels_w(const void *guide, const uint8_t *labels, int32_t fmt, int32_t sw,
+                          int32_t sh, int32_t lut_bits, const uint8_t *weights, int32_t nlabels,
+                          const uint32_t *lut, uint32_t *luts, void *workspace,
+                          size_t workspace_bytes, hipStream_t stream);
 
 /* -------------------------------------------------------- one frame */
 

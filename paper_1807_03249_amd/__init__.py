@@ -34,7 +34,8 @@ class SbStyle(ctypes.Structure):
     _fields_ = [("rgba", ctypes.c_void_p), ("guide", ctypes.c_void_p), ("lut", ctypes.c_void_p),
                 ("sw", ctypes.c_int32), ("sh", ctypes.c_int32), ("fmt", ctypes.c_int32),
                 ("lut_bits", ctypes.c_int32), ("labels", ctypes.c_void_p),
-                ("label_luts", ctypes.c_void_p), ("nlabels", ctypes.c_int32)]
+                ("label_luts", ctypes.c_void_p), ("nlabels", ctypes.c_int32),
+                ("weights", ctypes.c_uint8 * 4)]
 
 
 class SbTune(ctypes.Structure):
@@ -103,6 +104,8 @@ def lib():
                                 ctypes.POINTER(SbParams), vp, vp, vp, vp, sz,
                                 ctypes.POINTER(SbTune), vp]
     L.sb_lut_build_labels.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp]
+    L.sb_lut_build_w.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, sz, vp]
+    L.sb_lut_build_labels_w.argtypes = [vp, vp, i32, i32, i32, i32, vp, i32, vp, vp, vp, sz, vp]
     L.sb_stylize_seg.argtypes = [ctypes.POINTER(SbStyle), vp, vp, i32, i32, vp,
                                  ctypes.POINTER(SbParams), vp, vp, vp, vp, sz,
                                  ctypes.POINTER(SbTune), vp]
@@ -193,10 +196,13 @@ class Style:
     """A device-resident style: RGBA-packed exemplar, its guide and the lookup
     table built from it on the GPU (Sec. 3.1).  With ``labels`` (uint8
     (rows, cols), values below ``nlabels``) the style also carries the
-    segmentation guide: its label map and one lookup table per label."""
+    segmentation guide: its label map and one lookup table per label.
+    ``weights`` (three values 0..127, three-channel guides only) weight the
+    channels' squared differences in the table and in the error test (the
+    strong or weak appearance guide); None means unit weights."""
 
     def __init__(self, rgb, guide, lut_bits: int, stream=None, labels=None,
-                 nlabels: Optional[int] = None):
+                 nlabels: Optional[int] = None, weights=None):
         torch = _torch()
         self.rgb = _dev(torch, rgb)
         if self.rgb.dtype != torch.uint8 or self.rgb.dim() != 3 or self.rgb.shape[2] != 3:
@@ -223,8 +229,13 @@ class Style:
         ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
         self.lut = torch.empty(table_entries(self.fmt, self.lut_bits), dtype=torch.int32,
                                device="cuda")
-        _check(L.sb_lut_build(self.guide.data_ptr(), self.fmt, self.sw, self.sh, self.lut_bits,
-                              self.lut.data_ptr(), ws.data_ptr(), wsb, s), "sb_lut_build")
+        if weights is not None and len(weights) != 3:
+            raise ValueError("weights must hold three values")
+        self.weights = (ctypes.c_uint8 * 4)(*([int(v) for v in weights] + [0])
+                                            if weights is not None else (0, 0, 0, 0))
+        _check(L.sb_lut_build_w(self.guide.data_ptr(), self.fmt, self.sw, self.sh, self.lut_bits,
+                                self.weights, self.lut.data_ptr(), ws.data_ptr(), wsb, s),
+               "sb_lut_build_w")
         self._ws = ws  # keep alive until the enqueued build has run
         self.labels = self.label_luts = None
         self.nlabels = 0
@@ -235,15 +246,16 @@ class Style:
             self.nlabels = int(nlabels if nlabels is not None else int(self.labels.max()) + 1)
             self.label_luts = torch.empty((self.nlabels, table_entries(self.fmt, self.lut_bits)),
                                           dtype=torch.int32, device="cuda")
-            _check(L.sb_lut_build_labels(self.guide.data_ptr(), self.labels.data_ptr(), self.fmt,
-                                         self.sw, self.sh, self.lut_bits, self.nlabels,
-                                         self.lut.data_ptr(), self.label_luts.data_ptr(),
-                                         ws.data_ptr(), wsb, s), "sb_lut_build_labels")
+            _check(L.sb_lut_build_labels_w(self.guide.data_ptr(), self.labels.data_ptr(),
+                                           self.fmt, self.sw, self.sh, self.lut_bits,
+                                           self.weights, self.nlabels, self.lut.data_ptr(),
+                                           self.label_luts.data_ptr(), ws.data_ptr(), wsb, s),
+                   "sb_lut_build_labels_w")
         self.c = SbStyle(self.rgba.data_ptr(), self.guide.data_ptr(), self.lut.data_ptr(),
                          self.sw, self.sh, self.fmt, self.lut_bits,
                          self.labels.data_ptr() if self.labels is not None else None,
                          self.label_luts.data_ptr() if self.label_luts is not None else None,
-                         self.nlabels)
+                         self.nlabels, self.weights)
 
     def resident_bytes(self) -> int:
         n = (self.rgba.numel() * 4 + self.guide.numel() * self.guide.element_size()

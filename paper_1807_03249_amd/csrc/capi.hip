@@ -25,6 +25,8 @@ bool style_ok(const sb_style *s) {
   if (!s || !s->rgba || !s->guide || !s->lut) return false;
   if (!side_ok(s->sw) || !side_ok(s->sh)) return false;
   if (!fmt_ok(s->fmt)) return false;
+  int32_t wt[3];
+  if (!resolve_weights(s->fmt, s->weights, wt)) return false;
   if (s->nlabels < 0 || s->nlabels > SB_MAX_LABELS) return false;
   if (s->nlabels > 0 && (!s->labels || !s->label_luts)) return false;
   return s->lut_bits >= 1 && s->lut_bits <= fmt_depth(s->fmt) && s->lut_bits <= SB_MAX_LUT_BITS;
@@ -93,6 +95,10 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
   a->lut_bits = style->lut_bits;
   a->lut_shift = fmt_depth(style->fmt) - style->lut_bits;
   a->lut_log2 = fmt_channels(style->fmt) * style->lut_bits;
+  int32_t wt[3];
+  resolve_weights(style->fmt, style->weights, wt);  // checked by style_ok
+  a->wt02 = uint32_t(wt[0]) | (uint32_t(wt[2]) << 16);
+  a->wt1 = wt[1];
   a->threshold = params->threshold;
   a->radius = params->radius;
   a->fmt = style->fmt;
@@ -105,6 +111,16 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
     a->nlabels = style->nlabels;
   }
   return true;
+}
+
+bool resolve_weights(int32_t fmt, const uint8_t *in, int32_t out[3]) {
+  out[0] = out[1] = out[2] = 1;
+  if (!in || (in[0] == 0 && in[1] == 0 && in[2] == 0)) return true;
+  for (int32_t k = 0; k < 3; ++k) {
+    if (in[k] > 127) return false;
+    out[k] = in[k];
+  }
+  return fmt == SB_GUIDE_U8X3 || (out[0] == 1 && out[1] == 1 && out[2] == 1);
 }
 
 bool resolve_tune(const sb_tune *in, Tune *out) {
@@ -189,11 +205,20 @@ size_t sb_lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_b
 
 int sb_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
                  uint32_t *lut, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  return sb_lut_build_w(guide, fmt, sw, sh, lut_bits, nullptr, lut, workspace, workspace_bytes,
+                        stream);
+}
+
+int sb_lut_build_w(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
+                   const uint8_t *weights, uint32_t *lut, void *workspace,
+                   size_t workspace_bytes, hipStream_t stream) {
   if (!guide || !lut || !workspace) return SB_EINVAL;
+  int32_t wt[3];
+  if (!resolve_weights(fmt, weights, wt)) return SB_EINVAL;
   const size_t need = sb_lut_workspace_bytes(fmt, sw, sh, lut_bits);
   if (need == 0) return SB_EINVAL;
   if (workspace_bytes < need) return SB_ENOMEM;
-  hipError_t e = launch_lut_build(guide, fmt, sw, sh, lut_bits, lut, workspace, stream);
+  hipError_t e = launch_lut_build(guide, fmt, sw, sh, lut_bits, wt, lut, workspace, stream);
   if (e != hipSuccess) {
     set_hip_error(e, "sb_lut_build");
     return SB_EHIP;
@@ -205,13 +230,23 @@ int sb_lut_build_labels(const void *guide, const uint8_t *labels, int32_t fmt, i
                         int32_t sh, int32_t lut_bits, int32_t nlabels, const uint32_t *lut,
                         uint32_t *luts, void *workspace, size_t workspace_bytes,
                         hipStream_t stream) {
+  return sb_lut_build_labels_w(guide, labels, fmt, sw, sh, lut_bits, nullptr, nlabels, lut, luts,
+                               workspace, workspace_bytes, stream);
+}
+
+int sb_lut_build_labels_w(const void *guide, const uint8_t *labels, int32_t fmt, int32_t sw,
+                          int32_t sh, int32_t lut_bits, const uint8_t *weights, int32_t nlabels,
+                          const uint32_t *lut, uint32_t *luts, void *workspace,
+                          size_t workspace_bytes, hipStream_t stream) {
   if (!guide || !labels || !lut || !luts || !workspace) return SB_EINVAL;
   if (nlabels < 1 || nlabels > SB_MAX_LABELS) return SB_EINVAL;
+  int32_t wt[3];
+  if (!resolve_weights(fmt, weights, wt)) return SB_EINVAL;
   const size_t need = sb_lut_workspace_bytes(fmt, sw, sh, lut_bits);
   if (need == 0) return SB_EINVAL;
   if (workspace_bytes < need) return SB_ENOMEM;
-  const hipError_t e = launch_lut_build_labels(guide, labels, fmt, sw, sh, lut_bits, nlabels, lut,
-                                               luts, workspace, stream);
+  const hipError_t e = launch_lut_build_labels(guide, labels, fmt, sw, sh, lut_bits, wt, nlabels,
+                                               lut, luts, workspace, stream);
   if (e != hipSuccess) {
     set_hip_error(e, "sb_lut_build_labels");
     return SB_EHIP;

@@ -10,8 +10,8 @@
 // channel at a time -- first over channel 0 for every fixed value of the
 // other channels, then over channel 1, ... -- on the grid of bin centres.
 // Keys are uint64 (distance << 32 | index), so the lexicographic minimum is
-// the integer minimum, and adding one channel's squared distance to every
-// key of a line keeps their order.  Each pass is a brute-force minimum over
+// the integer minimum, and adding one channel's (weighted) squared distance
+// to every key of a line keeps their order.  Each pass is a brute-force minimum over
 // the 256 values of one channel, restricted to the values that hold a site.
 //
 // 16-bit guides (too many value tuples for a grid) bucket the source pixels
@@ -100,7 +100,8 @@ __global__ void k_sep_sites(const void *guide, int32_t npix, uint32_t *f0, const
 template <bool SITES, bool FINAL>
 __global__ __launch_bounds__(256) void k_sep_pass(const void *in, uint64_t *out, uint32_t *lut,
                                                   const uint32_t *fallback, int32_t inner,
-                                                  int32_t ti, int32_t lut_bits, int32_t sw) {
+                                                  int32_t ti, int32_t lut_bits, int32_t weight,
+                                                  int32_t sw) {
   __shared__ uint64_t key[256 * kSepTile];
   __shared__ uint8_t vlist[256];
   __shared__ uint32_t wcount[4];
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(256) void k_sep_pass(const void *in, uint64_t *out,
       const int32_t v = vlist[n];
       const uint64_t k = key[v * kSepTile + j];
       const int32_t d = centre - v;
-      const uint64_t cand = k + (uint64_t(uint32_t(d * d)) << 32);
+      const uint64_t cand = k + (uint64_t(uint32_t(weight * d * d)) << 32);
       best = (k != kNoKey && cand < best) ? cand : best;
     }
     const size_t dst = (o * size_t(nb) + size_t(b)) * size_t(inner) + size_t(i0 + j);
@@ -311,16 +312,17 @@ namespace {
 // Launch one pass over [outer][256][inner] -> [outer][nb][inner].
 template <bool SITES, bool FINAL>
 void sep_pass(const void *in, uint64_t *out, uint32_t *lut, const uint32_t *fallback,
-              size_t outer, int32_t inner, int32_t lut_bits, int32_t sw, hipStream_t stream) {
+              size_t outer, int32_t inner, int32_t lut_bits, int32_t weight, int32_t sw,
+              hipStream_t stream) {
   const int32_t ti = inner < kSepTile ? inner : kSepTile;
   const size_t blocks = outer * size_t(inner / ti);
   k_sep_pass<SITES, FINAL><<<unsigned(blocks), 256, 0, stream>>>(in, out, lut, fallback, inner,
-                                                                  ti, lut_bits, sw);
+                                                                  ti, lut_bits, weight, sw);
 }
 
 hipError_t build_sep(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
-                     uint32_t *lut, void *workspace, const uint8_t *labels, int32_t want,
-                     const uint32_t *fallback, hipStream_t stream) {
+                     const int32_t *wt, uint32_t *lut, void *workspace, const uint8_t *labels,
+                     int32_t want, const uint32_t *fallback, hipStream_t stream) {
   const int32_t nch = fmt_channels(fmt);
   const int32_t nb = 1 << lut_bits, npix = sw * sh;
   uint64_t *x = static_cast<uint64_t *>(workspace);
@@ -336,27 +338,28 @@ hipError_t build_sep(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int
     k_sep_sites<SB_GUIDE_U8X3><<<blocks_for(npix, 256), 256, 0, stream>>>(guide, npix, f0, labels,
                                                                           want);
   // channel 0: [v_rest][v0] -> [v_rest][b0]
-  sep_pass<true, false>(f0, x, nullptr, nullptr, size_t(1) << (8 * (nch - 1)), 1, lut_bits, sw,
-                        stream);
+  sep_pass<true, false>(f0, x, nullptr, nullptr, size_t(1) << (8 * (nch - 1)), 1, lut_bits,
+                        wt[0], sw, stream);
   if (nch == 2) {
     // channel 1: [v1][b0] -> [b1][b0], the table
-    sep_pass<false, true>(x, nullptr, lut, fallback, 1, nb, lut_bits, sw, stream);
+    sep_pass<false, true>(x, nullptr, lut, fallback, 1, nb, lut_bits, wt[1], sw, stream);
   } else {
     uint64_t *k1 = reinterpret_cast<uint64_t *>(y);  // the site grid is no longer needed
     // channel 1: [v2][v1][b0] -> [v2][b1][b0]
-    sep_pass<false, false>(x, k1, nullptr, nullptr, 256, nb, lut_bits, sw, stream);
+    sep_pass<false, false>(x, k1, nullptr, nullptr, 256, nb, lut_bits, wt[1], sw, stream);
     // channel 2: [v2][b1 b0] -> [b2][b1 b0], the table
-    sep_pass<false, true>(k1, nullptr, lut, fallback, 1, nb * nb, lut_bits, sw, stream);
+    sep_pass<false, true>(k1, nullptr, lut, fallback, 1, nb * nb, lut_bits, wt[2], sw, stream);
   }
   return hipGetLastError();
 }
 
 // One table: over all source pixels (labels null) or those labelled `want`.
 hipError_t build_one(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits,
-                     uint32_t *lut, void *workspace, const uint8_t *labels, int32_t want,
-                     const uint32_t *fallback, hipStream_t stream) {
+                     const int32_t *wt, uint32_t *lut, void *workspace, const uint8_t *labels,
+                     int32_t want, const uint32_t *fallback, hipStream_t stream) {
   if (fmt != SB_GUIDE_U16X2)
-    return build_sep(guide, fmt, sw, sh, lut_bits, lut, workspace, labels, want, fallback, stream);
+    return build_sep(guide, fmt, sw, sh, lut_bits, wt, lut, workspace, labels, want, fallback,
+                     stream);
   const LutGeom g = lut_geom(fmt, sw, sh, lut_bits);
   const LutWs w = lut_ws(workspace, g);
   const uint32_t nb = 1u << (2 * g.bucket_bits);
@@ -376,17 +379,18 @@ hipError_t build_one(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int
 }  // namespace
 
 hipError_t launch_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh,
-                            int32_t lut_bits, uint32_t *lut, void *workspace, hipStream_t stream) {
-  return build_one(guide, fmt, sw, sh, lut_bits, lut, workspace, nullptr, 0, nullptr, stream);
+                            int32_t lut_bits, const int32_t wt[3], uint32_t *lut,
+                            void *workspace, hipStream_t stream) {
+  return build_one(guide, fmt, sw, sh, lut_bits, wt, lut, workspace, nullptr, 0, nullptr, stream);
 }
 
 hipError_t launch_lut_build_labels(const void *guide, const uint8_t *labels, int32_t fmt,
-                                   int32_t sw, int32_t sh, int32_t lut_bits, int32_t nlabels,
-                                   const uint32_t *lut, uint32_t *luts, void *workspace,
-                                   hipStream_t stream) {
+                                   int32_t sw, int32_t sh, int32_t lut_bits, const int32_t wt[3],
+                                   int32_t nlabels, const uint32_t *lut, uint32_t *luts,
+                                   void *workspace, hipStream_t stream) {
   const size_t bins = size_t(1) << (fmt_channels(fmt) * lut_bits);
   for (int32_t l = 0; l < nlabels; ++l) {
-    const hipError_t e = build_one(guide, fmt, sw, sh, lut_bits, luts + size_t(l) * bins,
+    const hipError_t e = build_one(guide, fmt, sw, sh, lut_bits, wt, luts + size_t(l) * bins,
                                    workspace, labels, l, lut, stream);
     if (e != hipSuccess) return e;
   }

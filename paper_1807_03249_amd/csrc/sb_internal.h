@@ -83,6 +83,8 @@ struct FrameArgs {
   int32_t sw, sh, w, h;
   int32_t lut_bits, lut_shift; // lut_shift = guide depth - lut_bits
   int32_t lut_log2;            // log2 of the table's entries: channels * lut_bits
+  uint32_t wt02;               // channel weights w0 | w2 << 16 (three-channel guides)
+  int32_t wt1;                 // channel weight w1
   uint32_t threshold;
   int32_t radius;
   int32_t fmt;                 // sb_guide_fmt (read by the batch kernels)
@@ -145,13 +147,17 @@ void tile_counts(const FrameArgs &a, const Tune &t, uint32_t counts[kBatchKinds]
 // The passes over a batch described at desc_dev, persistent grids.
 hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, const Tune &t,
                         hipStream_t stream);
+// Channel weights from the caller's three bytes (NULL or all zero: unit);
+// false if a weight exceeds 127 or a two-channel format gets non-unit ones.
+bool resolve_weights(int32_t fmt, const uint8_t *in, int32_t out[3]);
 size_t lut_workspace_bytes(int32_t fmt, int32_t sw, int32_t sh, int32_t lut_bits);
 hipError_t launch_lut_build(const void *guide, int32_t fmt, int32_t sw, int32_t sh,
-                            int32_t lut_bits, uint32_t *lut, void *workspace, hipStream_t stream);
+                            int32_t lut_bits, const int32_t wt[3], uint32_t *lut,
+                            void *workspace, hipStream_t stream);
 hipError_t launch_lut_build_labels(const void *guide, const uint8_t *labels, int32_t fmt,
-                                   int32_t sw, int32_t sh, int32_t lut_bits, int32_t nlabels,
-                                   const uint32_t *lut, uint32_t *luts, void *workspace,
-                                   hipStream_t stream);
+                                   int32_t sw, int32_t sh, int32_t lut_bits, const int32_t wt[3],
+                                   int32_t nlabels, const uint32_t *lut, uint32_t *luts,
+                                   void *workspace, hipStream_t stream);
 
 __host__ __device__ inline uint32_t pack_xy(uint32_t x, uint32_t y) { return x | (y << 16); }
 

@@ -63,20 +63,23 @@ __device__ inline uint32_t lut_bin(uint32_t g, int32_t shift, int32_t bits) {
 
 // Exact squared L2 error of two guide words compared with t: true iff e < t.
 // 8-bit channels: the differences fit int16, one packed subtract and one
-// dot product (three channels: channels 0 and 2 as the packed pair, channel
-// 1's square as the accumulator; e <= 3 * 255^2).  16-bit channels: 24-bit
-// multiplies (|d| < 2^16, d^2 < 2^32) and a saturating add (a sum that
-// saturates is >= 2^32 - 1 >= t anyway).
+// dot product.  Three channels carry weights w0..w2 <= 127 (w02 = w0 | w2 <<
+// 16, w1): channels 0 and 2 as the packed pair against their weighted
+// differences (|w d| <= 127 * 255 fits int16), channel 1's weighted square as
+// the accumulator; e <= 3 * 127 * 255^2.  16-bit channels: 24-bit multiplies
+// (|d| < 2^16, d^2 < 2^32) and a saturating add (a sum that saturates is >=
+// 2^32 - 1 >= t anyway).
 template <int FMT>
-__device__ inline bool error_below(uint32_t a, uint32_t b, uint32_t t) {
+__device__ inline bool error_below(uint32_t a, uint32_t b, uint32_t t, uint32_t w02, int32_t w1) {
   if (FMT == SB_GUIDE_U8X2) {
     const short2_t d = __builtin_bit_cast(short2_t, a) - __builtin_bit_cast(short2_t, b);
     return uint32_t(__builtin_amdgcn_sdot2(d, d, 0, false)) < t;
   } else if (FMT == SB_GUIDE_U8X3) {
     const uint32_t m = 0x00FF00FFu;
     const short2_t d = __builtin_bit_cast(short2_t, a & m) - __builtin_bit_cast(short2_t, b & m);
+    const short2_t dw = d * __builtin_bit_cast(short2_t, w02);
     const int32_t d1 = int32_t((a >> 8) & 0xFFu) - int32_t((b >> 8) & 0xFFu);
-    return uint32_t(__builtin_amdgcn_sdot2(d, d, __mul24(d1, d1), false)) < t;
+    return uint32_t(__builtin_amdgcn_sdot2(d, dw, __mul24(d1, __mul24(d1, w1)), false)) < t;
   } else {
     const int32_t d0 = int32_t(a & 0xFFFFu) - int32_t(b & 0xFFFFu);
     const int32_t d1 = int32_t(a >> 16) - int32_t(b >> 16);
@@ -230,7 +233,8 @@ __device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *
   for (int32_t b = 0; b < B; ++b) {
 #pragma unroll
     for (int32_t u = 0; u < N; ++u) {
-      const bool below = error_below<FMT>(gt[b], guide_unpack<FMT>(g[b][u]), a.threshold);
+      const bool below =
+          error_below<FMT>(gt[b], guide_unpack<FMT>(g[b][u]), a.threshold, a.wt02, a.wt1);
       const bool same = !SEG || ls[b][u] == lt[b];
       const bool take = (!done[b]) & ok[b][u] & below & same;
       chunk[b] = take ? chunk_code(i0 + u, wq[b][u]) : chunk[b];
@@ -374,7 +378,7 @@ __device__ inline void assign_pixel(const FrameArgs &a, int32_t x, int32_t y) {
     const uint32_t vidx = uint32_t(vy) * sw + uint32_t(vx);
     if (SEG && glb(a.src_labels)[vidx] != glb(a.tgt_labels)[pidx]) continue;
     const uint32_t g = guide_word<FMT>(a.src_guide, vidx);
-    if (error_below<FMT>(gt, g, a.threshold)) {
+    if (error_below<FMT>(gt, g, a.threshold, a.wt02, a.wt1)) {
       chunk = chunk_code(i, w.x);
       off = w.y;
       done = true;

@@ -184,3 +184,35 @@ def test_segmentation_validation(L):
                                  None) == sb.SB_EINVAL
     assert L.sb_lut_build_labels(fake, fake, 0, 512, 512, 8, 2, fake, fake, fake, wsl - 1,
                                  None) == sb.SB_ENOMEM
+
+
+def test_channel_weight_validation(L):
+    """Weights above 127, or non-unit weights on a two-channel guide, are
+    refused on the host, for the table builds and for frames."""
+    import paper_1807_03249_amd as sb
+
+    fake = 0x1000
+    u8x3 = (ctypes.c_uint8 * 3)
+    ws3 = L.sb_lut_workspace_bytes(2, 64, 64, 4)
+    ws2 = L.sb_lut_workspace_bytes(0, 64, 64, 4)
+    assert L.sb_lut_build_w(fake, 2, 64, 64, 4, u8x3(1, 128, 1), fake, fake, ws3,
+                            None) == sb.SB_EINVAL
+    assert L.sb_lut_build_w(fake, 0, 64, 64, 4, u8x3(2, 1, 1), fake, fake, ws2,
+                            None) == sb.SB_EINVAL
+    assert L.sb_lut_build_labels_w(fake, fake, 2, 64, 64, 4, u8x3(200, 1, 1), 2, fake, fake,
+                                   fake, ws3, None) == sb.SB_EINVAL
+    # workspace checks still apply after valid weights
+    assert L.sb_lut_build_w(fake, 2, 64, 64, 4, u8x3(3, 1, 7), fake, fake, ws3 - 1,
+                            None) == sb.SB_ENOMEM
+    p = sb.params(4, 8, 32, 3)
+    ws = sb.workspace_bytes(64, 64, p)
+
+    def frame(style):
+        return L.sb_stylize(ctypes.byref(style), fake, 64, 64, fake, ctypes.byref(p), fake, fake,
+                            None, fake, ws, None)
+
+    w4 = ctypes.c_uint8 * 4
+    assert frame(sb.SbStyle(fake, fake, fake, 64, 64, 0, 4, None, None, 0,
+                            w4(2, 1, 1, 0))) == sb.SB_EINVAL
+    assert frame(sb.SbStyle(fake, fake, fake, 64, 64, 2, 4, None, None, 0,
+                            w4(1, 1, 128, 0))) == sb.SB_EINVAL

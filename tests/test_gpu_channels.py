@@ -218,3 +218,69 @@ def test_batch_mixes_formats(sb):
             assert torch.equal(j.out_rgb, rgb) and torch.equal(j.out_chunk, chunk)
             assert torch.equal(j.out_nnf, nnf)
     b.close()
+
+
+@pytest.mark.parametrize("weights", [(3, 1, 7), (1, 1, 0), (0, 2, 5), (127, 127, 1)])
+def test_weighted_tables_and_frames(sb, weights):
+    """Channel weights (strong or weak appearance guide): the weighted table
+    and frames under every kernel choice against the oracle."""
+    import torch
+
+    st_np = small_style(96, 71, 4)
+    style = sb.Style(st_np.rgb, st_np.guide, 4, weights=weights)
+    torch.cuda.synchronize()
+    lut = oracle.lut_build(st_np.guide, 4, weights)
+    say(f"weighted table {weights}")
+    np.testing.assert_array_equal(u32(style.lut), lut)
+    w, h = 150, 94
+    g = workloads.appearance_target(w, h, 4, 72)
+    jit = workloads.jitter_table(w, h, 3, 8, 73)
+    t = 60 * max(weights)
+    e_rgb, e_chunk, e_nnf = oracle.stylize(st_np.rgb, st_np.guide, lut, 4, g, jit, 3, 8, t, 2,
+                                           weights=weights)
+    prm = sb.params(3, 8, t, 2)
+    for tune in [None] + list(sb.TUNES)[::3]:
+        say(f"weighted frame {weights} tune={tune}")
+        rgb, chunk, nnf = sb.stylize(style, g, jit, prm, want_nnf=True, tune=tune)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(u32(chunk), e_chunk, err_msg=f"tune={tune}")
+        np.testing.assert_array_equal(u32(nnf), e_nnf, err_msg=f"tune={tune}")
+        np.testing.assert_array_equal(rgb.cpu().numpy(), e_rgb, err_msg=f"tune={tune}")
+
+
+def test_weighted_segmentation_and_batch(sb):
+    import torch
+
+    weights = (5, 2, 9)
+    st_np = small_style(80, 81, 4)
+    ls = workloads.voronoi_labels(80, 80, 3, 7, 82)
+    style = sb.Style(st_np.rgb, st_np.guide, 4, labels=ls, nlabels=3, weights=weights)
+    torch.cuda.synchronize()
+    luts = oracle.lut_build_labels(st_np.guide, ls, 3, 4, weights)
+    np.testing.assert_array_equal(u32(style.label_luts).reshape(3, -1), luts)
+    w, h = 120, 77
+    lt = workloads.voronoi_labels(w, h, 3, 9, 83)
+    g = workloads.appearance_target(w, h, 4, 84)
+    jit = workloads.jitter_table(w, h, 3, 8, 85)
+    say("weighted frame with the segmentation guide")
+    e = oracle.stylize_seg(st_np.rgb, st_np.guide, ls, luts, 3, 4, g, lt, jit, 3, 8, 900, 2,
+                           weights=weights)
+    rgb, chunk, nnf = sb.stylize(style, g, jit, sb.params(3, 8, 900, 2), want_nnf=True,
+                                 tgt_labels=lt)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u32(chunk), e[1])
+    np.testing.assert_array_equal(u32(nnf), e[2])
+    np.testing.assert_array_equal(rgb.cpu().numpy(), e[0])
+    say("batch mixing weighted and unweighted three-channel styles")
+    plain = sb.Style(st_np.rgb, st_np.guide, 4)
+    jobs = [sb.FrameJob(style if k % 2 else plain, workloads.appearance_target(w + k, h, 4, 86 + k),
+                        workloads.jitter_table(w + k, h, 3, 8, 87 + k), sb.params(3, 8, 900, 2))
+            for k in range(6)]
+    b = sb.Batch(use_graph=True)
+    b.run(jobs)
+    torch.cuda.synchronize()
+    for j in jobs:
+        r, c = sb.stylize(j.style, j.guide, j.jitter, j.params)
+        torch.cuda.synchronize()
+        assert torch.equal(j.out_rgb, r) and torch.equal(j.out_chunk, c)
+    b.close()
