@@ -85,6 +85,9 @@ struct FrameArgs {
   int32_t lut_log2;            // log2 of the table's entries: channels * lut_bits
   uint32_t wt02;               // channel weights w0 | w2 << 16 (three-channel guides)
   int32_t wt1;                 // channel weight w1
+  int32_t own_seeds;           // the block level loop makes its seed records itself
+                               // (8-bit two-channel table, finest spacing >= 8);
+                               // otherwise a seed pass fills the seed table first
   uint32_t threshold;
   int32_t radius;
   int32_t fmt;                 // sb_guide_fmt (read by the batch kernels)

@@ -126,16 +126,13 @@ __device__ inline const uint32_t *lut_of(const FrameArgs &a, uint32_t pidx) {
   return a.label_luts + (size_t(l) << a.lut_log2);
 }
 
-// Record idx of the padded seed table.
+// The seed record of cell (cx, cy) of level i (SeedPoint and the seed's
+// lookup): position 4x | 4y << 16 and the translation u* - q, or the empty
+// record for a cell outside the grid or a seed outside the target.
 template <int FMT>
-__device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
+__device__ inline u32x2 seed_record(const FrameArgs &a, int32_t i, int32_t cx, int32_t cy) {
   const Levels &lv = a.lv;
-  if (idx >= uint32_t(lv.poffset[lv.count])) return;
-  int32_t i = 0;
-  while (idx >= uint32_t(lv.poffset[i + 1])) ++i;
   const int32_t ncx = lv.cells_x[i], ncy = lv.cells_y[i];
-  const uint32_t local = idx - uint32_t(lv.poffset[i]), pc = uint32_t(ncx + 2);
-  const int32_t cx = int32_t(local % pc) - 1, cy = int32_t(local / pc) - 1;
   u32x2 rec = {kNoSeed, 0u};
   if (cx >= 0 && cy >= 0 && cx < ncx && cy < ncy) {
     const uint32_t j = glb(a.jitter)[lv.offset[i] + cy * ncx + cx];
@@ -149,7 +146,19 @@ __device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
       rec.y = pack_off(int32_t(u & 0xFFFFu) - int32_t(sx), int32_t(u >> 16) - int32_t(sy));
     }
   }
-  seed_table(a)[idx] = rec;
+  return rec;
+}
+
+// Record idx of the padded seed table (read by the per-pixel level loop of
+// hierarchies finer than 8 pixels; the block level loop makes its own).
+template <int FMT>
+__device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
+  const Levels &lv = a.lv;
+  if (idx >= uint32_t(lv.poffset[lv.count])) return;
+  int32_t i = 0;
+  while (idx >= uint32_t(lv.poffset[i + 1])) ++i;
+  const uint32_t local = idx - uint32_t(lv.poffset[i]), pc = uint32_t(lv.cells_x[i] + 2);
+  seed_table(a)[idx] = seed_record<FMT>(a, i, int32_t(local % pc) - 1, int32_t(local / pc) - 1);
 }
 
 template <int FMT>
@@ -268,26 +277,28 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
     gt[b] = guide_word<FMT>(a.tgt_guide, pidx[b]);
     lt[b] = SEG ? uint32_t(glb(a.tgt_labels)[pidx[b]]) : 0u;
   }
-  // record j of block b (level j / 9, neighbour j % 9) for lanes j and j + 64;
-  // a block past the frame's right edge stages the last column's cells (its
-  // pixels are all outside, so they are never used)
-  uint32_t ridx[B][2];
-  int32_t slot[B][2];
+  // record j of block b (level j / 9, neighbour j % 9) for lanes j and j + 64:
+  // read from the seed table, or, with a.own_seeds (a small lookup table, so
+  // the lookups stay in cache), made here from the jitter table, the target
+  // guide and the lookup table; a block past the frame's right edge stages
+  // the last column's cells (its pixels are all outside, so they are never
+  // used)
+  int32_t rl[B][2], rcx[B][2], rcy[B][2], slot[B][2];
 #pragma unroll
   for (int32_t b = 0; b < B; ++b) {
     const int32_t cx0 = min(bx0 + 8 * b, a.w - 1);
-    ridx[b][0] = ridx[b][1] = 0;
-    slot[b][0] = slot[b][1] = -1;
+#pragma unroll
+    for (int32_t h = 0; h < 2; ++h) rl[b][h] = rcx[b][h] = rcy[b][h] = 0, slot[b][h] = -1;
     for (int32_t i = 0; i < L; ++i) {
-      const int32_t ls = lv.log2_spacing[i], pc = lv.cells_x[i] + 2;
-      // padded coordinates of the 3x3 neighbourhood's top-left cell
-      const int32_t top = lv.poffset[i] + (by0 >> ls) * pc + (cx0 >> ls);
+      const int32_t ls = lv.log2_spacing[i];
 #pragma unroll
       for (int32_t h = 0; h < 2; ++h) {
         const int32_t k = lane + 64 * h - 9 * i;
         if (k >= 0 && k < 9) {
-          const int32_t kx = (k * 11) >> 5;  // k / 3 for k < 9
-          ridx[b][h] = uint32_t(top + (k - 3 * kx) * pc + kx);
+          const int32_t kx = (k * 11) >> 5;  // k / 3 for k < 9: x outer, y inner
+          rl[b][h] = i;
+          rcx[b][h] = (cx0 >> ls) - 1 + kx;
+          rcy[b][h] = (by0 >> ls) - 1 + (k - 3 * kx);
           slot[b][h] = b * kWaveRecs + kRecStride * i + k;
         }
       }
@@ -299,7 +310,15 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
 #pragma unroll
     for (int32_t h = 0; h < 2; ++h) {
       rec[b][h] = u32x2{0, 0};
-      if (slot[b][h] >= 0) rec[b][h] = seed_table(a)[ridx[b][h]];
+      if (slot[b][h] >= 0) {
+        if (a.own_seeds) {
+          rec[b][h] = seed_record<FMT>(a, rl[b][h], rcx[b][h], rcy[b][h]);
+        } else {
+          const int32_t i = rl[b][h];
+          rec[b][h] = seed_table(a)[uint32_t(lv.poffset[i] + (rcy[b][h] + 1) * (lv.cells_x[i] + 2) +
+                                             rcx[b][h] + 1)];
+        }
+      }
     }
   }
 #pragma unroll
@@ -395,7 +414,7 @@ __device__ inline void assign_pixel(const FrameArgs &a, int32_t x, int32_t y) {
 }
 
 // Whether every level's cells hold whole 8 x 8 blocks.
-__device__ inline bool uniform_cells(const Levels &lv) {
+__host__ __device__ inline bool uniform_cells(const Levels &lv) {
   return lv.count == 0 || lv.log2_spacing[lv.count - 1] >= 3;
 }
 
@@ -796,7 +815,8 @@ hipError_t launch_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint
 void tile_counts(const FrameArgs &a, const Tune &t, uint32_t counts[4]) {
   const uint32_t tw = 16 * uint32_t(t.ppt), th = uint32_t(t.rows);
   const uint32_t blend = ((uint32_t(a.w) + tw - 1) / tw) * ((uint32_t(a.h) + th - 1) / th);
-  counts[0] = (uint32_t(a.lv.poffset[a.lv.count]) + 255) / 256;
+  // no seed table when the block level loop makes its own records
+  counts[0] = a.own_seeds ? 0u : (uint32_t(a.lv.poffset[a.lv.count]) + 255) / 256;
   const uint32_t aw = 16 * uint32_t(t.apx);
   counts[1] = ((uint32_t(a.w) + aw - 1) / aw) * ((uint32_t(a.h) + 15) / 16);
   counts[2] = a.radius <= 3 ? blend : 0;
