@@ -100,10 +100,10 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
   a->wt02 = uint32_t(wt[0]) | (uint32_t(wt[2]) << 16);
   a->wt1 = wt[1];
   // records made in the level loop cost a table lookup per block and cell;
-  // worth it when the table (256 KiB) stays in cache and blocks hold whole
-  // cells, otherwise a separate pass builds each record once
+  // worth it when the one table (256 KiB) stays in cache and blocks hold
+  // whole cells, otherwise a separate pass builds each record once
   const Levels &lv = a->lv;
-  a->own_seeds = style->fmt == SB_GUIDE_U8X2 &&
+  a->own_seeds = style->fmt == SB_GUIDE_U8X2 && tgt_labels == nullptr &&
                  (lv.count == 0 || lv.log2_spacing[lv.count - 1] >= 3);
   a->threshold = params->threshold;
   a->radius = params->radius;

@@ -314,7 +314,11 @@ template <bool SITES, bool FINAL>
 void sep_pass(const void *in, uint64_t *out, uint32_t *lut, const uint32_t *fallback,
               size_t outer, int32_t inner, int32_t lut_bits, int32_t weight, int32_t sw,
               hipStream_t stream) {
-  const int32_t ti = inner < kSepTile ? inner : kSepTile;
+  // up to kSepTile columns per block, fewer when that leaves the chip
+  // short of blocks (the last pass of a two-channel table has one line of
+  // 2^lut_bits columns)
+  int32_t ti = inner < kSepTile ? inner : kSepTile;
+  while (ti > 1 && outer * size_t(inner / ti) < 2048) ti >>= 1;
   const size_t blocks = outer * size_t(inner / ti);
   k_sep_pass<SITES, FINAL><<<unsigned(blocks), 256, 0, stream>>>(in, out, lut, fallback, inner,
                                                                   ti, lut_bits, weight, sw);
