@@ -32,7 +32,9 @@ adversarial third channel that alone decides acceptance, and the level
 loop's invariants with the three-channel error.  Channel weights (the
 strong or weak appearance guide) are pinned by a weighted vectorised argmin,
 a zero weight that reduces the path to the first two channels, and uniform
-weights that only rescale the threshold.
+weights that only rescale the threshold.  The counter-based jitter
+generator (Philox4x64-10, from its published definition) is pinned block for
+block against numpy's own Philox bit generator (``tests/test_oracle_rng.py``).
 """
 from __future__ import annotations
 
@@ -87,6 +89,9 @@ def _load():
     lib.ora_lut_build_labels.argtypes = [vp, _u8p, i32, i32, i32, i32, i32, _u32p]
     lib.ora_lut_query.argtypes = [vp, i32, i32, i32, i32, _i64p, ctypes.c_int64, _u32p]
     lib.ora_set_threads.argtypes = [i32]
+    _u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.ora_philox4x64.argtypes = [_u64p, _u64p, _u64p]
+    lib.ora_jitter_fill.argtypes = [i32, i32, i32, i32, ctypes.c_uint64, ctypes.c_uint64, _u32p]
     lib.ora_lut_build_w.argtypes = [vp, i32, i32, i32, i32, _u8p, _u32p]
     lib.ora_lut_query_w.argtypes = [vp, i32, i32, i32, i32, _u8p, _i64p, ctypes.c_int64, _u32p]
     lib.ora_lut_build_labels_w.argtypes = [vp, _u8p, i32, i32, i32, i32, i32, _u8p, _u32p]
@@ -158,6 +163,28 @@ def set_threads(n: int) -> int:
     """Threads of the oracle's OpenMP loops (n <= 0: unchanged); returns the
     number in effect.  Timing only: results do not depend on it."""
     return int(_load().ora_set_threads(int(n)))
+
+
+def philox4x64(key, counter) -> np.ndarray:
+    """One Philox4x64-10 block: four uint64 words for a 2-word key and a
+    4-word counter."""
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    out = np.zeros(4, np.uint64)
+    p = ctypes.POINTER(ctypes.c_uint64)
+    _load().ora_philox4x64(k.ctypes.data_as(p), c.ctypes.data_as(p), out.ctypes.data_as(p))
+    return out
+
+
+def jitter_fill(w: int, h: int, levels: int, finest: int, seed: int, stream: int = 0) -> np.ndarray:
+    """The jitter table drawn from Philox4x64-10 under key (seed, stream):
+    entry e takes word 0 of block (e, 0, 0, 0), jx / jy from its low / high
+    half modulo the level's spacing."""
+    n = jitter_len(w, h, levels, finest)
+    out = np.zeros(max(n, 1), np.uint32)
+    _check(_load().ora_jitter_fill(w, h, levels, finest, seed, stream, _ptr(out, _u32p)),
+           "jitter_fill")
+    return out[:n]
 
 
 def jitter_len(w: int, h: int, levels: int, finest: int) -> int:

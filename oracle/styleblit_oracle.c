@@ -18,8 +18,8 @@
  *   - level spacings h_i = finest << (L-1-i), level 0 coarsest (the paper's
  *     2^l, l = L..1, is finest = 2);
  *   - RandomJitterTable: one integer jitter (jx, jy) in [0,h)^2 per cell and
- *     level, passed in; SeedPoint(b) = h*b + j, the integer form of
- *     floor(h*(b + j/h));
+ *     level, passed in (or drawn by ora_jitter_fill from Philox4x64-10);
+ *     SeedPoint(b) = h*b + j, the integer form of floor(h*(b + j/h));
  *   - seeds outside the target are not candidates; a level whose 3x3
  *     neighbourhood holds no in-image seed is skipped;
  *   - NearestSeed scans x outer, y inner over {-1,0,1} and keeps the first
@@ -379,6 +379,71 @@ int64_t ora_jitter_len(int w, int h, int levels, int finest)
 {
     seeds_t S = {w, h, levels, finest, NULL};
     return level_offset(&S, levels);
+}
+
+/* ---------------------------------------- jitter from a counter-based RNG
+ *
+ * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011), written from its definition: ten rounds, each
+ * multiplying words 0 and 2 of the counter by the two round constants and
+ * mixing the halves of the 128-bit products with words 1 and 3 and the key,
+ * which is bumped by the two Weyl constants between rounds.
+ */
+static void mul64_hilo(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    const unsigned __int128 p = (unsigned __int128)a * b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void ora_philox4x64(const uint64_t key_in[2], const uint64_t ctr_in[4], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+    uint64_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t hi0, lo0, hi1, lo1;
+        mul64_hilo(M0, c0, &hi0, &lo0);
+        mul64_hilo(M1, c2, &hi1, &lo1);
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* The jitter table of a W x H target drawn from Philox4x64-10 under key
+ * (seed, stream): entry e (levels coarsest first, cells row-major) takes word
+ * 0 of the block at counter (e, 0, 0, 0); jx = word mod h_i and jy = (word >>
+ * 32) mod h_i for the level's spacing h_i (a power of two). */
+int ora_jitter_fill(int w, int h, int levels, int finest, uint64_t seed, uint64_t stream,
+                    uint32_t *out)
+{
+    if (w < 1 || h < 1 || levels < 0 || levels > 12 || finest < 1 || (finest & (finest - 1)))
+        return ORA_EINVAL;
+    if (!out && levels > 0) return ORA_EINVAL;
+    seeds_t S = {w, h, levels, finest, NULL};
+    const uint64_t key[2] = {seed, stream};
+    for (int i = 0; i < levels; ++i) {
+        const uint64_t hm = (uint64_t)level_spacing(&S, i) - 1;
+        for (int64_t e = level_offset(&S, i); e < level_offset(&S, i + 1); ++e) {
+            const uint64_t ctr[4] = {(uint64_t)e, 0, 0, 0};
+            uint64_t r[4];
+            ora_philox4x64(key, ctr, r);
+            out[e] = (uint32_t)(r[0] & hm) | ((uint32_t)((r[0] >> 32) & hm) << 16);
+        }
+    }
+    return ORA_OK;
 }
 
 static int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
