@@ -113,6 +113,16 @@ const char *sb_last_hip_error(void);
  * it).  Returns -1 on invalid arguments. */
 int64_t sb_jitter_len(int32_t w, int32_t h, int32_t levels, int32_t finest);
 
+/* Draw that table on the device from a counter-based generator, so the
+ * per-frame seed schedule of an animation (Sec. 3.3: seeds re-drawn every
+ * frame, or every few frames) needs no host random numbers: Philox4x64-10
+ * (Salmon et al., SC 2011) under key (seed, stream_id); entry e takes word 0
+ * of the block at counter (e, 0, 0, 0), jx = word mod h_i and
+ * jy = (word >> 32) mod h_i.  jitter [device] sb_jitter_len() entries.
+ * SB_EINVAL on invalid sizes (nothing enqueued); no work when L = 0. */
+int sb_jitter_fill(int32_t w, int32_t h, int32_t levels, int32_t finest, uint64_t seed,
+                   uint64_t stream_id, uint32_t *jitter, hipStream_t stream);
+
 /* ------------------------------------------------- style registration */
 
 /* Texels of the padded exemplar of an Sw x Sh source (0 on invalid sizes).

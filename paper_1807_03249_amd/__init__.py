@@ -123,6 +123,7 @@ def lib():
                                   ctypes.POINTER(ctypes.c_void_p)]
     L.sb_batch_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(SbFrame), i32, vp, sz, vp]
     L.sb_batch_destroy.argtypes = [ctypes.c_void_p]
+    L.sb_jitter_fill.argtypes = [i32, i32, i32, i32, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
     L.sb_change_workspace_bytes.restype = sz
     L.sb_frame_change.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp, sz, vp]
     _lib = L
@@ -343,6 +344,22 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     if want_nnf:
         return out_rgb, out_chunk, nnf
     return out_rgb, out_chunk
+
+
+def jitter_fill(w: int, h: int, levels: int, finest: int, seed: int, stream_id: int = 0,
+                out=None):
+    """A jitter table drawn on the device (sb_jitter_fill: Philox4x64-10
+    under key (seed, stream_id)), as an int32 device tensor, enqueued on the
+    current stream."""
+    torch = _torch()
+    n = jitter_len(w, h, levels, finest)
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    elif out.numel() < n or out.element_size() != 4 or not out.is_cuda:
+        raise ValueError(f"jitter table needs {n} 32-bit device entries")
+    _check(lib().sb_jitter_fill(w, h, levels, finest, seed, stream_id, out.data_ptr(),
+                                _stream(torch)), "sb_jitter_fill")
+    return out
 
 
 def frame_change(chunk_a, chunk_b, nnf_a=None, nnf_b=None, counts=None, workspace=None):

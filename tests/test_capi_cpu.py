@@ -216,3 +216,13 @@ def test_channel_weight_validation(L):
                             w4(2, 1, 1, 0))) == sb.SB_EINVAL
     assert frame(sb.SbStyle(fake, fake, fake, 64, 64, 2, 4, None, None, 0,
                             w4(1, 1, 128, 0))) == sb.SB_EINVAL
+
+
+def test_jitter_fill_validation(L):
+    import paper_1807_03249_amd as sb
+
+    assert L.sb_jitter_fill(0, 10, 3, 8, 1, 0, 0x1000, None) == sb.SB_EINVAL
+    assert L.sb_jitter_fill(10, 10, 3, 6, 1, 0, 0x1000, None) == sb.SB_EINVAL  # finest not 2^k
+    assert L.sb_jitter_fill(10, 10, 13, 1, 1, 0, 0x1000, None) == sb.SB_EINVAL
+    assert L.sb_jitter_fill(10, 10, 3, 8, 1, 0, None, None) == sb.SB_EINVAL
+    assert L.sb_jitter_fill(10, 10, 0, 8, 1, 0, None, None) == sb.SB_OK  # no levels: no work

@@ -174,3 +174,42 @@ def test_plain_serving_keeps_nnf_and_sessions(sb):
         rgb, chunk, nnf = sb.stylize(r.style, r.guide, r.jitter, r.params, want_nnf=True)
         torch.cuda.synchronize()
         assert torch.equal(r.out_nnf, nnf)
+
+
+@pytest.mark.parametrize("w,h,levels,finest,seed,stream", [
+    (200, 136, 4, 8, 1, 0), (97, 61, 3, 4, 2**64 - 1, 2**63), (3840, 2160, 5, 8, 42, 7),
+    (1, 1, 1, 1, 5, 5), (64, 64, 0, 8, 1, 1)])
+def test_device_jitter_matches_oracle(sb, w, h, levels, finest, seed, stream):
+    import torch
+
+    say(f"device jitter {w}x{h} L={levels} f={finest} seed={seed} stream={stream}")
+    j = sb.jitter_fill(w, h, levels, finest, seed, stream)
+    torch.cuda.synchronize()
+    n = sb.jitter_len(w, h, levels, finest)
+    np.testing.assert_array_equal(j.cpu().numpy().view(np.uint32)[:n],
+                                  oracle.jitter_fill(w, h, levels, finest, seed, stream))
+
+
+def test_frames_with_device_seed_schedule(sb, style1):
+    """An animated sequence whose per-frame jitter comes from the device
+    generator (seed fixed, stream = frame index / hold) equals the oracle fed
+    the oracle's tables."""
+    import torch
+
+    st = style1
+    w, h, hold = 160, 120, 2
+    p = workloads.config(1)[1][0].params
+    guides = workloads.animated_bump_guides(w, h, 5, 4, 2.0, 91)
+    style = sb.Style(st.rgb, st.guide, st.lut_bits)
+    lut = oracle.lut_build(st.guide, st.lut_bits)
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
+    for f, g in enumerate(guides):
+        say(f"device seed schedule frame {f}")
+        j = sb.jitter_fill(w, h, p.levels, p.finest, 1234, f // hold)
+        rgb, chunk = sb.stylize(style, g, j, prm)
+        torch.cuda.synchronize()
+        e = oracle.stylize(st.rgb, st.guide, lut, st.lut_bits, g,
+                           oracle.jitter_fill(w, h, p.levels, p.finest, 1234, f // hold),
+                           p.levels, p.finest, p.threshold, p.radius)
+        np.testing.assert_array_equal(chunk.cpu().numpy().view(np.uint32), e[1])
+        np.testing.assert_array_equal(rgb.cpu().numpy(), e[0])
