@@ -80,6 +80,18 @@ def traffic_per_launch(workload_name):
     return fetch + write
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def valu_issue(workload_name, kernel_prefix, kernel_ms):
     """Vector-ALU issue rate of one per-frame kernel: its wave instructions
     per launch from the committed counter summary over the live kernel time,
@@ -262,6 +274,8 @@ def main():
         oracle.set_threads(nthreads)
         cpu["single_thread"] = {"value": round(w * h * n1 / c1 / 1e6, 3),
                                 "sample": f"{n1} full {w}x{h} frames on one thread"}
+        cpu["cpu_model"] = cpu_model()
+        cpu["host_cpus"] = os.cpu_count()
 
     seg = None if args.no_seg else seg_leg(sb, torch, np, workloads, st_np, fr, prm, ms_per_step)
     anim = None if args.no_anim else anim_leg(sb, torch, np, workloads, style, w, h, p)
