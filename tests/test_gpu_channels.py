@@ -284,3 +284,48 @@ def test_weighted_segmentation_and_batch(sb):
         torch.cuda.synchronize()
         assert torch.equal(j.out_rgb, r) and torch.equal(j.out_chunk, c)
     b.close()
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_random_three_channel_cases(sb, case):
+    """Random sizes, hierarchies, thresholds, radii, weights and (half the
+    cases) label maps, against the oracle."""
+    import torch
+
+    rng = np.random.default_rng(1000 + case)
+    ssz = int(rng.integers(24, 80))
+    bits = int(rng.integers(1, 6))
+    st_np = small_style(ssz, 2000 + case, bits)
+    weights = tuple(int(v) for v in rng.integers(0, 12, 3)) if case % 3 else None
+    w, h = int(rng.integers(1, 150)), int(rng.integers(1, 120))
+    levels = int(rng.integers(0, 5))
+    finest = int(2 ** rng.integers(0, 4))
+    while levels > 0 and (finest << (levels - 1)) > 8192:
+        levels -= 1
+    t = int(rng.integers(0, 3000))
+    r = int(rng.integers(0, 4))
+    g = workloads.appearance_target(w, h, 3, 3000 + case)
+    jit = oracle.jitter_fill(w, h, levels, finest, 4000 + case, case)
+    seg = case % 2 == 1
+    say(f"random three-channel case {case}: src {ssz} bits {bits} {w}x{h} L={levels} "
+        f"f={finest} t={t} r={r} w={weights} seg={seg}")
+    prm = sb.params(levels, finest, t, r)
+    if seg:
+        nl = int(rng.integers(1, 5))
+        ls = workloads.voronoi_labels(ssz, ssz, nl, 6, 5000 + case)
+        lt = workloads.voronoi_labels(w, h, nl + 1, 5, 6000 + case)
+        style = sb.Style(st_np.rgb, st_np.guide, bits, labels=ls, nlabels=nl, weights=weights)
+        luts = oracle.lut_build_labels(st_np.guide, ls, nl, bits, weights)
+        e = oracle.stylize_seg(st_np.rgb, st_np.guide, ls, luts, nl, bits, g, lt, jit, levels,
+                               finest, t, r, weights=weights)
+        rgb, chunk, nnf = sb.stylize(style, g, jit, prm, want_nnf=True, tgt_labels=lt)
+    else:
+        style = sb.Style(st_np.rgb, st_np.guide, bits, weights=weights)
+        lut = oracle.lut_build(st_np.guide, bits, weights)
+        e = oracle.stylize(st_np.rgb, st_np.guide, lut, bits, g, jit, levels, finest, t, r,
+                           weights=weights)
+        rgb, chunk, nnf = sb.stylize(style, g, jit, prm, want_nnf=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u32(chunk), e[1])
+    np.testing.assert_array_equal(u32(nnf), e[2])
+    np.testing.assert_array_equal(rgb.cpu().numpy(), e[0])

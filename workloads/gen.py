@@ -171,6 +171,14 @@ def sphere_guide_u8(size: int) -> np.ndarray:
     return _encode_normal(nx, ny)
 
 
+def _gradient(hf: np.ndarray):
+    """Central differences per axis (one-sided at the ends); zero along an
+    axis of a single sample."""
+    gy = np.gradient(hf, axis=0) if hf.shape[0] > 1 else np.zeros_like(hf)
+    gx = np.gradient(hf, axis=1) if hf.shape[1] > 1 else np.zeros_like(hf)
+    return gy, gx
+
+
 def bump_guide_u8(w: int, h: int, nbumps: int, seed: int) -> np.ndarray:
     """Normals of a heightfield made of Gaussian bumps (centres uniform,
     sigma in [0.03, 0.12]*min(w, h), signed amplitude in [0.5, 1.5]*sigma)."""
@@ -190,7 +198,7 @@ def bump_guide_u8(w: int, h: int, nbumps: int, seed: int) -> np.ndarray:
         xs = np.arange(x0, x1) + 0.5 - cx
         ys = np.arange(y0, y1) + 0.5 - cy
         hf[y0:y1, x0:x1] += amp * np.exp(-(ys[:, None] ** 2 + xs[None, :] ** 2) / (2 * sig * sig))
-    gy, gx = np.gradient(hf)
+    gy, gx = _gradient(hf)
     norm = np.sqrt(gx * gx + gy * gy + 1.0)
     return _encode_normal(-gx / norm, -gy / norm)
 
@@ -223,7 +231,7 @@ def animated_bump_guides(w: int, h: int, nbumps: int, nframes: int, drift: float
             xs = np.arange(x0, x1) + 0.5 - cx
             ys = np.arange(y0, y1) + 0.5 - cy
             hf[y0:y1, x0:x1] += amp * np.exp(-(ys[:, None] ** 2 + xs[None, :] ** 2) / (2 * sig * sig))
-        gy, gx = np.gradient(hf)
+        gy, gx = _gradient(hf)
         norm = np.sqrt(gx * gx + gy * gy + 1.0)
         out.append(_encode_normal(-gx / norm, -gy / norm))
     return out
