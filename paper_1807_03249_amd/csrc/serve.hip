@@ -174,6 +174,8 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
   std::vector<sb_frame> fr(static_cast<size_t>(n));
   std::deque<int32_t> pending, admitted, plain_inflight;
   std::map<int32_t, SessionTail> tails;  // session -> slot and batch of its latest frame
+  std::vector<Slot *> done;               // slots found finished in one polling pass
+  done.reserve(sl.size());
   int32_t next = 0, finished = 0, batch_id = 0, rc = SB_OK;
   const auto t0 = std::chrono::steady_clock::now();
   auto finish = [&](int32_t i, double t) {
@@ -236,7 +238,7 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
       // query every slot first, then retire them at one time stamp: a slot
       // that waited for another completes after it, and the two must not be
       // stamped in the opposite order
-      std::vector<Slot *> done;
+      done.clear();
       for (auto &s : sl) {
         if (!s.busy) continue;
         const hipError_t q = hipEventQuery(s.done);

@@ -83,6 +83,25 @@ class Request:
         return int(self.guide.shape[1])
 
 
+def _check_request(torch, i: int, r: Request):
+    """Shapes and types of a request's device tensors (the C loop checks
+    sizes and parameters, not what the pointers hold)."""
+    h, w = r.h, r.w
+
+    def need(t, shape, dtype, what):
+        if t is None:
+            return
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"request {i}: {what} must be a contiguous device tensor")
+        if tuple(t.shape) != shape or t.dtype != dtype:
+            raise ValueError(f"request {i}: {what} must be {dtype} of shape {shape}")
+
+    need(r.out_rgb, (h, w, 3), torch.uint8, "out_rgb")
+    need(r.out_chunk, (h, w), torch.int32, "out_chunk")
+    need(r.out_nnf, (h, w), torch.int32, "out_nnf")
+    need(r.tgt_labels, (h, w), torch.uint8, "tgt_labels")
+
+
 def run(requests: Sequence[Request], slots: int = 4, max_batch: int = 16,
         budget_bytes: int = 1 << 30, use_graph: bool = True, plain: bool = False, tune=None,
         blocks_per_cu: int = 0):
@@ -96,6 +115,7 @@ def run(requests: Sequence[Request], slots: int = 4, max_batch: int = 16,
     reqs = (SbRequest * n)()
     max_ws = 0
     for i, r in enumerate(requests):
+        _check_request(torch, i, r)
         reqs[i] = SbRequest(r.arrival_s, ctypes.pointer(r.style.c), r.guide.data_ptr(),
                             r.jitter.data_ptr(), r.w, r.h, r.params,
                             r.out_rgb.data_ptr() if r.out_rgb is not None else None,
