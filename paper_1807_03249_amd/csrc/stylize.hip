@@ -441,10 +441,19 @@ __device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t t
   }
 }
 
+// Tile of workgroup `bid` out of n: workgroups are dealt to the 8 XCDs in
+// turn (bid mod 8), so XCD x takes the x-th contiguous run of tiles -- a band
+// of rows -- and its L2 sees the source regions of one band instead of
+// scraps of all of them.  A bijection on [0, n) for any n.
+__device__ inline uint32_t xcd_tile(uint32_t bid, uint32_t n) {
+  const uint32_t x = bid & 7u, local = bid >> 3, q = n >> 3, r = n & 7u;
+  return x * q + min(x, r) + local;
+}
+
 template <int FMT, int G, int B, bool SEG>
 __global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
   __shared__ __attribute__((aligned(16))) uint32_t recs[4 * 2 * B * kWaveRecs];
-  assign_tile<FMT, G, B, SEG>(a, blockIdx.x, threadIdx.x, recs);
+  assign_tile<FMT, G, B, SEG>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, recs);
 }
 
 // Exact n / k for n < 2^20 and 1 <= k <= 225 via a float reciprocal and one
@@ -678,7 +687,7 @@ __device__ inline void blend_tile_r(const FrameArgs &a, uint32_t t_index, uint32
 template <int R, int PPT, int TH>
 __global__ void __launch_bounds__(16 * TH) k_blend(FrameArgs a) {
   __shared__ __attribute__((aligned(16))) int32_t lin[blend_lw(16 * PPT, R) * blend_lh(TH, R)];
-  blend_tile<R, PPT, TH>(a, blockIdx.x, threadIdx.x, lin);
+  blend_tile<R, PPT, TH>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lin);
 }
 
 // ------------------------------------------------------------------ batches
