@@ -723,8 +723,26 @@ __device__ __forceinline__ void batch_loop(const unsigned char *desc, Body body)
   for (uint32_t i = threadIdx.x; i <= n; i += NT) pre[i] = gpre[i];
   __syncthreads();
   const uint32_t total = pre[n];
+  // XCD-aware order: runs of kXcdRun consecutive tiles go to the XCDs in
+  // turn, and the workgroups on XCD x (those with blockIdx mod 8 = x) stride
+  // through the runs of x, so an XCD's L2 serves neighbouring tiles while the
+  // runs keep the XCDs' shares balanced across the batch
+  // (a grid of fewer than 8 workgroups strides plainly: some XCDs would
+  // own runs but have no workgroup)
+  constexpr uint32_t kXcdRun = 32;
+  const bool xcd = gridDim.x >= 8u;
+  const uint32_t x = xcd ? blockIdx.x & 7u : 0u, local = xcd ? blockIdx.x >> 3 : blockIdx.x;
+  const uint32_t per = xcd ? (gridDim.x >> 3) + (x < (gridDim.x & 7u) ? 1u : 0u) : gridDim.x;
   uint32_t cur = ~0u;
-  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+  for (uint32_t s = local;; s += per) {
+    const uint32_t t = xcd ? ((s / kXcdRun) * 8u + x) * kXcdRun + s % kXcdRun : s;
+    if (!xcd && t >= total) break;
+    if (t >= total) {
+      // runs of this XCD beyond the end: the next may still hold tiles only
+      // if this one was the partly filled last run
+      if ((s / kXcdRun) * 8u * kXcdRun >= total) break;
+      continue;
+    }
     const uint32_t f = frame_of(pre, n, t);
     if (f != cur) {  // block-uniform
       const uint32_t *src = reinterpret_cast<const uint32_t *>(desc + batch_frames_offset() +
