@@ -149,6 +149,13 @@ __device__ inline u32x2 seed_record(const FrameArgs &a, int32_t i, int32_t cx, i
   return rec;
 }
 
+// The table of a pixel's own lookup: the unconstrained one, or with the
+// segmentation guide the table of its label lt (past the last: the last).
+template <bool SEG>
+__device__ inline const uint32_t *own_table(const FrameArgs &a, uint32_t lt) {
+  return SEG ? a.label_luts + (size_t(min(lt, uint32_t(a.nlabels - 1))) << a.lut_log2) : a.lut;
+}
+
 // Record idx of the padded seed table (read by the per-pixel level loop of
 // hierarchies finer than 8 pixels; the block level loop makes its own).
 template <int FMT>
@@ -332,16 +339,18 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
     }
   }
   wave_lds_sync();
-  // the pixels' own lookups, used when no level accepts
+  // the pixels' own lookups, used when no level accepts: requested up front
+  // from a table that stays in cache (up to 2^18 entries, 1 MiB), else only
+  // for the pixels that end up needing them (a large table is mostly cold,
+  // and few pixels fall back)
+  const bool eager = a.lut_log2 <= 18;
   uint32_t own[B], chunk[B], off[B];
   short2_t p4[B];
   bool done[B];
 #pragma unroll
   for (int32_t b = 0; b < B; ++b) {
-    const uint32_t *table =
-        SEG ? a.label_luts + (size_t(min(lt[b], uint32_t(a.nlabels - 1))) << a.lut_log2)
-            : a.lut;
-    own[b] = glb(table)[lut_bin<FMT>(gt[b], a.lut_shift, a.lut_bits)];
+    own[b] = 0;
+    if (eager) own[b] = glb(own_table<SEG>(a, lt[b]))[lut_bin<FMT>(gt[b], a.lut_shift, a.lut_bits)];
     p4[b] = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x[b]), uint32_t(4 * y)));
     chunk[b] = off[b] = 0;
     done[b] = !in[b];
@@ -359,6 +368,7 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
   for (int32_t b = 0; b < B; ++b) {
     if (!in[b]) continue;
     if (!done[b]) {  // no level accepted: the pixel's own lookup
+      if (!eager) own[b] = glb(own_table<SEG>(a, lt[b]))[lut_bin<FMT>(gt[b], a.lut_shift, a.lut_bits)];
       chunk[b] = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x[b]);
       off[b] = pack_off(int32_t(own[b] & 0xFFFFu) - x[b], int32_t(own[b] >> 16) - y);
     }
