@@ -232,7 +232,9 @@ int sb_stylize_ex(const sb_style *style, const void *tgt_guide, int32_t w, int32
 /* sb_stylize_ex that also records events[0..3] (timing events, e.g. from
  * sb_timing_events_create) on `stream` before the seed-record pass, before
  * the level-loop pass, before the voting pass and after it, for per-pass
- * timing. */
+ * timing.  (Single frames of 8-bit two-channel styles without labels make
+ * their seed records inside the level loop, with no seed pass: events 0 and
+ * 1 are then recorded back to back.) */
 int sb_stylize_timed(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
                      const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
                      uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
