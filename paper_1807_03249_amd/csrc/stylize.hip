@@ -466,14 +466,13 @@ __global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
   assign_tile<FMT, G, B, SEG>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, recs);
 }
 
-// Exact n / k for n < 2^20 and 1 <= k <= 225 via a float reciprocal and one
-// correction step each way.
-__device__ inline uint32_t div_small(uint32_t n, uint32_t k) {
-  uint32_t q = uint32_t(float(n) * __builtin_amdgcn_rcpf(float(k)));
-  int32_t r = int32_t(n) - int32_t(q * k);
-  if (r < 0) --q;
-  else if (r >= int32_t(k)) ++q;
-  return q;
+// Exact floor(n / k) for n < 2^16 and 1 <= k <= 225, given rk within one ulp
+// of 1/k (v_rcp_f32): (n + 1/2) * rk lies within 0.5/k of (n + 1/2)/k, whose
+// fractional part keeps at least 0.5/k from the next integer, so truncation
+// gives floor(n / k).  (Checked exhaustively over every such n and k and the
+// three floats nearest 1/k.)
+__device__ inline uint32_t div_small(uint32_t n, float rk) {
+  return uint32_t((float(n) + 0.5f) * rk);
 }
 
 // LDS row length and rows of a voting tile of TW x TH pixels and radius R
@@ -655,8 +654,9 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
     // (mod 2^32); every channel sum is < 2^16 and k <= 225
     const uint32_t gk = S[j] - RB[j];
     const uint32_t k = gk >> 24, hk = k >> 1;
-    c[j] = div_small((RB[j] & 0xFFFFu) + hk, k) | (div_small(((gk >> 8) & 0xFFFFu) + hk, k) << 8) |
-           (div_small((RB[j] >> 16) + hk, k) << 16);
+    const float rk = __builtin_amdgcn_rcpf(float(k));
+    c[j] = div_small((RB[j] & 0xFFFFu) + hk, rk) | (div_small(((gk >> 8) & 0xFFFFu) + hk, rk) << 8) |
+           (div_small((RB[j] >> 16) + hk, rk) << 16);
   }
   const size_t at = 3 * (size_t(y) * size_t(a.w) + size_t(x));
   SB_GLOBAL uint8_t *o = glb(a.out_rgb) + at;
