@@ -143,7 +143,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(frames are independent: see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "(frames are independent, so several GPUs would each run their own share of "
+              "the frames with no exchange between them)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
