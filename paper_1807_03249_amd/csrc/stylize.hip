@@ -126,18 +126,18 @@ __device__ inline const uint32_t *lut_of(const FrameArgs &a, uint32_t pidx) {
   return a.label_luts + (size_t(l) << a.lut_log2);
 }
 
-// The seed record of cell (cx, cy) of level i (SeedPoint and the seed's
-// lookup): position 4x | 4y << 16 and the translation u* - q, or the empty
-// record for a cell outside the grid or a seed outside the target.
+// The seed record of cell (cx, cy) of a level with log2 spacing ls, a
+// ncx x ncy cell grid and its jitter entries from joff on (SeedPoint and the
+// seed's lookup): position 4x | 4y << 16 and the translation u* - q, or the
+// empty record for a cell outside the grid or a seed outside the target.
 template <int FMT>
-__device__ inline u32x2 seed_record(const FrameArgs &a, int32_t i, int32_t cx, int32_t cy) {
-  const Levels &lv = a.lv;
-  const int32_t ncx = lv.cells_x[i], ncy = lv.cells_y[i];
+__device__ inline u32x2 seed_record(const FrameArgs &a, int32_t ls, int32_t ncx, int32_t ncy,
+                                    int32_t joff, int32_t cx, int32_t cy) {
   u32x2 rec = {kNoSeed, 0u};
   if (cx >= 0 && cy >= 0 && cx < ncx && cy < ncy) {
-    const uint32_t j = glb(a.jitter)[lv.offset[i] + cy * ncx + cx];
-    const uint32_t sx = (uint32_t(cx) << lv.log2_spacing[i]) + (j & 0xFFFFu);
-    const uint32_t sy = (uint32_t(cy) << lv.log2_spacing[i]) + (j >> 16);
+    const uint32_t j = glb(a.jitter)[joff + cy * ncx + cx];
+    const uint32_t sx = (uint32_t(cx) << ls) + (j & 0xFFFFu);
+    const uint32_t sy = (uint32_t(cy) << ls) + (j >> 16);
     if (sx < uint32_t(a.w) && sy < uint32_t(a.h)) {
       const uint32_t g = guide_word<FMT>(a.tgt_guide, sy * uint32_t(a.w) + sx);
       const uint32_t u =
@@ -165,7 +165,9 @@ __device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
   int32_t i = 0;
   while (idx >= uint32_t(lv.poffset[i + 1])) ++i;
   const uint32_t local = idx - uint32_t(lv.poffset[i]), pc = uint32_t(lv.cells_x[i] + 2);
-  seed_table(a)[idx] = seed_record<FMT>(a, i, int32_t(local % pc) - 1, int32_t(local / pc) - 1);
+  seed_table(a)[idx] = seed_record<FMT>(a, lv.log2_spacing[i], lv.cells_x[i], lv.cells_y[i],
+                                        lv.offset[i], int32_t(local % pc) - 1,
+                                        int32_t(local / pc) - 1);
 }
 
 template <int FMT>
@@ -289,42 +291,44 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
   // the lookups stay in cache), made here from the jitter table, the target
   // guide and the lookup table; a block past the frame's right edge stages
   // the last column's cells (its pixels are all outside, so they are never
-  // used)
-  int32_t rl[B][2], rcx[B][2], rcy[B][2], slot[B][2];
-#pragma unroll
-  for (int32_t b = 0; b < B; ++b) {
-    const int32_t cx0 = min(bx0 + 8 * b, a.w - 1);
-#pragma unroll
-    for (int32_t h = 0; h < 2; ++h) rl[b][h] = rcx[b][h] = rcy[b][h] = 0, slot[b][h] = -1;
-    for (int32_t i = 0; i < L; ++i) {
-      const int32_t ls = lv.log2_spacing[i];
-#pragma unroll
-      for (int32_t h = 0; h < 2; ++h) {
-        const int32_t k = lane + 64 * h - 9 * i;
-        if (k >= 0 && k < 9) {
-          const int32_t kx = (k * 11) >> 5;  // k / 3 for k < 9: x outer, y inner
-          rl[b][h] = i;
-          rcx[b][h] = (cx0 >> ls) - 1 + kx;
-          rcy[b][h] = (by0 >> ls) - 1 + (k - 3 * kx);
-          slot[b][h] = b * kWaveRecs + kRecStride * i + k;
-        }
-      }
-    }
-  }
+  // used).  A lane's level geometry follows from the spacings h_i =
+  // h_0 / 2^i: log2 spacing ls0 - i and ceil(extent / h_i) cells per axis;
+  // only the level's first jitter entry (own records) or first table record
+  // is looked up, by a select per level, so nothing is indexed per lane in
+  // the kernel arguments.
+  const int32_t ls0 = L > 0 ? lv.log2_spacing[0] : 0;
+  const int32_t *first = a.own_seeds ? lv.offset : lv.poffset;
   u32x2 rec[B][2];
+  int32_t slot[B][2];
 #pragma unroll
-  for (int32_t b = 0; b < B; ++b) {
+  for (int32_t h = 0; h < 2; ++h) {
+    if (h > 0 && 9 * L <= 64) {  // one record per lane suffices
 #pragma unroll
-    for (int32_t h = 0; h < 2; ++h) {
+      for (int32_t b = 0; b < B; ++b) slot[b][h] = -1;
+      continue;
+    }
+    const uint32_t j = uint32_t(lane + 64 * h);
+    const uint32_t i = (j * 57u) >> 9;  // j / 9 for j < 128
+    const uint32_t k = j - 9u * i;
+    const uint32_t kx = (k * 11u) >> 5;  // k / 3 for k < 9: x outer, y inner
+    const bool staged = j < uint32_t(9 * L);
+    const int32_t ls = ls0 - int32_t(min(i, uint32_t(max(L - 1, 0))));  // clamped past the records
+    const int32_t ncx = ((a.w - 1) >> ls) + 1, ncy = ((a.h - 1) >> ls) + 1;
+    const int32_t rcy = (by0 >> ls) - 1 + int32_t(k - 3u * kx);
+    int32_t f = 0;
+#pragma unroll 1
+    for (int32_t l = 1; l < L; ++l) f = i >= uint32_t(l) ? first[l] : f;
+#pragma unroll
+    for (int32_t b = 0; b < B; ++b) {
+      const int32_t cx0 = min(bx0 + 8 * b, a.w - 1);
+      const int32_t rcx = (cx0 >> ls) - 1 + int32_t(kx);
+      slot[b][h] = staged ? b * kWaveRecs + kRecStride * int32_t(i) + int32_t(k) : -1;
       rec[b][h] = u32x2{0, 0};
-      if (slot[b][h] >= 0) {
-        if (a.own_seeds) {
-          rec[b][h] = seed_record<FMT>(a, rl[b][h], rcx[b][h], rcy[b][h]);
-        } else {
-          const int32_t i = rl[b][h];
-          rec[b][h] = seed_table(a)[uint32_t(lv.poffset[i] + (rcy[b][h] + 1) * (lv.cells_x[i] + 2) +
-                                             rcx[b][h] + 1)];
-        }
+      if (staged) {
+        if (a.own_seeds)
+          rec[b][h] = seed_record<FMT>(a, ls, ncx, ncy, f, rcx, rcy);
+        else
+          rec[b][h] = seed_table(a)[uint32_t(f + (rcy + 1) * (ncx + 2) + rcx + 1)];
       }
     }
   }
