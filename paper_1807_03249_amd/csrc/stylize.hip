@@ -13,6 +13,10 @@
 //   k_blend   the voting step (end of Sec. 3.2): a tile of offsets with an
 //             r-pixel halo in LDS; each lane averages the (2r+1)^2 votes of
 //             four adjacent pixels, one vector gather per (cell, pixel run).
+//
+// Every side is at most SB_MAX_SIDE = 8192 (the chunk code holds 13-bit
+// coordinates), so pixel and texel indices are formed with full-rate 24-bit
+// multiplies (__umul24 / __mul24) instead of 32- or 64-bit ones.
 #include "sb_internal.h"
 
 namespace sb {
@@ -135,13 +139,13 @@ __device__ inline u32x2 seed_record(const FrameArgs &a, int32_t ls, int32_t ncx,
                                     int32_t joff, int32_t cx, int32_t cy) {
   u32x2 rec = {kNoSeed, 0u};
   if (cx >= 0 && cy >= 0 && cx < ncx && cy < ncy) {
-    const uint32_t j = glb(a.jitter)[joff + cy * ncx + cx];
+    const uint32_t j = glb(a.jitter)[uint32_t(joff) + __umul24(uint32_t(cy), uint32_t(ncx)) + uint32_t(cx)];
     const uint32_t sx = (uint32_t(cx) << ls) + (j & 0xFFFFu);
     const uint32_t sy = (uint32_t(cy) << ls) + (j >> 16);
     if (sx < uint32_t(a.w) && sy < uint32_t(a.h)) {
-      const uint32_t g = guide_word<FMT>(a.tgt_guide, sy * uint32_t(a.w) + sx);
-      const uint32_t u =
-          glb(lut_of(a, sy * uint32_t(a.w) + sx))[lut_bin<FMT>(g, a.lut_shift, a.lut_bits)];
+      const uint32_t at = __umul24(sy, uint32_t(a.w)) + sx;
+      const uint32_t g = guide_word<FMT>(a.tgt_guide, at);
+      const uint32_t u = glb(lut_of(a, at))[lut_bin<FMT>(g, a.lut_shift, a.lut_bits)];
       rec.x = pack_xy(4 * sx, 4 * sy);
       rec.y = pack_off(int32_t(u & 0xFFFFu) - int32_t(sx), int32_t(u >> 16) - int32_t(sy));
     }
@@ -234,7 +238,7 @@ __device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *
       const int32_t vx = x[b] + off_x(wo[b][u]), vy = y + off_y(wo[b][u]);
       // non-short-circuit: keeps the group one straight-line block
       ok[b][u] = (i0 + u < L) & (key != INT32_MAX) & (uint32_t(vx) < sw) & (uint32_t(vy) < sh);
-      g[b][u] = ok[b][u] ? uint32_t(vy) * sw + uint32_t(vx) : 0u;
+      g[b][u] = ok[b][u] ? __umul24(uint32_t(vy), sw) + uint32_t(vx) : 0u;
     }
   }
   uint32_t ls[B][N];
@@ -282,7 +286,7 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
   for (int32_t b = 0; b < B; ++b) {
     x[b] = bx0 + 8 * b + (lane & 7);
     in[b] = x[b] < a.w && y < a.h;
-    pidx[b] = in[b] ? uint32_t(y) * uint32_t(a.w) + uint32_t(x[b]) : 0u;
+    pidx[b] = in[b] ? __umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x[b]) : 0u;
     gt[b] = guide_word<FMT>(a.tgt_guide, pidx[b]);
     lt[b] = SEG ? uint32_t(glb(a.tgt_labels)[pidx[b]]) : 0u;
   }
@@ -391,7 +395,7 @@ __device__ inline void assign_pixel(const FrameArgs &a, int32_t x, int32_t y) {
   if (x >= a.w || y >= a.h) return;
   const Levels &lv = a.lv;
   const int32_t L = lv.count;
-  const uint32_t pidx = uint32_t(y) * uint32_t(a.w) + uint32_t(x);
+  const uint32_t pidx = __umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x);
   const uint32_t gt = guide_word<FMT>(a.tgt_guide, pidx);
   const short2_t p4 = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x), uint32_t(4 * y)));
   const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
@@ -408,7 +412,7 @@ __device__ inline void assign_pixel(const FrameArgs &a, int32_t x, int32_t y) {
     const u32x2 w = top[(k - 3 * kx) * pc + kx];
     const int32_t vx = x + off_x(w.y), vy = y + off_y(w.y);
     if (uint32_t(vx) >= sw || uint32_t(vy) >= sh) continue;
-    const uint32_t vidx = uint32_t(vy) * sw + uint32_t(vx);
+    const uint32_t vidx = __umul24(uint32_t(vy), sw) + uint32_t(vx);
     if (SEG && glb(a.src_labels)[vidx] != glb(a.tgt_labels)[pidx]) continue;
     const uint32_t g = guide_word<FMT>(a.src_guide, vidx);
     if (error_below<FMT>(gt, g, a.threshold, a.wt02, a.wt1)) {
@@ -607,20 +611,30 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
   const int32_t Y0 = int32_t(t_index / tiles_x) * TH;
   const int32_t P = a.ex_stride;
   const int32_t zero_rel = int32_t(a.ex_zero) - ((Y0 + kExMargin) * P + (X0 + kExMargin));
-  for (int32_t e = int32_t(tid); e < NC; e += NT) {
+  // every thread's cells requested together (cells outside the target read
+  // offset 0 and discard it), then written
+  constexpr int32_t NPER = (NC + NT - 1) / NT;
+  uint32_t cell[NPER];
+  bool in[NPER];
+#pragma unroll
+  for (int32_t n = 0; n < NPER; ++n) {
+    const int32_t e = int32_t(tid) + n * NT;
     const int32_t cx = e % LW, cy = e / LW;
     const int32_t tx = X0 - R + cx, ty = Y0 - R + cy;
-    int32_t v = zero_rel;
-    if (tx >= 0 && ty >= 0 && tx < a.w && ty < a.h) {
-      const uint32_t o = glb(a.offsets)[uint32_t(ty) * uint32_t(a.w) + uint32_t(tx)];
-      v = off_y(o) * P + off_x(o);
-    }
-    lin[e] = 4 * v;
+    in[n] = tx >= 0 && ty >= 0 && tx < a.w && ty < a.h;
+    cell[n] = glb(a.offsets)[in[n] ? __umul24(uint32_t(ty), uint32_t(a.w)) + uint32_t(tx) : 0u];
+  }
+#pragma unroll
+  for (int32_t n = 0; n < NPER; ++n) {
+    const int32_t e = int32_t(tid) + n * NT;
+    if (n + 1 < NPER || e < NC)
+      lin[e] = 4 * (in[n] ? __mul24(off_y(cell[n]), P) + off_x(cell[n]) : zero_rel);
   }
   __syncthreads();
   const int32_t gx = int32_t(tid & 15), ly = int32_t(tid >> 4);
   const int32_t x = X0 + PPT * gx, y = Y0 + ly;
-  const uint32_t pbase = 4u * uint32_t((y + kExMargin) * P + (x + kExMargin));
+  const uint32_t pbase =
+      4u * (__umul24(uint32_t(y + kExMargin), uint32_t(P)) + uint32_t(x + kExMargin));
   const SB_GLOBAL unsigned char *ex = glb(reinterpret_cast<const unsigned char *>(a.src_rgba));
   uint32_t S[PPT] = {}, RB[PPT] = {};
   // the lane's cells of a window row: 2R + PPT, read as aligned PPT-vectors
@@ -662,7 +676,7 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
     c[j] = div_small((RB[j] & 0xFFFFu) + hk, rk) | (div_small(((gk >> 8) & 0xFFFFu) + hk, rk) << 8) |
            (div_small((RB[j] >> 16) + hk, rk) << 16);
   }
-  const size_t at = 3 * (size_t(y) * size_t(a.w) + size_t(x));
+  const size_t at = 3 * size_t(__umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x));
   SB_GLOBAL uint8_t *o = glb(a.out_rgb) + at;
   const uintptr_t oa = reinterpret_cast<uintptr_t>(a.out_rgb) + at;
   if (PPT == 4 && x + 4 <= a.w && (oa & 3) == 0) {
