@@ -478,15 +478,21 @@ __global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
 // of 1/k (v_rcp_f32): (n + 1/2) * rk lies within 0.5/k of (n + 1/2)/k, whose
 // fractional part keeps at least 0.5/k from the next integer, so truncation
 // gives floor(n / k).  (Checked exhaustively over every such n and k and the
-// three floats nearest 1/k.)
-__device__ inline uint32_t div_small(uint32_t n, float rk) {
-  return uint32_t((float(n) + 0.5f) * rk);
+// three floats nearest 1/k.)  Written as fma(n, rk, hk) with hk = rk / 2:
+// the same exact product rounded once.
+__device__ inline uint32_t div_small(uint32_t n, float rk, float hk) {
+  return uint32_t(__builtin_fmaf(float(n), rk, hk));
 }
 
 // LDS row length and rows of a voting tile of TW x TH pixels and radius R
 // (rows padded to a multiple of 4 cells so each lane's cells start aligned).
 __host__ __device__ constexpr int32_t blend_lw(int32_t tw, int32_t r) { return (tw + 2 * r + 3) & ~3; }
 __host__ __device__ constexpr int32_t blend_lh(int32_t th, int32_t r) { return th + 2 * r; }
+// LDS words of a voting tile: the rows and one unused row in front, so the
+// row above any tile row is an address inside the array.
+__host__ __device__ constexpr int32_t blend_words(int32_t tw, int32_t th, int32_t r) {
+  return blend_lw(tw, r) * (blend_lh(th, r) + 1);
+}
 
 // Load n = 1..4 consecutive texels at byte offset `at` of the exemplar.
 template <int N>
@@ -540,13 +546,14 @@ struct TexelsN {
 template <int R, int PPT, int C>
 __device__ __forceinline__ void vote_gather(const SB_GLOBAL unsigned char *ex, uint32_t pbase,
                                             const int32_t *cells, const int32_t *up_cells,
-                                            TexelsN<PPT> *row, const TexelsN<PPT> *up_row) {
+                                            bool has_up, TexelsN<PPT> *row,
+                                            const TexelsN<PPT> *up_row) {
   if constexpr (C < 2 * R + PPT) {
     constexpr int J0 = C - 2 * R > 0 ? C - 2 * R : 0;
     constexpr int J1 = C < PPT - 1 ? C : PPT - 1;
     constexpr int N = J1 - J0 + 1;
     const int32_t lin = cells[C];
-    const bool up = lin == up_cells[C];
+    const bool up = has_up && lin == up_cells[C];
     const bool left = C >= PPT && lin == cells[C > 0 ? C - 1 : 0];
     uint32_t t[PPT];
 #pragma unroll
@@ -554,7 +561,7 @@ __device__ __forceinline__ void vote_gather(const SB_GLOBAL unsigned char *ex, u
     if (!up && !left) load_texels<N>(ex, pbase + 4u * J0 + uint32_t(lin), t);
 #pragma unroll
     for (int m = 0; m < N; ++m) row[C].t[J0 + m] = t[m];
-    vote_gather<R, PPT, C + 1>(ex, pbase, cells, up_cells, row, up_row);
+    vote_gather<R, PPT, C + 1>(ex, pbase, cells, up_cells, has_up, row, up_row);
   }
 }
 
@@ -584,15 +591,15 @@ __device__ __forceinline__ void vote_sum(const int32_t *cells, TexelsN<PPT> *row
 template <int R, int PPT, int C>
 __device__ __forceinline__ void vote_row(const SB_GLOBAL unsigned char *ex, uint32_t pbase,
                                          const int32_t *cells, const int32_t *up_cells,
-                                         TexelsN<PPT> *row, const TexelsN<PPT> *up_row,
-                                         uint32_t *S, uint32_t *RB) {
-  vote_gather<R, PPT, C>(ex, pbase, cells, up_cells, row, up_row);
+                                         bool has_up, TexelsN<PPT> *row,
+                                         const TexelsN<PPT> *up_row, uint32_t *S, uint32_t *RB) {
+  vote_gather<R, PPT, C>(ex, pbase, cells, up_cells, has_up, row, up_row);
   vote_sum<R, PPT, C>(cells, row, S, RB);
 }
 
 // One (16 PPT) x TH pixel voting tile with 16 TH threads: thread t votes for
-// PPT horizontally adjacent pixels.  `lin` is LDS for blend_lw x blend_lh
-// cells; cell n holds 4 * (oy * P + ox) for its offset o = NNF[n] - n and the
+// PPT horizontally adjacent pixels.  `lin` is LDS for blend_words words: an
+// unused row, then blend_lw x blend_lh cells; cell n holds 4 * (oy * P + ox) for its offset o = NNF[n] - n and the
 // padded exemplar's row length P: a vote of n for pixel p is the texel at
 // p's own padded position plus that many bytes.  Cells outside the target
 // hold the distance to the exemplar's zero rows instead, so their votes read
@@ -628,7 +635,7 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
   for (int32_t n = 0; n < NPER; ++n) {
     const int32_t e = int32_t(tid) + n * NT;
     if (n + 1 < NPER || e < NC)
-      lin[e] = 4 * (in[n] ? __mul24(off_y(cell[n]), P) + off_x(cell[n]) : zero_rel);
+      lin[LW + e] = 4 * (in[n] ? __mul24(off_y(cell[n]), P) + off_x(cell[n]) : zero_rel);
   }
   __syncthreads();
   const int32_t gx = int32_t(tid & 15), ly = int32_t(tid >> 4);
@@ -640,27 +647,27 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
   // the lane's cells of a window row: 2R + PPT, read as aligned PPT-vectors
   constexpr int32_t NCL = 2 * R + PPT, NQ = (NCL + PPT - 1) / PPT;
   typedef int32_t lvec __attribute__((ext_vector_type(PPT)));
-  // the previous row's cells and texels; INT32_MIN is no cell value (|lin| < 2^30)
-  int32_t up_cells[PPT * NQ];
+  // the previous row's texels (unused in the first row, which has no row
+  // above: every lane there gathers or takes its left neighbour's texels);
+  // the previous row's cells are read again from LDS rather than carried
   TexelsN<PPT> up_row[NCL];
 #pragma unroll
-  for (int32_t c = 0; c < PPT * NQ; ++c) up_cells[c] = INT32_MIN;
-#pragma unroll
   for (int32_t c = 0; c < NCL; ++c) up_row[c] = TexelsN<PPT>{};
+  // (the tile starts one row into `lin`, so row dy - 1 is in the array for dy = 0 too)
+  const int32_t *lane_above = lin + ly * LW + PPT * gx;
 #pragma unroll 1
   for (int32_t dy = 0; dy < 2 * R + 1; ++dy) {
-    const lvec *q = reinterpret_cast<const lvec *>(lin + (ly + dy) * LW + PPT * gx);
-    int32_t cells[PPT * NQ];
+    const lvec *qu = reinterpret_cast<const lvec *>(lane_above + dy * LW);
+    const lvec *q = reinterpret_cast<const lvec *>(lane_above + (dy + 1) * LW);
+    int32_t cells[PPT * NQ], up_cells[PPT * NQ];
 #pragma unroll
     for (int32_t i = 0; i < NQ; ++i) {
-      const lvec v = q[i];
+      const lvec v = q[i], u = qu[i];
 #pragma unroll
-      for (int32_t j = 0; j < PPT; ++j) cells[PPT * i + j] = v[j];
+      for (int32_t j = 0; j < PPT; ++j) cells[PPT * i + j] = v[j], up_cells[PPT * i + j] = u[j];
     }
     TexelsN<PPT> row[NCL];
-    vote_row<R, PPT, 0>(ex, pbase, cells, up_cells, row, up_row, S, RB);
-#pragma unroll
-    for (int32_t c = 0; c < PPT * NQ; ++c) up_cells[c] = cells[c];
+    vote_row<R, PPT, 0>(ex, pbase, cells, up_cells, dy > 0, row, up_row, S, RB);
 #pragma unroll
     for (int32_t c = 0; c < NCL; ++c) up_row[c] = row[c];
   }
@@ -672,13 +679,14 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
     // (mod 2^32); every channel sum is < 2^16 and k <= 225
     const uint32_t gk = S[j] - RB[j];
     const uint32_t k = gk >> 24, hk = k >> 1;
-    const float rk = __builtin_amdgcn_rcpf(float(k));
-    c[j] = div_small((RB[j] & 0xFFFFu) + hk, rk) | (div_small(((gk >> 8) & 0xFFFFu) + hk, rk) << 8) |
-           (div_small((RB[j] >> 16) + hk, rk) << 16);
+    const float rk = __builtin_amdgcn_rcpf(float(k)), rh = 0.5f * rk;
+    c[j] = div_small((RB[j] & 0xFFFFu) + hk, rk, rh) |
+           (div_small(((gk >> 8) & 0xFFFFu) + hk, rk, rh) << 8) |
+           (div_small((RB[j] >> 16) + hk, rk, rh) << 16);
   }
-  const size_t at = 3 * size_t(__umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x));
+  const uint32_t at = 3u * (__umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x));  // < 2^28
   SB_GLOBAL uint8_t *o = glb(a.out_rgb) + at;
-  const uintptr_t oa = reinterpret_cast<uintptr_t>(a.out_rgb) + at;
+  const uint32_t oa = uint32_t(reinterpret_cast<uintptr_t>(a.out_rgb)) + at;  // alignment only
   if (PPT == 4 && x + 4 <= a.w && (oa & 3) == 0) {
     u32x3a4 v;
     v.x = c[0] | (c[1 % PPT] << 24);
@@ -714,7 +722,7 @@ __device__ inline void blend_tile_r(const FrameArgs &a, uint32_t t_index, uint32
 
 template <int R, int PPT, int TH>
 __global__ void __launch_bounds__(16 * TH) k_blend(FrameArgs a) {
-  __shared__ __attribute__((aligned(16))) int32_t lin[blend_lw(16 * PPT, R) * blend_lh(TH, R)];
+  __shared__ __attribute__((aligned(16))) int32_t lin[blend_words(16 * PPT, TH, R)];
   blend_tile<R, PPT, TH>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lin);
 }
 
@@ -815,7 +823,7 @@ __global__ void __launch_bounds__(256) k_batch_assign(const unsigned char *desc)
 
 template <int PPT, int TH, int RLO, int RHI>
 __global__ void __launch_bounds__(16 * TH) k_batch_blend(const unsigned char *desc) {
-  constexpr int WORDS = blend_lw(16 * PPT, RHI) * blend_lh(TH, RHI);
+  constexpr int WORDS = blend_words(16 * PPT, TH, RHI);
   batch_loop<RLO == 0 ? 2 : 3, 16 * TH, WORDS>(desc, [](const FrameArgs &fa, uint32_t local,
                                                         uint32_t *w) {
     blend_tile_r<PPT, TH, RLO, RHI>(fa, local, threadIdx.x, reinterpret_cast<int32_t *>(w));
