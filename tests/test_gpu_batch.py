@@ -202,3 +202,32 @@ def test_batch_mixed_radii(sb):
                                           err_msg=f"r={j.params.radius}")
             np.testing.assert_array_equal(j.out_chunk.cpu().numpy(), chunk.cpu().numpy())
         b.close()
+
+
+def test_batch_deep_hierarchy_matches_oracle(sb):
+    """A batch frame with 9 levels (9 L > 64 seed records per block, so the
+    second record per lane) next to a shallow one, against the oracle."""
+    import torch
+
+    rng = np.random.default_rng(909)
+    st_np = workloads.Style(workloads.value_noise_rgb(96, 80, 5), workloads.sphere_guide_u8(96)[:80],
+                            0, 8)
+    style = sb.Style(st_np.rgb, st_np.guide, st_np.lut_bits)
+    lut = oracle.lut_build(st_np.guide, st_np.lut_bits)
+    cases = [(301, 177, 9, 8, 90, 2), (150, 90, 3, 8, 40, 1)]
+    jobs, want = [], []
+    for w, h, levels, finest, t, r in cases:
+        g = rng.integers(0, 256, size=(h, w, 2), dtype=np.uint8)
+        jit = workloads.jitter_table(w, h, levels, finest, w + h)
+        jobs.append(sb.FrameJob(style, g, jit, sb.params(levels, finest, t, r)))
+        want.append(oracle.stylize(st_np.rgb, st_np.guide, lut, st_np.lut_bits, g, jit, levels,
+                                   finest, t, r))
+    b = sb.Batch(use_graph=True)
+    say("batch with a 9-level frame")
+    b.run(jobs)
+    torch.cuda.synchronize()
+    for k, (j, (e_rgb, e_chunk, _)) in enumerate(zip(jobs, want)):
+        np.testing.assert_array_equal(j.out_chunk.cpu().numpy().view(np.uint32), e_chunk,
+                                      err_msg=f"frame {k} chunk")
+        np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), e_rgb, err_msg=f"frame {k} rgb")
+    b.close()

@@ -171,6 +171,34 @@ def test_random_small(sb, seed):
                 tunes=all_tunes(sb))
 
 
+def _gradient_case(rng, w, h, sw, sh, u16):
+    scale = 65535 if u16 else 255
+    dt = np.uint16 if u16 else np.uint8
+    yy, xx = np.mgrid[0:h, 0:w]
+    noise = rng.integers(-scale // 40, scale // 40 + 1, size=(h, w, 2))
+    gt = np.clip(np.stack([xx * scale // w, yy * scale // h], 2) + noise, 0, scale).astype(dt)
+    syy, sxx = np.mgrid[0:sh, 0:sw]
+    gs = np.stack([sxx * scale // sw, syy * scale // sh], 2).astype(dt)
+    st = workloads.Style(rng.integers(0, 256, size=(sh, sw, 3), dtype=np.uint8), gs,
+                         1 if u16 else 0, 9 if u16 else 8)
+    return st, gt
+
+
+@pytest.mark.parametrize("u16,levels,finest,t", [(False, 8, 8, 60), (False, 11, 8, 30),
+                                                 (True, 9, 8, 1 << 22), (False, 12, 2, 60),
+                                                 (True, 10, 8, 0), (False, 7, 16, 60)])
+def test_deep_hierarchies(sb, u16, levels, finest, t):
+    """Eight or more levels: an 8 x 8 block stages 9 L > 64 seed records, so
+    lanes take a second record each (made in the level loop for 8-bit guides,
+    read from the seed table for 16-bit ones); spacings up to 8192 exceed the
+    frame.  L = 12 at finest 2 takes the per-pixel path."""
+    rng = np.random.default_rng(levels * 100 + finest + int(u16))
+    st, gt = _gradient_case(rng, 333, 217, 97, 83, u16)
+    jit = workloads.jitter_table(333, 217, levels, finest, levels + 7)
+    check_frame(sb, st, gt, jit, levels, finest, t, 2, name=f"deep u16={u16}",
+                tunes=all_tunes(sb))
+
+
 def test_degenerate_shapes(sb):
     rng = np.random.default_rng(77)
     st = workloads.Style(workloads.value_noise_rgb(64, 64, 1), workloads.sphere_guide_u8(64), 0, 8)
