@@ -645,8 +645,12 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
   const SB_GLOBAL unsigned char *ex = glb(reinterpret_cast<const unsigned char *>(a.src_rgba));
   uint32_t S[PPT] = {}, RB[PPT] = {};
   // the lane's cells of a window row: 2R + PPT, read as aligned PPT-vectors
-  constexpr int32_t NCL = 2 * R + PPT, NQ = (NCL + PPT - 1) / PPT;
+  // and, for the last 2R mod PPT cells (0 or 2), one aligned pair (reading
+  // only the cells used keeps the kernel within 64 VGPRs, 8 waves per SIMD)
+  constexpr int32_t NCL = 2 * R + PPT, NQ = NCL / PPT, NTAIL = NCL % PPT;
+  static_assert(NTAIL == 0 || NTAIL == 2, "cells per row are a multiple of 2");
   typedef int32_t lvec __attribute__((ext_vector_type(PPT)));
+  typedef int32_t lvec2 __attribute__((ext_vector_type(2)));
   // the previous row's texels (unused in the first row, which has no row
   // above: every lane there gathers or takes its left neighbour's texels);
   // the previous row's cells are read again from LDS rather than carried
@@ -659,12 +663,18 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
   for (int32_t dy = 0; dy < 2 * R + 1; ++dy) {
     const lvec *qu = reinterpret_cast<const lvec *>(lane_above + dy * LW);
     const lvec *q = reinterpret_cast<const lvec *>(lane_above + (dy + 1) * LW);
-    int32_t cells[PPT * NQ], up_cells[PPT * NQ];
+    int32_t cells[NCL], up_cells[NCL];
 #pragma unroll
     for (int32_t i = 0; i < NQ; ++i) {
       const lvec v = q[i], u = qu[i];
 #pragma unroll
       for (int32_t j = 0; j < PPT; ++j) cells[PPT * i + j] = v[j], up_cells[PPT * i + j] = u[j];
+    }
+    if constexpr (NTAIL == 2) {
+      const lvec2 v = *reinterpret_cast<const lvec2 *>(q + NQ);
+      const lvec2 u = *reinterpret_cast<const lvec2 *>(qu + NQ);
+      cells[NCL - 2] = v.x, cells[NCL - 1] = v.y;
+      up_cells[NCL - 2] = u.x, up_cells[NCL - 1] = u.y;
     }
     TexelsN<PPT> row[NCL];
     vote_row<R, PPT, 0>(ex, pbase, cells, up_cells, dy > 0, row, up_row, S, RB);
