@@ -611,31 +611,52 @@ template <int R, int PPT, int TH>
 __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t tid,
                                   int32_t *lin) {
   constexpr int32_t TW = 16 * PPT, NT = 16 * TH;
-  constexpr int32_t LW = blend_lw(TW, R), LH = blend_lh(TH, R), NC = LW * LH;
+  constexpr int32_t LW = blend_lw(TW, R), LH = blend_lh(TH, R);
   static_assert(TW <= kBlendMaxTW && TH <= kBlendMaxTH, "tile exceeds the exemplar zero rows");
   const uint32_t tiles_x = (uint32_t(a.w) + TW - 1) / TW;
   const int32_t X0 = int32_t(t_index % tiles_x) * TW;
   const int32_t Y0 = int32_t(t_index / tiles_x) * TH;
   const int32_t P = a.ex_stride;
   const int32_t zero_rel = int32_t(a.ex_zero) - ((Y0 + kExMargin) * P + (X0 + kExMargin));
-  // every thread's cells requested together (cells outside the target read
-  // offset 0 and discard it), then written
-  constexpr int32_t NPER = (NC + NT - 1) / NT;
-  uint32_t cell[NPER];
-  bool in[NPER];
+  // the tile's cells in runs of 4 along a row (LW is a multiple of 4), one
+  // dword-aligned 16-byte load per run and every thread's runs requested
+  // together; a run reaching past the target (border tiles only) reads its
+  // cells one by one, and cells outside the target take zero_rel
+  constexpr int32_t QW = LW / 4, NCH = QW * LH, CPER = (NCH + NT - 1) / NT;
+  static_assert(LW % 4 == 0, "tile rows are whole runs of 4 cells");
+  u32x4a4 run[CPER];
+  uint32_t inside[CPER];  // bit m: cell m of the run lies in the target
 #pragma unroll
-  for (int32_t n = 0; n < NPER; ++n) {
-    const int32_t e = int32_t(tid) + n * NT;
-    const int32_t cx = e % LW, cy = e / LW;
-    const int32_t tx = X0 - R + cx, ty = Y0 - R + cy;
-    in[n] = tx >= 0 && ty >= 0 && tx < a.w && ty < a.h;
-    cell[n] = glb(a.offsets)[in[n] ? __umul24(uint32_t(ty), uint32_t(a.w)) + uint32_t(tx) : 0u];
+  for (int32_t n = 0; n < CPER; ++n) {
+    const int32_t ch = int32_t(tid) + n * NT;
+    const int32_t tx = X0 - R + 4 * (ch % QW), ty = Y0 - R + ch / QW;
+    const bool row_in = ch < NCH && ty >= 0 && ty < a.h;
+    const SB_GLOBAL uint32_t *src =
+        glb(a.offsets) + (row_in ? __umul24(uint32_t(ty), uint32_t(a.w)) : 0u);
+    if (row_in && tx >= 0 && tx + 4 <= a.w) {
+      run[n] = *reinterpret_cast<const SB_GLOBAL u32x4a4 *>(src + tx);
+      inside[n] = 15u;
+    } else {
+      inside[n] = 0u;
+#pragma unroll
+      for (int32_t m = 0; m < 4; ++m) {
+        const bool in = row_in && tx + m >= 0 && tx + m < a.w;
+        run[n][m] = src[in ? uint32_t(tx + m) : 0u];
+        inside[n] |= uint32_t(in) << m;
+      }
+    }
   }
 #pragma unroll
-  for (int32_t n = 0; n < NPER; ++n) {
-    const int32_t e = int32_t(tid) + n * NT;
-    if (n + 1 < NPER || e < NC)
-      lin[LW + e] = 4 * (in[n] ? __mul24(off_y(cell[n]), P) + off_x(cell[n]) : zero_rel);
+  for (int32_t n = 0; n < CPER; ++n) {
+    const int32_t ch = int32_t(tid) + n * NT;
+    if (n + 1 < CPER || ch < NCH) {
+      i32x4 v;
+#pragma unroll
+      for (int32_t m = 0; m < 4; ++m)
+        v[m] = 4 * ((inside[n] >> m) & 1u ? __mul24(off_y(run[n][m]), P) + off_x(run[n][m])
+                                           : zero_rel);
+      *reinterpret_cast<i32x4 *>(lin + LW + 4 * ch) = v;
+    }
   }
   __syncthreads();
   const int32_t gx = int32_t(tid & 15), ly = int32_t(tid >> 4);
