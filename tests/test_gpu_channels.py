@@ -87,7 +87,8 @@ def test_full_size_table_sampled(sb):
 
 
 @pytest.mark.parametrize("w,h,levels,finest,t,r", [(200, 136, 4, 8, 64, 3), (97, 61, 3, 4, 300, 2),
-                                                  (64, 64, 0, 8, 0, 1), (131, 70, 4, 2, 25, 0)])
+                                                  (64, 64, 0, 8, 0, 1), (131, 70, 4, 2, 25, 0),
+                                                  (221, 143, 9, 8, 200, 2)])
 def test_frames_match_oracle_all_tunes(sb, w, h, levels, finest, t, r):
     import torch
 

@@ -109,6 +109,28 @@ def test_random_small(sb, seed):
           tunes=[None, (2, 8, 4, 1)])
 
 
+@pytest.mark.parametrize("u16,levels", [(False, 9), (True, 10)])
+def test_deep_hierarchy(sb, u16, levels):
+    """Nine or ten levels with labels: the block level loop stages two seed
+    records per lane from the seed table."""
+    rng = np.random.default_rng(500 + levels)
+    w, h, sw, sh = 251, 163, 47, 41
+    scale = 65535 if u16 else 255
+    dt = np.uint16 if u16 else np.uint8
+    yy, xx = np.mgrid[0:h, 0:w]
+    noise = rng.integers(-scale // 40, scale // 40 + 1, size=(h, w, 2))
+    gt = np.clip(np.stack([xx * scale // w, yy * scale // h], 2) + noise, 0, scale).astype(dt)
+    syy, sxx = np.mgrid[0:sh, 0:sw]
+    gs = np.stack([sxx * scale // sw, syy * scale // sh], 2).astype(dt)
+    st = workloads.Style(rng.integers(0, 256, size=(sh, sw, 3), dtype=np.uint8), gs,
+                         1 if u16 else 0, 7 if u16 else 8)
+    ls = (sxx * 3 // sw).astype(np.uint8)
+    lt = (xx * 3 // w).astype(np.uint8)
+    jit = workloads.jitter_table(w, h, levels, 8, levels)
+    check(sb, st, ls, 3, gt, lt, jit, levels, 8, (1 << 22) if u16 else 80, 2,
+          f"seg deep L={levels} u16={u16}", tunes=[None, (2, 8, 4, 1), (4, 16, 2, 2)])
+
+
 def test_one_label_equals_plain(sb):
     import torch
 
