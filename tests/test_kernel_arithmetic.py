@@ -9,7 +9,12 @@ ranges where they are used (host arithmetic only, no GPU):
   in place of the per-level table;
 - pixel and texel indices fit the 24-bit multiplier: every factor is below
   2^24 and every product y * w + x below 2^32 for sides up to 8192 (plus the
-  exemplar margin)."""
+  exemplar margin);
+- the block level loop reads the record at slot (key & 15) of a level even
+  when no neighbour holds a seed (key = INT32_MAX, slot 15): with records
+  staged kRecStride apart that read stays inside the block's records for
+  every hierarchy the block path runs (finest spacing >= 8, so at most
+  log2(8192) - 2 levels)."""
 import os
 import re
 
@@ -52,3 +57,19 @@ def test_index_products_fit_24_bit_multiplies():
     assert 3 * (SB_MAX_SIDE * SB_MAX_SIDE) < (1 << 32)
     # signed offsets times the row length fit the signed 24-bit multiply
     assert SB_MAX_SIDE * padded < (1 << 31)
+
+
+def _stylize_constant(name):
+    return _define("paper_1807_03249_amd/csrc/stylize.hip", r"constexpr int32_t " + name +
+                   r" = (\d+);")
+
+
+def test_empty_neighbourhood_slot_stays_in_block_records():
+    stride = _stylize_constant("kRecStride")
+    wave_recs = SB_MAX_LEVELS * stride
+    assert stride >= 9
+    # the block path needs log2(finest) >= 3 and log2(finest) + L - 1 <= log2(SB_MAX_SIDE)
+    max_levels = SB_MAX_SIDE.bit_length() - 1 - 3 + 1
+    assert max_levels <= SB_MAX_LEVELS
+    last_slot = stride * (max_levels - 1) + (0x7FFFFFFF & 15)
+    assert last_slot < wave_recs
