@@ -92,6 +92,9 @@ def _load():
     _u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.ora_philox4x64.argtypes = [_u64p, _u64p, _u64p]
     lib.ora_jitter_fill.argtypes = [i32, i32, i32, i32, ctypes.c_uint64, ctypes.c_uint64, _u32p]
+    lib.ora_jitter_hash.argtypes = [i32, i32, i32, i32, ctypes.c_uint32, _u32p]
+    lib.ora_jitter_hash_key.argtypes = [ctypes.c_uint32] * 4
+    lib.ora_jitter_hash_key.restype = ctypes.c_uint32
     lib.ora_lut_build_w.argtypes = [vp, i32, i32, i32, i32, _u8p, _u32p]
     lib.ora_lut_query_w.argtypes = [vp, i32, i32, i32, i32, _u8p, _i64p, ctypes.c_int64, _u32p]
     lib.ora_lut_build_labels_w.argtypes = [vp, _u8p, i32, i32, i32, i32, i32, _u8p, _u32p]
@@ -144,8 +147,14 @@ def _weights(weights):
     return w, _ptr(w, _u8p)
 
 
-def _jit(jitter: Optional[np.ndarray], w: int, h: int, levels: int, finest: int) -> np.ndarray:
+def _jit(jitter: Optional[np.ndarray], w: int, h: int, levels: int, finest: int,
+         seed: Optional[int] = None) -> np.ndarray:
+    """The jitter table a frame uses: ``jitter`` as given; else, with a
+    ``seed``, the table the integer hash defines; else all zero (seeds on the
+    cell corners)."""
     n = jitter_len(w, h, levels, finest)
+    if jitter is None and seed is not None:
+        return jitter_hash(w, h, levels, finest, seed) if n else np.zeros(1, np.uint32)
     if jitter is None:
         return np.zeros(max(n, 1), np.uint32)
     j = np.ascontiguousarray(jitter, dtype=np.uint32)
@@ -187,6 +196,23 @@ def jitter_fill(w: int, h: int, levels: int, finest: int, seed: int, stream: int
     return out[:n]
 
 
+def jitter_hash(w: int, h: int, levels: int, finest: int, seed: int) -> np.ndarray:
+    """The jitter table defined by the integer hash of (cell, log2 h, seed)
+    (the reading of RandomJitterTable used when a frame names a seed instead
+    of passing a table)."""
+    n = jitter_len(w, h, levels, finest)
+    out = np.zeros(max(n, 1), np.uint32)
+    _check(_load().ora_jitter_hash(w, h, levels, finest, int(seed) & 0xFFFFFFFF,
+                                   _ptr(out, _u32p)), "jitter_hash")
+    return out[:n]
+
+
+def jitter_hash_key(seed: int, log2h: int, bx: int, by: int) -> int:
+    """The 32-bit hash k of one cell (jx = k & (h-1), jy = (k >> 16) & (h-1))."""
+    return int(_load().ora_jitter_hash_key(int(seed) & 0xFFFFFFFF, log2h, bx & 0xFFFFFFFF,
+                                           by & 0xFFFFFFFF))
+
+
 def jitter_len(w: int, h: int, levels: int, finest: int) -> int:
     return int(_load().ora_jitter_len(w, h, levels, finest))
 
@@ -215,18 +241,19 @@ def lut_query(src_guide: np.ndarray, lut_bits: int, bins, weights=None) -> np.nd
     return out
 
 
-def seed_point(w, h, levels, finest, jitter, level, bx, by):
-    """(valid, sx, sy) of cell (bx, by) at level `level`."""
-    j = _jit(jitter, w, h, levels, finest)
+def seed_point(w, h, levels, finest, jitter, level, bx, by, seed=None):
+    """(valid, sx, sy) of cell (bx, by) at level `level` (``jitter`` None with a
+    ``seed``: the hash-defined table)."""
+    j = _jit(jitter, w, h, levels, finest, seed)
     sx, sy = ctypes.c_int64(), ctypes.c_int64()
     ok = _load().ora_seed_point(w, h, levels, finest, _ptr(j, _u32p), level, bx, by,
                                 ctypes.byref(sx), ctypes.byref(sy))
     return bool(ok), sx.value, sy.value
 
 
-def nearest_seed(w, h, levels, finest, jitter, level, px, py):
+def nearest_seed(w, h, levels, finest, jitter, level, px, py, seed=None):
     """(found, qx, qy) for pixel (px, py) at level `level`."""
-    j = _jit(jitter, w, h, levels, finest)
+    j = _jit(jitter, w, h, levels, finest, seed)
     qx, qy = ctypes.c_int64(-1), ctypes.c_int64(-1)
     ok = _load().ora_nearest_seed(w, h, levels, finest, _ptr(j, _u32p), level, px, py,
                                   ctypes.byref(qx), ctypes.byref(qy))
@@ -234,7 +261,7 @@ def nearest_seed(w, h, levels, finest, jitter, level, px, py):
 
 
 def assign(src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest, threshold,
-           rows: Optional[Tuple[int, int]] = None, weights=None):
+           rows: Optional[Tuple[int, int]] = None, weights=None, seed=None):
     """Per-pixel level loop only: returns (nnf, chunk), both uint32 (H, W).
     With ``rows=(row0, n)`` only those rows are computed (others stay 0)."""
     gs, fmt = _guide(src_guide)
@@ -242,7 +269,7 @@ def assign(src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest, threshol
     if fmt != fmt_t:
         raise ValueError("source and target guide formats differ")
     h, w = gt.shape[:2]
-    j = _jit(jitter, w, h, levels, finest)
+    j = _jit(jitter, w, h, levels, finest, seed)
     lut = np.ascontiguousarray(lut, dtype=np.uint32)
     if lut.size != _bins(fmt, lut_bits):
         raise ValueError("lookup table size does not match the guide format and lut_bits")
@@ -271,9 +298,10 @@ def blend(src_rgb: np.ndarray, nnf: np.ndarray, radius: int,
 
 
 def stylize(src_rgb, src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest, threshold,
-            radius, weights=None):
+            radius, weights=None, seed=None):
     """The whole per-frame path: returns (rgb (H,W,3) uint8, chunk (H,W) uint32,
-    nnf (H,W) uint32).  ``weights``: channel weights of a three-channel guide
+    nnf (H,W) uint32).  ``jitter``: the jitter table, or None for the table the
+    integer hash of ``seed`` defines (None too: seeds on the cell corners).  ``weights``: channel weights of a three-channel guide
     (the table must be built with the same weights)."""
     gs, fmt = _guide(src_guide)
     gt, fmt_t = _guide(tgt_guide)
@@ -281,7 +309,7 @@ def stylize(src_rgb, src_guide, lut, lut_bits, tgt_guide, jitter, levels, finest
         raise ValueError("source and target guide formats differ")
     rgb = np.ascontiguousarray(src_rgb, dtype=np.uint8)
     h, w = gt.shape[:2]
-    j = _jit(jitter, w, h, levels, finest)
+    j = _jit(jitter, w, h, levels, finest, seed)
     lut = np.ascontiguousarray(lut, dtype=np.uint32)
     if lut.size != _bins(fmt, lut_bits):
         raise ValueError("lookup table size does not match the guide format and lut_bits")
@@ -320,7 +348,7 @@ def lut_build_labels(src_guide: np.ndarray, src_labels: np.ndarray, nlabels: int
 
 
 def stylize_seg(src_rgb, src_guide, src_labels, luts, nlabels, lut_bits, tgt_guide, tgt_labels,
-                jitter, levels, finest, threshold, radius, weights=None):
+                jitter, levels, finest, threshold, radius, weights=None, seed=None):
     """The per-frame path with the segmentation guide as a hard constraint:
     returns (rgb, chunk, nnf) as ``stylize``."""
     gs, fmt = _guide(src_guide)
@@ -331,7 +359,7 @@ def stylize_seg(src_rgb, src_guide, src_labels, luts, nlabels, lut_bits, tgt_gui
     lt = _labels(tgt_labels, gt.shape[:2])
     rgb = np.ascontiguousarray(src_rgb, dtype=np.uint8)
     h, w = gt.shape[:2]
-    j = _jit(jitter, w, h, levels, finest)
+    j = _jit(jitter, w, h, levels, finest, seed)
     luts = np.ascontiguousarray(luts, dtype=np.uint32)
     if luts.size != nlabels * _bins(fmt, lut_bits):
         raise ValueError("luts must hold nlabels tables")

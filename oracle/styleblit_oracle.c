@@ -18,7 +18,9 @@
  *   - level spacings h_i = finest << (L-1-i), level 0 coarsest (the paper's
  *     2^l, l = L..1, is finest = 2);
  *   - RandomJitterTable: one integer jitter (jx, jy) in [0,h)^2 per cell and
- *     level, passed in (or drawn by ora_jitter_fill from Philox4x64-10);
+ *     level, passed in as a table: defined by an integer hash of (cell,
+ *     log2 h, seed) (ora_jitter_hash), drawn from Philox4x64-10
+ *     (ora_jitter_fill), or all zero (seeds on the cell corners);
  *     SeedPoint(b) = h*b + j, the integer form of floor(h*(b + j/h));
  *   - seeds outside the target are not candidates; a level whose 3x3
  *     neighbourhood holds no in-image seed is skipped;
@@ -441,6 +443,61 @@ int ora_jitter_fill(int w, int h, int levels, int finest, uint64_t seed, uint64_
             uint64_t r[4];
             ora_philox4x64(key, ctr, r);
             out[e] = (uint32_t)(r[0] & hm) | ((uint32_t)((r[0] >> 32) & hm) << 16);
+        }
+    }
+    return ORA_OK;
+}
+
+/* ------------------------------------ jitter from an integer hash
+ *
+ * The paper leaves RandomJitterTable's contents open (Algorithm 2,
+ * SeedPoint).  This reading defines them by a hash of (cell, level, seed), so
+ * a frame's seeds follow from one 32-bit seed value with no table:
+ *   mix(x):  x ^= x >> 16; x *= 0x9E3779B9; x ^= x >> 15; x *= 0x6A09E667;
+ *            x ^= x >> 16   (uint32 arithmetic, wrapping)
+ *   k = mix(mix(mix(mix(seed + 0xBB67AE85) ^ log2 h) ^ bx) ^ by)
+ *   jx = k & (h - 1),  jy = (k >> 16) & (h - 1)
+ * The multipliers are floor(2^32 / golden ratio) and the first 32 fraction
+ * bits of sqrt(2); the additive constant is the first 32 fraction bits of
+ * sqrt(3).  The level enters through log2 h, so one cell index at two levels
+ * gets unrelated jitter.
+ */
+static uint32_t hash_mix(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x9E3779B9u;
+    x ^= x >> 15;
+    x *= 0x6A09E667u;
+    x ^= x >> 16;
+    return x;
+}
+
+uint32_t ora_jitter_hash_key(uint32_t seed, uint32_t log2h, uint32_t bx, uint32_t by)
+{
+    uint32_t k = hash_mix(seed + 0xBB67AE85u);
+    k = hash_mix(k ^ log2h);
+    k = hash_mix(k ^ bx);
+    return hash_mix(k ^ by);
+}
+
+/* The jitter table that the hash defines for a W x H target: entry (level i,
+ * cell b) = jx | jy << 16 with the level's spacing h_i, in the table layout
+ * of ora_jitter_fill (levels coarsest first, cells row-major). */
+int ora_jitter_hash(int w, int h, int levels, int finest, uint32_t seed, uint32_t *out)
+{
+    if (w < 1 || h < 1 || levels < 0 || levels > 12 || finest < 1 || (finest & (finest - 1)))
+        return ORA_EINVAL;
+    if (!out && levels > 0) return ORA_EINVAL;
+    seeds_t S = {w, h, levels, finest, NULL};
+    for (int i = 0; i < levels; ++i) {
+        const int64_t sp = level_spacing(&S, i);
+        uint32_t lg = 0;
+        while (((int64_t)1 << lg) < sp) ++lg;
+        const int64_t ncx = cells_x(&S, i), base = level_offset(&S, i);
+        for (int64_t e = base; e < level_offset(&S, i + 1); ++e) {
+            const int64_t bx = (e - base) % ncx, by = (e - base) / ncx;
+            const uint32_t k = ora_jitter_hash_key(seed, lg, (uint32_t)bx, (uint32_t)by);
+            out[e] = (k & (uint32_t)(sp - 1)) | (((k >> 16) & (uint32_t)(sp - 1)) << 16);
         }
     }
     return ORA_OK;
