@@ -158,7 +158,7 @@ def main():
     styles, frames = workloads.config(args.workload)
     st_np, fr = styles[0], frames[0]
     p = fr.params
-    prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
     w, h = fr.w, fr.h
     wname = workloads.CONFIG_NAMES[args.workload]
 
@@ -174,7 +174,7 @@ def main():
     # rotating buffer sets
     g_np = fr.guide.view(np.int16) if fr.guide.dtype == np.uint16 else fr.guide
     guide0 = torch.from_numpy(g_np).cuda()
-    jit = torch.from_numpy(fr.jitter.view(np.int32)).cuda()
+    jit = None  # the seeds come from the jitter hash of prm.seed
     wsb = sb.workspace_bytes(w, h, prm)
     per_set = guide0.numel() * guide0.element_size() + w * h * 3 + w * h * 4 + wsb
     nsets = max(2, int(args.rotate_mb * 1e6 // per_set) + 1)
@@ -252,7 +252,7 @@ def main():
         c0 = time.perf_counter()
         while True:
             oracle.stylize(st_np.rgb, st_np.guide, lut, st_np.lut_bits, fr.guide, fr.jitter,
-                           p.levels, p.finest, p.threshold, p.radius)
+                           p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
             n += 1
             if time.perf_counter() - c0 >= args.cpu_seconds or n >= 200:
                 break
@@ -267,7 +267,7 @@ def main():
         c0 = time.perf_counter()
         while True:
             oracle.stylize(st_np.rgb, st_np.guide, lut, st_np.lut_bits, fr.guide, fr.jitter,
-                           p.levels, p.finest, p.threshold, p.radius)
+                           p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
             n1 += 1
             if time.perf_counter() - c0 >= args.cpu_seconds / 4 or n1 >= 20:
                 break
@@ -349,7 +349,7 @@ def seg_leg(sb, torch, np, workloads, st_np, fr, prm, plain_ms, nlabels=6, steps
     style = sb.Style(st_np.rgb, st_np.guide, st_np.lut_bits, labels=ls, nlabels=nlabels)
     g_np = fr.guide.view(np.int16) if fr.guide.dtype == np.uint16 else fr.guide
     g = torch.from_numpy(g_np).cuda()
-    jit = torch.from_numpy(fr.jitter.view(np.int32)).cuda()
+    jit = None  # the seeds come from the jitter hash of prm.seed
     ltd = torch.from_numpy(lt).cuda()
     rgb = torch.empty((fr.h, fr.w, 3), dtype=torch.uint8, device="cuda")
     chunk = torch.empty((fr.h, fr.w), dtype=torch.int32, device="cuda")
@@ -382,7 +382,7 @@ def channels_leg(sb, torch, np, workloads, plain_ms, steps=100):
     styles, frames = workloads.config(6)
     st_np, fr = styles[0], frames[0]
     p = fr.params
-    prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
     style = sb.Style(st_np.rgb, st_np.guide, st_np.lut_bits)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -390,7 +390,7 @@ def channels_leg(sb, torch, np, workloads, plain_ms, steps=100):
     torch.cuda.synchronize()
     reg_ms = (time.perf_counter() - t0) * 1e3
     g = torch.from_numpy(fr.guide).cuda()
-    jit = torch.from_numpy(fr.jitter.view(np.int32)).cuda()
+    jit = None  # the seeds come from the jitter hash of prm.seed
     rgb = torch.empty((fr.h, fr.w, 3), dtype=torch.uint8, device="cuda")
     chunk = torch.empty((fr.h, fr.w), dtype=torch.int32, device="cuda")
     ws = torch.empty(sb.workspace_bytes(fr.w, fr.h, prm), dtype=torch.uint8, device="cuda")
@@ -511,7 +511,7 @@ def batch_leg(sb, at, torch, workloads, no_tune, reps=5):
     for f in frames_np:
         p = f.params
         jobs.append(sb.FrameJob(styles[f.style], f.guide, f.jitter,
-                                sb.params(p.levels, p.finest, p.threshold, p.radius)))
+                                sb.params(p.levels, p.finest, p.threshold, p.radius, seed=f.seed)))
     px = sum(j.w * j.h for j in jobs)
     probe = sb.Batch(use_graph=True)
     ws = torch.empty(probe.workspace_bytes(jobs), dtype=torch.uint8, device="cuda")
@@ -558,7 +558,7 @@ def serve_leg(sb, torch, np, workloads, nreq, qps):
 
     trace = workloads.config(5, requests=nreq, qps=qps, pool=2)
     styles = [sb.Style(s.rgb, s.guide, s.lut_bits) for s in trace["styles"]]
-    guides, jits = {}, {}
+    guides = {}
     reqs, px = [], []
     for i in range(nreq):
         si, st = int(trace["size_idx"][i]), int(trace["style_idx"][i])
@@ -570,12 +570,10 @@ def serve_leg(sb, torch, np, workloads, nreq, qps):
         g = guides[key]
         h, w = int(g.shape[0]), int(g.shape[1])
         p = trace["params"][fmt]
-        jk = (w, h, fmt, i % 4)  # a few jitter tables per shape (per-frame seeds)
-        if jk not in jits:
-            jt = workloads.jitter_table(w, h, p.levels, p.finest, 7000 + len(jits))
-            jits[jk] = torch.from_numpy(jt.view(np.int32)).cuda()
-        reqs.append(sv.Request(float(trace["arrivals"][i]), styles[st], g, jits[jk],
-                               sb.params(p.levels, p.finest, p.threshold, p.radius)))
+        # every request its own jitter hash seed (per-frame seeds, no table)
+        reqs.append(sv.Request(float(trace["arrivals"][i]), styles[st], g, None,
+                               sb.params(p.levels, p.finest, p.threshold, p.radius,
+                                         seed=int(trace["seeds"][i]))))
         px.append(w * h)
     px = np.array(px, dtype=np.float64)
     res = {"qps": qps, "requests": nreq, "budget_mib": 1024}

@@ -13,7 +13,8 @@
  *
  * Conventions (all functions):
  *   - pointers marked [device] are HIP device pointers, [host] host pointers;
- *     the caller owns every buffer (the library allocates no device memory);
+ *     the caller owns every buffer; the library allocates device memory only
+ *     in sb_style_create (released by sb_style_destroy);
  *   - images are row-major; pixel p = (x, y), x the column; raster index
  *     y*W + x;
  *   - a guide has two interleaved channels, uint8 (SB_GUIDE_U8X2, 2 B/px) or
@@ -88,6 +89,25 @@ typedef struct {
     uint8_t weights[4];
 } sb_style;
 
+/* Where the seed hierarchy's jitter comes from (SeedPoint in Algorithm 2
+ * offsets each cell's seed by RandomJitterTable[b]; the paper leaves the
+ * table's contents open).  Every mode gives integer jitter (jx, jy) in
+ * [0, h)^2 for a cell b = (bx, by) of spacing h = 2^lg, and the seed
+ * (h*bx + jx, h*by + jy):
+ *   SB_JITTER_HASH   an integer hash of (cell, lg, seed), computed in the
+ *                    kernels (no table is read).  With wrapping uint32
+ *                    arithmetic, mix(x) = x ^= x >> 16; x *= 0x9E3779B9;
+ *                    x ^= x >> 15; x *= 0x6A09E667; x ^= x >> 16, and
+ *                    k = mix(mix(mix(mix(seed + 0xBB67AE85) ^ lg) ^ bx) ^ by),
+ *                    jx = k & (h - 1), jy = (k >> 16) & (h - 1).  One 32-bit
+ *                    seed per frame is the whole per-frame seed schedule of
+ *                    an animation (Sec. 3.3).
+ *   SB_JITTER_NONE   jx = jy = 0: seeds on the cell corners.
+ *   SB_JITTER_TABLE  read from a caller-owned table (sb_jitter_len entries;
+ *                    the `jitter` argument of the stylize calls), e.g. drawn
+ *                    on the device by sb_jitter_fill. */
+typedef enum { SB_JITTER_HASH = 0, SB_JITTER_NONE = 1, SB_JITTER_TABLE = 2 } sb_jitter;
+
 /* Per-frame parameters of Algorithm 2 and of the voting blend. */
 typedef struct {
     int32_t levels;         /* L, 0..SB_MAX_LEVELS; 0 = plain lookup (texture mapping) */
@@ -98,6 +118,8 @@ typedef struct {
                                error over all channels is < t (so t = 0 accepts
                                nothing) */
     int32_t radius;         /* r, 0..SB_MAX_RADIUS: voting window (2r+1)^2; 0 = copy */
+    uint32_t seed;          /* jitter hash seed (SB_JITTER_HASH; per frame for animation) */
+    int32_t jitter;         /* sb_jitter: where the seeds' jitter comes from */
 } sb_params;
 
 /* --------------------------------------------------------------- general */
@@ -106,11 +128,12 @@ const char *sb_version(void);
 const char *sb_status_string(int status);
 const char *sb_last_hip_error(void);
 
-/* Entries of the jitter table of a W x H target: level i (coarsest first) has
- * ceil(W/h_i) x ceil(H/h_i) cells, row-major; each entry is jx | (jy << 16)
- * with 0 <= jx, jy < h_i, and the cell's seed is (h_i*cx + jx, h_i*cy + jy)
- * (SeedPoint in Algorithm 2, whose RandomJitterTable this is; the caller draws
- * it).  Returns -1 on invalid arguments. */
+/* Entries of the jitter table of a W x H target (SB_JITTER_TABLE): level i
+ * (coarsest first) has ceil(W/h_i) x ceil(H/h_i) cells, row-major; each entry
+ * is jx | (jy << 16) with 0 <= jx, jy < h_i, and the cell's seed is
+ * (h_i*cx + jx, h_i*cy + jy) (SeedPoint in Algorithm 2, whose
+ * RandomJitterTable this is; the caller supplies it).  Returns -1 on invalid
+ * arguments. */
 int64_t sb_jitter_len(int32_t w, int32_t h, int32_t levels, int32_t finest);
 
 /* Draw that table on the device from a counter-based generator, so the
@@ -163,6 +186,26 @@ int sb_lut_build_w(const void *guide, int32_t fmt, int32_t sw, int32_t sh, int32
                    const uint8_t *weights, uint32_t *lut, void *workspace,
                    size_t workspace_bytes, hipStream_t stream);
 
+/* A library-owned style in one call: copies the exemplar and its guide into
+ * device memory the library allocates, packs the exemplar and builds the
+ * exact lookup table of Sec. 3.1 (as sb_pack_exemplar + sb_lut_build), and
+ * returns a style usable wherever an sb_style is taken.  Unit channel
+ * weights, no labels.
+ *   src_rgb    [device] Sw*Sh*3 bytes; src_guide [device] Sw*Sh texels of fmt;
+ *              both may be freed once `stream` has been synchronised (this
+ *              call synchronises it before returning)
+ *   lut_bits   as sb_style.lut_bits (8 for 8-bit guides; 1..SB_MAX_LUT_BITS
+ *              for SB_GUIDE_U16X2)
+ *   out        [host] receives the style
+ * Allocates with hipMalloc (the build workspace is freed before returning).
+ * SB_EINVAL on bad arguments, SB_EHIP if an allocation or launch fails
+ * (nothing is left allocated then). */
+int sb_style_create(const uint8_t *src_rgb, const void *src_guide, int32_t sw, int32_t sh,
+                    int32_t fmt, int32_t lut_bits, hipStream_t stream, sb_style **out);
+/* Free a style from sb_style_create (only those), once no work that reads
+ * it is in flight.  NULL is ignored. */
+int sb_style_destroy(sb_style *style);
+
 /* Per-label lookup tables for the segmentation guide: table l holds, for
  * every bin, the source pixel labelled l whose guide is nearest to the bin
  * centre (ties to the smallest raster index, as sb_lut_build); a label with
@@ -190,7 +233,9 @@ size_t sb_workspace_bytes(int32_t w, int32_t h, const sb_params *params);
 /* Stylise one frame (Algorithm 2 for every pixel, then the voting blend).
  *   style      [host] struct of device pointers, see sb_style
  *   tgt_guide  [device] W*H texels, same format as the style's guide
- *   jitter     [device] sb_jitter_len(W, H, L, finest) entries
+ *   jitter     [device] sb_jitter_len(W, H, L, finest) entries when
+ *              params->jitter is SB_JITTER_TABLE; not read (may be NULL)
+ *              with SB_JITTER_HASH or SB_JITTER_NONE
  *   out_rgb    [device] W*H*3 bytes: the stylised image C_T
  *   out_chunk  [device] W*H: chunk code (level << 26) | (qy << 13) | qx of the
  *              seed q whose chunk covers the pixel; level = L and q = p when
@@ -291,7 +336,8 @@ int sb_frame_change(const uint32_t *chunk_a, const uint32_t *chunk_b, const uint
 typedef struct {
     const sb_style *style;      /* [host] */
     const void *tgt_guide;      /* [device] W*H texels in the style's format */
-    const uint32_t *jitter;     /* [device] sb_jitter_len() entries */
+    const uint32_t *jitter;     /* [device] sb_jitter_len() entries (SB_JITTER_TABLE only;
+                                   may be NULL otherwise) */
     int32_t w, h;
     sb_params params;
     uint8_t *out_rgb;           /* [device] W*H*3 */
@@ -362,7 +408,8 @@ typedef struct {
     double arrival_s;           /* arrival time, seconds after the run starts; sorted */
     const sb_style *style;      /* [host] resident style */
     const void *tgt_guide;      /* [device] */
-    const uint32_t *jitter;     /* [device] */
+    const uint32_t *jitter;     /* [device] jitter table (SB_JITTER_TABLE only; may be
+                                   NULL otherwise) */
     int32_t w, h;
     sb_params params;
     uint8_t *out_rgb;           /* [device] or NULL: taken from the arena on admission and

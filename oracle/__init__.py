@@ -97,6 +97,8 @@ def _load():
     lib.ora_jitter_hash_key.restype = ctypes.c_uint32
     lib.ora_lut_build_w.argtypes = [vp, i32, i32, i32, i32, _u8p, _u32p]
     lib.ora_lut_query_w.argtypes = [vp, i32, i32, i32, i32, _u8p, _i64p, ctypes.c_int64, _u32p]
+    lib.ora_lut_query_sweep_w.argtypes = [vp, i32, i32, i32, i32, _u8p, _i64p, ctypes.c_int64,
+                                          _u32p]
     lib.ora_lut_build_labels_w.argtypes = [vp, _u8p, i32, i32, i32, i32, i32, _u8p, _u32p]
     lib.ora_assign_w.argtypes = [vp, i32, i32, _u32p, i32, i32, _u8p, vp, i32, i32, _u32p, i32,
                                  i32, ctypes.c_uint32, _u32p, _u32p, ctypes.c_int64,
@@ -238,6 +240,21 @@ def lut_query(src_guide: np.ndarray, lut_bits: int, bins, weights=None) -> np.nd
     w, wp = _weights(weights)
     _check(_load().ora_lut_query_w(g.ctypes.data, fmt, g.shape[1], g.shape[0], lut_bits, wp,
                                    _ptr(b, _i64p), b.size, _ptr(out, _u32p)), "lut_query")
+    return out
+
+
+def lut_query_sweep(src_guide: np.ndarray, lut_bits: int, bins, weights=None) -> np.ndarray:
+    """The same entries as ``lut_query``, visiting the source pixels outward
+    along channel 0 from each bin centre and stopping once that channel
+    alone rules out every pixel not yet seen (for the many bins one large
+    frame touches)."""
+    g, fmt = _guide(src_guide)
+    b = np.ascontiguousarray(bins, dtype=np.int64)
+    out = np.zeros(b.size, np.uint32)
+    w, wp = _weights(weights)
+    _check(_load().ora_lut_query_sweep_w(g.ctypes.data, fmt, g.shape[1], g.shape[0], lut_bits,
+                                         wp, _ptr(b, _i64p), b.size, _ptr(out, _u32p)),
+           "lut_query_sweep")
     return out
 
 

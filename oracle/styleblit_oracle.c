@@ -330,6 +330,83 @@ int ora_lut_query(const void *src_guide, int fmt, int sw, int sh, int lut_bits,
     return ora_lut_query_w(src_guide, fmt, sw, sh, lut_bits, NULL, bins, nbins, out);
 }
 
+/* The same entries as ora_lut_query_w, found faster for many bins: the
+ * source pixels are grouped by their channel-0 value (raster order within a
+ * group), and each query visits the groups outward from its centre's
+ * channel-0 value, nearest first.  A group at channel-0 distance k holds
+ * only pixels at (weighted) squared distance >= w0 k^2, so the walk stops
+ * once that bound exceeds the best distance found (strictly: a pixel at
+ * equal distance with a smaller raster index must still be seen).  Ties go
+ * to the smallest raster index, as in the definition. */
+int ora_lut_query_sweep_w(const void *src_guide, int fmt, int sw, int sh, int lut_bits,
+                          const uint8_t *weights, const int64_t *bins, int64_t nbins,
+                          uint32_t *out)
+{
+    if (!src_guide || !bins || !out || sw < 1 || sh < 1 || !fmt_ok(fmt)) return ORA_EINVAL;
+    int64_t w[3];
+    if (weights_get(fmt, weights, w)) return ORA_EINVAL;
+    if (lut_bits < 1 || lut_bits > guide_depth(fmt) || lut_bits > 12) return ORA_EINVAL;
+    const int nc = guide_channels(fmt);
+    const int64_t n = (int64_t)1 << lut_bits, npix = (int64_t)sw * sh;
+    const int64_t nv = (int64_t)1 << guide_depth(fmt); /* channel-0 values */
+    int64_t nb = 1;
+    for (int k = 0; k < nc; ++k) nb *= n;
+    for (int64_t j = 0; j < nbins; ++j)
+        if (bins[j] < 0 || bins[j] >= nb) return ORA_EINVAL;
+    /* counting sort of the pixels by channel 0, raster order kept */
+    int64_t *start = (int64_t *)calloc((size_t)(nv + 1), sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc((size_t)npix * sizeof(int64_t));
+    if (!start || !order) { free(start); free(order); return ORA_ENOMEM; }
+    for (int64_t i = 0; i < npix; ++i) {
+        int64_t g[3];
+        guide_read_all(src_guide, fmt, i, g);
+        start[g[0] + 1]++;
+    }
+    for (int64_t v = 0; v < nv; ++v) start[v + 1] += start[v];
+    {
+        int64_t *fill = (int64_t *)malloc((size_t)nv * sizeof(int64_t));
+        if (!fill) { free(start); free(order); return ORA_ENOMEM; }
+        memcpy(fill, start, (size_t)nv * sizeof(int64_t));
+        for (int64_t i = 0; i < npix; ++i) {
+            int64_t g[3];
+            guide_read_all(src_guide, fmt, i, g);
+            order[fill[g[0]]++] = i;
+        }
+        free(fill);
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t j = 0; j < nbins; ++j) {
+        int64_t q[3], c = bins[j];
+        for (int k = 0; k < nc; ++k, c /= n) q[k] = lut_bin_centre(c % n, fmt, lut_bits);
+        uint64_t best_d = UINT64_MAX;
+        int64_t best_i = -1;
+        for (int64_t k = 0; k < nv; ++k) {
+            const uint64_t lb = (uint64_t)(w[0] * k * k);
+            if (best_i >= 0 && lb > best_d) break;
+            for (int side = 0; side < (k == 0 ? 1 : 2); ++side) {
+                const int64_t v = side == 0 ? q[0] - k : q[0] + k;
+                if (v < 0 || v >= nv) continue;
+                for (int64_t e = start[v]; e < start[v + 1]; ++e) {
+                    const int64_t i = order[e];
+                    int64_t g[3];
+                    guide_read_all(src_guide, fmt, i, g);
+                    uint64_t d = 0;
+                    for (int m = 0; m < nc; ++m)
+                        d += (uint64_t)(w[m] * (q[m] - g[m]) * (q[m] - g[m]));
+                    if (d < best_d || (d == best_d && i < best_i)) {
+                        best_d = d;
+                        best_i = i;
+                    }
+                }
+            }
+        }
+        out[j] = (uint32_t)(best_i % sw) | ((uint32_t)(best_i / sw) << 16);
+    }
+    free(start);
+    free(order);
+    return ORA_OK;
+}
+
 /* Per-label tables luts[l * bins + c] for labels l = 0..nlabels-1, from the
  * source pixels labelled l; a label without source pixels gets the
  * unconstrained table. */

@@ -60,9 +60,13 @@ def tune_struct(tune) -> Optional[SbTune]:
     return SbTune(*vals)
 
 
+JITTER_HASH, JITTER_NONE, JITTER_TABLE = 0, 1, 2
+
+
 class SbParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("finest", ctypes.c_int32),
-                ("threshold", ctypes.c_uint32), ("radius", ctypes.c_int32)]
+                ("threshold", ctypes.c_uint32), ("radius", ctypes.c_int32),
+                ("seed", ctypes.c_uint32), ("jitter", ctypes.c_int32)]
 
 
 class SbFrame(ctypes.Structure):
@@ -124,6 +128,8 @@ def lib():
     L.sb_batch_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(SbFrame), i32, vp, sz, vp]
     L.sb_batch_destroy.argtypes = [ctypes.c_void_p]
     L.sb_jitter_fill.argtypes = [i32, i32, i32, i32, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
+    L.sb_style_create.argtypes = [vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(vp)]
+    L.sb_style_destroy.argtypes = [vp]
     L.sb_change_workspace_bytes.restype = sz
     L.sb_frame_change.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp, sz, vp]
     _lib = L
@@ -170,8 +176,40 @@ def jitter_len(w: int, h: int, levels: int, finest: int) -> int:
     return int(n)
 
 
-def params(levels: int, finest: int, threshold: int, radius: int) -> SbParams:
-    return SbParams(int(levels), int(finest), int(threshold), int(radius))
+def params(levels: int, finest: int, threshold: int, radius: int,
+           seed: Optional[int] = None) -> SbParams:
+    """Frame parameters.  ``seed``: the seeds' jitter is the integer hash of
+    (cell, level, seed) computed in the kernels (SB_JITTER_HASH); None puts
+    the seeds on the cell corners (SB_JITTER_NONE) unless a jitter table is
+    passed to the call, which then selects SB_JITTER_TABLE."""
+    if seed is None:
+        return SbParams(int(levels), int(finest), int(threshold), int(radius), 0, JITTER_NONE)
+    return SbParams(int(levels), int(finest), int(threshold), int(radius),
+                    int(seed) & 0xFFFFFFFF, JITTER_HASH)
+
+
+def _with_table(p: SbParams) -> SbParams:
+    """A copy of p that reads its jitter from the table passed beside it."""
+    return SbParams(p.levels, p.finest, p.threshold, p.radius, p.seed, JITTER_TABLE)
+
+
+def _jitter_arg(torch, jitter, p: SbParams, w: int, h: int):
+    """(params, jitter tensor or None) for a call: a given table selects
+    SB_JITTER_TABLE; without one, p's hash or corner mode needs no table."""
+    if jitter is None:
+        if p.jitter == JITTER_TABLE:
+            raise ValueError("SB_JITTER_TABLE needs a jitter table")
+        return p, None
+    nj = jitter_len(w, h, p.levels, p.finest)
+    j = jitter
+    if not isinstance(j, torch.Tensor):
+        j = j.view("int32") if str(j.dtype) == "uint32" else j
+    j = _dev(torch, j)
+    if j.numel() < nj or j.element_size() != 4:
+        raise ValueError(f"jitter table needs {nj} 32-bit entries, got {j.numel()}")
+    if j.numel() == 0:
+        j = torch.zeros(1, dtype=torch.int32, device="cuda")
+    return _with_table(p), j
 
 
 def _guide_fmt(torch, g) -> int:
@@ -292,18 +330,8 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     if _guide_fmt(torch, g) != style.fmt:
         raise TypeError("target guide format differs from the style's guide format")
     h, w = int(g.shape[0]), int(g.shape[1])
-    nj = jitter_len(w, h, p.levels, p.finest)
-    if jitter is None:  # seeds on the cell corners
-        j = torch.zeros(max(nj, 1), dtype=torch.int32, device="cuda")
-    else:
-        j = jitter
-        if not isinstance(j, torch.Tensor):
-            j = j.view("int32") if str(j.dtype) == "uint32" else j
-        j = _dev(torch, j)
-        if j.numel() < nj or j.element_size() != 4:
-            raise ValueError(f"jitter table needs {nj} 32-bit entries, got {j.numel()}")
-        if j.numel() == 0:
-            j = torch.zeros(1, dtype=torch.int32, device="cuda")
+    p, j = _jitter_arg(torch, jitter, p, w, h)
+    jp = j.data_ptr() if j is not None else None
     if out_rgb is None:
         out_rgb = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
     if out_chunk is None:
@@ -325,20 +353,20 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
         if tuple(lt.shape) != (h, w):
             raise ValueError("target label map and guide sizes differ")
         _check(lib().sb_stylize_seg(ctypes.byref(style.c), g.data_ptr(), lt.data_ptr(), w, h,
-                                    j.data_ptr(), ctypes.byref(p), out_rgb.data_ptr(),
+                                    jp, ctypes.byref(p), out_rgb.data_ptr(),
                                     out_chunk.data_ptr(), nnf_p, workspace.data_ptr(), wsb, tp, s),
                "sb_stylize_seg")
     elif events is not None:
-        _check(lib().sb_stylize_timed(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
+        _check(lib().sb_stylize_timed(ctypes.byref(style.c), g.data_ptr(), w, h, jp,
                                       ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
                                       nnf_p, workspace.data_ptr(), wsb, tp, events.handles, s),
                "sb_stylize_timed")
     elif tn is None:
-        _check(lib().sb_stylize(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
+        _check(lib().sb_stylize(ctypes.byref(style.c), g.data_ptr(), w, h, jp,
                                 ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
                                 nnf_p, workspace.data_ptr(), wsb, s), "sb_stylize")
     else:
-        _check(lib().sb_stylize_ex(ctypes.byref(style.c), g.data_ptr(), w, h, j.data_ptr(),
+        _check(lib().sb_stylize_ex(ctypes.byref(style.c), g.data_ptr(), w, h, jp,
                                    ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
                                    nnf_p, workspace.data_ptr(), wsb, tp, s), "sb_stylize_ex")
     if want_nnf:
@@ -434,19 +462,7 @@ class FrameJob:
         if _guide_fmt(torch, self.guide) != style.fmt:
             raise TypeError("target guide format differs from the style's guide format")
         self.h, self.w = int(self.guide.shape[0]), int(self.guide.shape[1])
-        nj = jitter_len(self.w, self.h, p.levels, p.finest)
-        if jitter is None:
-            self.jitter = torch.zeros(max(nj, 1), dtype=torch.int32, device="cuda")
-        else:
-            j = jitter
-            if not isinstance(j, torch.Tensor):
-                j = j.view("int32") if str(j.dtype) == "uint32" else j
-            self.jitter = _dev(torch, j)
-            if self.jitter.numel() < nj:
-                raise ValueError(f"jitter table needs {nj} entries")
-            if self.jitter.numel() == 0:
-                self.jitter = torch.zeros(1, dtype=torch.int32, device="cuda")
-        self.params = p
+        self.params, self.jitter = _jitter_arg(torch, jitter, p, self.w, self.h)
         self.out_rgb = out_rgb if out_rgb is not None else torch.empty(
             (self.h, self.w, 3), dtype=torch.uint8, device="cuda")
         self.out_chunk = out_chunk if out_chunk is not None else torch.empty(
@@ -455,7 +471,8 @@ class FrameJob:
         self.tgt_labels = None if tgt_labels is None else _dev(torch, tgt_labels, torch.uint8)
 
     def c(self) -> SbFrame:
-        return SbFrame(ctypes.pointer(self.style.c), self.guide.data_ptr(), self.jitter.data_ptr(),
+        return SbFrame(ctypes.pointer(self.style.c), self.guide.data_ptr(),
+                       self.jitter.data_ptr() if self.jitter is not None else None,
                        self.w, self.h, self.params, self.out_rgb.data_ptr(),
                        self.out_chunk.data_ptr(),
                        self.out_nnf.data_ptr() if self.out_nnf is not None else None,

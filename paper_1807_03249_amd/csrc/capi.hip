@@ -35,6 +35,8 @@ bool style_ok(const sb_style *s) {
 bool params_ok(const sb_params *p) {
   if (!p) return false;
   if (p->radius < 0 || p->radius > SB_MAX_RADIUS) return false;
+  if (p->jitter != SB_JITTER_HASH && p->jitter != SB_JITTER_NONE && p->jitter != SB_JITTER_TABLE)
+    return false;
   Levels lv;
   return make_levels(1, 1, p->levels, p->finest, &lv);
 }
@@ -77,14 +79,21 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
   if (!style_ok(style) || !tgt_guide || !out_rgb || !out_chunk) return false;
   if (tgt_labels && style->nlabels < 1) return false;  // labels on one side only
   if (!side_ok(w) || !side_ok(h) || !params_ok(params)) return false;
-  if (params->levels > 0 && !jitter) return false;
+  if (params->jitter == SB_JITTER_TABLE && params->levels > 0 && !jitter) return false;
   memset(a, 0, sizeof *a);
   make_levels(w, h, params->levels, params->finest, &a->lv);
+  a->jmode = params->jitter;
+  if (params->jitter == SB_JITTER_HASH) {
+    // the hash state after the seed and level words; the kernels add the cell
+    const uint32_t k0 = hash_mix(params->seed + 0xBB67AE85u);
+    for (int32_t i = 0; i < a->lv.count; ++i)
+      a->jhash[i] = hash_mix(k0 ^ uint32_t(a->lv.log2_spacing[i]));
+  }
   a->src_rgba = style->rgba;
   a->src_guide = style->guide;
   a->lut = style->lut;
   a->tgt_guide = tgt_guide;
-  a->jitter = jitter;
+  a->jitter = params->jitter == SB_JITTER_TABLE ? jitter : nullptr;
   a->out_rgb = out_rgb;
   a->out_chunk = out_chunk;
   a->out_nnf = out_nnf;

@@ -74,7 +74,7 @@ struct FrameArgs {
   const void *src_guide;      // Sw*Sh*2 channels
   const uint32_t *lut;        // (1 << lut_bits)^2
   const void *tgt_guide;      // W*H*2 channels
-  const uint32_t *jitter;     // Levels.offset[L] entries
+  const uint32_t *jitter;     // Levels.offset[L] entries (SB_JITTER_TABLE only)
   uint8_t *out_rgb;           // W*H*3
   uint32_t *out_chunk;        // W*H
   uint32_t *out_nnf;          // W*H or null
@@ -98,8 +98,34 @@ struct FrameArgs {
   const uint8_t *tgt_labels;   // W*H
   const uint32_t *label_luts;  // nlabels tables of (1 << lut_bits)^2 entries
   int32_t nlabels;
+  // seed jitter: sb_jitter mode, and for SB_JITTER_HASH level i's hash state
+  // after the seed and level words, mix(mix(seed + 0xBB67AE85) ^ lg_i), so a
+  // cell's jitter is two more mixing steps (hash_jitter)
+  int32_t jmode;
+  uint32_t jhash[SB_MAX_LEVELS];
   Levels lv;
 };
+
+// The 32-bit mixing step of the jitter hash (xor-shift, multiply by
+// floor(2^32 / golden ratio), xor-shift, multiply by the first 32 fraction
+// bits of sqrt(2), xor-shift; wrapping arithmetic).
+__host__ __device__ inline uint32_t hash_mix(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x9E3779B9u;
+  x ^= x >> 15;
+  x *= 0x6A09E667u;
+  x ^= x >> 16;
+  return x;
+}
+
+// Jitter word jx | jy << 16 of cell (cx, cy) at a level of spacing 2^ls whose
+// hash state is hk (FrameArgs::jhash).
+__host__ __device__ inline uint32_t hash_jitter(uint32_t hk, int32_t ls, uint32_t cx,
+                                                uint32_t cy) {
+  const uint32_t k = hash_mix(hash_mix(hk ^ cx) ^ cy);
+  const uint32_t m = (1u << ls) - 1u;
+  return (k & m) | (((k >> 16) & m) << 16);
+}
 
 // Batch descriptor block in device memory: header, per-pass tile prefix sums
 // (kMaxBatchFrames + 1 entries each: seeds, assign, blend of radius 0..3,

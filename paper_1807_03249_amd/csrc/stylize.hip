@@ -130,16 +130,27 @@ __device__ inline const uint32_t *lut_of(const FrameArgs &a, uint32_t pidx) {
   return a.label_luts + (size_t(l) << a.lut_log2);
 }
 
+// Jitter word jx | jy << 16 of cell (cx, cy) of a level with log2 spacing ls
+// and a ncx-wide cell grid: from the hash (level hash state hk), zero, or the
+// caller's table (the level's entries from joff on).
+__device__ inline uint32_t cell_jitter(const FrameArgs &a, int32_t ls, int32_t ncx, int32_t joff,
+                                       uint32_t hk, int32_t cx, int32_t cy) {
+  if (a.jmode == SB_JITTER_HASH) return hash_jitter(hk, ls, uint32_t(cx), uint32_t(cy));
+  if (a.jmode == SB_JITTER_NONE) return 0u;
+  return glb(a.jitter)[uint32_t(joff) + __umul24(uint32_t(cy), uint32_t(ncx)) + uint32_t(cx)];
+}
+
 // The seed record of cell (cx, cy) of a level with log2 spacing ls, a
-// ncx x ncy cell grid and its jitter entries from joff on (SeedPoint and the
-// seed's lookup): position 4x | 4y << 16 and the translation u* - q, or the
-// empty record for a cell outside the grid or a seed outside the target.
+// ncx x ncy cell grid, its jitter entries from joff on and hash state hk
+// (SeedPoint and the seed's lookup): position 4x | 4y << 16 and the
+// translation u* - q, or the empty record for a cell outside the grid or a
+// seed outside the target.
 template <int FMT>
 __device__ inline u32x2 seed_record(const FrameArgs &a, int32_t ls, int32_t ncx, int32_t ncy,
-                                    int32_t joff, int32_t cx, int32_t cy) {
+                                    int32_t joff, uint32_t hk, int32_t cx, int32_t cy) {
   u32x2 rec = {kNoSeed, 0u};
   if (cx >= 0 && cy >= 0 && cx < ncx && cy < ncy) {
-    const uint32_t j = glb(a.jitter)[uint32_t(joff) + __umul24(uint32_t(cy), uint32_t(ncx)) + uint32_t(cx)];
+    const uint32_t j = cell_jitter(a, ls, ncx, joff, hk, cx, cy);
     const uint32_t sx = (uint32_t(cx) << ls) + (j & 0xFFFFu);
     const uint32_t sy = (uint32_t(cy) << ls) + (j >> 16);
     if (sx < uint32_t(a.w) && sy < uint32_t(a.h)) {
@@ -170,7 +181,7 @@ __device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
   while (idx >= uint32_t(lv.poffset[i + 1])) ++i;
   const uint32_t local = idx - uint32_t(lv.poffset[i]), pc = uint32_t(lv.cells_x[i] + 2);
   seed_table(a)[idx] = seed_record<FMT>(a, lv.log2_spacing[i], lv.cells_x[i], lv.cells_y[i],
-                                        lv.offset[i], int32_t(local % pc) - 1,
+                                        lv.offset[i], a.jhash[i], int32_t(local % pc) - 1,
                                         int32_t(local / pc) - 1);
 }
 
@@ -320,8 +331,12 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
     const int32_t ncx = ((a.w - 1) >> ls) + 1, ncy = ((a.h - 1) >> ls) + 1;
     const int32_t rcy = (by0 >> ls) - 1 + int32_t(k - 3u * kx);
     int32_t f = 0;
+    uint32_t hk = a.jhash[0];
 #pragma unroll 1
-    for (int32_t l = 1; l < L; ++l) f = i >= uint32_t(l) ? first[l] : f;
+    for (int32_t l = 1; l < L; ++l) {
+      f = i >= uint32_t(l) ? first[l] : f;
+      hk = i >= uint32_t(l) ? a.jhash[l] : hk;
+    }
 #pragma unroll
     for (int32_t b = 0; b < B; ++b) {
       const int32_t cx0 = min(bx0 + 8 * b, a.w - 1);
@@ -330,7 +345,7 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
       rec[b][h] = u32x2{0, 0};
       if (staged) {
         if (a.own_seeds)
-          rec[b][h] = seed_record<FMT>(a, ls, ncx, ncy, f, rcx, rcy);
+          rec[b][h] = seed_record<FMT>(a, ls, ncx, ncy, f, hk, rcx, rcy);
         else
           rec[b][h] = seed_table(a)[uint32_t(f + (rcy + 1) * (ncx + 2) + rcx + 1)];
       }

@@ -11,9 +11,8 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-from . import (SB_OK, SbParams, SbStyle, SbTune, Style, StyleBlitError, _check, _dev, _torch, lib,
-               tune_struct,
-               workspace_bytes)
+from . import (JITTER_TABLE, SB_OK, SbParams, SbStyle, SbTune, Style, StyleBlitError, _check,
+               _dev, _torch, _with_table, lib, tune_struct, workspace_bytes)
 
 
 class SbServeConfig(ctypes.Structure):
@@ -54,8 +53,10 @@ def _bind():
 
 
 class Request:
-    """One request: a resident style, a device-resident target guide and
-    jitter table, the frame parameters and (optionally) output tensors.
+    """One request: a resident style, a device-resident target guide, a
+    jitter table (a device int32 tensor, which selects SB_JITTER_TABLE) or
+    None (the params' hash seed, or seeds on the cell corners), the frame
+    parameters and (optionally) output tensors.
     ``session`` >= 0 marks a frame of an animated sequence: frames of one
     session complete in arrival order.  ``tgt_labels`` (uint8 (H, W) device
     tensor) runs the frame with the segmentation guide."""
@@ -67,6 +68,10 @@ class Request:
         self.style = style
         self.guide = guide
         self.jitter = jitter
+        if jitter is not None:
+            p = _with_table(p)
+        elif p.jitter == JITTER_TABLE:
+            raise ValueError("SB_JITTER_TABLE needs a jitter table")
         self.params = p
         self.out_rgb = out_rgb
         self.out_chunk = out_chunk
@@ -117,7 +122,8 @@ def run(requests: Sequence[Request], slots: int = 4, max_batch: int = 16,
     for i, r in enumerate(requests):
         _check_request(torch, i, r)
         reqs[i] = SbRequest(r.arrival_s, ctypes.pointer(r.style.c), r.guide.data_ptr(),
-                            r.jitter.data_ptr(), r.w, r.h, r.params,
+                            r.jitter.data_ptr() if r.jitter is not None else None,
+                            r.w, r.h, r.params,
                             r.out_rgb.data_ptr() if r.out_rgb is not None else None,
                             r.out_chunk.data_ptr() if r.out_chunk is not None else None,
                             r.out_nnf.data_ptr() if r.out_nnf is not None else None,

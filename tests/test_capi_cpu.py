@@ -85,7 +85,7 @@ def test_validation_rejects_before_launch(L):
 
     fake = 0x1000  # never dereferenced: validation fails first
     st = sb.SbStyle(fake, fake, fake, 512, 512, 0, 8)
-    p = sb.params(4, 8, 32, 3)
+    p = sb._with_table(sb.params(4, 8, 32, 3))  # the jitter table argument is read
     ws = sb.workspace_bytes(64, 64, p)
 
     def call(style=st, g=fake, w=64, h=64, j=fake, prm=p, rgb=fake, chunk=fake, wsb=ws):
@@ -96,7 +96,11 @@ def test_validation_rejects_before_launch(L):
     assert call(g=None) == sb.SB_EINVAL
     assert call(rgb=None) == sb.SB_EINVAL
     assert call(chunk=None) == sb.SB_EINVAL
-    assert call(j=None) == sb.SB_EINVAL
+    assert call(j=None) == sb.SB_EINVAL  # SB_JITTER_TABLE without a table
+    bad_mode = sb.params(4, 8, 32, 3)
+    bad_mode.jitter = 3
+    assert call(prm=bad_mode) == sb.SB_EINVAL
+    assert L.sb_workspace_bytes(64, 64, ctypes.byref(bad_mode)) == 0
     assert call(prm=None) == sb.SB_EINVAL
     assert call(style=None) == sb.SB_EINVAL
     assert call(w=0) == sb.SB_EINVAL
@@ -226,3 +230,37 @@ def test_jitter_fill_validation(L):
     assert L.sb_jitter_fill(10, 10, 13, 1, 1, 0, 0x1000, None) == sb.SB_EINVAL
     assert L.sb_jitter_fill(10, 10, 3, 8, 1, 0, None, None) == sb.SB_EINVAL
     assert L.sb_jitter_fill(10, 10, 0, 8, 1, 0, None, None) == sb.SB_OK  # no levels: no work
+
+
+def test_style_create_validation(L):
+    """sb_style_create refuses bad arguments before allocating anything;
+    sb_style_destroy(NULL) is a no-op."""
+    import paper_1807_03249_amd as sb
+
+    fake = 0x1000
+    out = ctypes.c_void_p()
+    assert L.sb_style_create(None, fake, 64, 64, 0, 8, None, ctypes.byref(out)) == sb.SB_EINVAL
+    assert L.sb_style_create(fake, None, 64, 64, 0, 8, None, ctypes.byref(out)) == sb.SB_EINVAL
+    assert L.sb_style_create(fake, fake, 64, 64, 0, 8, None, None) == sb.SB_EINVAL
+    assert L.sb_style_create(fake, fake, 0, 64, 0, 8, None, ctypes.byref(out)) == sb.SB_EINVAL
+    assert L.sb_style_create(fake, fake, 64, 8193, 0, 8, None, ctypes.byref(out)) == sb.SB_EINVAL
+    assert L.sb_style_create(fake, fake, 64, 64, 0, 9, None, ctypes.byref(out)) == sb.SB_EINVAL
+    assert L.sb_style_create(fake, fake, 64, 64, 1, 13, None, ctypes.byref(out)) == sb.SB_EINVAL
+    assert L.sb_style_create(fake, fake, 64, 64, 3, 8, None, ctypes.byref(out)) == sb.SB_EINVAL
+    assert out.value is None
+    assert L.sb_style_destroy(None) == sb.SB_OK
+
+
+def test_params_layout_and_jitter_modes(L):
+    """sb_params as the header lays it out (seed and jitter mode after the
+    radius); the binding's params() picks the hash with a seed and the cell
+    corners without one."""
+    import paper_1807_03249_amd as sb
+
+    assert ctypes.sizeof(sb.SbParams) == 24
+    assert sb.SbParams.seed.offset == 16 and sb.SbParams.jitter.offset == 20
+    assert (sb.JITTER_HASH, sb.JITTER_NONE, sb.JITTER_TABLE) == (0, 1, 2)
+    h = sb.params(4, 8, 32, 3, seed=2**32 + 5)
+    assert h.jitter == sb.JITTER_HASH and h.seed == 5
+    assert sb.params(4, 8, 32, 3).jitter == sb.JITTER_NONE
+    assert sb._with_table(h).jitter == sb.JITTER_TABLE

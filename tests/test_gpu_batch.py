@@ -39,7 +39,7 @@ def jobs_for(sb, styles, frames_np, idx):
         f = frames_np[i]
         p = f.params
         out.append(sb.FrameJob(styles[f.style], f.guide, f.jitter,
-                               sb.params(p.levels, p.finest, p.threshold, p.radius)))
+                               sb.params(p.levels, p.finest, p.threshold, p.radius, seed=f.seed)))
     return out
 
 
@@ -48,7 +48,7 @@ def single(sb, styles, f):
 
     p = f.params
     rgb, chunk = sb.stylize(styles[f.style], f.guide, f.jitter,
-                            sb.params(p.levels, p.finest, p.threshold, p.radius))
+                            sb.params(p.levels, p.finest, p.threshold, p.radius, seed=f.seed))
     torch.cuda.synchronize()
     return rgb.cpu().numpy(), chunk.cpu().numpy()
 
@@ -107,7 +107,7 @@ def test_batch_matches_oracle(sb, mix):
         say(f"oracle frame {i} {f.w}x{f.h}")
         lut = oracle.lut_build(st.guide, st.lut_bits)
         e_rgb, e_chunk, _ = oracle.stylize(st.rgb, st.guide, lut, st.lut_bits, f.guide, f.jitter,
-                                           p.levels, p.finest, p.threshold, p.radius)
+                                           p.levels, p.finest, p.threshold, p.radius, seed=f.seed)
         np.testing.assert_array_equal(j.out_chunk.cpu().numpy().view(np.uint32), e_chunk)
         np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), e_rgb)
     b.close()
@@ -230,4 +230,44 @@ def test_batch_deep_hierarchy_matches_oracle(sb):
         np.testing.assert_array_equal(j.out_chunk.cpu().numpy().view(np.uint32), e_chunk,
                                       err_msg=f"frame {k} chunk")
         np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), e_rgb, err_msg=f"frame {k} rgb")
+    b.close()
+
+
+@pytest.mark.parametrize("tune,bpc", [(None, 0), ((4, 8, 2, 2), 16), ((2, 16, 4, 1), 4)])
+def test_full_workload_batch(sb, tune, bpc):
+    """The whole 64-frame mix of uneven sizes (half normal-guided, half
+    UV-guided, four styles) as one batch, as the benchmark runs it: every
+    frame equals its single-frame launch, and eight frames of both guide
+    formats equal the oracle."""
+    import torch
+
+    styles_np, frames_np = workloads.config(4)
+    assert len(frames_np) == 64
+    styles = [sb.Style(s.rgb, s.guide, s.lut_bits) for s in styles_np]
+    idx = list(range(64))
+    jobs = jobs_for(sb, styles, frames_np, idx)
+    b = sb.Batch(use_graph=True, tune=tune, blocks_per_cu=bpc)
+    say(f"full 64-frame batch tune={tune} blocks_per_cu={bpc}")
+    b.run(jobs)
+    torch.cuda.synchronize()
+    for i, j in zip(idx, jobs):
+        rgb, chunk = single(sb, styles, frames_np[i])
+        np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), rgb, err_msg=f"frame {i} rgb")
+        np.testing.assert_array_equal(j.out_chunk.cpu().numpy(), chunk, err_msg=f"frame {i} chunk")
+    if tune is None:
+        luts = {}
+        for i in [0, 5, 17, 31, 32, 40, 51, 63]:
+            f = frames_np[i]
+            st = styles_np[f.style]
+            p = f.params
+            say(f"oracle frame {i} {f.w}x{f.h} fmt={f.fmt}")
+            if f.style not in luts:
+                luts[f.style] = oracle.lut_build(st.guide, st.lut_bits)
+            e_rgb, e_chunk, _ = oracle.stylize(st.rgb, st.guide, luts[f.style], st.lut_bits,
+                                               f.guide, None, p.levels, p.finest, p.threshold,
+                                               p.radius, seed=f.seed)
+            np.testing.assert_array_equal(jobs[i].out_chunk.cpu().numpy().view(np.uint32),
+                                          e_chunk, err_msg=f"frame {i} chunk")
+            np.testing.assert_array_equal(jobs[i].out_rgb.cpu().numpy(), e_rgb,
+                                          err_msg=f"frame {i} rgb")
     b.close()

@@ -109,61 +109,59 @@ def test_frames_match_oracle_all_tunes(sb, w, h, levels, finest, t, r):
         np.testing.assert_array_equal(rgb.cpu().numpy(), e_rgb, err_msg=f"tune={tune}")
 
 
-def test_full_size_workload_sampled(sb):
-    """The 1080p appearance workload in the configuration the benchmark times:
-    chunk codes and NNF at 1200 sampled pixels, RGB at 40 sampled pixels whose
-    whole voting window is sampled.  The oracle's table holds exactly the bins
-    those pixels look up (each by brute force)."""
+def test_full_size_workload(sb):
+    """The 1080p appearance workload in the configuration the benchmark times,
+    element by element over the whole frame: every chunk code, NNF entry and
+    RGB triple against the oracle.  The oracle's table holds exactly the
+    entries the frame reads -- the bins of every seed, then of every pixel
+    that falls back -- each computed by the oracle's exact query."""
     import torch
 
     styles, frames = workloads.config(6)
     st_np, fr = styles[0], frames[0]
     p = fr.params
     w, h = fr.w, fr.h
-    rng = np.random.default_rng(5)
-    pts = set(zip(rng.integers(0, w, 1200).tolist(), rng.integers(0, h, 1200).tolist()))
-    pts |= {(0, 0), (w - 1, h - 1), (w - 1, 0), (0, h - 1), (w // 2, h // 2)}
-    centres = list(zip(rng.integers(p.radius, w - p.radius, 40).tolist(),
-                       rng.integers(p.radius, h - p.radius, 40).tolist()))
-    for cx, cy in centres:
-        for dy in range(-p.radius, p.radius + 1):
-            for dx in range(-p.radius, p.radius + 1):
-                pts.add((cx + dx, cy + dy))
-    say(f"appearance 1080p: {len(pts)} sampled pixels, collecting their table bins")
     bits = st_np.lut_bits
 
-    def bin_of(x, y):
-        c = fr.guide[y, x, :3].astype(np.int64) >> (8 - bits)
-        return int(c[0] + (c[1] << bits) + (c[2] << (2 * bits)))
+    def bins_at(xs, ys):
+        c = fr.guide[ys, xs, :3].astype(np.int64) >> (8 - bits)
+        return c[:, 0] + (c[:, 1] << bits) + (c[:, 2] << (2 * bits))
 
-    need = set()
-    for x, y in pts:
-        need.add(bin_of(x, y))
-        for lvl in range(p.levels):
-            ok, qx, qy = oracle.nearest_seed(w, h, p.levels, p.finest, fr.jitter, lvl, x, y)
-            if ok:
-                need.add(bin_of(qx, qy))
-    bins = np.array(sorted(need), np.int64)
-    say(f"appearance 1080p: {bins.size} bins by brute force")
+    jit = oracle.jitter_hash(w, h, p.levels, p.finest, fr.seed)
+    sx, sy, off = [], [], 0
+    for (cx, cy), sp in zip(workloads.jitter_cells(w, h, p.levels, p.finest),
+                            workloads.level_spacings(p.levels, p.finest)):
+        j = jit[off:off + cx * cy].astype(np.int64)
+        off += cx * cy
+        by, bx = np.divmod(np.arange(cx * cy), cx)
+        x, y = bx * sp + (j & 0xFFFF), by * sp + (j >> 16)
+        ok = (x < w) & (y < h)
+        sx.append(x[ok])
+        sy.append(y[ok])
+    seed_bins = np.unique(bins_at(np.concatenate(sx), np.concatenate(sy)))
+    say(f"appearance 1080p: {seed_bins.size} seed bins")
     lut = np.zeros(1 << (3 * bits), np.uint32)
-    lut[bins] = oracle.lut_query(st_np.guide, bits, bins)
+    lut[seed_bins] = oracle.lut_query_sweep(st_np.guide, bits, seed_bins)
+    # which pixels fall back depends only on the seeds' entries
+    _, chunk0 = oracle.assign(st_np.guide, lut, bits, fr.guide, None, p.levels, p.finest,
+                              p.threshold, seed=fr.seed)
+    fy, fx = np.nonzero((chunk0 >> 26) == p.levels)
+    own_bins = np.setdiff1d(np.unique(bins_at(fx, fy)), seed_bins)
+    say(f"appearance 1080p: {fy.size} fallback pixels, {own_bins.size} more bins")
+    lut[own_bins] = oracle.lut_query_sweep(st_np.guide, bits, own_bins)
     e_rgb, e_chunk, e_nnf = oracle.stylize(st_np.rgb, st_np.guide, lut, bits, fr.guide, fr.jitter,
-                                           p.levels, p.finest, p.threshold, p.radius)
+                                           p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
+    np.testing.assert_array_equal(e_chunk, chunk0)
     say("appearance 1080p: GPU frame")
     style = sb.Style(st_np.rgb, st_np.guide, bits)
     rgb, chunk, nnf = sb.stylize(style, fr.guide, fr.jitter,
-                                 sb.params(p.levels, p.finest, p.threshold, p.radius),
+                                 sb.params(p.levels, p.finest, p.threshold, p.radius, seed=fr.seed),
                                  want_nnf=True)
     torch.cuda.synchronize()
-    g_chunk, g_nnf, g_rgb = u32(chunk), u32(nnf), rgb.cpu().numpy()
-    xs = np.array([q[0] for q in pts])
-    ys = np.array([q[1] for q in pts])
-    np.testing.assert_array_equal(g_chunk[ys, xs], e_chunk[ys, xs])
-    np.testing.assert_array_equal(g_nnf[ys, xs], e_nnf[ys, xs])
-    cx = np.array([c[0] for c in centres])
-    cy = np.array([c[1] for c in centres])
-    np.testing.assert_array_equal(g_rgb[cy, cx], e_rgb[cy, cx])
-    lv = g_chunk >> 26
+    np.testing.assert_array_equal(u32(chunk), e_chunk)
+    np.testing.assert_array_equal(u32(nnf), e_nnf)
+    np.testing.assert_array_equal(rgb.cpu().numpy(), e_rgb)
+    lv = e_chunk >> 26
     assert 0.0 < float((lv == p.levels).mean()) < 0.9  # the level loop does accept
 
 

@@ -37,28 +37,31 @@ def u32(t):
 
 
 def run_gpu(sb, style_np, lut_bits, frame_guide, jit, levels, finest, t, r, style_obj=None,
-            tune=None):
+            tune=None, seed=None):
     import torch
 
     st = style_obj or sb.Style(style_np.rgb, style_np.guide, lut_bits)
-    p = sb.params(levels, finest, t, r)
+    p = sb.params(levels, finest, t, r, seed=seed)
     rgb, chunk, nnf = sb.stylize(st, frame_guide, jit, p, want_nnf=True, tune=tune)
     torch.cuda.synchronize()
     return to_np(rgb), u32(chunk), u32(nnf), st
 
 
 def check_frame(sb, st_np, fr_guide, jit, levels, finest, t, r, lut=None, style_obj=None,
-                name="", tunes=(None,)):
+                name="", tunes=(None,), seed=None):
+    """GPU frame against the oracle, element by element, under each kernel
+    choice.  The seeds' jitter: the table ``jit``, else the hash of ``seed``,
+    else none (cell corners)."""
     if lut is None:
         lut = oracle.lut_build(st_np.guide, st_np.lut_bits)
     e_rgb, e_chunk, e_nnf = oracle.stylize(st_np.rgb, st_np.guide, lut, st_np.lut_bits, fr_guide,
-                                           jit, levels, finest, t, r)
+                                           jit, levels, finest, t, r, seed=seed)
     st = style_obj
     for tune in tunes:
         say(f"{name} {fr_guide.shape[1]}x{fr_guide.shape[0]} L={levels} f={finest} t={t} r={r} "
-            f"tune={tune}")
+            f"tune={tune} seed={seed}")
         g_rgb, g_chunk, g_nnf, st = run_gpu(sb, st_np, st_np.lut_bits, fr_guide, jit, levels,
-                                            finest, t, r, st, tune)
+                                            finest, t, r, st, tune, seed)
         msg = f"{name} tune={tune}"
         np.testing.assert_array_equal(g_chunk, e_chunk, err_msg=f"{msg}: chunk map")
         np.testing.assert_array_equal(g_nnf, e_nnf, err_msg=f"{msg}: nnf")
@@ -127,8 +130,9 @@ def test_workload_frames(sb, n):
     styles, frames = workloads.config(n)
     st, fr = styles[0], frames[0]
     p = fr.params
+    assert fr.jitter is None and fr.seed is not None  # the workloads' seeds come from the hash
     check_frame(sb, st, fr.guide, fr.jitter, p.levels, p.finest, p.threshold, p.radius,
-                name=f"workload {n}", tunes=all_tunes(sb))
+                name=f"workload {n}", tunes=all_tunes(sb), seed=fr.seed)
 
 
 def test_workload2_param_sweep(sb):
@@ -140,7 +144,7 @@ def test_workload2_param_sweep(sb):
     for t, r in [(0, 0), (1, 1), (200, 2), (5000, 7), (1 << 31, 3)]:
         style_obj = check_frame(sb, st, fr.guide, fr.jitter, 4, 8, t, r, lut=lut,
                                 style_obj=style_obj, name="workload 2 sweep",
-                                tunes=[None, sb.TUNES[0]])
+                                tunes=[None, sb.TUNES[0]], seed=fr.seed)
 
 
 @pytest.mark.parametrize("seed", range(24))
@@ -164,11 +168,14 @@ def test_random_small(sb, seed):
     finest = int(2 ** rng.integers(0, 5))
     while levels and finest << (levels - 1) > 8192:
         levels -= 1
-    jit = workloads.jitter_table(w, h, levels, finest, seed)
+    # every third case draws its seeds from the jitter hash (its seed drawn
+    # over all 32 bits), the others from a table
+    hseed = int(rng.integers(0, 2**32)) if seed % 3 == 0 else None
+    jit = None if hseed is not None else workloads.jitter_table(w, h, levels, finest, seed)
     t = int(rng.integers(0, 8 * scale))
     r = int(rng.integers(0, 8))
     check_frame(sb, st, gt, jit, levels, finest, t, r, name=f"random {seed} u16={u16}",
-                tunes=all_tunes(sb))
+                tunes=all_tunes(sb), seed=hseed)
 
 
 def _gradient_case(rng, w, h, sw, sh, u16):
@@ -197,6 +204,9 @@ def test_deep_hierarchies(sb, u16, levels, finest, t):
     jit = workloads.jitter_table(333, 217, levels, finest, levels + 7)
     check_frame(sb, st, gt, jit, levels, finest, t, 2, name=f"deep u16={u16}",
                 tunes=all_tunes(sb))
+    # the same hierarchy with the seeds from the jitter hash
+    check_frame(sb, st, gt, None, levels, finest, t, 2, name=f"deep hash u16={u16}",
+                tunes=[None, sb.TUNES[0], sb.TUNES[-1]], seed=levels * 977 + finest)
 
 
 def test_degenerate_shapes(sb):
@@ -210,6 +220,9 @@ def test_degenerate_shapes(sb):
         jit = workloads.jitter_table(w, h, levels, finest, w * 31 + h)
         style_obj = check_frame(sb, st, gt, jit, levels, finest, 64, 3, lut=lut,
                                 style_obj=style_obj, name="degenerate", tunes=all_tunes(sb))
+        style_obj = check_frame(sb, st, gt, None, levels, finest, 64, 3, lut=lut,
+                                style_obj=style_obj, name="degenerate hash",
+                                tunes=[None, sb.TUNES[-1]], seed=w * 31 + h)
 
 
 def test_no_jitter_and_zero_levels(sb):
@@ -259,3 +272,53 @@ def test_unaligned_output_rows(sb):
     check_frame(sb, st, g, jit, 3, 8, 48, 2, lut=lut, name="width 253", tunes=all_tunes(sb))
 
 
+
+
+def test_library_owned_style(sb):
+    """sb_style_create builds the same padded exemplar and lookup table as
+    the caller-owned path, and a frame through it equals the oracle;
+    sb_style_destroy frees it."""
+    import ctypes
+
+    import torch
+
+    styles, frames = workloads.config(1)
+    st, fr = styles[0], frames[0]
+    p = fr.params
+    rgb_d = torch.from_numpy(st.rgb).cuda()
+    guide_d = torch.from_numpy(st.guide).cuda()
+    h = ctypes.POINTER(sb.SbStyle)()
+    say("sb_style_create 256x256")
+    rc = sb.lib().sb_style_create(rgb_d.data_ptr(), guide_d.data_ptr(), st.sw, st.sh, st.fmt,
+                                  st.lut_bits, torch.cuda.current_stream().cuda_stream,
+                                  ctypes.cast(ctypes.byref(h), ctypes.POINTER(ctypes.c_void_p)))
+    assert rc == sb.SB_OK
+    del rgb_d, guide_d  # the style holds its own copies
+    s = h.contents
+    assert (s.sw, s.sh, s.fmt, s.lut_bits, s.nlabels) == (st.sw, st.sh, st.fmt, st.lut_bits, 0)
+    class DevView:  # a view of library-owned device memory as a tensor
+        def __init__(self, ptr, n):
+            self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<i4",
+                                             "data": (ptr, False), "version": 2}
+
+    lut = oracle.lut_build(st.guide, st.lut_bits)
+    got = torch.as_tensor(DevView(s.lut, 1 << (2 * st.lut_bits)), device="cuda")
+    np.testing.assert_array_equal(u32(got), lut)
+    ref = sb.Style(st.rgb, st.guide, st.lut_bits)
+    ex = torch.as_tensor(DevView(s.rgba, ref.rgba.numel()), device="cuda")
+    assert torch.equal(ex, ref.rgba)
+
+    class Owned:  # the binding's Style interface over the library-owned struct
+        c = s
+        fmt = st.fmt
+
+    e_rgb, e_chunk, e_nnf = oracle.stylize(st.rgb, st.guide, lut, st.lut_bits, fr.guide, None,
+                                           p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
+    rgb, chunk, nnf = sb.stylize(Owned, fr.guide, None,
+                                 sb.params(p.levels, p.finest, p.threshold, p.radius, seed=fr.seed),
+                                 want_nnf=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u32(chunk), e_chunk)
+    np.testing.assert_array_equal(u32(nnf), e_nnf)
+    np.testing.assert_array_equal(to_np(rgb), e_rgb)
+    assert sb.lib().sb_style_destroy(h) == sb.SB_OK

@@ -27,19 +27,22 @@ def sb():
 
 
 def check(sb, st, ls, nlabels, tgt_guide, lt, jit, levels, finest, t, r, name, tunes=(None,),
-          style=None):
+          style=None, seed=None):
+    """GPU frame with labels against the oracle; the seeds' jitter is the
+    table ``jit``, else the hash of ``seed``."""
     import torch
 
     luts = oracle.lut_build_labels(st.guide, ls, nlabels, st.lut_bits)
     e_rgb, e_chunk, e_nnf = oracle.stylize_seg(st.rgb, st.guide, ls, luts, nlabels, st.lut_bits,
-                                               tgt_guide, lt, jit, levels, finest, t, r)
+                                               tgt_guide, lt, jit, levels, finest, t, r,
+                                               seed=seed)
     if style is None:
         style = sb.Style(st.rgb, st.guide, st.lut_bits, labels=ls, nlabels=nlabels)
     np.testing.assert_array_equal(style.label_luts.cpu().numpy().view(np.uint32), luts,
                                   err_msg=f"{name}: label tables")
     for tune in tunes:
         say(f"{name} {tgt_guide.shape[1]}x{tgt_guide.shape[0]} L={levels} t={t} r={r} tune={tune}")
-        rgb, chunk, nnf = sb.stylize(style, tgt_guide, jit, sb.params(levels, finest, t, r),
+        rgb, chunk, nnf = sb.stylize(style, tgt_guide, jit, sb.params(levels, finest, t, r, seed),
                                      want_nnf=True, tune=tune, tgt_labels=lt)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(chunk.cpu().numpy().view(np.uint32), e_chunk,
@@ -59,7 +62,7 @@ def test_normal_frame_all_tunes(sb):
     style = None
     for t in (p.threshold, 600):
         style = check(sb, st, ls, 3, fr.guide, lt, fr.jitter, p.levels, p.finest, t, p.radius,
-                      "normal 256", tunes=[None] + list(sb.TUNES), style=style)
+                      "normal 256", tunes=[None] + list(sb.TUNES), style=style, seed=fr.seed)
 
 
 def test_uv_frame_with_absent_label(sb):
@@ -102,11 +105,13 @@ def test_random_small(sb, seed):
     finest = int(2 ** rng.integers(0, 5))
     while levels and finest << (levels - 1) > 8192:
         levels -= 1
-    jit = workloads.jitter_table(w, h, levels, finest, seed)
+    # half the cases take their seeds from the jitter hash
+    hseed = 31 * seed + 5 if seed % 2 == 0 else None
+    jit = None if hseed is not None else workloads.jitter_table(w, h, levels, finest, seed)
     t = int(rng.integers(0, 8 * scale))
     r = int(rng.integers(0, 8))
     check(sb, st, ls, nl, gt, lt, jit, levels, finest, t, r, f"seg random {seed} u16={u16}",
-          tunes=[None, (2, 8, 4, 1)])
+          tunes=[None, (2, 8, 4, 1)], seed=hseed)
 
 
 @pytest.mark.parametrize("u16,levels", [(False, 9), (True, 10)])
@@ -137,7 +142,7 @@ def test_one_label_equals_plain(sb):
     styles, frames = workloads.config(1)
     st, fr = styles[0], frames[0]
     p = fr.params
-    prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
     zs = np.zeros(st.guide.shape[:2], np.uint8)
     zt = np.zeros(fr.guide.shape[:2], np.uint8)
     say("one label vs plain")

@@ -1,10 +1,11 @@
 """Serving on the GPU: a Poisson request trace through the native request
 loop (memory-budget admission, continuous batching over several streams).
 Each request's result in the mix must equal the same request stylised alone
-(tolerance 0: the outputs are integers)."""
+and, for a sample, the oracle (tolerance 0: the outputs are integers)."""
 import numpy as np
 import pytest
 
+import oracle
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -27,7 +28,10 @@ def env():
     return sb, sv, trace, styles
 
 
-def make_requests(env, explicit_outputs, n=None):
+def make_requests(env, explicit_outputs, n=None, burst=False):
+    """Requests of the trace: every fourth with its own jitter table, the
+    rest with their own jitter hash seed.  ``burst``: all arrive at once, so
+    the free slots take batches of several requests and run side by side."""
     import torch
 
     sb, sv, trace, styles = env
@@ -45,15 +49,20 @@ def make_requests(env, explicit_outputs, n=None):
         g = guides[key]
         h, w = int(g.shape[0]), int(g.shape[1])
         p = trace["params"][fmt]
-        jit = workloads.jitter_table(w, h, p.levels, p.finest, 9000 + i)
-        jt = torch.from_numpy(jit.view(np.int32)).cuda()
-        prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
+        if i % 4 == 0:
+            jit = workloads.jitter_table(w, h, p.levels, p.finest, 9000 + i)
+            jt = torch.from_numpy(jit.view(np.int32)).cuda()
+            prm = sb.params(p.levels, p.finest, p.threshold, p.radius)
+        else:
+            jt = None
+            prm = sb.params(p.levels, p.finest, p.threshold, p.radius,
+                            seed=int(trace["seeds"][i]))
         out_rgb = out_chunk = None
         if explicit_outputs:
             out_rgb = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
             out_chunk = torch.empty((h, w), dtype=torch.int32, device="cuda")
-        reqs.append(sv.Request(float(trace["arrivals"][i]), styles[st], g, jt, prm, out_rgb,
-                               out_chunk))
+        arrival = 0.0 if burst else float(trace["arrivals"][i])
+        reqs.append(sv.Request(arrival, styles[st], g, jt, prm, out_rgb, out_chunk))
     return reqs
 
 
@@ -65,16 +74,23 @@ def alone(sb, r):
     return rgb.cpu().numpy(), chunk.cpu().numpy()
 
 
-@pytest.mark.parametrize("plain", [False, True])
-def test_each_result_same_alone_and_in_mix(env, plain):
+@pytest.mark.parametrize("plain,burst", [(False, False), (False, True), (True, False)])
+def test_each_result_same_alone_and_in_mix(env, plain, burst):
     sb, sv, trace, styles = env
-    reqs = make_requests(env, explicit_outputs=True)
-    say(f"serve {len(reqs)} requests plain={plain}")
+    reqs = make_requests(env, explicit_outputs=True, burst=burst)
+    say(f"serve {len(reqs)} requests plain={plain} burst={burst}")
     out = sv.run(reqs, slots=3, max_batch=8, budget_bytes=1 << 30, plain=plain)
     assert np.all(out["status"] == sb.SB_OK)
     assert np.all(out["completed"] >= out["arrival"])
-    if not plain:
-        assert out["batch_size"].max() >= 1
+    if burst:
+        # continuous batching really ran: batches of several requests, and
+        # two slots' batches in flight at the same time
+        assert out["batch_size"].max() > 1
+        assert len(np.unique(out["batch"][out["batch_size"] > 1])) >= 2
+        sl, la, co = out["slot"], out["launched"], out["completed"]
+        overlap = any(sl[i] != sl[j] and la[i] < co[j] and la[j] < co[i]
+                      for i in range(len(reqs)) for j in range(i + 1, len(reqs)))
+        assert overlap, "no two slots were busy at once"
     for i, r in enumerate(reqs):
         rgb, chunk = alone(sb, r)
         np.testing.assert_array_equal(r.out_rgb.cpu().numpy(), rgb, err_msg=f"request {i}")
@@ -150,3 +166,36 @@ def test_mixed_guides_labels_and_sessions(env):
         assert torch.equal(r.out_rgb, rgb), f"request {i}"
         assert torch.equal(r.out_chunk, chunk), f"request {i}"
         assert torch.equal(r.out_nnf, nnf), f"request {i}"
+
+
+def test_served_results_match_oracle(env):
+    """A burst through the batched loop; a sample of the served frames (both
+    guide formats, every size, table and hash jitter) against the oracle."""
+    sb, sv, trace, styles = env
+    reqs = make_requests(env, explicit_outputs=True, burst=True)
+    say(f"serve {len(reqs)} requests in a burst, sample against the oracle")
+    out = sv.run(reqs, slots=3, max_batch=8, budget_bytes=1 << 30)
+    assert np.all(out["status"] == sb.SB_OK)
+    assert out["batch_size"].max() > 1
+    picked = {}
+    for i in range(len(reqs)):
+        key = (int(trace["size_idx"][i]), trace["styles"][int(trace["style_idx"][i])].fmt, i % 4 == 0)
+        picked.setdefault(key, i)
+    luts = {}
+    for i in sorted(picked.values()):
+        r = reqs[i]
+        st_i = int(trace["style_idx"][i])
+        st = trace["styles"][st_i]
+        p = trace["params"][st.fmt]
+        g = trace["guides"][(int(trace["size_idx"][i]), st.fmt, int(trace["pool_idx"][i]))]
+        jit = r.jitter.cpu().numpy().view(np.uint32) if r.jitter is not None else None
+        seed = None if r.jitter is not None else int(trace["seeds"][i])
+        if st_i not in luts:
+            luts[st_i] = oracle.lut_build(st.guide, st.lut_bits)
+        say(f"oracle request {i} {r.w}x{r.h} fmt={st.fmt} table={jit is not None} "
+            f"batch_size={out['batch_size'][i]}")
+        e_rgb, e_chunk, _ = oracle.stylize(st.rgb, st.guide, luts[st_i], st.lut_bits, g, jit,
+                                           p.levels, p.finest, p.threshold, p.radius, seed=seed)
+        np.testing.assert_array_equal(r.out_chunk.cpu().numpy().view(np.uint32), e_chunk,
+                                      err_msg=f"request {i} chunk")
+        np.testing.assert_array_equal(r.out_rgb.cpu().numpy(), e_rgb, err_msg=f"request {i} rgb")

@@ -24,7 +24,7 @@ def env():
     st, fr = styles[0], frames[0]
     style = sb.Style(st.rgb, st.guide, st.lut_bits)
     p = fr.params
-    return sb, style, fr, sb.params(p.levels, p.finest, p.threshold, p.radius)
+    return sb, style, fr, sb.params(p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
 
 
 def test_timed_entry_matches_plain_and_orders_events(env):
@@ -70,7 +70,7 @@ def test_tune_batch_picks_an_exact_choice(env, tmp_path):
     for f in frames_np:
         p = f.params
         jobs.append(sb.FrameJob(styles[f.style], f.guide, f.jitter,
-                                sb.params(p.levels, p.finest, p.threshold, p.radius)))
+                                sb.params(p.levels, p.finest, p.threshold, p.radius, seed=f.seed)))
     say(f"tune_batch over {len(jobs)} frames")
     r = at.tune_batch(jobs, candidates=[(4, 16, 2, 1), (2, 8, 4, 2)], blocks_per_cu=(2, 8), reps=2,
                       cache_path=str(tmp_path / "tune.json"))

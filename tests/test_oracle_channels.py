@@ -236,3 +236,43 @@ def test_weights_are_validated():
         oracle.lut_build(workloads.sphere_guide_u8(16), 3, (2, 1, 1))  # two channels: unit only
     np.testing.assert_array_equal(oracle.lut_build(workloads.sphere_guide_u8(16), 3, (1, 1, 1)),
                                   oracle.lut_build(workloads.sphere_guide_u8(16), 3))
+
+
+@pytest.mark.parametrize("fmt,case", [(2, 0), (2, 1), (2, 2), (0, 0), (0, 1), (1, 0), (1, 1)])
+def test_lut_query_sweep_equals_definition(fmt, case):
+    """The channel-0 sweep returns exactly the brute-force argmin (the
+    definition, lut_query) on small random sources with many ties (few
+    distinct values), for every guide format, with unit and with skewed
+    channel weights (channel-0 weight 0 turns the stopping bound off)."""
+    rng = np.random.default_rng(100 * fmt + case)
+    sh, sw = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+    if fmt == 2:
+        src = np.zeros((sh, sw, 4), np.uint8)
+        src[..., :3] = rng.choice(np.array([0, 7, 100, 101, 255], np.uint8), (sh, sw, 3))
+        src[..., 3] = rng.integers(0, 256, (sh, sw))
+        bits = int(rng.integers(1, 9))
+        nb = 1 << (3 * bits)
+        weights = [None, (0, 3, 1), (127, 1, 9)][case]
+    elif fmt == 0:
+        src = rng.choice(np.array([3, 4, 200, 201], np.uint8), (sh, sw, 2))
+        bits = int(rng.integers(1, 9))
+        nb = 1 << (2 * bits)
+        weights = None
+    else:
+        src = rng.choice(np.array([0, 1000, 1001, 65535], np.uint16), (sh, sw, 2))
+        bits = int(rng.integers(1, 13))
+        nb = 1 << (2 * bits)
+        weights = None
+    bins = rng.integers(0, nb, size=min(nb, 600))
+    np.testing.assert_array_equal(oracle.lut_query_sweep(src, bits, bins, weights=weights),
+                                  oracle.lut_query(src, bits, bins, weights=weights))
+
+
+def test_lut_query_sweep_on_appearance_style():
+    """The 512^2 appearance style at 8 bits (the table of the three-channel
+    1080p workload): sampled bins, sweep against the definition."""
+    st = workloads.config(6, w=64, h=64)[0][0]
+    rng = np.random.default_rng(3)
+    bins = rng.integers(0, 1 << 24, size=300)
+    np.testing.assert_array_equal(oracle.lut_query_sweep(st.guide, 8, bins),
+                                  oracle.lut_query(st.guide, 8, bins))

@@ -8,10 +8,19 @@ import os
 import numpy as np
 import pytest
 
+import oracle
 import workloads
 from tests.test_oracle_lut import brute_lut
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")))
+
+
+def frame_jitter(fr):
+    """A workload frame's jitter table: its own, or the one the jitter hash
+    of its seed defines."""
+    if fr.jitter is not None:
+        return fr.jitter
+    return oracle.jitter_hash(fr.w, fr.h, fr.params.levels, fr.params.finest, fr.seed)
 
 
 def grid_guide(w, h):
@@ -214,9 +223,9 @@ def test_invariants_workload1(ora):
     st, fr = styles[0], frames[0]
     lut = ora.lut_build(st.guide, st.lut_bits)
     p = fr.params
-    _invariants(ora, st.rgb, st.guide, fr.guide, lut, st.lut_bits, fr.jitter, p.levels, p.finest,
+    _invariants(ora, st.rgb, st.guide, fr.guide, lut, st.lut_bits, frame_jitter(fr), p.levels, p.finest,
                 p.threshold, p.radius)
-    _invariants(ora, st.rgb, st.guide, fr.guide, lut, st.lut_bits, fr.jitter, p.levels, p.finest,
+    _invariants(ora, st.rgb, st.guide, fr.guide, lut, st.lut_bits, frame_jitter(fr), p.levels, p.finest,
                 p.threshold, 0)
 
 
@@ -231,7 +240,7 @@ def test_threshold_monotone(ora):
     prev = None
     sizes = []
     for t in (0, 8, 32, 48, 128, 512, 4096):
-        nnf, chunk = ora.assign(st.guide, lut, 8, fr.guide, fr.jitter, p.levels, p.finest, t)
+        nnf, chunk = ora.assign(st.guide, lut, 8, fr.guide, frame_jitter(fr), p.levels, p.finest, t)
         lvl = chunk >> 26
         if prev is not None:
             assert np.all(lvl <= prev)
@@ -246,9 +255,9 @@ def test_row_range_matches_full(ora):
     st, fr = styles[0], frames[0]
     lut = ora.lut_build(st.guide, st.lut_bits)
     p = fr.params
-    nnf, chunk = ora.assign(st.guide, lut, 8, fr.guide, fr.jitter, p.levels, p.finest,
+    nnf, chunk = ora.assign(st.guide, lut, 8, fr.guide, frame_jitter(fr), p.levels, p.finest,
                             p.threshold)
-    nnf2, chunk2 = ora.assign(st.guide, lut, 8, fr.guide, fr.jitter, p.levels, p.finest,
+    nnf2, chunk2 = ora.assign(st.guide, lut, 8, fr.guide, frame_jitter(fr), p.levels, p.finest,
                               p.threshold, rows=(100, 20))
     np.testing.assert_array_equal(nnf2[100:120], nnf[100:120])
     np.testing.assert_array_equal(chunk2[100:120], chunk[100:120])

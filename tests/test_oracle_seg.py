@@ -8,6 +8,14 @@ import oracle
 import workloads
 
 
+def frame_jitter(fr):
+    """A workload frame's jitter table: its own, or the one the jitter hash
+    of its seed defines."""
+    if fr.jitter is not None:
+        return fr.jitter
+    return oracle.jitter_hash(fr.w, fr.h, fr.params.levels, fr.params.finest, fr.seed)
+
+
 def brute_lut_labels(gs, labels, label, lut_bits):
     """argmin over source pixels labelled `label` of the squared distance to
     each bin centre, ties to the smallest raster index; None if none."""
@@ -39,9 +47,9 @@ def test_one_label_reduces_to_plain_path():
     zt = np.zeros(fr.guide.shape[:2], np.uint8)
     luts = oracle.lut_build_labels(st.guide, zs, 1, st.lut_bits)
     np.testing.assert_array_equal(luts[0], lut)
-    a = oracle.stylize(st.rgb, st.guide, lut, st.lut_bits, fr.guide, fr.jitter, p.levels,
+    a = oracle.stylize(st.rgb, st.guide, lut, st.lut_bits, fr.guide, frame_jitter(fr), p.levels,
                        p.finest, p.threshold, p.radius)
-    b = oracle.stylize_seg(st.rgb, st.guide, zs, luts, 1, st.lut_bits, fr.guide, zt, fr.jitter,
+    b = oracle.stylize_seg(st.rgb, st.guide, zs, luts, 1, st.lut_bits, fr.guide, zt, frame_jitter(fr),
                            p.levels, p.finest, p.threshold, p.radius)
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x, y)
@@ -97,7 +105,7 @@ def test_label_invariants_on_a_frame():
     luts = oracle.lut_build_labels(st.guide, ls, 3, st.lut_bits)
     for t in (48, 400, 4000):
         _, chunk, nnf = oracle.stylize_seg(st.rgb, st.guide, ls, luts, 3, st.lut_bits, fr.guide,
-                                           lt, fr.jitter, p.levels, p.finest, t, p.radius)
+                                           lt, frame_jitter(fr), p.levels, p.finest, t, p.radius)
         vx, vy = (nnf & 0xFFFF).astype(np.int64), (nnf >> 16).astype(np.int64)
         got = ls[vy, vx]
         # every pixel, accepted or fallen back, lands on a source pixel of its

@@ -61,13 +61,15 @@ class Params:
 
 @dataclasses.dataclass
 class Frame:
-    """One target: its guide G_T, jitter table, parameters and style index."""
+    """One target: its guide G_T, the source of its seeds' jitter (a table,
+    or the seed of the jitter hash), parameters and style index."""
 
     guide: np.ndarray  # (H, W, 2)
     fmt: int
-    jitter: np.ndarray  # uint32, concatenated per-level tables
+    jitter: Optional[np.ndarray]  # uint32 per-level tables, or None: the hash of `seed`
     params: Params
     style: int = 0
+    seed: Optional[int] = None  # jitter hash seed when `jitter` is None
 
     @property
     def w(self) -> int:
@@ -357,10 +359,10 @@ def appearance_target(w: int, h: int, nbumps: int, seed: int) -> np.ndarray:
                       appearance_u8(value_noise_rgb(w, h, seed + 1), 4))
 
 
-def _frame(guide: np.ndarray, fmt: int, p: Params, jseed: Optional[int], style: int = 0) -> Frame:
-    h, w = guide.shape[:2]
-    return Frame(np.ascontiguousarray(guide), fmt, jitter_table(w, h, p.levels, p.finest, jseed),
-                 p, style)
+def _frame(guide: np.ndarray, fmt: int, p: Params, seed: int, style: int = 0) -> Frame:
+    """A workload frame whose seeds' jitter is the integer hash of (cell,
+    level, seed): no table travels with it."""
+    return Frame(np.ascontiguousarray(guide), fmt, None, p, style, seed)
 
 
 def config(n: int, **kw):
@@ -423,6 +425,8 @@ def config(n: int, **kw):
             "size_idx": size_idx,
             "style_idx": style_idx,
             "pool_idx": pool_idx,
+            # every request's own jitter hash seed (a fresh seed pattern per frame)
+            "seeds": 7000 + np.arange(nreq),
             "params": {GUIDE_U8X2: NORMAL_PARAMS, GUIDE_U16X2: UV_PARAMS},
         }
     if n == 6:
