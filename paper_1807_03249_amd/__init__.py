@@ -240,7 +240,7 @@ class Style:
     channels' squared differences in the table and in the error test (the
     strong or weak appearance guide); None means unit weights."""
 
-    def __init__(self, rgb, guide, lut_bits: int, stream=None, labels=None,
+    def __init__(self, rgb, guide, lut_bits: int, labels=None,
                  nlabels: Optional[int] = None, weights=None):
         torch = _torch()
         self.rgb = _dev(torch, rgb)
@@ -256,7 +256,9 @@ class Style:
             raise ValueError("exemplar and guide sizes differ")
         self.lut_bits = int(lut_bits)
         L = lib()
-        s = _stream(torch) if stream is None else stream
+        # every temporary below is allocated on, and used by, torch's current
+        # stream, so the caching allocator never hands it to other work early
+        s = _stream(torch)
         # padded RGBA exemplar (zero margins, alpha 1 inside), see sb_exemplar_texels
         self.rgba = torch.empty(int(L.sb_exemplar_texels(self.sw, self.sh)), dtype=torch.int32,
                                 device="cuda")
@@ -312,12 +314,13 @@ def workspace_bytes(w: int, h: int, p: SbParams) -> int:
 
 
 def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chunk=None,
-            want_nnf: bool = False, workspace=None, stream=None, tune=None, events=None,
+            want_nnf: bool = False, workspace=None, tune=None, events=None,
             tgt_labels=None):
     """Stylise one frame.  ``tgt_guide`` (H, W, 2) or (H, W, 4) and ``jitter`` (uint32 as
     int32 bits) may be numpy arrays or device tensors.  Returns
     ``(rgb (H,W,3) uint8, chunk (H,W) int32-bits[, nnf])`` as device tensors;
-    the work is enqueued on the current stream.  ``tune`` is a
+    the work is enqueued on torch's current stream, the stream every
+    temporary here is allocated on.  ``tune`` is a
     (blend_ppt, blend_rows, level_group, level_ppt) choice (None = defaults); with
     ``events`` (a TimingEvents) the passes are bracketed by its events
     (sb_stylize_timed).  With ``tgt_labels`` (uint8 (H, W)) the frame runs
@@ -336,13 +339,17 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
         out_rgb = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
     if out_chunk is None:
         out_chunk = torch.empty((h, w), dtype=torch.int32, device="cuda")
-    if out_rgb.numel() != h * w * 3 or out_rgb.dtype != torch.uint8 or out_chunk.numel() != h * w:
+    if out_rgb.numel() != h * w * 3 or out_rgb.dtype != torch.uint8 or out_chunk.numel() != h * w \
+            or out_chunk.element_size() != 4:
         raise ValueError("output tensors do not match the frame size")
+    if not (out_rgb.is_cuda and out_chunk.is_cuda and out_rgb.is_contiguous()
+            and out_chunk.is_contiguous()):
+        raise ValueError("output tensors must be contiguous device tensors")
     nnf = torch.empty((h, w), dtype=torch.int32, device="cuda") if want_nnf else None
     wsb = workspace_bytes(w, h, p)
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device="cuda")
-    s = _stream(torch) if stream is None else stream
+    s = _stream(torch)
     tn = tune_struct(tune)
     tp = ctypes.byref(tn) if tn is not None else None
     nnf_p = nnf.data_ptr() if nnf is not None else None
@@ -513,7 +520,9 @@ class Batch:
             raise StyleBlitError(SB_EINVAL, "sb_batch_workspace_bytes")
         return int(n)
 
-    def run(self, jobs, workspace=None, stream=None):
+    def run(self, jobs, workspace=None):
+        """Enqueue the batch on torch's current stream (where the workspace
+        is allocated too)."""
         torch = _torch()
         arr = (SbFrame * len(jobs))(*[j.c() for j in jobs])
         wsb = lib().sb_batch_workspace_bytes(arr, len(jobs))
@@ -521,7 +530,7 @@ class Batch:
             raise StyleBlitError(SB_EINVAL, "sb_batch_workspace_bytes")
         if workspace is None:
             workspace = torch.empty(wsb, dtype=torch.uint8, device="cuda")
-        s = _stream(torch) if stream is None else stream
+        s = _stream(torch)
         _check(lib().sb_batch_run(self.handle, arr, len(jobs), workspace.data_ptr(), wsb, s),
                "sb_batch_run")
         # keep this run's tensors alive until its descriptor half is reused
