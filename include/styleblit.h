@@ -248,6 +248,34 @@ int sb_stylize(const sb_style *style, const void *tgt_guide, int32_t w, int32_t 
                uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
                hipStream_t stream);
 
+/* Bytes of the library's static per-device scratch (40 MiB): the largest
+ * sb_workspace_bytes() that sb_stylize_noalloc accepts, enough for a
+ * 3840 x 2160 frame with finest spacing 8 (about 34.6 MB). */
+#define SB_NOALLOC_SCRATCH_BYTES 41943040u
+
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): sb_stylize without the workspace argument, bit-identical to
+ * it.  The seed table and offset map live in a static array of
+ * SB_NOALLOC_SCRATCH_BYTES bytes that the library holds on every device it
+ * runs on until the process ends; this call allocates nothing (no hipMalloc,
+ * no hipFree).  Its device address is looked up on the first call on each
+ * device, so the device current at the call must be the one `stream` runs
+ * on.  Every call on one device shares that device's array and keeps the
+ * last call's contents (nothing in it needs clearing: each call writes every
+ * byte it reads before reading it), so calls whose work overlaps on one
+ * device -- on two streams, or from two threads without ordering -- race
+ * and must be serialised by the caller.
+ * Returns SB_ENOMEM (with sb_last_hip_error() naming the sizes) when
+ * sb_workspace_bytes(w, h, params) exceeds SB_NOALLOC_SCRATCH_BYTES,
+ * SB_EINVAL as sb_stylize, SB_EHIP if the address lookup or a launch fails;
+ * nothing is enqueued on an error. */
+int sb_stylize_noalloc(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+                       const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+                       uint32_t *out_chunk, uint32_t *out_nnf, hipStream_t stream);
+/* SB_NOALLOC_SCRATCH_BYTES, for bindings that cannot read the macro. */
+size_t sb_noalloc_scratch_bytes(void);
+
 /* Kernel choice.  Every choice computes the same result bit for bit; they
  * differ only in speed, so an autotuner may pick any.  0 in a field takes the
  * library's default.

@@ -130,6 +130,9 @@ def lib():
     L.sb_jitter_fill.argtypes = [i32, i32, i32, i32, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
     L.sb_style_create.argtypes = [vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(vp)]
     L.sb_style_destroy.argtypes = [vp]
+    L.sb_stylize_noalloc.argtypes = [ctypes.POINTER(SbStyle), vp, i32, i32, vp,
+                                     ctypes.POINTER(SbParams), vp, vp, vp, vp]
+    L.sb_noalloc_scratch_bytes.restype = sz
     L.sb_change_workspace_bytes.restype = sz
     L.sb_frame_change.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp, sz, vp]
     _lib = L
@@ -379,6 +382,42 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     if want_nnf:
         return out_rgb, out_chunk, nnf
     return out_rgb, out_chunk
+
+
+def stylize_noalloc(style: Style, tgt_guide, jitter, p: SbParams, out_rgb, out_chunk,
+                    out_nnf=None):
+    """Stylise one frame through sb_stylize_noalloc (no workspace: the
+    library's static scratch).  ``tgt_guide``, ``jitter`` and the outputs must
+    already be contiguous device tensors (nothing is allocated here either);
+    the work is enqueued on torch's current stream."""
+    torch = _torch()
+    for t in (tgt_guide, out_rgb, out_chunk) + ((out_nnf,) if out_nnf is not None else ()):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("stylize_noalloc takes contiguous device tensors only")
+    if _guide_fmt(torch, tgt_guide) != style.fmt:
+        raise TypeError("target guide format differs from the style's guide format")
+    h, w = int(tgt_guide.shape[0]), int(tgt_guide.shape[1])
+    if out_rgb.numel() != h * w * 3 or out_rgb.dtype != torch.uint8 or out_chunk.numel() != h * w \
+            or out_chunk.element_size() != 4:
+        raise ValueError("output tensors do not match the frame size")
+    if out_nnf is not None and (out_nnf.numel() != h * w or out_nnf.element_size() != 4):
+        raise ValueError("nnf tensor does not match the frame size")
+    jp = None
+    if jitter is not None:
+        if not isinstance(jitter, torch.Tensor) or not jitter.is_cuda or jitter.element_size() != 4:
+            raise ValueError("stylize_noalloc takes a device jitter table")
+        p = _with_table(p)
+        jp = jitter.data_ptr()
+    _check(lib().sb_stylize_noalloc(ctypes.byref(style.c), tgt_guide.data_ptr(), w, h, jp,
+                                    ctypes.byref(p), out_rgb.data_ptr(), out_chunk.data_ptr(),
+                                    out_nnf.data_ptr() if out_nnf is not None else None,
+                                    _stream(torch)), "sb_stylize_noalloc")
+    return out_rgb, out_chunk
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of the static scratch behind sb_stylize_noalloc (bytes)."""
+    return int(lib().sb_noalloc_scratch_bytes())
 
 
 def jitter_fill(w: int, h: int, levels: int, finest: int, seed: int, stream_id: int = 0,

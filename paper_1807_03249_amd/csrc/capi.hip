@@ -276,12 +276,14 @@ size_t sb_workspace_bytes(int32_t w, int32_t h, const sb_params *params) {
   return align256(size_t(lv.poffset[lv.count]) * 8) + align256(size_t(w) * size_t(h) * 4);
 }
 
-namespace {
+}  // extern "C"
+
+namespace sb {
 int stylize_impl(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
                  const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
                  uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
                  const sb_tune *tune, hipEvent_t *events, hipStream_t stream,
-                 const uint8_t *tgt_labels = nullptr) {
+                 const uint8_t *tgt_labels) {
   FrameArgs a;
   if (!fill_frame(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf, &a,
                   tgt_labels))
@@ -298,14 +300,16 @@ int stylize_impl(const sb_style *style, const void *tgt_guide, int32_t w, int32_
   }
   return SB_OK;
 }
-}  // namespace
+}  // namespace sb
+
+extern "C" {
 
 int sb_stylize_ex(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
                   const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
                   uint32_t *out_chunk, uint32_t *out_nnf, void *workspace,
                   size_t workspace_bytes, const sb_tune *tune, hipStream_t stream) {
   return stylize_impl(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf,
-                      workspace, workspace_bytes, tune, nullptr, stream);
+                      workspace, workspace_bytes, tune, nullptr, stream, nullptr);
 }
 
 int sb_stylize_seg(const sb_style *style, const void *tgt_guide, const uint8_t *tgt_labels,
@@ -324,7 +328,7 @@ int sb_stylize_timed(const sb_style *style, const void *tgt_guide, int32_t w, in
                      hipStream_t stream) {
   if (!events || !events[0] || !events[1] || !events[2] || !events[3]) return SB_EINVAL;
   return stylize_impl(style, tgt_guide, w, h, jitter, params, out_rgb, out_chunk, out_nnf,
-                      workspace, workspace_bytes, tune, events, stream);
+                      workspace, workspace_bytes, tune, events, stream, nullptr);
 }
 
 int sb_timing_events_create(hipEvent_t events[4]) {

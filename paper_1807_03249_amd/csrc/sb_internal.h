@@ -159,6 +159,15 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
 // sb_workspace_bytes() bytes.
 void carve_workspace(FrameArgs *a, void *workspace);
 
+// One frame through the per-frame kernels after validation (the body of the
+// sb_stylize family): SB_EINVAL / SB_ENOMEM before anything is enqueued,
+// SB_EHIP if a launch fails.  events: NULL, or 4 events bracketing the passes.
+int stylize_impl(const sb_style *style, const void *tgt_guide, int32_t w, int32_t h,
+                 const uint32_t *jitter, const sb_params *params, uint8_t *out_rgb,
+                 uint32_t *out_chunk, uint32_t *out_nnf, void *workspace, size_t workspace_bytes,
+                 const sb_tune *tune, hipEvent_t *events, hipStream_t stream,
+                 const uint8_t *tgt_labels);
+
 // Thread-local error text of the last failed HIP call.
 void set_hip_error(hipError_t e, const char *where);
 void set_error_text(const char *msg);

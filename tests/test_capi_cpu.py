@@ -264,3 +264,29 @@ def test_params_layout_and_jitter_modes(L):
     assert h.jitter == sb.JITTER_HASH and h.seed == 5
     assert sb.params(4, 8, 32, 3).jitter == sb.JITTER_NONE
     assert sb._with_table(h).jitter == sb.JITTER_TABLE
+
+
+def test_noalloc_rejects_frames_beyond_the_static_scratch(L):
+    """sb_stylize_noalloc refuses, before any device call, a frame whose
+    workspace exceeds the static scratch; the limit is what the header says."""
+    import paper_1807_03249_amd as sb
+
+    cap = sb.noalloc_scratch_bytes()
+    assert cap == 41943040
+    p = sb.params(5, 8, 4096, 3, seed=1)
+    assert sb.workspace_bytes(3840, 2160, p) <= cap  # a 4K UHD frame fits
+    fake = ctypes.c_void_p(0x1000)
+    st = sb.SbStyle(fake, fake, fake, 512, 512, 0, 8)
+    big = sb.params(4, 8, 32, 3, seed=1)
+    assert sb.workspace_bytes(8192, 8192, big) > cap
+    rc = L.sb_stylize_noalloc(ctypes.byref(st), fake, 8192, 8192, None, ctypes.byref(big),
+                              fake, fake, None, None)
+    assert rc == sb.SB_ENOMEM
+    msg = L.sb_last_hip_error().decode()
+    assert "8192x8192" in msg and str(cap) in msg
+    # invalid arguments stay SB_EINVAL (radius 8 has no workspace size at all)
+    bad = sb.params(4, 8, 32, 8, seed=1)
+    assert L.sb_stylize_noalloc(ctypes.byref(st), fake, 64, 64, None, ctypes.byref(bad),
+                                fake, fake, None, None) == sb.SB_EINVAL
+    assert L.sb_stylize_noalloc(ctypes.byref(st), None, 64, 64, None, ctypes.byref(big),
+                                fake, fake, None, None) == sb.SB_EINVAL
