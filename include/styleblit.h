@@ -287,12 +287,17 @@ size_t sb_noalloc_scratch_bytes(void);
  *   level_group  levels of Algorithm 2 whose source-guide gathers are in
  *                flight together before their tests: 2 or 4 (default 2)
  *   level_ppt    pixels per thread of the level loop (horizontally adjacent
- *                8x8 blocks per wave): 1 or 2 (default 2) */
+ *                8x8 blocks per wave): 1 or 2 (default 2)
+ *   blend_split  2: the voting pass copies the texel of every pixel group
+ *                whose whole window holds one offset (their exact average)
+ *                and votes the other groups from a per-tile list; 1: every
+ *                group votes in place (default 2) */
 typedef struct {
     int32_t blend_ppt;
     int32_t blend_rows;
     int32_t level_group;
     int32_t level_ppt;
+    int32_t blend_split;
 } sb_tune;
 
 /* sb_stylize with an explicit kernel choice (tune may be NULL = defaults);

@@ -40,23 +40,25 @@ class SbStyle(ctypes.Structure):
 
 class SbTune(ctypes.Structure):
     _fields_ = [("blend_ppt", ctypes.c_int32), ("blend_rows", ctypes.c_int32),
-                ("level_group", ctypes.c_int32), ("level_ppt", ctypes.c_int32)]
+                ("level_group", ctypes.c_int32), ("level_ppt", ctypes.c_int32),
+                ("blend_split", ctypes.c_int32)]
 
 
-# every kernel choice (blend_ppt, blend_rows, level_group, level_ppt); all
-# compute the same bits, (0, 0, 0, 0) is the library default
-TUNES = [(ppt, rows, grp, lpx) for ppt in (4, 2) for rows in (16, 8) for grp in (2, 4)
-         for lpx in (1, 2)]
+# every kernel choice (blend_ppt, blend_rows, level_group, level_ppt, blend_split); all
+# compute the same bits, (0, 0, 0, 0, 0) is the library default
+TUNES = [(ppt, rows, grp, lpx, split) for ppt in (4, 2) for rows in (16, 8) for grp in (2, 4)
+         for lpx in (1, 2) for split in (2, 1)]
 
 
 def tune_struct(tune) -> Optional[SbTune]:
-    """SbTune from a (blend_ppt, blend_rows, level_group, level_ppt) tuple
-    (None stays None; a shorter tuple leaves the rest at their defaults)."""
+    """SbTune from a (blend_ppt, blend_rows, level_group, level_ppt,
+    blend_split) tuple (None stays None; a shorter tuple leaves the rest at
+    their defaults)."""
     if tune is None:
         return None
     if isinstance(tune, SbTune):
         return tune
-    vals = [int(v) for v in tune] + [0] * (4 - len(tune))
+    vals = [int(v) for v in tune] + [0] * (5 - len(tune))
     return SbTune(*vals)
 
 

@@ -1,8 +1,8 @@
 """Autotuner for the kernel choices of single frames and batches.
 
-Every choice (``sb_tune``: vote pixels per thread and tile rows, levels per
-gather round; for batches also the persistent grid's blocks per compute
-unit) computes the same bits, so the tuner may pick any of them.  It times
+Every choice (``sb_tune``: vote pixels per thread, tile rows and uniform-window
+split, levels per gather round and blocks per wave; for batches also the
+persistent grid's blocks per compute unit) computes the same bits, so the tuner may pick any of them.  It times
 each candidate on the caller's own work with HIP events, keeps only
 candidates whose outputs equal the default choice's bit for bit, and caches
 the winner in a JSON file keyed by the device name and a signature of the
@@ -23,7 +23,9 @@ BATCH_BLOCKS_PER_CU = (2, 4, 8, 16)
 
 
 def _device_name(torch) -> str:
-    return torch.cuda.get_device_name(0)
+    # the tag changes whenever the set of kernel choices does, so cached
+    # winners of an older set are never read back
+    return torch.cuda.get_device_name(0) + "|choices5"
 
 
 def _load(path: str) -> Dict[str, dict]:

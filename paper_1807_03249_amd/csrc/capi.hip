@@ -143,6 +143,7 @@ bool resolve_tune(const sb_tune *in, Tune *out) {
   out->rows = 8;
   out->group = 2;
   out->apx = 2;
+  out->split = 2;
   if (!in) return true;
   if (in->blend_ppt != 0) {
     if (in->blend_ppt != 2 && in->blend_ppt != 4) return false;
@@ -159,6 +160,10 @@ bool resolve_tune(const sb_tune *in, Tune *out) {
   if (in->level_ppt != 0) {
     if (in->level_ppt != 1 && in->level_ppt != 2) return false;
     out->apx = in->level_ppt;
+  }
+  if (in->blend_split != 0) {
+    if (in->blend_split != 1 && in->blend_split != 2) return false;
+    out->split = in->blend_split;
   }
   return true;
 }

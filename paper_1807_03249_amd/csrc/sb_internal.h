@@ -46,9 +46,10 @@ constexpr int32_t kBlendMaxTW = 64, kBlendMaxTH = 16;
 
 // A resolved kernel choice (see sb_tune): pixels per thread and tile rows of
 // the vote pass, levels per gather round and pixels per thread of the level
-// loop.
+// loop, and whether the vote copies uniform windows and lists the rest
+// (split = 2) or votes every pixel in place (1).
 struct Tune {
-  int32_t ppt, rows, group, apx;
+  int32_t ppt, rows, group, apx, split;
 };
 // Fill a Tune from the caller's sb_tune (NULL or 0 fields = defaults); false
 // if a field holds an unsupported value.

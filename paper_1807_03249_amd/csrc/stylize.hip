@@ -612,69 +612,46 @@ __device__ __forceinline__ void vote_row(const SB_GLOBAL unsigned char *ex, uint
   vote_sum<R, PPT, C>(cells, row, S, RB);
 }
 
-// One (16 PPT) x TH pixel voting tile with 16 TH threads: thread t votes for
-// PPT horizontally adjacent pixels.  `lin` is LDS for blend_words words: an
-// unused row, then blend_lw x blend_lh cells; cell n holds 4 * (oy * P + ox) for its offset o = NNF[n] - n and the
-// padded exemplar's row length P: a vote of n for pixel p is the texel at
-// p's own padded position plus that many bytes.  Cells outside the target
-// hold the distance to the exemplar's zero rows instead, so their votes read
-// zeros, which count for nothing (alpha 0).  Pixel p's average is
-// (sum + floor(k/2)) / k per channel over its k in-source votes, the vote
-// rule at the end of Sec. 3.2.  Ends with all threads past their last LDS
-// read (callers that reuse `lin` synchronise before refilling it).
-template <int R, int PPT, int TH>
-__device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t tid,
-                                  int32_t *lin) {
-  constexpr int32_t TW = 16 * PPT, NT = 16 * TH;
-  constexpr int32_t LW = blend_lw(TW, R), LH = blend_lh(TH, R);
-  static_assert(TW <= kBlendMaxTW && TH <= kBlendMaxTH, "tile exceeds the exemplar zero rows");
-  const uint32_t tiles_x = (uint32_t(a.w) + TW - 1) / TW;
-  const int32_t X0 = int32_t(t_index % tiles_x) * TW;
-  const int32_t Y0 = int32_t(t_index / tiles_x) * TH;
-  const int32_t P = a.ex_stride;
-  const int32_t zero_rel = int32_t(a.ex_zero) - ((Y0 + kExMargin) * P + (X0 + kExMargin));
-  // the tile's cells in runs of 4 along a row (LW is a multiple of 4), one
-  // dword-aligned 16-byte load per run and every thread's runs requested
-  // together; a run reaching past the target (border tiles only) reads its
-  // cells one by one, and cells outside the target take zero_rel
-  constexpr int32_t QW = LW / 4, NCH = QW * LH, CPER = (NCH + NT - 1) / NT;
-  static_assert(LW % 4 == 0, "tile rows are whole runs of 4 cells");
-  u32x4a4 run[CPER];
-  uint32_t inside[CPER];  // bit m: cell m of the run lies in the target
+// Store the RGB of a lane's PPT pixels (c[j] = R | G << 8 | B << 16) at (x, y):
+// one 12-byte (PPT 4) or 6-byte (PPT 2) write when the row holds them all
+// and the address allows, else byte by byte.
+template <int PPT>
+__device__ __forceinline__ void store_rgb(const FrameArgs &a, int32_t x, int32_t y,
+                                          const uint32_t *c) {
+  const uint32_t at = 3u * (__umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x));  // < 2^28
+  SB_GLOBAL uint8_t *o = glb(a.out_rgb) + at;
+  const uint32_t oa = uint32_t(reinterpret_cast<uintptr_t>(a.out_rgb)) + at;  // alignment only
+  if (PPT == 4 && x + 4 <= a.w && (oa & 3) == 0) {
+    u32x3a4 v;
+    v.x = (c[0] & 0xFFFFFFu) | (c[1 % PPT] << 24);
+    v.y = ((c[1 % PPT] >> 8) & 0xFFFFu) | (c[2 % PPT] << 16);
+    v.z = ((c[2 % PPT] >> 16) & 0xFFu) | (c[3 % PPT] << 8);
+    *reinterpret_cast<SB_GLOBAL u32x3a4 *>(o) = v;
+  } else if (PPT == 2 && x + 2 <= a.w && (oa & 1) == 0) {
+    SB_GLOBAL uint16_t *o16 = reinterpret_cast<SB_GLOBAL uint16_t *>(o);
+    o16[0] = uint16_t(c[0]);
+    o16[1] = uint16_t(((c[0] >> 16) & 0xFFu) | (c[1 % PPT] << 8));
+    o16[2] = uint16_t(c[1 % PPT] >> 8);
+  } else {
 #pragma unroll
-  for (int32_t n = 0; n < CPER; ++n) {
-    const int32_t ch = int32_t(tid) + n * NT;
-    const int32_t tx = X0 - R + 4 * (ch % QW), ty = Y0 - R + ch / QW;
-    const bool row_in = ch < NCH && ty >= 0 && ty < a.h;
-    const SB_GLOBAL uint32_t *src =
-        glb(a.offsets) + (row_in ? __umul24(uint32_t(ty), uint32_t(a.w)) : 0u);
-    if (row_in && tx >= 0 && tx + 4 <= a.w) {
-      run[n] = *reinterpret_cast<const SB_GLOBAL u32x4a4 *>(src + tx);
-      inside[n] = 15u;
-    } else {
-      inside[n] = 0u;
-#pragma unroll
-      for (int32_t m = 0; m < 4; ++m) {
-        const bool in = row_in && tx + m >= 0 && tx + m < a.w;
-        run[n][m] = src[in ? uint32_t(tx + m) : 0u];
-        inside[n] |= uint32_t(in) << m;
+    for (int32_t j = 0; j < PPT; ++j) {
+      if (x + j < a.w) {
+        o[3 * j] = uint8_t(c[j]);
+        o[3 * j + 1] = uint8_t(c[j] >> 8);
+        o[3 * j + 2] = uint8_t(c[j] >> 16);
       }
     }
   }
-#pragma unroll
-  for (int32_t n = 0; n < CPER; ++n) {
-    const int32_t ch = int32_t(tid) + n * NT;
-    if (n + 1 < CPER || ch < NCH) {
-      i32x4 v;
-#pragma unroll
-      for (int32_t m = 0; m < 4; ++m)
-        v[m] = 4 * ((inside[n] >> m) & 1u ? __mul24(off_y(run[n][m]), P) + off_x(run[n][m])
-                                           : zero_rel);
-      *reinterpret_cast<i32x4 *>(lin + LW + 4 * ch) = v;
-    }
-  }
-  __syncthreads();
-  const int32_t gx = int32_t(tid & 15), ly = int32_t(tid >> 4);
+}
+
+// The full vote of one lane's PPT pixels (group gx of tile row ly): every
+// window row's gathers and sums, then the average.  `lin` as in blend_tile.
+template <int R, int PPT, int TH>
+__device__ __forceinline__ void vote_group(const FrameArgs &a, int32_t X0, int32_t Y0, int32_t gx,
+                                           int32_t ly, const int32_t *lin) {
+  constexpr int32_t TW = 16 * PPT;
+  constexpr int32_t LW = blend_lw(TW, R);
+  const int32_t P = a.ex_stride;
   const int32_t x = X0 + PPT * gx, y = Y0 + ly;
   const uint32_t pbase =
       4u * (__umul24(uint32_t(y + kExMargin), uint32_t(P)) + uint32_t(x + kExMargin));
@@ -730,46 +707,169 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
            (div_small(((gk >> 8) & 0xFFFFu) + hk, rk, rh) << 8) |
            (div_small((RB[j] >> 16) + hk, rk, rh) << 16);
   }
-  const uint32_t at = 3u * (__umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x));  // < 2^28
-  SB_GLOBAL uint8_t *o = glb(a.out_rgb) + at;
-  const uint32_t oa = uint32_t(reinterpret_cast<uintptr_t>(a.out_rgb)) + at;  // alignment only
-  if (PPT == 4 && x + 4 <= a.w && (oa & 3) == 0) {
-    u32x3a4 v;
-    v.x = c[0] | (c[1 % PPT] << 24);
-    v.y = (c[1 % PPT] >> 8) | (c[2 % PPT] << 16);
-    v.z = (c[2 % PPT] >> 16) | (c[3 % PPT] << 8);
-    *reinterpret_cast<SB_GLOBAL u32x3a4 *>(o) = v;
-  } else if (PPT == 2 && x + 2 <= a.w && (oa & 1) == 0) {
-    SB_GLOBAL uint16_t *o16 = reinterpret_cast<SB_GLOBAL uint16_t *>(o);
-    o16[0] = uint16_t(c[0]);
-    o16[1] = uint16_t((c[0] >> 16) | (c[1 % PPT] << 8));
-    o16[2] = uint16_t(c[1 % PPT] >> 8);
-  } else {
+  store_rgb<PPT>(a, x, y, c);
+}
+
+// Extra LDS words of a voting tile with SPLIT: per window row of the tile
+// one flag byte per lane group (16 per row), the list of groups that need
+// the full vote (one word per thread) and its length.
+__host__ __device__ constexpr int32_t blend_split_words(int32_t th, int32_t r) {
+  return 4 * blend_lh(th, r) + 16 * th + 4;
+}
+
+// One (16 PPT) x TH pixel voting tile with 16 TH threads: thread t votes for
+// PPT horizontally adjacent pixels.  `lin` is LDS for blend_words words (plus
+// blend_split_words with SPLIT): an unused row, then blend_lw x blend_lh
+// cells; cell n holds 4 * (oy * P + ox) for its offset o = NNF[n] - n and the
+// padded exemplar's row length P: a vote of n for pixel p is the texel at
+// p's own padded position plus that many bytes.  Cells outside the target
+// hold the distance to the exemplar's zero rows instead, so their votes read
+// zeros, which count for nothing (alpha 0).  Pixel p's average is
+// (sum + floor(k/2)) / k per channel over its k in-source votes, the vote
+// rule at the end of Sec. 3.2.
+//
+// With SPLIT, groups whose whole window (2R + 1 rows of 2R + PPT cells)
+// holds one offset -- every vote then lands on the same in-source texel, so
+// the average is that texel exactly, which is the paper's remark that
+// voting only blends at chunk boundaries -- copy their texels with one
+// gather; the others are listed in LDS and voted by the tile's threads in
+// list order, so the full votes run in packed waves.  Uniformity is tested
+// separably: per window row, whether the group's cells are all equal (min =
+// max) and whether its first cell equals the one below, as flag bytes.
+// Ends with all threads past their last LDS read (callers that reuse `lin`
+// synchronise before refilling it).
+template <int R, int PPT, int TH, bool SPLIT>
+__device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t tid,
+                                  int32_t *lin) {
+  constexpr int32_t TW = 16 * PPT, NT = 16 * TH;
+  constexpr int32_t LW = blend_lw(TW, R), LH = blend_lh(TH, R);
+  static_assert(TW <= kBlendMaxTW && TH <= kBlendMaxTH, "tile exceeds the exemplar zero rows");
+  const uint32_t tiles_x = (uint32_t(a.w) + TW - 1) / TW;
+  const int32_t X0 = int32_t(t_index % tiles_x) * TW;
+  const int32_t Y0 = int32_t(t_index / tiles_x) * TH;
+  const int32_t P = a.ex_stride;
+  const int32_t zero_rel = int32_t(a.ex_zero) - ((Y0 + kExMargin) * P + (X0 + kExMargin));
+  // the tile's cells in runs of 4 along a row (LW is a multiple of 4), one
+  // dword-aligned 16-byte load per run and every thread's runs requested
+  // together; a run reaching past the target (border tiles only) reads its
+  // cells one by one, and cells outside the target take zero_rel
+  constexpr int32_t QW = LW / 4, NCH = QW * LH, CPER = (NCH + NT - 1) / NT;
+  static_assert(LW % 4 == 0, "tile rows are whole runs of 4 cells");
+  u32x4a4 run[CPER];
+  uint32_t inside[CPER];  // bit m: cell m of the run lies in the target
 #pragma unroll
-    for (int32_t j = 0; j < PPT; ++j) {
-      if (x + j < a.w) {
-        o[3 * j] = uint8_t(c[j]);
-        o[3 * j + 1] = uint8_t(c[j] >> 8);
-        o[3 * j + 2] = uint8_t(c[j] >> 16);
+  for (int32_t n = 0; n < CPER; ++n) {
+    const int32_t ch = int32_t(tid) + n * NT;
+    const int32_t tx = X0 - R + 4 * (ch % QW), ty = Y0 - R + ch / QW;
+    const bool row_in = ch < NCH && ty >= 0 && ty < a.h;
+    const SB_GLOBAL uint32_t *src =
+        glb(a.offsets) + (row_in ? __umul24(uint32_t(ty), uint32_t(a.w)) : 0u);
+    if (row_in && tx >= 0 && tx + 4 <= a.w) {
+      run[n] = *reinterpret_cast<const SB_GLOBAL u32x4a4 *>(src + tx);
+      inside[n] = 15u;
+    } else {
+      inside[n] = 0u;
+#pragma unroll
+      for (int32_t m = 0; m < 4; ++m) {
+        const bool in = row_in && tx + m >= 0 && tx + m < a.w;
+        run[n][m] = src[in ? uint32_t(tx + m) : 0u];
+        inside[n] |= uint32_t(in) << m;
       }
+    }
+  }
+#pragma unroll
+  for (int32_t n = 0; n < CPER; ++n) {
+    const int32_t ch = int32_t(tid) + n * NT;
+    if (n + 1 < CPER || ch < NCH) {
+      i32x4 v;
+#pragma unroll
+      for (int32_t m = 0; m < 4; ++m)
+        v[m] = 4 * ((inside[n] >> m) & 1u ? __mul24(off_y(run[n][m]), P) + off_x(run[n][m])
+                                           : zero_rel);
+      *reinterpret_cast<i32x4 *>(lin + LW + 4 * ch) = v;
+    }
+  }
+  constexpr bool split = SPLIT && R > 0;
+  uint8_t *flags = reinterpret_cast<uint8_t *>(lin + blend_words(TW, TH, R));
+  uint32_t *list = reinterpret_cast<uint32_t *>(flags) + 4 * LH;
+  uint32_t *count = list + NT;
+  if (split && tid == 0) *count = 0u;
+  __syncthreads();
+  const int32_t gx = int32_t(tid & 15), ly = int32_t(tid >> 4);
+  if constexpr (!split) {
+    vote_group<R, PPT, TH>(a, X0, Y0, gx, ly, lin);
+    return;
+  } else {
+    constexpr int32_t NCL = 2 * R + PPT;
+    // flag byte of (window row yy, group gx): bit 0 the group's NCL cells in
+    // that row are equal, bit 1 its first cell equals the one below
+#pragma unroll
+    for (int32_t h = 0; h * TH < LH; ++h) {
+      const int32_t yy = ly + TH * h;
+      if (yy < LH) {
+        const int32_t *c = lin + LW + yy * LW + PPT * gx;
+        int32_t mn = c[0], mx = c[0];
+#pragma unroll
+        for (int32_t i = 1; i < NCL; ++i) mn = min(mn, c[i]), mx = max(mx, c[i]);
+        const bool down = yy + 1 < LH && c[LW] == c[0];
+        flags[yy * 16 + gx] = uint8_t((mn == mx ? 1u : 0u) | (down ? 2u : 0u));
+      }
+    }
+    __syncthreads();
+    uint32_t f = 3u;
+#pragma unroll
+    for (int32_t dy = 0; dy < 2 * R; ++dy) f &= flags[(ly + dy) * 16 + gx];
+    const bool uni = f == 3u && (flags[(ly + 2 * R) * 16 + gx] & 1u) != 0u;
+    const int32_t x = X0 + PPT * gx, y = Y0 + ly;
+    const bool live = x < a.w && y < a.h;
+    if (uni && live) {
+      // one offset over the whole window: every pixel's average is its texel
+      const uint32_t pbase =
+          4u * (__umul24(uint32_t(y + kExMargin), uint32_t(P)) + uint32_t(x + kExMargin));
+      const SB_GLOBAL unsigned char *ex =
+          glb(reinterpret_cast<const unsigned char *>(a.src_rgba));
+      uint32_t c[PPT];
+      load_texels<PPT>(ex, pbase + uint32_t(lin[LW + (ly + R) * LW + PPT * gx + R]), c);
+      store_rgb<PPT>(a, x, y, c);
+    }
+    const bool need = live && !uni;
+    const uint64_t bal = __builtin_amdgcn_ballot_w64(need);
+    uint32_t base = 0;
+    if ((tid & 63) == 0 && bal != 0)
+      base = atomicAdd(count, uint32_t(__builtin_popcountll(bal)));
+    base = __builtin_amdgcn_readfirstlane(base);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+        uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+    if (need) list[base + below] = tid;
+    __syncthreads();
+    const uint32_t n = *count;
+    for (uint32_t e = tid; e < n; e += NT) {
+      const uint32_t t = list[e];
+      vote_group<R, PPT, TH>(a, X0, Y0, int32_t(t & 15), int32_t(t >> 4), lin);
     }
   }
 }
 
 // Radius dispatch over [RLO, RHI] for the batch kernels.
-template <int PPT, int TH, int RLO, int RHI>
+template <int PPT, int TH, int RLO, int RHI, bool SPLIT>
 __device__ inline void blend_tile_r(const FrameArgs &a, uint32_t t_index, uint32_t tid,
                                     int32_t *lin) {
   if constexpr (RLO <= RHI) {
-    if (a.radius == RLO) blend_tile<RLO, PPT, TH>(a, t_index, tid, lin);
-    else blend_tile_r<PPT, TH, RLO + 1, RHI>(a, t_index, tid, lin);
+    if (a.radius == RLO) blend_tile<RLO, PPT, TH, SPLIT>(a, t_index, tid, lin);
+    else blend_tile_r<PPT, TH, RLO + 1, RHI, SPLIT>(a, t_index, tid, lin);
   }
 }
 
-template <int R, int PPT, int TH>
+// LDS words of a voting tile of radius R.
+__host__ __device__ constexpr int32_t blend_tile_words(int32_t ppt, int32_t th, int32_t r,
+                                                       bool split) {
+  return blend_words(16 * ppt, th, r) + (split ? blend_split_words(th, r) : 0);
+}
+
+template <int R, int PPT, int TH, bool SPLIT>
 __global__ void __launch_bounds__(16 * TH) k_blend(FrameArgs a) {
-  __shared__ __attribute__((aligned(16))) int32_t lin[blend_words(16 * PPT, TH, R)];
-  blend_tile<R, PPT, TH>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lin);
+  __shared__ __attribute__((aligned(16))) int32_t lin[blend_tile_words(PPT, TH, R, SPLIT)];
+  blend_tile<R, PPT, TH, SPLIT>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lin);
 }
 
 // ------------------------------------------------------------------ batches
@@ -867,12 +967,12 @@ __global__ void __launch_bounds__(256) k_batch_assign(const unsigned char *desc)
   });
 }
 
-template <int PPT, int TH, int RLO, int RHI>
+template <int PPT, int TH, int RLO, int RHI, bool SPLIT>
 __global__ void __launch_bounds__(16 * TH) k_batch_blend(const unsigned char *desc) {
-  constexpr int WORDS = blend_words(16 * PPT, TH, RHI);
+  constexpr int WORDS = blend_tile_words(PPT, TH, RHI, SPLIT);
   batch_loop<RLO == 0 ? 2 : 3, 16 * TH, WORDS>(desc, [](const FrameArgs &fa, uint32_t local,
                                                         uint32_t *w) {
-    blend_tile_r<PPT, TH, RLO, RHI>(fa, local, threadIdx.x, reinterpret_cast<int32_t *>(w));
+    blend_tile_r<PPT, TH, RLO, RHI, SPLIT>(fa, local, threadIdx.x, reinterpret_cast<int32_t *>(w));
   });
 }
 
@@ -892,24 +992,37 @@ void launch_assign_any(const FrameArgs &a, const Tune &t, uint32_t blocks, hipSt
   else launch_assign<FMT, 2, 1>(a, blocks, stream);
 }
 
-template <int PPT, int TH>
+template <int PPT, int TH, bool SPLIT>
 void launch_blend(const FrameArgs &a, uint32_t blocks, hipStream_t stream) {
   switch (a.radius) {
-    case 0: k_blend<0, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
-    case 1: k_blend<1, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
-    case 2: k_blend<2, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
-    case 3: k_blend<3, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
-    case 4: k_blend<4, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
-    case 5: k_blend<5, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
-    case 6: k_blend<6, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
-    default: k_blend<7, PPT, TH><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 0: k_blend<0, PPT, TH, SPLIT><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 1: k_blend<1, PPT, TH, SPLIT><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 2: k_blend<2, PPT, TH, SPLIT><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 3: k_blend<3, PPT, TH, SPLIT><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 4: k_blend<4, PPT, TH, SPLIT><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 5: k_blend<5, PPT, TH, SPLIT><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    case 6: k_blend<6, PPT, TH, SPLIT><<<blocks, 16 * TH, 0, stream>>>(a); break;
+    default: k_blend<7, PPT, TH, SPLIT><<<blocks, 16 * TH, 0, stream>>>(a); break;
   }
 }
 
 template <int PPT, int TH>
+void launch_blend_any(const FrameArgs &a, bool split, uint32_t blocks, hipStream_t stream) {
+  if (split) launch_blend<PPT, TH, true>(a, blocks, stream);
+  else launch_blend<PPT, TH, false>(a, blocks, stream);
+}
+
+template <int PPT, int TH, bool SPLIT>
 void launch_batch_blend(const unsigned char *desc, uint32_t grid, hipStream_t stream) {
-  k_batch_blend<PPT, TH, 0, 3><<<grid, 16 * TH, 0, stream>>>(desc);
-  k_batch_blend<PPT, TH, 4, SB_MAX_RADIUS><<<grid, 16 * TH, 0, stream>>>(desc);
+  k_batch_blend<PPT, TH, 0, 3, SPLIT><<<grid, 16 * TH, 0, stream>>>(desc);
+  k_batch_blend<PPT, TH, 4, SB_MAX_RADIUS, SPLIT><<<grid, 16 * TH, 0, stream>>>(desc);
+}
+
+template <int PPT, int TH>
+void launch_batch_blend_any(const unsigned char *desc, bool split, uint32_t grid,
+                            hipStream_t stream) {
+  if (split) launch_batch_blend<PPT, TH, true>(desc, grid, stream);
+  else launch_batch_blend<PPT, TH, false>(desc, grid, stream);
 }
 
 }  // namespace
@@ -955,10 +1068,11 @@ hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, const Tune &t, hipEve
   if (ev && e == hipSuccess) e = hipEventRecord(ev[2], stream);
   if (e == hipSuccess) {
     const uint32_t nb = c[2] + c[3];
-    if (t.ppt == 4 && t.rows == 16) launch_blend<4, 16>(a, nb, stream);
-    else if (t.ppt == 4) launch_blend<4, 8>(a, nb, stream);
-    else if (t.rows == 16) launch_blend<2, 16>(a, nb, stream);
-    else launch_blend<2, 8>(a, nb, stream);
+    const bool sp = t.split == 2;
+    if (t.ppt == 4 && t.rows == 16) launch_blend_any<4, 16>(a, sp, nb, stream);
+    else if (t.ppt == 4) launch_blend_any<4, 8>(a, sp, nb, stream);
+    else if (t.rows == 16) launch_blend_any<2, 16>(a, sp, nb, stream);
+    else launch_blend_any<2, 8>(a, sp, nb, stream);
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[3], stream);
   if (e != hipSuccess) return e;
@@ -972,10 +1086,11 @@ hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, const Tune
   else if (t.group == 4) k_batch_assign<4, 1><<<grid, 256, 0, stream>>>(desc_dev);
   else if (t.apx == 2) k_batch_assign<2, 2><<<grid, 256, 0, stream>>>(desc_dev);
   else k_batch_assign<2, 1><<<grid, 256, 0, stream>>>(desc_dev);
-  if (t.ppt == 4 && t.rows == 16) launch_batch_blend<4, 16>(desc_dev, grid, stream);
-  else if (t.ppt == 4) launch_batch_blend<4, 8>(desc_dev, grid, stream);
-  else if (t.rows == 16) launch_batch_blend<2, 16>(desc_dev, grid, stream);
-  else launch_batch_blend<2, 8>(desc_dev, grid, stream);
+  const bool sp = t.split == 2;
+  if (t.ppt == 4 && t.rows == 16) launch_batch_blend_any<4, 16>(desc_dev, sp, grid, stream);
+  else if (t.ppt == 4) launch_batch_blend_any<4, 8>(desc_dev, sp, grid, stream);
+  else if (t.rows == 16) launch_batch_blend_any<2, 16>(desc_dev, sp, grid, stream);
+  else launch_batch_blend_any<2, 8>(desc_dev, sp, grid, stream);
   return hipGetLastError();
 }
 
