@@ -414,6 +414,15 @@ int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace
 /* Wait for the plan's runs, then release its graphs and events. */
 int sb_batch_destroy(sb_batch *b);
 
+/* The per-frame alternative to a batch: the n frames one after another on
+ * `stream`, each through the per-frame kernels exactly as sb_stylize_ex (or
+ * sb_stylize_seg for frames with target labels) would run it, from one
+ * call.  They share workspace [device], which must hold the largest frame's
+ * sb_workspace_bytes().  Every frame is validated before anything is
+ * enqueued (SB_EINVAL / SB_ENOMEM); SB_EHIP if a launch fails. */
+int sb_stylize_frames(const sb_frame *frames, int32_t n, void *workspace,
+                      size_t workspace_bytes, const sb_tune *tune, hipStream_t stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /* Device bytes a request's outputs take from the serving arena. */

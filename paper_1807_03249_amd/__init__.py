@@ -129,6 +129,8 @@ def lib():
                                   ctypes.POINTER(ctypes.c_void_p)]
     L.sb_batch_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(SbFrame), i32, vp, sz, vp]
     L.sb_batch_destroy.argtypes = [ctypes.c_void_p]
+    L.sb_stylize_frames.argtypes = [ctypes.POINTER(SbFrame), i32, vp, sz,
+                                    ctypes.POINTER(SbTune), vp]
     L.sb_jitter_fill.argtypes = [i32, i32, i32, i32, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
     L.sb_style_create.argtypes = [vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(vp)]
     L.sb_style_destroy.argtypes = [vp]
@@ -525,6 +527,23 @@ class FrameJob:
                        self.out_chunk.data_ptr(),
                        self.out_nnf.data_ptr() if self.out_nnf is not None else None,
                        self.tgt_labels.data_ptr() if self.tgt_labels is not None else None)
+
+
+def stylize_frames(jobs, workspace=None, tune=None):
+    """The frames of ``jobs`` (FrameJob) one after another, each through the
+    per-frame kernels (sb_stylize_frames: one C call, no batching), on
+    torch's current stream.  ``workspace`` must hold the largest frame's
+    workspace (allocated here when not given)."""
+    torch = _torch()
+    arr = (SbFrame * len(jobs))(*[j.c() for j in jobs])
+    wsb = max(workspace_bytes(j.w, j.h, j.params) for j in jobs)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    tn = tune_struct(tune)
+    _check(lib().sb_stylize_frames(arr, len(jobs), workspace.data_ptr(), workspace.numel(),
+                                   ctypes.byref(tn) if tn is not None else None, _stream(torch)),
+           "sb_stylize_frames")
+    return jobs
 
 
 class Batch:

@@ -180,4 +180,29 @@ int sb_batch_destroy(sb_batch *b) {
   return SB_OK;
 }
 
+int sb_stylize_frames(const sb_frame *frames, int32_t n, void *workspace,
+                      size_t workspace_bytes, const sb_tune *tune, hipStream_t stream) {
+  if (!frames || n < 1 || !workspace) return SB_EINVAL;
+  Tune t;
+  if (!resolve_tune(tune, &t)) return SB_EINVAL;
+  // every frame is checked before the first is enqueued
+  for (int32_t f = 0; f < n; ++f) {
+    const sb_frame &fr = frames[f];
+    FrameArgs a;
+    if (!fill_frame(fr.style, fr.tgt_guide, fr.w, fr.h, fr.jitter, &fr.params, fr.out_rgb,
+                    fr.out_chunk, fr.out_nnf, &a, fr.tgt_labels))
+      return SB_EINVAL;
+    if (workspace_bytes < sb_workspace_bytes(fr.w, fr.h, &fr.params)) return SB_ENOMEM;
+  }
+  // the frames run one after another on one stream, so they share the workspace
+  for (int32_t f = 0; f < n; ++f) {
+    const sb_frame &fr = frames[f];
+    const int rc = stylize_impl(fr.style, fr.tgt_guide, fr.w, fr.h, fr.jitter, &fr.params,
+                                fr.out_rgb, fr.out_chunk, fr.out_nnf, workspace, workspace_bytes,
+                                tune, nullptr, stream, fr.tgt_labels);
+    if (rc != SB_OK) return rc;
+  }
+  return SB_OK;
+}
+
 }  // extern "C"

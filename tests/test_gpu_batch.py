@@ -271,3 +271,23 @@ def test_full_workload_batch(sb, tune, bpc):
             np.testing.assert_array_equal(jobs[i].out_rgb.cpu().numpy(), e_rgb,
                                           err_msg=f"frame {i} rgb")
     b.close()
+
+
+def test_stylize_frames_equals_single(sb, mix):
+    """sb_stylize_frames (the per-frame baseline of the batch bench: all
+    frames through the per-frame kernels from one call, one shared
+    workspace) gives every frame exactly what a lone sb_stylize gives, under
+    the default and a non-default kernel choice."""
+    import torch
+
+    styles_np, frames_np, styles = mix
+    idx = list(range(len(frames_np)))
+    for tune in (None, (2, 16, 4, 1, 1)):
+        say(f"stylize_frames {len(idx)} frames tune={tune}")
+        jobs = jobs_for(sb, styles, frames_np, idx)
+        sb.stylize_frames(jobs, tune=tune)
+        torch.cuda.synchronize()
+        for i, j in zip(idx, jobs):
+            rgb, chunk = single(sb, styles, frames_np[i])
+            np.testing.assert_array_equal(j.out_chunk.cpu().numpy(), chunk, err_msg=f"frame {i}")
+            np.testing.assert_array_equal(j.out_rgb.cpu().numpy(), rgb, err_msg=f"frame {i}")
