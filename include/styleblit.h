@@ -281,7 +281,7 @@ size_t sb_noalloc_scratch_bytes(void);
  * library's default.
  *   blend_ppt    pixels per thread of the voting pass, adjacent in a row: 2 or
  *                4 (default 4); each vote gather loads that many texels
- *   blend_rows   rows of the voting tile: 8 or 16 (default 8); the tile is
+ *   blend_rows   rows of the voting tile: 8 or 16 (default 16); the tile is
  *                (16 * blend_ppt) x blend_rows pixels, one thread per
  *                blend_ppt pixels
  *   level_group  levels of Algorithm 2 whose source-guide gathers are in

@@ -140,7 +140,7 @@ bool resolve_weights(int32_t fmt, const uint8_t *in, int32_t out[3]) {
 
 bool resolve_tune(const sb_tune *in, Tune *out) {
   out->ppt = 4;
-  out->rows = 8;
+  out->rows = 16;
   out->group = 2;
   out->apx = 2;
   out->split = 2;
