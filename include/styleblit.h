@@ -286,8 +286,9 @@ size_t sb_noalloc_scratch_bytes(void);
  *                blend_ppt pixels
  *   level_group  levels of Algorithm 2 whose source-guide gathers are in
  *                flight together before their tests: 2 or 4 (default 2)
- *   level_ppt    pixels per thread of the level loop (horizontally adjacent
- *                8x8 blocks per wave): 1 or 2 (default 2)
+ *   level_ppt    pixels per thread of the level loop, i.e. 8x8 blocks per
+ *                wave: 1, 2 (side by side) or 4 (2 x 2) (default 2); the
+ *                blocks of a wave share the seed records they have in common
  *   blend_split  2: the voting pass copies the texel of every pixel group
  *                whose whole window holds one offset (their exact average)
  *                and votes the other groups from a per-tile list; 1: every

@@ -47,7 +47,7 @@ class SbTune(ctypes.Structure):
 # every kernel choice (blend_ppt, blend_rows, level_group, level_ppt, blend_split); all
 # compute the same bits, (0, 0, 0, 0, 0) is the library default
 TUNES = [(ppt, rows, grp, lpx, split) for ppt in (4, 2) for rows in (16, 8) for grp in (2, 4)
-         for lpx in (1, 2) for split in (2, 1)]
+         for lpx in (1, 2, 4) for split in (2, 1)]
 
 
 def tune_struct(tune) -> Optional[SbTune]:

@@ -158,7 +158,7 @@ bool resolve_tune(const sb_tune *in, Tune *out) {
     out->group = in->level_group;
   }
   if (in->level_ppt != 0) {
-    if (in->level_ppt != 1 && in->level_ppt != 2) return false;
+    if (in->level_ppt != 1 && in->level_ppt != 2 && in->level_ppt != 4) return false;
     out->apx = in->level_ppt;
   }
   if (in->blend_split != 0) {

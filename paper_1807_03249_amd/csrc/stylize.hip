@@ -206,9 +206,18 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Records staged per wave: level i's nine at [kRecStride * i, + 9).
+// Records staged per wave: level i's nine at [kRecStride * i, + 9) of each
+// block's record array (its 3 x 3 neighbourhood, x outer, y inner).
 constexpr int32_t kRecStride = 12;
 constexpr int32_t kWaveRecs = SB_MAX_LEVELS * kRecStride;
+// Union grid of a multi-block wave: per level the 4 x 4 cells around the
+// wave's region (16 slots, row-major), positions then offsets.
+constexpr int32_t kUnion = 16;
+constexpr int32_t kUnionWords = 2 * kUnion * SB_MAX_LEVELS;
+// LDS words per wave of the block level loop for B blocks.
+__host__ __device__ constexpr int32_t wave_recs_words(int32_t b) {
+  return 2 * b * kWaveRecs + (b > 1 ? kUnionWords : 0);
+}
 
 // N levels i0 .. i0+N-1 of the block level loop for the lane's B pixels
 // (pixel b in block b, whose records start at lpos + b * kWaveRecs): NearestSeed
@@ -219,9 +228,9 @@ constexpr int32_t kWaveRecs = SB_MAX_LEVELS * kRecStride;
 template <int FMT, int N, int B, bool SEG>
 __device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *lpos,
                                             const uint32_t *loff, int32_t i0, const int32_t *x,
-                                            int32_t y, const short2_t *p4, const uint32_t *gt,
-                                            const uint32_t *lt, uint32_t *chunk, uint32_t *off,
-                                            bool *done) {
+                                            const int32_t *y, const short2_t *p4,
+                                            const uint32_t *gt, const uint32_t *lt,
+                                            uint32_t *chunk, uint32_t *off, bool *done) {
   const int32_t L = a.lv.count;
   const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
   uint32_t g[B][N], wq[B][N], wo[B][N];
@@ -246,7 +255,7 @@ __device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *
       key = min(key, seed_key(P[8], p4[b], 8));
       wq[b][u] = P[key & 15];
       wo[b][u] = O[key & 15];
-      const int32_t vx = x[b] + off_x(wo[b][u]), vy = y + off_y(wo[b][u]);
+      const int32_t vx = x[b] + off_x(wo[b][u]), vy = y[b] + off_y(wo[b][u]);
       // non-short-circuit: keeps the group one straight-line block
       ok[b][u] = (i0 + u < L) & (key != INT32_MAX) & (uint32_t(vx) < sw) & (uint32_t(vy) < sh);
       g[b][u] = ok[b][u] ? __umul24(uint32_t(vy), sw) + uint32_t(vx) : 0u;
@@ -277,87 +286,146 @@ __device__ __forceinline__ void level_group(const FrameArgs &a, const uint32_t *
   }
 }
 
-// The level loop for B horizontally adjacent 8 x 8 blocks whose pixels share
-// one cell at every level (every spacing >= 8); lane l takes pixel l of each
-// block.  The wave stages each block's 9 L seed records in LDS (one gather
-// per 64 records) and runs the levels in groups of G (level_group).  The
-// target guide, the records and the pixels' own lookups (their fallback) are
-// all requested up front, so the chain of dependent memory round trips is
-// guide -> lookup and records -> source guide, side by side.
-template <int FMT, int G, int B, bool SEG>
+// The level's first jitter entry (own records) or first seed-table record,
+// and its hash state, for a lane whose level is `i`: a select per level, so
+// nothing is indexed per lane in the kernel arguments.
+__device__ __forceinline__ void level_select(const FrameArgs &a, uint32_t i, int32_t lo,
+                                             int32_t hi, int32_t &f, uint32_t &hk) {
+  const int32_t *first = a.own_seeds ? a.lv.offset : a.lv.poffset;
+  f = first[lo];
+  hk = a.jhash[lo];
+#pragma unroll 1
+  for (int32_t l = lo + 1; l < hi; ++l) {
+    f = i >= uint32_t(l) ? first[l] : f;
+    hk = i >= uint32_t(l) ? a.jhash[l] : hk;
+  }
+}
+
+// The record of cell (cx, cy) of a level with log2 spacing ls: made from the
+// jitter, the target guide and the table (own records), or read from the
+// padded seed table (first record f of the level).
+template <int FMT>
+__device__ __forceinline__ u32x2 level_record(const FrameArgs &a, int32_t ls, int32_t f,
+                                              uint32_t hk, int32_t cx, int32_t cy) {
+  const int32_t ncx = ((a.w - 1) >> ls) + 1, ncy = ((a.h - 1) >> ls) + 1;
+  if (a.own_seeds) return seed_record<FMT>(a, ls, ncx, ncy, f, hk, cx, cy);
+  return seed_table(a)[uint32_t(f + (cy + 1) * (ncx + 2) + cx + 1)];
+}
+
+// The level loop for a wave's region of BX x BY blocks of 8 x 8 pixels at
+// (bx0, by0) whose pixels share one cell per block at every level (every
+// spacing >= 8); lane l takes pixel (l & 7, l >> 3) of every block.  The
+// wave stages each block's 9 L seed records in LDS: with one block, one
+// lane per record (two when 9 L > 64); with several, the region's blocks
+// draw on one union grid per level (the cells the region touches and a
+// ring, at most 4 x 4), staged 16 lanes per level and then copied into each
+// block's record array, so a record shared by the blocks is made once.
+// The union pays where records are made in the kernel (jitter -> target
+// guide -> table); records read from the seed table are read per block.
+// Levels run in groups of G (level_group).  The target guide, the records
+// and the pixels' own lookups (their fallback) are all requested up front,
+// so the chain of dependent memory round trips is guide -> lookup and
+// records -> source guide, side by side.
+template <int FMT, int G, int BX, int BY, bool SEG>
 __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0, int32_t lane,
-                                    uint32_t *lpos, uint32_t *loff) {
+                                    uint32_t *lds) {
+  constexpr int32_t B = BX * BY;
+  uint32_t *lpos = lds, *loff = lds + B * kWaveRecs;
   const Levels &lv = a.lv;
   const int32_t L = lv.count;
-  const int32_t y = by0 + (lane >> 3);
-  int32_t x[B];
+  int32_t x[B], y[B];
   bool in[B];
   uint32_t pidx[B], gt[B], lt[B];
 #pragma unroll
   for (int32_t b = 0; b < B; ++b) {
-    x[b] = bx0 + 8 * b + (lane & 7);
-    in[b] = x[b] < a.w && y < a.h;
-    pidx[b] = in[b] ? __umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x[b]) : 0u;
+    x[b] = bx0 + 8 * (b % BX) + (lane & 7);
+    y[b] = by0 + 8 * (b / BX) + (lane >> 3);
+    in[b] = x[b] < a.w && y[b] < a.h;
+    pidx[b] = in[b] ? __umul24(uint32_t(y[b]), uint32_t(a.w)) + uint32_t(x[b]) : 0u;
     gt[b] = guide_word<FMT>(a.tgt_guide, pidx[b]);
     lt[b] = SEG ? uint32_t(glb(a.tgt_labels)[pidx[b]]) : 0u;
   }
-  // record j of block b (level j / 9, neighbour j % 9) for lanes j and j + 64:
-  // read from the seed table, or, with a.own_seeds (a small lookup table, so
-  // the lookups stay in cache), made here from the jitter table, the target
-  // guide and the lookup table; a block past the frame's right edge stages
-  // the last column's cells (its pixels are all outside, so they are never
-  // used).  A lane's level geometry follows from the spacings h_i =
-  // h_0 / 2^i: log2 spacing ls0 - i and ceil(extent / h_i) cells per axis;
-  // only the level's first jitter entry (own records) or first table record
-  // is looked up, by a select per level, so nothing is indexed per lane in
-  // the kernel arguments.
+  // a lane's level geometry follows from the spacings h_i = h_0 / 2^i: log2
+  // spacing ls0 - i and ceil(extent / h_i) cells per axis
   const int32_t ls0 = L > 0 ? lv.log2_spacing[0] : 0;
-  const int32_t *first = a.own_seeds ? lv.offset : lv.poffset;
-  u32x2 rec[B][2];
-  int32_t slot[B][2];
+  if (B == 1 || !a.own_seeds) {
+    // records read from the seed table (or a lone block's own records):
+    // record j (level j / 9, neighbour j % 9) of block b for lanes j and
+    // j + 64; a block wholly outside the frame stages the region's first
+    // block's cells (its pixels are never used)
+    u32x2 rec[B][2];
+    int32_t slot[B][2];
 #pragma unroll
-  for (int32_t h = 0; h < 2; ++h) {
-    if (h > 0 && 9 * L <= 64) {  // one record per lane suffices
+    for (int32_t h = 0; h < 2; ++h) {
+      const uint32_t j = uint32_t(lane + 64 * h);
+      const uint32_t i = (j * 57u) >> 9;  // j / 9 for j < 128
+      const uint32_t k = j - 9u * i;
+      const uint32_t kx = (k * 11u) >> 5;  // k / 3 for k < 9: x outer, y inner
+      const bool staged = (h == 0 || 9 * L > 64) && j < uint32_t(9 * L);
+      const int32_t ls = ls0 - int32_t(min(i, uint32_t(max(L - 1, 0))));
+      int32_t f = 0;
+      uint32_t hk = 0;
+      if (staged) level_select(a, i, 0, L, f, hk);
 #pragma unroll
-      for (int32_t b = 0; b < B; ++b) slot[b][h] = -1;
-      continue;
-    }
-    const uint32_t j = uint32_t(lane + 64 * h);
-    const uint32_t i = (j * 57u) >> 9;  // j / 9 for j < 128
-    const uint32_t k = j - 9u * i;
-    const uint32_t kx = (k * 11u) >> 5;  // k / 3 for k < 9: x outer, y inner
-    const bool staged = j < uint32_t(9 * L);
-    const int32_t ls = ls0 - int32_t(min(i, uint32_t(max(L - 1, 0))));  // clamped past the records
-    const int32_t ncx = ((a.w - 1) >> ls) + 1, ncy = ((a.h - 1) >> ls) + 1;
-    const int32_t rcy = (by0 >> ls) - 1 + int32_t(k - 3u * kx);
-    int32_t f = 0;
-    uint32_t hk = a.jhash[0];
-#pragma unroll 1
-    for (int32_t l = 1; l < L; ++l) {
-      f = i >= uint32_t(l) ? first[l] : f;
-      hk = i >= uint32_t(l) ? a.jhash[l] : hk;
+      for (int32_t b = 0; b < B; ++b) {
+        const int32_t X0 = bx0 + (bx0 + 8 * (b % BX) < a.w ? 8 * (b % BX) : 0);
+        const int32_t Y0 = by0 + (by0 + 8 * (b / BX) < a.h ? 8 * (b / BX) : 0);
+        slot[b][h] = staged ? b * kWaveRecs + kRecStride * int32_t(i) + int32_t(k) : -1;
+        rec[b][h] = u32x2{0, 0};
+        if (staged)
+          rec[b][h] = level_record<FMT>(a, ls, f, hk, (X0 >> ls) - 1 + int32_t(kx),
+                                        (Y0 >> ls) - 1 + int32_t(k - 3u * kx));
+      }
     }
 #pragma unroll
     for (int32_t b = 0; b < B; ++b) {
-      const int32_t cx0 = min(bx0 + 8 * b, a.w - 1);
-      const int32_t rcx = (cx0 >> ls) - 1 + int32_t(kx);
-      slot[b][h] = staged ? b * kWaveRecs + kRecStride * int32_t(i) + int32_t(k) : -1;
-      rec[b][h] = u32x2{0, 0};
-      if (staged) {
-        if (a.own_seeds)
-          rec[b][h] = seed_record<FMT>(a, ls, ncx, ncy, f, hk, rcx, rcy);
-        else
-          rec[b][h] = seed_table(a)[uint32_t(f + (rcy + 1) * (ncx + 2) + rcx + 1)];
+#pragma unroll
+      for (int32_t h = 0; h < 2; ++h) {
+        if (slot[b][h] >= 0) {
+          lpos[slot[b][h]] = rec[b][h].x;
+          loff[slot[b][h]] = rec[b][h].y;
+        }
       }
     }
-  }
+  } else {
+    // own records for several blocks: one union grid, each shared record made once
+    uint32_t *upos = lds + 2 * B * kWaveRecs, *uoff = upos + kUnion * SB_MAX_LEVELS;
+    // the region's last in-frame pixel
+    const int32_t rx1 = min(bx0 + 8 * BX, a.w) - 1, ry1 = min(by0 + 8 * BY, a.h) - 1;
+    // union cell t = (ux, uy) of level 4r + (lane >> 4), four levels per round
+    for (int32_t r = 0; 4 * r < L; ++r) {
+      const int32_t i = 4 * r + (lane >> 4), t = lane & 15, ux = t & 3, uy = t >> 2;
+      const int32_t ls = ls0 - min(i, L - 1);
+      const int32_t c0x = bx0 >> ls, c0y = by0 >> ls;
+      if (i < L && ux <= (rx1 >> ls) - c0x + 2 && uy <= (ry1 >> ls) - c0y + 2) {
+        int32_t f;
+        uint32_t hk;
+        level_select(a, uint32_t(i), 4 * r, min(4 * r + 4, L), f, hk);
+        const u32x2 rec = level_record<FMT>(a, ls, f, hk, c0x - 1 + ux, c0y - 1 + uy);
+        upos[kUnion * i + t] = rec.x;
+        uoff[kUnion * i + t] = rec.y;
+      }
+    }
+    wave_lds_sync();
+    // each block's neighbourhood out of the union: record j = (level j / 9,
+    // neighbour j % 9) of block b; a block wholly outside the frame copies
+    // the region's first block's cells (its pixels are never used)
 #pragma unroll
-  for (int32_t b = 0; b < B; ++b) {
+    for (int32_t b = 0; b < B; ++b) {
+      const int32_t X0 = bx0 + (bx0 + 8 * (b % BX) < a.w ? 8 * (b % BX) : 0);
+      const int32_t Y0 = by0 + (by0 + 8 * (b / BX) < a.h ? 8 * (b / BX) : 0);
 #pragma unroll
-    for (int32_t h = 0; h < 2; ++h) {
-      if (slot[b][h] >= 0) {
-        lpos[slot[b][h]] = rec[b][h].x;
-        loff[slot[b][h]] = rec[b][h].y;
+      for (int32_t h = 0; h < 2; ++h) {
+        if (h > 0 && 9 * L <= 64) continue;
+        const uint32_t j = uint32_t(lane + 64 * h);
+        if (j >= uint32_t(9 * L)) continue;
+        const uint32_t i = (j * 57u) >> 9, k = j - 9u * i, kx = (k * 11u) >> 5;
+        const int32_t ls = ls0 - int32_t(i);
+        const int32_t u = kUnion * int32_t(i) + ((Y0 >> ls) - (by0 >> ls) + int32_t(k - 3u * kx)) * 4 +
+                          (X0 >> ls) - (bx0 >> ls) + int32_t(kx);
+        const int32_t s = b * kWaveRecs + kRecStride * int32_t(i) + int32_t(k);
+        lpos[s] = upos[u];
+        loff[s] = uoff[u];
       }
     }
   }
@@ -374,7 +442,7 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
   for (int32_t b = 0; b < B; ++b) {
     own[b] = 0;
     if (eager) own[b] = glb(own_table<SEG>(a, lt[b]))[lut_bin<FMT>(gt[b], a.lut_shift, a.lut_bits)];
-    p4[b] = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x[b]), uint32_t(4 * y)));
+    p4[b] = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x[b]), uint32_t(4 * y[b])));
     chunk[b] = off[b] = 0;
     done[b] = !in[b];
   }
@@ -392,14 +460,14 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
     if (!in[b]) continue;
     if (!done[b]) {  // no level accepted: the pixel's own lookup
       if (!eager) own[b] = glb(own_table<SEG>(a, lt[b]))[lut_bin<FMT>(gt[b], a.lut_shift, a.lut_bits)];
-      chunk[b] = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x[b]);
-      off[b] = pack_off(int32_t(own[b] & 0xFFFFu) - x[b], int32_t(own[b] >> 16) - y);
+      chunk[b] = (uint32_t(L) << 26) | (uint32_t(y[b]) << 13) | uint32_t(x[b]);
+      off[b] = pack_off(int32_t(own[b] & 0xFFFFu) - x[b], int32_t(own[b] >> 16) - y[b]);
     }
     glb(a.out_chunk)[pidx[b]] = chunk[b];
     glb(a.offsets)[pidx[b]] = off[b];
     if (a.out_nnf)
       glb(a.out_nnf)[pidx[b]] =
-          pack_xy(uint32_t(x[b] + off_x(off[b])), uint32_t(y + off_y(off[b])));
+          pack_xy(uint32_t(x[b] + off_x(off[b])), uint32_t(y[b] + off_y(off[b])));
   }
 }
 
@@ -451,26 +519,29 @@ __host__ __device__ inline bool uniform_cells(const Levels &lv) {
   return lv.count == 0 || lv.log2_spacing[lv.count - 1] >= 3;
 }
 
-// One (16 B) x 16 tile: four groups of B 8 x 8 blocks, one group per wave, on
-// the uniform-cell path; otherwise B pixels per thread.  `recs` is LDS for 4
-// waves' records (2 B kWaveRecs words each).
+// One (16 BX) x (16 BY) tile with BX BY = B: four regions of BX x BY blocks
+// of 8 x 8 pixels, one per wave, on the uniform-cell path; otherwise B
+// pixels per thread.  `lds` holds 4 waves' records (wave_recs_words(B) each).
 template <int FMT, int G, int B, bool SEG>
 __device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t tid,
-                                   uint32_t *recs) {
-  const uint32_t tw = 16 * B;
+                                   uint32_t *lds) {
+  constexpr int32_t BX = B >= 2 ? 2 : 1, BY = B / BX;
+  static_assert(BX * BY == B && (B == 1 || B == 2 || B == 4), "regions of 1, 2 or 4 blocks");
+  const uint32_t tw = 16 * BX, th = 16 * BY;
   const uint32_t tiles_x = (uint32_t(a.w) + tw - 1) / tw;
-  const int32_t tx0 = int32_t((tile % tiles_x) * tw), ty0 = int32_t((tile / tiles_x) * 16);
+  const int32_t tx0 = int32_t((tile % tiles_x) * tw), ty0 = int32_t((tile / tiles_x) * th);
   if (uniform_cells(a.lv)) {
     const int32_t wave = __builtin_amdgcn_readfirstlane(int32_t(tid >> 6));
-    const int32_t bx0 = tx0 + (wave & 1) * 8 * B, by0 = ty0 + (wave >> 1) * 8;
-    // a block group wholly outside the frame has no cells in the table
+    const int32_t bx0 = tx0 + (wave & 1) * 8 * BX, by0 = ty0 + (wave >> 1) * 8 * BY;
+    // a region wholly outside the frame has no cells in the table
     if (bx0 >= a.w || by0 >= a.h) return;
-    uint32_t *lpos = recs + wave * 2 * B * kWaveRecs;
-    assign_block<FMT, G, B, SEG>(a, bx0, by0, int32_t(tid & 63), lpos, lpos + B * kWaveRecs);
+    assign_block<FMT, G, BX, BY, SEG>(a, bx0, by0, int32_t(tid & 63),
+                                      lds + wave * wave_recs_words(B));
   } else {
 #pragma unroll
     for (int32_t b = 0; b < B; ++b)
-      assign_pixel<FMT, SEG>(a, tx0 + 16 * b + int32_t(tid & 15), ty0 + int32_t(tid >> 4));
+      assign_pixel<FMT, SEG>(a, tx0 + int32_t(tid & 15) + 16 * (b % BX),
+                             ty0 + int32_t(tid >> 4) + 16 * (b / BX));
   }
 }
 
@@ -485,8 +556,8 @@ __device__ inline uint32_t xcd_tile(uint32_t bid, uint32_t n) {
 
 template <int FMT, int G, int B, bool SEG>
 __global__ void __launch_bounds__(256) k_assign(FrameArgs a) {
-  __shared__ __attribute__((aligned(16))) uint32_t recs[4 * 2 * B * kWaveRecs];
-  assign_tile<FMT, G, B, SEG>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, recs);
+  __shared__ __attribute__((aligned(16))) uint32_t lds[4 * wave_recs_words(B)];
+  assign_tile<FMT, G, B, SEG>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lds);
 }
 
 // Exact floor(n / k) for n < 2^16 and 1 <= k <= 225, given rk within one ulp
@@ -951,7 +1022,7 @@ __global__ void __launch_bounds__(256) k_batch_seeds(const unsigned char *desc) 
 
 template <int G, int B>
 __global__ void __launch_bounds__(256) k_batch_assign(const unsigned char *desc) {
-  batch_loop<1, 256, 4 * 2 * B * kWaveRecs>(desc, [](const FrameArgs &fa, uint32_t local,
+  batch_loop<1, 256, 4 * wave_recs_words(B)>(desc, [](const FrameArgs &fa, uint32_t local,
                                                      uint32_t *w) {
     const bool seg = fa.tgt_labels != nullptr;
     if (fa.fmt == SB_GUIDE_U8X2) {
@@ -986,10 +1057,15 @@ void launch_assign(const FrameArgs &a, uint32_t blocks, hipStream_t stream) {
 
 template <int FMT>
 void launch_assign_any(const FrameArgs &a, const Tune &t, uint32_t blocks, hipStream_t stream) {
-  if (t.group == 4 && t.apx == 2) launch_assign<FMT, 4, 2>(a, blocks, stream);
-  else if (t.group == 4) launch_assign<FMT, 4, 1>(a, blocks, stream);
-  else if (t.apx == 2) launch_assign<FMT, 2, 2>(a, blocks, stream);
-  else launch_assign<FMT, 2, 1>(a, blocks, stream);
+  if (t.group == 4) {
+    if (t.apx == 4) launch_assign<FMT, 4, 4>(a, blocks, stream);
+    else if (t.apx == 2) launch_assign<FMT, 4, 2>(a, blocks, stream);
+    else launch_assign<FMT, 4, 1>(a, blocks, stream);
+  } else {
+    if (t.apx == 4) launch_assign<FMT, 2, 4>(a, blocks, stream);
+    else if (t.apx == 2) launch_assign<FMT, 2, 2>(a, blocks, stream);
+    else launch_assign<FMT, 2, 1>(a, blocks, stream);
+  }
 }
 
 template <int PPT, int TH, bool SPLIT>
@@ -1039,8 +1115,8 @@ void tile_counts(const FrameArgs &a, const Tune &t, uint32_t counts[4]) {
   const uint32_t blend = ((uint32_t(a.w) + tw - 1) / tw) * ((uint32_t(a.h) + th - 1) / th);
   // no seed table when the block level loop makes its own records
   counts[0] = a.own_seeds ? 0u : (uint32_t(a.lv.poffset[a.lv.count]) + 255) / 256;
-  const uint32_t aw = 16 * uint32_t(t.apx);
-  counts[1] = ((uint32_t(a.w) + aw - 1) / aw) * ((uint32_t(a.h) + 15) / 16);
+  const uint32_t aw = t.apx >= 2 ? 32u : 16u, ah = t.apx == 4 ? 32u : 16u;
+  counts[1] = ((uint32_t(a.w) + aw - 1) / aw) * ((uint32_t(a.h) + ah - 1) / ah);
   counts[2] = a.radius <= 3 ? blend : 0;
   counts[3] = a.radius <= 3 ? 0 : blend;
 }
@@ -1082,10 +1158,15 @@ hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, const Tune &t, hipEve
 hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, const Tune &t,
                         hipStream_t stream) {
   k_batch_seeds<<<grid, 256, 0, stream>>>(desc_dev);
-  if (t.group == 4 && t.apx == 2) k_batch_assign<4, 2><<<grid, 256, 0, stream>>>(desc_dev);
-  else if (t.group == 4) k_batch_assign<4, 1><<<grid, 256, 0, stream>>>(desc_dev);
-  else if (t.apx == 2) k_batch_assign<2, 2><<<grid, 256, 0, stream>>>(desc_dev);
-  else k_batch_assign<2, 1><<<grid, 256, 0, stream>>>(desc_dev);
+  if (t.group == 4) {
+    if (t.apx == 4) k_batch_assign<4, 4><<<grid, 256, 0, stream>>>(desc_dev);
+    else if (t.apx == 2) k_batch_assign<4, 2><<<grid, 256, 0, stream>>>(desc_dev);
+    else k_batch_assign<4, 1><<<grid, 256, 0, stream>>>(desc_dev);
+  } else {
+    if (t.apx == 4) k_batch_assign<2, 4><<<grid, 256, 0, stream>>>(desc_dev);
+    else if (t.apx == 2) k_batch_assign<2, 2><<<grid, 256, 0, stream>>>(desc_dev);
+    else k_batch_assign<2, 1><<<grid, 256, 0, stream>>>(desc_dev);
+  }
   const bool sp = t.split == 2;
   if (t.ppt == 4 && t.rows == 16) launch_batch_blend_any<4, 16>(desc_dev, sp, grid, stream);
   else if (t.ppt == 4) launch_batch_blend_any<4, 8>(desc_dev, sp, grid, stream);
