@@ -11,7 +11,10 @@ import ctypes
 import os
 from typing import Optional, Sequence
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstyleblit.so")
+# STYLEBLIT_LIB names another build of the same library (e.g. to compare two
+# builds in one process); by default the in-tree build is loaded
+LIB_PATH = os.environ.get("STYLEBLIT_LIB") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libstyleblit.so")
 
 GUIDE_U8X2 = 0
 GUIDE_U16X2 = 1

@@ -80,7 +80,8 @@ struct FrameArgs {
   uint32_t *out_chunk;        // W*H
   uint32_t *out_nnf;          // W*H or null
   uint2 *seeds;               // workspace: per padded cell {4x | 4y << 16, dx | dy << 16}
-  uint32_t *offsets;          // workspace: per pixel NNF[p] - p as two int16
+  uint32_t *offsets;          // workspace: per pixel the vote's byte distance
+                              // 4 (oy ex_stride + ox) of its offset o = NNF[p] - p
   int32_t sw, sh, w, h;
   int32_t lut_bits, lut_shift; // lut_shift = guide depth - lut_bits
   int32_t lut_log2;            // log2 of the table's entries: channels * lut_bits

@@ -9,7 +9,8 @@
 //             3x3 cells, the exact integer guide error at u* + (p - q)
 //             against the threshold (with the segmentation guide, also the
 //             label test), and the own-lookup fallback.  Writes the chunk
-//             code and the offset NNF[p] - p.
+//             code and the offset NNF[p] - p as the byte distance the vote
+//             adds in the padded exemplar.
 //   k_blend   the voting step (end of Sec. 3.2): a tile of offsets with an
 //             r-pixel halo in LDS; each lane averages the (2r+1)^2 votes of
 //             four adjacent pixels, one vector gather per (cell, pixel run).
@@ -103,6 +104,13 @@ __device__ inline int32_t off_y(uint32_t o) { return int32_t(int16_t(o >> 16)); 
 // Chunk code of the seed whose position word (4x | 4y << 16) is q4.
 __device__ inline uint32_t chunk_code(int32_t level, uint32_t q4) {
   return (uint32_t(level) << 26) | ((q4 >> 18) << 13) | ((q4 & 0xFFFFu) >> 2);
+}
+
+// What the vote needs of a pixel's offset o = NNF[p] - p: the byte distance
+// 4 (oy P + ox) it adds to a pixel's position in the padded exemplar (rows of
+// P texels) to reach the co-located texel of that source patch.
+__device__ inline uint32_t vote_distance(const FrameArgs &a, uint32_t off) {
+  return uint32_t(4 * (__mul24(off_y(off), a.ex_stride) + off_x(off)));
 }
 
 // Every texel of the padded exemplar: source texels with alpha 1, margins and
@@ -464,7 +472,7 @@ __device__ inline void assign_block(const FrameArgs &a, int32_t bx0, int32_t by0
       off[b] = pack_off(int32_t(own[b] & 0xFFFFu) - x[b], int32_t(own[b] >> 16) - y[b]);
     }
     glb(a.out_chunk)[pidx[b]] = chunk[b];
-    glb(a.offsets)[pidx[b]] = off[b];
+    glb(a.offsets)[pidx[b]] = vote_distance(a, off[b]);
     if (a.out_nnf)
       glb(a.out_nnf)[pidx[b]] =
           pack_xy(uint32_t(x[b] + off_x(off[b])), uint32_t(y[b] + off_y(off[b])));
@@ -510,7 +518,7 @@ __device__ inline void assign_pixel(const FrameArgs &a, int32_t x, int32_t y) {
     off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
   }
   glb(a.out_chunk)[pidx] = chunk;
-  glb(a.offsets)[pidx] = off;
+  glb(a.offsets)[pidx] = vote_distance(a, off);
   if (a.out_nnf) glb(a.out_nnf)[pidx] = pack_xy(uint32_t(x + off_x(off)), uint32_t(y + off_y(off)));
 }
 
@@ -819,7 +827,7 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
   const int32_t X0 = int32_t(t_index % tiles_x) * TW;
   const int32_t Y0 = int32_t(t_index / tiles_x) * TH;
   const int32_t P = a.ex_stride;
-  const int32_t zero_rel = int32_t(a.ex_zero) - ((Y0 + kExMargin) * P + (X0 + kExMargin));
+  const int32_t zero_rel = 4 * (int32_t(a.ex_zero) - ((Y0 + kExMargin) * P + (X0 + kExMargin)));
   // the tile's cells in runs of 4 along a row (LW is a multiple of 4), one
   // dword-aligned 16-byte load per run and every thread's runs requested
   // together; a run reaching past the target (border tiles only) reads its
@@ -855,8 +863,7 @@ __device__ inline void blend_tile(const FrameArgs &a, uint32_t t_index, uint32_t
       i32x4 v;
 #pragma unroll
       for (int32_t m = 0; m < 4; ++m)
-        v[m] = 4 * ((inside[n] >> m) & 1u ? __mul24(off_y(run[n][m]), P) + off_x(run[n][m])
-                                           : zero_rel);
+        v[m] = (inside[n] >> m) & 1u ? int32_t(run[n][m]) : zero_rel;
       *reinterpret_cast<i32x4 *>(lin + LW + 4 * ch) = v;
     }
   }
