@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--streams", type=int, default=2,
+                    help="streams the timed frames are enqueued on, round robin")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rotate-mb", type=float, default=600.0)
     ap.add_argument("--tune", action="store_true",
@@ -178,6 +180,7 @@ def main():
     wsb = sb.workspace_bytes(w, h, prm)
     per_set = guide0.numel() * guide0.element_size() + w * h * 3 + w * h * 4 + wsb
     nsets = max(2, int(args.rotate_mb * 1e6 // per_set) + 1)
+    nsets += nsets % args.streams  # a buffer set is always reused on the same stream
     sets = []
     for _ in range(nsets):
         sets.append((guide0.clone(), torch.empty((h, w, 3), dtype=torch.uint8, device="cuda"),
@@ -189,29 +192,39 @@ def main():
     if args.tune:
         tune = at.tune_frame(style, guide0, jit, prm)["tune"]
 
-    def step(k, events=None):
+    # frames are enqueued round robin on `--streams` streams (each with its
+    # own buffer sets), so one frame's level loop overlaps the previous
+    # frame's vote: both kernels are latency-bound and leave issue slots idle
+    streams = [torch.cuda.Stream() for _ in range(args.streams)]
+
+    def step(k, events=None, stream=None):
         g, o_rgb, o_chunk, ws = sets[k % nsets]
-        sb.stylize(style, g, jit, prm, out_rgb=o_rgb, out_chunk=o_chunk, workspace=ws, tune=tune,
-                   events=events)
+        with torch.cuda.stream(stream if stream is not None else streams[k % args.streams]):
+            sb.stylize(style, g, jit, prm, out_rgb=o_rgb, out_chunk=o_chunk, workspace=ws,
+                       tune=tune, events=events)
 
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
+    def timed(nsteps, nstreams):
+        for k in range(args.warmup):
+            step(k, stream=streams[k % nstreams])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(nsteps):
+            step(k, stream=streams[k % nstreams])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
-    # timed region: exactly K steps
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(k)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    # one stream alone first (context for the per-frame latency), then the
+    # timed region: exactly K steps on all streams
+    single_s = timed(args.steps, 1)
+    elapsed = timed(args.steps, args.streams)
     ms_per_step = elapsed * 1e3 / args.steps
     mpx_s = w * h * args.steps / elapsed / 1e6
 
     # per-pass durations: fence-free HIP timing events recorded by the
-    # library between the passes, on the launch stream
+    # library between the passes, on one stream (frames one after another)
     evs = [sb.TimingEvents() for _ in range(args.steps)]
     for k in range(args.steps):
-        step(k, evs[k])
+        step(k, evs[k], stream=streams[0])
     torch.cuda.synchronize()
     passes = np.array([e.pass_ms() for e in evs])
     for e in evs:
@@ -311,7 +324,9 @@ def main():
         "config": {"workload": wname, "width": w, "height": h,
                    "source": f"{st_np.sw}x{st_np.sh}", "levels": p.levels, "finest": p.finest,
                    "threshold": p.threshold, "radius": p.radius, "buffer_sets": nsets,
-                   "tune": list(tune) if tune else "default"},
+                   "tune": list(tune) if tune else "default", "streams": args.streams},
+        "single_stream": {"ms_per_step": round(single_s * 1e3 / args.steps, 6),
+                          "value": round(w * h * args.steps / single_s / 1e6, 3)},
         "frame_latency_ms": {"p50": round(float(frame_ms[len(frame_ms) // 2]), 6),
                              "p99": round(float(frame_ms[min(len(frame_ms) - 1,
                                                              int(0.99 * len(frame_ms)))]), 6)},
