@@ -34,13 +34,21 @@ HBM_PEAK_GBS = 8000.0
 # VALU issue peak: 256 CUs x 4 SIMDs, each issuing one wave64 instruction
 # every 4 cycles (16 lanes per cycle), at 2.4 GHz = 614.4 G wave instructions/s
 VALU_PEAK_G_WAVE_INSTR = 256 * 2.4
-# counter summary of the voting kernel at 1080p (FETCH_SIZE / WRITE_SIZE per
-# dispatch and the copy-kernel calibration), valid for the kernel source it
-# names
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_1080p_traffic.json")
-# instruction counts of the per-frame kernels at 1080p (SQ_INSTS_VALU etc. per
-# dispatch), valid for the kernel source it names
-INSTR_FILE = os.path.join(ROOT, "profiles", "path_1080p_instructions.json")
+# counter summaries per workload, valid for the kernel source they name: the
+# voting kernel's FETCH_SIZE / WRITE_SIZE per dispatch with the copy-kernel
+# calibration, and the per-frame kernels' instruction counts (SQ_INSTS_VALU
+# etc. per dispatch)
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def traffic_file(workload_name):
+    return os.path.join(PROFILES, f"k_blend_{workload_name}_traffic.json")
+
+
+def instr_file(workload_name):
+    return os.path.join(PROFILES, f"path_{workload_name}_instructions.json")
+
+
 KERNEL_SRC = os.path.join(ROOT, "paper_1807_03249_amd", "csrc", "stylize.hip")
 
 
@@ -59,6 +67,11 @@ def vote_algorithmic_bytes(w, h, sw, sh):
     return w * h * 3 + sw * sh * 3
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_sha():
     with open(KERNEL_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -69,7 +82,7 @@ def traffic_per_launch(workload_name):
     None when it is missing, for another workload, or for older kernel
     source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(workload_name)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -98,7 +111,7 @@ def valu_issue(workload_name, kernel_prefix, kernel_ms):
     against the issue peak; None when the summary is missing, for another
     workload, or for older kernel source."""
     try:
-        with open(INSTR_FILE) as f:
+        with open(instr_file(workload_name)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -291,14 +304,21 @@ def main():
         cpu["cpu_model"] = cpu_model()
         cpu["host_cpus"] = os.cpu_count()
 
+    progress("main leg and CPU baseline done")
     seg = None if args.no_seg else seg_leg(sb, torch, np, workloads, st_np, fr, prm, ms_per_step)
+    progress("segmentation leg done")
     anim = None if args.no_anim else anim_leg(sb, torch, np, workloads, style, w, h, p)
+    progress("animation leg done")
     chan = None if args.no_channels else channels_leg(sb, torch, np, workloads, ms_per_step)
+    progress("three-channel leg done")
     batch = None if args.no_batch else batch_leg(sb, at, torch, workloads, args.no_tune)
+    progress("batch leg done")
     serve = None
     if not args.no_serve:
-        serve = [serve_leg(sb, torch, np, workloads, args.serve_requests, float(q))
-                 for q in args.serve_qps.split(",")]
+        serve = []
+        for q in args.serve_qps.split(","):
+            serve.append(serve_leg(sb, torch, np, workloads, args.serve_requests, float(q)))
+            progress(f"serving at {q} QPS done")
 
     if args.calibrate_copy_mb > 0:
         nb = int(args.calibrate_copy_mb * 1e6) // 4 * 4
