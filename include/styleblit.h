@@ -398,10 +398,13 @@ size_t sb_batch_workspace_bytes(const sb_frame *frames, int32_t n);
  * one descriptor half followed by persistent kernels (seed records,
  * per-pixel level loop, voting for radius 0..3 and for 4..7) that stride
  * over the concatenated tiles of all frames of the batch.  The graphs hold
- * no shapes, so they serve every later batch.  With use_graph == 0 the same
- * upload and kernels are enqueued directly on each run.  tune (may be NULL)
- * fixes the kernel choice of every run; blocks_per_cu (0 = 8, else 1..16)
- * sets the persistent grid to that many blocks per compute unit. */
+ * no shapes, so they serve every later batch.  With use_graph == 0 each run
+ * enqueues the upload and the same kernels directly, each with an exact
+ * grid (one workgroup per tile of the batch, no persistent loop), so batches
+ * on several streams interleave on the device as separate frames would.
+ * tune (may be NULL) fixes the kernel choice of every run; blocks_per_cu
+ * (0 = 8, else 1..16) sets the persistent grid of the graphs to that many
+ * blocks per compute unit. */
 int sb_batch_create(void *desc_dev, void *desc_host, int32_t use_graph, const sb_tune *tune,
                     int32_t blocks_per_cu, hipStream_t stream, sb_batch **out);
 /* Stylise n frames (1..sb_batch_max_frames()) with one graph launch on

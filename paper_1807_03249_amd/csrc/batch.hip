@@ -122,9 +122,11 @@ int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace
     if (!fill_frame(fr.style, fr.tgt_guide, fr.w, fr.h, fr.jitter, &fr.params, fr.out_rgb,
                     fr.out_chunk, fr.out_nnf, &args[f], fr.tgt_labels))
       return SB_EINVAL;
-    // the batch's seed pass is one persistent launch over every frame, so
-    // each record is built once there rather than per block
-    args[f].own_seeds = 0;
+    // graphs: the batch's seed pass is one persistent launch over every
+    // frame, so each record is built once there rather than per block;
+    // direct launches keep single frames' choice (records made in the level
+    // loop for 8-bit styles), which saves a pass and its wait
+    if (b->use_graph) args[f].own_seeds = 0;
     carve_workspace(&args[f], ws);
     ws += align256(sb_workspace_bytes(fr.w, fr.h, &fr.params));
   }
@@ -156,8 +158,12 @@ int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace
   if (b->use_graph) {
     e = hipGraphLaunch(b->exec[k], stream);
   } else {
+    // direct launches know the batch's shape: exact grids, one tile per
+    // workgroup, so kernels on other streams interleave with them
     e = hipMemcpyAsync(b->desc_dev[k], hd, batch_desc_bytes(), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = launch_batch(b->desc_dev[k], b->grid, b->tune, stream);
+    uint32_t totals[kBatchKinds];
+    for (int kind = 0; kind < kBatchKinds; ++kind) totals[kind] = pre[kind][n];
+    if (e == hipSuccess) e = launch_batch_exact(b->desc_dev[k], totals, b->tune, stream);
   }
   if (e == hipSuccess) e = hipEventRecord(b->done[k], stream);
   if (e != hipSuccess) {

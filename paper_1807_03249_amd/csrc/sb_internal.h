@@ -187,6 +187,10 @@ void tile_counts(const FrameArgs &a, const Tune &t, uint32_t counts[kBatchKinds]
 // The passes over a batch described at desc_dev, persistent grids.
 hipError_t launch_batch(const unsigned char *desc_dev, uint32_t grid, const Tune &t,
                         hipStream_t stream);
+// The same passes with exact grids: totals[kind] workgroups (the batch's
+// tiles of that pass), one tile each; passes without tiles are not launched.
+hipError_t launch_batch_exact(const unsigned char *desc_dev, const uint32_t totals[kBatchKinds],
+                              const Tune &t, hipStream_t stream);
 // Channel weights from the caller's three bytes (NULL or all zero: unit);
 // false if a weight exceeds 127 or a two-channel format gets non-unit ones.
 bool resolve_weights(int32_t fmt, const uint8_t *in, int32_t out[3]);

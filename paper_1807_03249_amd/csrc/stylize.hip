@@ -971,29 +971,47 @@ __device__ inline uint32_t frame_of(const uint32_t *pre, uint32_t n, uint32_t t)
   return lo;
 }
 
-// Batch pass KIND over the descriptor's frames; BODY(fa, local tile, work).
+// The arguments of frame f of a batch descriptor, read in place: the
+// descriptor is read-only for the whole launch and the frame index is
+// wave-uniform, so the compiler loads the fields the kernels use through the
+// scalar cache, as it does a single frame's kernel arguments.
+__device__ __forceinline__ const FrameArgs &batch_frame(const unsigned char *__restrict__ desc,
+                                                        uint32_t f) {
+  f = __builtin_amdgcn_readfirstlane(f);
+  return *reinterpret_cast<const FrameArgs *>(desc + batch_frames_offset() +
+                                              size_t(f) * sizeof(FrameArgs));
+}
+
+// Batch pass KIND over the descriptor's frames; BODY(frame args, local tile, work).
 template <int KIND, int NT, int WORDS, class Body>
-__device__ __forceinline__ void batch_loop(const unsigned char *desc, Body body) {
+__device__ __forceinline__ void batch_loop(const unsigned char *__restrict__ desc, Body body) {
   __shared__ __attribute__((aligned(16))) uint32_t work[WORDS];
   __shared__ uint32_t pre[kMaxBatchFrames + 1];
-  __shared__ FrameArgs fa;
   const BatchHeader *hd = reinterpret_cast<const BatchHeader *>(desc);
   const uint32_t n = hd->nframes;
   const uint32_t *gpre = reinterpret_cast<const uint32_t *>(desc + batch_prefix_offset(KIND));
   for (uint32_t i = threadIdx.x; i <= n; i += NT) pre[i] = gpre[i];
   __syncthreads();
   const uint32_t total = pre[n];
-  // XCD-aware order: runs of kXcdRun consecutive tiles go to the XCDs in
-  // turn, and the workgroups on XCD x (those with blockIdx mod 8 = x) stride
-  // through the runs of x, so an XCD's L2 serves neighbouring tiles while the
-  // runs keep the XCDs' shares balanced across the batch
-  // (a grid of fewer than 8 workgroups strides plainly: some XCDs would
-  // own runs but have no workgroup)
+  if (gridDim.x == total) {
+    // an exact grid (direct launches): one tile per workgroup, dealt to the
+    // XCDs by contiguous bands like a single frame's, and short-lived
+    // workgroups that other streams' kernels can interleave with
+    const uint32_t t = xcd_tile(blockIdx.x, total);
+    const uint32_t f = frame_of(pre, n, t);
+    body(batch_frame(desc, f), t - pre[f], work);
+    return;
+  }
+  // persistent grid: XCD-aware order: runs of kXcdRun consecutive tiles go to
+  // the XCDs in turn, and the workgroups on XCD x (those with blockIdx mod 8
+  // = x) stride through the runs of x, so an XCD's L2 serves neighbouring
+  // tiles while the runs keep the XCDs' shares balanced across the batch (a
+  // grid of fewer than 8 workgroups strides plainly: some XCDs would own
+  // runs but have no workgroup)
   constexpr uint32_t kXcdRun = 32;
   const bool xcd = gridDim.x >= 8u;
   const uint32_t x = xcd ? blockIdx.x & 7u : 0u, local = xcd ? blockIdx.x >> 3 : blockIdx.x;
   const uint32_t per = xcd ? (gridDim.x >> 3) + (x < (gridDim.x & 7u) ? 1u : 0u) : gridDim.x;
-  uint32_t cur = ~0u;
   for (uint32_t s = local;; s += per) {
     const uint32_t t = xcd ? ((s / kXcdRun) * 8u + x) * kXcdRun + s % kXcdRun : s;
     if (!xcd && t >= total) break;
@@ -1004,22 +1022,14 @@ __device__ __forceinline__ void batch_loop(const unsigned char *desc, Body body)
       continue;
     }
     const uint32_t f = frame_of(pre, n, t);
-    if (f != cur) {  // block-uniform
-      const uint32_t *src = reinterpret_cast<const uint32_t *>(desc + batch_frames_offset() +
-                                                               size_t(f) * sizeof(FrameArgs));
-      uint32_t *dst = reinterpret_cast<uint32_t *>(&fa);
-      __syncthreads();  // every thread is done with the previous frame's arguments
-      for (uint32_t i = threadIdx.x; i < sizeof(FrameArgs) / 4; i += NT) dst[i] = src[i];
-      __syncthreads();
-      cur = f;
-    }
-    body(fa, t - pre[f], work);
+    body(batch_frame(desc, f), t - pre[f], work);
     __syncthreads();  // the next tile restages its LDS
   }
 }
 
-__global__ void __launch_bounds__(256) k_batch_seeds(const unsigned char *desc) {
-  batch_loop<0, 256, 1>(desc, [](const FrameArgs &fa, uint32_t local, uint32_t *) {
+__global__ void __launch_bounds__(256) k_batch_seeds(const unsigned char *__restrict__ desc) {
+  batch_loop<0, 256, 1>(desc, [](const FrameArgs &fa, uint32_t local, uint32_t *)
+                                  __attribute__((always_inline)) {
     const uint32_t idx = local * 256 + threadIdx.x;
     if (fa.fmt == SB_GUIDE_U8X2) seeds_body<SB_GUIDE_U8X2>(fa, idx);
     else if (fa.fmt == SB_GUIDE_U8X3) seeds_body<SB_GUIDE_U8X3>(fa, idx);
@@ -1028,9 +1038,9 @@ __global__ void __launch_bounds__(256) k_batch_seeds(const unsigned char *desc) 
 }
 
 template <int G, int B>
-__global__ void __launch_bounds__(256) k_batch_assign(const unsigned char *desc) {
+__global__ void __launch_bounds__(256) k_batch_assign(const unsigned char *__restrict__ desc) {
   batch_loop<1, 256, 4 * wave_recs_words(B)>(desc, [](const FrameArgs &fa, uint32_t local,
-                                                     uint32_t *w) {
+                                                     uint32_t *w) __attribute__((always_inline)) {
     const bool seg = fa.tgt_labels != nullptr;
     if (fa.fmt == SB_GUIDE_U8X2) {
       if (seg) assign_tile<SB_GUIDE_U8X2, G, B, true>(fa, local, threadIdx.x, w);
@@ -1046,10 +1056,11 @@ __global__ void __launch_bounds__(256) k_batch_assign(const unsigned char *desc)
 }
 
 template <int PPT, int TH, int RLO, int RHI, bool SPLIT>
-__global__ void __launch_bounds__(16 * TH) k_batch_blend(const unsigned char *desc) {
+__global__ void __launch_bounds__(16 * TH) k_batch_blend(const unsigned char *__restrict__ desc) {
   constexpr int WORDS = blend_tile_words(PPT, TH, RHI, SPLIT);
   batch_loop<RLO == 0 ? 2 : 3, 16 * TH, WORDS>(desc, [](const FrameArgs &fa, uint32_t local,
-                                                        uint32_t *w) {
+                                                        uint32_t *w)
+                                                         __attribute__((always_inline)) {
     blend_tile_r<PPT, TH, RLO, RHI, SPLIT>(fa, local, threadIdx.x, reinterpret_cast<int32_t *>(w));
   });
 }
@@ -1108,6 +1119,21 @@ void launch_batch_blend_any(const unsigned char *desc, bool split, uint32_t grid
   else launch_batch_blend<PPT, TH, false>(desc, grid, stream);
 }
 
+template <int PPT, int TH, bool SPLIT>
+void launch_batch_blend_exact(const unsigned char *desc, const uint32_t *totals,
+                              hipStream_t stream) {
+  if (totals[2]) k_batch_blend<PPT, TH, 0, 3, SPLIT><<<totals[2], 16 * TH, 0, stream>>>(desc);
+  if (totals[3])
+    k_batch_blend<PPT, TH, 4, SB_MAX_RADIUS, SPLIT><<<totals[3], 16 * TH, 0, stream>>>(desc);
+}
+
+template <int PPT, int TH>
+void launch_batch_blend_exact_any(const unsigned char *desc, bool split, const uint32_t *totals,
+                                  hipStream_t stream) {
+  if (split) launch_batch_blend_exact<PPT, TH, true>(desc, totals, stream);
+  else launch_batch_blend_exact<PPT, TH, false>(desc, totals, stream);
+}
+
 }  // namespace
 
 hipError_t launch_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t *rgba,
@@ -1159,6 +1185,28 @@ hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, const Tune &t, hipEve
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[3], stream);
   if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_exact(const unsigned char *desc_dev, const uint32_t totals[kBatchKinds],
+                              const Tune &t, hipStream_t stream) {
+  if (totals[0]) k_batch_seeds<<<totals[0], 256, 0, stream>>>(desc_dev);
+  if (totals[1]) {
+    if (t.group == 4) {
+      if (t.apx == 4) k_batch_assign<4, 4><<<totals[1], 256, 0, stream>>>(desc_dev);
+      else if (t.apx == 2) k_batch_assign<4, 2><<<totals[1], 256, 0, stream>>>(desc_dev);
+      else k_batch_assign<4, 1><<<totals[1], 256, 0, stream>>>(desc_dev);
+    } else {
+      if (t.apx == 4) k_batch_assign<2, 4><<<totals[1], 256, 0, stream>>>(desc_dev);
+      else if (t.apx == 2) k_batch_assign<2, 2><<<totals[1], 256, 0, stream>>>(desc_dev);
+      else k_batch_assign<2, 1><<<totals[1], 256, 0, stream>>>(desc_dev);
+    }
+  }
+  const bool sp = t.split == 2;
+  if (t.ppt == 4 && t.rows == 16) launch_batch_blend_exact_any<4, 16>(desc_dev, sp, totals, stream);
+  else if (t.ppt == 4) launch_batch_blend_exact_any<4, 8>(desc_dev, sp, totals, stream);
+  else if (t.rows == 16) launch_batch_blend_exact_any<2, 16>(desc_dev, sp, totals, stream);
+  else launch_batch_blend_exact_any<2, 8>(desc_dev, sp, totals, stream);
   return hipGetLastError();
 }
 
