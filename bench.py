@@ -568,8 +568,20 @@ def batch_leg(sb, at, torch, workloads, no_tune, reps=5):
     def run_plain():
         sb.stylize_frames(jobs, workspace=plain_ws, tune=pick["tune"])
 
+    # the same per-frame launches split over two streams (halves of the list)
+    side = torch.cuda.Stream()
+    plain_ws2 = torch.empty_like(plain_ws)
+    half = len(jobs) // 2
+
+    def run_plain2():
+        side.wait_stream(torch.cuda.current_stream())
+        sb.stylize_frames(jobs[:half], workspace=plain_ws, tune=pick["tune"])
+        with torch.cuda.stream(side):
+            sb.stylize_frames(jobs[half:], workspace=plain_ws2, tune=pick["tune"])
+        torch.cuda.current_stream().wait_stream(side)
+
     out = {}
-    for name, fn in (("graph", run_batch), ("plain", run_plain)):
+    for name, fn in (("graph", run_batch), ("plain", run_plain), ("plain_2_streams", run_plain2)):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -600,7 +612,8 @@ def batch_leg(sb, at, torch, workloads, no_tune, reps=5):
     out["speedup"] = round(out["plain"]["ms_per_batch"] / out["graph"]["ms_per_batch"], 3)
     out["tune"] = list(pick["tune"]) if pick["tune"] else "default"
     out["blocks_per_cu"] = pick["blocks_per_cu"] or 8
-    out["plain_launch"] = "sb_stylize_frames (one C call, per-frame kernels, same tune)"
+    out["plain_launch"] = ("sb_stylize_frames (one C call, per-frame kernels, same tune); "
+                           "plain_2_streams: the two halves of the list on two streams")
     return out
 
 
@@ -630,11 +643,14 @@ def serve_leg(sb, torch, np, workloads, nreq, qps):
         px.append(w * h)
     px = np.array(px, dtype=np.float64)
     res = {"qps": qps, "requests": nreq, "budget_mib": 1024}
-    # continuous batching on 4 streams; the same 4 streams with one request
-    # per launch (per-request launches that still overlap); one stream, one
-    # request per launch, in arrival order
-    for name, kw in (("batched", dict(slots=4, max_batch=16, plain=False)),
-                     ("per_request_4", dict(slots=4, max_batch=1, plain=False)),
+    # continuous batching: 8 slots (streams), each taking up to 4 admitted
+    # requests per launch as direct launches with exact grids; the same on 4
+    # slots as captured graphs of up to 16; per-request launches on 8 slots
+    # (no batching, same overlap); one stream, one request per launch, in
+    # arrival order (the plain path)
+    for name, kw in (("batched", dict(slots=8, max_batch=4, use_graph=False)),
+                     ("batched_graph_4", dict(slots=4, max_batch=16, use_graph=True)),
+                     ("per_request_8", dict(slots=8, max_batch=1)),
                      ("plain", dict(plain=True))):
         out = sv.run(reqs, budget_bytes=1 << 30, **kw)
         summ = sv.summarize(out, pixels=px)
