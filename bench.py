@@ -524,7 +524,8 @@ def anim_leg(sb, torch, np, workloads, style, w, h, p, nframes=12, reps=5):
         rq = [sv.Request(a, style, guides[(k + s) % nframes], pool[(s * 13 + k) % len(pool)],
                          prm, session=s) for a, s, k in reqs]
         ent = {"sessions": nses, "fps": 60, "frames": len(rq)}
-        for name, kw in (("batched", dict(slots=4, max_batch=16)), ("plain", dict(plain=True))):
+        for name, kw in (("batched", dict(slots=8, max_batch=4, use_graph=False)),
+                         ("plain", dict(plain=True))):
             out = sv.run(rq, budget_bytes=1 << 30, **kw)
             summ = sv.summarize(out, pixels=np.full(len(rq), float(w * h)))
             order = all(np.all(np.diff(out["completed"][out["session"] == s]) >= 0)
