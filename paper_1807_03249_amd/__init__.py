@@ -391,6 +391,46 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     return out_rgb, out_chunk
 
 
+class FramePlan:
+    """One frame's sb_stylize_ex call with its arguments checked and
+    marshalled once (device tensors for guide, outputs and workspace), so a
+    loop over many frames pays only the C call per launch.  ``launch()``
+    enqueues the frame on torch's current stream (or on ``stream``, a raw
+    stream handle); the tensors must stay alive while the plan is used."""
+
+    def __init__(self, style: Style, tgt_guide, jitter, p: SbParams, out_rgb, out_chunk,
+                 workspace, tune=None):
+        torch = _torch()
+        for t in (tgt_guide, out_rgb, out_chunk, workspace):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("FramePlan takes contiguous device tensors only")
+        if _guide_fmt(torch, tgt_guide) != style.fmt:
+            raise TypeError("target guide format differs from the style's guide format")
+        h, w = int(tgt_guide.shape[0]), int(tgt_guide.shape[1])
+        if out_rgb.numel() != h * w * 3 or out_rgb.dtype != torch.uint8 \
+                or out_chunk.numel() != h * w or out_chunk.element_size() != 4:
+            raise ValueError("output tensors do not match the frame size")
+        self.params, self.jitter = _jitter_arg(torch, jitter, p, w, h)
+        wsb = workspace_bytes(w, h, self.params)
+        if workspace.numel() < wsb:
+            raise ValueError(f"workspace needs {wsb} bytes")
+        self.tune = tune_struct(tune)
+        self._keep = (style, tgt_guide, out_rgb, out_chunk, workspace)
+        self._fn = lib().sb_stylize_ex
+        self._args = (ctypes.byref(style.c), tgt_guide.data_ptr(), w, h,
+                      self.jitter.data_ptr() if self.jitter is not None else None,
+                      ctypes.byref(self.params), out_rgb.data_ptr(), out_chunk.data_ptr(), None,
+                      workspace.data_ptr(), workspace.numel(),
+                      ctypes.byref(self.tune) if self.tune is not None else None)
+        self._torch = torch
+
+    def launch(self, stream=None):
+        s = self._torch.cuda.current_stream().cuda_stream if stream is None else stream
+        rc = self._fn(*self._args, s)
+        if rc != SB_OK:
+            _check(rc, "sb_stylize_ex")
+
+
 def stylize_noalloc(style: Style, tgt_guide, jitter, p: SbParams, out_rgb, out_chunk,
                     out_nnf=None):
     """Stylise one frame through sb_stylize_noalloc (no workspace: the

@@ -322,3 +322,33 @@ def test_library_owned_style(sb):
     np.testing.assert_array_equal(u32(nnf), e_nnf)
     np.testing.assert_array_equal(to_np(rgb), e_rgb)
     assert sb.lib().sb_style_destroy(h) == sb.SB_OK
+
+
+def test_frame_plan_equals_stylize():
+    """FramePlan (arguments marshalled once, one C call per launch) gives the
+    frame sb_stylize gives, on the current stream and on an explicit one."""
+    import torch
+
+    import paper_1807_03249_amd as sb
+
+    styles, frames = workloads.config(2)
+    st_np, fr = styles[0], frames[0]
+    p = fr.params
+    style = sb.Style(st_np.rgb, st_np.guide, st_np.lut_bits)
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
+    g = torch.from_numpy(fr.guide).cuda()
+    e_rgb, e_chunk = sb.stylize(style, g, None, prm)
+    ws = torch.empty(sb.workspace_bytes(fr.w, fr.h, prm), dtype=torch.uint8, device="cuda")
+    for tune in (None, (2, 8, 4, 1, 1)):
+        rgb = torch.empty_like(e_rgb)
+        chunk = torch.empty_like(e_chunk)
+        plan = sb.FramePlan(style, g, None, prm, rgb, chunk, ws, tune=tune)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(rgb, e_rgb) and torch.equal(chunk, e_chunk)
+        s = torch.cuda.Stream()
+        rgb.zero_()
+        torch.cuda.synchronize()
+        plan.launch(s.cuda_stream)
+        s.synchronize()
+        assert torch.equal(rgb, e_rgb) and torch.equal(chunk, e_chunk)
