@@ -32,7 +32,15 @@ adversarial third channel that alone decides acceptance, and the level
 loop's invariants with the three-channel error.  Channel weights (the
 strong or weak appearance guide) are pinned by a weighted vectorised argmin,
 a zero weight that reduces the path to the first two channels, and uniform
-weights that only rescale the threshold.  The counter-based jitter
+weights that only rescale the threshold.  Guides of 2..8 channels of 8 or 16 bits
+(formats 3 and 4, each lookup an exact nearest-pixel search, the search the
+paper suggests for additional channels) are pinned in
+``tests/test_oracle_search.py``: the lookup against the pinned two- and
+three-channel tables, a closed form with ties at 16 bits, zero-weight
+channel removal and channel permutations, the channel-0 sweep against brute
+force; the level loop against the pinned two- and three-channel paths,
+texture mapping at t = 0, a translation with a closed-form NNF, and its
+invariants.  The counter-based jitter
 generator (Philox4x64-10, from its published definition) is pinned block for
 block against numpy's own Philox bit generator (``tests/test_oracle_rng.py``).
 """
@@ -111,6 +119,13 @@ def _load():
     lib.ora_stylize_seg.argtypes = [_u8p, vp, _u8p, i32, i32, _u32p, i32, i32, i32, vp, _u8p,
                                     i32, i32, _u32p, i32, i32, ctypes.c_uint32, i32, _u8p, _u32p,
                                     _u32p]
+    lib.ora_texel_bytes.argtypes = [i32, i32]
+    lib.ora_nn_query_n.argtypes = [vp, i32, i32, i32, i32, _u8p, vp, ctypes.c_int64, _u32p]
+    lib.ora_nn_sweep_n.argtypes = [vp, i32, i32, i32, i32, _u8p, vp, ctypes.c_int64, _u32p]
+    lib.ora_assign_n.argtypes = [vp, i32, i32, i32, i32, _u8p, vp, i32, i32, _u32p, i32, i32,
+                                 ctypes.c_uint32, _u32p, _u32p]
+    lib.ora_stylize_n.argtypes = [_u8p, vp, i32, i32, i32, i32, _u8p, vp, i32, i32, _u32p, i32,
+                                  i32, ctypes.c_uint32, i32, _u8p, _u32p, _u32p]
     _lib = lib
     return lib
 
@@ -415,3 +430,102 @@ def frame_change(chunk_a, chunk_b, nnf_a=None, nnf_b=None) -> Tuple[int, int]:
     if na.shape != a.shape or nb.shape != a.shape:
         raise ValueError("frames differ in size")
     return code, int(np.count_nonzero(na != nb))
+
+
+# ----------------------------------------------- guides of many channels
+
+def texel_bytes(depth: int, channels: int) -> int:
+    """Bytes per texel of a ``channels``-channel guide of ``depth`` bits (4, 8
+    or 16: the smallest that holds them); 0 if invalid."""
+    return int(_load().ora_texel_bytes(depth, channels))
+
+
+def _guide_n(g: np.ndarray, channels: int) -> Tuple[np.ndarray, int]:
+    """Texels of a many-channel guide and its depth: (rows, cols, E) uint8
+    or uint16 with E elements per texel, E * element bytes = the texel size
+    of ``channels`` channels (elements past ``channels`` are ignored)."""
+    g = np.ascontiguousarray(g)
+    if g.ndim != 3 or g.dtype not in (np.uint8, np.uint16):
+        raise ValueError("a many-channel guide is (rows, cols, elements) uint8 or uint16")
+    depth = 8 * g.dtype.itemsize
+    tb = texel_bytes(depth, channels)
+    if tb == 0 or g.shape[2] * g.dtype.itemsize != tb:
+        raise ValueError(f"{channels} channels of {depth} bits need {tb}-byte texels")
+    return g, depth
+
+
+def _weights_n(weights, channels: int):
+    if weights is None:
+        return None, None
+    w = np.zeros(8, np.uint8)
+    v = np.asarray(weights, dtype=np.int64).ravel()
+    if v.size != channels or v.min() < 0 or v.max() > 255:
+        raise ValueError(f"weights must hold {channels} values")
+    w[:channels] = v
+    return w, _ptr(w, _u8p)
+
+
+def nn_query_n(src_guide, channels: int, queries, weights=None) -> np.ndarray:
+    """Exact lookups of query texels ((..., E) in the guide's layout) by brute
+    force over every source pixel: the argmin of sum_k w_k (q_k - G_S[u]_k)^2,
+    ties to the smallest raster index.  Returns x | y << 16 per query."""
+    gs, depth = _guide_n(src_guide, channels)
+    q = np.ascontiguousarray(queries, dtype=gs.dtype).reshape(-1, gs.shape[2])
+    out = np.zeros(q.shape[0], np.uint32)
+    w, wp = _weights_n(weights, channels)
+    _check(_load().ora_nn_query_n(gs.ctypes.data, depth, channels, gs.shape[1], gs.shape[0], wp,
+                                 q.ctypes.data, q.shape[0], _ptr(out, _u32p)), "nn_query_n")
+    return out
+
+
+def nn_sweep_n(src_guide, channels: int, queries, weights=None) -> np.ndarray:
+    """The same lookups as ``nn_query_n``, walking the source pixels outward
+    along channel 0 with an exact stopping bound."""
+    gs, depth = _guide_n(src_guide, channels)
+    q = np.ascontiguousarray(queries, dtype=gs.dtype).reshape(-1, gs.shape[2])
+    out = np.zeros(q.shape[0], np.uint32)
+    w, wp = _weights_n(weights, channels)
+    _check(_load().ora_nn_sweep_n(gs.ctypes.data, depth, channels, gs.shape[1], gs.shape[0], wp,
+                                  q.ctypes.data, q.shape[0], _ptr(out, _u32p)), "nn_sweep_n")
+    return out
+
+
+def assign_n(src_guide, channels: int, tgt_guide, jitter, levels, finest, threshold,
+             weights=None, seed=None):
+    """Level loop with a many-channel guide (exact search lookups): returns
+    (nnf, chunk), both uint32 (H, W)."""
+    gs, depth = _guide_n(src_guide, channels)
+    gt, depth_t = _guide_n(tgt_guide, channels)
+    if depth != depth_t:
+        raise ValueError("source and target guide depths differ")
+    h, w = gt.shape[:2]
+    j = _jit(jitter, w, h, levels, finest, seed)
+    nnf = np.zeros((h, w), np.uint32)
+    chunk = np.zeros((h, w), np.uint32)
+    wt, wp = _weights_n(weights, channels)
+    _check(_load().ora_assign_n(gs.ctypes.data, gs.shape[1], gs.shape[0], depth, channels, wp,
+                                gt.ctypes.data, w, h, _ptr(j, _u32p), levels, finest, threshold,
+                                _ptr(nnf, _u32p), _ptr(chunk, _u32p)), "assign_n")
+    return nnf, chunk
+
+
+def stylize_n(src_rgb, src_guide, channels: int, tgt_guide, jitter, levels, finest, threshold,
+              radius, weights=None, seed=None):
+    """The whole per-frame path with a many-channel guide: returns (rgb,
+    chunk, nnf) as ``stylize``."""
+    gs, depth = _guide_n(src_guide, channels)
+    gt, depth_t = _guide_n(tgt_guide, channels)
+    if depth != depth_t:
+        raise ValueError("source and target guide depths differ")
+    rgb = np.ascontiguousarray(src_rgb, dtype=np.uint8)
+    h, w = gt.shape[:2]
+    j = _jit(jitter, w, h, levels, finest, seed)
+    out = np.zeros((h, w, 3), np.uint8)
+    chunk = np.zeros((h, w), np.uint32)
+    nnf = np.zeros((h, w), np.uint32)
+    wt, wp = _weights_n(weights, channels)
+    _check(_load().ora_stylize_n(_ptr(rgb, _u8p), gs.ctypes.data, gs.shape[1], gs.shape[0], depth,
+                                 channels, wp, gt.ctypes.data, w, h, _ptr(j, _u32p), levels,
+                                 finest, threshold, radius, _ptr(out, _u8p), _ptr(chunk, _u32p),
+                                 _ptr(nnf, _u32p)), "stylize_n")
+    return out, chunk, nnf

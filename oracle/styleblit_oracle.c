@@ -61,6 +61,12 @@
  * each channel's squared difference, in the table's argmin and in the
  * error alike: e = sum_k w_k (a_k - b_k)^2.  Unit weights are the plain
  * case; two-channel formats take unit weights only.
+ *
+ * Guides of 2..8 channels of 8 or 16 bits (fmt 3 and 4, at the end of this
+ * file) take the search the paper suggests literally, as an exact one: each
+ * lookup is the nearest source pixel over the raw channel values (no
+ * table, no quantisation), ties to the smallest raster index, with optional
+ * channel weights 0..127.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -874,5 +880,277 @@ int ora_stylize_seg(const uint8_t *src_rgb, const void *src_guide, const uint8_t
                             tgt_labels, w, h, jitter, levels, finest, threshold, nnf, out_chunk);
     if (rc == ORA_OK) rc = ora_blend(src_rgb, sw, sh, nnf, w, h, radius, out_rgb, 0, -1);
     if (!out_nnf) free(nnf);
+    return rc;
+}
+
+/* ------------------------------------ guides of many channels, exact search
+ *
+ * The additional guiding channels of Sec. 3.1, where the paper suggests a
+ * search tree instead of a table: a guide of C = 2..8 channels of depth 8
+ * (fmt 3) or 16 bits (fmt 4).  Pixel i's channels are elements 0..C-1 of
+ * its texel of S bytes, S the smallest of 4, 8 and 16 that holds C channels;
+ * elements past C are ignored.  Read as an exact search with no
+ * quantisation: the lookup of a guide value g is
+ *     u*(g) = argmin over source pixels u of sum_k w_k (g_k - G_S[u]_k)^2,
+ * ties to the smallest raster index, with integer weights w_k in 0..127
+ * (NULL or all zero: unit).  The guide error of the level loop is the same
+ * weighted sum, accepted iff it is < t; everything else (seeds, NearestSeed,
+ * the fallback to the pixel's own lookup, voting) is the plain path's.
+ */
+
+/* Bytes per texel of a C-channel guide of the given depth; 0 if invalid. */
+int ora_texel_bytes(int depth, int channels)
+{
+    if ((depth != 8 && depth != 16) || channels < 2 || channels > 8) return 0;
+    const int bytes = channels * depth / 8;
+    return bytes <= 4 ? 4 : bytes <= 8 ? 8 : 16;
+}
+
+typedef struct {
+    const void *g;   /* texels */
+    int depth, channels, stride;
+} guide_n_t;
+
+static int64_t chan_n(const guide_n_t *G, int64_t idx, int k)
+{
+    const uint8_t *p = (const uint8_t *)G->g + idx * G->stride;
+    if (G->depth == 8) return p[k];
+    uint16_t v;
+    memcpy(&v, p + 2 * k, 2);
+    return v;
+}
+
+/* Weights of a many-channel guide: NULL or all zero = unit; else 0..127. */
+static int weights_get_n(const uint8_t *weights, int channels, int64_t *w)
+{
+    int any = 0;
+    for (int k = 0; k < 8; ++k) w[k] = 1;
+    if (!weights) return ORA_OK;
+    for (int k = 0; k < channels; ++k) any |= weights[k] != 0;
+    if (!any) return ORA_OK;
+    for (int k = 0; k < channels; ++k) {
+        if (weights[k] > 127) return ORA_EINVAL;
+        w[k] = weights[k];
+    }
+    return ORA_OK;
+}
+
+/* sum_k w_k (a_k - b_k)^2 between texel ia of A and texel ib of B. */
+static uint64_t dist_n(const guide_n_t *A, int64_t ia, const guide_n_t *B, int64_t ib,
+                       const int64_t *w)
+{
+    uint64_t d = 0;
+    for (int k = 0; k < A->channels; ++k) {
+        const int64_t e = chan_n(A, ia, k) - chan_n(B, ib, k);
+        d += (uint64_t)w[k] * (uint64_t)(e * e);
+    }
+    return d;
+}
+
+static int guide_n_make(const void *g, int depth, int channels, guide_n_t *G)
+{
+    G->g = g;
+    G->depth = depth;
+    G->channels = channels;
+    G->stride = ora_texel_bytes(depth, channels);
+    return g && G->stride ? ORA_OK : ORA_EINVAL;
+}
+
+static uint32_t pack_src(int64_t i, int sw)
+{
+    return (uint32_t)(i % sw) | ((uint32_t)(i / sw) << 16);
+}
+
+/* The lookup of every query texel by brute force over every source pixel in
+ * raster order with a strict compare (the definition). */
+int ora_nn_query_n(const void *src_guide, int depth, int channels, int sw, int sh,
+                   const uint8_t *weights, const void *queries, int64_t nq, uint32_t *out)
+{
+    guide_n_t S, Q;
+    int64_t w[8];
+    if (sw < 1 || sh < 1 || !out || nq < 0) return ORA_EINVAL;
+    if (guide_n_make(src_guide, depth, channels, &S) || guide_n_make(queries, depth, channels, &Q))
+        return ORA_EINVAL;
+    if (weights_get_n(weights, channels, w)) return ORA_EINVAL;
+    const int64_t npix = (int64_t)sw * sh;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < nq; ++j) {
+        uint64_t best_d = UINT64_MAX;
+        int64_t best_i = -1;
+        for (int64_t i = 0; i < npix; ++i) {
+            const uint64_t d = dist_n(&Q, j, &S, i, w);
+            if (d < best_d) {
+                best_d = d;
+                best_i = i;
+            }
+        }
+        out[j] = pack_src(best_i, sw);
+    }
+    return ORA_OK;
+}
+
+/* Source pixels grouped by their channel-0 value (raster order within a
+ * group), for the sweep below. */
+typedef struct {
+    int64_t nv;       /* channel-0 values: 2^depth */
+    int64_t *start;   /* nv + 1 group starts */
+    int64_t *order;   /* raster indices by group */
+} sweep_t;
+
+static void sweep_free(sweep_t *T)
+{
+    free(T->start);
+    free(T->order);
+}
+
+static int sweep_make(const guide_n_t *S, int64_t npix, sweep_t *T)
+{
+    T->nv = (int64_t)1 << S->depth;
+    T->start = (int64_t *)calloc((size_t)(T->nv + 1), sizeof(int64_t));
+    T->order = (int64_t *)malloc((size_t)npix * sizeof(int64_t));
+    int64_t *fill = (int64_t *)malloc((size_t)T->nv * sizeof(int64_t));
+    if (!T->start || !T->order || !fill) {
+        free(fill);
+        sweep_free(T);
+        return ORA_ENOMEM;
+    }
+    for (int64_t i = 0; i < npix; ++i) T->start[chan_n(S, i, 0) + 1]++;
+    for (int64_t v = 0; v < T->nv; ++v) T->start[v + 1] += T->start[v];
+    memcpy(fill, T->start, (size_t)T->nv * sizeof(int64_t));
+    for (int64_t i = 0; i < npix; ++i) T->order[fill[chan_n(S, i, 0)]++] = i;
+    free(fill);
+    return ORA_OK;
+}
+
+/* The lookup of texel j of Q: the groups are visited outward from the
+ * query's channel-0 value v0, at distance k = 0, 1, 2, ...; a group at
+ * distance k holds only pixels at weighted squared distance >= w0 k^2, so the
+ * walk stops once that bound exceeds the best distance (strictly: a pixel at
+ * equal distance with a smaller raster index must still be seen).  Ties to
+ * the smallest raster index, as in the definition. */
+static uint32_t sweep_query(const guide_n_t *S, int sw, const sweep_t *T, const guide_n_t *Q,
+                            int64_t j, const int64_t *w)
+{
+    const int64_t v0 = chan_n(Q, j, 0);
+    uint64_t best_d = UINT64_MAX;
+    int64_t best_i = -1;
+    for (int64_t k = 0; k < T->nv; ++k) {
+        if (best_i >= 0 && (uint64_t)w[0] * (uint64_t)(k * k) > best_d) break;
+        for (int side = 0; side < (k == 0 ? 1 : 2); ++side) {
+            const int64_t v = side == 0 ? v0 - k : v0 + k;
+            if (v < 0 || v >= T->nv) continue;
+            for (int64_t e = T->start[v]; e < T->start[v + 1]; ++e) {
+                const int64_t i = T->order[e];
+                const uint64_t d = dist_n(Q, j, S, i, w);
+                if (d < best_d || (d == best_d && i < best_i)) {
+                    best_d = d;
+                    best_i = i;
+                }
+            }
+        }
+    }
+    return pack_src(best_i, sw);
+}
+
+/* The same lookups as ora_nn_query_n, by the channel-0 sweep. */
+int ora_nn_sweep_n(const void *src_guide, int depth, int channels, int sw, int sh,
+                   const uint8_t *weights, const void *queries, int64_t nq, uint32_t *out)
+{
+    guide_n_t S, Q;
+    sweep_t T;
+    int64_t w[8];
+    if (sw < 1 || sh < 1 || !out || nq < 0) return ORA_EINVAL;
+    if (guide_n_make(src_guide, depth, channels, &S) || guide_n_make(queries, depth, channels, &Q))
+        return ORA_EINVAL;
+    if (weights_get_n(weights, channels, w)) return ORA_EINVAL;
+    if (sweep_make(&S, (int64_t)sw * sh, &T)) return ORA_ENOMEM;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < nq; ++j) out[j] = sweep_query(&S, sw, &T, &Q, j, w);
+    sweep_free(&T);
+    return ORA_OK;
+}
+
+/* The level loop (Algorithm 2) with a many-channel guide: as assign_pixel,
+ * with u* the exact search above.  Each seed's lookup is a function of the
+ * seed alone, so it is found once per seed (seed_u, per level and cell, in
+ * the jitter table's order) and read by every pixel whose NearestSeed it is;
+ * the fallback searches per pixel. */
+int ora_assign_n(const void *src_guide, int sw, int sh, int depth, int channels,
+                 const uint8_t *weights, const void *tgt_guide, int w, int h,
+                 const uint32_t *jitter, int levels, int finest, uint32_t threshold,
+                 uint32_t *out_nnf, uint32_t *out_chunk)
+{
+    guide_n_t S, T;
+    int64_t wt[8];
+    if (sw < 1 || sh < 1 || sw > 8192 || sh > 8192 || w < 1 || h < 1 || w > 8192 || h > 8192)
+        return ORA_EINVAL;
+    if (levels < 0 || levels > 12 || finest < 1 || (finest & (finest - 1)) != 0) return ORA_EINVAL;
+    if (levels > 0 && ((int64_t)finest << (levels - 1)) > 8192) return ORA_EINVAL;
+    if (levels > 0 && !jitter) return ORA_EINVAL;
+    if (!out_nnf || !out_chunk) return ORA_EINVAL;
+    if (guide_n_make(src_guide, depth, channels, &S) || guide_n_make(tgt_guide, depth, channels, &T))
+        return ORA_EINVAL;
+    if (weights_get_n(weights, channels, wt)) return ORA_EINVAL;
+    const seeds_t sd = {w, h, levels, finest, jitter};
+    sweep_t sweep;
+    if (sweep_make(&S, (int64_t)sw * sh, &sweep)) return ORA_ENOMEM;
+    const int64_t nseeds = levels > 0 ? level_offset(&sd, levels) : 0;
+    uint32_t *seed_u = (uint32_t *)malloc((size_t)(nseeds > 0 ? nseeds : 1) * sizeof(uint32_t));
+    if (!seed_u) {
+        sweep_free(&sweep);
+        return ORA_ENOMEM;
+    }
+    /* the lookup of every in-target seed */
+    for (int i = 0; i < levels; ++i) {
+        const int64_t ncx = cells_x(&sd, i), ncy = cells_y(&sd, i), base = level_offset(&sd, i);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t c = 0; c < ncx * ncy; ++c) {
+            int64_t sx, sy;
+            seed_u[base + c] = 0;
+            if (seed_point(&sd, i, c % ncx, c / ncx, &sx, &sy))
+                seed_u[base + c] = sweep_query(&S, sw, &sweep, &T, sy * w + sx, wt);
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t py = 0; py < h; ++py) {
+        for (int64_t px = 0; px < w; ++px) {
+            const int64_t p = py * w + px;
+            int done = 0;
+            for (int i = 0; i < levels && !done; ++i) {
+                int64_t qx, qy;
+                if (!nearest_seed(&sd, i, px, py, &qx, &qy)) continue;
+                const int64_t hsp = level_spacing(&sd, i);
+                const int64_t cell = level_offset(&sd, i) + (qy / hsp) * cells_x(&sd, i) + qx / hsp;
+                const uint32_t u = seed_u[cell];
+                const int64_t vx = (int64_t)(u & 0xFFFFu) + (px - qx);
+                const int64_t vy = (int64_t)(u >> 16) + (py - qy);
+                if (vx < 0 || vy < 0 || vx >= sw || vy >= sh) continue;
+                if (dist_n(&T, p, &S, vy * sw + vx, wt) < (uint64_t)threshold) {
+                    out_nnf[p] = (uint32_t)vx | ((uint32_t)vy << 16);
+                    out_chunk[p] = ((uint32_t)i << 26) | ((uint32_t)qy << 13) | (uint32_t)qx;
+                    done = 1;
+                }
+            }
+            if (!done) {
+                out_nnf[p] = sweep_query(&S, sw, &sweep, &T, p, wt);
+                out_chunk[p] = ((uint32_t)levels << 26) | ((uint32_t)py << 13) | (uint32_t)px;
+            }
+        }
+    }
+    free(seed_u);
+    sweep_free(&sweep);
+    return ORA_OK;
+}
+
+/* The whole path with a many-channel guide: ora_assign_n, then the vote. */
+int ora_stylize_n(const uint8_t *src_rgb, const void *src_guide, int sw, int sh, int depth,
+                  int channels, const uint8_t *weights, const void *tgt_guide, int w, int h,
+                  const uint32_t *jitter, int levels, int finest, uint32_t threshold, int radius,
+                  uint8_t *out_rgb, uint32_t *out_chunk, uint32_t *out_nnf)
+{
+    if (!out_rgb || !out_chunk || !out_nnf) return ORA_EINVAL;
+    int rc = ora_assign_n(src_guide, sw, sh, depth, channels, weights, tgt_guide, w, h, jitter,
+                          levels, finest, threshold, out_nnf, out_chunk);
+    if (rc == ORA_OK) rc = ora_blend(src_rgb, sw, sh, out_nnf, w, h, radius, out_rgb, 0, -1);
     return rc;
 }

@@ -33,6 +33,14 @@ int ora_stylize_seg_w(const uint8_t *, const void *, const uint8_t *, int, int, 
 int ora_blend(const uint8_t *, int, int, const uint32_t *, int, int, int, uint8_t *, int64_t,
               int64_t);
 int ora_set_threads(int);
+int ora_texel_bytes(int, int);
+int ora_nn_query_n(const void *, int, int, int, int, const uint8_t *, const void *, int64_t,
+                   uint32_t *);
+int ora_nn_sweep_n(const void *, int, int, int, int, const uint8_t *, const void *, int64_t,
+                   uint32_t *);
+int ora_stylize_n(const uint8_t *, const void *, int, int, int, int, const uint8_t *,
+                  const void *, int, int, const uint32_t *, int, int, uint32_t, int, uint8_t *,
+                  uint32_t *, uint32_t *);
 
 static uint64_t rng = 0x9E3779B97F4A7C15ull;
 static uint32_t next32(void) {
@@ -186,6 +194,45 @@ int main(void) {
       }
       style_free(&S);
     }
+  }
+  /* guides of many channels: every depth and channel count, exact-size
+     texel buffers, lookups and whole frames */
+  for (int depth = 8; depth <= 16; depth += 8) {
+    for (int ch = 2; ch <= 8; ++ch) {
+      const int tb = ora_texel_bytes(depth, ch);
+      const int sw = 3 + (int)(next32() % 20), sh = 1 + (int)(next32() % 12);
+      const int w = 1 + (int)(next32() % 40), h = 1 + (int)(next32() % 24);
+      uint8_t *sg = fill_random((size_t)sw * sh * tb);
+      uint8_t *srgb = fill_random((size_t)sw * sh * 3);
+      uint8_t *tg = fill_random((size_t)w * h * tb);
+      uint8_t *wts = fill_random(8);
+      for (int k = 0; k < 8; ++k) wts[k] &= 127;
+      uint32_t *qo = (uint32_t *)malloc((size_t)w * h * 4);
+      uint32_t *qs = (uint32_t *)malloc((size_t)w * h * 4);
+      EXPECT(ora_nn_query_n(sg, depth, ch, sw, sh, wts, tg, (int64_t)w * h, qo), 0);
+      EXPECT(ora_nn_sweep_n(sg, depth, ch, sw, sh, wts, tg, (int64_t)w * h, qs), 0);
+      if (memcmp(qo, qs, (size_t)w * h * 4) != 0) {
+        fprintf(stderr, "sweep differs from brute force (depth %d, %d channels)\n", depth, ch);
+        ++failures;
+      }
+      const int levels = (int)(next32() % 4), finest = 1 << (next32() % 3);
+      const int64_t nj = ora_jitter_len(w, h, levels, finest);
+      uint32_t *jit = (uint32_t *)malloc((size_t)(nj > 0 ? nj : 1) * 4);
+      EXPECT(ora_jitter_hash(w, h, levels, finest, next32(), jit), 0);
+      uint8_t *out_rgb = (uint8_t *)malloc((size_t)w * h * 3);
+      uint32_t *chunk = (uint32_t *)malloc((size_t)w * h * 4);
+      uint32_t *nnf = (uint32_t *)malloc((size_t)w * h * 4);
+      EXPECT(ora_stylize_n(srgb, sg, sw, sh, depth, ch, (ch & 1) ? wts : NULL, tg, w, h, jit,
+                           levels, finest, next32() % 5000, (int)(next32() % 4), out_rgb, chunk,
+                           nnf),
+             0);
+      free(sg); free(srgb); free(tg); free(wts); free(qo); free(qs); free(jit);
+      free(out_rgb); free(chunk); free(nnf);
+    }
+  }
+  if (ora_texel_bytes(8, 9) != 0 || ora_texel_bytes(10, 3) != 0) {
+    fprintf(stderr, "bad many-channel layout accepted\n");
+    ++failures;
   }
   /* invalid arguments are refused without touching memory */
   uint32_t dummy = 0;

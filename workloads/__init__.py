@@ -10,6 +10,8 @@ from .gen import (  # noqa: F401
     GUIDE_U8X2,
     GUIDE_U16X2,
     GUIDE_U8X3,
+    GUIDE_U8XN,
+    GUIDE_U16XN,
     Frame,
     Style,
     Params,
@@ -28,6 +30,14 @@ from .gen import (  # noqa: F401
     guide_u8x3,
     appearance_target,
     APPEARANCE_PARAMS,
+    texel_elements,
+    guide_n,
+    chroma_u8,
+    features_u8,
+    features_u16,
+    features_target,
+    FEATURE_PARAMS,
+    FEATURE16_PARAMS,
     config,
     CONFIG_NAMES,
 )

@@ -15,6 +15,10 @@ Conventions shared by both consumers (oracle and HIP library):
   (format ``GUIDE_U16X2``), or three ``uint8`` channels stored in four bytes
   per pixel, the fourth zero (format ``GUIDE_U8X3``: a normal pair plus an
   appearance channel);
+* a guide of C = 2..8 channels of 8 bits (format ``GUIDE_U8XN``) or 16 bits
+  (format ``GUIDE_U16XN``) stores each pixel's channels in order in a texel
+  of 4, 8 or 16 bytes (the smallest that holds them), the rest zero:
+  ``(rows, cols, elements)`` of uint8 or uint16;
 * the seed hierarchy has ``levels`` levels with spacings
   ``finest << (levels - 1 - i)`` for level i = 0 (coarsest) ... levels-1;
 * level i's jitter table covers ``ceil(W/h) x ceil(H/h)`` cells, row-major,
@@ -31,6 +35,8 @@ import numpy as np
 GUIDE_U8X2 = 0
 GUIDE_U16X2 = 1
 GUIDE_U8X3 = 2
+GUIDE_U8XN = 3
+GUIDE_U16XN = 4
 
 
 @dataclasses.dataclass
@@ -271,6 +277,59 @@ def guide_u8x3(two: np.ndarray, third: np.ndarray) -> np.ndarray:
     return out
 
 
+def texel_elements(depth: int, channels: int) -> int:
+    """Elements per texel of a ``channels``-channel guide of ``depth`` bits."""
+    b = channels * depth // 8
+    return (4 if b <= 4 else 8 if b <= 8 else 16) * 8 // depth
+
+
+def guide_n(chans, depth: int) -> np.ndarray:
+    """A many-channel guide in its storage layout from a list of C (rows,
+    cols) channel arrays: (rows, cols, elements) of uint8 (depth 8) or
+    uint16 (depth 16), channel k in element k, the rest zero."""
+    h, w = np.asarray(chans[0]).shape
+    dt = np.uint8 if depth == 8 else np.uint16
+    out = np.zeros((h, w, texel_elements(depth, len(chans))), dt)
+    for k, c in enumerate(chans):
+        out[..., k] = c
+    return out
+
+
+def _box_mean_u8(v: np.ndarray, radius: int) -> np.ndarray:
+    """Integer box average over a (2 radius + 1)^2 window clamped at the
+    borders, rounded to nearest."""
+    h, w = v.shape
+    k = 2 * radius + 1
+    pad = np.pad(v.astype(np.int64), radius, mode="edge")
+    c = np.zeros((h + 2 * radius + 1, w + 2 * radius + 1), np.int64)
+    c[1:, 1:] = pad.cumsum(0).cumsum(1)
+    box = c[k:, k:] - c[:-k, k:] - c[k:, :-k] + c[:-k, :-k]
+    return ((box + k * k // 2) // (k * k)).astype(np.uint8)
+
+
+def chroma_u8(rgb: np.ndarray, radius: int):
+    """Two opponent-colour channels of an image, box-averaged like the
+    appearance channel: (R - G + 255) / 2 and (R + G - 2 B + 510) / 4, in
+    integers."""
+    r, g, b = (rgb[..., k].astype(np.int64) for k in range(3))
+    return (_box_mean_u8((r - g + 255) // 2, radius),
+            _box_mean_u8((r + g - 2 * b + 510) // 4, radius))
+
+
+def features_u8(rgb: np.ndarray, normals: np.ndarray) -> np.ndarray:
+    """Five 8-bit guide channels: a normal pair, the appearance channel and
+    the two chroma channels of ``rgb`` (8-byte texels)."""
+    c1, c2 = chroma_u8(rgb, 4)
+    return guide_n([normals[..., 0], normals[..., 1], appearance_u8(rgb, 4), c1, c2], 8)
+
+
+def features_u16(uv: np.ndarray, normals: np.ndarray) -> np.ndarray:
+    """Four 16-bit guide channels: texture coordinates and the normal pair
+    widened to 16 bits (x 257) (8-byte texels)."""
+    return guide_n([uv[..., 0], uv[..., 1], normals[..., 0].astype(np.uint16) * 257,
+                    normals[..., 1].astype(np.uint16) * 257], 16)
+
+
 def identity_uv_guide_u16(sw: int, sh: int) -> np.ndarray:
     """Texture coordinates of each texel centre, scaled to 16 bits."""
     gx = np.floor((np.arange(sw) + 0.5) * 65536.0 / sw).astype(np.int64)
@@ -328,6 +387,7 @@ CONFIG_NAMES = {
     4: "batch-64-uneven",
     5: "serve-poisson",
     6: "appearance-1920x1080",
+    7: "features-1920x1080",
 }
 
 NORMAL_PARAMS = Params(levels=4, finest=8, threshold=32, radius=3)
@@ -359,6 +419,40 @@ def appearance_target(w: int, h: int, nbumps: int, seed: int) -> np.ndarray:
                       appearance_u8(value_noise_rgb(w, h, seed + 1), 4))
 
 
+FEATURE_PARAMS = Params(levels=4, finest=8, threshold=160, radius=3)
+FEATURE16_PARAMS = Params(levels=4, finest=8, threshold=1 << 22, radius=3)
+
+
+def _features_style(size: int, seed: int, depth: int) -> Style:
+    """Exemplar with a five-channel 8-bit guide (sphere normals, appearance,
+    chroma), or a four-channel 16-bit one (texture coordinates and sphere
+    normals)."""
+    rgb = value_noise_rgb(size, size, seed)
+    if depth == 8:
+        return Style(rgb, features_u8(rgb, sphere_guide_u8(size)), GUIDE_U8XN, 0)
+    return Style(rgb, features_u16(identity_uv_guide_u16(size, size), sphere_guide_u8(size)),
+                 GUIDE_U16XN, 0)
+
+
+def features_target(w: int, h: int, seed: int, depth: int, src_rgb: np.ndarray) -> np.ndarray:
+    """Target of the features workload: an object textured with the exemplar
+    through warped texture coordinates (``warped_uv_guide_u16`` over the
+    exemplar's size).  Its normals are the exemplar's sphere normals at those
+    coordinates plus bump detail ((bump - 128) / 8, clamped); with 8 bits the
+    other channels are the appearance and chroma of the exemplar seen
+    through the same coordinates, with 16 bits the coordinates themselves."""
+    sh, sw = src_rgb.shape[:2]
+    uv = warped_uv_guide_u16(w, h, sw, sh, seed + 1)
+    iu = (uv[..., 0].astype(np.int64) * sw) >> 16
+    iv = (uv[..., 1].astype(np.int64) * sh) >> 16
+    bump = bump_guide_u8(w, h, 64, seed).astype(np.int64)
+    n = sphere_guide_u8(sw)[iv, iu].astype(np.int64) + (bump - 128) // 8
+    n = np.clip(n, 0, 255).astype(np.uint8)
+    if depth == 8:
+        return features_u8(src_rgb[iv, iu], n)
+    return features_u16(uv, n)
+
+
 def _frame(guide: np.ndarray, fmt: int, p: Params, seed: int, style: int = 0) -> Frame:
     """A workload frame whose seeds' jitter is the integer hash of (cell,
     level, seed): no table travels with it."""
@@ -366,9 +460,12 @@ def _frame(guide: np.ndarray, fmt: int, p: Params, seed: int, style: int = 0) ->
 
 
 def config(n: int, **kw):
-    """Return ``(styles, frames)`` for workload n (1..4, 6), or for n == 5 a
+    """Return ``(styles, frames)`` for workload n (1..4, 6, 7), or for n == 5 a
     dict describing the serving trace.  Keyword overrides: ``frames`` (cfg 4),
-    ``requests`` and ``qps`` (cfg 5), ``lut_bits``, ``w`` and ``h`` (cfg 6)."""
+    ``requests`` and ``qps`` (cfg 5), ``lut_bits``, ``w`` and ``h`` (cfg 6),
+    ``w``, ``h``, ``size`` (exemplar side) and ``depth`` (8 or 16) (cfg 7).
+    A workload-7 style's ``guide`` holds 5 channels (8 bits) or 4 (16 bits)
+    and its ``lut_bits`` is 0 (its lookups are exact searches)."""
     if n == 1:
         st = _sphere_style(256, 101)
         p = Params(levels=3, finest=8, threshold=48, radius=2)
@@ -433,4 +530,12 @@ def config(n: int, **kw):
         st = _appearance_style(512, 601, int(kw.get("lut_bits", 8)))
         w, h = int(kw.get("w", 1920)), int(kw.get("h", 1080))
         return [st], [_frame(appearance_target(w, h, 64, 602), GUIDE_U8X3, APPEARANCE_PARAMS, 1)]
+    if n == 7:
+        depth = int(kw.get("depth", 8))
+        size = int(kw.get("size", 512))
+        st = _features_style(size, 701, depth)
+        w, h = int(kw.get("w", 1920)), int(kw.get("h", 1080))
+        g = features_target(w, h, 702, depth, st.rgb)
+        p = FEATURE_PARAMS if depth == 8 else FEATURE16_PARAMS
+        return [st], [_frame(g, GUIDE_U8XN if depth == 8 else GUIDE_U16XN, p, 1)]
     raise ValueError(f"unknown workload {n}")
