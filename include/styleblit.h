@@ -21,7 +21,10 @@
  *     uint16 (SB_GUIDE_U16X2, 4 B/px, native little-endian), or three uint8
  *     channels in 4 B/px (SB_GUIDE_U8X3: channels in bytes 0..2, byte 3
  *     ignored) -- the additional guiding channels of Sec. 3.1, e.g. a
- *     normal pair plus an appearance channel;
+ *     normal pair plus an appearance channel; or 2..8 channels of uint8
+ *     (SB_GUIDE_U8XN) or uint16 (SB_GUIDE_U16XN) in texels of 4, 8 or 16
+ *     bytes (sb_texel_bytes), channel k in element k, later elements
+ *     ignored -- looked up by an exact search instead of a table;
  *   - source coordinates are packed x | (y << 16);
  *   - work is enqueued asynchronously on `stream` (0 = the null stream); the
  *     caller synchronises.  Arguments are validated before anything is
@@ -48,7 +51,13 @@ typedef enum {
     SB_EBUDGET = -4  /* serving: request larger than the memory budget */
 } sb_status;
 
-typedef enum { SB_GUIDE_U8X2 = 0, SB_GUIDE_U16X2 = 1, SB_GUIDE_U8X3 = 2 } sb_guide_fmt;
+typedef enum {
+    SB_GUIDE_U8X2 = 0,
+    SB_GUIDE_U16X2 = 1,
+    SB_GUIDE_U8X3 = 2,
+    SB_GUIDE_U8XN = 3,   /* 2..8 uint8 channels, exact search (sb_style.channels) */
+    SB_GUIDE_U16XN = 4   /* 2..8 uint16 channels, exact search */
+} sb_guide_fmt;
 
 /* Largest target and source side, and limits of the parameters. */
 #define SB_MAX_SIDE 8192
@@ -56,6 +65,7 @@ typedef enum { SB_GUIDE_U8X2 = 0, SB_GUIDE_U16X2 = 1, SB_GUIDE_U8X3 = 2 } sb_gui
 #define SB_MAX_RADIUS 7
 #define SB_MAX_LUT_BITS 12
 #define SB_MAX_LABELS 256
+#define SB_MAX_CHANNELS 8
 
 /* A style: the exemplar C_S, its guide G_S and the lookup table built from
  * G_S (Sec. 3.1).  A plain struct of caller-owned device pointers; it must
@@ -63,15 +73,17 @@ typedef enum { SB_GUIDE_U8X2 = 0, SB_GUIDE_U16X2 = 1, SB_GUIDE_U8X3 = 2 } sb_gui
 typedef struct {
     const uint32_t *rgba;   /* [device] padded exemplar of sb_exemplar_texels(sw, sh)
                                texels, written by sb_pack_exemplar */
-    const void *guide;      /* [device] Sw*Sh guide texels (2 or 4 B each, by fmt) */
+    const void *guide;      /* [device] Sw*Sh guide texels (2 or 4 B each, by fmt;
+                               sb_texel_bytes for SB_GUIDE_U8XN / U16XN) */
     const uint32_t *lut;    /* [device] (1<<lut_bits)^2 source coordinates, bin index
                                c = c0 + (c1 << lut_bits); SB_GUIDE_U8X3: (1<<lut_bits)^3,
                                c = c0 + (c1 << lut_bits) + (c2 << 2*lut_bits); written
-                               by sb_lut_build */
+                               by sb_lut_build; not read (may be NULL) for
+                               SB_GUIDE_U8XN / U16XN */
     int32_t sw, sh;         /* source size, 1..SB_MAX_SIDE */
     int32_t fmt;            /* sb_guide_fmt */
     int32_t lut_bits;       /* bits per channel of the lookup table: U8X2 and U8X3
-                               1..8, U16X2 1..SB_MAX_LUT_BITS */
+                               1..8, U16X2 1..SB_MAX_LUT_BITS; 0 for U8XN / U16XN */
     /* Segmentation guide (optional; nlabels = 0 and NULLs without it): a
      * label per source pixel and one lookup table per label, so chunks stay
      * inside regions of equal label (the extra segmentation guide of the
@@ -81,12 +93,18 @@ typedef struct {
     const uint32_t *label_luts; /* [device] nlabels tables of (1<<lut_bits)^2 entries,
                                    written by sb_lut_build_labels */
     int32_t nlabels;            /* 0, or 1..SB_MAX_LABELS */
-    /* Channel weights of a three-channel guide (the paper's strong or weak
-     * appearance guide): the error and the table's argmin sum w_k * d_k^2.
-     * weights[0..2] in 0..127 (byte 3 unused); all zero means unit weights,
-     * the only choice for two-channel guides.  The tables must have been
-     * built with the same weights (sb_lut_build_w). */
-    uint8_t weights[4];
+    /* Channel weights of a guide of three or more channels (the paper's
+     * strong or weak appearance guide): the error and the lookup's argmin
+     * sum w_k * d_k^2.  weights[k] in 0..127 for the guide's channels k
+     * (SB_GUIDE_U8X3: 0..2); all zero means unit weights, the only choice
+     * for two-channel table formats.  Tables must have been built with the
+     * same weights (sb_lut_build_w). */
+    uint8_t weights[8];
+    /* SB_GUIDE_U8XN / U16XN only (0 / NULL otherwise): the number of
+     * channels, 2..SB_MAX_CHANNELS, and the search tree over the source
+     * guide written by sb_tree_build. */
+    int32_t channels;
+    const void *tree;       /* [device] sb_tree_bytes() bytes */
 } sb_style;
 
 /* Where the seed hierarchy's jitter comes from (SeedPoint in Algorithm 2
@@ -205,6 +223,63 @@ int sb_style_create(const uint8_t *src_rgb, const void *src_guide, int32_t sw, i
 /* Free a style from sb_style_create (only those), once no work that reads
  * it is in flight.  NULL is ignored. */
 int sb_style_destroy(sb_style *style);
+
+/* ----------------------------------------- guides of many channels (search)
+ *
+ * The additional guiding channels of Sec. 3.1, for which the paper suggests
+ * a search tree in place of the table: SB_GUIDE_U8XN / SB_GUIDE_U16XN guides
+ * of 2..8 channels, each lookup the exact nearest source pixel
+ *   u*(g) = argmin_u sum_k w_k (g_k - G_S[u]_k)^2, ties to the smallest
+ *   raster index of u,
+ * over the raw channel values (no quantisation), with the style's weights.
+ * The search runs on a k-d tree of the source guide built on the device:
+ * every node holds the tight bounding box of its texels, inner nodes split
+ * the widest (weighted) channel at the middle of the box, leaves hold at
+ * most 8 texels (texels equal in every weighted channel collapse to the one
+ * of smallest raster index), and a search skips a subtree only when its box
+ * lies strictly farther than the best texel found, so the result is the
+ * exact argmin for any tree shape.  Per frame: a seed pass searches each
+ * seed's lookup; the level loop then runs as for the table formats, and the
+ * pixels no level accepts search their own lookup in the same pass
+ * (gathered per tile so the searches run in full waves); the vote is
+ * unchanged.  Not available with labels, in batches or in sb_serve_run. */
+
+/* Bytes per texel of a `channels`-channel guide of fmt SB_GUIDE_U8XN or
+ * SB_GUIDE_U16XN: the smallest of 4, 8, 16 that holds the channels; 0 if
+ * the pair is invalid. */
+int32_t sb_texel_bytes(int32_t fmt, int32_t channels);
+/* Bytes of the search tree of an Sw x Sh source (an upper bound: the tree
+ * has at most 2 Sw Sh - 1 nodes); 0 on invalid arguments. */
+size_t sb_tree_bytes(int32_t fmt, int32_t channels, int32_t sw, int32_t sh);
+/* Device workspace of sb_tree_build. */
+size_t sb_tree_workspace_bytes(int32_t fmt, int32_t channels, int32_t sw, int32_t sh);
+/* Build the search tree of a source guide.
+ *   guide     [device] Sw*Sh texels of sb_texel_bytes(fmt, channels) bytes
+ *   weights   [host] `channels` values 0..127 (NULL or all zero: unit); they
+ *             steer the splits only -- the tree answers exactly for any
+ *             weights, the style's weights decide the lookups
+ *   tree      [device] sb_tree_bytes() bytes; workspace [device] of
+ *             sb_tree_workspace_bytes()
+ * Builds one tree level per round of launches and reads each level's node
+ * count back, so it synchronises `stream` (and returns after the tree is
+ * complete).  SB_EINVAL / SB_ENOMEM on bad arguments or small buffers,
+ * SB_EHIP if a launch or copy fails. */
+int sb_tree_build(const void *guide, int32_t fmt, int32_t channels, int32_t sw, int32_t sh,
+                  const uint8_t *weights, void *tree, size_t tree_bytes, void *workspace,
+                  size_t workspace_bytes, hipStream_t stream);
+/* Exact lookups of n query texels through a style's tree:
+ * out[i] = u*(queries[i]) as x | y << 16.  style: an SB_GUIDE_U8XN / U16XN
+ * style (its weights apply); queries [device] n texels; out [device] n. */
+int sb_tree_query(const sb_style *style, const void *queries, int64_t n, uint32_t *out,
+                  hipStream_t stream);
+/* A library-owned style of a many-channel guide in one call: copies the
+ * exemplar and guide, packs the exemplar and builds the search tree, as
+ * sb_style_create does for the table formats.  weights [host] `channels`
+ * values 0..127 or NULL (unit); synchronises `stream`.  Free with
+ * sb_style_destroy. */
+int sb_style_create_n(const uint8_t *src_rgb, const void *src_guide, int32_t sw, int32_t sh,
+                      int32_t fmt, int32_t channels, const uint8_t *weights, hipStream_t stream,
+                      sb_style **out);
 
 /* Per-label lookup tables for the segmentation guide: table l holds, for
  * every bin, the source pixel labelled l whose guide is nearest to the bin

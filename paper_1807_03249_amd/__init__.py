@@ -19,6 +19,9 @@ LIB_PATH = os.environ.get("STYLEBLIT_LIB") or os.path.join(
 GUIDE_U8X2 = 0
 GUIDE_U16X2 = 1
 GUIDE_U8X3 = 2  # three uint8 channels in 4 bytes per pixel (byte 3 ignored)
+GUIDE_U8XN = 3  # 2..8 uint8 channels in 4- or 8-byte texels, exact search lookups
+GUIDE_U16XN = 4  # 2..8 uint16 channels in 4-, 8- or 16-byte texels, exact search lookups
+MAX_CHANNELS = 8
 MAX_SIDE = 8192
 MAX_LEVELS = 12
 MAX_RADIUS = 7
@@ -38,7 +41,8 @@ class SbStyle(ctypes.Structure):
                 ("sw", ctypes.c_int32), ("sh", ctypes.c_int32), ("fmt", ctypes.c_int32),
                 ("lut_bits", ctypes.c_int32), ("labels", ctypes.c_void_p),
                 ("label_luts", ctypes.c_void_p), ("nlabels", ctypes.c_int32),
-                ("weights", ctypes.c_uint8 * 4)]
+                ("weights", ctypes.c_uint8 * 8), ("channels", ctypes.c_int32),
+                ("tree", ctypes.c_void_p)]
 
 
 class SbTune(ctypes.Structure):
@@ -136,6 +140,15 @@ def lib():
                                     ctypes.POINTER(SbTune), vp]
     L.sb_jitter_fill.argtypes = [i32, i32, i32, i32, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
     L.sb_style_create.argtypes = [vp, vp, i32, i32, i32, i32, vp, ctypes.POINTER(vp)]
+    L.sb_style_create_n.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, ctypes.POINTER(vp)]
+    L.sb_texel_bytes.restype = i32
+    L.sb_texel_bytes.argtypes = [i32, i32]
+    L.sb_tree_bytes.restype = sz
+    L.sb_tree_bytes.argtypes = [i32, i32, i32, i32]
+    L.sb_tree_workspace_bytes.restype = sz
+    L.sb_tree_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.sb_tree_build.argtypes = [vp, i32, i32, i32, i32, vp, vp, sz, vp, sz, vp]
+    L.sb_tree_query.argtypes = [ctypes.POINTER(SbStyle), vp, ctypes.c_int64, vp, vp]
     L.sb_style_destroy.argtypes = [vp]
     L.sb_stylize_noalloc.argtypes = [ctypes.POINTER(SbStyle), vp, i32, i32, vp,
                                      ctypes.POINTER(SbParams), vp, vp, vp, vp]
@@ -236,6 +249,33 @@ def _guide_fmt(torch, g) -> int:
     raise TypeError("guides are uint8 or uint16 with two channels")
 
 
+def _search_fmt(torch, g, channels: int) -> int:
+    """Format of a many-channel guide tensor (rows, cols, elements): uint8
+    (GUIDE_U8XN) or uint16 / int16 bits (GUIDE_U16XN), whose texels
+    (elements x element bytes) are the texel size of ``channels`` channels."""
+    if g.dim() != 3:
+        raise TypeError("a many-channel guide is (rows, cols, elements)")
+    if g.dtype == torch.uint8:
+        fmt = GUIDE_U8XN
+    elif g.dtype in (torch.uint16, torch.int16):
+        fmt = GUIDE_U16XN
+    else:
+        raise TypeError("many-channel guides are uint8 or uint16")
+    tb = int(lib().sb_texel_bytes(fmt, int(channels)))
+    if tb == 0 or g.shape[2] * g.element_size() != tb:
+        raise TypeError(f"{channels} channels of this depth need {tb}-byte texels")
+    return fmt
+
+
+def _check_guide(torch, g, style) -> None:
+    """A target guide must have its style's format (and channel count)."""
+    if style.fmt in (GUIDE_U8XN, GUIDE_U16XN):
+        if _search_fmt(torch, g, style.channels) != style.fmt:
+            raise TypeError("target guide format differs from the style's guide format")
+    elif _guide_fmt(torch, g) != style.fmt:
+        raise TypeError("target guide format differs from the style's guide format")
+
+
 def table_entries(fmt: int, lut_bits: int) -> int:
     """Entries of one lookup table: (2**lut_bits)**channels."""
     return 1 << ((3 if fmt == GUIDE_U8X3 else 2) * lut_bits)
@@ -248,10 +288,15 @@ class Style:
     segmentation guide: its label map and one lookup table per label.
     ``weights`` (three values 0..127, three-channel guides only) weight the
     channels' squared differences in the table and in the error test (the
-    strong or weak appearance guide); None means unit weights."""
+    strong or weak appearance guide); None means unit weights.
 
-    def __init__(self, rgb, guide, lut_bits: int, labels=None,
-                 nlabels: Optional[int] = None, weights=None):
+    With ``channels`` (2..8) the guide holds that many channels of uint8 or
+    uint16 in the texel layout of ``sb_texel_bytes`` ((rows, cols, elements)),
+    looked up by the exact search on a k-d tree built on the GPU instead of a
+    table (``lut_bits`` is then 0); ``weights`` then hold ``channels`` values."""
+
+    def __init__(self, rgb, guide, lut_bits: int = 0, labels=None,
+                 nlabels: Optional[int] = None, weights=None, channels: Optional[int] = None):
         torch = _torch()
         self.rgb = _dev(torch, rgb)
         if self.rgb.dtype != torch.uint8 or self.rgb.dim() != 3 or self.rgb.shape[2] != 3:
@@ -260,7 +305,9 @@ class Style:
         if not isinstance(g, torch.Tensor) and getattr(g, "dtype", None) is not None and str(g.dtype) == "uint16":
             g = g.view("int16")  # torch.from_numpy has no uint16 on every build; same bits
         self.guide = _dev(torch, g)
-        self.fmt = _guide_fmt(torch, self.guide)
+        self.channels = int(channels) if channels is not None else 0
+        self.fmt = (_search_fmt(torch, self.guide, self.channels) if channels is not None
+                    else _guide_fmt(torch, self.guide))
         self.sh, self.sw = int(self.rgb.shape[0]), int(self.rgb.shape[1])
         if tuple(self.guide.shape[:2]) != (self.sh, self.sw):
             raise ValueError("exemplar and guide sizes differ")
@@ -274,6 +321,11 @@ class Style:
                                 device="cuda")
         _check(L.sb_pack_exemplar(self.rgb.data_ptr(), self.sw, self.sh, self.rgba.data_ptr(), s),
                "sb_pack_exemplar")
+        self.labels = self.label_luts = self.lut = self.tree = None
+        self.nlabels = 0
+        if channels is not None:
+            self._init_search(torch, L, s, weights, labels)
+            return
         wsb = L.sb_lut_workspace_bytes(self.fmt, self.sw, self.sh, self.lut_bits)
         if wsb == 0:
             raise StyleBlitError(SB_EINVAL, "sb_lut_workspace_bytes")
@@ -282,14 +334,12 @@ class Style:
                                device="cuda")
         if weights is not None and len(weights) != 3:
             raise ValueError("weights must hold three values")
-        self.weights = (ctypes.c_uint8 * 4)(*([int(v) for v in weights] + [0])
-                                            if weights is not None else (0, 0, 0, 0))
+        self.weights = (ctypes.c_uint8 * 8)(*([int(v) for v in weights] + [0] * 5)
+                                            if weights is not None else (0,) * 8)
         _check(L.sb_lut_build_w(self.guide.data_ptr(), self.fmt, self.sw, self.sh, self.lut_bits,
                                 self.weights, self.lut.data_ptr(), ws.data_ptr(), wsb, s),
                "sb_lut_build_w")
         self._ws = ws  # keep alive until the enqueued build has run
-        self.labels = self.label_luts = None
-        self.nlabels = 0
         if labels is not None:
             self.labels = _dev(torch, labels, torch.uint8)
             if tuple(self.labels.shape) != (self.sh, self.sw):
@@ -308,7 +358,47 @@ class Style:
                          self.label_luts.data_ptr() if self.label_luts is not None else None,
                          self.nlabels, self.weights)
 
+    def _init_search(self, torch, L, s, weights, labels):
+        if labels is not None:
+            raise ValueError("many-channel guides take no labels")
+        if int(self.lut_bits) != 0:
+            raise ValueError("many-channel guides have no table: lut_bits must be 0")
+        if weights is not None and len(weights) != self.channels:
+            raise ValueError(f"weights must hold {self.channels} values")
+        w = [int(v) for v in weights] if weights is not None else []
+        self.weights = (ctypes.c_uint8 * 8)(*(w + [0] * (8 - len(w))))
+        tb = int(L.sb_tree_bytes(self.fmt, self.channels, self.sw, self.sh))
+        wsb = int(L.sb_tree_workspace_bytes(self.fmt, self.channels, self.sw, self.sh))
+        if tb == 0 or wsb == 0:
+            raise StyleBlitError(SB_EINVAL, "sb_tree_bytes")
+        self.tree = torch.empty(tb, dtype=torch.uint8, device="cuda")
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        # synchronises the stream: the workspace is idle when this returns
+        _check(L.sb_tree_build(self.guide.data_ptr(), self.fmt, self.channels, self.sw, self.sh,
+                               self.weights, self.tree.data_ptr(), tb, ws.data_ptr(), wsb, s),
+               "sb_tree_build")
+        self.c = SbStyle(self.rgba.data_ptr(), self.guide.data_ptr(), None, self.sw, self.sh,
+                         self.fmt, 0, None, None, 0, self.weights, self.channels,
+                         self.tree.data_ptr())
+
+    def query(self, texels):
+        """Exact lookups of guide texels ((..., elements) in this style's
+        layout, on the device) through the search tree: x | y << 16 per texel
+        as int32 bits (sb_tree_query)."""
+        torch = _torch()
+        if self.tree is None:
+            raise ValueError("query needs a many-channel style")
+        q = _dev(torch, texels)
+        n = q.numel() * q.element_size() // int(lib().sb_texel_bytes(self.fmt, self.channels))
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(lib().sb_tree_query(ctypes.byref(self.c), q.data_ptr(), n, out.data_ptr(),
+                                   _stream(torch)), "sb_tree_query")
+        return out
+
     def resident_bytes(self) -> int:
+        if self.tree is not None:
+            return (self.rgba.numel() * 4 + self.guide.numel() * self.guide.element_size()
+                    + self.tree.numel())
         n = (self.rgba.numel() * 4 + self.guide.numel() * self.guide.element_size()
              + self.lut.numel() * 4)
         if self.labels is not None:
@@ -326,12 +416,13 @@ def workspace_bytes(w: int, h: int, p: SbParams) -> int:
 def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chunk=None,
             want_nnf: bool = False, workspace=None, tune=None, events=None,
             tgt_labels=None):
-    """Stylise one frame.  ``tgt_guide`` (H, W, 2) or (H, W, 4) and ``jitter`` (uint32 as
-    int32 bits) may be numpy arrays or device tensors.  Returns
+    """Stylise one frame.  ``tgt_guide`` (H, W, 2) or (H, W, 4), or a many-channel
+    style's texel layout (H, W, elements), and ``jitter`` (uint32 as int32
+    bits) may be numpy arrays or device tensors.  Returns
     ``(rgb (H,W,3) uint8, chunk (H,W) int32-bits[, nnf])`` as device tensors;
     the work is enqueued on torch's current stream, the stream every
-    temporary here is allocated on.  ``tune`` is a
-    (blend_ppt, blend_rows, level_group, level_ppt) choice (None = defaults); with
+    temporary here is allocated on.  ``tune`` is a (blend_ppt, blend_rows,
+    level_group, level_ppt, blend_split) choice (None = defaults); with
     ``events`` (a TimingEvents) the passes are bracketed by its events
     (sb_stylize_timed).  With ``tgt_labels`` (uint8 (H, W)) the frame runs
     with the segmentation guide (sb_stylize_seg; the style must carry labels)."""
@@ -340,8 +431,7 @@ def stylize(style: Style, tgt_guide, jitter, p: SbParams, out_rgb=None, out_chun
     if not isinstance(g, torch.Tensor) and str(getattr(g, "dtype", "")) == "uint16":
         g = g.view("int16")
     g = _dev(torch, g)
-    if _guide_fmt(torch, g) != style.fmt:
-        raise TypeError("target guide format differs from the style's guide format")
+    _check_guide(torch, g, style)
     h, w = int(g.shape[0]), int(g.shape[1])
     p, j = _jitter_arg(torch, jitter, p, w, h)
     jp = j.data_ptr() if j is not None else None
@@ -404,8 +494,7 @@ class FramePlan:
         for t in (tgt_guide, out_rgb, out_chunk, workspace):
             if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
                 raise ValueError("FramePlan takes contiguous device tensors only")
-        if _guide_fmt(torch, tgt_guide) != style.fmt:
-            raise TypeError("target guide format differs from the style's guide format")
+        _check_guide(torch, tgt_guide, style)
         h, w = int(tgt_guide.shape[0]), int(tgt_guide.shape[1])
         if out_rgb.numel() != h * w * 3 or out_rgb.dtype != torch.uint8 \
                 or out_chunk.numel() != h * w or out_chunk.element_size() != 4:
@@ -441,8 +530,7 @@ def stylize_noalloc(style: Style, tgt_guide, jitter, p: SbParams, out_rgb, out_c
     for t in (tgt_guide, out_rgb, out_chunk) + ((out_nnf,) if out_nnf is not None else ()):
         if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
             raise ValueError("stylize_noalloc takes contiguous device tensors only")
-    if _guide_fmt(torch, tgt_guide) != style.fmt:
-        raise TypeError("target guide format differs from the style's guide format")
+    _check_guide(torch, tgt_guide, style)
     h, w = int(tgt_guide.shape[0]), int(tgt_guide.shape[1])
     if out_rgb.numel() != h * w * 3 or out_rgb.dtype != torch.uint8 or out_chunk.numel() != h * w \
             or out_chunk.element_size() != 4:
@@ -552,8 +640,7 @@ class FrameJob:
             g = g.view("int16")
         self.style = style
         self.guide = _dev(torch, g)
-        if _guide_fmt(torch, self.guide) != style.fmt:
-            raise TypeError("target guide format differs from the style's guide format")
+        _check_guide(torch, self.guide, style)
         self.h, self.w = int(self.guide.shape[0]), int(self.guide.shape[1])
         self.params, self.jitter = _jitter_arg(torch, jitter, p, self.w, self.h)
         self.out_rgb = out_rgb if out_rgb is not None else torch.empty(

@@ -122,6 +122,8 @@ int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace
     if (!fill_frame(fr.style, fr.tgt_guide, fr.w, fr.h, fr.jitter, &fr.params, fr.out_rgb,
                     fr.out_chunk, fr.out_nnf, &args[f], fr.tgt_labels))
       return SB_EINVAL;
+    // the batch kernels cover the table formats only
+    if (fmt_search(fr.style->fmt)) return SB_EINVAL;
     // graphs: the batch's seed pass is one persistent launch over every
     // frame, so each record is built once there rather than per block;
     // direct launches keep single frames' choice (records made in the level

@@ -22,9 +22,15 @@ int32_t ilog2(int32_t v) {
 bool side_ok(int32_t v) { return v >= 1 && v <= SB_MAX_SIDE; }
 
 bool style_ok(const sb_style *s) {
-  if (!s || !s->rgba || !s->guide || !s->lut) return false;
+  if (!s || !s->rgba || !s->guide) return false;
   if (!side_ok(s->sw) || !side_ok(s->sh)) return false;
-  if (!fmt_ok(s->fmt)) return false;
+  if (fmt_search(s->fmt)) {
+    // many channels: the search tree instead of tables; no labels
+    uint32_t wn[2];
+    return s->tree && search_texel_bytes(s->fmt, s->channels) != 0 && s->lut_bits == 0 &&
+           s->nlabels == 0 && resolve_weights_n(s->weights, s->channels, wn);
+  }
+  if (!s->lut || !fmt_ok(s->fmt)) return false;
   int32_t wt[3];
   if (!resolve_weights(s->fmt, s->weights, wt)) return false;
   if (s->nlabels < 0 || s->nlabels > SB_MAX_LABELS) return false;
@@ -114,6 +120,7 @@ bool fill_frame(const sb_style *style, const void *tgt_guide, int32_t w, int32_t
   const Levels &lv = a->lv;
   a->own_seeds = style->fmt == SB_GUIDE_U8X2 && tgt_labels == nullptr &&
                  (lv.count == 0 || lv.log2_spacing[lv.count - 1] >= 3);
+  if (fmt_search(style->fmt)) fill_tree_args(style, a);
   a->threshold = params->threshold;
   a->radius = params->radius;
   a->fmt = style->fmt;

@@ -37,7 +37,39 @@ __host__ __device__ constexpr int32_t fmt_channels(int32_t fmt) {
   return fmt == SB_GUIDE_U8X3 ? 3 : 2;
 }
 __host__ __device__ constexpr int32_t fmt_depth(int32_t fmt) {
-  return fmt == SB_GUIDE_U16X2 ? 16 : 8;
+  return fmt == SB_GUIDE_U16X2 || fmt == SB_GUIDE_U16XN ? 16 : 8;
+}
+// Guides of 2..8 channels looked up by the exact search (search.hip).
+__host__ __device__ constexpr bool fmt_search(int32_t fmt) {
+  return fmt == SB_GUIDE_U8XN || fmt == SB_GUIDE_U16XN;
+}
+// Bytes per texel of a search-format guide of `channels` channels: 4, 8 or
+// 16; 0 if invalid.
+__host__ __device__ constexpr int32_t search_texel_bytes(int32_t fmt, int32_t channels) {
+  return !fmt_search(fmt) || channels < 2 || channels > SB_MAX_CHANNELS ? 0
+         : channels * fmt_depth(fmt) <= 32                               ? 4
+         : channels * fmt_depth(fmt) <= 64                               ? 8
+                                                                         : 16;
+}
+
+// The search tree of an n-texel source guide of t-byte texels, in one
+// buffer: node records (uint2: inner {first child, 0}, the two children
+// adjacent; leaf {first texel, count | kTreeLeaf}), node boxes (the lowest
+// and highest value of every element over the node's texels, as two
+// texels), leaf texels and their source coordinates (x | y << 16).
+constexpr uint32_t kTreeLeaf = 0x80000000u;
+struct TreeLayout {
+  size_t meta, box, vals, keys, total;
+};
+inline TreeLayout tree_layout(size_t n, size_t t) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  TreeLayout l;
+  l.meta = 256;
+  l.box = l.meta + al(2 * n * 8);
+  l.vals = l.box + al(2 * n * 2 * t);
+  l.keys = l.vals + al(n * t);
+  l.total = l.keys + al(n * 4);
+  return l;
 }
 
 // Largest voting tile of the blend (pixels): 256 threads, 4 horizontal
@@ -105,6 +137,15 @@ struct FrameArgs {
   // cell's jitter is two more mixing steps (hash_jitter)
   int32_t jmode;
   uint32_t jhash[SB_MAX_LEVELS];
+  // search formats (SB_GUIDE_U8XN / U16XN): the tree's sections, the
+  // texel size and the eight channel weights (byte k = weight of element k,
+  // 0 past the guide's channels)
+  const void *t_meta;
+  const void *t_box;
+  const void *t_vals;
+  const uint32_t *t_keys;
+  int32_t texel;
+  uint32_t wn[2];
   Levels lv;
 };
 
@@ -182,6 +223,14 @@ hipError_t launch_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint
 // seed, assignment and vote passes and after the vote pass.
 hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, const Tune &t, hipEvent_t *ev,
                           hipStream_t stream);
+// The seed and level-loop passes of a search-format frame (search.hip); with
+// ev, records ev[1] between them.
+hipError_t launch_search_frame(const FrameArgs &a, hipEvent_t *ev, hipStream_t stream);
+// Element weights of a search-format guide: `channels` bytes 0..127 (NULL or
+// all zero: unit), packed as FrameArgs::wn; false if a weight exceeds 127.
+bool resolve_weights_n(const uint8_t *in, int32_t channels, uint32_t out[2]);
+// Point a frame's tree fields at a search-format style's tree.
+void fill_tree_args(const sb_style *style, FrameArgs *a);
 // Tiles of one frame per batch pass kind (seeds, assign, vote r <= 3, vote r >= 4).
 void tile_counts(const FrameArgs &a, const Tune &t, uint32_t counts[kBatchKinds]);
 // The passes over a batch described at desc_dev, persistent grids.

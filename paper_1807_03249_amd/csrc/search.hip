@@ -1,0 +1,721 @@
+// search.hip -- guides of 2..8 channels (SB_GUIDE_U8XN / SB_GUIDE_U16XN),
+// looked up by an exact nearest-texel search instead of a table: the
+// additional guiding channels of Sec. 3.1, for which the paper suggests a
+// search tree.
+//
+//   tree build   a k-d tree of the source guide, one level per round of
+//                launches.  k_tree_level takes one node per workgroup (its
+//                texels are a contiguous run), computes the node's tight box
+//                and either makes it a leaf (at most kLeafMax texels, the
+//                depth limit, or texels equal in every channel -- then the
+//                one of smallest raster index stands for all) or splits the
+//                widest element (by weight, then by raw range) at the middle
+//                of the box, both sides non-empty, with a stable partition
+//                into the other texel buffer.  k_tree_alloc numbers the next
+//                level's nodes in order with a block scan, so the tree is the
+//                same on every run.
+//   search       depth first, nearer child first; a subtree is skipped only
+//                if its box lies strictly farther than the best texel so far
+//                (one at equal distance may hold a smaller raster index), so
+//                the result is the exact argmin of sum_k w_k (q_k - g_k)^2,
+//                ties to the smallest raster index, for any tree shape.
+//   k_seeds_n    one thread per padded seed record: the seed and its search.
+//   k_assign_n   the level loop of Algorithm 2 per pixel (64 x 16 tiles, four
+//                rows per thread) with the many-channel error; pixels no
+//                level accepts are listed in LDS and searched by the tile's
+//                threads in list order, so the searches fill whole waves.
+//   k_tree_query the search of caller-given texels (sb_tree_query).
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <type_traits>
+
+#include "sb_device.h"
+
+namespace sb {
+namespace {
+
+constexpr uint32_t kLeafMax = 8;
+constexpr int32_t kMaxDepth = 40;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Squared distances: 8-bit channels fit 32 bits (8 * 127 * 255^2), 16-bit
+// ones need 64 (8 * 127 * 65535^2).
+template <int D>
+struct DistOf {
+  typedef uint32_t type;
+};
+template <>
+struct DistOf<16> {
+  typedef uint64_t type;
+};
+
+// A texel of S bytes: S / (D / 8) elements of D bits.
+template <int S>
+struct Tx {
+  uint32_t w[S / 4];
+};
+
+template <int S>
+__device__ __forceinline__ Tx<S> load_tx(const void *base, uint32_t i) {
+  Tx<S> t;
+  if constexpr (S == 4) {
+    t.w[0] = glb(static_cast<const uint32_t *>(base))[i];
+  } else if constexpr (S == 8) {
+    const u32x2 v = glb(static_cast<const u32x2 *>(base))[i];
+    t.w[0] = v.x, t.w[1] = v.y;
+  } else {
+    const u32x4 v = glb(static_cast<const u32x4 *>(base))[i];
+    t.w[0] = v.x, t.w[1] = v.y, t.w[2] = v.z, t.w[3] = v.w;
+  }
+  return t;
+}
+
+template <int S>
+__device__ __forceinline__ void store_tx(void *base, uint32_t i, const Tx<S> &t) {
+  if constexpr (S == 4) {
+    glb(static_cast<uint32_t *>(base))[i] = t.w[0];
+  } else if constexpr (S == 8) {
+    glb(static_cast<u32x2 *>(base))[i] = u32x2{t.w[0], t.w[1]};
+  } else {
+    glb(static_cast<u32x4 *>(base))[i] = u32x4{t.w[0], t.w[1], t.w[2], t.w[3]};
+  }
+}
+
+template <int D, int S>
+constexpr int kElems = S * 8 / D;
+
+// Element k (compile-time) of a texel.
+template <int D, int S, int K>
+__device__ __forceinline__ uint32_t elem(const Tx<S> &t) {
+  if constexpr (D == 8) return (t.w[K >> 2] >> ((K & 3) * 8)) & 0xFFu;
+  else return (t.w[K >> 1] >> ((K & 1) * 16)) & 0xFFFFu;
+}
+
+// Weight of element k: byte k of wn (0 past the guide's channels).
+template <int K>
+__device__ __forceinline__ uint32_t weight(const uint32_t *wn) {
+  return (wn[K >> 2] >> ((K & 3) * 8)) & 0xFFu;
+}
+
+// Unrolled loop over the elements k = 0..E-1 with k a compile-time constant.
+template <int K, int E, class F>
+__device__ __forceinline__ void for_elems(F &&f) {
+  if constexpr (K < E) {
+    f(std::integral_constant<int, K>());
+    for_elems<K + 1, E>(f);
+  }
+}
+
+// sum_k w_k (a_k - b_k)^2.  |a_k - b_k| < 2^16 fits the 24-bit multiply and
+// its square fits 32 bits.
+template <int D, int S>
+__device__ __forceinline__ typename DistOf<D>::type tx_dist(const Tx<S> &a, const Tx<S> &b,
+                                                           const uint32_t *wn) {
+  typename DistOf<D>::type d = 0;
+  for_elems<0, kElems<D, S>>([&](auto k) {
+    constexpr int K = decltype(k)::value;
+    const int32_t e = int32_t(elem<D, S, K>(a)) - int32_t(elem<D, S, K>(b));
+    const uint32_t e2 = uint32_t(__mul24(e, e));
+    if constexpr (D == 8) d += __umul24(e2, weight<K>(wn));
+    else d += uint64_t(e2) * weight<K>(wn);
+  });
+  return d;
+}
+
+// The same sum from q to the nearest point of the box [lo, hi].
+template <int D, int S>
+__device__ __forceinline__ typename DistOf<D>::type box_dist(const Tx<S> &q, const Tx<S> &lo,
+                                                            const Tx<S> &hi,
+                                                            const uint32_t *wn) {
+  typename DistOf<D>::type d = 0;
+  for_elems<0, kElems<D, S>>([&](auto k) {
+    constexpr int K = decltype(k)::value;
+    const uint32_t v = elem<D, S, K>(q), l = elem<D, S, K>(lo), h = elem<D, S, K>(hi);
+    const uint32_t e = v < l ? l - v : (v > h ? v - h : 0u);
+    const uint32_t e2 = __umul24(e, e);
+    if constexpr (D == 8) d += __umul24(e2, weight<K>(wn));
+    else d += uint64_t(e2) * weight<K>(wn);
+  });
+  return d;
+}
+
+struct TreeView {
+  const u32x2 *meta;
+  const void *box;
+  const void *vals;
+  const uint32_t *keys;
+};
+
+TreeView tree_view(const void *tree, size_t n, size_t t) {
+  const TreeLayout l = tree_layout(n, t);
+  const char *b = static_cast<const char *>(tree);
+  return TreeView{reinterpret_cast<const u32x2 *>(b + l.meta), b + l.box, b + l.vals,
+                  reinterpret_cast<const uint32_t *>(b + l.keys)};
+}
+
+// The exact lookup of q: the source coordinate x | y << 16 of the texel
+// nearest to q under the weights, ties to the smallest raster index (the
+// coordinate word y << 16 | x orders like the raster index).  The stack
+// holds at most one deferred sibling per tree level of the current path,
+// and inner nodes lie above depth kMaxDepth - 1.
+template <int D, int S>
+__device__ uint32_t tree_search(const TreeView &tv, const Tx<S> &q, const uint32_t *wn) {
+  typedef typename DistOf<D>::type Dist;
+  Dist best = ~Dist(0);
+  uint32_t best_key = 0xFFFFFFFFu;
+  uint32_t st_node[kMaxDepth];
+  Dist st_bound[kMaxDepth];
+  int32_t sp = 0;
+  uint32_t node = 0;
+  Dist bound = 0;
+  for (;;) {
+    if (bound <= best) {
+      const u32x2 m = glb(tv.meta)[node];
+      if (m.y & kTreeLeaf) {
+        const uint32_t end = m.x + (m.y & ~kTreeLeaf);
+        for (uint32_t i = m.x; i < end; ++i) {
+          const Dist d = tx_dist<D, S>(q, load_tx<S>(tv.vals, i), wn);
+          const uint32_t k = glb(tv.keys)[i];
+          if (d < best || (d == best && k < best_key)) best = d, best_key = k;
+        }
+      } else {
+        const uint32_t c = m.x;
+        const Dist b0 = box_dist<D, S>(q, load_tx<S>(tv.box, 2 * c), load_tx<S>(tv.box, 2 * c + 1), wn);
+        const Dist b1 =
+            box_dist<D, S>(q, load_tx<S>(tv.box, 2 * c + 2), load_tx<S>(tv.box, 2 * c + 3), wn);
+        const bool first0 = b0 <= b1;
+        const Dist bf = first0 ? b1 : b0;
+        if (bf <= best) {
+          st_node[sp] = first0 ? c + 1 : c;
+          st_bound[sp] = bf;
+          ++sp;
+        }
+        node = first0 ? c : c + 1;
+        bound = first0 ? b0 : b1;
+        continue;
+      }
+    }
+    if (sp == 0) break;
+    --sp;
+    node = st_node[sp];
+    bound = st_bound[sp];
+  }
+  return best_key;
+}
+
+// ---------------------------------------------------------------- tree build
+
+struct BuildArgs {
+  const u32x4 *list_in;  // this level's nodes {first texel, count, node, 0}
+  u32x2 *res;            // per list entry {split, texels left of the split}
+  const void *vals_in;
+  const uint32_t *keys_in;
+  void *vals_out;  // the next level's texels (split nodes' children)
+  uint32_t *keys_out;
+  u32x2 *meta;     // the tree's sections
+  void *box;
+  void *tvals;
+  uint32_t *tkeys;
+  uint32_t wn[2];  // build weights (split choice only)
+  int32_t channels;
+};
+
+template <int S>
+__global__ void __launch_bounds__(256) k_tree_init(const void *guide, uint32_t n, uint32_t sw,
+                                                   void *vals, uint32_t *keys, u32x4 *list) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    store_tx<S>(vals, i, load_tx<S>(guide, i));
+    glb(keys)[i] = ((i / sw) << 16) | (i % sw);
+  }
+  if (i == 0) glb(list)[0] = u32x4{0u, n, 0u, 0u};
+}
+
+// One node per workgroup (256 threads).
+template <int D, int S>
+__global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) {
+  constexpr int E = kElems<D, S>;
+  __shared__ uint32_t s_lo[8], s_hi[8], s_cnt, s_key, s_wave[4];
+  const u32x4 ent = glb(a.list_in)[blockIdx.x];
+  const uint32_t b = ent.x, c = ent.y, node = ent.z, tid = threadIdx.x;
+  if (tid < 8) s_lo[tid] = 0xFFFFFFFFu, s_hi[tid] = 0u;
+  if (tid == 0) s_cnt = 0u, s_key = 0xFFFFFFFFu;
+  __syncthreads();
+  // the node's box
+  uint32_t lo[E], hi[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) lo[k] = 0xFFFFFFFFu, hi[k] = 0u;
+  for (uint32_t i = b + tid; i < b + c; i += 256) {
+    const Tx<S> t = load_tx<S>(a.vals_in, i);
+    for_elems<0, E>([&](auto k) {
+      constexpr int K = decltype(k)::value;
+      lo[K] = min(lo[K], elem<D, S, K>(t));
+      hi[K] = max(hi[K], elem<D, S, K>(t));
+    });
+  }
+  if (tid < c) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) atomicMin(&s_lo[k], lo[k]), atomicMax(&s_hi[k], hi[k]);
+  }
+  __syncthreads();
+  Tx<S> blo, bhi;
+#pragma unroll
+  for (int k = 0; k < S / 4; ++k) blo.w[k] = 0u, bhi.w[k] = 0u;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int sh = D == 8 ? (k & 3) * 8 : (k & 1) * 16, wi = D == 8 ? k >> 2 : k >> 1;
+    blo.w[wi] |= s_lo[k] << sh;
+    bhi.w[wi] |= s_hi[k] << sh;
+  }
+  if (tid == 0) {
+    store_tx<S>(a.box, 2 * node, blo);
+    store_tx<S>(a.box, 2 * node + 1, bhi);
+  }
+  // the split element: widest by weight, else by raw range; none if every
+  // channel is constant over the node
+  int32_t ds = -1, dr = -1;
+  uint64_t best_w = 0;
+  uint32_t best_r = 0;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    if (k >= a.channels) continue;
+    const uint32_t r = s_hi[k] - s_lo[k];
+    const uint64_t wr = uint64_t(r) * r * ((a.wn[k >> 2] >> ((k & 3) * 8)) & 0xFFu);
+    if (wr > best_w) best_w = wr, ds = k;
+    if (r > best_r) best_r = r, dr = k;
+  }
+  if (ds < 0) ds = dr;
+  if (ds < 0) {
+    // texels equal in every channel: every query sees them at one distance,
+    // so the one of smallest raster index stands for all
+    uint32_t mk = 0xFFFFFFFFu;
+    for (uint32_t i = b + tid; i < b + c; i += 256) mk = min(mk, glb(a.keys_in)[i]);
+    if (tid < c) atomicMin(&s_key, mk);
+    __syncthreads();
+    if (tid == 0) {
+      store_tx<S>(a.tvals, b, blo);
+      glb(a.tkeys)[b] = s_key;
+      glb(a.meta)[node] = u32x2{b, 1u | kTreeLeaf};
+      glb(a.res)[blockIdx.x] = u32x2{0u, 0u};
+    }
+    return;
+  }
+  if (c <= kLeafMax || depth >= kMaxDepth - 1) {
+    for (uint32_t i = b + tid; i < b + c; i += 256) {
+      store_tx<S>(a.tvals, i, load_tx<S>(a.vals_in, i));
+      glb(a.tkeys)[i] = glb(a.keys_in)[i];
+    }
+    if (tid == 0) {
+      glb(a.meta)[node] = u32x2{b, c | kTreeLeaf};
+      glb(a.res)[blockIdx.x] = u32x2{0u, 0u};
+    }
+    return;
+  }
+  // split at s = lo + (hi - lo + 1) / 2: lo < s <= hi, so both sides hold
+  // texels (the box is tight)
+  const uint32_t s = s_lo[ds] + (s_hi[ds] - s_lo[ds] + 1) / 2;
+  auto side_left = [&](const Tx<S> &t) {
+    uint32_t v = 0;
+    for_elems<0, E>([&](auto k) {
+      constexpr int K = decltype(k)::value;
+      if (K == ds) v = elem<D, S, K>(t);
+    });
+    return v < s;
+  };
+  uint32_t nl = 0;
+  for (uint32_t i = b + tid; i < b + c; i += 256) nl += side_left(load_tx<S>(a.vals_in, i)) ? 1u : 0u;
+  if (tid < c) atomicAdd(&s_cnt, nl);
+  __syncthreads();
+  const uint32_t lc = s_cnt;
+  // stable partition, 256 texels per round: left texels to [b, b + lc),
+  // right ones to [b + lc, b + c), each side in its input order
+  const uint32_t lane = tid & 63u, wave = tid >> 6;
+  uint32_t lbase = 0, rbase = 0;
+  for (uint32_t base = 0; base < c; base += 256) {
+    const uint32_t i = b + base + tid;
+    const bool valid = base + tid < c;
+    Tx<S> t;
+    uint32_t key = 0;
+    bool left = false;
+    if (valid) {
+      t = load_tx<S>(a.vals_in, i);
+      key = glb(a.keys_in)[i];
+      left = side_left(t);
+    }
+    const uint64_t bal = __ballot(left);
+    const uint32_t pre =
+        __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+    if (lane == 0) s_wave[wave] = uint32_t(__popcll(bal));
+    __syncthreads();
+    uint32_t woff = 0, tot = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < 4; ++w) {
+      woff += w < wave ? s_wave[w] : 0u;
+      tot += s_wave[w];
+    }
+    if (valid) {
+      const uint32_t pl = woff + pre;  // left texels before this one in the round
+      const uint32_t dst = left ? b + lbase + pl : b + lc + rbase + (tid - pl);
+      store_tx<S>(a.vals_out, dst, t);
+      glb(a.keys_out)[dst] = key;
+    }
+    lbase += tot;
+    rbase += min(256u, c - base) - tot;
+    __syncthreads();
+  }
+  if (tid == 0) glb(a.res)[blockIdx.x] = u32x2{1u, lc};
+}
+
+// Numbers the children of this level's split nodes in list order (one
+// workgroup of 1024 threads): child pair r of the level gets nodes
+// nnodes + 2r, + 2r + 1 and list entries 2r, 2r + 1.  ctr[0] = entries of
+// the next level, ctr[1] = nodes so far.
+__global__ void __launch_bounds__(1024) k_tree_alloc(const u32x4 *list_in, const u32x2 *res,
+                                                     uint32_t m, uint32_t nnodes, u32x4 *list_out,
+                                                     u32x2 *meta, uint32_t *ctr) {
+  __shared__ uint32_t s_wave[16];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  uint32_t run = 0;
+  for (uint32_t base = 0; base < m; base += 1024) {
+    const uint32_t j = base + tid;
+    const bool split = j < m && glb(res)[j].x != 0u;
+    const uint64_t bal = __ballot(split);
+    const uint32_t pre =
+        __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+    if (lane == 0) s_wave[wave] = uint32_t(__popcll(bal));
+    __syncthreads();
+    uint32_t woff = 0, tot = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+      woff += w < wave ? s_wave[w] : 0u;
+      tot += s_wave[w];
+    }
+    if (split) {
+      const uint32_t r = run + woff + pre, child = nnodes + 2 * r;
+      const u32x4 e = glb(list_in)[j];
+      const uint32_t lc = glb(res)[j].y;
+      glb(meta)[e.z] = u32x2{child, 0u};
+      glb(list_out)[2 * r] = u32x4{e.x, lc, child, 0u};
+      glb(list_out)[2 * r + 1] = u32x4{e.x + lc, e.y - lc, child + 1, 0u};
+    }
+    run += tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    glb(ctr)[0] = 2 * run;
+    glb(ctr)[1] = nnodes + 2 * run;
+  }
+}
+
+// ------------------------------------------------------------- frame passes
+
+__device__ inline TreeView frame_tree(const FrameArgs &a) {
+  return TreeView{static_cast<const u32x2 *>(a.t_meta), a.t_box, a.t_vals, a.t_keys};
+}
+
+// Record idx of the padded seed table: the seed of its cell and the
+// translation u* - q of the seed's search.
+template <int D, int S>
+__global__ void __launch_bounds__(256) k_seeds_n(FrameArgs a) {
+  const uint32_t idx = blockIdx.x * 256 + threadIdx.x;
+  const Levels &lv = a.lv;
+  if (idx >= uint32_t(lv.poffset[lv.count])) return;
+  int32_t i = 0;
+  while (idx >= uint32_t(lv.poffset[i + 1])) ++i;
+  const uint32_t local = idx - uint32_t(lv.poffset[i]), pc = uint32_t(lv.cells_x[i] + 2);
+  const int32_t cx = int32_t(local % pc) - 1, cy = int32_t(local / pc) - 1;
+  const int32_t ls = lv.log2_spacing[i];
+  u32x2 rec = {kNoSeed, 0u};
+  if (cx >= 0 && cy >= 0 && cx < lv.cells_x[i] && cy < lv.cells_y[i]) {
+    const uint32_t j = cell_jitter(a, ls, lv.cells_x[i], lv.offset[i], a.jhash[i], cx, cy);
+    const uint32_t sx = (uint32_t(cx) << ls) + (j & 0xFFFFu);
+    const uint32_t sy = (uint32_t(cy) << ls) + (j >> 16);
+    if (sx < uint32_t(a.w) && sy < uint32_t(a.h)) {
+      const uint32_t at = __umul24(sy, uint32_t(a.w)) + sx;
+      const uint32_t u = tree_search<D, S>(frame_tree(a), load_tx<S>(a.tgt_guide, at), a.wn);
+      rec.x = pack_xy(4 * sx, 4 * sy);
+      rec.y = pack_off(int32_t(u & 0xFFFFu) - int32_t(sx), int32_t(u >> 16) - int32_t(sy));
+    }
+  }
+  seed_table(a)[idx] = rec;
+}
+
+constexpr uint32_t kAssignTW = 64, kAssignTH = 16;
+
+template <int D, int S>
+__global__ void __launch_bounds__(256) k_assign_n(FrameArgs a) {
+  __shared__ uint32_t s_list[kAssignTW * kAssignTH];
+  __shared__ uint32_t s_n;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t tiles_x = (uint32_t(a.w) + kAssignTW - 1) / kAssignTW;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int32_t tx0 = int32_t((tile % tiles_x) * kAssignTW);
+  const int32_t ty0 = int32_t((tile / tiles_x) * kAssignTH);
+  if (tid == 0) s_n = 0u;
+  __syncthreads();
+  const Levels &lv = a.lv;
+  const int32_t L = lv.count;
+  const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
+#pragma unroll 1
+  for (int32_t r = 0; r < int32_t(kAssignTH / 4); ++r) {
+    const int32_t x = tx0 + int32_t(tid & 63u), y = ty0 + int32_t(tid >> 6) + 4 * r;
+    if (x >= a.w || y >= a.h) continue;
+    const uint32_t pidx = __umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x);
+    const Tx<S> gt = load_tx<S>(a.tgt_guide, pidx);
+    const short2_t p4 = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x), uint32_t(4 * y)));
+    bool done = false;
+    for (int32_t i = 0; i < L && !done; ++i) {
+      const int32_t ls = lv.log2_spacing[i], pc = lv.cells_x[i] + 2;
+      const SB_GLOBAL u32x2 *top = seed_table(a) + lv.poffset[i] + (y >> ls) * pc + (x >> ls);
+      int32_t key = INT32_MAX;
+#pragma unroll
+      for (int32_t k = 0; k < 9; ++k) key = min(key, seed_key(top[(k % 3) * pc + k / 3].x, p4, k));
+      if (key == INT32_MAX) continue;
+      const int32_t k = key & 15, kx = (k * 11) >> 5;
+      const u32x2 rec = top[(k - 3 * kx) * pc + kx];
+      const int32_t vx = x + off_x(rec.y), vy = y + off_y(rec.y);
+      if (uint32_t(vx) >= sw || uint32_t(vy) >= sh) continue;
+      const uint32_t vidx = __umul24(uint32_t(vy), sw) + uint32_t(vx);
+      if (tx_dist<D, S>(gt, load_tx<S>(a.src_guide, vidx), a.wn) < a.threshold) {
+        glb(a.out_chunk)[pidx] = chunk_code(i, rec.x);
+        glb(a.offsets)[pidx] = vote_distance(a, rec.y);
+        if (a.out_nnf) glb(a.out_nnf)[pidx] = pack_xy(uint32_t(vx), uint32_t(vy));
+        done = true;
+      }
+    }
+    if (!done) {
+      glb(a.out_chunk)[pidx] = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
+      s_list[atomicAdd(&s_n, 1u)] = pack_xy(uint32_t(x), uint32_t(y));
+    }
+  }
+  __syncthreads();
+  // the tile's fallback pixels: their own lookups, in list order
+  const uint32_t nf = s_n;
+  for (uint32_t k = tid; k < nf; k += 256) {
+    const uint32_t xy = s_list[k], x = xy & 0xFFFFu, y = xy >> 16;
+    const uint32_t pidx = __umul24(y, uint32_t(a.w)) + x;
+    const uint32_t u = tree_search<D, S>(frame_tree(a), load_tx<S>(a.tgt_guide, pidx), a.wn);
+    const uint32_t off = pack_off(int32_t(u & 0xFFFFu) - int32_t(x), int32_t(u >> 16) - int32_t(y));
+    glb(a.offsets)[pidx] = vote_distance(a, off);
+    if (a.out_nnf) glb(a.out_nnf)[pidx] = u;
+  }
+}
+
+template <int D, int S>
+__global__ void __launch_bounds__(256) k_tree_query(TreeView tv, const void *q, uint32_t n,
+                                                    uint32_t *out, uint32_t w0, uint32_t w1) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t wn[2] = {w0, w1};
+  glb(out)[i] = tree_search<D, S>(tv, load_tx<S>(q, i), wn);
+}
+
+// ------------------------------------------------------------------- host
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Calls f(depth, texel bytes) with both as integral constants for the
+// guide's format and texel size.
+template <class F>
+hipError_t with_format(int32_t fmt, int32_t texel, F &&f) {
+  if (fmt == SB_GUIDE_U8XN) {
+    if (texel == 4) return f(IC<8>(), IC<4>());
+    if (texel == 8) return f(IC<8>(), IC<8>());
+  } else if (fmt == SB_GUIDE_U16XN) {
+    if (texel == 4) return f(IC<16>(), IC<4>());
+    if (texel == 8) return f(IC<16>(), IC<8>());
+    if (texel == 16) return f(IC<16>(), IC<16>());
+  }
+  return hipErrorInvalidValue;
+}
+
+unsigned blocks_for(uint64_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
+
+bool side_ok(int32_t v) { return v >= 1 && v <= SB_MAX_SIDE; }
+
+struct BuildWs {
+  void *vals[2];
+  uint32_t *keys[2];
+  u32x4 *list[2];
+  u32x2 *res;
+  uint32_t *ctr;
+  size_t total;
+};
+
+BuildWs build_ws(char *base, size_t n, size_t t) {
+  BuildWs w;
+  size_t at = 0;
+  for (int k = 0; k < 2; ++k) {
+    w.vals[k] = base ? base + at : nullptr;
+    at += align256(n * t);
+  }
+  for (int k = 0; k < 2; ++k) {
+    w.keys[k] = base ? reinterpret_cast<uint32_t *>(base + at) : nullptr;
+    at += align256(n * 4);
+  }
+  for (int k = 0; k < 2; ++k) {
+    w.list[k] = base ? reinterpret_cast<u32x4 *>(base + at) : nullptr;
+    at += align256(n * 16);
+  }
+  w.res = base ? reinterpret_cast<u32x2 *>(base + at) : nullptr;
+  at += align256(n * 8);
+  w.ctr = base ? reinterpret_cast<uint32_t *>(base + at) : nullptr;
+  at += 256;
+  w.total = at;
+  return w;
+}
+
+}  // namespace
+
+bool resolve_weights_n(const uint8_t *in, int32_t channels, uint32_t out[2]) {
+  out[0] = out[1] = 0u;
+  bool any = false;
+  for (int32_t k = 0; in && k < channels; ++k) any |= in[k] != 0;
+  for (int32_t k = 0; k < channels; ++k) {
+    const uint32_t w = any ? in[k] : 1u;
+    if (w > 127u) return false;
+    out[k >> 2] |= w << ((k & 3) * 8);
+  }
+  return true;
+}
+
+hipError_t launch_search_frame(const FrameArgs &a, hipEvent_t *ev, hipStream_t stream) {
+  const uint32_t records = uint32_t(a.lv.poffset[a.lv.count]);
+  const uint32_t tiles = ((uint32_t(a.w) + kAssignTW - 1) / kAssignTW) *
+                         ((uint32_t(a.h) + kAssignTH - 1) / kAssignTH);
+  return with_format(a.fmt, a.texel, [&](auto d, auto s) -> hipError_t {
+    constexpr int D = decltype(d)::value, S = decltype(s)::value;
+    if (records > 0) k_seeds_n<D, S><<<blocks_for(records, 256), 256, 0, stream>>>(a);
+    if (ev) {
+      const hipError_t e = hipEventRecord(ev[1], stream);
+      if (e != hipSuccess) return e;
+    }
+    k_assign_n<D, S><<<tiles, 256, 0, stream>>>(a);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace sb
+
+using namespace sb;
+
+extern "C" {
+
+int32_t sb_texel_bytes(int32_t fmt, int32_t channels) { return search_texel_bytes(fmt, channels); }
+
+size_t sb_tree_bytes(int32_t fmt, int32_t channels, int32_t sw, int32_t sh) {
+  const int32_t t = search_texel_bytes(fmt, channels);
+  if (t == 0 || !side_ok(sw) || !side_ok(sh)) return 0;
+  return tree_layout(size_t(sw) * size_t(sh), size_t(t)).total;
+}
+
+size_t sb_tree_workspace_bytes(int32_t fmt, int32_t channels, int32_t sw, int32_t sh) {
+  const int32_t t = search_texel_bytes(fmt, channels);
+  if (t == 0 || !side_ok(sw) || !side_ok(sh)) return 0;
+  return build_ws(nullptr, size_t(sw) * size_t(sh), size_t(t)).total;
+}
+
+int sb_tree_build(const void *guide, int32_t fmt, int32_t channels, int32_t sw, int32_t sh,
+                  const uint8_t *weights, void *tree, size_t tree_bytes, void *workspace,
+                  size_t workspace_bytes, hipStream_t stream) {
+  const int32_t t = search_texel_bytes(fmt, channels);
+  if (!guide || !tree || !workspace || t == 0 || !side_ok(sw) || !side_ok(sh)) return SB_EINVAL;
+  uint32_t wn[2];
+  if (!resolve_weights_n(weights, channels, wn)) return SB_EINVAL;
+  const uint32_t n = uint32_t(sw) * uint32_t(sh);
+  const TreeLayout l = tree_layout(n, size_t(t));
+  if (tree_bytes < l.total) return SB_ENOMEM;
+  const BuildWs ws = build_ws(static_cast<char *>(workspace), n, size_t(t));
+  if (workspace_bytes < ws.total) return SB_ENOMEM;
+  char *tb = static_cast<char *>(tree);
+  BuildArgs a;
+  memset(&a, 0, sizeof a);
+  a.meta = reinterpret_cast<u32x2 *>(tb + l.meta);
+  a.box = tb + l.box;
+  a.tvals = tb + l.vals;
+  a.tkeys = reinterpret_cast<uint32_t *>(tb + l.keys);
+  a.res = ws.res;
+  a.wn[0] = wn[0];
+  a.wn[1] = wn[1];
+  a.channels = channels;
+  hipError_t e = with_format(fmt, t, [&](auto d, auto s) -> hipError_t {
+    constexpr int D = decltype(d)::value, S = decltype(s)::value;
+    k_tree_init<S><<<blocks_for(n, 256), 256, 0, stream>>>(guide, n, uint32_t(sw), ws.vals[0],
+                                                          ws.keys[0], ws.list[0]);
+    uint32_t m = 1, nnodes = 1;
+    int cur = 0;
+    for (int32_t depth = 0; m > 0; ++depth) {
+      if (depth >= kMaxDepth) return hipErrorUnknown;  // every node at the limit is a leaf
+      a.list_in = ws.list[cur];
+      a.vals_in = ws.vals[cur];
+      a.keys_in = ws.keys[cur];
+      a.vals_out = ws.vals[cur ^ 1];
+      a.keys_out = ws.keys[cur ^ 1];
+      k_tree_level<D, S><<<m, 256, 0, stream>>>(a, depth);
+      k_tree_alloc<<<1, 1024, 0, stream>>>(ws.list[cur], ws.res, m, nnodes, ws.list[cur ^ 1],
+                                           a.meta, ws.ctr);
+      uint32_t hc[2] = {0u, 0u};
+      hipError_t ec = hipMemcpyAsync(hc, ws.ctr, sizeof hc, hipMemcpyDeviceToHost, stream);
+      if (ec == hipSuccess) ec = hipStreamSynchronize(stream);
+      if (ec != hipSuccess) return ec;
+      m = hc[0];
+      nnodes = hc[1];
+      cur ^= 1;
+    }
+    // header: nodes, texels, texel bytes, channels (for inspection only)
+    uint32_t hdr[4] = {nnodes, n, uint32_t(t), uint32_t(channels)};
+    hipError_t ec = hipMemcpyAsync(tb, hdr, sizeof hdr, hipMemcpyHostToDevice, stream);
+    if (ec == hipSuccess) ec = hipStreamSynchronize(stream);
+    if (ec != hipSuccess) return ec;
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) {
+    set_hip_error(e, "sb_tree_build");
+    return SB_EHIP;
+  }
+  return SB_OK;
+}
+
+int sb_tree_query(const sb_style *style, const void *queries, int64_t n, uint32_t *out,
+                  hipStream_t stream) {
+  if (!style || !fmt_search(style->fmt) || !style->tree || !queries || !out || n < 0 ||
+      n > int64_t(UINT32_MAX) || !side_ok(style->sw) || !side_ok(style->sh))
+    return SB_EINVAL;
+  const int32_t t = search_texel_bytes(style->fmt, style->channels);
+  uint32_t wn[2];
+  if (t == 0 || !resolve_weights_n(style->weights, style->channels, wn)) return SB_EINVAL;
+  if (n == 0) return SB_OK;
+  const TreeView tv = tree_view(style->tree, size_t(style->sw) * size_t(style->sh), size_t(t));
+  hipError_t e = with_format(style->fmt, t, [&](auto d, auto s) -> hipError_t {
+    constexpr int D = decltype(d)::value, S = decltype(s)::value;
+    k_tree_query<D, S><<<blocks_for(uint64_t(n), 256), 256, 0, stream>>>(tv, queries, uint32_t(n),
+                                                                        out, wn[0], wn[1]);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) {
+    set_hip_error(e, "sb_tree_query");
+    return SB_EHIP;
+  }
+  return SB_OK;
+}
+
+}  // extern "C"
+
+namespace sb {
+// The tree sections a frame of a search-format style reads.
+void fill_tree_args(const sb_style *style, FrameArgs *a) {
+  const int32_t t = search_texel_bytes(style->fmt, style->channels);
+  const TreeView tv = tree_view(style->tree, size_t(style->sw) * size_t(style->sh), size_t(t));
+  a->t_meta = tv.meta;
+  a->t_box = tv.box;
+  a->t_vals = tv.vals;
+  a->t_keys = tv.keys;
+  a->texel = t;
+  resolve_weights_n(style->weights, style->channels, a->wn);
+}
+}  // namespace sb

@@ -137,6 +137,7 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
     if (!fill_frame(r.style, r.tgt_guide, r.w, r.h, r.jitter, &r.params, probe_rgb, probe_chunk,
                     nullptr, &a, r.tgt_labels))
       return SB_EINVAL;
+    if (fmt_search(r.style->fmt)) return SB_EINVAL;  // batches hold table formats only
     if (i > 0 && r.arrival_s < reqs[i - 1].arrival_s) return SB_EINVAL;  // sorted arrivals
     if ((r.out_rgb == nullptr) != (r.out_chunk == nullptr)) return SB_EINVAL;  // both or neither
     // a batch of max_batch requests of this size must fit one slot's workspace

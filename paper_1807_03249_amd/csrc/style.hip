@@ -1,9 +1,11 @@
-// style.hip -- library-owned styles (sb_style_create / sb_style_destroy).
+// style.hip -- library-owned styles (sb_style_create, sb_style_create_n,
+// sb_style_destroy).
 //
 // The one place the library allocates device memory: a style's padded
-// exemplar, a copy of its guide and its exact lookup table (Sec. 3.1) in one
-// block, built on the caller's stream with the same launchers the
-// caller-owned path uses.  The build workspace is freed before returning.
+// exemplar, a copy of its guide and its exact lookup table (Sec. 3.1), or for
+// guides of many channels its search tree, in one block, built on the
+// caller's stream with the same launchers the caller-owned path uses.  The
+// build workspace is freed before returning.
 #include <new>
 
 #include "sb_internal.h"
@@ -74,6 +76,60 @@ int sb_style_create(const uint8_t *src_rgb, const void *src_guide, int32_t sw, i
   o->s.sh = sh;
   o->s.fmt = fmt;
   o->s.lut_bits = lut_bits;
+  o->magic = kStyleMagic;
+  *out = &o->s;
+  return SB_OK;
+}
+
+int sb_style_create_n(const uint8_t *src_rgb, const void *src_guide, int32_t sw, int32_t sh,
+                      int32_t fmt, int32_t channels, const uint8_t *weights, hipStream_t stream,
+                      sb_style **out) {
+  const int32_t t = sb_texel_bytes(fmt, channels);
+  uint32_t wn[2];
+  if (!src_rgb || !src_guide || !out || !side_ok(sw) || !side_ok(sh) || t == 0 ||
+      !resolve_weights_n(weights, channels, wn))
+    return SB_EINVAL;
+  const size_t ex_bytes = align256(ex_texels(sw, sh) * 4);
+  const size_t guide_bytes = align256(size_t(sw) * size_t(sh) * size_t(t));
+  const size_t tree_bytes = sb_tree_bytes(fmt, channels, sw, sh);
+  const size_t wsb = sb_tree_workspace_bytes(fmt, channels, sw, sh);
+  OwnedStyle *o = new (std::nothrow) OwnedStyle;
+  if (!o) return SB_ENOMEM;
+  memset(o, 0, sizeof *o);
+  void *ws = nullptr;
+  hipError_t e = hipMalloc(&o->block, ex_bytes + guide_bytes + tree_bytes);
+  if (e == hipSuccess) e = hipMalloc(&ws, wsb);
+  int rc = SB_OK;
+  if (e == hipSuccess) {
+    char *blk = static_cast<char *>(o->block);
+    uint32_t *rgba = reinterpret_cast<uint32_t *>(blk);
+    void *guide = blk + ex_bytes;
+    void *tree = blk + ex_bytes + guide_bytes;
+    e = hipMemcpyAsync(guide, src_guide, size_t(sw) * size_t(sh) * size_t(t),
+                       hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) e = launch_pack_exemplar(src_rgb, sw, sh, rgba, stream);
+    // the build synchronises the stream, so the workspace is idle after it
+    if (e == hipSuccess)
+      rc = sb_tree_build(guide, fmt, channels, sw, sh, weights, tree, tree_bytes, ws, wsb, stream);
+    else
+      hipStreamSynchronize(stream);
+    o->s.rgba = rgba;
+    o->s.guide = guide;
+    o->s.tree = tree;
+  }
+  if (ws) hipFree(ws);
+  if (e != hipSuccess || rc != SB_OK) {
+    if (e != hipSuccess) set_hip_error(e, "sb_style_create_n");
+    if (o->block) hipFree(o->block);
+    delete o;
+    return rc != SB_OK ? rc : SB_EHIP;
+  }
+  o->s.sw = sw;
+  o->s.sh = sh;
+  o->s.fmt = fmt;
+  o->s.lut_bits = 0;
+  o->s.channels = channels;
+  for (int32_t k = 0; weights && k < channels; ++k) o->s.weights[k] = weights[k];
   o->magic = kStyleMagic;
   *out = &o->s;
   return SB_OK;

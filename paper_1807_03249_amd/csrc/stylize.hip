@@ -18,24 +18,17 @@
 // Every side is at most SB_MAX_SIDE = 8192 (the chunk code holds 13-bit
 // coordinates), so pixel and texel indices are formed with full-rate 24-bit
 // multiplies (__umul24 / __mul24) instead of 32- or 64-bit ones.
-#include "sb_internal.h"
+#include "sb_device.h"
 
 namespace sb {
 namespace {
 
-typedef short short2_t __attribute__((ext_vector_type(2)));
 // Dword-aligned vectors of 2..4 texels (global loads need dword alignment
 // only).
 typedef uint32_t u32x2a4 __attribute__((ext_vector_type(2), aligned(4)));
 typedef uint32_t u32x3a4 __attribute__((ext_vector_type(3), aligned(4)));
 typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-
-// Seed records as plain vectors in global memory.
-__device__ __forceinline__ SB_GLOBAL u32x2 *seed_table(const FrameArgs &a) {
-  return reinterpret_cast<SB_GLOBAL u32x2 *>(glb(a.seeds));
-}
 
 // A guide texel as stored (2 x u8, 2 x u16 or 3 x u8 in a word) and unpacked
 // to its guide word: two channels as a u16 pair (channel 1 in the high
@@ -94,25 +87,6 @@ __device__ inline bool error_below(uint32_t a, uint32_t b, uint32_t t, uint32_t 
   }
 }
 
-// Offsets are two int16 in one word; x in the low half.
-__device__ inline uint32_t pack_off(int32_t dx, int32_t dy) {
-  return (uint32_t(dx) & 0xFFFFu) | (uint32_t(dy) << 16);
-}
-__device__ inline int32_t off_x(uint32_t o) { return int32_t(int16_t(o & 0xFFFFu)); }
-__device__ inline int32_t off_y(uint32_t o) { return int32_t(int16_t(o >> 16)); }
-
-// Chunk code of the seed whose position word (4x | 4y << 16) is q4.
-__device__ inline uint32_t chunk_code(int32_t level, uint32_t q4) {
-  return (uint32_t(level) << 26) | ((q4 >> 18) << 13) | ((q4 & 0xFFFFu) >> 2);
-}
-
-// What the vote needs of a pixel's offset o = NNF[p] - p: the byte distance
-// 4 (oy P + ox) it adds to a pixel's position in the padded exemplar (rows of
-// P texels) to reach the co-located texel of that source patch.
-__device__ inline uint32_t vote_distance(const FrameArgs &a, uint32_t off) {
-  return uint32_t(4 * (__mul24(off_y(off), a.ex_stride) + off_x(off)));
-}
-
 // Every texel of the padded exemplar: source texels with alpha 1, margins and
 // zero rows 0.
 __global__ void k_pack_exemplar(const uint8_t *rgb, int32_t sw, int32_t sh, uint32_t n,
@@ -136,16 +110,6 @@ __device__ inline const uint32_t *lut_of(const FrameArgs &a, uint32_t pidx) {
   if (!a.tgt_labels) return a.lut;
   const uint32_t l = min(uint32_t(glb(a.tgt_labels)[pidx]), uint32_t(a.nlabels - 1));
   return a.label_luts + (size_t(l) << a.lut_log2);
-}
-
-// Jitter word jx | jy << 16 of cell (cx, cy) of a level with log2 spacing ls
-// and a ncx-wide cell grid: from the hash (level hash state hk), zero, or the
-// caller's table (the level's entries from joff on).
-__device__ inline uint32_t cell_jitter(const FrameArgs &a, int32_t ls, int32_t ncx, int32_t joff,
-                                       uint32_t hk, int32_t cx, int32_t cy) {
-  if (a.jmode == SB_JITTER_HASH) return hash_jitter(hk, ls, uint32_t(cx), uint32_t(cy));
-  if (a.jmode == SB_JITTER_NONE) return 0u;
-  return glb(a.jitter)[uint32_t(joff) + __umul24(uint32_t(cy), uint32_t(ncx)) + uint32_t(cx)];
 }
 
 // The seed record of cell (cx, cy) of a level with log2 spacing ls, a
@@ -196,17 +160,6 @@ __device__ inline void seeds_body(const FrameArgs &a, uint32_t idx) {
 template <int FMT>
 __global__ void __launch_bounds__(256) k_seeds(FrameArgs a) {
   seeds_body<FMT>(a, blockIdx.x * blockDim.x + threadIdx.x);
-}
-
-// NearestSeed key of candidate k (k = (dx+1)*3 + (dy+1): x outer, y inner):
-// 16 d + k for the squared distance d, from the packed int16 pair 4q - 4p
-// (|4 dx| <= 4 * 8191 fits int16, so 16 d + k <= 2146959400 < 2^31 - 1).
-// The empty record (-32768, -32768) saturates the subtraction and then the
-// dot product, giving INT32_MAX, above every real key.  The minimum key over
-// k = 0..8 is NearestSeed's first strict minimum; INT32_MAX means no seed.
-__device__ inline int32_t seed_key(uint32_t q4, short2_t p4, int32_t k) {
-  const short2_t dv = __builtin_elementwise_sub_sat(__builtin_bit_cast(short2_t, q4), p4);
-  return __builtin_amdgcn_sdot2(dv, dv, k, true);
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -551,15 +504,6 @@ __device__ inline void assign_tile(const FrameArgs &a, uint32_t tile, uint32_t t
       assign_pixel<FMT, SEG>(a, tx0 + int32_t(tid & 15) + 16 * (b % BX),
                              ty0 + int32_t(tid >> 4) + 16 * (b / BX));
   }
-}
-
-// Tile of workgroup `bid` out of n: workgroups are dealt to the 8 XCDs in
-// turn (bid mod 8), so XCD x takes the x-th contiguous run of tiles -- a band
-// of rows -- and its L2 sees the source regions of one band instead of
-// scraps of all of them.  A bijection on [0, n) for any n.
-__device__ inline uint32_t xcd_tile(uint32_t bid, uint32_t n) {
-  const uint32_t x = bid & 7u, local = bid >> 3, q = n >> 3, r = n & 7u;
-  return x * q + min(x, r) + local;
 }
 
 template <int FMT, int G, int B, bool SEG>
@@ -1160,19 +1104,24 @@ hipError_t launch_stylize(const FrameArgs &a, int32_t fmt, const Tune &t, hipEve
   tile_counts(a, t, c);
   hipError_t e = hipSuccess;
   if (ev) e = hipEventRecord(ev[0], stream);
-  if (e == hipSuccess && c[0] > 0) {
-    if (fmt == SB_GUIDE_U8X2)
-      k_seeds<SB_GUIDE_U8X2><<<c[0], 256, 0, stream>>>(a);
-    else if (fmt == SB_GUIDE_U8X3)
-      k_seeds<SB_GUIDE_U8X3><<<c[0], 256, 0, stream>>>(a);
-    else
-      k_seeds<SB_GUIDE_U16X2><<<c[0], 256, 0, stream>>>(a);
-  }
-  if (ev && e == hipSuccess) e = hipEventRecord(ev[1], stream);
-  if (e == hipSuccess) {
-    if (fmt == SB_GUIDE_U8X2) launch_assign_any<SB_GUIDE_U8X2>(a, t, c[1], stream);
-    else if (fmt == SB_GUIDE_U8X3) launch_assign_any<SB_GUIDE_U8X3>(a, t, c[1], stream);
-    else launch_assign_any<SB_GUIDE_U16X2>(a, t, c[1], stream);
+  if (fmt_search(fmt)) {
+    // seed and level-loop passes of the search formats; the vote is shared
+    if (e == hipSuccess) e = launch_search_frame(a, ev, stream);
+  } else {
+    if (e == hipSuccess && c[0] > 0) {
+      if (fmt == SB_GUIDE_U8X2)
+        k_seeds<SB_GUIDE_U8X2><<<c[0], 256, 0, stream>>>(a);
+      else if (fmt == SB_GUIDE_U8X3)
+        k_seeds<SB_GUIDE_U8X3><<<c[0], 256, 0, stream>>>(a);
+      else
+        k_seeds<SB_GUIDE_U16X2><<<c[0], 256, 0, stream>>>(a);
+    }
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[1], stream);
+    if (e == hipSuccess) {
+      if (fmt == SB_GUIDE_U8X2) launch_assign_any<SB_GUIDE_U8X2>(a, t, c[1], stream);
+      else if (fmt == SB_GUIDE_U8X3) launch_assign_any<SB_GUIDE_U8X3>(a, t, c[1], stream);
+      else launch_assign_any<SB_GUIDE_U16X2>(a, t, c[1], stream);
+    }
   }
   if (ev && e == hipSuccess) e = hipEventRecord(ev[2], stream);
   if (e == hipSuccess) {

@@ -215,11 +215,86 @@ def test_channel_weight_validation(L):
         return L.sb_stylize(ctypes.byref(style), fake, 64, 64, fake, ctypes.byref(p), fake, fake,
                             None, fake, ws, None)
 
-    w4 = ctypes.c_uint8 * 4
+    w8 = ctypes.c_uint8 * 8
     assert frame(sb.SbStyle(fake, fake, fake, 64, 64, 0, 4, None, None, 0,
-                            w4(2, 1, 1, 0))) == sb.SB_EINVAL
+                            w8(2, 1, 1, 0))) == sb.SB_EINVAL
     assert frame(sb.SbStyle(fake, fake, fake, 64, 64, 2, 4, None, None, 0,
-                            w4(1, 1, 128, 0))) == sb.SB_EINVAL
+                            w8(1, 1, 128, 0))) == sb.SB_EINVAL
+
+
+@pytest.mark.parametrize("fmt,channels,want", [
+    (3, 2, 4), (3, 4, 4), (3, 5, 8), (3, 8, 8), (4, 2, 4), (4, 3, 8), (4, 4, 8), (4, 5, 16),
+    (4, 8, 16), (3, 1, 0), (3, 9, 0), (2, 3, 0), (0, 2, 0), (5, 4, 0)])
+def test_texel_bytes(L, fmt, channels, want):
+    assert L.sb_texel_bytes(fmt, channels) == want
+
+
+def test_search_format_validation(L):
+    """Guides of many channels: sizes, the tree build and query, and frames
+    of search-format styles refuse bad arguments before touching memory."""
+    import paper_1807_03249_amd as sb
+
+    fake = 0x1000
+    U8XN, U16XN = sb.GUIDE_U8XN, sb.GUIDE_U16XN
+    tb = L.sb_tree_bytes(U8XN, 5, 64, 48)
+    wb = L.sb_tree_workspace_bytes(U8XN, 5, 64, 48)
+    # at most 2n - 1 nodes of 8 B and two 8-byte box texels, n texels and keys
+    n = 64 * 48
+    assert tb >= 2 * n * 8 + 2 * n * 16 + n * 8 + n * 4
+    assert wb >= 2 * n * (8 + 4)
+    assert L.sb_tree_bytes(U8XN, 9, 64, 48) == 0 and L.sb_tree_bytes(U8XN, 5, 0, 48) == 0
+    assert L.sb_tree_workspace_bytes(2, 3, 64, 48) == 0
+    w8 = ctypes.c_uint8 * 8
+    ok_w = w8(1, 2, 3, 4, 5)
+
+    def build(fmt=U8XN, ch=5, w=ok_w, tree_bytes=tb, ws_bytes=wb, guide=fake, tree=fake,
+              ws=fake):
+        return L.sb_tree_build(guide, fmt, ch, 64, 48, w, tree, tree_bytes, ws, ws_bytes, None)
+
+    assert build(fmt=2) == sb.SB_EINVAL
+    assert build(ch=1) == sb.SB_EINVAL
+    assert build(w=w8(1, 2, 128, 4, 5)) == sb.SB_EINVAL
+    assert build(guide=None) == sb.SB_EINVAL and build(tree=None) == sb.SB_EINVAL
+    assert build(ws=None) == sb.SB_EINVAL
+    assert build(tree_bytes=tb - 1) == sb.SB_ENOMEM
+    assert build(ws_bytes=wb - 1) == sb.SB_ENOMEM
+    # a weight past the channel count is ignored
+    assert build(fmt=U16XN, ch=2, w=w8(1, 1, 200), tree_bytes=0) == sb.SB_ENOMEM
+
+    def style(fmt=U8XN, lut_bits=0, nlabels=0, channels=5, tree=fake, w=None):
+        return sb.SbStyle(fake, fake, None, 64, 48, fmt, lut_bits, fake if nlabels else None,
+                          fake if nlabels else None, nlabels, w or w8(), channels, tree)
+
+    out = fake
+    assert L.sb_tree_query(ctypes.byref(style(fmt=2)), fake, 4, out, None) == sb.SB_EINVAL
+    assert L.sb_tree_query(ctypes.byref(style()), fake, -1, out, None) == sb.SB_EINVAL
+    assert L.sb_tree_query(ctypes.byref(style(tree=None)), fake, 4, out, None) == sb.SB_EINVAL
+    assert L.sb_tree_query(ctypes.byref(style(channels=9)), fake, 4, out, None) == sb.SB_EINVAL
+    assert L.sb_tree_query(ctypes.byref(style()), fake, 0, out, None) == sb.SB_OK  # no work
+    p = sb.params(4, 8, 32, 3)
+    ws = sb.workspace_bytes(64, 48, p)
+
+    def frame(st, labels=None):
+        if labels is not None:
+            return L.sb_stylize_seg(ctypes.byref(st), fake, labels, 64, 48, fake,
+                                    ctypes.byref(p), fake, fake, None, fake, ws, None, None)
+        return L.sb_stylize(ctypes.byref(st), fake, 64, 48, fake, ctypes.byref(p), fake, fake,
+                            None, fake, ws, None)
+
+    assert frame(style(lut_bits=8)) == sb.SB_EINVAL
+    assert frame(style(nlabels=2)) == sb.SB_EINVAL
+    assert frame(style(), labels=fake) == sb.SB_EINVAL
+    assert frame(style(tree=None)) == sb.SB_EINVAL
+    assert frame(style(channels=1)) == sb.SB_EINVAL
+    assert frame(style(w=w8(1, 1, 1, 1, 255))) == sb.SB_EINVAL
+    sp = ctypes.c_void_p()
+    assert L.sb_style_create_n(fake, fake, 64, 48, U8XN, 9, None, None,
+                               ctypes.byref(sp)) == sb.SB_EINVAL
+    assert L.sb_style_create_n(fake, fake, 64, 48, 1, 4, None, None,
+                               ctypes.byref(sp)) == sb.SB_EINVAL
+    assert L.sb_style_create_n(None, fake, 64, 48, U8XN, 4, None, None,
+                               ctypes.byref(sp)) == sb.SB_EINVAL
+    assert not sp.value
 
 
 def test_jitter_fill_validation(L):

@@ -1,0 +1,220 @@
+"""GPU parity of guides of many channels (formats 3 and 4: 2..8 channels of 8
+or 16 bits, each lookup the exact nearest source texel through the k-d tree
+built on the device) against the oracle.  Tolerance 0: every output is an
+integer (source coordinates, chunk codes, RGB bytes)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(8, 2), (8, 3), (8, 4), (8, 5), (8, 8), (16, 2), (16, 3), (16, 4), (16, 5), (16, 8)]
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def sb():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1807_03249_amd as sb
+
+    return sb
+
+
+def _dev(a):
+    import torch
+
+    a = np.ascontiguousarray(a)
+    return torch.from_numpy(a.view(np.int16) if a.dtype == np.uint16 else a).cuda()
+
+
+def _host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _random_source(rng, depth, channels, sw, sh, levels_of_values):
+    top = (1 << depth) - 1
+    vals = np.linspace(0, top, levels_of_values).astype(np.int64)
+    chans = [vals[rng.integers(0, levels_of_values, (sh, sw))] for _ in range(channels)]
+    g = workloads.guide_n(chans, depth)
+    g[: sh // 3, : sw // 4] = g[0, 0]  # a block of identical texels (one collapsed leaf)
+    e = g.shape[2]
+    if e > channels:  # elements past the channels hold noise that must be ignored
+        g[..., channels:] = rng.integers(0, top + 1, g[..., channels:].shape)
+    return g
+
+
+@pytest.mark.parametrize("depth,channels", CASES)
+def test_tree_query_random(sb, depth, channels):
+    """Random sources with many duplicates and ties, random and copied
+    queries, unit, random and zero weights: every lookup equals the oracle's
+    brute force."""
+    import torch
+
+    rng = np.random.default_rng(depth * 100 + channels)
+    sw, sh = 53, 37
+    g = _random_source(rng, depth, channels, sw, sh, 6)
+    rgb = rng.integers(0, 256, (sh, sw, 3)).astype(np.uint8)
+    top = (1 << depth) - 1
+    q = workloads.guide_n([rng.integers(0, top + 1, (1, 3000)) for _ in range(channels)],
+                          depth).reshape(3000, -1)
+    q = np.concatenate([q, g.reshape(sw * sh, -1)[rng.integers(0, sw * sh, 1000)]])
+    w = rng.integers(0, 128, channels)
+    w[rng.integers(0, channels)] = 0
+    for weights in (None, w):
+        say(f"tree query depth={depth} channels={channels} weights={weights}")
+        st = sb.Style(rgb, g, channels=channels, weights=weights)
+        got = _host(st.query(_dev(q)))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got, oracle.nn_query_n(g, channels, q, weights=weights))
+
+
+@pytest.mark.parametrize("depth", [8, 16])
+def test_tree_query_workload_style(sb, depth):
+    """The features workload's 512 x 512 style (five 8-bit or four 16-bit
+    channels): lookups of 20 000 target texels and 5 000 random ones against
+    the oracle's sweep (pinned to brute force)."""
+    styles, frames = workloads.config(7, depth=depth)
+    st_np, fr = styles[0], frames[0]
+    ch = 5 if depth == 8 else 4
+    rng = np.random.default_rng(70 + depth)
+    flat = fr.guide.reshape(fr.w * fr.h, -1)
+    top = (1 << depth) - 1
+    q = np.concatenate([flat[rng.integers(0, flat.shape[0], 20000)],
+                        workloads.guide_n([rng.integers(0, top + 1, (1, 5000))
+                                           for _ in range(ch)], depth).reshape(5000, -1)])
+    say(f"workload-7 style lookups depth={depth}")
+    st = sb.Style(st_np.rgb, st_np.guide, channels=ch)
+    got = _host(st.query(_dev(q)))
+    np.testing.assert_array_equal(got, oracle.nn_sweep_n(st_np.guide, ch, q))
+
+
+def _frame_cases():
+    # (levels, finest, threshold scale, radius, jitter mode, weights)
+    return [
+        (4, 8, 1.0, 3, "hash", None),
+        (3, 4, 1.0, 2, "table", None),
+        (4, 8, 1.0, 1, "none", None),
+        (0, 8, 1.0, 2, "hash", None),   # no levels: texture mapping
+        (2, 2, 1.0, 0, "hash", None),   # cells finer than 8 pixels, copy vote
+        (4, 8, 0.0, 3, "hash", None),   # threshold 0: every pixel searches
+        (4, 8, 4.0, 7, "hash", None),   # large window
+        (4, 8, 1.0, 3, "hash", "w"),    # channel weights
+    ]
+
+
+@pytest.mark.parametrize("depth", [8, 16])
+@pytest.mark.parametrize("case", range(len(_frame_cases())))
+def test_frames_match_oracle(sb, depth, case):
+    """Ragged frames (333 x 177, tiles of 64 x 16 and a partial tail) of the
+    features workload against the oracle's whole path, element by element."""
+    import torch
+
+    levels, finest, tscale, radius, jmode, wmode = _frame_cases()[case]
+    styles, frames = workloads.config(7, depth=depth, w=333, h=177, size=96)
+    st_np, fr = styles[0], frames[0]
+    ch = 5 if depth == 8 else 4
+    weights = None if wmode is None else [3, 1, 2, 1, 5][:ch]
+    t = int(fr.params.threshold * tscale)
+    jit, seed = None, None
+    if jmode == "hash":
+        seed = 4242 + case
+    elif jmode == "table" and levels > 0:
+        jit = workloads.jitter_table(fr.w, fr.h, levels, finest, 77 + case)
+    say(f"search frame depth={depth} L={levels} finest={finest} t={t} r={radius} "
+        f"jitter={jmode} weights={weights}")
+    e_rgb, e_chunk, e_nnf = oracle.stylize_n(st_np.rgb, st_np.guide, ch, fr.guide, jit, levels,
+                                             finest, t, radius, weights=weights, seed=seed)
+    st = sb.Style(st_np.rgb, st_np.guide, channels=ch, weights=weights)
+    prm = sb.params(levels, finest, t, radius, seed=seed)
+    jt = _dev(jit.view(np.int32)) if jit is not None else None
+    for tune in (None, (2, 8, 2, 2, 1)):
+        rgb, chunk, nnf = sb.stylize(st, _dev(fr.guide), jt, prm, want_nnf=True, tune=tune)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(_host(chunk), e_chunk, err_msg=f"chunk tune={tune}")
+        np.testing.assert_array_equal(_host(nnf), e_nnf, err_msg=f"nnf tune={tune}")
+        np.testing.assert_array_equal(rgb.cpu().numpy(), e_rgb, err_msg=f"rgb tune={tune}")
+
+
+@pytest.mark.parametrize("depth", [8, 16])
+def test_full_size_frame(sb, depth):
+    """The features workload at its full size (1920 x 1080 target, 512 x 512
+    style), every pixel against the oracle."""
+    import torch
+
+    styles, frames = workloads.config(7, depth=depth)
+    st_np, fr = styles[0], frames[0]
+    ch = 5 if depth == 8 else 4
+    p = fr.params
+    say(f"full-size search frame depth={depth} {fr.w}x{fr.h}")
+    st = sb.Style(st_np.rgb, st_np.guide, channels=ch)
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
+    rgb, chunk, nnf = sb.stylize(st, _dev(fr.guide), None, prm, want_nnf=True)
+    torch.cuda.synchronize()
+    g_rgb, g_chunk, g_nnf = rgb.cpu().numpy(), _host(chunk), _host(nnf)
+    say("oracle full frame")
+    e_rgb, e_chunk, e_nnf = oracle.stylize_n(st_np.rgb, st_np.guide, ch, fr.guide, None,
+                                             p.levels, p.finest, p.threshold, p.radius,
+                                             seed=fr.seed)
+    np.testing.assert_array_equal(g_chunk, e_chunk)
+    np.testing.assert_array_equal(g_nnf, e_nnf)
+    np.testing.assert_array_equal(g_rgb, e_rgb)
+
+
+def test_other_entry_points(sb):
+    """A search-format style through sb_stylize_noalloc, sb_stylize_frames
+    and a library-owned style (sb_style_create_n) gives the sb_stylize
+    frame; batches and serving refuse it."""
+    import torch
+
+    styles, frames = workloads.config(7, w=200, h=150, size=64)
+    st_np, fr = styles[0], frames[0]
+    p = fr.params
+    st = sb.Style(st_np.rgb, st_np.guide, channels=5)
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius, seed=fr.seed)
+    g = _dev(fr.guide)
+    e_rgb, e_chunk = sb.stylize(st, g, None, prm)
+    torch.cuda.synchronize()
+    say("noalloc with a search-format style")
+    rgb, chunk = torch.empty_like(e_rgb), torch.empty_like(e_chunk)
+    sb.stylize_noalloc(st, g, None, prm, rgb, chunk)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, e_rgb) and torch.equal(chunk, e_chunk)
+    say("stylize_frames with a search-format style")
+    jobs = [sb.FrameJob(st, g, None, prm) for _ in range(2)]
+    sb.stylize_frames(jobs)
+    torch.cuda.synchronize()
+    for j in jobs:
+        assert torch.equal(j.out_rgb, e_rgb) and torch.equal(j.out_chunk, e_chunk)
+    with pytest.raises(sb.StyleBlitError):
+        b = sb.Batch(use_graph=False)
+        try:
+            b.run(jobs)
+        finally:
+            b.close()
+    say("library-owned search-format style")
+    L = sb.lib()
+    rgb_d, guide_d = _dev(st_np.rgb), _dev(st_np.guide)
+    sp = ctypes.c_void_p()
+    s = torch.cuda.current_stream().cuda_stream
+    assert L.sb_style_create_n(rgb_d.data_ptr(), guide_d.data_ptr(), st_np.sw, st_np.sh,
+                               sb.GUIDE_U8XN, 5, None, s, ctypes.byref(sp)) == sb.SB_OK
+    try:
+        ws = torch.empty(sb.workspace_bytes(fr.w, fr.h, prm), dtype=torch.uint8, device="cuda")
+        rgb2, chunk2 = torch.empty_like(e_rgb), torch.empty_like(e_chunk)
+        rc = L.sb_stylize(ctypes.cast(sp, ctypes.POINTER(sb.SbStyle)), g.data_ptr(), fr.w, fr.h,
+                          None, ctypes.byref(prm), rgb2.data_ptr(), chunk2.data_ptr(), None,
+                          ws.data_ptr(), ws.numel(), s)
+        assert rc == sb.SB_OK
+        torch.cuda.synchronize()
+        assert torch.equal(rgb2, e_rgb) and torch.equal(chunk2, e_chunk)
+    finally:
+        assert L.sb_style_destroy(sp) == sb.SB_OK
