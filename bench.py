@@ -49,7 +49,8 @@ def instr_file(workload_name):
     return os.path.join(PROFILES, f"path_{workload_name}_instructions.json")
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_1807_03249_amd", "csrc", "stylize.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1807_03249_amd", "csrc", f)
+               for f in ("stylize.hip", "sb_device.h")]
 
 
 def path_algorithmic_bytes(w, h, fmt, sw, sh, nseeds, nfallback):
@@ -73,8 +74,13 @@ def progress(msg):
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the frame kernels' sources (the kernels and the device helpers
+    they include), which the counter summaries record."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_per_launch(workload_name):
@@ -148,6 +154,8 @@ def main():
     ap.add_argument("--no-anim", action="store_true", help="skip the animation leg")
     ap.add_argument("--no-channels", action="store_true",
                     help="skip the three-channel (appearance) guide leg")
+    ap.add_argument("--no-search", action="store_true",
+                    help="skip the many-channel (exact search) leg")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-qps", type=str, default="2000,12000,24000,36000,48000",
                     help="comma-separated request rates of the serving sweep")
@@ -317,6 +325,9 @@ def main():
     progress("animation leg done")
     chan = None if args.no_channels else channels_leg(sb, torch, np, workloads, ms_per_step)
     progress("three-channel leg done")
+    search = None if args.no_search else search_leg(sb, torch, np, workloads, ms_per_step,
+                                                    cpu_frame=not args.no_cpu)
+    progress("many-channel leg done")
     batch = None if args.no_batch else batch_leg(sb, at, torch, workloads, args.no_tune)
     progress("batch leg done")
     serve = None
@@ -375,6 +386,7 @@ def main():
         "segmentation": seg,
         "animation": anim,
         "three_channels": chan,
+        "many_channels": search,
         "batch": batch,
         "serve": serve,
     }
@@ -454,6 +466,86 @@ def channels_leg(sb, torch, np, workloads, plain_ms, steps=100):
             "fallback_fraction": round(float((lv == p.levels).mean()), 4),
             "table_mib": round(style.lut.numel() * 4 / 2**20, 1),
             "style_registration_ms": round(reg_ms, 3)}
+
+
+def search_leg(sb, torch, np, workloads, plain_ms, steps=50, cpu_frame=True):
+    """Guides of many channels, each lookup the exact search on the k-d tree
+    built on the GPU: the features workload at 1080p with five 8-bit channels
+    (normals, appearance, chroma) and with four 16-bit ones (texture
+    coordinates, normals); tree build, frame and passes, searches per frame.
+    Also the three-channel appearance frame through the search instead of
+    its 2^24-bin table, and one oracle frame for scale."""
+    import oracle
+
+    def frame_stats(style, guide_np, p, seed):
+        prm = sb.params(p.levels, p.finest, p.threshold, p.radius, seed=seed)
+        g = torch.from_numpy(guide_np.view(np.int16) if guide_np.dtype == np.uint16
+                             else guide_np).cuda()
+        h, w = guide_np.shape[:2]
+        rgb = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
+        chunk = torch.empty((h, w), dtype=torch.int32, device="cuda")
+        ws = torch.empty(sb.workspace_bytes(w, h, prm), dtype=torch.uint8, device="cuda")
+        plan = sb.FramePlan(style, g, None, prm, rgb, chunk, ws)
+        for _ in range(5):
+            plan.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.launch()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ev = sb.TimingEvents()
+        passes = []
+        for _ in range(20):
+            sb.stylize(style, g, None, prm, out_rgb=rgb, out_chunk=chunk, workspace=ws, events=ev)
+            torch.cuda.synchronize()
+            passes.append(ev.pass_ms())
+        ev.close()
+        med = np.median(np.array(passes), axis=0)
+        lv = chunk.cpu().numpy().view(np.uint32) >> 26
+        nfb = int((lv == p.levels).sum())
+        nseeds = int(sum(-(-w // (p.finest << k)) * -(-h // (p.finest << k))
+                         for k in range(p.levels)))
+        return {"ms_per_frame": round(ms, 6), "mpixel_per_s": round(w * h / (ms * 1e-3) / 1e6, 2),
+                "pass_ms": {"seeds": round(float(med[0]), 6), "level_loop": round(float(med[1]), 6),
+                            "vote": round(float(med[2]), 6)},
+                "fallback_fraction": round(nfb / (w * h), 4),
+                "searches_per_frame": nseeds + nfb,
+                "searches_per_us": round((nseeds + nfb) / ((med[0] + med[1]) * 1e3), 1)}
+
+    out = {}
+    for depth, ch in ((8, 5), (16, 4)):
+        styles, frames = workloads.config(7, depth=depth)
+        st_np, fr = styles[0], frames[0]
+        style = sb.Style(st_np.rgb, st_np.guide, channels=ch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        style = sb.Style(st_np.rgb, st_np.guide, channels=ch)
+        torch.cuda.synchronize()
+        reg_ms = (time.perf_counter() - t0) * 1e3
+        hdr = style.tree[:16].cpu().numpy().view(np.uint32)
+        r = {"workload": workloads.CONFIG_NAMES[7], "channels": ch, "depth": depth,
+             "threshold": fr.params.threshold, "style_registration_ms": round(reg_ms, 3),
+             "tree_nodes": int(hdr[0]), "tree_mib": round(style.tree.numel() / 2**20, 1)}
+        r.update(frame_stats(style, fr.guide, fr.params, fr.seed))
+        r["vs_two_channel"] = round(plain_ms / r["ms_per_frame"], 3)
+        if cpu_frame and depth == 8:
+            p = fr.params
+            c0 = time.perf_counter()
+            oracle.stylize_n(st_np.rgb, st_np.guide, ch, fr.guide, None, p.levels, p.finest,
+                             p.threshold, p.radius, seed=fr.seed)
+            r["oracle_frame_s"] = round(time.perf_counter() - c0, 3)
+            r["oracle_threads"] = oracle.set_threads(0)
+        out[f"u{depth}x{ch}"] = r
+    # the appearance workload (three 8-bit channels) through the search
+    styles, frames = workloads.config(6)
+    st_np, fr = styles[0], frames[0]
+    style = sb.Style(st_np.rgb, st_np.guide, channels=3)
+    r = {"workload": workloads.CONFIG_NAMES[6], "channels": 3, "depth": 8,
+         "tree_mib": round(style.tree.numel() / 2**20, 1)}
+    r.update(frame_stats(style, fr.guide, fr.params, fr.seed))
+    out["u8x3_search"] = r
+    return out
 
 
 def anim_leg(sb, torch, np, workloads, style, w, h, p, nframes=12, reps=5):

@@ -53,20 +53,21 @@ __host__ __device__ constexpr int32_t search_texel_bytes(int32_t fmt, int32_t ch
 }
 
 // The search tree of an n-texel source guide of t-byte texels, in one
-// buffer: node records (uint2: inner {first child, 0}, the two children
-// adjacent; leaf {first texel, count | kTreeLeaf}), node boxes (the lowest
-// and highest value of every element over the node's texels, as two
-// texels), leaf texels and their source coordinates (x | y << 16).
+// buffer: node records of 2t + 8 bytes -- the node's box (the lowest and the
+// highest value of every element over its texels, as two texels) and its
+// link (inner: {first child, 0}, the two children adjacent; leaf: {first
+// texel, count | kTreeLeaf}) -- then the leaves' texels and their source
+// coordinates (x | y << 16).  A tree has at most 2n - 1 nodes.
 constexpr uint32_t kTreeLeaf = 0x80000000u;
+__host__ __device__ constexpr size_t tree_record_bytes(size_t t) { return 2 * t + 8; }
 struct TreeLayout {
-  size_t meta, box, vals, keys, total;
+  size_t nodes, vals, keys, total;
 };
 inline TreeLayout tree_layout(size_t n, size_t t) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   TreeLayout l;
-  l.meta = 256;
-  l.box = l.meta + al(2 * n * 8);
-  l.vals = l.box + al(2 * n * 2 * t);
+  l.nodes = 256;
+  l.vals = l.nodes + al(2 * n * tree_record_bytes(t));
   l.keys = l.vals + al(n * t);
   l.total = l.keys + al(n * 4);
   return l;
@@ -140,8 +141,7 @@ struct FrameArgs {
   // search formats (SB_GUIDE_U8XN / U16XN): the tree's sections, the
   // texel size and the eight channel weights (byte k = weight of element k,
   // 0 past the guide's channels)
-  const void *t_meta;
-  const void *t_box;
+  const void *t_nodes;
   const void *t_vals;
   const uint32_t *t_keys;
   int32_t texel;

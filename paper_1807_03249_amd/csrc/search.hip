@@ -23,7 +23,9 @@
 //   k_assign_n   the level loop of Algorithm 2 per pixel (64 x 16 tiles, four
 //                rows per thread) with the many-channel error; pixels no
 //                level accepts are listed in LDS and searched by the tile's
-//                threads in list order, so the searches fill whole waves.
+//                threads in list order, so the searches fill whole waves,
+//                each starting from the nearest candidate its level loop
+//                measured.
 //   k_tree_query the search of caller-given texels (sb_tree_query).
 #include <stdio.h>
 #include <string.h>
@@ -37,9 +39,13 @@ namespace sb {
 namespace {
 
 constexpr uint32_t kLeafMax = 8;
-constexpr int32_t kMaxDepth = 40;
+constexpr int32_t kMaxDepth = 32;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// Dword-aligned vectors (node records are 8-byte aligned; global loads need
+// dword alignment only).
+typedef uint32_t u32x2a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -145,8 +151,7 @@ __device__ __forceinline__ typename DistOf<D>::type box_dist(const Tx<S> &q, con
 }
 
 struct TreeView {
-  const u32x2 *meta;
-  const void *box;
+  const void *nodes;
   const void *vals;
   const uint32_t *keys;
 };
@@ -154,56 +159,113 @@ struct TreeView {
 TreeView tree_view(const void *tree, size_t n, size_t t) {
   const TreeLayout l = tree_layout(n, t);
   const char *b = static_cast<const char *>(tree);
-  return TreeView{reinterpret_cast<const u32x2 *>(b + l.meta), b + l.box, b + l.vals,
-                  reinterpret_cast<const uint32_t *>(b + l.keys)};
+  return TreeView{b + l.nodes, b + l.vals, reinterpret_cast<const uint32_t *>(b + l.keys)};
+}
+
+// A node record: box [lo, hi] and link (see tree_layout).
+template <int S>
+struct Rec {
+  Tx<S> lo, hi;
+  u32x2 link;
+};
+
+template <int S>
+__device__ __forceinline__ const SB_GLOBAL unsigned char *rec_at(const void *nodes, uint32_t i) {
+  return glb(static_cast<const unsigned char *>(nodes)) + uint64_t(i) * tree_record_bytes(S);
+}
+
+template <int S>
+__device__ __forceinline__ Rec<S> load_rec(const void *nodes, uint32_t i) {
+  const SB_GLOBAL unsigned char *p = rec_at<S>(nodes, i);
+  Rec<S> r;
+  if constexpr (S == 4) {
+    const u32x4a4 v = *reinterpret_cast<const SB_GLOBAL u32x4a4 *>(p);
+    r.lo.w[0] = v.x, r.hi.w[0] = v.y, r.link = u32x2{v.z, v.w};
+  } else if constexpr (S == 8) {
+    const u32x4a4 v = *reinterpret_cast<const SB_GLOBAL u32x4a4 *>(p);
+    const u32x2a4 m = *reinterpret_cast<const SB_GLOBAL u32x2a4 *>(p + 16);
+    r.lo.w[0] = v.x, r.lo.w[1] = v.y, r.hi.w[0] = v.z, r.hi.w[1] = v.w, r.link = u32x2{m.x, m.y};
+  } else {
+    const u32x4a4 a = *reinterpret_cast<const SB_GLOBAL u32x4a4 *>(p);
+    const u32x4a4 b = *reinterpret_cast<const SB_GLOBAL u32x4a4 *>(p + 16);
+    const u32x2a4 m = *reinterpret_cast<const SB_GLOBAL u32x2a4 *>(p + 32);
+    r.lo.w[0] = a.x, r.lo.w[1] = a.y, r.lo.w[2] = a.z, r.lo.w[3] = a.w;
+    r.hi.w[0] = b.x, r.hi.w[1] = b.y, r.hi.w[2] = b.z, r.hi.w[3] = b.w;
+    r.link = u32x2{m.x, m.y};
+  }
+  return r;
+}
+
+template <int S>
+__device__ __forceinline__ void store_rec_box(void *nodes, uint32_t i, const Tx<S> &lo,
+                                              const Tx<S> &hi) {
+  SB_GLOBAL uint32_t *p = reinterpret_cast<SB_GLOBAL uint32_t *>(
+      const_cast<SB_GLOBAL unsigned char *>(rec_at<S>(nodes, i)));
+#pragma unroll
+  for (int k = 0; k < S / 4; ++k) p[k] = lo.w[k], p[S / 4 + k] = hi.w[k];
+}
+
+__device__ __forceinline__ void store_rec_link(void *nodes, uint32_t rec_bytes, uint32_t i,
+                                               u32x2 link) {
+  SB_GLOBAL uint32_t *p = reinterpret_cast<SB_GLOBAL uint32_t *>(
+      glb(static_cast<unsigned char *>(nodes)) + uint64_t(i) * rec_bytes + (rec_bytes - 8));
+  p[0] = link.x;
+  p[1] = link.y;
 }
 
 // The exact lookup of q: the source coordinate x | y << 16 of the texel
 // nearest to q under the weights, ties to the smallest raster index (the
-// coordinate word y << 16 | x orders like the raster index).  The stack
-// holds at most one deferred sibling per tree level of the current path,
-// and inner nodes lie above depth kMaxDepth - 1.
+// coordinate word y << 16 | x orders like the raster index).  An inner node
+// loads both children's records at once (boxes and links), so each level of
+// the descent costs one round trip; a deferred sibling is kept with its link
+// and its box distance.  The stack holds at most one deferred sibling per
+// tree level of the current path, and inner nodes lie above depth
+// kMaxDepth - 1.
+//
+// (best, best_key) may start at a real source texel's distance and
+// coordinate (a candidate the caller already measured): every subtree that
+// could hold a texel at that distance or nearer is still visited, so the
+// result is the same, found with fewer visits.
 template <int D, int S>
-__device__ uint32_t tree_search(const TreeView &tv, const Tx<S> &q, const uint32_t *wn) {
+__device__ uint32_t tree_search(const TreeView &tv, const Tx<S> &q, const uint32_t *wn,
+                                typename DistOf<D>::type best = ~typename DistOf<D>::type(0),
+                                uint32_t best_key = 0xFFFFFFFFu) {
   typedef typename DistOf<D>::type Dist;
-  Dist best = ~Dist(0);
-  uint32_t best_key = 0xFFFFFFFFu;
-  uint32_t st_node[kMaxDepth];
-  Dist st_bound[kMaxDepth];
+  // one 16-byte entry per deferred sibling (link, bound as two words): one
+  // scratch store per push and one load per pop
+  u32x4 stack[kMaxDepth];
   int32_t sp = 0;
-  uint32_t node = 0;
+  u32x2 link = load_rec<S>(tv.nodes, 0).link;
   Dist bound = 0;
   for (;;) {
     if (bound <= best) {
-      const u32x2 m = glb(tv.meta)[node];
-      if (m.y & kTreeLeaf) {
-        const uint32_t end = m.x + (m.y & ~kTreeLeaf);
-        for (uint32_t i = m.x; i < end; ++i) {
+      if (link.y & kTreeLeaf) {
+        const uint32_t end = link.x + (link.y & ~kTreeLeaf);
+        for (uint32_t i = link.x; i < end; ++i) {
           const Dist d = tx_dist<D, S>(q, load_tx<S>(tv.vals, i), wn);
           const uint32_t k = glb(tv.keys)[i];
           if (d < best || (d == best && k < best_key)) best = d, best_key = k;
         }
       } else {
-        const uint32_t c = m.x;
-        const Dist b0 = box_dist<D, S>(q, load_tx<S>(tv.box, 2 * c), load_tx<S>(tv.box, 2 * c + 1), wn);
-        const Dist b1 =
-            box_dist<D, S>(q, load_tx<S>(tv.box, 2 * c + 2), load_tx<S>(tv.box, 2 * c + 3), wn);
+        const Rec<S> r0 = load_rec<S>(tv.nodes, link.x);
+        const Rec<S> r1 = load_rec<S>(tv.nodes, link.x + 1);
+        const Dist b0 = box_dist<D, S>(q, r0.lo, r0.hi, wn);
+        const Dist b1 = box_dist<D, S>(q, r1.lo, r1.hi, wn);
         const bool first0 = b0 <= b1;
         const Dist bf = first0 ? b1 : b0;
         if (bf <= best) {
-          st_node[sp] = first0 ? c + 1 : c;
-          st_bound[sp] = bf;
-          ++sp;
+          const u32x2 fl = first0 ? r1.link : r0.link;
+          stack[sp++] = u32x4{fl.x, fl.y, uint32_t(bf), uint32_t(uint64_t(bf) >> 32)};
         }
-        node = first0 ? c : c + 1;
+        link = first0 ? r0.link : r1.link;
         bound = first0 ? b0 : b1;
         continue;
       }
     }
     if (sp == 0) break;
-    --sp;
-    node = st_node[sp];
-    bound = st_bound[sp];
+    const u32x4 e = stack[--sp];
+    link = u32x2{e.x, e.y};
+    bound = Dist(e.z) | Dist(uint64_t(e.w) << 32);
   }
   return best_key;
 }
@@ -217,8 +279,7 @@ struct BuildArgs {
   const uint32_t *keys_in;
   void *vals_out;  // the next level's texels (split nodes' children)
   uint32_t *keys_out;
-  u32x2 *meta;     // the tree's sections
-  void *box;
+  void *nodes;     // the tree's sections
   void *tvals;
   uint32_t *tkeys;
   uint32_t wn[2];  // build weights (split choice only)
@@ -272,10 +333,7 @@ __global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) 
     blo.w[wi] |= s_lo[k] << sh;
     bhi.w[wi] |= s_hi[k] << sh;
   }
-  if (tid == 0) {
-    store_tx<S>(a.box, 2 * node, blo);
-    store_tx<S>(a.box, 2 * node + 1, bhi);
-  }
+  if (tid == 0) store_rec_box<S>(a.nodes, node, blo, bhi);
   // the split element: widest by weight, else by raw range; none if every
   // channel is constant over the node
   int32_t ds = -1, dr = -1;
@@ -300,7 +358,7 @@ __global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) 
     if (tid == 0) {
       store_tx<S>(a.tvals, b, blo);
       glb(a.tkeys)[b] = s_key;
-      glb(a.meta)[node] = u32x2{b, 1u | kTreeLeaf};
+      store_rec_link(a.nodes, tree_record_bytes(S), node, u32x2{b, 1u | kTreeLeaf});
       glb(a.res)[blockIdx.x] = u32x2{0u, 0u};
     }
     return;
@@ -311,7 +369,7 @@ __global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) 
       glb(a.tkeys)[i] = glb(a.keys_in)[i];
     }
     if (tid == 0) {
-      glb(a.meta)[node] = u32x2{b, c | kTreeLeaf};
+      store_rec_link(a.nodes, tree_record_bytes(S), node, u32x2{b, c | kTreeLeaf});
       glb(a.res)[blockIdx.x] = u32x2{0u, 0u};
     }
     return;
@@ -377,7 +435,8 @@ __global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) 
 // the next level, ctr[1] = nodes so far.
 __global__ void __launch_bounds__(1024) k_tree_alloc(const u32x4 *list_in, const u32x2 *res,
                                                      uint32_t m, uint32_t nnodes, u32x4 *list_out,
-                                                     u32x2 *meta, uint32_t *ctr) {
+                                                     void *nodes, uint32_t rec_bytes,
+                                                     uint32_t *ctr) {
   __shared__ uint32_t s_wave[16];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   uint32_t run = 0;
@@ -398,7 +457,7 @@ __global__ void __launch_bounds__(1024) k_tree_alloc(const u32x4 *list_in, const
       const uint32_t r = run + woff + pre, child = nnodes + 2 * r;
       const u32x4 e = glb(list_in)[j];
       const uint32_t lc = glb(res)[j].y;
-      glb(meta)[e.z] = u32x2{child, 0u};
+      store_rec_link(nodes, rec_bytes, e.z, u32x2{child, 0u});
       glb(list_out)[2 * r] = u32x4{e.x, lc, child, 0u};
       glb(list_out)[2 * r + 1] = u32x4{e.x + lc, e.y - lc, child + 1, 0u};
     }
@@ -414,7 +473,7 @@ __global__ void __launch_bounds__(1024) k_tree_alloc(const u32x4 *list_in, const
 // ------------------------------------------------------------- frame passes
 
 __device__ inline TreeView frame_tree(const FrameArgs &a) {
-  return TreeView{static_cast<const u32x2 *>(a.t_meta), a.t_box, a.t_vals, a.t_keys};
+  return TreeView{a.t_nodes, a.t_vals, a.t_keys};
 }
 
 // Record idx of the padded seed table: the seed of its cell and the
@@ -448,7 +507,12 @@ constexpr uint32_t kAssignTW = 64, kAssignTH = 16;
 
 template <int D, int S>
 __global__ void __launch_bounds__(256) k_assign_n(FrameArgs a) {
+  typedef typename DistOf<D>::type Dist;
+  // fallback pixels: position, and the nearest candidate the level loop
+  // measured (its coordinate and distance), the search's starting bound
   __shared__ uint32_t s_list[kAssignTW * kAssignTH];
+  __shared__ uint32_t s_ckey[kAssignTW * kAssignTH];
+  __shared__ Dist s_cd[kAssignTW * kAssignTH];
   __shared__ uint32_t s_n;
   const uint32_t tid = threadIdx.x;
   const uint32_t tiles_x = (uint32_t(a.w) + kAssignTW - 1) / kAssignTW;
@@ -468,6 +532,8 @@ __global__ void __launch_bounds__(256) k_assign_n(FrameArgs a) {
     const Tx<S> gt = load_tx<S>(a.tgt_guide, pidx);
     const short2_t p4 = __builtin_bit_cast(short2_t, pack_xy(uint32_t(4 * x), uint32_t(4 * y)));
     bool done = false;
+    Dist cd = ~Dist(0);
+    uint32_t ckey = 0xFFFFFFFFu;
     for (int32_t i = 0; i < L && !done; ++i) {
       const int32_t ls = lv.log2_spacing[i], pc = lv.cells_x[i] + 2;
       const SB_GLOBAL u32x2 *top = seed_table(a) + lv.poffset[i] + (y >> ls) * pc + (x >> ls);
@@ -480,16 +546,22 @@ __global__ void __launch_bounds__(256) k_assign_n(FrameArgs a) {
       const int32_t vx = x + off_x(rec.y), vy = y + off_y(rec.y);
       if (uint32_t(vx) >= sw || uint32_t(vy) >= sh) continue;
       const uint32_t vidx = __umul24(uint32_t(vy), sw) + uint32_t(vx);
-      if (tx_dist<D, S>(gt, load_tx<S>(a.src_guide, vidx), a.wn) < a.threshold) {
+      const Dist e = tx_dist<D, S>(gt, load_tx<S>(a.src_guide, vidx), a.wn);
+      if (e < a.threshold) {
         glb(a.out_chunk)[pidx] = chunk_code(i, rec.x);
         glb(a.offsets)[pidx] = vote_distance(a, rec.y);
         if (a.out_nnf) glb(a.out_nnf)[pidx] = pack_xy(uint32_t(vx), uint32_t(vy));
         done = true;
       }
+      const uint32_t vkey = pack_xy(uint32_t(vx), uint32_t(vy));
+      if (e < cd || (e == cd && vkey < ckey)) cd = e, ckey = vkey;
     }
     if (!done) {
       glb(a.out_chunk)[pidx] = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
-      s_list[atomicAdd(&s_n, 1u)] = pack_xy(uint32_t(x), uint32_t(y));
+      const uint32_t slot = atomicAdd(&s_n, 1u);
+      s_list[slot] = pack_xy(uint32_t(x), uint32_t(y));
+      s_ckey[slot] = ckey;
+      s_cd[slot] = cd;
     }
   }
   __syncthreads();
@@ -498,7 +570,8 @@ __global__ void __launch_bounds__(256) k_assign_n(FrameArgs a) {
   for (uint32_t k = tid; k < nf; k += 256) {
     const uint32_t xy = s_list[k], x = xy & 0xFFFFu, y = xy >> 16;
     const uint32_t pidx = __umul24(y, uint32_t(a.w)) + x;
-    const uint32_t u = tree_search<D, S>(frame_tree(a), load_tx<S>(a.tgt_guide, pidx), a.wn);
+    const uint32_t u = tree_search<D, S>(frame_tree(a), load_tx<S>(a.tgt_guide, pidx), a.wn,
+                                         s_cd[k], s_ckey[k]);
     const uint32_t off = pack_off(int32_t(u & 0xFFFFu) - int32_t(x), int32_t(u >> 16) - int32_t(y));
     glb(a.offsets)[pidx] = vote_distance(a, off);
     if (a.out_nnf) glb(a.out_nnf)[pidx] = u;
@@ -635,8 +708,7 @@ int sb_tree_build(const void *guide, int32_t fmt, int32_t channels, int32_t sw, 
   char *tb = static_cast<char *>(tree);
   BuildArgs a;
   memset(&a, 0, sizeof a);
-  a.meta = reinterpret_cast<u32x2 *>(tb + l.meta);
-  a.box = tb + l.box;
+  a.nodes = tb + l.nodes;
   a.tvals = tb + l.vals;
   a.tkeys = reinterpret_cast<uint32_t *>(tb + l.keys);
   a.res = ws.res;
@@ -658,7 +730,7 @@ int sb_tree_build(const void *guide, int32_t fmt, int32_t channels, int32_t sw, 
       a.keys_out = ws.keys[cur ^ 1];
       k_tree_level<D, S><<<m, 256, 0, stream>>>(a, depth);
       k_tree_alloc<<<1, 1024, 0, stream>>>(ws.list[cur], ws.res, m, nnodes, ws.list[cur ^ 1],
-                                           a.meta, ws.ctr);
+                                           a.nodes, uint32_t(tree_record_bytes(S)), ws.ctr);
       uint32_t hc[2] = {0u, 0u};
       hipError_t ec = hipMemcpyAsync(hc, ws.ctr, sizeof hc, hipMemcpyDeviceToHost, stream);
       if (ec == hipSuccess) ec = hipStreamSynchronize(stream);
@@ -711,8 +783,7 @@ namespace sb {
 void fill_tree_args(const sb_style *style, FrameArgs *a) {
   const int32_t t = search_texel_bytes(style->fmt, style->channels);
   const TreeView tv = tree_view(style->tree, size_t(style->sw) * size_t(style->sh), size_t(t));
-  a->t_meta = tv.meta;
-  a->t_box = tv.box;
+  a->t_nodes = tv.nodes;
   a->t_vals = tv.vals;
   a->t_keys = tv.keys;
   a->texel = t;
