@@ -157,6 +157,59 @@ int main() {
   rq.params = p;
   cfg.workspace_bytes_per_slot = 16;  // a request that cannot fit a slot's workspace
   EXPECT(sb_serve_run(&cfg, &rq, 1, &res), SB_ENOMEM);
+  // guides of many channels: sizes, tree build and query, frames and serving
+  EXPECT(sb_texel_bytes(SB_GUIDE_U8XN, 5), 8);
+  EXPECT(sb_texel_bytes(SB_GUIDE_U16XN, 5), 16);
+  EXPECT(sb_texel_bytes(SB_GUIDE_U8X3, 3), 0);
+  EXPECT(sb_texel_bytes(SB_GUIDE_U8XN, 9), 0);
+  const size_t tb = sb_tree_bytes(SB_GUIDE_U16XN, 4, 64, 48);
+  const size_t twb = sb_tree_workspace_bytes(SB_GUIDE_U16XN, 4, 64, 48);
+  EXPECT(tb > 64u * 48u * 8u, 1);
+  EXPECT(twb > 64u * 48u * 8u, 1);
+  EXPECT(sb_tree_bytes(SB_GUIDE_U16XN, 4, 0, 48), 0);
+  const uint8_t w_bad[8] = {1, 2, 200, 4};
+  EXPECT(sb_tree_build(fake, SB_GUIDE_U16XN, 4, 64, 48, w_bad, fake, tb, fake, twb, nullptr),
+         SB_EINVAL);
+  EXPECT(sb_tree_build(fake, SB_GUIDE_U16XN, 4, 64, 48, nullptr, fake, tb - 1, fake, twb,
+                       nullptr),
+         SB_ENOMEM);
+  EXPECT(sb_tree_build(fake, SB_GUIDE_U16XN, 4, 64, 48, nullptr, fake, tb, fake, twb - 1,
+                       nullptr),
+         SB_ENOMEM);
+  EXPECT(sb_tree_build(fake, SB_GUIDE_U8X2, 2, 64, 48, nullptr, fake, tb, fake, twb, nullptr),
+         SB_EINVAL);
+  sb_style sst;
+  memset(&sst, 0, sizeof sst);
+  sst.rgba = reinterpret_cast<const uint32_t *>(fake);
+  sst.guide = fake;
+  sst.sw = 64;
+  sst.sh = 48;
+  sst.fmt = SB_GUIDE_U16XN;
+  sst.channels = 4;
+  sst.tree = fake;
+  uint32_t qout = 0;
+  EXPECT(sb_tree_query(&sst, fake, -1, &qout, nullptr), SB_EINVAL);
+  EXPECT(sb_tree_query(&sst, fake, 0, &qout, nullptr), SB_OK);
+  sb_style sst_bad = sst;
+  sst_bad.lut_bits = 8;
+  EXPECT(sb_stylize(&sst_bad, fake, 64, 64, nullptr, &p, rgb, chunk, nullptr, fake, 1 << 30,
+                    nullptr),
+         SB_EINVAL);
+  sst_bad = sst;
+  sst_bad.weights[1] = 128;
+  EXPECT(sb_stylize(&sst_bad, fake, 64, 64, nullptr, &p, rgb, chunk, nullptr, fake, 1 << 30,
+                    nullptr),
+         SB_EINVAL);
+  EXPECT(sb_stylize_seg(&sst, fake, reinterpret_cast<const uint8_t *>(fake), 64, 64, nullptr, &p, rgb,
+                        chunk, nullptr, fake, 1 << 30, nullptr, nullptr),
+         SB_EINVAL);
+  sb_style *owned = nullptr;
+  EXPECT(sb_style_create_n(nullptr, fake, 64, 48, SB_GUIDE_U8XN, 5, nullptr, nullptr, &owned),
+         SB_EINVAL);
+  EXPECT(owned == nullptr, 1);
+  cfg.workspace_bytes_per_slot = size_t(1) << 30;
+  rq.style = &sst;  // batches and serving hold table formats only
+  EXPECT(sb_serve_run(&cfg, &rq, 1, &res), SB_EINVAL);
   EXPECT(sb_frame_change(nullptr, nullptr, nullptr, nullptr, 16, nullptr, nullptr, 0, nullptr),
          SB_EINVAL);
   EXPECT(sb_jitter_fill(0, 8, 2, 8, 1, 0, nullptr, nullptr), SB_EINVAL);

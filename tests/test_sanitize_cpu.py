@@ -42,7 +42,7 @@ def test_oracle_under_asan_ubsan():
     assert "ERROR: AddressSanitizer" not in log and "runtime error" not in log, log
 
 
-HOST_SOURCES = ["capi", "batch", "serve", "noalloc", "style", "change", "jitter"]
+HOST_SOURCES = ["capi", "batch", "serve", "noalloc", "style", "change", "jitter", "search"]
 
 
 @pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)),
