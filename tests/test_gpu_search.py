@@ -218,3 +218,65 @@ def test_other_entry_points(sb):
         assert torch.equal(rgb2, e_rgb) and torch.equal(chunk2, e_chunk)
     finally:
         assert L.sb_style_destroy(sp) == sb.SB_OK
+
+
+def test_large_source_16bit(sb):
+    """A 2048 x 2048 source (4.2 M texels, four 16-bit channels: texture
+    coordinates and sphere normals): the tree holds every distinct texel;
+    lookups against the oracle's sweep."""
+    size = 2048
+    g = workloads.features_u16(workloads.identity_uv_guide_u16(size, size),
+                               workloads.sphere_guide_u8(size))
+    rgb = np.zeros((size, size, 3), np.uint8)
+    rng = np.random.default_rng(81)
+    q = np.concatenate([g.reshape(-1, 4)[rng.integers(0, size * size, 1500)],
+                        rng.integers(0, 65536, (300, 4)).astype(np.uint16)])
+    say("2048x2048 16-bit source, 1800 lookups")
+    st = sb.Style(rgb, g, channels=4)
+    got = _host(st.query(_dev(q)))
+    np.testing.assert_array_equal(got, oracle.nn_sweep_n(g, 4, q))
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (3, 7), (40, 30)])
+def test_degenerate_sources(sb, shape):
+    """Sources of one texel, and sources whose texels are all equal (one
+    collapsed leaf: the smallest raster index answers every query)."""
+    h, w = shape
+    rng = np.random.default_rng(h * 100 + w)
+    g = np.zeros((h, w, 8), np.uint8)
+    g[..., :5] = rng.integers(0, 256, 5)
+    g[..., 5:] = rng.integers(0, 256, (h, w, 3))  # ignored elements differ
+    rgb = rng.integers(0, 256, (h, w, 3)).astype(np.uint8)
+    q = rng.integers(0, 256, (500, 8)).astype(np.uint8)
+    say(f"degenerate source {w}x{h}")
+    st = sb.Style(rgb, g, channels=5)
+    got = _host(st.query(_dev(q)))
+    assert np.all(got == 0)
+    np.testing.assert_array_equal(got, oracle.nn_query_n(g, 5, q))
+
+
+def test_depth_limit(sb):
+    """A tight cluster of 200 texels with outliers at power-of-two distances
+    along every channel (16 bits): each split at the middle of a box peels
+    one outlier off, so the cluster's path reaches the depth limit and the
+    node there becomes a leaf of about 200 texels; lookups stay exact."""
+    rng = np.random.default_rng(91)
+    pts = [1000 + rng.integers(0, 4, 4) for _ in range(200)]
+    for c in range(4):
+        for k in list(range(2, 16)) + [-k for k in range(2, 10)]:
+            v = np.full(4, 1001)
+            v[c] = 1000 + (1 << k) if k > 0 else 1000 - (1 << -k)
+            pts.append(v)
+    pts = np.array(pts)[rng.permutation(len(pts))]  # 288 texels as 18 x 16
+    g = workloads.guide_n([pts[:, c].reshape(18, 16) for c in range(4)], 16)
+    rgb = np.zeros((18, 16, 3), np.uint8)
+    q = np.concatenate([pts[rng.integers(0, len(pts), 500)],
+                        1000 + rng.integers(-40, 80, (1500, 4)),
+                        rng.integers(0, 65536, (500, 4))]).astype(np.uint16)
+    q = workloads.guide_n([q[:, c][None] for c in range(4)], 16).reshape(len(q), -1)
+    say("depth-limit source")
+    st = sb.Style(rgb, g, channels=4, weights=[1, 2, 3, 4])
+    hdr = st.tree[:16].cpu().numpy().view(np.uint32)
+    assert hdr[0] > 2 * 31  # nodes: the outliers' chain reaches the depth limit
+    got = _host(st.query(_dev(q)))
+    np.testing.assert_array_equal(got, oracle.nn_query_n(g, 4, q, weights=[1, 2, 3, 4]))
