@@ -482,18 +482,27 @@ def search_leg(sb, torch, np, workloads, plain_ms, steps=50, cpu_frame=True):
         g = torch.from_numpy(guide_np.view(np.int16) if guide_np.dtype == np.uint16
                              else guide_np).cuda()
         h, w = guide_np.shape[:2]
-        rgb = torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")
-        chunk = torch.empty((h, w), dtype=torch.int32, device="cuda")
-        ws = torch.empty(sb.workspace_bytes(w, h, prm), dtype=torch.uint8, device="cuda")
-        plan = sb.FramePlan(style, g, None, prm, rgb, chunk, ws)
-        for _ in range(5):
-            plan.launch()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            plan.launch()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
+        bufs = [(torch.empty((h, w, 3), dtype=torch.uint8, device="cuda"),
+                 torch.empty((h, w), dtype=torch.int32, device="cuda"),
+                 torch.empty(sb.workspace_bytes(w, h, prm), dtype=torch.uint8, device="cuda"))
+                for _ in range(2)]
+        plans = [sb.FramePlan(style, g, None, prm, o_rgb, o_chunk, o_ws)
+                 for o_rgb, o_chunk, o_ws in bufs]
+        rgb, chunk, ws = bufs[0]
+        streams = [torch.cuda.current_stream().cuda_stream, torch.cuda.Stream().cuda_stream]
+
+        def timed(nstreams):
+            for k in range(5):
+                plans[k % 2].launch(streams[k % nstreams])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(steps):
+                plans[k % 2].launch(streams[k % nstreams])
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / steps
+
+        ms = timed(1)
+        ms2 = timed(2)
         ev = sb.TimingEvents()
         passes = []
         for _ in range(20):
@@ -507,6 +516,8 @@ def search_leg(sb, torch, np, workloads, plain_ms, steps=50, cpu_frame=True):
         nseeds = int(sum(-(-w // (p.finest << k)) * -(-h // (p.finest << k))
                          for k in range(p.levels)))
         return {"ms_per_frame": round(ms, 6), "mpixel_per_s": round(w * h / (ms * 1e-3) / 1e6, 2),
+                "two_streams": {"ms_per_frame": round(ms2, 6),
+                                "mpixel_per_s": round(w * h / (ms2 * 1e-3) / 1e6, 2)},
                 "pass_ms": {"seeds": round(float(med[0]), 6), "level_loop": round(float(med[1]), 6),
                             "vote": round(float(med[2]), 6)},
                 "fallback_fraction": round(nfb / (w * h), 4),
