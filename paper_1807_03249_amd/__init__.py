@@ -388,8 +388,13 @@ class Style:
         torch = _torch()
         if self.tree is None:
             raise ValueError("query needs a many-channel style")
+        if not isinstance(texels, torch.Tensor) and str(getattr(texels, "dtype", "")) == "uint16":
+            texels = texels.view("int16")  # same bits; not every torch build takes uint16
         q = _dev(torch, texels)
-        n = q.numel() * q.element_size() // int(lib().sb_texel_bytes(self.fmt, self.channels))
+        tb = int(lib().sb_texel_bytes(self.fmt, self.channels))
+        if (q.numel() * q.element_size()) % tb != 0:
+            raise ValueError(f"query texels must be whole {tb}-byte texels")
+        n = q.numel() * q.element_size() // tb
         out = torch.empty(n, dtype=torch.int32, device="cuda")
         _check(lib().sb_tree_query(ctypes.byref(self.c), q.data_ptr(), n, out.data_ptr(),
                                    _stream(torch)), "sb_tree_query")
