@@ -220,6 +220,28 @@ def test_other_entry_points(sb):
         assert L.sb_style_destroy(sp) == sb.SB_OK
 
 
+def test_hand_case_weighted_tie(sb):
+    """The hand-worked lookup of tests/golden through the device search."""
+    from tests.test_oracle_search import hand_case
+
+    case, src, q, want = hand_case()
+    rgb = np.zeros((case["sh"], case["sw"], 3), np.uint8)
+    st = sb.Style(rgb, src, channels=case["channels"], weights=case["weights"])
+    np.testing.assert_array_equal(_host(st.query(_dev(q))), want)
+
+
+def test_all_zero_weights_mean_unit(sb):
+    """All-zero weights select unit weights in the library as in the oracle."""
+    rng = np.random.default_rng(23)
+    g = _random_source(rng, 16, 3, 31, 17, 9)
+    rgb = np.zeros((17, 31, 3), np.uint8)
+    q = rng.integers(0, 65536, (800, 4)).astype(np.uint16)
+    a = _host(sb.Style(rgb, g, channels=3, weights=[0, 0, 0]).query(_dev(q)))
+    b = _host(sb.Style(rgb, g, channels=3).query(_dev(q)))
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, oracle.nn_query_n(g, 3, q))
+
+
 def test_large_source_16bit(sb):
     """A 2048 x 2048 source (4.2 M texels, four 16-bit channels: texture
     coordinates and sphere normals): the tree holds every distinct texel;

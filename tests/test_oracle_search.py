@@ -9,11 +9,16 @@ permutations; the channel-0 sweep against brute force; the level loop
 against the pinned two- and three-channel paths, texture mapping at t = 0, a
 translation whose NNF is known in closed form, and the level loop's
 invariants."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import workloads
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")))
 
 
 def _pack(chans, depth):
@@ -23,6 +28,25 @@ def _pack(chans, depth):
 def _coords(idx, sw):
     idx = np.asarray(idx, np.int64)
     return ((idx % sw) | ((idx // sw) << 16)).astype(np.uint32)
+
+
+def hand_case():
+    case = GOLD["search_weighted_tie"]
+    src = np.zeros((case["sh"], case["sw"], 8), np.uint8)
+    src.reshape(-1, 8)[:, :case["channels"]] = case["src_texels"]
+    q = np.zeros((len(case["queries"]), 8), np.uint8)
+    q[:, :case["channels"]] = case["queries"]
+    want = np.array([x | (y << 16) for x, y in case["expect_xy"]], np.uint32)
+    return case, src, q, want
+
+
+def test_hand_case_weighted_tie():
+    """A hand-worked lookup (tests/golden): weights, an ignored channel, and a
+    tie won by the smaller raster index although the other texel lies nearer
+    along channel 0."""
+    case, src, q, want = hand_case()
+    for fn in (oracle.nn_query_n, oracle.nn_sweep_n):
+        np.testing.assert_array_equal(fn(src, case["channels"], q, weights=case["weights"]), want)
 
 
 @pytest.mark.parametrize("depth,channels,want", [
@@ -109,6 +133,18 @@ def test_sweep_equals_brute_force(depth, channels):
     for weights in (None, w):
         np.testing.assert_array_equal(oracle.nn_sweep_n(src, channels, q, weights=weights),
                                       oracle.nn_query_n(src, channels, q, weights=weights))
+
+
+@pytest.mark.parametrize("depth", [8, 16])
+def test_all_zero_weights_mean_unit(depth):
+    """Weights that are all zero select unit weights (they would otherwise
+    make every texel equally near, so the lookup would always be texel 0)."""
+    rng = np.random.default_rng(17 + depth)
+    src, q, _, _ = _random_guides(rng, depth, 4, 21, 12, 500, 9)
+    unit = oracle.nn_query_n(src, 4, q)
+    np.testing.assert_array_equal(oracle.nn_query_n(src, 4, q, weights=[0, 0, 0, 0]), unit)
+    np.testing.assert_array_equal(oracle.nn_query_n(src, 4, q, weights=[1, 1, 1, 1]), unit)
+    assert np.unique(unit).size > 10
 
 
 @pytest.mark.parametrize("depth", [8, 16])
