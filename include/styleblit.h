@@ -242,7 +242,8 @@ int sb_style_destroy(sb_style *style);
  * seed's lookup; the level loop then runs as for the table formats, and the
  * pixels no level accepts search their own lookup in the same pass
  * (gathered per tile so the searches run in full waves); the vote is
- * unchanged.  Not available with labels, in batches or in sb_serve_run. */
+ * unchanged.  Not available with labels or in sb_batch_run; sb_serve_run
+ * runs each such request alone through the per-frame kernels. */
 
 /* Bytes per texel of a `channels`-channel guide of fmt SB_GUIDE_U8XN or
  * SB_GUIDE_U16XN: the smallest of 4, 8, 16 that holds the channels; 0 if
@@ -557,8 +558,9 @@ typedef struct {
  * frames of one session completing in order,
  * continuous batching over `slots` streams (a free slot takes every admitted
  * request up to max_batch and runs them as one batch-plan replay, or, for a
- * single request, as one sb_stylize_ex on the slot's stream), completion by
- * event polling.  Every result is
+ * single request, as one sb_stylize_ex on the slot's stream; a request of a
+ * many-channel style always runs alone that way), completion by event
+ * polling.  Every result is
  * the one sb_stylize gives for that request alone.  Returns after the last
  * request finished and the slots' streams drained. */
 int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,

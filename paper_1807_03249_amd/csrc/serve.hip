@@ -137,7 +137,6 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
     if (!fill_frame(r.style, r.tgt_guide, r.w, r.h, r.jitter, &r.params, probe_rgb, probe_chunk,
                     nullptr, &a, r.tgt_labels))
       return SB_EINVAL;
-    if (fmt_search(r.style->fmt)) return SB_EINVAL;  // batches hold table formats only
     if (i > 0 && r.arrival_s < reqs[i - 1].arrival_s) return SB_EINVAL;  // sorted arrivals
     if ((r.out_rgb == nullptr) != (r.out_chunk == nullptr)) return SB_EINVAL;  // both or neither
     // a batch of max_batch requests of this size must fit one slot's workspace
@@ -282,9 +281,14 @@ int sb_serve_run(const sb_serve_config *cfg, const sb_request *reqs, int32_t n,
         if (S.busy) continue;
         std::vector<sb_frame> bf;
         while (!admitted.empty() && int32_t(S.reqs.size()) < maxb) {
+          // a request of a search format (many-channel guide) runs through
+          // the per-frame kernels, in a batch of its own, in arrival order
+          const bool alone = fmt_search(fr[size_t(admitted.front())].style->fmt);
+          if (alone && !S.reqs.empty()) break;
           S.reqs.push_back(admitted.front());
           bf.push_back(fr[size_t(admitted.front())]);
           admitted.pop_front();
+          if (alone) break;
         }
         // sessions whose previous frame still runs on another slot: wait
         // for that slot's batch (each slot once)

@@ -207,9 +207,6 @@ int main() {
   EXPECT(sb_style_create_n(nullptr, fake, 64, 48, SB_GUIDE_U8XN, 5, nullptr, nullptr, &owned),
          SB_EINVAL);
   EXPECT(owned == nullptr, 1);
-  cfg.workspace_bytes_per_slot = size_t(1) << 30;
-  rq.style = &sst;  // batches and serving hold table formats only
-  EXPECT(sb_serve_run(&cfg, &rq, 1, &res), SB_EINVAL);
   EXPECT(sb_frame_change(nullptr, nullptr, nullptr, nullptr, 16, nullptr, nullptr, 0, nullptr),
          SB_EINVAL);
   EXPECT(sb_jitter_fill(0, 8, 2, 8, 1, 0, nullptr, nullptr), SB_EINVAL);

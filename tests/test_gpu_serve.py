@@ -199,3 +199,41 @@ def test_served_results_match_oracle(env):
         np.testing.assert_array_equal(r.out_chunk.cpu().numpy().view(np.uint32), e_chunk,
                                       err_msg=f"request {i} chunk")
         np.testing.assert_array_equal(r.out_rgb.cpu().numpy(), e_rgb, err_msg=f"request {i} rgb")
+
+
+def test_many_channel_requests_run_alone(env):
+    """Requests of a many-channel style (exact search) mixed into a burst of
+    table-format requests: each runs in a batch of its own, and every result
+    equals the request stylised alone."""
+    import torch
+
+    sb, sv, trace, styles = env
+    reqs = make_requests(env, explicit_outputs=True, n=24, burst=True)
+    st_np = workloads.config(7, w=64, h=64, size=64)[0][0]
+    sst = sb.Style(st_np.rgb, st_np.guide, channels=5)
+    rng = np.random.default_rng(61)
+    p = workloads.FEATURE_PARAMS
+    prm = sb.params(p.levels, p.finest, p.threshold, p.radius, seed=5)
+    many = []
+    for i in range(8):
+        w, h = int(rng.integers(100, 400)), int(rng.integers(80, 300))
+        g = torch.from_numpy(workloads.features_target(w, h, 640 + i, 8, st_np.rgb)).cuda()
+        many.append(sv.Request(0.0, sst, g, None, prm,
+                               torch.empty((h, w, 3), dtype=torch.uint8, device="cuda"),
+                               torch.empty((h, w), dtype=torch.int32, device="cuda")))
+    mixed = []
+    for i, r in enumerate(reqs):
+        mixed.append(r)
+        if i % 3 == 0 and many:
+            mixed.append(many.pop())
+    say(f"serve {len(mixed)} requests, some of a many-channel style")
+    out = sv.run(mixed, slots=3, max_batch=8, budget_bytes=1 << 30)
+    assert np.all(out["status"] == sb.SB_OK)
+    assert out["batch_size"].max() > 1
+    for i, r in enumerate(mixed):
+        if r.style is sst:
+            assert out["batch_size"][i] == 1
+        rgb, chunk = sb.stylize(r.style, r.guide, r.jitter, r.params)
+        torch.cuda.synchronize()
+        assert torch.equal(r.out_rgb, rgb), f"request {i}"
+        assert torch.equal(r.out_chunk, chunk), f"request {i}"
