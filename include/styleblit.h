@@ -242,8 +242,9 @@ int sb_style_destroy(sb_style *style);
  * seed's lookup; the level loop then runs as for the table formats, and the
  * pixels no level accepts search their own lookup in the same pass
  * (gathered per tile so the searches run in full waves); the vote is
- * unchanged.  Not available with labels or in sb_batch_run; sb_serve_run
- * runs each such request alone through the per-frame kernels. */
+ * unchanged.  Not available with labels.  In a batch (sb_batch_run) such
+ * frames run through the per-frame kernels after the batch kernels, on the
+ * same stream; sb_serve_run runs each such request alone on a slot. */
 
 /* Bytes per texel of a `channels`-channel guide of fmt SB_GUIDE_U8XN or
  * SB_GUIDE_U16XN: the smallest of 4, 8, 16 that holds the channels; 0 if
@@ -484,7 +485,8 @@ size_t sb_batch_workspace_bytes(const sb_frame *frames, int32_t n);
 int sb_batch_create(void *desc_dev, void *desc_host, int32_t use_graph, const sb_tune *tune,
                     int32_t blocks_per_cu, hipStream_t stream, sb_batch **out);
 /* Stylise n frames (1..sb_batch_max_frames()) with one graph launch on
- * `stream`; the results equal n separate sb_stylize calls bit for bit.
+ * `stream` (frames of many-channel styles follow it through the per-frame
+ * kernels); the results equal n separate sb_stylize calls bit for bit.
  * Validates every frame first (SB_EINVAL / SB_ENOMEM and nothing enqueued
  * on a bad argument).  Blocks only while the run two calls back still reads
  * the descriptor half this run reuses.  workspace [device] of at least

@@ -114,22 +114,26 @@ int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace
   const size_t need = sb_batch_workspace_bytes(frames, n);
   if (need == 0) return SB_EINVAL;
   if (workspace_bytes < need) return SB_ENOMEM;
-  // validate every frame before touching the descriptor buffer
-  static thread_local FrameArgs args[kMaxBatchFrames];
+  // validate every frame before touching the descriptor buffer; frames of
+  // the table formats go to the batch kernels (args[0 .. nt)), frames of
+  // the search formats (many-channel guides) to the per-frame kernels after
+  // them on the same stream (search[0 .. ns)), each in its own workspace
+  static thread_local FrameArgs args[kMaxBatchFrames], search[kMaxBatchFrames];
   char *ws = static_cast<char *>(workspace);
+  int32_t nt = 0, ns = 0;
   for (int32_t f = 0; f < n; ++f) {
     const sb_frame &fr = frames[f];
+    const bool srch = fr.style && fmt_search(fr.style->fmt);
+    FrameArgs &a = srch ? search[ns++] : args[nt++];
     if (!fill_frame(fr.style, fr.tgt_guide, fr.w, fr.h, fr.jitter, &fr.params, fr.out_rgb,
-                    fr.out_chunk, fr.out_nnf, &args[f], fr.tgt_labels))
+                    fr.out_chunk, fr.out_nnf, &a, fr.tgt_labels))
       return SB_EINVAL;
-    // the batch kernels cover the table formats only
-    if (fmt_search(fr.style->fmt)) return SB_EINVAL;
     // graphs: the batch's seed pass is one persistent launch over every
     // frame, so each record is built once there rather than per block;
     // direct launches keep single frames' choice (records made in the level
     // loop for 8-bit styles), which saves a pass and its wait
-    if (b->use_graph) args[f].own_seeds = 0;
-    carve_workspace(&args[f], ws);
+    if (b->use_graph && !srch) a.own_seeds = 0;
+    carve_workspace(&a, ws);
     ws += align256(sb_workspace_bytes(fr.w, fr.h, &fr.params));
   }
   const int k = b->next;
@@ -143,30 +147,32 @@ int sb_batch_run(sb_batch *b, const sb_frame *frames, int32_t n, void *workspace
   unsigned char *hd = b->desc_host[k];
   BatchHeader hdr;
   memset(&hdr, 0, sizeof hdr);
-  hdr.nframes = uint32_t(n);
+  hdr.nframes = uint32_t(nt);
   memcpy(hd, &hdr, sizeof hdr);
   uint32_t *pre[kBatchKinds];
   for (int kind = 0; kind < kBatchKinds; ++kind) {
     pre[kind] = reinterpret_cast<uint32_t *>(hd + batch_prefix_offset(kind));
     pre[kind][0] = 0;
   }
-  for (int32_t f = 0; f < n; ++f) {
+  for (int32_t f = 0; f < nt; ++f) {
     uint32_t c[kBatchKinds];
     tile_counts(args[f], b->tune, c);
     for (int kind = 0; kind < kBatchKinds; ++kind) pre[kind][f + 1] = pre[kind][f] + c[kind];
   }
-  memcpy(hd + batch_frames_offset(), args, size_t(n) * sizeof(FrameArgs));
-  hipError_t e;
-  if (b->use_graph) {
+  memcpy(hd + batch_frames_offset(), args, size_t(nt) * sizeof(FrameArgs));
+  hipError_t e = hipSuccess;
+  if (nt > 0 && b->use_graph) {
     e = hipGraphLaunch(b->exec[k], stream);
-  } else {
+  } else if (nt > 0) {
     // direct launches know the batch's shape: exact grids, one tile per
     // workgroup, so kernels on other streams interleave with them
     e = hipMemcpyAsync(b->desc_dev[k], hd, batch_desc_bytes(), hipMemcpyHostToDevice, stream);
     uint32_t totals[kBatchKinds];
-    for (int kind = 0; kind < kBatchKinds; ++kind) totals[kind] = pre[kind][n];
+    for (int kind = 0; kind < kBatchKinds; ++kind) totals[kind] = pre[kind][nt];
     if (e == hipSuccess) e = launch_batch_exact(b->desc_dev[k], totals, b->tune, stream);
   }
+  for (int32_t f = 0; f < ns && e == hipSuccess; ++f)
+    e = launch_stylize(search[f], search[f].fmt, b->tune, nullptr, stream);
   if (e == hipSuccess) e = hipEventRecord(b->done[k], stream);
   if (e != hipSuccess) {
     set_hip_error(e, "sb_batch_run");

@@ -170,9 +170,9 @@ def test_full_size_frame(sb, depth):
 
 
 def test_other_entry_points(sb):
-    """A search-format style through sb_stylize_noalloc, sb_stylize_frames
-    and a library-owned style (sb_style_create_n) gives the sb_stylize
-    frame; batches and serving refuse it."""
+    """A search-format style through sb_stylize_noalloc, sb_stylize_frames,
+    batches (mixed with table-format frames, graphs and direct launches) and
+    a library-owned style (sb_style_create_n) gives the sb_stylize frame."""
     import torch
 
     styles, frames = workloads.config(7, w=200, h=150, size=64)
@@ -194,12 +194,35 @@ def test_other_entry_points(sb):
     torch.cuda.synchronize()
     for j in jobs:
         assert torch.equal(j.out_rgb, e_rgb) and torch.equal(j.out_chunk, e_chunk)
-    with pytest.raises(sb.StyleBlitError):
-        b = sb.Batch(use_graph=False)
+    for use_graph in (False, True):
+        say(f"batch of table and many-channel frames, graph={use_graph}")
+        st2_np, fr2 = workloads.config(1)[0][0], workloads.config(1)[1][0]
+        st2 = sb.Style(st2_np.rgb, st2_np.guide, st2_np.lut_bits)
+        p2 = fr2.params
+        prm2 = sb.params(p2.levels, p2.finest, p2.threshold, p2.radius, seed=fr2.seed)
+        g2 = _dev(fr2.guide)
+        e2_rgb, e2_chunk = sb.stylize(st2, g2, None, prm2)
+        mix = [sb.FrameJob(st, g, None, prm), sb.FrameJob(st2, g2, None, prm2),
+               sb.FrameJob(st, g, None, prm), sb.FrameJob(st2, g2, None, prm2)]
+        b = sb.Batch(use_graph=use_graph)
         try:
-            b.run(jobs)
+            for _ in range(2):  # both descriptor halves
+                b.run(mix)
         finally:
             b.close()
+        torch.cuda.synchronize()
+        for j in mix:
+            want = (e_rgb, e_chunk) if j.style is st else (e2_rgb, e2_chunk)
+            assert torch.equal(j.out_rgb, want[0]) and torch.equal(j.out_chunk, want[1])
+        b = sb.Batch(use_graph=use_graph)
+        try:
+            only = [sb.FrameJob(st, g, None, prm) for _ in range(3)]
+            b.run(only)  # no table-format frame: no batch kernels at all
+        finally:
+            b.close()
+        torch.cuda.synchronize()
+        for j in only:
+            assert torch.equal(j.out_rgb, e_rgb) and torch.equal(j.out_chunk, e_chunk)
     say("library-owned search-format style")
     L = sb.lib()
     rgb_d, guide_d = _dev(st_np.rgb), _dev(st_np.guide)
