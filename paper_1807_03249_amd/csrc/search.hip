@@ -10,8 +10,9 @@
 //                depth limit, or texels equal in every channel -- then the
 //                one of smallest raster index stands for all) or splits the
 //                widest element (by weight, then by raw range) at the middle
-//                of the box, both sides non-empty, with a stable partition
-//                into the other texel buffer.  k_tree_alloc numbers the next
+//                of the box, both sides non-empty, partitioning in one pass
+//                into the other texel buffer (left texels from the front,
+//                right ones from the back).  k_tree_alloc numbers the next
 //                level's nodes in order with a block scan, so the tree is the
 //                same on every run.
 //   search       depth first, nearer child first; a subtree is skipped only
@@ -297,28 +298,36 @@ __global__ void __launch_bounds__(256) k_tree_init(const void *guide, uint32_t n
   if (i == 0) glb(list)[0] = u32x4{0u, n, 0u, 0u};
 }
 
-// One node per workgroup (256 threads).
-template <int D, int S>
-__global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) {
+// One node per workgroup of NT threads (1024 while the level's nodes are
+// large, else 256).
+template <int D, int S, int NT>
+__global__ void __launch_bounds__(NT) k_tree_level(BuildArgs a, int32_t depth) {
   constexpr int E = kElems<D, S>;
-  __shared__ uint32_t s_lo[8], s_hi[8], s_cnt, s_key, s_wave[4];
+  constexpr uint32_t NW = NT / 64;
+  __shared__ uint32_t s_lo[8], s_hi[8], s_key, s_wave[NW];
   const u32x4 ent = glb(a.list_in)[blockIdx.x];
   const uint32_t b = ent.x, c = ent.y, node = ent.z, tid = threadIdx.x;
   if (tid < 8) s_lo[tid] = 0xFFFFFFFFu, s_hi[tid] = 0u;
-  if (tid == 0) s_cnt = 0u, s_key = 0xFFFFFFFFu;
+  if (tid == 0) s_key = 0xFFFFFFFFu;
   __syncthreads();
-  // the node's box
+  // the node's box; four texels per thread in flight
   uint32_t lo[E], hi[E];
 #pragma unroll
   for (int k = 0; k < E; ++k) lo[k] = 0xFFFFFFFFu, hi[k] = 0u;
-  for (uint32_t i = b + tid; i < b + c; i += 256) {
-    const Tx<S> t = load_tx<S>(a.vals_in, i);
+  auto widen = [&](const Tx<S> &t) {
     for_elems<0, E>([&](auto k) {
       constexpr int K = decltype(k)::value;
       lo[K] = min(lo[K], elem<D, S, K>(t));
       hi[K] = max(hi[K], elem<D, S, K>(t));
     });
+  };
+  uint32_t i = b + tid;
+  for (; i + 3 * NT < b + c; i += 4 * NT) {
+    const Tx<S> t0 = load_tx<S>(a.vals_in, i), t1 = load_tx<S>(a.vals_in, i + NT);
+    const Tx<S> t2 = load_tx<S>(a.vals_in, i + 2 * NT), t3 = load_tx<S>(a.vals_in, i + 3 * NT);
+    widen(t0), widen(t1), widen(t2), widen(t3);
   }
+  for (; i < b + c; i += NT) widen(load_tx<S>(a.vals_in, i));
   if (tid < c) {
 #pragma unroll
     for (int k = 0; k < E; ++k) atomicMin(&s_lo[k], lo[k]), atomicMax(&s_hi[k], hi[k]);
@@ -352,7 +361,7 @@ __global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) 
     // texels equal in every channel: every query sees them at one distance,
     // so the one of smallest raster index stands for all
     uint32_t mk = 0xFFFFFFFFu;
-    for (uint32_t i = b + tid; i < b + c; i += 256) mk = min(mk, glb(a.keys_in)[i]);
+    for (uint32_t i = b + tid; i < b + c; i += NT) mk = min(mk, glb(a.keys_in)[i]);
     if (tid < c) atomicMin(&s_key, mk);
     __syncthreads();
     if (tid == 0) {
@@ -364,7 +373,7 @@ __global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) 
     return;
   }
   if (c <= kLeafMax || depth >= kMaxDepth - 1) {
-    for (uint32_t i = b + tid; i < b + c; i += 256) {
+    for (uint32_t i = b + tid; i < b + c; i += NT) {
       store_tx<S>(a.tvals, i, load_tx<S>(a.vals_in, i));
       glb(a.tkeys)[i] = glb(a.keys_in)[i];
     }
@@ -375,26 +384,14 @@ __global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) 
     return;
   }
   // split at s = lo + (hi - lo + 1) / 2: lo < s <= hi, so both sides hold
-  // texels (the box is tight)
+  // texels (the box is tight).  One pass, NT texels per round: left texels
+  // fill [b, b + left) from the front, right ones [b + left, b + c) from the
+  // back (the order inside a node does not matter: ties are decided by the
+  // stored coordinate), so the left count is known at the end.
   const uint32_t s = s_lo[ds] + (s_hi[ds] - s_lo[ds] + 1) / 2;
-  auto side_left = [&](const Tx<S> &t) {
-    uint32_t v = 0;
-    for_elems<0, E>([&](auto k) {
-      constexpr int K = decltype(k)::value;
-      if (K == ds) v = elem<D, S, K>(t);
-    });
-    return v < s;
-  };
-  uint32_t nl = 0;
-  for (uint32_t i = b + tid; i < b + c; i += 256) nl += side_left(load_tx<S>(a.vals_in, i)) ? 1u : 0u;
-  if (tid < c) atomicAdd(&s_cnt, nl);
-  __syncthreads();
-  const uint32_t lc = s_cnt;
-  // stable partition, 256 texels per round: left texels to [b, b + lc),
-  // right ones to [b + lc, b + c), each side in its input order
   const uint32_t lane = tid & 63u, wave = tid >> 6;
   uint32_t lbase = 0, rbase = 0;
-  for (uint32_t base = 0; base < c; base += 256) {
+  for (uint32_t base = 0; base < c; base += NT) {
     const uint32_t i = b + base + tid;
     const bool valid = base + tid < c;
     Tx<S> t;
@@ -403,7 +400,12 @@ __global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) 
     if (valid) {
       t = load_tx<S>(a.vals_in, i);
       key = glb(a.keys_in)[i];
-      left = side_left(t);
+      uint32_t v = 0;
+      for_elems<0, E>([&](auto k) {
+        constexpr int K = decltype(k)::value;
+        if (K == ds) v = elem<D, S, K>(t);
+      });
+      left = v < s;
     }
     const uint64_t bal = __ballot(left);
     const uint32_t pre =
@@ -412,21 +414,21 @@ __global__ void __launch_bounds__(256) k_tree_level(BuildArgs a, int32_t depth) 
     __syncthreads();
     uint32_t woff = 0, tot = 0;
 #pragma unroll
-    for (uint32_t w = 0; w < 4; ++w) {
+    for (uint32_t w = 0; w < NW; ++w) {
       woff += w < wave ? s_wave[w] : 0u;
       tot += s_wave[w];
     }
     if (valid) {
       const uint32_t pl = woff + pre;  // left texels before this one in the round
-      const uint32_t dst = left ? b + lbase + pl : b + lc + rbase + (tid - pl);
+      const uint32_t dst = left ? b + lbase + pl : b + c - 1u - (rbase + (tid - pl));
       store_tx<S>(a.vals_out, dst, t);
       glb(a.keys_out)[dst] = key;
     }
     lbase += tot;
-    rbase += min(256u, c - base) - tot;
+    rbase += min(NT, c - base) - tot;
     __syncthreads();
   }
-  if (tid == 0) glb(a.res)[blockIdx.x] = u32x2{1u, lc};
+  if (tid == 0) glb(a.res)[blockIdx.x] = u32x2{1u, lbase};
 }
 
 // Numbers the children of this level's split nodes in list order (one
@@ -728,7 +730,11 @@ int sb_tree_build(const void *guide, int32_t fmt, int32_t channels, int32_t sw, 
       a.keys_in = ws.keys[cur];
       a.vals_out = ws.vals[cur ^ 1];
       a.keys_out = ws.keys[cur ^ 1];
-      k_tree_level<D, S><<<m, 256, 0, stream>>>(a, depth);
+      // large nodes (the top levels) take 1024 threads each
+      if (uint64_t(m) * 16384u <= uint64_t(n))
+        k_tree_level<D, S, 1024><<<m, 1024, 0, stream>>>(a, depth);
+      else
+        k_tree_level<D, S, 256><<<m, 256, 0, stream>>>(a, depth);
       k_tree_alloc<<<1, 1024, 0, stream>>>(ws.list[cur], ws.res, m, nnodes, ws.list[cur ^ 1],
                                            a.nodes, uint32_t(tree_record_bytes(S)), ws.ctr);
       uint32_t hc[2] = {0u, 0u};
