@@ -60,6 +60,7 @@ __host__ __device__ constexpr int32_t search_texel_bytes(int32_t fmt, int32_t ch
 // coordinates (x | y << 16).  A tree has at most 2n - 1 nodes.
 constexpr uint32_t kTreeLeaf = 0x80000000u;
 __host__ __device__ constexpr size_t tree_record_bytes(size_t t) { return 2 * t + 8; }
+constexpr size_t kLeafGroup = 4;
 struct TreeLayout {
   size_t nodes, vals, keys, total;
 };
@@ -68,8 +69,10 @@ inline TreeLayout tree_layout(size_t n, size_t t) {
   TreeLayout l;
   l.nodes = 256;
   l.vals = l.nodes + al(2 * n * tree_record_bytes(t));
-  l.keys = l.vals + al(n * t);
-  l.total = l.keys + al(n * 4);
+  // room for kLeafGroup - 1 entries past the last texel and key: a search
+  // reads a leaf's texels and keys in groups of kLeafGroup
+  l.keys = l.vals + al((n + kLeafGroup) * t);
+  l.total = l.keys + al((n + kLeafGroup) * 4);
   return l;
 }
 

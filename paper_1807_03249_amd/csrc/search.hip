@@ -214,6 +214,25 @@ __device__ __forceinline__ void store_rec_link(void *nodes, uint32_t rec_bytes, 
   p[1] = link.y;
 }
 
+// Texels i .. i + kLeafGroup - 1 of the tree's leaves and their keys.
+template <int S>
+__device__ __forceinline__ void load_group(const TreeView &tv, uint32_t i, Tx<S> *t,
+                                           uint32_t *k) {
+  static_assert(kLeafGroup == 4, "groups of four texels");
+  const SB_GLOBAL u32x4a4 *v = reinterpret_cast<const SB_GLOBAL u32x4a4 *>(
+      glb(static_cast<const unsigned char *>(tv.vals)) + uint64_t(i) * S);
+  constexpr int W = S / 4;  // words per texel
+  u32x4 w[W];
+#pragma unroll
+  for (int n = 0; n < W; ++n) w[n] = v[n];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int c = 0; c < W; ++c) t[m].w[c] = w[(m * W + c) / 4][(m * W + c) % 4];
+  const u32x4 kk = *reinterpret_cast<const SB_GLOBAL u32x4a4 *>(glb(tv.keys) + i);
+  k[0] = kk.x, k[1] = kk.y, k[2] = kk.z, k[3] = kk.w;
+}
+
 // The exact lookup of q: the source coordinate x | y << 16 of the texel
 // nearest to q under the weights, ties to the smallest raster index (the
 // coordinate word y << 16 | x orders like the raster index).  An inner node
@@ -233,19 +252,31 @@ __device__ uint32_t tree_search(const TreeView &tv, const Tx<S> &q, const uint32
                                 uint32_t best_key = 0xFFFFFFFFu) {
   typedef typename DistOf<D>::type Dist;
   // one 16-byte entry per deferred sibling (link, bound as two words): one
-  // scratch store per push and one load per pop
+  // scratch store per push and one load per pop, the load issued with a
+  // leaf's texels when a leaf comes before the pop
   u32x4 stack[kMaxDepth];
   int32_t sp = 0;
   u32x2 link = load_rec<S>(tv.nodes, 0).link;
   Dist bound = 0;
   for (;;) {
+    u32x4 nxt = {0u, 0u, 0u, 0u};
     if (bound <= best) {
       if (link.y & kTreeLeaf) {
-        const uint32_t end = link.x + (link.y & ~kTreeLeaf);
-        for (uint32_t i = link.x; i < end; ++i) {
-          const Dist d = tx_dist<D, S>(q, load_tx<S>(tv.vals, i), wn);
-          const uint32_t k = glb(tv.keys)[i];
-          if (d < best || (d == best && k < best_key)) best = d, best_key = k;
+        // the entry popped after this leaf, loaded with the leaf's texels
+        if (sp > 0) nxt = stack[sp - 1];
+        // the leaf's texels and keys in groups of kLeafGroup, each group's
+        // loads issued together (the tree has room past its last entries)
+        const uint32_t cnt = link.y & ~kTreeLeaf;
+        for (uint32_t j = 0; j < cnt; j += kLeafGroup) {
+          Tx<S> t[kLeafGroup];
+          uint32_t k[kLeafGroup];
+          load_group<S>(tv, link.x + j, t, k);
+#pragma unroll
+          for (uint32_t m = 0; m < kLeafGroup; ++m) {
+            const Dist d = tx_dist<D, S>(q, t[m], wn);
+            if (j + m < cnt && (d < best || (d == best && k[m] < best_key)))
+              best = d, best_key = k[m];
+          }
         }
       } else {
         const Rec<S> r0 = load_rec<S>(tv.nodes, link.x);
@@ -264,7 +295,8 @@ __device__ uint32_t tree_search(const TreeView &tv, const Tx<S> &q, const uint32
       }
     }
     if (sp == 0) break;
-    const u32x4 e = stack[--sp];
+    const u32x4 e = (link.y & kTreeLeaf) && bound <= best ? nxt : stack[sp - 1];
+    --sp;
     link = u32x2{e.x, e.y};
     bound = Dist(e.z) | Dist(uint64_t(e.w) << 32);
   }
