@@ -233,6 +233,40 @@ __device__ __forceinline__ void load_group(const TreeView &tv, uint32_t i, Tx<S>
   k[0] = kk.x, k[1] = kk.y, k[2] = kk.z, k[3] = kk.w;
 }
 
+// A deferred sibling on the search stack: its link and box distance.  For
+// 8-bit guides one 8-byte entry, the link packed into a word (inner: the
+// first child, < 2^27; leaf: kTreeLeaf | count << 27 | first texel, count
+// <= kLeafMax, first texel < 2^26), for 16-bit ones 16 bytes.
+template <int D>
+struct StackOf {
+  typedef u32x4 type;
+};
+template <>
+struct StackOf<8> {
+  typedef u32x2 type;
+};
+template <int D>
+__device__ __forceinline__ typename StackOf<D>::type push_entry(u32x2 l,
+                                                                typename DistOf<D>::type b) {
+  if constexpr (D == 8) {
+    const uint32_t w = (l.y & kTreeLeaf) ? (kTreeLeaf | ((l.y & ~kTreeLeaf) << 27) | l.x) : l.x;
+    return u32x2{w, b};
+  } else {
+    return u32x4{l.x, l.y, uint32_t(b), uint32_t(uint64_t(b) >> 32)};
+  }
+}
+template <int D>
+__device__ __forceinline__ void pop_entry(const typename StackOf<D>::type &e, u32x2 &l,
+                                          typename DistOf<D>::type &b) {
+  if constexpr (D == 8) {
+    l = u32x2{e.x & 0x07FFFFFFu, (e.x & kTreeLeaf) ? (kTreeLeaf | ((e.x >> 27) & 15u)) : 0u};
+    b = e.y;
+  } else {
+    l = u32x2{e.x, e.y};
+    b = typename DistOf<D>::type(e.z) | (typename DistOf<D>::type(e.w) << 32);
+  }
+}
+
 // The exact lookup of q: the source coordinate x | y << 16 of the texel
 // nearest to q under the weights, ties to the smallest raster index (the
 // coordinate word y << 16 | x orders like the raster index).  An inner node
@@ -251,15 +285,15 @@ __device__ uint32_t tree_search(const TreeView &tv, const Tx<S> &q, const uint32
                                 typename DistOf<D>::type best = ~typename DistOf<D>::type(0),
                                 uint32_t best_key = 0xFFFFFFFFu) {
   typedef typename DistOf<D>::type Dist;
-  // one 16-byte entry per deferred sibling (link, bound as two words): one
-  // scratch store per push and one load per pop, the load issued with a
-  // leaf's texels when a leaf comes before the pop
-  u32x4 stack[kMaxDepth];
+  // one entry per deferred sibling (its link and bound): one scratch store
+  // per push and one load per pop, the load issued with a leaf's texels
+  // when a leaf comes before the pop
+  typename StackOf<D>::type stack[kMaxDepth];
   int32_t sp = 0;
   u32x2 link = load_rec<S>(tv.nodes, 0).link;
   Dist bound = 0;
   for (;;) {
-    u32x4 nxt = {0u, 0u, 0u, 0u};
+    typename StackOf<D>::type nxt = {};
     if (bound <= best) {
       if (link.y & kTreeLeaf) {
         // the entry popped after this leaf, loaded with the leaf's texels
@@ -287,7 +321,7 @@ __device__ uint32_t tree_search(const TreeView &tv, const Tx<S> &q, const uint32
         const Dist bf = first0 ? b1 : b0;
         if (bf <= best) {
           const u32x2 fl = first0 ? r1.link : r0.link;
-          stack[sp++] = u32x4{fl.x, fl.y, uint32_t(bf), uint32_t(uint64_t(bf) >> 32)};
+          stack[sp++] = push_entry<D>(fl, bf);
         }
         link = first0 ? r0.link : r1.link;
         bound = first0 ? b0 : b1;
@@ -295,10 +329,10 @@ __device__ uint32_t tree_search(const TreeView &tv, const Tx<S> &q, const uint32
       }
     }
     if (sp == 0) break;
-    const u32x4 e = (link.y & kTreeLeaf) && bound <= best ? nxt : stack[sp - 1];
+    const typename StackOf<D>::type e =
+        (link.y & kTreeLeaf) && bound <= best ? nxt : stack[sp - 1];
     --sp;
-    link = u32x2{e.x, e.y};
-    bound = Dist(e.z) | Dist(uint64_t(e.w) << 32);
+    pop_entry<D>(e, link, bound);
   }
   return best_key;
 }
