@@ -20,7 +20,8 @@
 //                (one at equal distance may hold a smaller raster index), so
 //                the result is the exact argmin of sum_k w_k (q_k - g_k)^2,
 //                ties to the smallest raster index, for any tree shape.
-//   k_seeds_n    one thread per padded seed record: the seed and its search.
+//   k_seeds_n    eight lanes per padded seed record: the seed and its search,
+//                the lanes searching disjoint subtrees under a shared bound.
 //   k_assign_n   the level loop of Algorithm 2 per pixel (64 x 16 tiles, four
 //                rows per thread) with the many-channel error; pixels no
 //                level accepts are listed in LDS and searched by the tile's
@@ -337,6 +338,100 @@ __device__ uint32_t tree_search(const TreeView &tv, const Tx<S> &q, const uint32
   return best_key;
 }
 
+// v of another lane of the row by the DPP pattern CTRL (every lane of the
+// group active).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_from(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_from(uint64_t v) {
+  return uint64_t(dpp_from<CTRL>(uint32_t(v))) | (uint64_t(dpp_from<CTRL>(uint32_t(v >> 32))) << 32);
+}
+
+// The least of v over each aligned group of 8 lanes, in every lane of the
+// group (all eight active): pairs within quads (lane ^ 1, lane ^ 2), then
+// the group's two quads (lane 7 - i of the group).
+template <class T>
+__device__ __forceinline__ T group8_min(T v) {
+  v = min(v, dpp_from<0xB1>(v));
+  v = min(v, dpp_from<0x4E>(v));
+  return min(v, dpp_from<0x141>(v));
+}
+
+// The same lookup by an aligned group of 8 lanes given the same q: lane g
+// of the group searches the subtree reached from the root by the path of
+// g's three bits (a leaf met on the way is searched by the one lane whose
+// remaining bits are zero), one node per step, and every step prunes with
+// the group's best distance so far, which every lane's subtree search may
+// use: a subtree farther than a texel any lane has found holds no texel at
+// the least distance.  The group's nearest texel, ties to the smallest key,
+// is returned to every lane; the subtrees partition the texels, so the
+// result is the search's own.
+template <int D, int S>
+__device__ uint32_t tree_search_group8(const TreeView &tv, const Tx<S> &q, const uint32_t *wn,
+                                       uint32_t g) {
+  typedef typename DistOf<D>::type Dist;
+  Dist best = ~Dist(0), bound = 0;
+  uint32_t best_key = 0xFFFFFFFFu;
+  u32x2 link = load_rec<S>(tv.nodes, 0).link;
+  bool done = false;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (link.y & kTreeLeaf) {
+      done = (g >> l) != 0u;
+      break;
+    }
+    const Rec<S> r = load_rec<S>(tv.nodes, link.x + ((g >> l) & 1u));
+    link = r.link;
+    bound = box_dist<D, S>(q, r.lo, r.hi, wn);
+  }
+  typename StackOf<D>::type stack[kMaxDepth];
+  int32_t sp = 0;
+  const uint32_t base = __lane_id() & ~7u;
+  for (;;) {
+    const Dist gb = group8_min(best);
+    if (((__ballot(done) >> base) & 0xFFu) == 0xFFu) break;
+    if (done) continue;
+    if (bound <= gb) {
+      if (link.y & kTreeLeaf) {
+        const uint32_t cnt = link.y & ~kTreeLeaf;
+        for (uint32_t j = 0; j < cnt; j += kLeafGroup) {
+          Tx<S> t[kLeafGroup];
+          uint32_t k[kLeafGroup];
+          load_group<S>(tv, link.x + j, t, k);
+#pragma unroll
+          for (uint32_t m = 0; m < kLeafGroup; ++m) {
+            const Dist d = tx_dist<D, S>(q, t[m], wn);
+            if (j + m < cnt && (d < best || (d == best && k[m] < best_key)))
+              best = d, best_key = k[m];
+          }
+        }
+      } else {
+        const Rec<S> r0 = load_rec<S>(tv.nodes, link.x);
+        const Rec<S> r1 = load_rec<S>(tv.nodes, link.x + 1);
+        const Dist b0 = box_dist<D, S>(q, r0.lo, r0.hi, wn);
+        const Dist b1 = box_dist<D, S>(q, r1.lo, r1.hi, wn);
+        const bool first0 = b0 <= b1;
+        const Dist bf = first0 ? b1 : b0;
+        if (bf <= gb) stack[sp++] = push_entry<D>(first0 ? r1.link : r0.link, bf);
+        link = first0 ? r0.link : r1.link;
+        bound = first0 ? b0 : b1;
+        continue;
+      }
+    }
+    if (sp == 0) {
+      done = true;
+      continue;
+    }
+    --sp;
+    pop_entry<D>(stack[sp], link, bound);
+  }
+  // the group's nearest: least distance, then least key
+  const Dist dmin = group8_min(best);
+  return group8_min(best == dmin ? best_key : 0xFFFFFFFFu);
+}
+
 // ---------------------------------------------------------------- tree build
 
 struct BuildArgs {
@@ -548,7 +643,8 @@ __device__ inline TreeView frame_tree(const FrameArgs &a) {
 // translation u* - q of the seed's search.
 template <int D, int S>
 __global__ void __launch_bounds__(256) k_seeds_n(FrameArgs a) {
-  const uint32_t idx = blockIdx.x * 256 + threadIdx.x;
+  // eight lanes per record, each searching part of the tree
+  const uint32_t idx = (blockIdx.x * 256 + threadIdx.x) >> 3, g = threadIdx.x & 7u;
   const Levels &lv = a.lv;
   if (idx >= uint32_t(lv.poffset[lv.count])) return;
   int32_t i = 0;
@@ -563,12 +659,13 @@ __global__ void __launch_bounds__(256) k_seeds_n(FrameArgs a) {
     const uint32_t sy = (uint32_t(cy) << ls) + (j >> 16);
     if (sx < uint32_t(a.w) && sy < uint32_t(a.h)) {
       const uint32_t at = __umul24(sy, uint32_t(a.w)) + sx;
-      const uint32_t u = tree_search<D, S>(frame_tree(a), load_tx<S>(a.tgt_guide, at), a.wn);
+      const uint32_t u =
+          tree_search_group8<D, S>(frame_tree(a), load_tx<S>(a.tgt_guide, at), a.wn, g);
       rec.x = pack_xy(4 * sx, 4 * sy);
       rec.y = pack_off(int32_t(u & 0xFFFFu) - int32_t(sx), int32_t(u >> 16) - int32_t(sy));
     }
   }
-  seed_table(a)[idx] = rec;
+  if (g == 0) seed_table(a)[idx] = rec;
 }
 
 constexpr uint32_t kAssignTW = 64, kAssignTH = 16;
@@ -731,7 +828,7 @@ hipError_t launch_search_frame(const FrameArgs &a, hipEvent_t *ev, hipStream_t s
                          ((uint32_t(a.h) + kAssignTH - 1) / kAssignTH);
   return with_format(a.fmt, a.texel, [&](auto d, auto s) -> hipError_t {
     constexpr int D = decltype(d)::value, S = decltype(s)::value;
-    if (records > 0) k_seeds_n<D, S><<<blocks_for(records, 256), 256, 0, stream>>>(a);
+    if (records > 0) k_seeds_n<D, S><<<blocks_for(uint64_t(records) * 8, 256), 256, 0, stream>>>(a);
     if (ev) {
       const hipError_t e = hipEventRecord(ev[1], stream);
       if (e != hipSuccess) return e;
