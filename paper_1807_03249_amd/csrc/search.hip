@@ -23,11 +23,11 @@
 //   k_seeds_n    eight lanes per padded seed record: the seed and its search,
 //                the lanes searching disjoint subtrees under a shared bound.
 //   k_assign_n   the level loop of Algorithm 2 per pixel (64 x 16 tiles, four
-//                rows per thread) with the many-channel error; pixels no
-//                level accepts are listed in LDS and searched by the tile's
-//                threads in list order, so the searches fill whole waves,
-//                each starting from the nearest candidate its level loop
+//                rows per thread) with the many-channel error; a pixel no
+//                level accepts keeps the nearest candidate its level loop
 //                measured.
+//   k_fallback_n those pixels' own lookups, one thread per pixel, each search
+//                starting from that candidate.
 //   k_tree_query the search of caller-given texels (sb_tree_query).
 #include <stdio.h>
 #include <string.h>
@@ -673,19 +673,11 @@ constexpr uint32_t kAssignTW = 64, kAssignTH = 16;
 template <int D, int S>
 __global__ void __launch_bounds__(256) k_assign_n(FrameArgs a) {
   typedef typename DistOf<D>::type Dist;
-  // fallback pixels: position, and the nearest candidate the level loop
-  // measured (its coordinate and distance), the search's starting bound
-  __shared__ uint32_t s_list[kAssignTW * kAssignTH];
-  __shared__ uint32_t s_ckey[kAssignTW * kAssignTH];
-  __shared__ Dist s_cd[kAssignTW * kAssignTH];
-  __shared__ uint32_t s_n;
   const uint32_t tid = threadIdx.x;
   const uint32_t tiles_x = (uint32_t(a.w) + kAssignTW - 1) / kAssignTW;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int32_t tx0 = int32_t((tile % tiles_x) * kAssignTW);
   const int32_t ty0 = int32_t((tile / tiles_x) * kAssignTH);
-  if (tid == 0) s_n = 0u;
-  __syncthreads();
   const Levels &lv = a.lv;
   const int32_t L = lv.count;
   const uint32_t sw = uint32_t(a.sw), sh = uint32_t(a.sh);
@@ -722,25 +714,42 @@ __global__ void __launch_bounds__(256) k_assign_n(FrameArgs a) {
       if (e < cd || (e == cd && vkey < ckey)) cd = e, ckey = vkey;
     }
     if (!done) {
+      // no level accepts: the fallback code, and in the vote-distance slot
+      // the nearest candidate measured (its coordinate, or none), from
+      // which k_fallback_n starts the pixel's own search
       glb(a.out_chunk)[pidx] = (uint32_t(L) << 26) | (uint32_t(y) << 13) | uint32_t(x);
-      const uint32_t slot = atomicAdd(&s_n, 1u);
-      s_list[slot] = pack_xy(uint32_t(x), uint32_t(y));
-      s_ckey[slot] = ckey;
-      s_cd[slot] = cd;
+      glb(a.offsets)[pidx] = ckey;
     }
   }
-  __syncthreads();
-  // the tile's fallback pixels: their own lookups, in list order
-  const uint32_t nf = s_n;
-  for (uint32_t k = tid; k < nf; k += 256) {
-    const uint32_t xy = s_list[k], x = xy & 0xFFFFu, y = xy >> 16;
-    const uint32_t pidx = __umul24(y, uint32_t(a.w)) + x;
-    const uint32_t u = tree_search<D, S>(frame_tree(a), load_tx<S>(a.tgt_guide, pidx), a.wn,
-                                         s_cd[k], s_ckey[k]);
-    const uint32_t off = pack_off(int32_t(u & 0xFFFFu) - int32_t(x), int32_t(u >> 16) - int32_t(y));
-    glb(a.offsets)[pidx] = vote_distance(a, off);
-    if (a.out_nnf) glb(a.out_nnf)[pidx] = u;
-  }
+}
+
+// The own lookups of the pixels no level accepted (fallback chunk code),
+// one thread per pixel of 16 x 16 tiles, so a region where most pixels fall
+// back has every lane searching once rather than a few lanes searching in
+// turn.  The search starts from the candidate the level loop left in the
+// vote-distance slot (its distance measured again here), then the slot
+// takes the result's vote distance.
+template <int D, int S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+    k_fallback_n(FrameArgs a) {
+  typedef typename DistOf<D>::type Dist;
+  const uint32_t tiles_x = (uint32_t(a.w) + 15u) / 16u;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int32_t x = int32_t((tile % tiles_x) * 16u + (threadIdx.x & 15u));
+  const int32_t y = int32_t((tile / tiles_x) * 16u + (threadIdx.x >> 4));
+  if (x >= a.w || y >= a.h) return;
+  const uint32_t pidx = __umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x);
+  if ((glb(a.out_chunk)[pidx] >> 26) != uint32_t(a.lv.count)) return;
+  const uint32_t ckey = glb(a.offsets)[pidx];
+  const Tx<S> gt = load_tx<S>(a.tgt_guide, pidx);
+  Dist cd = ~Dist(0);
+  if (ckey != 0xFFFFFFFFu)
+    cd = tx_dist<D, S>(gt, load_tx<S>(a.src_guide, __umul24(ckey >> 16, uint32_t(a.sw)) + (ckey & 0xFFFFu)),
+                       a.wn);
+  const uint32_t u = tree_search<D, S>(frame_tree(a), gt, a.wn, cd, ckey);
+  const uint32_t off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
+  glb(a.offsets)[pidx] = vote_distance(a, off);
+  if (a.out_nnf) glb(a.out_nnf)[pidx] = u;
 }
 
 template <int D, int S>
@@ -834,6 +843,8 @@ hipError_t launch_search_frame(const FrameArgs &a, hipEvent_t *ev, hipStream_t s
       if (e != hipSuccess) return e;
     }
     k_assign_n<D, S><<<tiles, 256, 0, stream>>>(a);
+    const uint32_t ftiles = ((uint32_t(a.w) + 15u) / 16u) * ((uint32_t(a.h) + 15u) / 16u);
+    k_fallback_n<D, S><<<ftiles, 256, 0, stream>>>(a);
     return hipGetLastError();
   });
 }
