@@ -724,9 +724,10 @@ __global__ void __launch_bounds__(256) k_assign_n(FrameArgs a) {
 }
 
 // The own lookups of the pixels no level accepted (fallback chunk code),
-// one thread per pixel of 16 x 16 tiles, so a region where most pixels fall
-// back has every lane searching once rather than a few lanes searching in
-// turn.  The search starts from the candidate the level loop left in the
+// one thread per pixel of 16 x 16 tiles, each wave an 8 x 8 quarter of its
+// tile (neighbours' searches take similar paths and lengths), so a region
+// where most pixels fall back has every lane searching once rather than a
+// few lanes searching in turn.  The search starts from the candidate the level loop left in the
 // vote-distance slot (its distance measured again here), then the slot
 // takes the result's vote distance.
 template <int D, int S>
@@ -735,8 +736,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
   typedef typename DistOf<D>::type Dist;
   const uint32_t tiles_x = (uint32_t(a.w) + 15u) / 16u;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int32_t x = int32_t((tile % tiles_x) * 16u + (threadIdx.x & 15u));
-  const int32_t y = int32_t((tile / tiles_x) * 16u + (threadIdx.x >> 4));
+  const uint32_t wq = threadIdx.x >> 6, ln = threadIdx.x & 63u;
+  const int32_t x = int32_t((tile % tiles_x) * 16u + (wq & 1u) * 8u + (ln & 7u));
+  const int32_t y = int32_t((tile / tiles_x) * 16u + (wq >> 1) * 8u + (ln >> 3));
   if (x >= a.w || y >= a.h) return;
   const uint32_t pidx = __umul24(uint32_t(y), uint32_t(a.w)) + uint32_t(x);
   if ((glb(a.out_chunk)[pidx] >> 26) != uint32_t(a.lv.count)) return;
