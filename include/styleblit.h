@@ -239,9 +239,10 @@ int sb_style_destroy(sb_style *style);
  * of smallest raster index), and a search skips a subtree only when its box
  * lies strictly farther than the best texel found, so the result is the
  * exact argmin for any tree shape.  Per frame: a seed pass searches each
- * seed's lookup; the level loop then runs as for the table formats, and the
- * pixels no level accepts search their own lookup in the same pass
- * (gathered per tile so the searches run in full waves); the vote is
+ * seed's lookup (eight lanes per seed, over disjoint subtrees); the level
+ * loop then runs as for the table formats, and a pass of its own searches
+ * the own lookup of every pixel no level accepts (one thread per pixel,
+ * starting from the nearest candidate its level loop measured); the vote is
  * unchanged.  Not available with labels.  In a batch (sb_batch_run) such
  * frames run through the per-frame kernels after the batch kernels, on the
  * same stream; sb_serve_run runs each such request alone on a slot. */
