@@ -169,6 +169,45 @@ def test_full_size_frame(sb, depth):
     np.testing.assert_array_equal(g_rgb, e_rgb)
 
 
+@pytest.mark.parametrize("depth", [8, 16])
+def test_two_streams_round_robin(sb, depth):
+    """The many-channel leg's two-stream timing: prepared full-size frames
+    over four buffer sets (each its own jitter seed) launched round robin on
+    two streams, twice, with no synchronisation between launches; every set
+    equals the same frame run alone (which the full-size test pins to the
+    oracle)."""
+    import torch
+
+    styles, frames = workloads.config(7, depth=depth)
+    st_np, fr = styles[0], frames[0]
+    ch = 5 if depth == 8 else 4
+    p = fr.params
+    st = sb.Style(st_np.rgb, st_np.guide, channels=ch)
+    g = _dev(fr.guide)
+    seeds = [fr.seed + 31 * i for i in range(4)]
+    say(f"search frames round robin on two streams depth={depth} seeds={seeds}")
+    alone, sets, plans = [], [], []
+    for sd in seeds:
+        prm = sb.params(p.levels, p.finest, p.threshold, p.radius, seed=sd)
+        rgb, chunk = sb.stylize(st, g, None, prm)
+        alone.append((rgb.clone(), chunk.clone()))
+        o = torch.empty_like(rgb)
+        c = torch.empty_like(chunk)
+        ws = torch.empty(sb.workspace_bytes(fr.w, fr.h, prm), dtype=torch.uint8, device="cuda")
+        sets.append((o, c))
+        plans.append(sb.FramePlan(st, g, None, prm, o, c, ws))
+    torch.cuda.synchronize()
+    other = torch.cuda.Stream()
+    streams = [torch.cuda.current_stream().cuda_stream, other.cuda_stream]
+    for _ in range(2):
+        for k, plan in enumerate(plans):
+            plan.launch(streams[k % 2])
+    torch.cuda.synchronize()
+    for sd, (o, c), (e_rgb, e_chunk) in zip(seeds, sets, alone):
+        assert torch.equal(c, e_chunk), f"chunk seed={sd}"
+        assert torch.equal(o, e_rgb), f"rgb seed={sd}"
+
+
 def test_other_entry_points(sb):
     """A search-format style through sb_stylize_noalloc, sb_stylize_frames,
     batches (mixed with table-format frames, graphs and direct launches) and
