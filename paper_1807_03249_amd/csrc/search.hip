@@ -346,7 +346,8 @@ __device__ __forceinline__ uint32_t dpp_from(uint32_t v) {
 }
 template <int CTRL>
 __device__ __forceinline__ uint64_t dpp_from(uint64_t v) {
-  return uint64_t(dpp_from<CTRL>(uint32_t(v))) | (uint64_t(dpp_from<CTRL>(uint32_t(v >> 32))) << 32);
+  const uint64_t lo = dpp_from<CTRL>(uint32_t(v)), hi = dpp_from<CTRL>(uint32_t(v >> 32));
+  return lo | (hi << 32);
 }
 
 // The least of v over each aligned group of 8 lanes, in every lane of the
@@ -727,9 +728,9 @@ __global__ void __launch_bounds__(256) k_assign_n(FrameArgs a) {
 // one thread per pixel of 16 x 16 tiles, each wave an 8 x 8 quarter of its
 // tile (neighbours' searches take similar paths and lengths), so a region
 // where most pixels fall back has every lane searching once rather than a
-// few lanes searching in turn.  The search starts from the candidate the level loop left in the
-// vote-distance slot (its distance measured again here), then the slot
-// takes the result's vote distance.
+// few lanes searching in turn.  The search starts from the candidate the
+// level loop left in the vote-distance slot (its distance measured again
+// here), then the slot takes the result's vote distance.
 template <int D, int S>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
     k_fallback_n(FrameArgs a) {
@@ -745,9 +746,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
   const uint32_t ckey = glb(a.offsets)[pidx];
   const Tx<S> gt = load_tx<S>(a.tgt_guide, pidx);
   Dist cd = ~Dist(0);
-  if (ckey != 0xFFFFFFFFu)
-    cd = tx_dist<D, S>(gt, load_tx<S>(a.src_guide, __umul24(ckey >> 16, uint32_t(a.sw)) + (ckey & 0xFFFFu)),
-                       a.wn);
+  if (ckey != 0xFFFFFFFFu) {
+    const uint32_t cidx = __umul24(ckey >> 16, uint32_t(a.sw)) + (ckey & 0xFFFFu);
+    cd = tx_dist<D, S>(gt, load_tx<S>(a.src_guide, cidx), a.wn);
+  }
   const uint32_t u = tree_search<D, S>(frame_tree(a), gt, a.wn, cd, ckey);
   const uint32_t off = pack_off(int32_t(u & 0xFFFFu) - x, int32_t(u >> 16) - y);
   glb(a.offsets)[pidx] = vote_distance(a, off);
